@@ -1,0 +1,227 @@
+"""CPU oracle for PERCH 2.0 pose scoring -- test infrastructure only.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It wraps ``liboracle.so`` (built from
+``perch_oracle.c`` by ``oracle.build.build()``) with ctypes; the arithmetic
+lives in the C file, whose header lists the paper passages it follows and the
+readings it takes where the paper is silent.
+
+Meshes are any object with ``xyz`` (V x 3 float32, mm), ``tri`` (T x 3 int32)
+and ``rgb`` (V x 3 uint8 or None).  Scenes are any object with ``K`` (a
+``(width, height, fx, fy, cx, cy)`` tuple), ``depth`` (H x W uint16 mm),
+``rgb`` (H x W x 3 uint8 or None) and ``labels`` (H x W int32 or None).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+USE_RGB = 1
+MARK_OCCLUDERS = 2
+VOL_AABB = 0 << 4
+VOL_LABEL = 2 << 4
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+
+class _Intrinsics(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("n_verts", ctypes.c_int32),
+                ("tri", ctypes.c_void_p), ("n_tris", ctypes.c_int32),
+                ("rgb", ctypes.c_void_p)]
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("K", _Intrinsics), ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float),
+                ("tau_c", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("stride", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_render.argtypes = [P, P, P, P, P, P]
+        lib.oracle_render.restype = ctypes.c_int
+        lib.oracle_backproject.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
+        lib.oracle_backproject.restype = None
+        lib.oracle_srgb_to_lab64.argtypes = [P, P]
+        lib.oracle_srgb_to_lab32.argtypes = [P, P]
+        lib.oracle_ciede2000_64.argtypes = [P, P]
+        lib.oracle_ciede2000_64.restype = ctypes.c_double
+        lib.oracle_ciede2000_32.argtypes = [P, P]
+        lib.oracle_ciede2000_32.restype = ctypes.c_float
+        lib.oracle_score.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P, ctypes.c_int32]
+        lib.oracle_score.restype = ctypes.c_int
+        lib.oracle_score_detail.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
+        lib.oracle_score_detail.restype = ctypes.c_int
+        lib.oracle_best.argtypes = [P, P, ctypes.c_int32, P, P, P]
+        lib.oracle_best.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _intr(K):
+    w, h, fx, fy, cx, cy = K
+    return _Intrinsics(int(w), int(h), float(fx), float(fy), float(cx), float(cy))
+
+
+class _MeshArgs:
+    def __init__(self, mesh):
+        self.xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float32)
+        self.tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
+        rgb = getattr(mesh, "rgb", None)
+        self.rgb = None if rgb is None else np.ascontiguousarray(rgb, dtype=np.uint8)
+        self.s = _Mesh(_ptr(self.xyz), self.xyz.shape[0], _ptr(self.tri), self.tri.shape[0],
+                       _ptr(self.rgb))
+
+
+class _SceneArgs:
+    def __init__(self, scene, delta_mm, tau_c, flags, stride):
+        self.depth = np.ascontiguousarray(scene.depth, dtype=np.uint16)
+        rgb = getattr(scene, "rgb", None)
+        lab = getattr(scene, "labels", None)
+        self.rgb = None if rgb is None else np.ascontiguousarray(rgb, dtype=np.uint8)
+        self.labels = None if lab is None else np.ascontiguousarray(lab, dtype=np.int32)
+        self.s = _Scene(_intr(scene.K), _ptr(self.depth), _ptr(self.rgb), _ptr(self.labels),
+                        float(delta_mm), float(tau_c), int(flags), int(stride))
+
+
+def render(mesh, pose, K):
+    """Full-image render of one pose (Sec. IV-A "Parallel Rendering").
+
+    Returns (depth uint16 H x W, tri_id int32 H x W (-1 empty), rgb uint8 H x W x 3).
+    """
+    lib = _load()
+    m = _MeshArgs(mesh)
+    pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+    k = _intr(K)
+    depth = np.zeros((k.height, k.width), np.uint16)
+    tri = np.zeros((k.height, k.width), np.int32)
+    rgb = np.zeros((k.height, k.width, 3), np.uint8)
+    rc = lib.oracle_render(ctypes.byref(m.s), _ptr(pose), ctypes.byref(k), _ptr(depth), _ptr(tri),
+                           _ptr(rgb))
+    if rc != 0:
+        raise ValueError(f"oracle_render failed ({rc})")
+    return depth, tri, rgb
+
+
+def backproject(K, i, j, d):
+    """Pixel (i, j) at depth d mm -> (Xq, Yq, Zq) in 1/16 mm (Sec. IV-A)."""
+    lib = _load()
+    out = np.zeros(3, np.int32)
+    k = _intr(K)
+    lib.oracle_backproject(ctypes.byref(k), int(i), int(j), int(d), _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def srgb_to_lab64(rgb):
+    lib = _load()
+    a = np.ascontiguousarray(rgb, dtype=np.uint8).reshape(3)
+    out = np.zeros(3, np.float64)
+    lib.oracle_srgb_to_lab64(_ptr(a), _ptr(out))
+    return out
+
+
+def srgb_to_lab32(rgb):
+    lib = _load()
+    a = np.ascontiguousarray(rgb, dtype=np.uint8).reshape(3)
+    out = np.zeros(3, np.float32)
+    lib.oracle_srgb_to_lab32(_ptr(a), _ptr(out))
+    return out
+
+
+def ciede2000_64(lab1, lab2):
+    """CIEDE2000 colour difference in binary64 (Sec. IV-B, Eq. 4)."""
+    lib = _load()
+    a = np.ascontiguousarray(lab1, dtype=np.float64).reshape(3)
+    b = np.ascontiguousarray(lab2, dtype=np.float64).reshape(3)
+    return float(lib.oracle_ciede2000_64(_ptr(a), _ptr(b)))
+
+
+def ciede2000_32(lab1, lab2):
+    """CIEDE2000 in binary32, the precision of the colour decision."""
+    lib = _load()
+    a = np.ascontiguousarray(lab1, dtype=np.float32).reshape(3)
+    b = np.ascontiguousarray(lab2, dtype=np.float32).reshape(3)
+    return float(lib.oracle_ciede2000_32(_ptr(a), _ptr(b)))
+
+
+def score(mesh, scene, poses, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1, label=0,
+          threads=0):
+    """Brute-force J_r, J_o, L, Q for every pose (Eq. 3, Eq. 4).
+
+    poses: n x 12 float32 row-major [R|t], object -> camera, mm.
+    Returns four int32 arrays (jr, jo, nr, nq).
+    """
+    lib = _load()
+    m = _MeshArgs(mesh)
+    s = _SceneArgs(scene, delta_mm, tau_c, flags, stride)
+    poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
+    n = poses.shape[0]
+    jr = np.zeros(n, np.int32)
+    jo = np.zeros(n, np.int32)
+    nr = np.zeros(n, np.int32)
+    nq = np.zeros(n, np.int32)
+    rc = lib.oracle_score(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(poses), n,
+                          _ptr(jr), _ptr(jo), _ptr(nr), _ptr(nq), int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_score failed ({rc})")
+    return jr, jo, nr, nq
+
+
+def score_detail(mesh, scene, pose, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1,
+                 label=0):
+    """One pose with per-pixel classes.
+
+    Returns ((jr, jo, L, Q), r_flag, o_flag) where r_flag is 0 not rendered,
+    1 inlier, 2 distance outlier, 3 colour outlier, 4 occluded; o_flag is 0
+    outside V, 1 explained, 2 distance outlier, 3 colour outlier.
+    """
+    lib = _load()
+    m = _MeshArgs(mesh)
+    s = _SceneArgs(scene, delta_mm, tau_c, flags, stride)
+    pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+    W, H = int(scene.K[0]), int(scene.K[1])
+    out = np.zeros(4, np.int32)
+    rf = np.zeros((H, W), np.uint8)
+    of = np.zeros((H, W), np.uint8)
+    rc = lib.oracle_score_detail(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(pose),
+                                 _ptr(out), _ptr(rf), _ptr(of))
+    if rc != 0:
+        raise ValueError(f"oracle_score_detail failed ({rc})")
+    return tuple(int(v) for v in out), rf, of
+
+
+def best(jr, jo):
+    """argmin of J = J_r + J_o, lowest index among ties (Sec. IV-A)."""
+    lib = _load()
+    jr = np.ascontiguousarray(jr, dtype=np.int32)
+    jo = np.ascontiguousarray(jo, dtype=np.int32)
+    bi = np.zeros(1, np.int32)
+    bc = np.zeros(1, np.int32)
+    nt = np.zeros(1, np.int32)
+    rc = lib.oracle_best(_ptr(jr), _ptr(jo), jr.shape[0], _ptr(bi), _ptr(bc), _ptr(nt))
+    if rc != 0:
+        raise ValueError("oracle_best: empty input")
+    return int(bi[0]), int(bc[0]), int(nt[0])

@@ -1,0 +1,682 @@
+/*
+ * PERCH 2.0 pose-scoring oracle: a plain, slow, obviously-correct CPU model.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The library built from this file may be loaded
+ * by the test-suite, by the smoke check and by the CPU-baseline leg of the
+ * benchmark, nowhere else.  It shares no code, header, table or constant
+ * generator with the HIP path, and it does not include any of the HIP path's
+ * headers.
+ *
+ * What it computes, following Agarwal, Han, Likhachev, "PERCH 2.0: Fast and
+ * Accurate GPU-based Perception via Search for Object Pose Estimation":
+ *   - Sec. III-B, Eq. 1: J = J_o + J_r, an unweighted sum of outlier counts.
+ *   - Sec. III-B, Eq. 2: a point is an outlier w.r.t. a cloud iff its nearest
+ *     point in that cloud is farther than delta (the sensor resolution).
+ *   - Sec. IV-A "Parallel Search", Eq. 3: J_r counts rendered points that are
+ *     not occluders; J_o counts observed points inside the object's volume
+ *     V(O); the occluders C are found from the input depth image.
+ *   - Sec. IV-B, Eq. 4: in RGB mode a point that does have a neighbour within
+ *     delta is still an outlier when the CIEDE2000 difference between its
+ *     CIELAB colour and its match's exceeds tau_c; applied to rendered and
+ *     observed points alike ("or vice-versa").
+ *   - Sec. IV-A "Parallel Rendering": every candidate pose is rendered into
+ *     depth (and colour) and back-projected to a point cloud, downsampled in
+ *     image space.
+ *   - Sec. IV-A "Parallel Search": the per-object minimum-cost pose.
+ *   - Sec. V-C: with segmentation labels, J_o counts the observed points that
+ *     carry the object's label, and only pixels of another label occlude.
+ *
+ * The paper fixes no rasterization, quantization or precision convention.
+ * The readings followed here (the HIP path follows the same ones):
+ *   R1 Transform: Xc = ((R00 x + R01 y) + R02 z) + t0 in binary64 from binary32
+ *      inputs, left to right, no fused multiply-add.
+ *   R2 Projection: iz = 1/Zc; u = ((fx Xc) iz) + cx; U = rint(256 u) (8
+ *      sub-pixel bits).  Integer pixel coordinates are pixel centres.  A
+ *      triangle is dropped if any vertex has Zc < 100 mm or |256 u| > 2^24.
+ *   R3 Edge functions E_ab(p) = (b.y-a.y)(p.x-a.x) - (b.x-a.x)(p.y-a.y) in
+ *      int64; area A = E_01(v2); a triangle is drawn iff A > 0 (the mesh is
+ *      counter-clockwise about the outward normal and the screen y axis points
+ *      down).  A pixel is covered iff each edge has E > 0, or E == 0 and the
+ *      edge is top-left (dy > 0, or dy == 0 and dx < 0).
+ *   R4 Depth: t_k = w_k * iz_k, s = (t0 + t1) + t2, z = A / s, d = rint(z) in
+ *      millimetres; the fragment is kept iff 1 <= d <= 65534.  Visibility
+ *      uses a 16-bit millimetre depth buffer with triangles drawn in index
+ *      order under a strict less-than test: the fragment with the smallest
+ *      (d, triangle index) wins.
+ *   R5 Colour: c = ((t0 c0 + t1 c1) + t2 c2) / s per channel, rint, clamped
+ *      to [0, 255].
+ *   R6 Occluders: a rendered pixel is dropped iff the observed depth d_o > 0
+ *      and 16 d_o + dq < 16 d (dq = rint(16 delta)); in label mode only an
+ *      observed pixel whose label differs from the object's label occludes.
+ *   R7 Points in 1/16 mm: kx[i] = ((i - cx) 16) / fx, Xq = rint(kx[i] d),
+ *      likewise Yq with ky[j], Zq = 16 d.  R keeps pixels with i and j
+ *      multiples of the stride.
+ *   R8 Neighbours: dx^2 + dy^2 + dz^2 <= dq^2 in exact integers.
+ *   R9 In RGB mode the match is the nearest neighbour, ties broken by the
+ *      lower row-major pixel index.  The colour decision dE00(point, match)
+ *      > tau_c is taken in binary32, the precision of the GPU path; the
+ *      binary64 colour functions exist to pin the binary32 ones.
+ *   R10 Volume: the object-frame AABB of the mesh, inflated by delta, tested
+ *      in binary64 on q = R^T (P - t) with P = (Xq, Yq, Zq) / 16.
+ *   R11 Selection: lowest J; ties go to the lowest pose index.
+ *
+ * Colour: sRGB8 is linearised with the IEC 61966-2-1 piecewise curve (256-
+ * entry table computed in binary64), mapped to XYZ with the four-digit sRGB
+ * matrix, and to CIELAB with the white point equal to the matrix row sums
+ * (so sRGB white maps to L* = 100, a* = b* = 0).  CIEDE2000 uses
+ * kL = kC = kH = 1.  Its rotation term R_T is parity unpinned: the tests pin
+ * it only where it vanishes and through symmetry.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_USE_RGB 1u
+#define OR_MARK_OCCLUDERS 2u
+#define OR_VOL_MASK (3u << 4)
+#define OR_VOL_AABB (0u << 4)
+#define OR_VOL_LABEL (2u << 4)
+
+#define OR_NEAR_MM 100.0
+#define OR_COORD_LIMIT 16777216.0
+#define OR_EMPTY_KEY 0xFFFFFFFFu
+
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} oracle_intrinsics;
+
+typedef struct {
+    const float *xyz;     /* n_verts * 3, millimetres, object frame */
+    int32_t n_verts;
+    const int32_t *tri;   /* n_tris * 3 */
+    int32_t n_tris;
+    const uint8_t *rgb;   /* n_verts * 3 sRGB8, or NULL */
+} oracle_mesh;
+
+typedef struct {
+    oracle_intrinsics K;
+    const uint16_t *depth;  /* H * W millimetres, 0 = no reading */
+    const uint8_t *rgb;     /* H * W * 3 sRGB8, or NULL */
+    const int32_t *labels;  /* H * W, or NULL */
+    float delta_mm;
+    float tau_c;
+    uint32_t flags;
+    int32_t stride;
+} oracle_scene;
+
+/* ------------------------------------------------------------------ */
+/* Geometry                                                           */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int ok;          /* 1 if the vertex may take part in a drawn triangle */
+    int32_t U, V;    /* 24.8 fixed point screen position */
+    double iz;       /* 1 / Zc */
+} or_vertex;
+
+static void or_transform(const float *pose, const float *v, double out[3])
+{
+    double x = (double)v[0], y = (double)v[1], z = (double)v[2];
+    out[0] = (((double)pose[0] * x + (double)pose[1] * y) + (double)pose[2] * z) + (double)pose[3];
+    out[1] = (((double)pose[4] * x + (double)pose[5] * y) + (double)pose[6] * z) + (double)pose[7];
+    out[2] = (((double)pose[8] * x + (double)pose[9] * y) + (double)pose[10] * z) + (double)pose[11];
+}
+
+static or_vertex or_project(const float *pose, const float *v, const oracle_intrinsics *K)
+{
+    or_vertex o;
+    double c[3];
+    or_transform(pose, v, c);
+    o.ok = 0; o.U = 0; o.V = 0; o.iz = 0.0;
+    if (!(c[2] >= OR_NEAR_MM)) return o;
+    o.iz = 1.0 / c[2];
+    double u = (((double)K->fx * c[0]) * o.iz) + (double)K->cx;
+    double w = (((double)K->fy * c[1]) * o.iz) + (double)K->cy;
+    double su = 256.0 * u, sv = 256.0 * w;
+    if (!(fabs(su) <= OR_COORD_LIMIT) || !(fabs(sv) <= OR_COORD_LIMIT)) return o;
+    o.U = (int32_t)nearbyint(su);
+    o.V = (int32_t)nearbyint(sv);
+    o.ok = 1;
+    return o;
+}
+
+static int64_t or_edge(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px, int64_t py)
+{
+    return (by - ay) * (px - ax) - (bx - ax) * (py - ay);
+}
+
+static int or_top_left(int64_t ax, int64_t ay, int64_t bx, int64_t by)
+{
+    int64_t dy = by - ay, dx = bx - ax;
+    return dy > 0 || (dy == 0 && dx < 0);
+}
+
+static int or_inside(int64_t e, int tl) { return e > 0 || (e == 0 && tl); }
+
+static int32_t or_floor_div256(int64_t a) { return (int32_t)(a >= 0 ? a / 256 : -((-a + 255) / 256)); }
+static int32_t or_ceil_div256(int64_t a) { return (int32_t)(a >= 0 ? (a + 255) / 256 : -((-a) / 256)); }
+
+/* Render one pose of one mesh into full-size images.  depth: 0 where empty.
+ * tri_id: winning triangle or -1.  rgb (optional, needs mesh colours). */
+int oracle_render(const oracle_mesh *m, const float *pose, const oracle_intrinsics *K,
+                  uint16_t *depth, int32_t *tri_id, uint8_t *rgb)
+{
+    const int W = K->width, H = K->height;
+    if (W <= 0 || H <= 0 || m->n_tris > 65536 || m->n_verts <= 0) return -1;
+    uint32_t *zbuf = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)W * H);
+    or_vertex *pv = (or_vertex *)malloc(sizeof(or_vertex) * (size_t)m->n_verts);
+    if (!zbuf || !pv) { free(zbuf); free(pv); return -2; }
+    for (size_t k = 0; k < (size_t)W * H; ++k) zbuf[k] = OR_EMPTY_KEY;
+    for (int32_t k = 0; k < m->n_verts; ++k) pv[k] = or_project(pose, m->xyz + 3 * (size_t)k, K);
+
+    for (int32_t t = 0; t < m->n_tris; ++t) {
+        const int32_t *ix = m->tri + 3 * (size_t)t;
+        const or_vertex a = pv[ix[0]], b = pv[ix[1]], c = pv[ix[2]];
+        if (!a.ok || !b.ok || !c.ok) continue;
+        int64_t A = or_edge(a.U, a.V, b.U, b.V, c.U, c.V);
+        if (A <= 0) continue;
+        int64_t minU = a.U, maxU = a.U, minV = a.V, maxV = a.V;
+        if (b.U < minU) minU = b.U; if (b.U > maxU) maxU = b.U;
+        if (c.U < minU) minU = c.U; if (c.U > maxU) maxU = c.U;
+        if (b.V < minV) minV = b.V; if (b.V > maxV) maxV = b.V;
+        if (c.V < minV) minV = c.V; if (c.V > maxV) maxV = c.V;
+        int32_t i0 = or_ceil_div256(minU), i1 = or_floor_div256(maxU);
+        int32_t j0 = or_ceil_div256(minV), j1 = or_floor_div256(maxV);
+        if (i0 < 0) i0 = 0;
+        if (j0 < 0) j0 = 0;
+        if (i1 > W - 1) i1 = W - 1;
+        if (j1 > H - 1) j1 = H - 1;
+        int tl0 = or_top_left(b.U, b.V, c.U, c.V);
+        int tl1 = or_top_left(c.U, c.V, a.U, a.V);
+        int tl2 = or_top_left(a.U, a.V, b.U, b.V);
+        for (int32_t j = j0; j <= j1; ++j) {
+            for (int32_t i = i0; i <= i1; ++i) {
+                int64_t px = 256 * (int64_t)i, py = 256 * (int64_t)j;
+                int64_t w0 = or_edge(b.U, b.V, c.U, c.V, px, py);
+                int64_t w1 = or_edge(c.U, c.V, a.U, a.V, px, py);
+                int64_t w2 = or_edge(a.U, a.V, b.U, b.V, px, py);
+                if (!or_inside(w0, tl0) || !or_inside(w1, tl1) || !or_inside(w2, tl2)) continue;
+                double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
+                double s = (t0 + t1) + t2;
+                double z = (double)A / s;
+                double d = nearbyint(z);
+                if (!(d >= 1.0 && d <= 65534.0)) continue;
+                uint32_t key = ((uint32_t)d << 16) | (uint32_t)t;
+                size_t k = (size_t)j * W + i;
+                if (key < zbuf[k]) zbuf[k] = key;
+            }
+        }
+    }
+
+    for (int32_t j = 0; j < H; ++j) {
+        for (int32_t i = 0; i < W; ++i) {
+            size_t k = (size_t)j * W + i;
+            uint32_t key = zbuf[k];
+            if (key == OR_EMPTY_KEY) {
+                depth[k] = 0;
+                if (tri_id) tri_id[k] = -1;
+                if (rgb) rgb[3 * k] = rgb[3 * k + 1] = rgb[3 * k + 2] = 0;
+                continue;
+            }
+            if (rgb && !m->rgb) {
+                rgb[3 * k] = rgb[3 * k + 1] = rgb[3 * k + 2] = 0;
+            }
+            int32_t t = (int32_t)(key & 0xFFFFu);
+            depth[k] = (uint16_t)(key >> 16);
+            if (tri_id) tri_id[k] = t;
+            if (rgb && m->rgb) {
+                const int32_t *ix = m->tri + 3 * (size_t)t;
+                const or_vertex a = pv[ix[0]], b = pv[ix[1]], c = pv[ix[2]];
+                int64_t px = 256 * (int64_t)i, py = 256 * (int64_t)j;
+                int64_t w0 = or_edge(b.U, b.V, c.U, c.V, px, py);
+                int64_t w1 = or_edge(c.U, c.V, a.U, a.V, px, py);
+                int64_t w2 = or_edge(a.U, a.V, b.U, b.V, px, py);
+                double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
+                double s = (t0 + t1) + t2;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double c0 = m->rgb[3 * (size_t)ix[0] + ch];
+                    double c1 = m->rgb[3 * (size_t)ix[1] + ch];
+                    double c2 = m->rgb[3 * (size_t)ix[2] + ch];
+                    double v = nearbyint(((t0 * c0 + t1 * c1) + t2 * c2) / s);
+                    if (v < 0.0) v = 0.0;
+                    if (v > 255.0) v = 255.0;
+                    rgb[3 * k + ch] = (uint8_t)v;
+                }
+            }
+        }
+    }
+    free(zbuf);
+    free(pv);
+    return 0;
+}
+
+/* Back-projection of pixel (i, j) at depth d mm to a point in 1/16 mm. */
+void oracle_backproject(const oracle_intrinsics *K, int32_t i, int32_t j, int32_t d, int32_t out[3])
+{
+    double kx = (((double)i - (double)K->cx) * 16.0) / (double)K->fx;
+    double ky = (((double)j - (double)K->cy) * 16.0) / (double)K->fy;
+    out[0] = (int32_t)nearbyint(kx * (double)d);
+    out[1] = (int32_t)nearbyint(ky * (double)d);
+    out[2] = 16 * d;
+}
+
+/* ------------------------------------------------------------------ */
+/* Colour: sRGB8 -> CIELAB, CIEDE2000                                  */
+/* ------------------------------------------------------------------ */
+
+static double or_srgb_linear64(int v)
+{
+    double c = (double)v / 255.0;
+    return c <= 0.04045 ? c / 12.92 : pow((c + 0.055) / 1.055, 2.4);
+}
+
+static double or_lab_f64(double t)
+{
+    const double e = (6.0 / 29.0) * (6.0 / 29.0) * (6.0 / 29.0);
+    return t > e ? cbrt(t) : t / (3.0 * (6.0 / 29.0) * (6.0 / 29.0)) + 4.0 / 29.0;
+}
+
+void oracle_srgb_to_lab64(const uint8_t *rgb, double *lab)
+{
+    double r = or_srgb_linear64(rgb[0]), g = or_srgb_linear64(rgb[1]), b = or_srgb_linear64(rgb[2]);
+    double X = (0.4124 * r + 0.3576 * g) + 0.1805 * b;
+    double Y = (0.2126 * r + 0.7152 * g) + 0.0722 * b;
+    double Z = (0.0193 * r + 0.1192 * g) + 0.9505 * b;
+    double Xn = (0.4124 + 0.3576) + 0.1805;
+    double Yn = (0.2126 + 0.7152) + 0.0722;
+    double Zn = (0.0193 + 0.1192) + 0.9505;
+    double fx = or_lab_f64(X / Xn), fy = or_lab_f64(Y / Yn), fz = or_lab_f64(Z / Zn);
+    lab[0] = 116.0 * fy - 16.0;
+    lab[1] = 500.0 * (fx - fy);
+    lab[2] = 200.0 * (fy - fz);
+}
+
+double oracle_ciede2000_64(const double *x, const double *y)
+{
+    const double PI = 3.14159265358979323846;
+    const double D2R = PI / 180.0, R2D = 180.0 / PI;
+    const double P25 = 6103515625.0; /* 25^7 */
+    double L1 = x[0], a1 = x[1], b1 = x[2];
+    double L2 = y[0], a2 = y[1], b2 = y[2];
+    double C1 = sqrt(a1 * a1 + b1 * b1), C2 = sqrt(a2 * a2 + b2 * b2);
+    double Cm = (C1 + C2) / 2.0;
+    double Cm7 = Cm * Cm * Cm * Cm * Cm * Cm * Cm;
+    double G = 0.5 * (1.0 - sqrt(Cm7 / (Cm7 + P25)));
+    double a1p = (1.0 + G) * a1, a2p = (1.0 + G) * a2;
+    double C1p = sqrt(a1p * a1p + b1 * b1), C2p = sqrt(a2p * a2p + b2 * b2);
+    double h1p = (a1p == 0.0 && b1 == 0.0) ? 0.0 : atan2(b1, a1p) * R2D;
+    double h2p = (a2p == 0.0 && b2 == 0.0) ? 0.0 : atan2(b2, a2p) * R2D;
+    if (h1p < 0.0) h1p += 360.0;
+    if (h2p < 0.0) h2p += 360.0;
+    double dLp = L2 - L1;
+    double dCp = C2p - C1p;
+    double dhp;
+    double CC = C1p * C2p;
+    if (CC == 0.0) dhp = 0.0;
+    else if (fabs(h2p - h1p) <= 180.0) dhp = h2p - h1p;
+    else if (h2p - h1p > 180.0) dhp = h2p - h1p - 360.0;
+    else dhp = h2p - h1p + 360.0;
+    double dHp = 2.0 * sqrt(CC) * sin(dhp * D2R / 2.0);
+    double Lmp = (L1 + L2) / 2.0;
+    double Cmp = (C1p + C2p) / 2.0;
+    double hmp;
+    if (CC == 0.0) hmp = h1p + h2p;
+    else if (fabs(h1p - h2p) <= 180.0) hmp = (h1p + h2p) / 2.0;
+    else if (h1p + h2p < 360.0) hmp = (h1p + h2p + 360.0) / 2.0;
+    else hmp = (h1p + h2p - 360.0) / 2.0;
+    double T = 1.0 - 0.17 * cos((hmp - 30.0) * D2R) + 0.24 * cos(2.0 * hmp * D2R)
+               + 0.32 * cos((3.0 * hmp + 6.0) * D2R) - 0.20 * cos((4.0 * hmp - 63.0) * D2R);
+    double dth = 30.0 * exp(-((hmp - 275.0) / 25.0) * ((hmp - 275.0) / 25.0));
+    double Cmp7 = Cmp * Cmp * Cmp * Cmp * Cmp * Cmp * Cmp;
+    double RC = 2.0 * sqrt(Cmp7 / (Cmp7 + P25));
+    double Lm50 = (Lmp - 50.0) * (Lmp - 50.0);
+    double SL = 1.0 + 0.015 * Lm50 / sqrt(20.0 + Lm50);
+    double SC = 1.0 + 0.045 * Cmp;
+    double SH = 1.0 + 0.015 * Cmp * T;
+    double RT = -sin(2.0 * dth * D2R) * RC;
+    double tL = dLp / SL, tC = dCp / SC, tH = dHp / SH;
+    return sqrt(tL * tL + tC * tC + tH * tH + RT * tC * tH);
+}
+
+/* binary32 twins: the precision in which the colour decision is taken. */
+static float or_lin32_table[256];
+static int or_lin32_ready = 0;
+
+static void or_lin32_init(void)
+{
+    if (or_lin32_ready) return;
+    for (int v = 0; v < 256; ++v) or_lin32_table[v] = (float)or_srgb_linear64(v);
+    or_lin32_ready = 1;
+}
+
+static float or_lab_f32(float t)
+{
+    const float e = 216.0f / 24389.0f;          /* (6/29)^3 */
+    const float k = 841.0f / 108.0f;            /* 1 / (3 (6/29)^2) */
+    return t > e ? cbrtf(t) : t * k + 4.0f / 29.0f;
+}
+
+void oracle_srgb_to_lab32(const uint8_t *rgb, float *lab)
+{
+    or_lin32_init();
+    float r = or_lin32_table[rgb[0]], g = or_lin32_table[rgb[1]], b = or_lin32_table[rgb[2]];
+    float X = (0.4124f * r + 0.3576f * g) + 0.1805f * b;
+    float Y = (0.2126f * r + 0.7152f * g) + 0.0722f * b;
+    float Z = (0.0193f * r + 0.1192f * g) + 0.9505f * b;
+    float Xn = (0.4124f + 0.3576f) + 0.1805f;
+    float Yn = (0.2126f + 0.7152f) + 0.0722f;
+    float Zn = (0.0193f + 0.1192f) + 0.9505f;
+    float fx = or_lab_f32(X / Xn), fy = or_lab_f32(Y / Yn), fz = or_lab_f32(Z / Zn);
+    lab[0] = 116.0f * fy - 16.0f;
+    lab[1] = 500.0f * (fx - fy);
+    lab[2] = 200.0f * (fy - fz);
+}
+
+float oracle_ciede2000_32(const float *x, const float *y)
+{
+    const float D2R = 0.017453292519943295f, R2D = 57.29577951308232f;
+    const float P25 = 6103515625.0f;
+    float L1 = x[0], a1 = x[1], b1 = x[2];
+    float L2 = y[0], a2 = y[1], b2 = y[2];
+    float C1 = sqrtf(a1 * a1 + b1 * b1), C2 = sqrtf(a2 * a2 + b2 * b2);
+    float Cm = (C1 + C2) * 0.5f;
+    float Cm2 = Cm * Cm;
+    float Cm7 = ((Cm2 * Cm2) * Cm2) * Cm;
+    float G = 0.5f * (1.0f - sqrtf(Cm7 / (Cm7 + P25)));
+    float a1p = (1.0f + G) * a1, a2p = (1.0f + G) * a2;
+    float C1p = sqrtf(a1p * a1p + b1 * b1), C2p = sqrtf(a2p * a2p + b2 * b2);
+    float h1p = (a1p == 0.0f && b1 == 0.0f) ? 0.0f : atan2f(b1, a1p) * R2D;
+    float h2p = (a2p == 0.0f && b2 == 0.0f) ? 0.0f : atan2f(b2, a2p) * R2D;
+    if (h1p < 0.0f) h1p += 360.0f;
+    if (h2p < 0.0f) h2p += 360.0f;
+    float dLp = L2 - L1;
+    float dCp = C2p - C1p;
+    float CC = C1p * C2p;
+    float dhp;
+    if (CC == 0.0f) dhp = 0.0f;
+    else if (fabsf(h2p - h1p) <= 180.0f) dhp = h2p - h1p;
+    else if (h2p - h1p > 180.0f) dhp = h2p - h1p - 360.0f;
+    else dhp = h2p - h1p + 360.0f;
+    float dHp = 2.0f * sqrtf(CC) * sinf(dhp * D2R * 0.5f);
+    float Lmp = (L1 + L2) * 0.5f;
+    float Cmp = (C1p + C2p) * 0.5f;
+    float hmp;
+    if (CC == 0.0f) hmp = h1p + h2p;
+    else if (fabsf(h1p - h2p) <= 180.0f) hmp = (h1p + h2p) * 0.5f;
+    else if (h1p + h2p < 360.0f) hmp = (h1p + h2p + 360.0f) * 0.5f;
+    else hmp = (h1p + h2p - 360.0f) * 0.5f;
+    float T = 1.0f - 0.17f * cosf((hmp - 30.0f) * D2R) + 0.24f * cosf(2.0f * hmp * D2R)
+              + 0.32f * cosf((3.0f * hmp + 6.0f) * D2R) - 0.20f * cosf((4.0f * hmp - 63.0f) * D2R);
+    float hq = (hmp - 275.0f) / 25.0f;
+    float dth = 30.0f * expf(-(hq * hq));
+    float Cmp2 = Cmp * Cmp;
+    float Cmp7 = ((Cmp2 * Cmp2) * Cmp2) * Cmp;
+    float RC = 2.0f * sqrtf(Cmp7 / (Cmp7 + P25));
+    float Lm50 = (Lmp - 50.0f) * (Lmp - 50.0f);
+    float SL = 1.0f + 0.015f * Lm50 / sqrtf(20.0f + Lm50);
+    float SC = 1.0f + 0.045f * Cmp;
+    float SH = 1.0f + 0.015f * Cmp * T;
+    float RT = -sinf(2.0f * dth * D2R) * RC;
+    float tL = dLp / SL, tC = dCp / SC, tH = dHp / SH;
+    return sqrtf(tL * tL + tC * tC + tH * tH + RT * tC * tH);
+}
+
+/* ------------------------------------------------------------------ */
+/* Cost (Eq. 3 / Eq. 4) by brute force                                 */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n;
+    int32_t *x, *y, *z, *pix;
+    float *lab; /* n * 3, RGB mode only */
+} or_cloud;
+
+static void or_cloud_free(or_cloud *c)
+{
+    free(c->x); free(c->y); free(c->z); free(c->pix); free(c->lab);
+    memset(c, 0, sizeof(*c));
+}
+
+static int or_cloud_alloc(or_cloud *c, size_t n, int with_lab)
+{
+    memset(c, 0, sizeof(*c));
+    size_t m = n ? n : 1;
+    c->x = (int32_t *)malloc(m * sizeof(int32_t));
+    c->y = (int32_t *)malloc(m * sizeof(int32_t));
+    c->z = (int32_t *)malloc(m * sizeof(int32_t));
+    c->pix = (int32_t *)malloc(m * sizeof(int32_t));
+    c->lab = with_lab ? (float *)malloc(m * 3 * sizeof(float)) : NULL;
+    if (!c->x || !c->y || !c->z || !c->pix || (with_lab && !c->lab)) { or_cloud_free(c); return -1; }
+    return 0;
+}
+
+/* For point p (coords px,py,pz) search cloud c.  Returns 1 if any point is
+ * within dq.  If want_nn, *nn is the index (into c) of the nearest one, ties
+ * broken by the lower pixel index. */
+static int or_search(const or_cloud *c, int64_t px, int64_t py, int64_t pz, int64_t dq2,
+                     int64_t dq, int want_nn, int32_t *nn)
+{
+    int found = 0;
+    int64_t best_d2 = 0;
+    int32_t best_pix = 0, best = -1;
+    for (int32_t k = 0; k < c->n; ++k) {
+        int64_t dz = (int64_t)c->z[k] - pz;
+        if (dz > dq || dz < -dq) continue; /* then dz^2 alone exceeds dq^2 */
+        int64_t dx = (int64_t)c->x[k] - px, dy = (int64_t)c->y[k] - py;
+        int64_t d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 > dq2) continue;
+        if (!want_nn) return 1;
+        if (!found || d2 < best_d2 || (d2 == best_d2 && c->pix[k] < best_pix)) {
+            best_d2 = d2; best_pix = c->pix[k]; best = k;
+        }
+        found = 1;
+    }
+    if (nn) *nn = best;
+    return found;
+}
+
+/* Score one pose; optionally fill per-pixel detail images:
+ *  r_flag[k]: 0 not in R, 1 inlier, 2 outlier (distance), 3 outlier (colour), 4 occluded
+ *  o_flag[k]: 0 not in Vset, 1 explained, 2 outlier (distance), 3 outlier (colour) */
+static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t label,
+                        const float *pose, const or_cloud *obs, int32_t out[4],
+                        uint8_t *r_flag, uint8_t *o_flag)
+{
+    const oracle_intrinsics *K = &sc->K;
+    const int W = K->width, H = K->height;
+    const size_t N = (size_t)W * H;
+    const int use_rgb = (sc->flags & OR_USE_RGB) != 0;
+    const int mark = (sc->flags & OR_MARK_OCCLUDERS) != 0;
+    const uint32_t vol = sc->flags & OR_VOL_MASK;
+    const int64_t dq = (int64_t)nearbyint(16.0 * (double)sc->delta_mm);
+    const int64_t dq2 = dq * dq;
+    const int stride = sc->stride;
+    int rc = 0;
+
+    uint16_t *dren = (uint16_t *)malloc(N * sizeof(uint16_t));
+    uint8_t *cren = use_rgb ? (uint8_t *)malloc(N * 3) : NULL;
+    or_cloud R;
+    if (!dren || (use_rgb && !cren) || or_cloud_alloc(&R, N, use_rgb)) {
+        free(dren); free(cren); return -2;
+    }
+    if (oracle_render(m, pose, K, dren, NULL, cren) != 0) { rc = -1; goto done; }
+
+    /* R \ C : rendered, on the stride grid, not occluded (R6, R7). */
+    R.n = 0;
+    for (int32_t j = 0; j < H; ++j) {
+        for (int32_t i = 0; i < W; ++i) {
+            size_t k = (size_t)j * W + i;
+            if (r_flag) r_flag[k] = 0;
+            int32_t d = dren[k];
+            if (d == 0) continue;
+            if (i % stride != 0 || j % stride != 0) continue;
+            int32_t dob = sc->depth[k];
+            if (mark && dob > 0 && 16 * (int64_t)dob + dq < 16 * (int64_t)d) {
+                int other = !(vol == OR_VOL_LABEL && sc->labels) || sc->labels[k] != label;
+                if (other) { if (r_flag) r_flag[k] = 4; continue; }
+            }
+            int32_t p[3];
+            oracle_backproject(K, i, j, d, p);
+            R.x[R.n] = p[0]; R.y[R.n] = p[1]; R.z[R.n] = p[2]; R.pix[R.n] = (int32_t)k;
+            if (use_rgb) oracle_srgb_to_lab32(cren + 3 * k, R.lab + 3 * (size_t)R.n);
+            R.n++;
+        }
+    }
+
+    /* J_r: every rendered point against the whole observed cloud. */
+    int32_t jr = 0;
+    for (int32_t r = 0; r < R.n; ++r) {
+        int32_t nn = -1;
+        int found = or_search(obs, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb, &nn);
+        int flag = 1;
+        if (!found) flag = 2;
+        else if (use_rgb && oracle_ciede2000_32(R.lab + 3 * (size_t)r, obs->lab + 3 * (size_t)nn) > sc->tau_c) flag = 3;
+        if (flag != 1) jr++;
+        if (r_flag) r_flag[R.pix[r]] = (uint8_t)flag;
+    }
+
+    /* J_o: every observed point inside V(O) against the whole render. */
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = (double)m->xyz[a]; hi[a] = (double)m->xyz[a]; }
+    for (int32_t v = 1; v < m->n_verts; ++v)
+        for (int a = 0; a < 3; ++a) {
+            double c = (double)m->xyz[3 * (size_t)v + a];
+            if (c < lo[a]) lo[a] = c;
+            if (c > hi[a]) hi[a] = c;
+        }
+    const double dl = (double)sc->delta_mm;
+    int32_t jo = 0, q = 0;
+    for (int32_t p = 0; p < obs->n; ++p) {
+        int32_t k = obs->pix[p];
+        if (o_flag) o_flag[k] = 0;
+        int in;
+        if (vol == OR_VOL_LABEL) {
+            in = sc->labels && sc->labels[k] == label;
+        } else {
+            double e0 = (double)obs->x[p] / 16.0 - (double)pose[3];
+            double e1 = (double)obs->y[p] / 16.0 - (double)pose[7];
+            double e2 = (double)obs->z[p] / 16.0 - (double)pose[11];
+            double q0 = ((double)pose[0] * e0 + (double)pose[4] * e1) + (double)pose[8] * e2;
+            double q1 = ((double)pose[1] * e0 + (double)pose[5] * e1) + (double)pose[9] * e2;
+            double q2 = ((double)pose[2] * e0 + (double)pose[6] * e1) + (double)pose[10] * e2;
+            in = (lo[0] - dl <= q0) && (q0 <= hi[0] + dl) && (lo[1] - dl <= q1) && (q1 <= hi[1] + dl)
+                 && (lo[2] - dl <= q2) && (q2 <= hi[2] + dl);
+        }
+        if (!in) continue;
+        q++;
+        int32_t nn = -1;
+        int found = or_search(&R, obs->x[p], obs->y[p], obs->z[p], dq2, dq, use_rgb, &nn);
+        int flag = 1;
+        if (!found) flag = 2;
+        else if (use_rgb && oracle_ciede2000_32(obs->lab + 3 * (size_t)p, R.lab + 3 * (size_t)nn) > sc->tau_c) flag = 3;
+        if (flag != 1) jo++;
+        if (o_flag) o_flag[k] = (uint8_t)flag;
+    }
+    out[0] = jr; out[1] = jo; out[2] = R.n; out[3] = q;
+done:
+    free(dren); free(cren); or_cloud_free(&R);
+    return rc;
+}
+
+static int or_scene_valid(const oracle_mesh *m, const oracle_scene *sc)
+{
+    if (sc->K.width <= 0 || sc->K.height <= 0 || !sc->depth) return 0;
+    if (!(sc->delta_mm > 0.0f) || sc->stride < 1) return 0;
+    if ((sc->flags & OR_USE_RGB) && (!sc->rgb || !m->rgb)) return 0;
+    uint32_t vol = sc->flags & OR_VOL_MASK;
+    if (vol != OR_VOL_AABB && vol != OR_VOL_LABEL) return 0;
+    if (vol == OR_VOL_LABEL && !sc->labels) return 0;
+    for (int32_t t = 0; t < 3 * m->n_tris; ++t)
+        if (m->tri[t] < 0 || m->tri[t] >= m->n_verts) return 0;
+    return 1;
+}
+
+static int or_observed_cloud(const oracle_scene *sc, or_cloud *obs)
+{
+    const int W = sc->K.width, H = sc->K.height;
+    const int use_rgb = (sc->flags & OR_USE_RGB) != 0;
+    size_t n = 0;
+    for (size_t k = 0; k < (size_t)W * H; ++k) n += sc->depth[k] > 0;
+    if (or_cloud_alloc(obs, n, use_rgb)) return -2;
+    obs->n = 0;
+    for (int32_t j = 0; j < H; ++j)
+        for (int32_t i = 0; i < W; ++i) {
+            size_t k = (size_t)j * W + i;
+            if (sc->depth[k] == 0) continue;
+            int32_t p[3];
+            oracle_backproject(&sc->K, i, j, sc->depth[k], p);
+            obs->x[obs->n] = p[0]; obs->y[obs->n] = p[1]; obs->z[obs->n] = p[2];
+            obs->pix[obs->n] = (int32_t)k;
+            if (use_rgb) oracle_srgb_to_lab32(sc->rgb + 3 * k, obs->lab + 3 * (size_t)obs->n);
+            obs->n++;
+        }
+    return 0;
+}
+
+/* Score n poses (n x 12 binary32, row-major [R|t], object -> camera, mm).
+ * Outputs jr, jo, nr (= L, the size of R \ C) and nq (= Q, the size of the
+ * observed set inside V).  n_threads <= 0 uses the OpenMP default. */
+int oracle_score(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses,
+                 int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, int32_t n_threads)
+{
+    if (n < 0 || !or_scene_valid(m, sc) || m->n_tris > 65536) return -1;
+    or_lin32_init();
+    or_cloud obs;
+    if (or_observed_cloud(sc, &obs)) return -2;
+    int err = 0;
+#ifdef _OPENMP
+    int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : err)
+#endif
+    for (int32_t p = 0; p < n; ++p) {
+        int32_t out[4] = {0, 0, 0, 0};
+        int rc = or_score_one(m, sc, label, poses + 12 * (size_t)p, &obs, out, NULL, NULL);
+        if (rc) err |= 1;
+        jr[p] = out[0]; jo[p] = out[1];
+        if (nr) nr[p] = out[2];
+        if (nq) nq[p] = out[3];
+    }
+    (void)n_threads;
+    or_cloud_free(&obs);
+    return err ? -2 : 0;
+}
+
+/* One pose, with per-pixel classification images (see or_score_one). */
+int oracle_score_detail(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
+                        int32_t out[4], uint8_t *r_flag, uint8_t *o_flag)
+{
+    if (!or_scene_valid(m, sc) || m->n_tris > 65536) return -1;
+    or_lin32_init();
+    or_cloud obs;
+    if (or_observed_cloud(sc, &obs)) return -2;
+    size_t N = (size_t)sc->K.width * sc->K.height;
+    if (o_flag) memset(o_flag, 0, N);
+    int rc = or_score_one(m, sc, label, pose, &obs, out, r_flag, o_flag);
+    or_cloud_free(&obs);
+    return rc;
+}
+
+/* Minimum of J = jr + jo; ties go to the lowest index.  n_ties counts the
+ * poses that share the minimum. */
+int oracle_best(const int32_t *jr, const int32_t *jo, int32_t n, int32_t *best_idx,
+                int32_t *best_cost, int32_t *n_ties)
+{
+    if (n <= 0) return -1;
+    int32_t bi = 0;
+    int64_t bc = (int64_t)jr[0] + jo[0];
+    int32_t ties = 1;
+    for (int32_t p = 1; p < n; ++p) {
+        int64_t c = (int64_t)jr[p] + jo[p];
+        if (c < bc) { bc = c; bi = p; ties = 1; }
+        else if (c == bc) ties++;
+    }
+    *best_idx = bi;
+    *best_cost = (int32_t)bc;
+    if (n_ties) *n_ties = ties;
+    return 0;
+}

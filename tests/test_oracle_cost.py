@@ -1,0 +1,268 @@
+"""Pins for the oracle's explanation cost (Eq. 3, Eq. 4) and selection (CPU only).
+
+The cost is checked against an independent radius search (scipy's k-d tree on
+the same 1/16 mm points: every coordinate is an exact binary fraction, so the
+float64 distances decide exactly like the integer predicate), against the
+self-render identity (a noiseless scene scored at its own pose costs zero),
+against the occluder rule written as a set, and against monotonicity and
+bound invariants.
+"""
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle
+from tiny_meshes import TMesh, TScene, box, pose_matrix, rot_x, rot_z
+
+K = (80, 60, 90.0, 90.0, 40.0, 30.0)
+DELTA = 10.0
+
+
+def _table_cam():
+    # camera looking down 45 degrees at the world origin from 0.8 m
+    c = np.array([0.0, -800 * np.cos(np.pi / 4), 800 * np.sin(np.pi / 4)])
+    f = -c / np.linalg.norm(c)
+    right = np.cross(f, [0, 0, 1.0]); right /= np.linalg.norm(right)
+    down = np.cross(f, right)
+    Rcw = np.stack([right, down, f])
+    return Rcw, c
+
+
+def _obj_pose(x, y, yaw):
+    Rcw, c = _table_cam()
+    R = Rcw @ rot_z(yaw)
+    t = Rcw @ (np.array([x, y, 0.0]) - c)
+    return pose_matrix(R, t)
+
+
+def _compose(parts, Kc):
+    """z-composite oracle renders: parts = [(mesh, pose, label)]"""
+    W, H = Kc[0], Kc[1]
+    depth = np.zeros((H, W), np.uint16)
+    rgb = np.zeros((H, W, 3), np.uint8)
+    lab = np.zeros((H, W), np.int32)
+    for mesh, pose, label in parts:
+        d, _, c = oracle.render(mesh, pose, Kc)
+        take = (d > 0) & ((depth == 0) | (d < depth))
+        depth[take] = d[take]
+        rgb[take] = c[take]
+        lab[take] = label
+    return depth, rgb, lab
+
+
+OBJ = box((-40, -30, 0), (40, 30, 120), n=3, rgb_seed=11)
+TABLE = box((-400, -400, -20), (400, 400, 0), n=2, rgb_seed=None)
+TABLE.rgb = np.full((len(TABLE.xyz), 3), 128, np.uint8)
+
+
+def _scene(seed, noise=2.0, occluder=True):
+    rng = np.random.default_rng(seed)
+    gt = (rng.uniform(-30, 30), rng.uniform(-30, 30), rng.uniform(0, 2 * np.pi))
+    parts = [(TABLE, _obj_pose(0, 0, 0), 0), (OBJ, _obj_pose(*gt), 1)]
+    if occluder:
+        occ = box((-15, -15, 0), (15, 15, 200), n=1, rgb_seed=5)
+        parts.append((occ, _obj_pose(gt[0] + 20, gt[1] - 90, 0.3), 2))
+    d, c, lab = _compose(parts, K)
+    valid = d > 0
+    dn = np.rint(d + rng.normal(0, noise, d.shape)).clip(1, 65534).astype(np.uint16)
+    dn[~valid] = 0
+    cn = np.clip(np.rint(c + rng.normal(0, 5, c.shape)), 0, 255).astype(np.uint8)
+    return TScene(K, dn, cn, lab), gt
+
+
+def _points(depth, Kc, mask):
+    js, is_ = np.nonzero(mask)
+    pts = np.array([oracle.backproject(Kc, i, j, depth[j, i]) for j, i in zip(js, is_)], np.float64).reshape(-1, 3)
+    return pts, (js * Kc[0] + is_)
+
+
+def _independent_cost(mesh, scene, pose, delta, tau, flags, stride, label):
+    """J_r, J_o, L, Q from scipy k-d trees over the oracle's points."""
+    W, H = scene.K[0], scene.K[1]
+    dr, _, cr = oracle.render(mesh, pose, scene.K)
+    dq = int(np.rint(16 * delta))
+    jj, ii = np.mgrid[0:H, 0:W]
+    inR = (dr > 0) & (ii % stride == 0) & (jj % stride == 0)
+    if flags & oracle.MARK_OCCLUDERS:
+        occ = (scene.depth > 0) & (scene.depth.astype(np.int64) < dr.astype(np.int64) - dq / 16.0)
+        if (flags & 0x30) == oracle.VOL_LABEL:
+            occ &= scene.labels != label
+        inR &= ~occ
+    R, rpix = _points(dr, scene.K, inR)
+    I, ipix = _points(scene.depth, scene.K, scene.depth > 0)
+    use_rgb = bool(flags & oracle.USE_RGB)
+    r16 = dq / 16.0
+
+    def nn_search(src, spix, dst, dpix):
+        # returns per src point: has neighbour, index (into dst) of nearest with pixel tie-break
+        out = np.full(len(src), -1)
+        if len(dst) == 0 or len(src) == 0:
+            return out
+        tree = cKDTree(dst / 16.0)
+        lists = tree.query_ball_point(src / 16.0, r16 * (1 + 1e-12))
+        for k, lst in enumerate(lists):
+            best = None
+            for m in lst:
+                d2 = int(((dst[m] - src[k]) ** 2).sum())
+                if d2 > dq * dq:
+                    continue
+                key = (d2, dpix[m])
+                if best is None or key < best[0]:
+                    best = (key, m)
+            if best is not None:
+                out[k] = best[1]
+        return out
+
+    nr = nn_search(R, rpix, I, ipix)
+    if (flags & 0x30) == oracle.VOL_LABEL:
+        inV = scene.labels.reshape(-1)[ipix] == label
+    else:
+        P = pose.reshape(3, 4).astype(np.float64)
+        lo = mesh.xyz.astype(np.float64).min(0) - delta
+        hi = mesh.xyz.astype(np.float64).max(0) + delta
+        q = (I / 16.0 - P[:, 3]) @ P[:, :3]
+        inV = np.all((q >= lo) & (q <= hi), axis=1)
+    no = nn_search(I[inV], ipix[inV], R, rpix)
+
+    def lab32(c):
+        return oracle.srgb_to_lab32(c)
+
+    jr = 0
+    for k in range(len(R)):
+        if nr[k] < 0:
+            jr += 1
+        elif use_rgb:
+            a = lab32(cr.reshape(-1, 3)[rpix[k]])
+            b = lab32(scene.rgb.reshape(-1, 3)[ipix[nr[k]]])
+            jr += oracle.ciede2000_32(a, b) > tau
+    jo = 0
+    Iv, ivpix = I[inV], ipix[inV]
+    for k in range(len(Iv)):
+        if no[k] < 0:
+            jo += 1
+        elif use_rgb:
+            a = lab32(scene.rgb.reshape(-1, 3)[ivpix[k]])
+            b = lab32(cr.reshape(-1, 3)[rpix[no[k]]])
+            jo += oracle.ciede2000_32(a, b) > tau
+    return jr, jo, len(R), int(inV.sum())
+
+
+def test_self_render_costs_zero():
+    for seed in range(3):
+        rng = np.random.default_rng(seed)
+        pose = _obj_pose(rng.uniform(-20, 20), rng.uniform(-20, 20), rng.uniform(0, 6.28))
+        d, _, c = oracle.render(OBJ, pose, K)
+        scene = TScene(K, d, c, None)
+        for flags in (oracle.MARK_OCCLUDERS, oracle.MARK_OCCLUDERS | oracle.USE_RGB, oracle.USE_RGB):
+            jr, jo, nr, nq = oracle.score(OBJ, scene, pose[None], delta_mm=DELTA, tau_c=0.0, flags=flags)
+            assert jr[0] == 0 and jo[0] == 0
+            assert nr[0] == (d > 0).sum() and nq[0] == (d > 0).sum()
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("flags,stride", [(oracle.MARK_OCCLUDERS, 1), (0, 1), (oracle.MARK_OCCLUDERS | oracle.USE_RGB, 1),
+                                          (oracle.MARK_OCCLUDERS, 2), (oracle.USE_RGB, 3)])
+def test_cost_matches_kdtree_search(seed, flags, stride):
+    scene, gt = _scene(seed)
+    rng = np.random.default_rng(1000 + seed)
+    poses = [_obj_pose(*gt)] + [_obj_pose(gt[0] + rng.uniform(-25, 25), gt[1] + rng.uniform(-25, 25),
+                                          rng.uniform(0, 6.28)) for _ in range(3)]
+    poses = np.stack(poses)
+    jr, jo, nr, nq = oracle.score(OBJ, scene, poses, delta_mm=DELTA, tau_c=20.0, flags=flags, stride=stride)
+    for k in range(len(poses)):
+        exp = _independent_cost(OBJ, scene, poses[k], DELTA, 20.0, flags, stride, 1)
+        assert (jr[k], jo[k], nr[k], nq[k]) == exp
+
+
+def test_label_mode_matches_kdtree_search():
+    scene, gt = _scene(7)
+    flags = oracle.MARK_OCCLUDERS | oracle.USE_RGB | oracle.VOL_LABEL
+    poses = np.stack([_obj_pose(*gt), _obj_pose(gt[0] + 12, gt[1] - 5, gt[2] + 0.4)])
+    jr, jo, nr, nq = oracle.score(OBJ, scene, poses, delta_mm=DELTA, tau_c=20.0, flags=flags, label=1)
+    for k in range(2):
+        assert (jr[k], jo[k], nr[k], nq[k]) == _independent_cost(OBJ, scene, poses[k], DELTA, 20.0, flags, 1, 1)
+    assert nq[0] == (scene.labels == 1).sum() - ((scene.labels == 1) & (scene.depth == 0)).sum()
+
+
+def test_occluder_set_is_the_rule():
+    scene, gt = _scene(3)
+    pose = _obj_pose(*gt)
+    (_, _, L, _), rf, _ = oracle.score_detail(OBJ, scene, pose, delta_mm=DELTA, flags=oracle.MARK_OCCLUDERS)
+    dr = oracle.render(OBJ, pose, K)[0].astype(np.int64)
+    do = scene.depth.astype(np.int64)
+    rule = (dr > 0) & (do > 0) & (do < dr - DELTA)
+    assert np.array_equal(rf == 4, rule)
+    assert rule.sum() > 0
+    assert L == ((dr > 0) & ~rule).sum()
+
+
+def test_occluder_marking_lowers_jr_at_ground_truth():
+    scene, gt = _scene(3)
+    pose = _obj_pose(*gt)[None]
+    on = oracle.score(OBJ, scene, pose, delta_mm=DELTA, flags=oracle.MARK_OCCLUDERS)
+    off = oracle.score(OBJ, scene, pose, delta_mm=DELTA, flags=0)
+    dropped = off[2][0] - on[2][0]
+    assert dropped > 0
+    assert on[0][0] < off[0][0]
+    assert off[0][0] - on[0][0] <= dropped
+
+
+def test_monotone_in_delta_and_bounds():
+    scene, gt = _scene(4)
+    rng = np.random.default_rng(9)
+    poses = np.stack([_obj_pose(gt[0] + rng.uniform(-20, 20), gt[1] + rng.uniform(-20, 20), rng.uniform(0, 6.28))
+                      for _ in range(4)])
+    prev = None
+    for delta in (2.0, 5.0, 10.0, 20.0, 40.0):
+        jr, jo, nr, nq = oracle.score(OBJ, scene, poses, delta_mm=delta, flags=0)
+        assert np.all((0 <= jr) & (jr <= nr)) and np.all((0 <= jo) & (jo <= nq))
+        if prev is not None:
+            assert np.all(jr <= prev[0])
+            assert np.all(nr == prev[2])
+        prev = (jr, jo, nr, nq)
+
+
+def test_rgb_outliers_superset_of_depth_outliers():
+    scene, gt = _scene(5)
+    pose = _obj_pose(gt[0] + 6, gt[1] - 4, gt[2] + 0.2)
+    _, rf_d, of_d = oracle.score_detail(OBJ, scene, pose, delta_mm=DELTA, flags=oracle.MARK_OCCLUDERS)
+    _, rf_c, of_c = oracle.score_detail(OBJ, scene, pose, delta_mm=DELTA, tau_c=20.0,
+                                        flags=oracle.MARK_OCCLUDERS | oracle.USE_RGB)
+    assert np.all((rf_c >= 2) | (rf_d < 2))
+    assert np.all((of_c >= 2) | (of_d < 2))
+    assert np.array_equal(rf_c > 0, rf_d > 0) and np.array_equal(of_c > 0, of_d > 0)
+
+
+def test_empty_render_and_empty_volume():
+    scene, _ = _scene(6)
+    behind = pose_matrix(np.eye(3), (0, 0, -1000))
+    jr, jo, nr, nq = oracle.score(OBJ, scene, behind[None], delta_mm=DELTA, flags=oracle.MARK_OCCLUDERS)
+    assert nr[0] == 0 and jr[0] == 0
+    assert nq[0] == 0 and jo[0] == 0  # V is behind the camera as well
+    far = pose_matrix(np.eye(3), (0, 0, 60000))
+    jr, jo, nr, nq = oracle.score(OBJ, scene, far[None], delta_mm=DELTA, flags=oracle.MARK_OCCLUDERS)
+    assert jr[0] == nr[0] and jo[0] == nq[0]
+
+
+def test_tiny_grid_argmin_finds_ground_truth():
+    # noiseless scene of the object alone at a grid pose; 3 x 3 x 4 grid
+    grid = [(x, y, yaw) for x in (-20, 0, 20) for y in (-20, 0, 20) for yaw in (0, np.pi / 2, np.pi, 3 * np.pi / 2)]
+    gt_idx = 4 * 4 + 1
+    Ks = (64, 48, 80.0, 80.0, 32.0, 24.0)
+    d, _, c = oracle.render(OBJ, _obj_pose(*grid[gt_idx]), Ks)
+    scene = TScene(Ks, d, c, None)
+    poses = np.stack([_obj_pose(*g) for g in grid])
+    for flags in (oracle.MARK_OCCLUDERS, oracle.MARK_OCCLUDERS | oracle.USE_RGB):
+        jr, jo, _, _ = oracle.score(OBJ, scene, poses, delta_mm=DELTA, tau_c=20.0, flags=flags)
+        J = jr + jo
+        assert J[gt_idx] == 0
+        bi, bc, nt = oracle.best(jr, jo)
+        assert bc == 0 and J[bi] == 0 and bi == int(np.flatnonzero(J == 0)[0])
+        assert nt == int((J == 0).sum())
+
+
+def test_best_ties_lowest_index():
+    jr = np.array([5, 3, 2, 4, 1], np.int32)
+    jo = np.array([0, 1, 2, 0, 3], np.int32)
+    assert oracle.best(jr, jo) == (1, 4, 4)
+    assert oracle.best(np.array([7], np.int32), np.array([0], np.int32)) == (0, 7, 1)
