@@ -1,0 +1,159 @@
+/*
+ * perch.h -- C ABI of the MI355X pose-scoring library (libperch.so).
+ *
+ * The library scores candidate 6-DoF object poses against an observed RGB-D
+ * scene with the explanation cost of PERCH 2.0 (Agarwal, Han, Likhachev):
+ *   J = J_r + J_o                                      (Sec. III-B, Eq. 1)
+ *   J_r = rendered points, minus the occluded ones, with no observed point
+ *         within delta                                 (Eq. 2, Eq. 3)
+ *   J_o = observed points inside the object's volume with no rendered point
+ *         within delta                                 (Eq. 2, Eq. 3)
+ * and, with the RGB term, a point whose nearest neighbour lies within delta
+ * is still an outlier when their CIEDE2000 colour difference exceeds tau_c
+ * (Sec. IV-B, Eq. 4).  Each pose is rendered into depth (and colour) and
+ * back-projected to points (Sec. IV-A "Parallel Rendering"); the best pose of
+ * each object is the one of minimum cost (Sec. IV-A "Parallel Search").
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a perch_status; PERCH_OK is 0.  On error nothing is
+ *    launched, no state changes, and perch_last_error() (thread-local) holds
+ *    a message.  No C++ exception crosses the ABI.
+ *  - Lengths are millimetres.  A pose is 12 binary32 values, row-major
+ *    [R | t], mapping object coordinates to camera coordinates (x right,
+ *    y down, z forward).  Intrinsics follow the pinhole model, and integer
+ *    pixel coordinates are pixel centres.
+ *  - Pointers named *_dev are device memory owned by the caller; they must
+ *    stay valid until the work queued on the given stream has completed.
+ *    Host pointers are read during the call only.
+ *  - Results are deterministic: the same inputs give bit-identical outputs,
+ *    whatever else is queued on the device.
+ *  - A context belongs to one device; calls on one context from several
+ *    threads are serialised internally.
+ *
+ * Geometry, depth, coverage, point coordinates and all depth-only counts are
+ * exact integers (8 sub-pixel bits, top-left fill rule, 16-bit millimetre
+ * depth buffer, points in 1/16 mm).  The colour decision is taken in binary32
+ * CIELAB/CIEDE2000.
+ */
+#ifndef PERCH_H
+#define PERCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PERCH_OK = 0,
+    PERCH_EINVAL = -1,    /* bad argument: sizes, indices, flags, null pointers */
+    PERCH_ENOMEM = -2,    /* the context's HBM budget (or the device) is exhausted */
+    PERCH_EDEVICE = -3,   /* a HIP runtime call failed */
+    PERCH_ENOTFOUND = -4, /* unknown mesh or scene id */
+    PERCH_EBUSY = -5      /* the object is in use (e.g. unload while queued) */
+} perch_status;
+
+typedef struct perch_ctx perch_ctx;
+
+/* Scene flags. */
+#define PERCH_USE_RGB 1u           /* Eq. 4 colour term (needs scene and mesh colours) */
+#define PERCH_MARK_OCCLUDERS 2u    /* Eq. 3 occluders C from the observed depth */
+#define PERCH_VOL_AABB (0u << 4)   /* V(O): object-frame mesh AABB inflated by delta */
+#define PERCH_VOL_LABEL (2u << 4)  /* V(O): observed pixels carrying the object's label (Sec. V-C) */
+#define PERCH_VOL_MASK (3u << 4)
+
+typedef struct {
+    int32_t width, height;   /* pixels, 1 .. 4096 */
+    float fx, fy, cx, cy;    /* fx, fy > 0 */
+} perch_intrinsics;
+
+typedef struct {
+    perch_intrinsics K;
+    const uint16_t *depth_mm; /* H*W row-major host array, 0 = no reading (required) */
+    const uint8_t *rgb;       /* H*W*3 sRGB8 host array, or NULL (depth only) */
+    const int32_t *labels;    /* H*W host array, or NULL (required for PERCH_VOL_LABEL) */
+    float delta_mm;           /* sensor resolution delta, 0 < delta <= 500 */
+    float tau_c;              /* CIEDE2000 threshold tau_c >= 0, used with PERCH_USE_RGB */
+    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* */
+    int32_t stride;           /* image-space downsampling of the render, >= 1 (Sec. IV-A) */
+} perch_scene_desc;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory held for meshes, scenes and work buffers (0 = no cap).  The context
+ * owns one HIP stream used when a call passes a NULL stream. */
+perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out);
+
+/* Release every mesh, scene and buffer of the context, after waiting for its
+ * queued work.  A NULL context is accepted. */
+perch_status perch_destroy(perch_ctx *ctx);
+
+/* Copy a triangle mesh to the device (the object model of Sec. III-A).
+ * xyz_mm: n_verts*3 binary32, object frame.  tri: n_tris*3 vertex indices,
+ * counter-clockwise about the outward normal (back faces are culled).
+ * rgb: n_verts*3 sRGB8 per-vertex colours, or NULL.  1 <= n_tris <= 65535. */
+perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz_mm, int32_t n_verts,
+                             const int32_t *tri, int32_t n_tris, const uint8_t *rgb,
+                             int32_t *mesh_id);
+perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id);
+
+/* Copy an observed RGB-D image to the device and prepare it for scoring:
+ * back-projection to points in 1/16 mm, CIELAB colours, and per-8x8-block
+ * depth ranges for the radius search (the input cloud I of Sec. III-B). */
+perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *desc, int32_t *scene_id);
+perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id);
+
+/* Score n poses of one mesh in one scene (Eq. 3 / Eq. 4).  Asynchronous on
+ * hip_stream (NULL = the context's stream).
+ *   label:      the object's label; used by PERCH_VOL_LABEL and, in that
+ *               mode, to keep same-label pixels from occluding (Sec. V-C).
+ *   poses_dev:  n*12 binary32 device array.
+ *   jr_dev, jo_dev: n int32 device arrays, J_r and J_o per pose.
+ *   nr_dev, nq_dev: n int32 device arrays or NULL: L = |R \ C| and
+ *               Q = |I inside V(O)| per pose.
+ * n may be 0 (nothing is launched). */
+perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                               const float *poses_dev, int32_t n, int32_t *jr_dev,
+                               int32_t *jo_dev, int32_t *nr_dev, int32_t *nq_dev,
+                               void *hip_stream);
+
+/* Minimum-cost pose of each of n_obj objects (Sec. IV-A "Parallel Search"):
+ * scores every candidate and reduces J = J_r + J_o per object on the device;
+ * ties go to the lowest pose index.  Blocks until the results are on the
+ * host.  mesh_ids, labels, n_poses: n_obj host arrays; poses_dev: n_obj host
+ * pointers to device pose arrays.  best_idx_host, best_cost_host: n_obj host
+ * outputs.  Every n_poses[k] must be >= 1. */
+perch_status perch_best_poses(perch_ctx *ctx, int32_t scene_id, int32_t n_obj,
+                              const int32_t *mesh_ids, const int32_t *labels,
+                              const float *const *poses_dev, const int32_t *n_poses,
+                              int32_t *best_idx_host, int32_t *best_cost_host,
+                              void *hip_stream);
+
+/* Render n poses of a mesh with the scene's camera into full images, with
+ * the same rasterizer the scorer uses (Sec. IV-A "Parallel Rendering"):
+ * depth_dev n*H*W uint16 (0 = empty), rgb_dev n*H*W*3 uint8 or NULL (needs
+ * mesh colours), tri_dev n*H*W int32 winning triangle (-1 = empty) or NULL.
+ * Asynchronous; 1 <= n <= 256.  Meant for inspection and testing. */
+perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id,
+                          const float *poses_dev, int32_t n, uint16_t *depth_dev,
+                          uint8_t *rgb_dev, int32_t *tri_dev, void *hip_stream);
+
+/* Kernel timing.  perch_profile_enable(ctx, 1) clears the record and from
+ * then on brackets every kernel launch of the context with HIP events on the
+ * launch stream; 0 stops recording.  perch_profile_read waits for the
+ * recorded events and returns, per slot, the summed duration in
+ * milliseconds and the number of launches since the last enable.  Slots:
+ * 0 pose set-up/classification, 1 scoring (LDS tile, small class),
+ * 2 scoring (LDS tile, large class), 3 scoring (global-memory tile),
+ * 4 argmin, 5 scene preparation, 6 render. */
+perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
+perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *perch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERCH_H */

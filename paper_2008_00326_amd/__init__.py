@@ -1,0 +1,242 @@
+"""MI355X-native PERCH 2.0 pose scoring: Python binding of libperch.so.
+
+The binding only marshals arguments to the C ABI declared in
+``include/perch.h``; every step of rendering and scoring runs in the HIP
+kernels of the library.  Torch tensors provide device memory and streams.
+There is no fallback: if the library is missing, importing the binding's
+entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Context", "PerchError", "load_library", "library_path", "USE_RGB", "MARK_OCCLUDERS",
+           "VOL_AABB", "VOL_LABEL"]
+
+USE_RGB = 1
+MARK_OCCLUDERS = 2
+VOL_AABB = 0 << 4
+VOL_LABEL = 2 << 4
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_STATUS = {0: "PERCH_OK", -1: "PERCH_EINVAL", -2: "PERCH_ENOMEM", -3: "PERCH_EDEVICE",
+           -4: "PERCH_ENOTFOUND", -5: "PERCH_EBUSY"}
+
+
+class PerchError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Intrinsics(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class _SceneDesc(ctypes.Structure):
+    _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
+                ("flags", ctypes.c_uint32), ("stride", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return os.environ.get("PERCH_LIBRARY", os.path.join(_HERE, "libperch.so"))
+
+
+_lib = None
+
+
+def load_library():
+    """Load libperch.so (built by ``paper_2008_00326_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"libperch.so not built ({path}); run paper_2008_00326_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, VP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p
+    sig = {
+        "perch_create": ([ctypes.c_int, ctypes.c_size_t, P], ctypes.c_int),
+        "perch_destroy": ([P], ctypes.c_int),
+        "perch_load_mesh": ([P, P, I32, P, I32, P, P], ctypes.c_int),
+        "perch_unload_mesh": ([P, I32], ctypes.c_int),
+        "perch_set_scene": ([P, P, P], ctypes.c_int),
+        "perch_drop_scene": ([P, I32], ctypes.c_int),
+        "perch_score_poses": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP], ctypes.c_int),
+        "perch_best_poses": ([P, I32, I32, P, P, P, P, P, P, VP], ctypes.c_int),
+        "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
+        "perch_profile_enable": ([P, I32], ctypes.c_int),
+        "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
+        "perch_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load_library().perch_last_error().decode(errors="replace")
+        raise PerchError(status, msg)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _dev_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    """One device context: resident meshes and scenes, scoring entry points."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self._lib.perch_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.perch_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- resident objects -------------------------------------------------
+    def load_mesh(self, xyz, tri, rgb=None) -> int:
+        xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+        tri = np.ascontiguousarray(tri, np.int32).reshape(-1, 3)
+        rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8).reshape(-1, 3)
+        mid = ctypes.c_int32()
+        _check(self._lib.perch_load_mesh(self._h, _np_ptr(xyz), xyz.shape[0], _np_ptr(tri), tri.shape[0],
+                                         _np_ptr(rgb), ctypes.byref(mid)))
+        return mid.value
+
+    def unload_mesh(self, mesh_id: int):
+        _check(self._lib.perch_unload_mesh(self._h, int(mesh_id)))
+
+    def set_scene(self, K, depth, rgb=None, labels=None, *, delta_mm=10.0, tau_c=20.0, flags=None,
+                  use_rgb=None, mark_occluders=True, volume="aabb", stride=1) -> int:
+        depth = np.ascontiguousarray(depth, np.uint16)
+        rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        labels = None if labels is None else np.ascontiguousarray(labels, np.int32)
+        if flags is None:
+            if use_rgb is None:
+                use_rgb = rgb is not None
+            flags = (USE_RGB if use_rgb else 0) | (MARK_OCCLUDERS if mark_occluders else 0)
+            flags |= VOL_LABEL if volume == "label" else VOL_AABB
+        w, h, fx, fy, cx, cy = K
+        desc = _SceneDesc(_Intrinsics(int(w), int(h), float(fx), float(fy), float(cx), float(cy)),
+                          _np_ptr(depth), _np_ptr(rgb), _np_ptr(labels), float(delta_mm), float(tau_c),
+                          int(flags), int(stride))
+        sid = ctypes.c_int32()
+        _check(self._lib.perch_set_scene(self._h, ctypes.byref(desc), ctypes.byref(sid)))
+        return sid.value
+
+    def drop_scene(self, scene_id: int):
+        _check(self._lib.perch_drop_scene(self._h, int(scene_id)))
+
+    # -- scoring -----------------------------------------------------------
+    def score_poses(self, scene_id, mesh_id, poses, *, label=0, out=None, counts=True, stream=None):
+        """Score a (n, 12) float32 CUDA tensor of poses.  Returns (jr, jo, nr, nq)
+        int32 CUDA tensors (nr, nq None when counts=False).  Asynchronous."""
+        import torch
+        if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
+            raise ValueError("poses must be a contiguous float32 CUDA tensor")
+        n = poses.numel() // 12
+        if out is None:
+            jr = torch.empty(n, dtype=torch.int32, device=poses.device)
+            jo = torch.empty_like(jr)
+            nr = torch.empty_like(jr) if counts else None
+            nq = torch.empty_like(jr) if counts else None
+        else:
+            jr, jo, nr, nq = out
+        if stream is None:
+            stream = torch.cuda.current_stream(poses.device)
+        _check(self._lib.perch_score_poses(self._h, int(scene_id), int(mesh_id), int(label), _dev_ptr(poses), n,
+                                           _dev_ptr(jr), _dev_ptr(jo), _dev_ptr(nr), _dev_ptr(nq),
+                                           _stream_ptr(stream)))
+        return jr, jo, nr, nq
+
+    def best_poses(self, scene_id, mesh_ids, labels, poses_list, stream=None):
+        """Per object (mesh_ids[k], labels[k], poses_list[k] CUDA tensor): the
+        index and cost of the minimum-cost pose.  Blocks."""
+        import torch
+        k = len(mesh_ids)
+        mids = np.ascontiguousarray(mesh_ids, np.int32)
+        labs = np.ascontiguousarray(labels, np.int32)
+        ptrs = (ctypes.c_void_p * k)(*[p.data_ptr() for p in poses_list])
+        ns = np.ascontiguousarray([p.numel() // 12 for p in poses_list], np.int32)
+        bi = np.zeros(k, np.int32)
+        bc = np.zeros(k, np.int32)
+        if stream is None:
+            stream = torch.cuda.current_stream(poses_list[0].device)
+        _check(self._lib.perch_best_poses(self._h, int(scene_id), k, _np_ptr(mids), _np_ptr(labs), ptrs, _np_ptr(ns),
+                                          _np_ptr(bi), _np_ptr(bc), _stream_ptr(stream)))
+        return bi, bc
+
+    PROFILE_SLOTS = ("setup", "score_small", "score_large", "score_overflow", "argmin", "scene_prep", "render")
+
+    def profile(self, enable: bool = True):
+        """Start (clearing the record) or stop bracketing kernel launches with HIP events."""
+        _check(self._lib.perch_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{slot name: (total ms, launches)} since the last profile(True)."""
+        n = len(self.PROFILE_SLOTS)
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int32)
+        _check(self._lib.perch_profile_read(self._h, n, _np_ptr(ms), _np_ptr(cnt)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PROFILE_SLOTS)}
+
+    def render(self, scene_id, mesh_id, poses, K, *, rgb=False, tri=False, stream=None):
+        """Full-image renders of (n, 12) poses: (depth u16, rgb u8 or None, tri i32 or None) tensors."""
+        import torch
+        n = poses.numel() // 12
+        W, H = int(K[0]), int(K[1])
+        depth = torch.empty((n, H, W), dtype=torch.int16, device=poses.device)
+        col = torch.empty((n, H, W, 3), dtype=torch.uint8, device=poses.device) if rgb else None
+        tid = torch.empty((n, H, W), dtype=torch.int32, device=poses.device) if tri else None
+        if stream is None:
+            stream = torch.cuda.current_stream(poses.device)
+        _check(self._lib.perch_render(self._h, int(scene_id), int(mesh_id), _dev_ptr(poses), n, _dev_ptr(depth),
+                                      _dev_ptr(col), _dev_ptr(tid), _stream_ptr(stream)))
+        return depth, col, tid
+
+
+def load_workload(ctx: Context, w, *, flags=None):
+    """Make a generated workload resident: returns (scene_id, [mesh_id per mesh])."""
+    s = w.scene
+    sid = ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None,
+                        s.labels if w.volume == "label" else None,
+                        delta_mm=w.delta_mm, tau_c=w.tau_c, flags=flags, use_rgb=w.use_rgb,
+                        mark_occluders=w.mark_occluders, volume=w.volume, stride=w.stride)
+    mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb if w.use_rgb else None) for m in w.meshes]
+    return sid, mids

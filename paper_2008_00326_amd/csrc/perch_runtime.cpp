@@ -1,0 +1,666 @@
+// Host runtime behind the C ABI declared in include/perch.h: contexts, the
+// resident mesh and scene registry with its HBM budget, per-stream work
+// buffers, argument validation and kernel launches.
+
+#include "perch.h"
+#include "perch_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace perch;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+perch_status fail(perch_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+perch_status ok()
+{
+    g_last_error.clear();
+    return PERCH_OK;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? PERCH_ENOMEM : PERCH_EDEVICE, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                                    \
+    } while (0)
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct MeshRec {
+    DevBuf verts, tris, rgb;
+    MeshDev dev{};
+    size_t bytes = 0;
+};
+
+struct SceneRec {
+    DevBuf depth, rgb, labels, oxy, olab, oblk, kx, ky;
+    SceneDev dev{};
+    std::vector<int32_t> host_labels;
+    std::map<int32_t, std::vector<int>> label_boxes;
+    size_t bytes = 0;
+};
+
+struct StreamBufs {
+    DevBuf info, lists, counts, scratch, tmp;
+    size_t bytes() const { return info.bytes + lists.bytes + counts.bytes + scratch.bytes + tmp.bytes; }
+};
+
+}  // namespace
+
+struct perch_ctx {
+    int device = 0;
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    size_t lds_max = 0;
+    int next_mesh = 1, next_scene = 1;
+    std::map<int32_t, MeshRec> meshes;
+    std::map<int32_t, SceneRec> scenes;
+    std::map<hipStream_t, StreamBufs> work;
+    std::recursive_mutex mu;
+
+    // profiler: HIP events around each launch, on the launch stream
+    bool prof = false;
+    struct Rec {
+        int slot;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[kNumProfSlots] = {};
+    int launches[kNumProfSlots] = {};
+
+    hipEvent_t event()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    template <class F>
+    hipError_t timed(int slot, hipStream_t st, F &&launch)
+    {
+        if (!prof) return launch();
+        Rec r{slot, event(), event()};
+        (void)hipEventRecord(r.a, st);
+        hipError_t e = launch();
+        (void)hipEventRecord(r.b, st);
+        pending.push_back(r);
+        return e;
+    }
+    void collect()
+    {
+        for (Rec &r : pending) {
+            (void)hipEventSynchronize(r.b);
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                total_ms[r.slot] += ms;
+                launches[r.slot] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+
+    perch_status alloc(DevBuf &b, size_t bytes)
+    {
+        if (bytes == 0) bytes = 256;
+        if (budget && used + bytes > budget)
+            return fail(PERCH_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", used, bytes, budget);
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? PERCH_ENOMEM : PERCH_EDEVICE, "hipMalloc(%zu): %s", bytes,
+                        hipGetErrorString(e));
+        b.ptr = p;
+        b.bytes = bytes;
+        used += bytes;
+        return PERCH_OK;
+    }
+    void release(DevBuf &b)
+    {
+        if (b.ptr) {
+            (void)hipFree(b.ptr);
+            used -= b.bytes;
+        }
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    // grow a per-stream buffer; waits for the device first so no queued
+    // kernel still reads the old allocation
+    perch_status ensure(DevBuf &b, size_t bytes)
+    {
+        if (b.bytes >= bytes && b.ptr) return PERCH_OK;
+        if (b.ptr) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return fail(PERCH_EDEVICE, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+            release(b);
+        }
+        return alloc(b, bytes);
+    }
+};
+
+namespace {
+
+perch_status enter(perch_ctx *ctx)
+{
+    if (!ctx) return fail(PERCH_EINVAL, "null context");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail(PERCH_EDEVICE, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
+    return PERCH_OK;
+}
+
+hipStream_t pick_stream(perch_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
+
+// sRGB8 -> linear (IEC 61966-2-1), computed in binary64 and rounded.
+void colour_table(float out[256])
+{
+    for (int v = 0; v < 256; ++v) {
+        const double c = (double)v / 255.0;
+        out[v] = (float)(c <= 0.04045 ? c / 12.92 : std::pow((c + 0.055) / 1.055, 2.4));
+    }
+}
+
+int cap_for_lds(size_t bytes, int W, int H)
+{
+    // largest cap with lds_bytes_for(cap) + 64 (static counters) <= bytes
+    const long long fixed = 8LL * ((W + H) / 4 + 4) + 64;
+    long long cap = ((long long)bytes - fixed) * 64 / (4 * 64 + 8);
+    cap = std::max(0LL, cap - 64);
+    while (cap > 0 && (long long)lds_bytes_for((int)cap, W, H) + 64 > (long long)bytes) --cap;
+    return (int)cap;
+}
+
+LaunchCfg launch_cfg(const perch_ctx *ctx, const SceneDev &s)
+{
+    LaunchCfg c;
+    c.cap_large = std::min(cap_for_lds(ctx->lds_max, s.W, s.H), s.W * s.H);
+    c.cap_small = std::min(cap_for_lds(ctx->lds_max / 2, s.W, s.H), c.cap_large);
+    c.cap_small = std::min(c.cap_small, 16384);
+    c.grid_small = ctx->n_cu * 2;
+    c.grid_large = ctx->n_cu;
+    c.grid_ovf = std::min(ctx->n_cu, 64);
+    return c;
+}
+
+bool finite3(const float *p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+}  // namespace
+
+namespace {
+
+std::vector<int> label_box(SceneRec &r, int32_t label)
+{
+    auto it = r.label_boxes.find(label);
+    if (it != r.label_boxes.end()) return it->second;
+    const int W = r.dev.W, H = r.dev.H;
+    int x0 = W, y0 = H, x1 = -1, y1 = -1;
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i)
+            if (r.host_labels[(size_t)j * W + i] == label) {
+                x0 = std::min(x0, i);
+                x1 = std::max(x1, i);
+                y0 = std::min(y0, j);
+                y1 = std::max(y1, j);
+            }
+    std::vector<int> b = x1 < 0 ? std::vector<int>{0, 0, 0, 0} : std::vector<int>{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
+    r.label_boxes[label] = b;
+    return b;
+}
+
+perch_status prepare_work(perch_ctx *ctx, SceneRec &sr, MeshRec &mr, int32_t label, const float *poses, int32_t n,
+                          int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, hipStream_t st, Work &w,
+                          LaunchCfg &cfg)
+{
+    StreamBufs &b = ctx->work[st];
+    cfg = launch_cfg(ctx, sr.dev);
+    const size_t slot = (size_t)sr.dev.W * sr.dev.H + 2 * (size_t)sr.dev.bw * sr.dev.bh;
+    perch_status s;
+    if ((s = ctx->ensure(b.info, (size_t)n * sizeof(PoseInfo)))) return s;
+    if ((s = ctx->ensure(b.lists, (size_t)kNumClasses * n * sizeof(int)))) return s;
+    if ((s = ctx->ensure(b.counts, 64))) return s;
+    if ((s = ctx->ensure(b.scratch, (size_t)cfg.grid_ovf * slot * 4))) return s;
+    w = Work{};
+    w.poses = poses;
+    w.n = n;
+    w.label = label;
+    w.jr = jr;
+    w.jo = jo;
+    w.nr = nr;
+    w.nq = nq;
+    w.info = (PoseInfo *)b.info.ptr;
+    w.lists = (int *)b.lists.ptr;
+    w.counts = (int *)b.counts.ptr;
+    w.gscratch = (uint32_t *)b.scratch.ptr;
+    w.gscratch_stride = slot;
+    w.cap_small = cfg.cap_small;
+    w.cap_large = cfg.cap_large;
+    if ((sr.dev.flags & PERCH_VOL_MASK) == PERCH_VOL_LABEL) {
+        std::vector<int> box = label_box(sr, label);
+        for (int a = 0; a < 4; ++a) w.vbox_label[a] = box[a];
+    }
+    (void)mr;
+    return PERCH_OK;
+}
+
+perch_status lookup(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, SceneRec **sr, MeshRec **mr)
+{
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    auto mi = ctx->meshes.find(mesh_id);
+    if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    if ((si->second.dev.flags & PERCH_USE_RGB) && !mi->second.dev.vrgb)
+        return fail(PERCH_EINVAL, "scene uses the RGB term but mesh %d has no vertex colours", mesh_id);
+    *sr = &si->second;
+    *mr = &mi->second;
+    return PERCH_OK;
+}
+
+perch_status score_locked(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label, const float *poses,
+                          int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, hipStream_t st)
+{
+    SceneRec *sr;
+    MeshRec *mr;
+    if (perch_status s = lookup(ctx, scene_id, mesh_id, &sr, &mr)) return s;
+    if (n < 0) return fail(PERCH_EINVAL, "n must be >= 0");
+    if (n == 0) return PERCH_OK;
+    if (!poses || !jr || !jo) return fail(PERCH_EINVAL, "null poses, jr or jo");
+    Work w;
+    LaunchCfg cfg;
+    if (perch_status s = prepare_work(ctx, *sr, *mr, label, poses, n, jr, jo, nr, nq, st, w, cfg)) return s;
+    hipError_t e = ctx->timed(kProfSetup, st, [&] { return launch_setup(sr->dev, mr->dev, w, st); });
+    for (int cls = 0; cls < kNumClasses && e == hipSuccess; ++cls)
+        e = ctx->timed(kProfSmall + cls, st, [&] { return launch_score_class(sr->dev, mr->dev, w, cfg, cls, st); });
+    if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
+    return PERCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *perch_last_error(void) { return g_last_error.c_str(); }
+
+perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
+{
+    if (!out) return fail(PERCH_EINVAL, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(PERCH_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(PERCH_EINVAL, "device %d out of range [0, %d)", device, n);
+    HIP_TRY(hipSetDevice(device));
+    auto *ctx = new perch_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device);
+    ctx->n_cu = (e == hipSuccess && v > 0) ? v : 256;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    ctx->lds_max = (e == hipSuccess && v > 0) ? (size_t)v : 65536;
+    float lin[256];
+    colour_table(lin);
+    e = upload_colour_table(lin);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(PERCH_EDEVICE, "context set-up: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return ok();
+}
+
+perch_status perch_destroy(perch_ctx *ctx)
+{
+    if (!ctx) return ok();
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->meshes) {
+        ctx->release(kv.second.verts);
+        ctx->release(kv.second.tris);
+        ctx->release(kv.second.rgb);
+    }
+    for (auto &kv : ctx->scenes) {
+        SceneRec &r = kv.second;
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky}) ctx->release(*b);
+    }
+    for (auto &kv : ctx->work) {
+        StreamBufs &w = kv.second;
+        for (DevBuf *b : {&w.info, &w.lists, &w.counts, &w.scratch, &w.tmp}) ctx->release(*b);
+    }
+    ctx->collect();
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return ok();
+}
+
+perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz, int32_t n_verts, const int32_t *tri,
+                             int32_t n_tris, const uint8_t *rgb, int32_t *mesh_id)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!xyz || !tri || !mesh_id) return fail(PERCH_EINVAL, "null xyz, tri or mesh_id");
+    if (n_verts < 1) return fail(PERCH_EINVAL, "n_verts must be >= 1 (got %d)", n_verts);
+    if (n_tris < 1 || n_tris > kMaxTris)
+        return fail(PERCH_EINVAL, "n_tris must be in [1, %d] (got %d)", kMaxTris, n_tris);
+    std::vector<float4> v((size_t)n_verts);
+    float lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+    for (int32_t k = 0; k < n_verts; ++k) {
+        const float *p = xyz + 3 * (size_t)k;
+        if (!finite3(p)) return fail(PERCH_EINVAL, "vertex %d is not finite", k);
+        v[k] = make_float4(p[0], p[1], p[2], 0.0f);
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], p[a]);
+            hi[a] = std::max(hi[a], p[a]);
+        }
+    }
+    std::vector<int4> t((size_t)n_tris);
+    for (int32_t k = 0; k < n_tris; ++k) {
+        const int32_t *q = tri + 3 * (size_t)k;
+        for (int a = 0; a < 3; ++a)
+            if (q[a] < 0 || q[a] >= n_verts) return fail(PERCH_EINVAL, "triangle %d index %d out of range", k, q[a]);
+        t[k] = make_int4(q[0], q[1], q[2], 0);
+    }
+    std::vector<uint32_t> c;
+    if (rgb) {
+        c.resize((size_t)n_verts);
+        for (int32_t k = 0; k < n_verts; ++k)
+            c[k] = (uint32_t)rgb[3 * (size_t)k] | ((uint32_t)rgb[3 * (size_t)k + 1] << 8)
+                   | ((uint32_t)rgb[3 * (size_t)k + 2] << 16);
+    }
+    MeshRec r;
+    perch_status st;
+    if ((st = ctx->alloc(r.verts, v.size() * sizeof(float4))) || (st = ctx->alloc(r.tris, t.size() * sizeof(int4)))
+        || (rgb && (st = ctx->alloc(r.rgb, c.size() * sizeof(uint32_t))))) {
+        std::string msg = g_last_error;
+        ctx->release(r.verts);
+        ctx->release(r.tris);
+        ctx->release(r.rgb);
+        return fail(st, "%s", msg.c_str());
+    }
+    hipError_t e = hipMemcpy(r.verts.ptr, v.data(), v.size() * sizeof(float4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r.tris.ptr, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess && rgb) e = hipMemcpy(r.rgb.ptr, c.data(), c.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ctx->release(r.verts);
+        ctx->release(r.tris);
+        ctx->release(r.rgb);
+        return fail(PERCH_EDEVICE, "mesh upload: %s", hipGetErrorString(e));
+    }
+    r.dev.verts = (const float4 *)r.verts.ptr;
+    r.dev.tris = (const int4 *)r.tris.ptr;
+    r.dev.vrgb = (const uint32_t *)r.rgb.ptr;
+    r.dev.nv = n_verts;
+    r.dev.nt = n_tris;
+    for (int a = 0; a < 3; ++a) {
+        r.dev.lo[a] = lo[a];
+        r.dev.hi[a] = hi[a];
+    }
+    r.bytes = r.verts.bytes + r.tris.bytes + r.rgb.bytes;
+    const int32_t id = ctx->next_mesh++;
+    ctx->meshes[id] = r;
+    *mesh_id = id;
+    return ok();
+}
+
+perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->meshes.find(mesh_id);
+    if (it == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    (void)hipDeviceSynchronize();
+    ctx->release(it->second.verts);
+    ctx->release(it->second.tris);
+    ctx->release(it->second.rgb);
+    ctx->meshes.erase(it);
+    return ok();
+}
+
+perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t *scene_id)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!d || !scene_id) return fail(PERCH_EINVAL, "null descriptor or scene_id");
+    const perch_intrinsics &K = d->K;
+    if (K.width < 1 || K.width > 4096 || K.height < 1 || K.height > 4096)
+        return fail(PERCH_EINVAL, "image size %dx%d outside [1, 4096]", K.width, K.height);
+    if (!(K.fx > 0.0f) || !(K.fy > 0.0f) || !std::isfinite(K.fx) || !std::isfinite(K.fy) || !std::isfinite(K.cx)
+        || !std::isfinite(K.cy))
+        return fail(PERCH_EINVAL, "intrinsics must be finite with fx, fy > 0");
+    if (!d->depth_mm) return fail(PERCH_EINVAL, "depth_mm is required");
+    if (!(d->delta_mm > 0.0f) || !(d->delta_mm <= 500.0f)) return fail(PERCH_EINVAL, "delta_mm must be in (0, 500]");
+    if (!(d->tau_c >= 0.0f) || !std::isfinite(d->tau_c)) return fail(PERCH_EINVAL, "tau_c must be finite and >= 0");
+    if (d->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
+    const uint32_t known = PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK;
+    if (d->flags & ~known) return fail(PERCH_EINVAL, "unknown flag bits 0x%x", d->flags & ~known);
+    const uint32_t vol = d->flags & PERCH_VOL_MASK;
+    if (vol != PERCH_VOL_AABB && vol != PERCH_VOL_LABEL) return fail(PERCH_EINVAL, "unsupported volume mode");
+    if ((d->flags & PERCH_USE_RGB) && !d->rgb) return fail(PERCH_EINVAL, "PERCH_USE_RGB needs scene rgb");
+    if (vol == PERCH_VOL_LABEL && !d->labels) return fail(PERCH_EINVAL, "PERCH_VOL_LABEL needs labels");
+    const int W = K.width, H = K.height;
+    const size_t N = (size_t)W * H;
+    const bool use_rgb = (d->flags & PERCH_USE_RGB) != 0;
+
+    std::vector<double> kx(W), ky(H);
+    for (int i = 0; i < W; ++i) kx[i] = (((double)i - (double)K.cx) * 16.0) / (double)K.fx;
+    for (int j = 0; j < H; ++j) ky[j] = (((double)j - (double)K.cy) * 16.0) / (double)K.fy;
+
+    SceneRec r;
+    const int bw = (W + kBlockPx - 1) / kBlockPx, bh = (H + kBlockPx - 1) / kBlockPx;
+    perch_status st = PERCH_OK;
+    auto A = [&](DevBuf &b, size_t n) {
+        if (st == PERCH_OK) st = ctx->alloc(b, n);
+    };
+    A(r.depth, N * 2);
+    A(r.oxy, N * sizeof(int2));
+    A(r.oblk, (size_t)bw * bh * 4);
+    A(r.kx, W * 8);
+    A(r.ky, H * 8);
+    if (use_rgb) {
+        A(r.rgb, N * 3);
+        A(r.olab, N * sizeof(float4));
+    }
+    if (d->labels) A(r.labels, N * 4);
+    auto cleanup = [&]() {
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky}) ctx->release(*b);
+    };
+    if (st != PERCH_OK) {
+        std::string msg = g_last_error;
+        cleanup();
+        return fail(st, "%s", msg.c_str());
+    }
+    hipError_t e = hipMemcpy(r.depth.ptr, d->depth_mm, N * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r.kx.ptr, kx.data(), W * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r.ky.ptr, ky.data(), H * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess && use_rgb) e = hipMemcpy(r.rgb.ptr, d->rgb, N * 3, hipMemcpyHostToDevice);
+    if (e == hipSuccess && d->labels) e = hipMemcpy(r.labels.ptr, d->labels, N * 4, hipMemcpyHostToDevice);
+    SceneDev &s = r.dev;
+    s.depth = (const uint16_t *)r.depth.ptr;
+    s.oxy = (const int2 *)r.oxy.ptr;
+    s.olab = (const float4 *)r.olab.ptr;
+    s.labels = (const int32_t *)r.labels.ptr;
+    s.oblk = (const uint32_t *)r.oblk.ptr;
+    s.kx = (const double *)r.kx.ptr;
+    s.ky = (const double *)r.ky.ptr;
+    s.W = W;
+    s.H = H;
+    s.bw = bw;
+    s.bh = bh;
+    s.fx = K.fx;
+    s.fy = K.fy;
+    s.cx = K.cx;
+    s.cy = K.cy;
+    s.dq = (int)std::nearbyint(16.0 * (double)d->delta_mm);
+    s.dq2 = s.dq * s.dq;
+    s.dzmm = s.dq / 16;
+    s.delta = d->delta_mm;
+    s.tau = d->tau_c;
+    s.flags = d->flags;
+    s.stride = d->stride;
+    if (e == hipSuccess)
+        e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
+            return launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int2 *)r.oxy.ptr, (float4 *)r.olab.ptr,
+                                     (uint32_t *)r.oblk.ptr, ctx->stream);
+        });
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(PERCH_EDEVICE, "scene upload / preparation: %s", hipGetErrorString(e));
+    }
+    if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
+    r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.oxy.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
+              + r.ky.bytes;
+    const int32_t id = ctx->next_scene++;
+    ctx->scenes[id] = std::move(r);
+    *scene_id = id;
+    return ok();
+}
+
+perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->scenes.find(scene_id);
+    if (it == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    (void)hipDeviceSynchronize();
+    SceneRec &r = it->second;
+    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky}) ctx->release(*b);
+    ctx->scenes.erase(it);
+    return ok();
+}
+
+perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                               const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
+                               int32_t *nr_dev, int32_t *nq_dev, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    perch_status s = score_locked(ctx, scene_id, mesh_id, label, poses_dev, n, jr_dev, jo_dev, nr_dev, nq_dev,
+                                  pick_stream(ctx, hip_stream));
+    return s ? s : ok();
+}
+
+perch_status perch_best_poses(perch_ctx *ctx, int32_t scene_id, int32_t n_obj, const int32_t *mesh_ids,
+                              const int32_t *labels, const float *const *poses_dev, const int32_t *n_poses,
+                              int32_t *best_idx_host, int32_t *best_cost_host, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (n_obj < 1) return fail(PERCH_EINVAL, "n_obj must be >= 1");
+    if (!mesh_ids || !labels || !poses_dev || !n_poses || !best_idx_host || !best_cost_host)
+        return fail(PERCH_EINVAL, "null argument");
+    int32_t nmax = 0;
+    for (int32_t k = 0; k < n_obj; ++k) {
+        if (n_poses[k] < 1) return fail(PERCH_EINVAL, "object %d has no poses", k);
+        if (!poses_dev[k]) return fail(PERCH_EINVAL, "object %d: null poses", k);
+        SceneRec *sr;
+        MeshRec *mr;
+        if (perch_status s = lookup(ctx, scene_id, mesh_ids[k], &sr, &mr)) return s;
+        nmax = std::max(nmax, n_poses[k]);
+    }
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    StreamBufs &b = ctx->work[st];
+    const size_t tmp_bytes = (size_t)2 * nmax * 4 + (size_t)2 * n_obj * 4;
+    if (perch_status s = ctx->ensure(b.tmp, tmp_bytes)) return s;
+    int32_t *jr = (int32_t *)b.tmp.ptr, *jo = jr + nmax, *res = jo + nmax;
+    for (int32_t k = 0; k < n_obj; ++k) {
+        if (perch_status s = score_locked(ctx, scene_id, mesh_ids[k], labels[k], poses_dev[k], n_poses[k], jr, jo,
+                                          nullptr, nullptr, st))
+            return s;
+        HIP_TRY(ctx->timed(kProfArgmin, st, [&] { return launch_argmin(jr, jo, n_poses[k], res + 2 * k, st); }));
+    }
+    std::vector<int32_t> host((size_t)2 * n_obj);
+    HIP_TRY(hipMemcpyAsync(host.data(), res, host.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t k = 0; k < n_obj; ++k) {
+        best_idx_host[k] = host[2 * k];
+        best_cost_host[k] = host[2 * k + 1];
+    }
+    return ok();
+}
+
+perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, const float *poses_dev, int32_t n,
+                          uint16_t *depth_dev, uint8_t *rgb_dev, int32_t *tri_dev, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    auto mi = ctx->meshes.find(mesh_id);
+    if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    if (n < 1 || n > 256) return fail(PERCH_EINVAL, "n must be in [1, 256]");
+    if (!poses_dev || !depth_dev) return fail(PERCH_EINVAL, "null poses or depth");
+    if (rgb_dev && !mi->second.dev.vrgb) return fail(PERCH_EINVAL, "mesh %d has no vertex colours", mesh_id);
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    StreamBufs &b = ctx->work[st];
+    const SceneDev &s = si->second.dev;
+    if (perch_status e = ctx->ensure(b.scratch, (size_t)n * s.W * s.H * 4)) return e;
+    HIP_TRY(ctx->timed(kProfRender, st, [&] {
+        return launch_render(s, mi->second.dev, poses_dev, n, (uint32_t *)b.scratch.ptr, depth_dev, rgb_dev, tri_dev,
+                             st);
+    }));
+    return ok();
+}
+
+perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->collect();
+    for (int k = 0; k < kNumProfSlots; ++k) {
+        ctx->total_ms[k] = 0.0;
+        ctx->launches[k] = 0;
+    }
+    ctx->prof = enable != 0;
+    return ok();
+}
+
+perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (n_slots < 0 || (n_slots > 0 && (!total_ms || !launches))) return fail(PERCH_EINVAL, "bad output arrays");
+    ctx->collect();
+    for (int k = 0; k < n_slots; ++k) {
+        total_ms[k] = k < kNumProfSlots ? ctx->total_ms[k] : 0.0;
+        launches[k] = k < kNumProfSlots ? ctx->launches[k] : 0;
+    }
+    return ok();
+}
+
+}  // extern "C"

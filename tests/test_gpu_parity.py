@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Depth images, coverage, L, Q and every depth-only count must be bit-exact.
+With the RGB term the colour decision is binary32 on both sides but uses
+different transcendental implementations, so counts may differ by at most
+ceil(0.001 L) (J_r) and ceil(0.001 Q) (J_o) per pose.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2008_00326_amd as pk  # noqa: E402
+from paper_2008_00326_amd.workloads import make_config  # noqa: E402
+from tiny_meshes import TMesh, TScene, box, pose_matrix  # noqa: E402
+
+THREADS = 16
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def oracle_flags(w):
+    f = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0)
+    return f | (oracle.VOL_LABEL if w.volume == "label" else oracle.VOL_AABB)
+
+
+def oracle_mesh(w, m):
+    return m if w.use_rgb else TMesh(m.xyz, m.tri, None)
+
+
+def oracle_scene(w):
+    s = w.scene
+    return TScene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels)
+
+
+def gpu_score(ctx, sid, mid, poses, label=0):
+    t = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).cuda()
+    jr, jo, nr, nq = ctx.score_poses(sid, mid, t, label=label)
+    torch.cuda.synchronize()
+    return jr.cpu().numpy(), jo.cpu().numpy(), nr.cpu().numpy(), nq.cpu().numpy()
+
+
+def check_counts(w, got, exp, what):
+    jr, jo, nr, nq = got
+    ejr, ejo, enr, enq = exp
+    assert np.array_equal(nr, enr), f"{what}: L differs at {np.flatnonzero(nr != enr)[:10]}"
+    assert np.array_equal(nq, enq), f"{what}: Q differs at {np.flatnonzero(nq != enq)[:10]}"
+    if not w.use_rgb:
+        assert np.array_equal(jr, ejr), f"{what}: J_r differs at {np.flatnonzero(jr != ejr)[:10]}"
+        assert np.array_equal(jo, ejo), f"{what}: J_o differs at {np.flatnonzero(jo != ejo)[:10]}"
+    else:
+        tol_r = np.ceil(0.001 * enr).astype(int)
+        tol_o = np.ceil(0.001 * enq).astype(int)
+        assert np.all(np.abs(jr - ejr) <= tol_r), f"{what}: J_r beyond tolerance {np.abs(jr - ejr).max()}"
+        assert np.all(np.abs(jo - ejo) <= tol_o), f"{what}: J_o beyond tolerance {np.abs(jo - ejo).max()}"
+
+
+# ---------------------------------------------------------------- render
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_render_bit_exact(ctx, cfg):
+    w = make_config(cfg, 0)
+    say(f"render parity cfg{cfg}")
+    sid, mids = pk.load_workload(ctx, w)
+    rng = np.random.default_rng(cfg)
+    for o in w.objects[:3]:
+        m = w.meshes[o.mesh]
+        idx = rng.choice(o.poses.shape[0], 4, replace=False)
+        poses = np.concatenate([o.gt_pose[None], o.poses[idx]])
+        t = torch.from_numpy(poses).cuda()
+        d, c, tri = ctx.render(sid, mids[o.mesh], t, w.scene.K, rgb=w.use_rgb, tri=True)
+        torch.cuda.synchronize()
+        d = d.cpu().numpy().view(np.uint16)
+        tri = tri.cpu().numpy()
+        c = c.cpu().numpy() if c is not None else None
+        for k in range(poses.shape[0]):
+            ed, et, ec = oracle.render(oracle_mesh(w, m), poses[k], w.scene.K)
+            assert np.array_equal(d[k], ed), f"depth differs in {np.count_nonzero(d[k] != ed)} px"
+            assert np.array_equal(tri[k], et)
+            if c is not None:
+                assert np.array_equal(c[k], ec)
+    ctx.drop_scene(sid)
+    for mid in mids:
+        ctx.unload_mesh(mid)
+
+
+# ---------------------------------------------------------------- score
+
+def test_cfg1_full_bit_exact(ctx):
+    w = make_config(1, 0)
+    say("cfg1 full 512 poses")
+    sid, mids = pk.load_workload(ctx, w)
+    o = w.objects[0]
+    got = gpu_score(ctx, sid, mids[0], o.poses)
+    exp = oracle.score(w.meshes[0], oracle_scene(w), o.poses, delta_mm=w.delta_mm, flags=oracle_flags(w),
+                       threads=THREADS)
+    check_counts(w, got, exp, "cfg1")
+    # best pose: same argmin as the oracle, through the C-ABI reduction
+    bi, bc = ctx.best_poses(sid, [mids[0]], [o.label], [torch.from_numpy(o.poses).cuda()])
+    ebi, ebc, _ = oracle.best(exp[0], exp[1])
+    assert (bi[0], bc[0]) == (ebi, ebc)
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mids[0])
+
+
+@pytest.mark.parametrize("cfg,variant", [(2, "rgb"), (2, "depth"), (3, "rgb"), (3, "label"), (2, "stride2-nocc")])
+def test_sampled_poses(ctx, cfg, variant):
+    w = make_config(cfg, 0)
+    if variant == "depth":
+        w.use_rgb = False
+    elif variant == "label":
+        w.volume = "label"
+    elif variant == "stride2-nocc":
+        w.stride = 2
+        w.mark_occluders = False
+    say(f"sampled cfg{cfg} {variant}")
+    sid, mids = pk.load_workload(ctx, w)
+    rng = np.random.default_rng(10 * cfg + len(variant))
+    for o in w.objects:
+        m = w.meshes[o.mesh]
+        sel = rng.choice(o.poses.shape[0], 5, replace=False)
+        poses = np.concatenate([o.gt_pose[None], o.poses[sel]])
+        got = gpu_score(ctx, sid, mids[o.mesh], poses, label=o.label)
+        exp = oracle.score(oracle_mesh(w, m), oracle_scene(w), poses, delta_mm=w.delta_mm, tau_c=w.tau_c,
+                           flags=oracle_flags(w), stride=w.stride, label=o.label, threads=THREADS)
+        check_counts(w, got, exp, f"cfg{cfg} {variant} object {o.label}")
+    ctx.drop_scene(sid)
+    for mid in mids:
+        ctx.unload_mesh(mid)
+
+
+def test_cfg2_full_size_sampled_outputs(ctx):
+    """All 32,000 cfg2 poses in the launch shape the benchmark uses; the
+    oracle checks a spread sample of the outputs one by one."""
+    w = make_config(2, 0)
+    say("cfg2 full size")
+    sid, mids = pk.load_workload(ctx, w)
+    outs = []
+    for o in w.objects:
+        outs.append(gpu_score(ctx, sid, mids[o.mesh], o.poses, label=o.label))
+    rng = np.random.default_rng(99)
+    for o, got in zip(w.objects, outs):
+        sel = np.sort(rng.choice(o.poses.shape[0], 6, replace=False))
+        exp = oracle.score(w.meshes[o.mesh], oracle_scene(w), o.poses[sel], delta_mm=w.delta_mm, tau_c=w.tau_c,
+                           flags=oracle_flags(w), label=o.label, threads=THREADS)
+        check_counts(w, tuple(g[sel] for g in got), exp, f"cfg2 object {o.label}")
+        jr, jo, nr, nq = got
+        assert np.all((jr >= 0) & (jr <= nr)) and np.all((jo >= 0) & (jo <= nq))
+    # best_poses equals the argmin of the scored costs, per object
+    polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
+    bi, bc = ctx.best_poses(sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects], polys)
+    for k, got in enumerate(outs):
+        J = got[0].astype(np.int64) + got[1]
+        assert bc[k] == J.min() and bi[k] == int(np.flatnonzero(J == J.min())[0])
+    ctx.drop_scene(sid)
+    for mid in mids:
+        ctx.unload_mesh(mid)
+
+
+# ---------------------------------------------------------------- edges
+
+def test_edge_cases(ctx):
+    say("edge cases")
+    K = (96, 72, 110.0, 110.0, 48.0, 36.0)
+    cube = box((-40, -40, -40), (40, 40, 40), n=2, rgb_seed=3)
+    d, _, c = oracle.render(cube, pose_matrix(np.eye(3), (5, -3, 600)), K)
+    sid = ctx.set_scene(K, d, c, delta_mm=10.0, tau_c=20.0, use_rgb=True)
+    mid = ctx.load_mesh(cube.xyz, cube.tri, cube.rgb)
+    poses = np.stack([
+        pose_matrix(np.eye(3), (5, -3, 600)),          # self render: J = 0
+        pose_matrix(np.eye(3), (0, 0, -900)),          # behind the camera
+        pose_matrix(np.eye(3), (0, 0, 150)),           # fills the image: overflow class
+        pose_matrix(np.eye(3), (900, 0, 600)),         # off screen
+        pose_matrix(np.eye(3), (30, 20, 620)),
+    ])
+    got = gpu_score(ctx, sid, mid, poses)
+    exp = oracle.score(cube, TScene(K, d, c, None), poses, delta_mm=10.0, tau_c=20.0,
+                       flags=oracle.USE_RGB | oracle.MARK_OCCLUDERS, threads=THREADS)
+    for a, b in zip(got, exp):
+        assert np.array_equal(a, b), (got, exp)
+    assert got[0][0] == 0 and got[1][0] == 0
+    assert got[2][1] == 0
+    # n = 0 launches nothing and succeeds
+    e = torch.empty((0, 12), dtype=torch.float32, device="cuda")
+    ctx.score_poses(sid, mid, e)
+    # a one-triangle mesh
+    tri_mesh = TMesh(np.array([[-50, -50, 0], [50, -50, 0], [0, 50, 0]], np.float32), np.array([[0, 2, 1]], np.int32))
+    mid1 = ctx.load_mesh(tri_mesh.xyz, tri_mesh.tri, np.full((3, 3), 200, np.uint8))
+    p1 = np.stack([pose_matrix(np.eye(3), (0, 0, 500)), pose_matrix(np.diag([1, -1, -1.0]), (0, 0, 500))])
+    got = gpu_score(ctx, sid, mid1, p1)
+    exp = oracle.score(TMesh(tri_mesh.xyz, tri_mesh.tri, np.full((3, 3), 200, np.uint8)), TScene(K, d, c, None), p1,
+                       delta_mm=10.0, tau_c=20.0, flags=oracle.USE_RGB | oracle.MARK_OCCLUDERS, threads=THREADS)
+    for a, b in zip(got, exp):
+        assert np.array_equal(a, b)
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
+    ctx.unload_mesh(mid1)
+
+
+def test_errors_are_reported(ctx):
+    say("error paths")
+    with pytest.raises(pk.PerchError) as e:
+        ctx.load_mesh(np.zeros((3, 3), np.float32), np.array([[0, 1, 5]], np.int32))
+    assert e.value.status == -1
+    with pytest.raises(pk.PerchError):
+        ctx.set_scene((64, 48, 50.0, 50.0, 32.0, 24.0), np.zeros((48, 64), np.uint16), delta_mm=-1.0)
+    with pytest.raises(pk.PerchError) as e:
+        ctx.drop_scene(12345)
+    assert e.value.status == -4
+    sid = ctx.set_scene((64, 48, 50.0, 50.0, 32.0, 24.0), np.zeros((48, 64), np.uint16), delta_mm=10.0)
+    mid = ctx.load_mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.int32))
+    with pytest.raises(pk.PerchError):
+        ctx.score_poses(sid, 999, torch.zeros((1, 12), device="cuda"))
+    # RGB scene with a colourless mesh
+    sid2 = ctx.set_scene((64, 48, 50.0, 50.0, 32.0, 24.0), np.zeros((48, 64), np.uint16),
+                         np.zeros((48, 64, 3), np.uint8), delta_mm=10.0)
+    with pytest.raises(pk.PerchError):
+        ctx.score_poses(sid2, mid, torch.zeros((1, 12), device="cuda"))
+    ctx.drop_scene(sid)
+    ctx.drop_scene(sid2)
+    ctx.unload_mesh(mid)
+
+
+def test_budget_enforced():
+    say("budget")
+    c = pk.Context(0, hbm_budget_bytes=1 << 20)
+    with pytest.raises(pk.PerchError) as e:
+        c.set_scene((640, 480, 525.0, 525.0, 320.0, 240.0), np.zeros((480, 640), np.uint16), delta_mm=10.0)
+    assert e.value.status == -2
+    c.close()
+
+
+def test_deterministic_and_batch_independent(ctx):
+    w = make_config(2, 1)
+    say("determinism")
+    sid, mids = pk.load_workload(ctx, w)
+    o = w.objects[1]
+    full = gpu_score(ctx, sid, mids[o.mesh], o.poses, label=o.label)
+    again = gpu_score(ctx, sid, mids[o.mesh], o.poses, label=o.label)
+    for a, b in zip(full, again):
+        assert np.array_equal(a, b)
+    sub = np.arange(37, 6400, 97)
+    part = gpu_score(ctx, sid, mids[o.mesh], o.poses[sub], label=o.label)
+    for a, b in zip(part, full):
+        assert np.array_equal(a, b[sub])
+    ctx.drop_scene(sid)
+    for mid in mids:
+        ctx.unload_mesh(mid)
