@@ -138,7 +138,8 @@ def main():
     dom_ms, dom_launches = prof[dom]
     areas = tile_areas(w)
     W, H = w.scene.K[0], w.scene.K[1]
-    caps = ctx_caps(ctx, w)
+    info = ctx.scene_info(sid)
+    caps = (info["tile_cap_small"], info["tile_cap_large"])
     cls_idx = {"score_small": 0, "score_large": 1, "score_overflow": 2}[dom]
     ops = 0.0
     byts = 0.0
@@ -179,6 +180,8 @@ def main():
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "set_scene_and_meshes": round(scene_ms, 3)},
+        "scene": {"device_MB": round(info["device_bytes"] / 2**20, 1), "table_entries": info["table_entries"],
+                  "window": [info["window_x"], info["window_y"]], "tile_caps": list(caps)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved_tops, 4), "peak": round(ALU_PEAK_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 5), "traffic": None,
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4), "launches": dom_launches,
@@ -190,24 +193,6 @@ def main():
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     ctx.close()
     print(json.dumps(result), flush=True)
-
-
-def ctx_caps(ctx, w):
-    """LDS tile capacities the runtime picks (mirrors its rule, from the device's LDS size)."""
-    import torch
-    props = torch.cuda.get_device_properties(0)
-    lds = int(getattr(props, "shared_memory_per_block", 65536) or 65536)
-    W, H = w.scene.K[0], w.scene.K[1]
-
-    def cap_for(b):
-        nb = lambda c: c // 64 + (W + H) // 4 + 4  # noqa: E731
-        cap = max(0, (b - (8 * ((W + H) // 4 + 4) + 64)) * 64 // 264 - 64)
-        while cap > 0 and cap * 4 + nb(cap) * 8 + 64 > b:
-            cap -= 1
-        return cap
-    large = min(cap_for(lds), W * H)
-    small = min(cap_for(lds // 2), large, 16384)
-    return small, large
 
 
 def cpu_baseline(w, sample):

@@ -103,6 +103,17 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id);
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *desc, int32_t *scene_id);
 perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id);
 
+typedef struct {
+    size_t device_bytes;          /* HBM held by the scene (images, points, neighbour table) */
+    int64_t table_entries;        /* entries of its nearest-neighbour table */
+    int32_t window_x, window_y;   /* pixel half-windows that contain every neighbour pair */
+    int32_t tile_cap_small;       /* LDS tile capacity (pixels) of the two scoring classes; */
+    int32_t tile_cap_large;       /*   larger footprints are scored from device memory */
+} perch_scene_info;
+
+/* Describe a resident scene (footprint, search windows, tile classes). */
+perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_info *out);
+
 /* Score n poses of one mesh in one scene (Eq. 3 / Eq. 4).  Asynchronous on
  * hip_stream (NULL = the context's stream).
  *   label:      the object's label; used by PERCH_VOL_LABEL and, in that

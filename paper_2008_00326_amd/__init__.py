@@ -37,6 +37,12 @@ class _Intrinsics(ctypes.Structure):
                 ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
 
 
+class _SceneInfo(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_size_t), ("table_entries", ctypes.c_int64),
+                ("window_x", ctypes.c_int32), ("window_y", ctypes.c_int32),
+                ("tile_cap_small", ctypes.c_int32), ("tile_cap_large", ctypes.c_int32)]
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
@@ -70,6 +76,7 @@ def load_library():
         "perch_score_poses": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP], ctypes.c_int),
         "perch_best_poses": ([P, I32, I32, P, P, P, P, P, P, VP], ctypes.c_int),
         "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
+        "perch_scene_info_get": ([P, I32, P], ctypes.c_int),
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
         "perch_last_error": ([], ctypes.c_char_p),
@@ -162,6 +169,12 @@ class Context:
 
     def drop_scene(self, scene_id: int):
         _check(self._lib.perch_drop_scene(self._h, int(scene_id)))
+
+    def scene_info(self, scene_id: int) -> dict:
+        """HBM footprint, neighbour-table size, search windows and tile classes of a scene."""
+        info = _SceneInfo()
+        _check(self._lib.perch_scene_info_get(self._h, int(scene_id), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in _SceneInfo._fields_}
 
     # -- scoring -----------------------------------------------------------
     def score_poses(self, scene_id, mesh_id, poses, *, label=0, out=None, counts=True, stream=None):

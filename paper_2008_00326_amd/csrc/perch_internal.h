@@ -25,7 +25,10 @@ struct SceneDev {
     const uint32_t *oblk;    // bw*bh: min depth | max depth << 16 of valid pixels
     const double *kx;        // W: 16 (i - cx) / fx
     const double *ky;        // H: 16 (j - cy) / fy
+    const int2 *thdr;        // H*W nearest-neighbour table header: {first entry, lo | n << 16}
+    const int32_t *tnn;      // entry (pixel, lo + e): nearest observed pixel within delta, -1 none
     int W, H, bw, bh;
+    int wtx, wty;            // window half-sizes that contain every neighbour pair of the scene
     float fx, fy, cx, cy;
     int dq, dq2, dzmm;       // delta in 1/16 mm, its square, floor(dq / 16)
     float delta, tau;
@@ -65,11 +68,21 @@ struct LaunchCfg {
 // Upper bound on the 8x8 blocks of any tile of at most `cap` pixels inside a
 // W x H image: ceil(w/8) ceil(h/8) <= cap/64 + 7 (W + H)/64 + 1.
 inline int nbcap_for(int cap, int W, int H) { return cap / 64 + (W + H) / 4 + 4; }
-size_t lds_bytes_for(int cap, int W, int H);
+size_t lds_bytes_for(int cap, int W, int H, int wtx, int wty);
 hipError_t upload_colour_table(const float *lin256);
 
 hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *oxy, float4 *olab,
                              uint32_t *oblk, hipStream_t st);
+// Nearest-neighbour table of the observed cloud: per pixel the depth range
+// that can have an observed point within delta, then one entry per depth.
+hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st);
+hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
+// Words of the LDS "explained" bitmap for a tile of at most `cap` pixels.
+inline int bmcap_for(int cap, int W, int H, int wtx, int wty)
+{
+    const long long bits = (long long)cap + 2LL * wtx * H + 2LL * wty * W + 4LL * wtx * wty;
+    return (int)(bits / 32 + 2);
+}
 hipError_t launch_setup(const SceneDev &s, const MeshDev &m, const Work &w, hipStream_t st);
 hipError_t launch_score_class(const SceneDev &s, const MeshDev &m, const Work &w, const LaunchCfg &c, int cls,
                               hipStream_t st);

@@ -148,6 +148,7 @@ __device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev
 // Perspective-correct vertex colour of triangle t at pixel (i, j), rounded to sRGB8.
 __device__ uint32_t triangle_colour(const SceneDev &s, const MeshDev &m, const float *P, int t, int i, int j)
 {
+    if (t < 0 || t >= m.nt) return 0;
     const int4 ix = m.tris[t];
     const Vtx a = project_vertex(P, m.verts[ix.x], s);
     const Vtx b = project_vertex(P, m.verts[ix.y], s);
@@ -257,117 +258,116 @@ __device__ __forceinline__ int window_half(float f, float lat, float z, float dl
     return (int)bnd + 1;
 }
 
-// J_r search: observed points within delta of rendered point (i, j, d, X, Y).
-// Depth-only: any neighbour; RGB: the nearest, ties to the lower pixel index.
-template <bool NN>
-__device__ bool search_observed(const SceneDev &s, int i, int j, int d, int X, int Y, int *nn_pix)
+// Wave-cooperative window scans.  The caller's whole wave works on one
+// point: each iteration covers one 8x8 block of the window, lane l taking
+// pixel (l & 7, l >> 3) of the block; blocks whose depth range cannot hold a
+// point within delta are skipped for the whole wave.
+
+// Back-projection factors 16 (i - cx) / fx and 16 (j - cy) / fy, computed
+// with the same correctly rounded binary64 operations as the per-column
+// tables, so that no table load sits on the critical path.
+__device__ __forceinline__ double kx_of(const SceneDev &s, int i)
 {
+    return (((double)i - (double)s.cx) * 16.0) / (double)s.fx;
+}
+__device__ __forceinline__ double ky_of(const SceneDev &s, int j)
+{
+    return (((double)j - (double)s.cy) * 16.0) / (double)s.fy;
+}
+
+// Mark, in the "explained" bitmap, every observed point within delta of the
+// rendered point (i, j, d): the J_o side of Eq. 3 for this point.  The depth
+// loads of four window blocks are issued before any of them is used.
+template <bool G>
+__device__ void wave_mark_neighbours(const SceneDev &s, int i, int j, int d, uint32_t *bm, int bx0, int by0,
+                                     int bmw, int bmh, int lane)
+{
+    const int X = (int)rint(s.kx[i] * (double)d);
+    const int Y = (int)rint(s.ky[j] * (double)d);
     const float dl = s.delta + 0.25f;
     const int wu = window_half(s.fx, (float)X * 0.0625f, (float)d, dl, s.W);
     const int wv = window_half(s.fy, (float)Y * 0.0625f, (float)d, dl, s.H);
     const int i0 = max(i - wu, 0), i1 = min(i + wu, s.W - 1);
     const int j0 = max(j - wv, 0), j1 = min(j + wv, s.H - 1);
-    const int dlo = d - s.dzmm, dhi = d + s.dzmm;
     const int Z = 16 * d;
-    bool found = false;
-    int best_d2 = 0x7fffffff, best_pix = 0x7fffffff;
-    for (int by = j0 >> 3; by <= (j1 >> 3); ++by) {
-        for (int bx = i0 >> 3; bx <= (i1 >> 3); ++bx) {
-            const uint32_t blk = s.oblk[by * s.bw + bx];
-            const int bmin = (int)(blk & 0xFFFFu), bmax = (int)(blk >> 16);
-            if (bmax < dlo || bmin > dhi) continue;
-            if (NN && found) {
-                const int gap = bmin > d ? bmin - d : (bmax < d ? d - bmax : 0);
-                if (256 * gap * gap > best_d2) continue;
-            }
-            const int ja = max(by << 3, j0), jb = min((by << 3) + 7, j1);
-            const int ia = max(bx << 3, i0), ib = min((bx << 3) + 7, i1);
-            for (int jj = ja; jj <= jb; ++jj) {
-                const int rowp = jj * s.W;
-                for (int ii = ia; ii <= ib; ++ii) {
-                    const int pix = rowp + ii;
-                    const int dp = s.depth[pix];
-                    if (dp == 0) continue;
-                    const int dz = 16 * dp - Z;
-                    if (dz > s.dq || dz < -s.dq) continue;
-                    const int2 q = s.oxy[pix];
-                    const int dx = q.x - X;
-                    if (dx > s.dq || dx < -s.dq) continue;
-                    const int dy = q.y - Y;
-                    if (dy > s.dq || dy < -s.dq) continue;
-                    const int d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > s.dq2) continue;
-                    if (!NN) return true;
-                    if (d2 < best_d2 || (d2 == best_d2 && pix < best_pix)) {
-                        best_d2 = d2;
-                        best_pix = pix;
-                    }
-                    found = true;
-                }
-            }
+    const int bxa = i0 >> 3, bya = j0 >> 3;
+    const int nbw = (i1 >> 3) - bxa + 1;
+    const int nb = nbw * ((j1 >> 3) - bya + 1);
+    for (int b0 = 0; b0 < nb; b0 += 4) {
+        int dp[4], px[4], py[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u;
+            const int by = bya + b / nbw, bx = bxa + b % nbw;
+            px[u] = (bx << 3) + (lane & 7);
+            py[u] = (by << 3) + (lane >> 3);
+            const bool in = b < nb && px[u] >= i0 && px[u] <= i1 && py[u] >= j0 && py[u] <= j1;
+            dp[u] = in ? (int)s.depth[py[u] * s.W + px[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int dz = 16 * dp[u] - Z;
+            if (dp[u] == 0 || dz > s.dq || dz < -s.dq) continue;
+            const int dx = (int)rint(kx_of(s, px[u]) * (double)dp[u]) - X;
+            const int dy = (int)rint(ky_of(s, py[u]) * (double)dp[u]) - Y;
+            if (dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq) continue;
+            if (dx * dx + dy * dy + dz * dz > s.dq2) continue;
+            const int bxr = px[u] - bx0, byr = py[u] - by0;
+            if (bxr < 0 || bxr >= bmw || byr < 0 || byr >= bmh) continue;  // never taken: window <= (wtx, wty)
+            const int bit = byr * bmw + bxr;
+            if constexpr (G)
+                __hip_atomic_fetch_or(bm + (bit >> 5), 1u << (bit & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                atomicOr(bm + (bit >> 5), 1u << (bit & 31));
         }
     }
-    *nn_pix = best_pix;
-    return found;
 }
 
-// J_o search: rendered points of the tile within delta of observed point p.
-// Returns the tile index of the nearest one in *nn_k (RGB mode).
-template <bool NN, bool G>
-__device__ bool search_rendered(const SceneDev &s, const uint32_t *tile, const uint32_t *rbmin,
-                                const uint32_t *rbmax, const PoseInfo &in, int nbx, int i, int j,
-                                int dp, int X, int Y, int *nn_k)
+// Nearest rendered point of the tile within delta of observed point
+// (i, j, dp, X, Y): the smallest (squared distance, tile index), returned to
+// every lane; ~0 if none.
+template <bool G>
+__device__ unsigned long long wave_nearest_rendered(const SceneDev &s, const uint32_t *tile, const uint32_t *rbmin,
+                                                    const uint32_t *rbmax, const PoseInfo &in, int nbx, int i,
+                                                    int j, int dp, int X, int Y, int lane)
 {
     const float dl = s.delta + 0.25f;
     const int wu = window_half(s.fx, (float)X * 0.0625f, (float)dp, dl, s.W);
     const int wv = window_half(s.fy, (float)Y * 0.0625f, (float)dp, dl, s.H);
     const int i0 = max(i - wu, in.tx0) - in.tx0, i1 = min(i + wu, in.tx0 + in.tw - 1) - in.tx0;
     const int j0 = max(j - wv, in.ty0) - in.ty0, j1 = min(j + wv, in.ty0 + in.th - 1) - in.ty0;
-    if (i0 > i1 || j0 > j1) return false;
     const int dlo = dp - s.dzmm, dhi = dp + s.dzmm;
     const int Z = 16 * dp;
-    bool found = false;
-    int best_d2 = 0x7fffffff, best_k = 0x7fffffff;
-    for (int by = j0 >> 3; by <= (j1 >> 3); ++by) {
-        for (int bx = i0 >> 3; bx <= (i1 >> 3); ++bx) {
-            const int b = by * nbx + bx;
-            const int bmin = (int)tld<G>(rbmin + b), bmax = (int)tld<G>(rbmax + b);
-            if (bmax < dlo || bmin > dhi) continue;
-            if (NN && found) {
-                const int gap = bmin > dp ? bmin - dp : (bmax < dp ? dp - bmax : 0);
-                if (256 * gap * gap > best_d2) continue;
-            }
-            const int ja = max(by << 3, j0), jb = min((by << 3) + 7, j1);
-            const int ia = max(bx << 3, i0), ib = min((bx << 3) + 7, i1);
-            for (int ty = ja; ty <= jb; ++ty) {
-                const double kyv = s.ky[in.ty0 + ty];
-                for (int tx = ia; tx <= ib; ++tx) {
-                    const int k = ty * in.tw + tx;
-                    const uint32_t key = tld<G>(tile + k);
-                    if (key == kEmptyKey) continue;
-                    const int dr = (int)(key >> 16);
-                    const int dz = Z - 16 * dr;
-                    if (dz > s.dq || dz < -s.dq) continue;
-                    const int xr = (int)rint(s.kx[in.tx0 + tx] * (double)dr);
-                    const int dx = X - xr;
-                    if (dx > s.dq || dx < -s.dq) continue;
-                    const int yr = (int)rint(kyv * (double)dr);
-                    const int dy = Y - yr;
-                    if (dy > s.dq || dy < -s.dq) continue;
-                    const int d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > s.dq2) continue;
-                    if (!NN) return true;
-                    if (d2 < best_d2 || (d2 == best_d2 && k < best_k)) {
-                        best_d2 = d2;
-                        best_k = k;
-                    }
-                    found = true;
-                }
+    unsigned long long best = ~0ULL;
+    if (i0 <= i1 && j0 <= j1) {
+        for (int by = j0 >> 3; by <= (j1 >> 3); ++by) {
+            for (int bx = i0 >> 3; bx <= (i1 >> 3); ++bx) {
+                const int b = by * nbx + bx;
+                if ((int)tld<G>(rbmax + b) < dlo || (int)tld<G>(rbmin + b) > dhi) continue;
+                const int tx = (bx << 3) + (lane & 7), ty = (by << 3) + (lane >> 3);
+                if (tx < i0 || tx > i1 || ty < j0 || ty > j1) continue;
+                const int k = ty * in.tw + tx;
+                const uint32_t key = tld<G>(tile + k);
+                if (key == kEmptyKey) continue;
+                const int dr = (int)(key >> 16);
+                const int dz = Z - 16 * dr;
+                if (dz > s.dq || dz < -s.dq) continue;
+                const int dx = X - (int)rint(kx_of(s, in.tx0 + tx) * (double)dr);
+                const int dy = Y - (int)rint(ky_of(s, in.ty0 + ty) * (double)dr);
+                if (dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq) continue;
+                const int d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 > s.dq2) continue;
+                const unsigned long long c = ((unsigned long long)d2 << 32) | (uint32_t)k;
+                best = c < best ? c : best;
             }
         }
     }
-    *nn_k = best_k;
-    return found;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+    }
+    return best;
 }
 
 // Is observed point (X, Y, Z in 1/16 mm) inside the object's AABB at pose P,
@@ -393,8 +393,10 @@ __device__ __forceinline__ int wave_popc(bool pred)
 
 template <int BLOCK, bool G, bool RGB>
 __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, int p, uint32_t *tile,
-                           uint32_t *rbmin, uint32_t *rbmax, int *cnt)
+                           uint32_t *rbmin, uint32_t *rbmax, uint32_t *bm, int *cnt, int *queue, int *qn)
 {
+    constexpr int NW = BLOCK / 64;
+    const int wave = threadIdx.x >> 6;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const PoseInfo in = w.info[p];
@@ -411,6 +413,11 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
         tst<G>(rbmin + k, 0xFFFFu);
         tst<G>(rbmax + k, 0u);
     }
+    // explained-bitmap region: the tile dilated by the scene's neighbour window
+    const int bx0 = in.tx0 - s.wtx, by0 = in.ty0 - s.wty;
+    const int bmw = in.tw + 2 * s.wtx, bmh = in.th + 2 * s.wty;
+    const int bmwords = (bmw * bmh + 31) >> 5;
+    for (int k = tid; k < bmwords; k += BLOCK) tst<G>(bm + k, 0u);
     if (tid < 4) cnt[tid] = 0;
     __syncthreads();
 
@@ -455,60 +462,105 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     }
     __syncthreads();
 
-    // 3. J_r
+    // 3. J_r: nearest observed neighbour from the scene table.  The inliers
+    //    of each chunk go to a workgroup queue, and every wave takes queue
+    //    items in turn to mark their observed neighbours for J_o.
     int cR = 0;
     for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
         const int k = k0 + tid;
-        bool out = false;
+        if (tid == 0) *qn = 0;
+        __syncthreads();
+        bool valid = false;
+        int i = 0, j = 0, nn = -1;
+        uint32_t key = kEmptyKey;
         if (k < tpx) {
-            const uint32_t key = tld<G>(tile + k);
+            key = tld<G>(tile + k);
             if (key != kEmptyKey) {
                 const int ty = k / in.tw, tx = k - ty * in.tw;
-                const int i = in.tx0 + tx, j = in.ty0 + ty;
-                const int d = (int)(key >> 16);
-                const int X = (int)rint(s.kx[i] * (double)d);
-                const int Y = (int)rint(s.ky[j] * (double)d);
-                int nn = -1;
-                const bool found = search_observed<RGB>(s, i, j, d, X, Y, &nn);
-                out = !found;
-                if (RGB && found) {
-                    const float4 lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), i, j));
-                    out = ciede2000(lr, s.olab[nn]) > s.tau;
-                }
+                i = in.tx0 + tx;
+                j = in.ty0 + ty;
+                valid = true;
+                const int2 th = s.thdr[j * s.W + i];
+                const int e = (int)(key >> 16) - (th.y & 0xFFFF);
+                if (e >= 0 && e < (int)((uint32_t)th.y >> 16)) nn = s.tnn[th.x + e];
+                if (nn >= 0) queue[atomicAdd(qn, 1)] = k;
             }
         }
+        __syncthreads();
+        const int nq = *qn;
+        for (int t = wave; t < nq; t += NW) {
+            const int kk = queue[t];
+            const int ty = kk / in.tw, tx = kk - ty * in.tw;
+            const int dd = (int)(tld<G>(tile + kk) >> 16);
+            wave_mark_neighbours<G>(s, in.tx0 + tx, in.ty0 + ty, dd, bm, bx0, by0, bmw, bmh, lane);
+        }
+        bool out = valid && nn < 0;
+        if (RGB && nn >= 0) {
+            const float4 lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), i, j));
+            out = ciede2000(lr, s.olab[nn]) > s.tau;
+        }
         cR += wave_popc(out);
+        __syncthreads();
     }
 
-    // 4. J_o
+    // 4. J_o: observed points in V(O); explained iff marked.  In RGB mode the
+    //    explained points of each chunk are queued and the waves find their
+    //    nearest rendered points; the result replaces the queue entry.
     int cQ = 0, cO = 0;
     const int vpx = in.vw * in.vh;
     const double dl = (double)s.delta;
     for (int k0 = 0; k0 < vpx; k0 += BLOCK) {
         const int k = k0 + tid;
-        bool inq = false, out = false;
+        if (RGB) {
+            if (tid == 0) *qn = 0;
+            __syncthreads();
+        }
+        bool inq = false, expl = false;
+        int pix = 0, slot = -1;
         if (k < vpx) {
             const int vy = k / in.vw, vx = k - vy * in.vw;
             const int i = in.vx0 + vx, j = in.vy0 + vy;
-            const int pix = j * s.W + i;
+            pix = j * s.W + i;
             const int dp = s.depth[pix];
             if (dp > 0) {
                 const int2 q = s.oxy[pix];
                 inq = label_mode ? (s.labels[pix] == w.label) : in_volume(m, P, q.x, q.y, dp, dl);
-                if (inq) {
-                    int kr = -1;
-                    const bool found = (tpx > 0) && search_rendered<RGB, G>(s, tile, rbmin, rbmax, in, nbx, i, j,
-                                                                          dp, q.x, q.y, &kr);
-                    out = !found;
-                    if (RGB && found) {
-                        const uint32_t key = tld<G>(tile + kr);
-                        const int ty = kr / in.tw, tx = kr - ty * in.tw;
-                        const float4 lr = srgb_to_lab(
-                            triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                        out = ciede2000(s.olab[pix], lr) > s.tau;
-                    }
+                const int bxr = i - bx0, byr = j - by0;
+                if (inq && bxr >= 0 && bxr < bmw && byr >= 0 && byr < bmh) {
+                    const int bit = byr * bmw + bxr;
+                    expl = (tld<G>(bm + (bit >> 5)) >> (bit & 31)) & 1u;
+                }
+                if (RGB && expl) {
+                    slot = atomicAdd(qn, 1);
+                    queue[slot] = pix;
                 }
             }
+        }
+        bool out = inq && !expl;
+        if (RGB) {
+            __syncthreads();
+            const int nq = *qn;
+            for (int t = wave; t < nq; t += NW) {
+                const int qp = queue[t];
+                const int qj = qp / s.W, qi = qp - qj * s.W;
+                const int dp = s.depth[qp];
+                const int2 q = s.oxy[qp];
+                const unsigned long long r =
+                    wave_nearest_rendered<G>(s, tile, rbmin, rbmax, in, nbx, qi, qj, dp, q.x, q.y, lane);
+                if (lane == 0) queue[t] = r == ~0ULL ? -1 : (int)(r & 0xFFFFFFFFu);
+            }
+            __syncthreads();
+            if (slot >= 0) {
+                const int kr = queue[slot];
+                if (kr >= 0) {
+                    const uint32_t key = tld<G>(tile + kr);
+                    const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                    const float4 lr =
+                        srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                    out = ciede2000(s.olab[pix], lr) > s.tau;
+                }
+            }
+            __syncthreads();
         }
         cQ += wave_popc(inq);
         cO += wave_popc(out);
@@ -535,20 +587,24 @@ __global__ __launch_bounds__(BLOCK) void score_kernel(SceneDev s, MeshDev m, Wor
 {
     extern __shared__ uint32_t smem[];
     __shared__ int cnt[4];
+    __shared__ int queue[BLOCK];
+    __shared__ int qn;
     const int count = w.counts[cls];
-    uint32_t *tile, *rbmin, *rbmax;
+    uint32_t *tile, *rbmin, *rbmax, *bm;
     if constexpr (G) {
         tile = w.gscratch + (size_t)blockIdx.x * w.gscratch_stride;
         rbmin = tile + (size_t)s.W * s.H;
         rbmax = rbmin + (size_t)s.bw * s.bh;
+        bm = rbmax + (size_t)s.bw * s.bh;
     } else {
         tile = smem;
         rbmin = smem + cap;
         rbmax = rbmin + nbcap;
+        bm = rbmax + nbcap;
     }
     for (int it = blockIdx.x; it < count; it += gridDim.x) {
         const int p = w.lists[cls * w.n + it];
-        score_pose<BLOCK, G, RGB>(s, m, w, p, tile, rbmin, rbmax, cnt);
+        score_pose<BLOCK, G, RGB>(s, m, w, p, tile, rbmin, rbmax, bm, cnt, queue, &qn);
     }
 }
 
@@ -681,6 +737,147 @@ __global__ void scene_blocks_kernel(SceneDev s, uint32_t *oblk)
     oblk[b] = (uint32_t)mn | ((uint32_t)mx << 16);
 }
 
+// ------------------------------------------------------------------ NN table
+
+// Row pass of the window min/max of valid observed depths: min | max << 16.
+__global__ void table_rows_kernel(SceneDev s, uint32_t *tmp)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= s.W * s.H) return;
+    const int j = k / s.W, i = k - j * s.W;
+    int mn = 0xFFFF, mx = 0;
+    for (int ii = max(i - s.wtx, 0); ii <= min(i + s.wtx, s.W - 1); ++ii) {
+        const int d = s.depth[j * s.W + ii];
+        if (d == 0) continue;
+        mn = min(mn, d);
+        mx = max(mx, d);
+    }
+    tmp[k] = (uint32_t)mn | ((uint32_t)mx << 16);
+}
+
+// Column pass: the depths a rendered point at this pixel may have and still
+// find an observed point within delta: [min - dzmm, max + dzmm].
+__global__ void table_cols_kernel(SceneDev s, const uint32_t *tmp, int2 *thdr)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= s.W * s.H) return;
+    const int j = k / s.W, i = k - j * s.W;
+    int mn = 0xFFFF, mx = 0;
+    for (int jj = max(j - s.wty, 0); jj <= min(j + s.wty, s.H - 1); ++jj) {
+        const uint32_t v = tmp[jj * s.W + i];
+        mn = min(mn, (int)(v & 0xFFFFu));
+        mx = max(mx, (int)(v >> 16));
+    }
+    int lo = 0, n = 0;
+    if (mx > 0) {
+        lo = max(1, mn - s.dzmm);
+        const int hi = min(65534, mx + s.dzmm);
+        n = hi - lo + 1;
+    }
+    thdr[k] = make_int2(0, lo | (n << 16));
+}
+
+// Exclusive scan of the per-pixel entry counts into thdr[].x (one block).
+__global__ __launch_bounds__(1024) void table_scan_kernel(int N, int2 *thdr, long long *total)
+{
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (N + 1023) / 1024;
+    const int a = t * chunk, b = min(a + chunk, N);
+    long long sum = 0;
+    for (int k = a; k < b; ++k) sum += (long long)((uint32_t)thdr[k].y >> 16);
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        long long run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const long long v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    long long run = part[t];
+    for (int k = a; k < b; ++k) {
+        const int n = (int)((uint32_t)thdr[k].y >> 16);
+        thdr[k].x = (int)run;
+        run += n;
+    }
+}
+
+// One wave per pixel: each lane takes one depth of the pixel's range and
+// finds the nearest observed point within delta (ties: lower pixel index),
+// scanning the window of the chunk's smallest depth (the widest one) with
+// wave-uniform loads of the observed data.
+__global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tnn)
+{
+    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (a >= s.W * s.H) return;
+    const int2 th = s.thdr[a];
+    const int lo = th.y & 0xFFFF, n = (int)((uint32_t)th.y >> 16);
+    if (n == 0) return;
+    const int j = a / s.W, i = a - j * s.W;
+    const double kxi = s.kx[i], kyj = s.ky[j];
+    const float dl = s.delta + 0.25f;
+    for (int e0 = 0; e0 < n; e0 += 64) {
+        const int e = e0 + lane;
+        const int d = lo + min(e, n - 1);
+        const int X = (int)rint(kxi * (double)d);
+        const int Y = (int)rint(kyj * (double)d);
+        const int Z = 16 * d;
+        const int dmin = lo + e0, dmax = lo + min(e0 + 63, n - 1);
+        const int Xmin = (int)rint(kxi * (double)dmin), Ymin = (int)rint(kyj * (double)dmin);
+        const int wu = window_half(s.fx, (float)Xmin * 0.0625f, (float)dmin, dl, s.W);
+        const int wv = window_half(s.fy, (float)Ymin * 0.0625f, (float)dmin, dl, s.H);
+        const int i0 = max(i - wu, 0), i1 = min(i + wu, s.W - 1);
+        const int j0 = max(j - wv, 0), j1 = min(j + wv, s.H - 1);
+        const int dlo = dmin - s.dzmm, dhi = dmax + s.dzmm;
+        unsigned long long best = ~0ULL;
+        for (int by = j0 >> 3; by <= (j1 >> 3); ++by) {
+            for (int bx = i0 >> 3; bx <= (i1 >> 3); ++bx) {
+                const uint32_t blk = s.oblk[by * s.bw + bx];
+                if ((int)(blk >> 16) < dlo || (int)(blk & 0xFFFFu) > dhi) continue;
+                const int ja = max(by << 3, j0), jb = min((by << 3) + 7, j1);
+                const int ia = max(bx << 3, i0), ib = min((bx << 3) + 7, i1);
+                for (int jj = ja; jj <= jb; ++jj) {
+                    for (int ii = ia; ii <= ib; ++ii) {
+                        const int pix = jj * s.W + ii;
+                        const int dp = s.depth[pix];
+                        if (dp < dlo || dp > dhi || dp == 0) continue;
+                        const int2 q = s.oxy[pix];
+                        const int dz = 16 * dp - Z;
+                        const int dx = q.x - X, dy = q.y - Y;
+                        if (dz > s.dq || dz < -s.dq || dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq) continue;
+                        const int d2 = dx * dx + dy * dy + dz * dz;
+                        if (d2 > s.dq2) continue;
+                        const unsigned long long key = ((unsigned long long)d2 << 32) | (uint32_t)pix;
+                        best = key < best ? key : best;
+                    }
+                }
+            }
+        }
+        if (e < n) tnn[th.x + e] = best == ~0ULL ? -1 : (int32_t)(best & 0xFFFFFFFFu);
+    }
+}
+
+hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st)
+{
+    const int N = s.W * s.H;
+    table_rows_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, tmp);
+    table_cols_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, tmp, thdr);
+    table_scan_kernel<<<1, 1024, 0, st>>>(N, thdr, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st)
+{
+    const int N = s.W * s.H;
+    table_fill_kernel<<<(N + 3) / 4, 256, 0, st>>>(s, tnn);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ render (inspection)
 
 __global__ __launch_bounds__(256) void render_kernel(SceneDev s, MeshDev m, const float *poses, uint32_t *keys,
@@ -748,9 +945,9 @@ __global__ __launch_bounds__(1024) void argmin_kernel(const int32_t *jr, const i
 
 // ------------------------------------------------------------------ launchers
 
-size_t lds_bytes_for(int cap, int W, int H)
+size_t lds_bytes_for(int cap, int W, int H, int wtx, int wty)
 {
-    return (size_t)cap * 4 + (size_t)nbcap_for(cap, W, H) * 8;
+    return (size_t)cap * 4 + (size_t)nbcap_for(cap, W, H) * 8 + (size_t)bmcap_for(cap, W, H, wtx, wty) * 4;
 }
 
 hipError_t upload_colour_table(const float *lin256)
@@ -773,14 +970,14 @@ static hipError_t launch_class_t(const SceneDev &s, const MeshDev &m, const Work
                                  hipStream_t st)
 {
     if (cls == 0) {
-        const size_t lds = lds_bytes_for(c.cap_small, s.W, s.H);
+        const size_t lds = lds_bytes_for(c.cap_small, s.W, s.H, s.wtx, s.wty);
         hipError_t e = hipFuncSetAttribute((const void *)score_kernel<512, false, RGB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         score_kernel<512, false, RGB><<<c.grid_small, 512, lds, st>>>(s, m, w, 0, c.cap_small,
                                                                       nbcap_for(c.cap_small, s.W, s.H));
     } else if (cls == 1) {
-        const size_t lds = lds_bytes_for(c.cap_large, s.W, s.H);
+        const size_t lds = lds_bytes_for(c.cap_large, s.W, s.H, s.wtx, s.wty);
         hipError_t e = hipFuncSetAttribute((const void *)score_kernel<1024, false, RGB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;

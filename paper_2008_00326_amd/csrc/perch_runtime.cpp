@@ -60,7 +60,7 @@ struct MeshRec {
 };
 
 struct SceneRec {
-    DevBuf depth, rgb, labels, oxy, olab, oblk, kx, ky;
+    DevBuf depth, rgb, labels, oxy, olab, oblk, kx, ky, thdr, tnn;
     SceneDev dev{};
     std::vector<int32_t> host_labels;
     std::map<int32_t, std::vector<int>> label_boxes;
@@ -193,21 +193,26 @@ void colour_table(float out[256])
     }
 }
 
-int cap_for_lds(size_t bytes, int W, int H)
+constexpr long long kStaticLds = 4 * 1024 + 256;
+
+int cap_for_lds(size_t bytes, int W, int H, int wtx, int wty)
 {
-    // largest cap with lds_bytes_for(cap) + 64 (static counters) <= bytes
-    const long long fixed = 8LL * ((W + H) / 4 + 4) + 64;
-    long long cap = ((long long)bytes - fixed) * 64 / (4 * 64 + 8);
-    cap = std::max(0LL, cap - 64);
-    while (cap > 0 && (long long)lds_bytes_for((int)cap, W, H) + 64 > (long long)bytes) --cap;
-    return (int)cap;
+    // largest cap with lds_bytes_for(cap) + static LDS (counters and the
+    // 1024-entry work queue) <= bytes
+    long long lo = 0, hi = (long long)bytes / 4;
+    while (lo < hi) {
+        const long long mid = (lo + hi + 1) / 2;
+        if ((long long)lds_bytes_for((int)mid, W, H, wtx, wty) + kStaticLds <= (long long)bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return (int)lo;
 }
 
 LaunchCfg launch_cfg(const perch_ctx *ctx, const SceneDev &s)
 {
     LaunchCfg c;
-    c.cap_large = std::min(cap_for_lds(ctx->lds_max, s.W, s.H), s.W * s.H);
-    c.cap_small = std::min(cap_for_lds(ctx->lds_max / 2, s.W, s.H), c.cap_large);
+    c.cap_large = std::min(cap_for_lds(ctx->lds_max, s.W, s.H, s.wtx, s.wty), s.W * s.H);
+    c.cap_small = std::min(cap_for_lds(ctx->lds_max / 2, s.W, s.H, s.wtx, s.wty), c.cap_large);
     c.cap_small = std::min(c.cap_small, 16384);
     c.grid_small = ctx->n_cu * 2;
     c.grid_large = ctx->n_cu;
@@ -246,7 +251,9 @@ perch_status prepare_work(perch_ctx *ctx, SceneRec &sr, MeshRec &mr, int32_t lab
 {
     StreamBufs &b = ctx->work[st];
     cfg = launch_cfg(ctx, sr.dev);
-    const size_t slot = (size_t)sr.dev.W * sr.dev.H + 2 * (size_t)sr.dev.bw * sr.dev.bh;
+    const SceneDev &sd = sr.dev;
+    const size_t bm_words = ((size_t)(sd.W + 2 * sd.wtx) * (sd.H + 2 * sd.wty)) / 32 + 2;
+    const size_t slot = (size_t)sd.W * sd.H + 2 * (size_t)sd.bw * sd.bh + bm_words;
     perch_status s;
     if ((s = ctx->ensure(b.info, (size_t)n * sizeof(PoseInfo)))) return s;
     if ((s = ctx->ensure(b.lists, (size_t)kNumClasses * n * sizeof(int)))) return s;
@@ -355,7 +362,8 @@ perch_status perch_destroy(perch_ctx *ctx)
     }
     for (auto &kv : ctx->scenes) {
         SceneRec &r = kv.second;
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky}) ctx->release(*b);
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
+            ctx->release(*b);
     }
     for (auto &kv : ctx->work) {
         StreamBufs &w = kv.second;
@@ -496,8 +504,10 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         A(r.olab, N * sizeof(float4));
     }
     if (d->labels) A(r.labels, N * 4);
+    DevBuf tmp;
     auto cleanup = [&]() {
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky}) ctx->release(*b);
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn, &tmp})
+            ctx->release(*b);
     };
     if (st != PERCH_OK) {
         std::string msg = g_last_error;
@@ -532,19 +542,71 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.tau = d->tau_c;
     s.flags = d->flags;
     s.stride = d->stride;
+    // Window half-sizes that hold every neighbour pair of this scene: a
+    // rendered point with an observed neighbour has depth >= dmin - dzmm,
+    // and the pixel window shrinks with depth.
+    int dmin = 65535;
+    for (size_t k = 0; k < N; ++k)
+        if (d->depth_mm[k] > 0 && d->depth_mm[k] < dmin) dmin = d->depth_mm[k];
+    {
+        const double dl = (double)d->delta_mm + 0.25;
+        const double z = (double)dmin - (double)s.dzmm;
+        const double rx = std::max(std::fabs(0.0 - K.cx), std::fabs((double)(W - 1) - K.cx)) / K.fx;
+        const double ry = std::max(std::fabs(0.0 - K.cy), std::fabs((double)(H - 1) - K.cy)) / K.fy;
+        s.wtx = W;
+        s.wty = H;
+        if (dmin < 65535 && z - dl > 1.0) {
+            s.wtx = std::min(W, (int)(K.fx * dl * std::sqrt(1.0 + rx * rx) / (z - dl)) + 2);
+            s.wty = std::min(H, (int)(K.fy * dl * std::sqrt(1.0 + ry * ry) / (z - dl)) + 2);
+        }
+    }
     if (e == hipSuccess)
         e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
             return launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int2 *)r.oxy.ptr, (float4 *)r.olab.ptr,
                                      (uint32_t *)r.oblk.ptr, ctx->stream);
         });
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         cleanup();
         return fail(PERCH_EDEVICE, "scene upload / preparation: %s", hipGetErrorString(e));
     }
+    // nearest-neighbour table of the observed cloud
+    if ((st = ctx->alloc(r.thdr, N * sizeof(int2))) || (st = ctx->alloc(tmp, N * 4 + 64))) {
+        std::string msg = g_last_error;
+        cleanup();
+        return fail(st, "%s", msg.c_str());
+    }
+    s.thdr = (const int2 *)r.thdr.ptr;
+    long long *total_dev = (long long *)((char *)tmp.ptr + N * 4);
+    long long total = 0;
+    e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
+        return launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev, ctx->stream);
+    });
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, total_dev, 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(PERCH_EDEVICE, "scene table ranges: %s", hipGetErrorString(e));
+    }
+    ctx->release(tmp);
+    if (total >= (1LL << 31) - 1) {
+        cleanup();
+        return fail(PERCH_ENOMEM, "scene neighbour table too large (%lld entries)", total);
+    }
+    if ((st = ctx->alloc(r.tnn, (size_t)std::max(total, 1LL) * 4))) {
+        std::string msg = g_last_error;
+        cleanup();
+        return fail(st, "%s", msg.c_str());
+    }
+    s.tnn = (const int32_t *)r.tnn.ptr;
+    e = ctx->timed(kProfScenePrep, ctx->stream, [&] { return launch_table_fill(s, (int32_t *)r.tnn.ptr, ctx->stream); });
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(PERCH_EDEVICE, "scene table fill: %s", hipGetErrorString(e));
+    }
     if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
     r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.oxy.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
-              + r.ky.bytes;
+              + r.ky.bytes + r.thdr.bytes + r.tnn.bytes;
     const int32_t id = ctx->next_scene++;
     ctx->scenes[id] = std::move(r);
     *scene_id = id;
@@ -559,7 +621,8 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     if (it == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
     (void)hipDeviceSynchronize();
     SceneRec &r = it->second;
-    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky}) ctx->release(*b);
+    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
+        ctx->release(*b);
     ctx->scenes.erase(it);
     return ok();
 }
@@ -660,6 +723,24 @@ perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_m
         total_ms[k] = k < kNumProfSlots ? ctx->total_ms[k] : 0.0;
         launches[k] = k < kNumProfSlots ? ctx->launches[k] : 0;
     }
+    return ok();
+}
+
+perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_info *out)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!out) return fail(PERCH_EINVAL, "null output");
+    auto it = ctx->scenes.find(scene_id);
+    if (it == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    const SceneRec &r = it->second;
+    const LaunchCfg c = launch_cfg(ctx, r.dev);
+    out->device_bytes = r.bytes;
+    out->table_entries = (int64_t)(r.tnn.bytes / 4);
+    out->window_x = r.dev.wtx;
+    out->window_y = r.dev.wty;
+    out->tile_cap_small = c.cap_small;
+    out->tile_cap_large = c.cap_large;
     return ok();
 }
 

@@ -264,3 +264,30 @@ def test_deterministic_and_batch_independent(ctx):
     ctx.drop_scene(sid)
     for mid in mids:
         ctx.unload_mesh(mid)
+
+
+def test_overflow_class_and_scene_info(ctx):
+    """A footprint larger than any LDS tile is scored from device memory."""
+    say("overflow class")
+    K = (320, 240, 262.5, 262.5, 160.0, 120.0)
+    cube = box((-100, -100, -100), (100, 100, 100), n=6, rgb_seed=8)
+    P0 = pose_matrix(np.eye(3), (10, -5, 420))
+    d, _, c = oracle.render(cube, P0, K)
+    sid = ctx.set_scene(K, d, c, delta_mm=10.0, tau_c=20.0, use_rgb=True)
+    info = ctx.scene_info(sid)
+    assert info["tile_cap_large"] < K[0] * K[1]
+    assert info["table_entries"] > 0 and info["device_bytes"] > 0
+    mid = ctx.load_mesh(cube.xyz, cube.tri, cube.rgb)
+    poses = np.stack([P0, pose_matrix(np.eye(3), (14, -2, 415)), pose_matrix(np.eye(3), (0, 0, 330)),
+                      pose_matrix(np.eye(3), (-20, 10, 700))])
+    got = gpu_score(ctx, sid, mid, poses)
+    assert got[2][2] > info["tile_cap_large"] // 2
+    exp = oracle.score(cube, TScene(K, d, c, None), poses, delta_mm=10.0, tau_c=20.0,
+                       flags=oracle.USE_RGB | oracle.MARK_OCCLUDERS, threads=THREADS)
+    for a, b in zip(got[2:], exp[2:]):
+        assert np.array_equal(a, b)
+    for a, b, L in zip(got[:2], exp[:2], (exp[2], exp[3])):
+        assert np.all(np.abs(a - b) <= np.ceil(0.001 * L))
+    assert got[0][0] == 0 and got[1][0] == 0
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
