@@ -101,11 +101,12 @@ def main():
     obj_label = [o.label for o in w.objects]
     n_poses = sum(p.shape[0] for p in poses)
 
-    # per-pose L and Q for the work accounting (untimed)
+    # per-pose L, Q and footprint class for the work accounting (untimed)
     LQ = []
     for p, mid, lab in zip(poses, obj_mesh, obj_label):
-        jr, jo, nr, nq = ctx.score_poses(sid, mid, p, label=lab)
-        LQ.append((nr.cpu().numpy().astype(np.float64), nq.cpu().numpy().astype(np.float64)))
+        jr, jo, nr, nq = ctx.score_poses(sid, mid, p, label=lab, stream=stream)
+        cls = ctx.last_classes(p.shape[0], stream=stream)
+        LQ.append((nr.cpu().numpy().astype(np.float64), nq.cpu().numpy().astype(np.float64), cls))
     torch.cuda.synchronize()
 
     def step():
@@ -133,23 +134,25 @@ def main():
     value = n_poses * args.steps / elapsed
 
     # dominant kernel and its roofline
-    score_slots = ["score_small", "score_large", "score_overflow"]
+    score_slots = ["score_lds512", "score_lds1024", "score_lds_tile", "score_device"]
     dom = max(score_slots, key=lambda k: prof[k][0])
     dom_ms, dom_launches = prof[dom]
     areas = tile_areas(w)
     W, H = w.scene.K[0], w.scene.K[1]
     info = ctx.scene_info(sid)
     caps = (info["tile_cap_small"], info["tile_cap_large"])
-    cls_idx = {"score_small": 0, "score_large": 1, "score_overflow": 2}[dom]
+    cls_idx = score_slots.index(dom)
     ops = 0.0
     byts = 0.0
     c_q = 600.0 + (300.0 if w.use_rgb else 0.0)
     c_o = 300.0
     b_pix = 5.0 if w.use_rgb else 2.0
-    for o, (L, Q), ar in zip(w.objects, LQ, areas):
+    class_poses = [0, 0, 0, 0]
+    for o, (L, Q, cls), ar in zip(w.objects, LQ, areas):
         m = w.meshes[o.mesh]
         tile = ar[:, 0]
-        cls = np.where(tile <= caps[0], 0, np.where(tile <= caps[1], 1, 2))
+        for c in range(4):
+            class_poses[c] += int((cls == c).sum())
         sel = cls == cls_idx
         ops += float(np.sum(60.0 * m.n_tris + 10.0 * tile[sel] + c_q * L[sel] + c_o * Q[sel]))
         if sel.any():
@@ -187,6 +190,7 @@ def main():
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4), "launches": dom_launches,
                      "hbm_achieved_GBs": round(hbm_gbs, 2), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 6)},
         "kernels_ms": {k: round(v[0] / max(args.steps, 1), 4) for k, v in prof.items() if v[1]},
+        "poses_per_class": class_poses,
     }
 
     if not args.no_cpu_baseline:

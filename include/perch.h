@@ -107,8 +107,8 @@ typedef struct {
     size_t device_bytes;          /* HBM held by the scene (images, points, neighbour table) */
     int64_t table_entries;        /* entries of its nearest-neighbour table */
     int32_t window_x, window_y;   /* pixel half-windows that contain every neighbour pair */
-    int32_t tile_cap_small;       /* LDS tile capacity (pixels) of the two scoring classes; */
-    int32_t tile_cap_large;       /*   larger footprints are scored from device memory */
+    int32_t tile_cap_small;       /* LDS words (raster tile + J_o keys) of the scoring classes */
+    int32_t tile_cap_large;       /*   1 and 2; larger footprints use device memory */
 } perch_scene_info;
 
 /* Describe a resident scene (footprint, search windows, tile classes). */
@@ -154,11 +154,18 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id,
  * launch stream; 0 stops recording.  perch_profile_read waits for the
  * recorded events and returns, per slot, the summed duration in
  * milliseconds and the number of launches since the last enable.  Slots:
- * 0 pose set-up/classification, 1 scoring (LDS tile, small class),
- * 2 scoring (LDS tile, large class), 3 scoring (global-memory tile),
- * 4 argmin, 5 scene preparation, 6 render. */
+ * 0 pose set-up/classification; scoring kernels by footprint class:
+ * 1 tile and keys in LDS (512 threads), 2 tile and keys in LDS (1024
+ * threads), 3 tile in LDS and keys in device memory, 4 tile and keys in
+ * device memory; 5 argmin, 6 scene preparation, 7 render. */
 perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
+
+/* Footprint class (0..3, the scoring slots 1..4 of the profiler) that the
+ * last perch_score_poses call on hip_stream (NULL = the context's stream)
+ * assigned to each of its n poses: class_host[i] for pose i.  Blocks until
+ * that call has finished.  Meant for inspection and work accounting. */
+perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int32_t *class_host);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char *perch_last_error(void);

@@ -79,6 +79,7 @@ def load_library():
         "perch_scene_info_get": ([P, I32, P], ctypes.c_int),
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
+        "perch_last_classes": ([P, VP, I32, P], ctypes.c_int),
         "perch_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -215,7 +216,8 @@ class Context:
                                           _np_ptr(bi), _np_ptr(bc), _stream_ptr(stream)))
         return bi, bc
 
-    PROFILE_SLOTS = ("setup", "score_small", "score_large", "score_overflow", "argmin", "scene_prep", "render")
+    PROFILE_SLOTS = ("setup", "score_lds512", "score_lds1024", "score_lds_tile", "score_device", "argmin",
+                     "scene_prep", "render")
 
     def profile(self, enable: bool = True):
         """Start (clearing the record) or stop bracketing kernel launches with HIP events."""
@@ -228,6 +230,15 @@ class Context:
         cnt = np.zeros(n, np.int32)
         _check(self._lib.perch_profile_read(self._h, n, _np_ptr(ms), _np_ptr(cnt)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PROFILE_SLOTS)}
+
+    def last_classes(self, n: int, stream=None):
+        """Footprint class (0..3) of each pose of the last score_poses call on the stream."""
+        import torch
+        out = np.zeros(n, np.int32)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(self._lib.perch_last_classes(self._h, _stream_ptr(stream), int(n), _np_ptr(out)))
+        return out
 
     def render(self, scene_id, mesh_id, poses, K, *, rgb=False, tri=False, stream=None):
         """Full-image renders of (n, 12) poses: (depth u16, rgb u8 or None, tri i32 or None) tensors."""

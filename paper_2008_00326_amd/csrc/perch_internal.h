@@ -9,12 +9,13 @@ namespace perch {
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 constexpr int kBlockPx = 8;         // side of the depth-range blocks (pixels)
 constexpr int kMaxTris = 65535;     // triangle index lives in 16 bits of the key
-constexpr int kNumClasses = 3;      // LDS small, LDS large, global overflow
+constexpr int kNumClasses = 4;      // LDS small, LDS large, LDS tile + device keys, device memory
 
 // Per-pose screen regions, computed by the setup kernel.
 struct PoseInfo {
     int tx0, ty0, tw, th;   // raster tile (clipped to the image), may be empty
     int vx0, vy0, vw, vh;   // region holding every observed pixel that may lie in V(O)
+    int jx0, jy0, jw, jh;   // part of the V region within reach of a rendered point
 };
 
 struct SceneDev {
@@ -52,23 +53,21 @@ struct Work {
     PoseInfo *info;          // n
     int *lists;              // kNumClasses * n pose indices
     int *counts;             // kNumClasses counters
-    uint32_t *gscratch;      // overflow tiles
-    size_t gscratch_stride;  // uint32 words per overflow slot
-    int cap_small, cap_large;
+    uint32_t *gscratch;      // device-memory slots of classes 2 (keys) and 3 (tile + keys)
+    size_t slot_base[kNumClasses];   // first word of each class's slots
+    size_t slot_words[kNumClasses];  // words per work-group slot
+    int cap_small, cap_large; // LDS words (tile + keys) of the two LDS classes
+    int key32;               // squared radius fits the 16-bit distance field of LDS keys
     int vbox_label[4];       // label mode: x0, y0, w, h of the label's pixels
 };
 
 // Launch configuration chosen by the runtime (and the tuner).
 struct LaunchCfg {
-    int cap_small;      // LDS tile capacity (pixels), class 0
-    int cap_large;      // class 1
-    int grid_small, grid_large, grid_ovf;
+    int cap_small;      // LDS words per work-group (tile + keys), class 0
+    int cap_large;      // classes 1 and 2 (class 2: tile only)
+    int grid[kNumClasses];
 };
 
-// Upper bound on the 8x8 blocks of any tile of at most `cap` pixels inside a
-// W x H image: ceil(w/8) ceil(h/8) <= cap/64 + 7 (W + H)/64 + 1.
-inline int nbcap_for(int cap, int W, int H) { return cap / 64 + (W + H) / 4 + 4; }
-size_t lds_bytes_for(int cap, int W, int H, int wtx, int wty);
 hipError_t upload_colour_table(const float *lin256);
 
 hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *oxy, float4 *olab,
@@ -77,19 +76,13 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *ox
 // that can have an observed point within delta, then one entry per depth.
 hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st);
 hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
-// Words of the LDS "explained" bitmap for a tile of at most `cap` pixels.
-inline int bmcap_for(int cap, int W, int H, int wtx, int wty)
-{
-    const long long bits = (long long)cap + 2LL * wtx * H + 2LL * wty * W + 4LL * wtx * wty;
-    return (int)(bits / 32 + 2);
-}
 hipError_t launch_setup(const SceneDev &s, const MeshDev &m, const Work &w, hipStream_t st);
 hipError_t launch_score_class(const SceneDev &s, const MeshDev &m, const Work &w, const LaunchCfg &c, int cls,
                               hipStream_t st);
 
 // Kernel slots reported by the profiler (perch_profile_read).
-enum ProfSlot { kProfSetup = 0, kProfSmall = 1, kProfLarge = 2, kProfOverflow = 3, kProfArgmin = 4,
-                kProfScenePrep = 5, kProfRender = 6, kNumProfSlots = 8 };
+enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
+                kNumProfSlots = 8 };
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n,
                          uint32_t *keys, uint16_t *depth, uint8_t *rgb, int32_t *tri,
                          hipStream_t st);

@@ -88,13 +88,6 @@ __device__ __forceinline__ void tmin(uint32_t *p, uint32_t v)
     if constexpr (G) __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else atomicMin(p, v);
 }
-template <bool G>
-__device__ __forceinline__ void tmax(uint32_t *p, uint32_t v)
-{
-    if constexpr (G) __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else atomicMax(p, v);
-}
-
 // Rasterize triangle t into the tile covering pixels [tx0, tx0+tw) x [ty0, ty0+th).
 template <bool G>
 __device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev &m, const float *P,
@@ -258,116 +251,78 @@ __device__ __forceinline__ int window_half(float f, float lat, float z, float dl
     return (int)bnd + 1;
 }
 
-// Wave-cooperative window scans.  The caller's whole wave works on one
-// point: each iteration covers one 8x8 block of the window, lane l taking
-// pixel (l & 7, l >> 3) of the block; blocks whose depth range cannot hold a
-// point within delta are skipped for the whole wave.
+// Nearest-neighbour keys of the J_o region: smallest (squared distance,
+// tile index of the rendered point) over the rendered points within delta.
+// 32 bits (distance << 16 | index) in LDS, 64 bits in device memory.
+template <bool G> struct KeyOf;
+template <> struct KeyOf<false> {
+    using T = uint32_t;
+    static constexpr T kEmpty = 0xFFFFFFFFu;
+    __device__ static T make(int d2, int k) { return ((uint32_t)d2 << 16) | (uint32_t)k; }
+    __device__ static int index(T key) { return (int)(key & 0xFFFFu); }
+    __device__ static void min(T *p, T v) { atomicMin(p, v); }
+    __device__ static T load(const T *p) { return *p; }
+    __device__ static void store(T *p, T v) { *p = v; }
+};
+template <> struct KeyOf<true> {
+    using T = unsigned long long;
+    static constexpr T kEmpty = ~0ULL;
+    __device__ static T make(int d2, int k) { return ((unsigned long long)(uint32_t)d2 << 32) | (uint32_t)k; }
+    __device__ static int index(T key) { return (int)(key & 0xFFFFFFFFu); }
+    __device__ static void min(T *p, T v) { __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ static T load(const T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ static void store(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+};
 
-// Back-projection factors 16 (i - cx) / fx and 16 (j - cy) / fy, computed
-// with the same correctly rounded binary64 operations as the per-column
-// tables, so that no table load sits on the critical path.
-__device__ __forceinline__ double kx_of(const SceneDev &s, int i)
-{
-    return (((double)i - (double)s.cx) * 16.0) / (double)s.fx;
-}
-__device__ __forceinline__ double ky_of(const SceneDev &s, int j)
-{
-    return (((double)j - (double)s.cy) * 16.0) / (double)s.fy;
-}
-
-// Mark, in the "explained" bitmap, every observed point within delta of the
-// rendered point (i, j, d): the J_o side of Eq. 3 for this point.  The depth
-// loads of four window blocks are issued before any of them is used.
+// The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
+// visits every observed pixel of r's window inside the J_o region: each
+// observed point within delta of r min-combines (d2, k) into its key.  This
+// marks the points that r explains (Eq. 3) and, over all r, leaves each
+// observed point's nearest rendered neighbour (Eq. 4).  Lanes stride over the
+// window in row-major order, four pixels per lane per round, and every load
+// of a round is issued before any is used.
 template <bool G>
-__device__ void wave_mark_neighbours(const SceneDev &s, int i, int j, int d, uint32_t *bm, int bx0, int by0,
-                                     int bmw, int bmh, int lane)
+__device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typename KeyOf<G>::T *keys, int jx0,
+                          int jy0, int jw, int jh, int lane)
 {
+    using K = KeyOf<G>;
     const int X = (int)rint(s.kx[i] * (double)d);
     const int Y = (int)rint(s.ky[j] * (double)d);
     const float dl = s.delta + 0.25f;
     const int wu = window_half(s.fx, (float)X * 0.0625f, (float)d, dl, s.W);
     const int wv = window_half(s.fy, (float)Y * 0.0625f, (float)d, dl, s.H);
-    const int i0 = max(i - wu, 0), i1 = min(i + wu, s.W - 1);
-    const int j0 = max(j - wv, 0), j1 = min(j + wv, s.H - 1);
+    const int i0 = max(max(i - wu, 0), jx0), i1 = min(min(i + wu, s.W - 1), jx0 + jw - 1);
+    const int j0 = max(max(j - wv, 0), jy0), j1 = min(min(j + wv, s.H - 1), jy0 + jh - 1);
+    if (i0 > i1 || j0 > j1) return;
+    const int ww = i1 - i0 + 1;
+    const int ws = ww * (j1 - j0 + 1);
+    const float inv = 1.0f / (float)ww;
     const int Z = 16 * d;
-    const int bxa = i0 >> 3, bya = j0 >> 3;
-    const int nbw = (i1 >> 3) - bxa + 1;
-    const int nb = nbw * ((j1 >> 3) - bya + 1);
-    for (int b0 = 0; b0 < nb; b0 += 4) {
+    for (int q0 = 0; q0 < ws; q0 += 256) {
         int dp[4], px[4], py[4];
+        int2 xy[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int b = b0 + u;
-            const int by = bya + b / nbw, bx = bxa + b % nbw;
-            px[u] = (bx << 3) + (lane & 7);
-            py[u] = (by << 3) + (lane >> 3);
-            const bool in = b < nb && px[u] >= i0 && px[u] <= i1 && py[u] >= j0 && py[u] <= j1;
-            dp[u] = in ? (int)s.depth[py[u] * s.W + px[u]] : 0;
+            const int q = q0 + 64 * u + lane;
+            const int qy = (int)(((float)q + 0.5f) * inv);  // exact: q < 2^20, ww <= 2^12
+            px[u] = i0 + (q - qy * ww);
+            py[u] = j0 + qy;
+            const bool in = q < ws;
+            const int pix = in ? py[u] * s.W + px[u] : 0;
+            dp[u] = in ? (int)s.depth[pix] : 0;
+            xy[u] = in ? s.oxy[pix] : make_int2(0, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int dz = 16 * dp[u] - Z;
-            if (dp[u] == 0 || dz > s.dq || dz < -s.dq) continue;
-            const int dx = (int)rint(kx_of(s, px[u]) * (double)dp[u]) - X;
-            const int dy = (int)rint(ky_of(s, py[u]) * (double)dp[u]) - Y;
-            if (dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq) continue;
-            if (dx * dx + dy * dy + dz * dz > s.dq2) continue;
-            const int bxr = px[u] - bx0, byr = py[u] - by0;
-            if (bxr < 0 || bxr >= bmw || byr < 0 || byr >= bmh) continue;  // never taken: window <= (wtx, wty)
-            const int bit = byr * bmw + bxr;
-            if constexpr (G)
-                __hip_atomic_fetch_or(bm + (bit >> 5), 1u << (bit & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                atomicOr(bm + (bit >> 5), 1u << (bit & 31));
+            const int dx = xy[u].x - X, dy = xy[u].y - Y;
+            if (dp[u] == 0 || dz > s.dq || dz < -s.dq || dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq)
+                continue;
+            const int d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 > s.dq2) continue;
+            K::min(keys + (py[u] - jy0) * jw + (px[u] - jx0), K::make(d2, k));
         }
     }
-}
-
-// Nearest rendered point of the tile within delta of observed point
-// (i, j, dp, X, Y): the smallest (squared distance, tile index), returned to
-// every lane; ~0 if none.
-template <bool G>
-__device__ unsigned long long wave_nearest_rendered(const SceneDev &s, const uint32_t *tile, const uint32_t *rbmin,
-                                                    const uint32_t *rbmax, const PoseInfo &in, int nbx, int i,
-                                                    int j, int dp, int X, int Y, int lane)
-{
-    const float dl = s.delta + 0.25f;
-    const int wu = window_half(s.fx, (float)X * 0.0625f, (float)dp, dl, s.W);
-    const int wv = window_half(s.fy, (float)Y * 0.0625f, (float)dp, dl, s.H);
-    const int i0 = max(i - wu, in.tx0) - in.tx0, i1 = min(i + wu, in.tx0 + in.tw - 1) - in.tx0;
-    const int j0 = max(j - wv, in.ty0) - in.ty0, j1 = min(j + wv, in.ty0 + in.th - 1) - in.ty0;
-    const int dlo = dp - s.dzmm, dhi = dp + s.dzmm;
-    const int Z = 16 * dp;
-    unsigned long long best = ~0ULL;
-    if (i0 <= i1 && j0 <= j1) {
-        for (int by = j0 >> 3; by <= (j1 >> 3); ++by) {
-            for (int bx = i0 >> 3; bx <= (i1 >> 3); ++bx) {
-                const int b = by * nbx + bx;
-                if ((int)tld<G>(rbmax + b) < dlo || (int)tld<G>(rbmin + b) > dhi) continue;
-                const int tx = (bx << 3) + (lane & 7), ty = (by << 3) + (lane >> 3);
-                if (tx < i0 || tx > i1 || ty < j0 || ty > j1) continue;
-                const int k = ty * in.tw + tx;
-                const uint32_t key = tld<G>(tile + k);
-                if (key == kEmptyKey) continue;
-                const int dr = (int)(key >> 16);
-                const int dz = Z - 16 * dr;
-                if (dz > s.dq || dz < -s.dq) continue;
-                const int dx = X - (int)rint(kx_of(s, in.tx0 + tx) * (double)dr);
-                const int dy = Y - (int)rint(ky_of(s, in.ty0 + ty) * (double)dr);
-                if (dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq) continue;
-                const int d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 > s.dq2) continue;
-                const unsigned long long c = ((unsigned long long)d2 << 32) | (uint32_t)k;
-                best = c < best ? c : best;
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(best, off);
-        best = o < best ? o : best;
-    }
-    return best;
 }
 
 // Is observed point (X, Y, Z in 1/16 mm) inside the object's AABB at pose P,
@@ -391,33 +346,25 @@ __device__ __forceinline__ int wave_popc(bool pred)
 
 // ------------------------------------------------------------------ per pose
 
-template <int BLOCK, bool G, bool RGB>
+template <int BLOCK, bool G, bool KG, bool RGB>
 __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, int p, uint32_t *tile,
-                           uint32_t *rbmin, uint32_t *rbmax, uint32_t *bm, int *cnt, int *queue, int *qn)
+                           typename KeyOf<KG>::T *keys, int *cnt, int *queue, int *qn)
 {
+    using K = KeyOf<KG>;
     constexpr int NW = BLOCK / 64;
-    const int wave = threadIdx.x >> 6;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
+    const int lane = tid & 63, wave = tid >> 6;
     const PoseInfo in = w.info[p];
     float P[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) P[k] = w.poses[12 * (size_t)p + k];
     const int tpx = in.tw * in.th;
-    const int nbx = (in.tw + 7) >> 3, nby = (in.th + 7) >> 3;
+    const int jpx = in.jw * in.jh;
     const bool mark = (s.flags & 2u) != 0;
     const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
 
     for (int k = tid; k < tpx; k += BLOCK) tst<G>(tile + k, kEmptyKey);
-    for (int k = tid; k < nbx * nby; k += BLOCK) {
-        tst<G>(rbmin + k, 0xFFFFu);
-        tst<G>(rbmax + k, 0u);
-    }
-    // explained-bitmap region: the tile dilated by the scene's neighbour window
-    const int bx0 = in.tx0 - s.wtx, by0 = in.ty0 - s.wty;
-    const int bmw = in.tw + 2 * s.wtx, bmh = in.th + 2 * s.wty;
-    const int bmwords = (bmw * bmh + 31) >> 5;
-    for (int k = tid; k < bmwords; k += BLOCK) tst<G>(bm + k, 0u);
+    for (int k = tid; k < jpx; k += BLOCK) K::store(keys + k, K::kEmpty);
     if (tid < 4) cnt[tid] = 0;
     __syncthreads();
 
@@ -430,7 +377,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     }
     __syncthreads();
 
-    // 2. resolve: occluders and stride
+    // 2. resolve: occluders (Eq. 3) and the downsampling stride
     int cL = 0;
     for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
         const int k = k0 + tid;
@@ -449,13 +396,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                         if (!(label_mode && s.labels) || s.labels[pix] != w.label) keep = false;
                     }
                 }
-                if (!keep) {
-                    tst<G>(tile + k, kEmptyKey);
-                } else {
-                    const int b = (ty >> 3) * nbx + (tx >> 3);
-                    tmin<G>(rbmin + b, (uint32_t)d);
-                    tmax<G>(rbmax + b, (uint32_t)d);
-                }
+                if (!keep) tst<G>(tile + k, kEmptyKey);
             }
         }
         cL += wave_popc(keep);
@@ -463,8 +404,8 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     __syncthreads();
 
     // 3. J_r: nearest observed neighbour from the scene table.  The inliers
-    //    of each chunk go to a workgroup queue, and every wave takes queue
-    //    items in turn to mark their observed neighbours for J_o.
+    //    of each chunk go to a workgroup queue; every wave takes queue items
+    //    in turn and marks the observed points each one explains.
     int cR = 0;
     for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
         const int k = k0 + tid;
@@ -483,7 +424,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                 const int2 th = s.thdr[j * s.W + i];
                 const int e = (int)(key >> 16) - (th.y & 0xFFFF);
                 if (e >= 0 && e < (int)((uint32_t)th.y >> 16)) nn = s.tnn[th.x + e];
-                if (nn >= 0) queue[atomicAdd(qn, 1)] = k;
+                if (nn >= 0 && jpx > 0) queue[atomicAdd(qn, 1)] = k;
             }
         }
         __syncthreads();
@@ -492,7 +433,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
             const int kk = queue[t];
             const int ty = kk / in.tw, tx = kk - ty * in.tw;
             const int dd = (int)(tld<G>(tile + kk) >> 16);
-            wave_mark_neighbours<G>(s, in.tx0 + tx, in.ty0 + ty, dd, bm, bx0, by0, bmw, bmh, lane);
+            wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, in.jy0, in.jw, in.jh, lane);
         }
         bool out = valid && nn < 0;
         if (RGB && nn >= 0) {
@@ -503,56 +444,28 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
         __syncthreads();
     }
 
-    // 4. J_o: observed points in V(O); explained iff marked.  In RGB mode the
-    //    explained points of each chunk are queued and the waves find their
-    //    nearest rendered points; the result replaces the queue entry.
+    // 4. J_o: observed points in V(O); explained iff some rendered point
+    //    keyed it; in RGB mode the key names the nearest rendered point.
     int cQ = 0, cO = 0;
     const int vpx = in.vw * in.vh;
     const double dl = (double)s.delta;
     for (int k0 = 0; k0 < vpx; k0 += BLOCK) {
         const int k = k0 + tid;
-        if (RGB) {
-            if (tid == 0) *qn = 0;
-            __syncthreads();
-        }
-        bool inq = false, expl = false;
-        int pix = 0, slot = -1;
+        bool inq = false, out = false;
         if (k < vpx) {
             const int vy = k / in.vw, vx = k - vy * in.vw;
             const int i = in.vx0 + vx, j = in.vy0 + vy;
-            pix = j * s.W + i;
+            const int pix = j * s.W + i;
             const int dp = s.depth[pix];
             if (dp > 0) {
                 const int2 q = s.oxy[pix];
                 inq = label_mode ? (s.labels[pix] == w.label) : in_volume(m, P, q.x, q.y, dp, dl);
-                const int bxr = i - bx0, byr = j - by0;
-                if (inq && bxr >= 0 && bxr < bmw && byr >= 0 && byr < bmh) {
-                    const int bit = byr * bmw + bxr;
-                    expl = (tld<G>(bm + (bit >> 5)) >> (bit & 31)) & 1u;
-                }
-                if (RGB && expl) {
-                    slot = atomicAdd(qn, 1);
-                    queue[slot] = pix;
-                }
-            }
-        }
-        bool out = inq && !expl;
-        if (RGB) {
-            __syncthreads();
-            const int nq = *qn;
-            for (int t = wave; t < nq; t += NW) {
-                const int qp = queue[t];
-                const int qj = qp / s.W, qi = qp - qj * s.W;
-                const int dp = s.depth[qp];
-                const int2 q = s.oxy[qp];
-                const unsigned long long r =
-                    wave_nearest_rendered<G>(s, tile, rbmin, rbmax, in, nbx, qi, qj, dp, q.x, q.y, lane);
-                if (lane == 0) queue[t] = r == ~0ULL ? -1 : (int)(r & 0xFFFFFFFFu);
-            }
-            __syncthreads();
-            if (slot >= 0) {
-                const int kr = queue[slot];
-                if (kr >= 0) {
+                typename K::T nk = K::kEmpty;
+                const int jx = i - in.jx0, jy = j - in.jy0;
+                if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < in.jh) nk = K::load(keys + jy * in.jw + jx);
+                out = inq && nk == K::kEmpty;
+                if (RGB && inq && nk != K::kEmpty) {
+                    const int kr = K::index(nk);
                     const uint32_t key = tld<G>(tile + kr);
                     const int ty = kr / in.tw, tx = kr - ty * in.tw;
                     const float4 lr =
@@ -560,7 +473,6 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                     out = ciede2000(s.olab[pix], lr) > s.tau;
                 }
             }
-            __syncthreads();
         }
         cQ += wave_popc(inq);
         cO += wave_popc(out);
@@ -582,29 +494,29 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     __syncthreads();
 }
 
-template <int BLOCK, bool G, bool RGB>
-__global__ __launch_bounds__(BLOCK) void score_kernel(SceneDev s, MeshDev m, Work w, int cls, int cap, int nbcap)
+// Persistent scoring kernel for one size class.  G: the tile lives in
+// device memory instead of LDS; KG: the J_o keys live in device memory
+// (64-bit) instead of LDS (32-bit, after the tile).  Work-groups take the
+// class's poses in turn.
+template <int BLOCK, bool G, bool KG, bool RGB>
+__global__ __launch_bounds__(BLOCK, 1024 / BLOCK) void score_kernel(SceneDev s, MeshDev m, Work w, int cls)
 {
     extern __shared__ uint32_t smem[];
     __shared__ int cnt[4];
     __shared__ int queue[BLOCK];
     __shared__ int qn;
     const int count = w.counts[cls];
-    uint32_t *tile, *rbmin, *rbmax, *bm;
-    if constexpr (G) {
-        tile = w.gscratch + (size_t)blockIdx.x * w.gscratch_stride;
-        rbmin = tile + (size_t)s.W * s.H;
-        rbmax = rbmin + (size_t)s.bw * s.bh;
-        bm = rbmax + (size_t)s.bw * s.bh;
-    } else {
-        tile = smem;
-        rbmin = smem + cap;
-        rbmax = rbmin + nbcap;
-        bm = rbmax + nbcap;
-    }
+    uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
     for (int it = blockIdx.x; it < count; it += gridDim.x) {
         const int p = w.lists[cls * w.n + it];
-        score_pose<BLOCK, G, RGB>(s, m, w, p, tile, rbmin, rbmax, bm, cnt, queue, &qn);
+        const PoseInfo &in = w.info[p];
+        uint32_t *tile = G ? slot : smem;
+        typename KeyOf<KG>::T *keys;
+        if constexpr (KG)
+            keys = reinterpret_cast<unsigned long long *>(G ? slot + (((size_t)s.W * s.H + 1) & ~(size_t)1) : slot);
+        else
+            keys = smem + in.tw * in.th;
+        score_pose<BLOCK, G, KG, RGB>(s, m, w, p, tile, keys, cnt, queue, &qn);
     }
 }
 
@@ -693,9 +605,22 @@ __global__ void setup_kernel(SceneDev s, MeshDev m, Work w)
             in.vh = s.H;
         }
     }
+    // J_o region: the part of the V region that a rendered point's
+    // neighbours can reach (the tile dilated by the neighbour window).
+    in.jx0 = max(in.vx0, in.tx0 - s.wtx);
+    in.jy0 = max(in.vy0, in.ty0 - s.wty);
+    const int jx1 = min(in.vx0 + in.vw - 1, in.tx0 + in.tw - 1 + s.wtx);
+    const int jy1 = min(in.vy0 + in.vh - 1, in.ty0 + in.th - 1 + s.wty);
+    in.jw = (in.tw > 0 && jx1 >= in.jx0) ? jx1 - in.jx0 + 1 : 0;
+    in.jh = (in.th > 0 && jy1 >= in.jy0) ? jy1 - in.jy0 + 1 : 0;
+    if (in.jw == 0 || in.jh == 0) in.jw = in.jh = 0;
     w.info[p] = in;
-    const int px = in.tw * in.th;
-    const int cls = px <= w.cap_small ? 0 : (px <= w.cap_large ? 1 : 2);
+    // LDS words: tile + 32-bit keys; 32-bit keys need d2 < 2^16 and tile
+    // indices < 2^16, otherwise the pose is scored from device memory
+    const int tile_words = in.tw * in.th;
+    const int words = tile_words + in.jw * in.jh;
+    int cls = tile_words <= w.cap_large ? 2 : 3;
+    if (w.key32 && words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
     const int slot = atomicAdd(&w.counts[cls], 1);
     w.lists[cls * w.n + slot] = p;
 }
@@ -945,11 +870,6 @@ __global__ __launch_bounds__(1024) void argmin_kernel(const int32_t *jr, const i
 
 // ------------------------------------------------------------------ launchers
 
-size_t lds_bytes_for(int cap, int W, int H, int wtx, int wty)
-{
-    return (size_t)cap * 4 + (size_t)nbcap_for(cap, W, H) * 8 + (size_t)bmcap_for(cap, W, H, wtx, wty) * 4;
-}
-
 hipError_t upload_colour_table(const float *lin256)
 {
     return hipMemcpyToSymbol(HIP_SYMBOL(c_lin), lin256, 256 * sizeof(float));
@@ -965,28 +885,30 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *ox
     return hipGetLastError();
 }
 
+template <int BLOCK, bool G, bool KG, bool RGB>
+static hipError_t launch_one(const SceneDev &s, const MeshDev &m, const Work &w, int cls, int grid, int lds_words,
+                             hipStream_t st)
+{
+    const size_t lds = (size_t)lds_words * 4;
+    if (lds > 0) {
+        hipError_t e = hipFuncSetAttribute((const void *)score_kernel<BLOCK, G, KG, RGB>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    score_kernel<BLOCK, G, KG, RGB><<<grid, BLOCK, lds, st>>>(s, m, w, cls);
+    return hipGetLastError();
+}
+
 template <bool RGB>
 static hipError_t launch_class_t(const SceneDev &s, const MeshDev &m, const Work &w, const LaunchCfg &c, int cls,
                                  hipStream_t st)
 {
-    if (cls == 0) {
-        const size_t lds = lds_bytes_for(c.cap_small, s.W, s.H, s.wtx, s.wty);
-        hipError_t e = hipFuncSetAttribute((const void *)score_kernel<512, false, RGB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        score_kernel<512, false, RGB><<<c.grid_small, 512, lds, st>>>(s, m, w, 0, c.cap_small,
-                                                                      nbcap_for(c.cap_small, s.W, s.H));
-    } else if (cls == 1) {
-        const size_t lds = lds_bytes_for(c.cap_large, s.W, s.H, s.wtx, s.wty);
-        hipError_t e = hipFuncSetAttribute((const void *)score_kernel<1024, false, RGB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        score_kernel<1024, false, RGB><<<c.grid_large, 1024, lds, st>>>(s, m, w, 1, c.cap_large,
-                                                                        nbcap_for(c.cap_large, s.W, s.H));
-    } else {
-        score_kernel<256, true, RGB><<<c.grid_ovf, 256, 0, st>>>(s, m, w, 2, 0, 0);
+    switch (cls) {
+    case 0: return launch_one<512, false, false, RGB>(s, m, w, 0, c.grid[0], c.cap_small, st);
+    case 1: return launch_one<1024, false, false, RGB>(s, m, w, 1, c.grid[1], c.cap_large, st);
+    case 2: return launch_one<1024, false, true, RGB>(s, m, w, 2, c.grid[2], c.cap_large, st);
+    default: return launch_one<256, true, true, RGB>(s, m, w, 3, c.grid[3], 0, st);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_setup(const SceneDev &s, const MeshDev &m, const Work &w, hipStream_t st)

@@ -69,6 +69,7 @@ struct SceneRec {
 
 struct StreamBufs {
     DevBuf info, lists, counts, scratch, tmp;
+    int32_t last_n = 0;       // poses of the last scoring call on this stream
     size_t bytes() const { return info.bytes + lists.bytes + counts.bytes + scratch.bytes + tmp.bytes; }
 };
 
@@ -193,30 +194,20 @@ void colour_table(float out[256])
     }
 }
 
+// static LDS of the scoring kernels: counters and the 1024-entry work queue
 constexpr long long kStaticLds = 4 * 1024 + 256;
-
-int cap_for_lds(size_t bytes, int W, int H, int wtx, int wty)
-{
-    // largest cap with lds_bytes_for(cap) + static LDS (counters and the
-    // 1024-entry work queue) <= bytes
-    long long lo = 0, hi = (long long)bytes / 4;
-    while (lo < hi) {
-        const long long mid = (lo + hi + 1) / 2;
-        if ((long long)lds_bytes_for((int)mid, W, H, wtx, wty) + kStaticLds <= (long long)bytes) lo = mid;
-        else hi = mid - 1;
-    }
-    return (int)lo;
-}
 
 LaunchCfg launch_cfg(const perch_ctx *ctx, const SceneDev &s)
 {
     LaunchCfg c;
-    c.cap_large = std::min(cap_for_lds(ctx->lds_max, s.W, s.H, s.wtx, s.wty), s.W * s.H);
-    c.cap_small = std::min(cap_for_lds(ctx->lds_max / 2, s.W, s.H, s.wtx, s.wty), c.cap_large);
-    c.cap_small = std::min(c.cap_small, 16384);
-    c.grid_small = ctx->n_cu * 2;
-    c.grid_large = ctx->n_cu;
-    c.grid_ovf = std::min(ctx->n_cu, 64);
+    // LDS words of tile + keys; tile indices must fit the 16-bit key field
+    c.cap_large = (int)std::min<long long>(((long long)ctx->lds_max - kStaticLds) / 4, 65535);
+    c.cap_small = (int)std::min<long long>(((long long)ctx->lds_max / 2 - kStaticLds) / 4, c.cap_large);
+    c.grid[0] = ctx->n_cu * 2;
+    c.grid[1] = ctx->n_cu;
+    c.grid[2] = ctx->n_cu;
+    c.grid[3] = std::min(ctx->n_cu, 64);
+    (void)s;
     return c;
 }
 
@@ -252,13 +243,22 @@ perch_status prepare_work(perch_ctx *ctx, SceneRec &sr, MeshRec &mr, int32_t lab
     StreamBufs &b = ctx->work[st];
     cfg = launch_cfg(ctx, sr.dev);
     const SceneDev &sd = sr.dev;
-    const size_t bm_words = ((size_t)(sd.W + 2 * sd.wtx) * (sd.H + 2 * sd.wty)) / 32 + 2;
-    const size_t slot = (size_t)sd.W * sd.H + 2 * (size_t)sd.bw * sd.bh + bm_words;
+    // device-memory slots: class 2 holds 64-bit keys over at most the image,
+    // class 3 also the tile (rounded to 8 bytes)
+    const size_t img = (size_t)sd.W * sd.H;
+    size_t slot_words[kNumClasses] = {0, 0, 2 * img, ((img + 1) & ~(size_t)1) + 2 * img};
+    size_t slot_base[kNumClasses] = {0, 0, 0, 0};
+    size_t total_words = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        slot_base[c] = total_words;
+        total_words += slot_words[c] * (size_t)cfg.grid[c];
+    }
     perch_status s;
     if ((s = ctx->ensure(b.info, (size_t)n * sizeof(PoseInfo)))) return s;
     if ((s = ctx->ensure(b.lists, (size_t)kNumClasses * n * sizeof(int)))) return s;
     if ((s = ctx->ensure(b.counts, 64))) return s;
-    if ((s = ctx->ensure(b.scratch, (size_t)cfg.grid_ovf * slot * 4))) return s;
+    if ((s = ctx->ensure(b.scratch, total_words * 4))) return s;
+    b.last_n = n;
     w = Work{};
     w.poses = poses;
     w.n = n;
@@ -271,9 +271,13 @@ perch_status prepare_work(perch_ctx *ctx, SceneRec &sr, MeshRec &mr, int32_t lab
     w.lists = (int *)b.lists.ptr;
     w.counts = (int *)b.counts.ptr;
     w.gscratch = (uint32_t *)b.scratch.ptr;
-    w.gscratch_stride = slot;
+    for (int c = 0; c < kNumClasses; ++c) {
+        w.slot_base[c] = slot_base[c];
+        w.slot_words[c] = slot_words[c];
+    }
     w.cap_small = cfg.cap_small;
     w.cap_large = cfg.cap_large;
+    w.key32 = sd.dq2 < 65536;
     if ((sr.dev.flags & PERCH_VOL_MASK) == PERCH_VOL_LABEL) {
         std::vector<int> box = label_box(sr, label);
         for (int a = 0; a < 4; ++a) w.vbox_label[a] = box[a];
@@ -309,7 +313,7 @@ perch_status score_locked(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int
     if (perch_status s = prepare_work(ctx, *sr, *mr, label, poses, n, jr, jo, nr, nq, st, w, cfg)) return s;
     hipError_t e = ctx->timed(kProfSetup, st, [&] { return launch_setup(sr->dev, mr->dev, w, st); });
     for (int cls = 0; cls < kNumClasses && e == hipSuccess; ++cls)
-        e = ctx->timed(kProfSmall + cls, st, [&] { return launch_score_class(sr->dev, mr->dev, w, cfg, cls, st); });
+        e = ctx->timed(kProfClass0 + cls, st, [&] { return launch_score_class(sr->dev, mr->dev, w, cfg, cls, st); });
     if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
     return PERCH_OK;
 }
@@ -741,6 +745,28 @@ perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_
     out->window_y = r.dev.wty;
     out->tile_cap_small = c.cap_small;
     out->tile_cap_large = c.cap_large;
+    return ok();
+}
+
+perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int32_t *class_host)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    auto it = ctx->work.find(st);
+    if (it == ctx->work.end() || it->second.last_n <= 0) return fail(PERCH_ENOTFOUND, "no scoring call on this stream");
+    StreamBufs &b = it->second;
+    if (n != b.last_n || !class_host) return fail(PERCH_EINVAL, "n must equal the last call's %d poses", b.last_n);
+    std::vector<int32_t> counts(kNumClasses), lists((size_t)kNumClasses * n);
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(counts.data(), b.counts.ptr, kNumClasses * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(lists.data(), b.lists.ptr, lists.size() * 4, hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < n; ++i) class_host[i] = -1;
+    for (int c = 0; c < kNumClasses; ++c)
+        for (int32_t k = 0; k < counts[c] && k < n; ++k) {
+            const int32_t p = lists[(size_t)c * n + k];
+            if (p >= 0 && p < n) class_host[p] = c;
+        }
     return ok();
 }
 

@@ -153,12 +153,17 @@ def test_cfg2_full_size_sampled_outputs(ctx):
     w = make_config(2, 0)
     say("cfg2 full size")
     sid, mids = pk.load_workload(ctx, w)
-    outs = []
+    outs, classes = [], []
     for o in w.objects:
         outs.append(gpu_score(ctx, sid, mids[o.mesh], o.poses, label=o.label))
+        classes.append(ctx.last_classes(o.poses.shape[0]))
+    seen = np.unique(np.concatenate(classes))
+    assert set(seen.tolist()) >= {0, 1, 2}, seen   # the footprint classes this workload exercises
     rng = np.random.default_rng(99)
-    for o, got in zip(w.objects, outs):
-        sel = np.sort(rng.choice(o.poses.shape[0], 6, replace=False))
+    for o, got, cls in zip(w.objects, outs, classes):
+        # two poses of every class present, plus two at random
+        sel = [rng.choice(np.flatnonzero(cls == c), min(2, int((cls == c).sum())), replace=False) for c in np.unique(cls)]
+        sel = np.unique(np.concatenate(sel + [rng.choice(o.poses.shape[0], 2, replace=False)]))
         exp = oracle.score(w.meshes[o.mesh], oracle_scene(w), o.poses[sel], delta_mm=w.delta_mm, tau_c=w.tau_c,
                            flags=oracle_flags(w), label=o.label, threads=THREADS)
         check_counts(w, tuple(g[sel] for g in got), exp, f"cfg2 object {o.label}")
@@ -281,6 +286,7 @@ def test_overflow_class_and_scene_info(ctx):
     poses = np.stack([P0, pose_matrix(np.eye(3), (14, -2, 415)), pose_matrix(np.eye(3), (0, 0, 330)),
                       pose_matrix(np.eye(3), (-20, 10, 700))])
     got = gpu_score(ctx, sid, mid, poses)
+    assert 3 in ctx.last_classes(len(poses)).tolist()   # tile and keys in device memory
     assert got[2][2] > info["tile_cap_large"] // 2
     exp = oracle.score(cube, TScene(K, d, c, None), poses, delta_mm=10.0, tau_c=20.0,
                        flags=oracle.USE_RGB | oracle.MARK_OCCLUDERS, threads=THREADS)
