@@ -70,7 +70,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=64, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -186,17 +191,53 @@ def main():
         "scene": {"device_MB": round(info["device_bytes"] / 2**20, 1), "table_entries": info["table_entries"],
                   "window": [info["window_x"], info["window_y"]], "tile_caps": list(caps)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved_tops, 4), "peak": round(ALU_PEAK_TOPS, 2),
-                     "unit": "TOP/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 5), "traffic": None,
+                     "unit": "TOP/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 5),
+                     "traffic": measured_traffic(dom), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4), "launches": dom_launches,
                      "hbm_achieved_GBs": round(hbm_gbs, 2), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 6)},
         "kernels_ms": {k: round(v[0] / max(args.steps, 1), 4) for k, v in prof.items() if v[1]},
         "poses_per_class": class_poses,
+        "kernel_source_sha": kernel_source_sha(),
     }
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of exactly 1 GiB, five times: the
+    reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+
+
+def kernel_source_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2008_00326_amd", "csrc", "perch_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel_slot):
+    """HBM bytes per launch of the kernel from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "score_kernel_cfg2_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel_slot)
+    if not k:
+        return None
+    return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"], 1)
 
 
 def cpu_baseline(w, sample):
