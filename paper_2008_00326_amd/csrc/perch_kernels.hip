@@ -348,7 +348,7 @@ __device__ __forceinline__ int wave_popc(bool pred)
 
 template <int BLOCK, bool G, bool KG, bool RGB>
 __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, int p, uint32_t *tile,
-                           typename KeyOf<KG>::T *keys, int *cnt, int *queue, int *qn)
+                           typename KeyOf<KG>::T *keys, int *cnt, int *queue, int *queue2, int *qn)
 {
     using K = KeyOf<KG>;
     constexpr int NW = BLOCK / 64;
@@ -404,53 +404,67 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     __syncthreads();
 
     // 3. J_r: nearest observed neighbour from the scene table.  The inliers
-    //    of each chunk go to a workgroup queue; every wave takes queue items
-    //    in turn and marks the observed points each one explains.
+    //    of each chunk go to a workgroup queue: every wave takes queue items
+    //    in turn and marks the observed points each one explains, then the
+    //    colour test of Eq. 4 runs densely over the queue.
     int cR = 0;
     for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
         const int k = k0 + tid;
         if (tid == 0) *qn = 0;
         __syncthreads();
-        bool valid = false;
-        int i = 0, j = 0, nn = -1;
-        uint32_t key = kEmptyKey;
+        bool miss = false;
         if (k < tpx) {
-            key = tld<G>(tile + k);
+            const uint32_t key = tld<G>(tile + k);
             if (key != kEmptyKey) {
                 const int ty = k / in.tw, tx = k - ty * in.tw;
-                i = in.tx0 + tx;
-                j = in.ty0 + ty;
-                valid = true;
-                const int2 th = s.thdr[j * s.W + i];
+                const int2 th = s.thdr[(in.ty0 + ty) * s.W + in.tx0 + tx];
                 const int e = (int)(key >> 16) - (th.y & 0xFFFF);
-                if (e >= 0 && e < (int)((uint32_t)th.y >> 16)) nn = s.tnn[th.x + e];
-                if (nn >= 0 && jpx > 0) queue[atomicAdd(qn, 1)] = k;
+                const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? s.tnn[th.x + e] : -1;
+                miss = nn < 0;
+                if (nn >= 0 && (RGB || jpx > 0)) {
+                    const int slot = atomicAdd(qn, 1);
+                    queue[slot] = k;
+                    queue2[slot] = nn;
+                }
             }
         }
+        cR += wave_popc(miss);
         __syncthreads();
         const int nq = *qn;
-        for (int t = wave; t < nq; t += NW) {
-            const int kk = queue[t];
-            const int ty = kk / in.tw, tx = kk - ty * in.tw;
-            const int dd = (int)(tld<G>(tile + kk) >> 16);
-            wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, in.jy0, in.jw, in.jh, lane);
+        if (jpx > 0) {
+            for (int t = wave; t < nq; t += NW) {
+                const int kk = queue[t];
+                const int ty = kk / in.tw, tx = kk - ty * in.tw;
+                const int dd = (int)(tld<G>(tile + kk) >> 16);
+                wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, in.jy0, in.jw, in.jh, lane);
+            }
         }
-        bool out = valid && nn < 0;
-        if (RGB && nn >= 0) {
-            const float4 lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), i, j));
-            out = ciede2000(lr, s.olab[nn]) > s.tau;
+        if (RGB) {
+            bool out = false;
+            if (tid < nq) {
+                const int kk = queue[tid];
+                const uint32_t key = tld<G>(tile + kk);
+                const int ty = kk / in.tw, tx = kk - ty * in.tw;
+                const float4 lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                out = ciede2000(lr, s.olab[queue2[tid]]) > s.tau;
+            }
+            cR += wave_popc(out);
         }
-        cR += wave_popc(out);
         __syncthreads();
     }
 
     // 4. J_o: observed points in V(O); explained iff some rendered point
-    //    keyed it; in RGB mode the key names the nearest rendered point.
+    //    keyed it.  In RGB mode the key names the nearest rendered point and
+    //    the explained points of each chunk are queued for a dense colour test.
     int cQ = 0, cO = 0;
     const int vpx = in.vw * in.vh;
     const double dl = (double)s.delta;
     for (int k0 = 0; k0 < vpx; k0 += BLOCK) {
         const int k = k0 + tid;
+        if (RGB) {
+            if (tid == 0) *qn = 0;
+            __syncthreads();
+        }
         bool inq = false, out = false;
         if (k < vpx) {
             const int vy = k / in.vw, vx = k - vy * in.vw;
@@ -465,17 +479,29 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                 if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < in.jh) nk = K::load(keys + jy * in.jw + jx);
                 out = inq && nk == K::kEmpty;
                 if (RGB && inq && nk != K::kEmpty) {
-                    const int kr = K::index(nk);
-                    const uint32_t key = tld<G>(tile + kr);
-                    const int ty = kr / in.tw, tx = kr - ty * in.tw;
-                    const float4 lr =
-                        srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                    out = ciede2000(s.olab[pix], lr) > s.tau;
+                    const int slot = atomicAdd(qn, 1);
+                    queue[slot] = pix;
+                    queue2[slot] = K::index(nk);
                 }
             }
         }
         cQ += wave_popc(inq);
         cO += wave_popc(out);
+        if (RGB) {
+            __syncthreads();
+            const int nq = *qn;
+            bool cout = false;
+            if (tid < nq) {
+                const int pix = queue[tid], kr = queue2[tid];
+                const uint32_t key = tld<G>(tile + kr);
+                const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                const float4 lr =
+                    srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                cout = ciede2000(s.olab[pix], lr) > s.tau;
+            }
+            cO += wave_popc(cout);
+            __syncthreads();
+        }
     }
 
     if (lane == 0) {
@@ -499,11 +525,12 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
 // (64-bit) instead of LDS (32-bit, after the tile).  Work-groups take the
 // class's poses in turn.
 template <int BLOCK, bool G, bool KG, bool RGB>
-__global__ __launch_bounds__(BLOCK, 1024 / BLOCK) void score_kernel(SceneDev s, MeshDev m, Work w, int cls)
+__global__ __launch_bounds__(BLOCK, 4) void score_kernel(SceneDev s, MeshDev m, Work w, int cls)
 {
     extern __shared__ uint32_t smem[];
     __shared__ int cnt[4];
     __shared__ int queue[BLOCK];
+    __shared__ int queue2[BLOCK];
     __shared__ int qn;
     const int count = w.counts[cls];
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
@@ -516,7 +543,7 @@ __global__ __launch_bounds__(BLOCK, 1024 / BLOCK) void score_kernel(SceneDev s, 
             keys = reinterpret_cast<unsigned long long *>(G ? slot + (((size_t)s.W * s.H + 1) & ~(size_t)1) : slot);
         else
             keys = smem + in.tw * in.th;
-        score_pose<BLOCK, G, KG, RGB>(s, m, w, p, tile, keys, cnt, queue, &qn);
+        score_pose<BLOCK, G, KG, RGB>(s, m, w, p, tile, keys, cnt, queue, queue2, &qn);
     }
 }
 

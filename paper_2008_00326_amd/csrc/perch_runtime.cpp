@@ -194,8 +194,8 @@ void colour_table(float out[256])
     }
 }
 
-// static LDS of the scoring kernels: counters and the 1024-entry work queue
-constexpr long long kStaticLds = 4 * 1024 + 256;
+// static LDS of the scoring kernels: counters and two 1024-entry work queues
+constexpr long long kStaticLds = 8 * 1024 + 256;
 
 LaunchCfg launch_cfg(const perch_ctx *ctx, const SceneDev &s)
 {
