@@ -128,6 +128,38 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
                                int32_t *jo_dev, int32_t *nr_dev, int32_t *nq_dev,
                                void *hip_stream);
 
+/* One slice of a launch: the candidate poses of one object in one scene.
+ * Pointers as in perch_score_poses; n_poses may be 0. */
+typedef struct {
+    int32_t scene_id, mesh_id, label, n_poses;
+    const float *poses_dev;        /* n_poses * 12 binary32 */
+    int32_t *jr_dev, *jo_dev;      /* n_poses each */
+    int32_t *nr_dev, *nq_dev;      /* n_poses each, or NULL */
+} perch_work;
+
+/* Score many (scene, object, poses) items -- any mix of resident scenes and
+ * meshes -- in one launch sequence on hip_stream; asynchronous.  Each item's
+ * outputs are bit-identical to scoring it alone with perch_score_poses. */
+perch_status perch_score_batch(perch_ctx *ctx, const perch_work *items, int32_t n_items, void *hip_stream);
+
+/* A prepared batch: buffers for up to max_items items holding max_poses poses
+ * in total, in scenes of at most max_image_pixels pixels, and a captured HIP
+ * graph (descriptor upload, scoring, per-item minimum, result download).
+ * perch_batch_set writes the work descriptors (waiting for a previous launch
+ * of the batch to finish); perch_batch_launch replays the graph on
+ * hip_stream; perch_batch_wait blocks and returns, per item, the minimum-cost
+ * pose index and its J (-1 for items without poses).  Items' J_r / J_o
+ * arrays are filled as in perch_score_batch.  Scenes and meshes named by a
+ * set batch must stay resident: dropping one while a launch is pending
+ * returns PERCH_EBUSY, otherwise it invalidates the batch until the next set. */
+typedef struct perch_batch perch_batch;
+perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_poses, int32_t max_image_pixels,
+                                perch_batch **out);
+perch_status perch_batch_set(perch_batch *batch, const perch_work *items, int32_t n_items);
+perch_status perch_batch_launch(perch_batch *batch, void *hip_stream);
+perch_status perch_batch_wait(perch_batch *batch, int32_t *best_idx_host, int32_t *best_cost_host);
+perch_status perch_batch_destroy(perch_batch *batch);
+
 /* Minimum-cost pose of each of n_obj objects (Sec. IV-A "Parallel Search"):
  * scores every candidate and reduces J = J_r + J_o per object on the device;
  * ties go to the lowest pose index.  Blocks until the results are on the

@@ -43,6 +43,12 @@ class _SceneInfo(ctypes.Structure):
                 ("tile_cap_small", ctypes.c_int32), ("tile_cap_large", ctypes.c_int32)]
 
 
+class _Work(ctypes.Structure):
+    _fields_ = [("scene_id", ctypes.c_int32), ("mesh_id", ctypes.c_int32), ("label", ctypes.c_int32),
+                ("n_poses", ctypes.c_int32), ("poses_dev", ctypes.c_void_p), ("jr_dev", ctypes.c_void_p),
+                ("jo_dev", ctypes.c_void_p), ("nr_dev", ctypes.c_void_p), ("nq_dev", ctypes.c_void_p)]
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
@@ -80,6 +86,12 @@ def load_library():
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
         "perch_last_classes": ([P, VP, I32, P], ctypes.c_int),
+        "perch_score_batch": ([P, P, I32, VP], ctypes.c_int),
+        "perch_batch_create": ([P, I32, I32, I32, P], ctypes.c_int),
+        "perch_batch_set": ([P, P, I32], ctypes.c_int),
+        "perch_batch_launch": ([P, VP], ctypes.c_int),
+        "perch_batch_wait": ([P, P, P], ctypes.c_int),
+        "perch_batch_destroy": ([P], ctypes.c_int),
         "perch_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -231,6 +243,23 @@ class Context:
         _check(self._lib.perch_profile_read(self._h, n, _np_ptr(ms), _np_ptr(cnt)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.PROFILE_SLOTS)}
 
+    def score_batch(self, items, stream=None):
+        """Score a list of work items in one launch.  Each item is a dict with
+        scene, mesh, label, poses (CUDA tensor) and optionally jr, jo, nr, nq
+        output tensors (allocated when absent).  Returns the items with their
+        outputs filled in (asynchronously)."""
+        import torch
+        arr, items = _work_array(items)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(self._lib.perch_score_batch(self._h, ctypes.byref(arr) if len(items) else None, len(items),
+                                           _stream_ptr(stream)))
+        return items
+
+    def batch(self, max_items: int, max_poses: int, max_image_pixels: int) -> "Batch":
+        """A prepared, graph-captured batch of the given capacity."""
+        return Batch(self, max_items, max_poses, max_image_pixels)
+
     def last_classes(self, n: int, stream=None):
         """Footprint class (0..3) of each pose of the last score_poses call on the stream."""
         import torch
@@ -253,6 +282,73 @@ class Context:
         _check(self._lib.perch_render(self._h, int(scene_id), int(mesh_id), _dev_ptr(poses), n, _dev_ptr(depth),
                                       _dev_ptr(col), _dev_ptr(tid), _stream_ptr(stream)))
         return depth, col, tid
+
+
+def _work_array(items):
+    import torch
+    out = []
+    arr = (_Work * max(len(items), 1))()
+    for k, it in enumerate(items):
+        poses = it["poses"]
+        n = poses.numel() // 12
+        it = dict(it)
+        for key in ("jr", "jo"):
+            if it.get(key) is None:
+                it[key] = torch.empty(n, dtype=torch.int32, device=poses.device)
+        for key in ("nr", "nq"):
+            it.setdefault(key, None)
+        arr[k] = _Work(int(it["scene"]), int(it["mesh"]), int(it.get("label", 0)), n, poses.data_ptr(),
+                       it["jr"].data_ptr(), it["jo"].data_ptr(),
+                       None if it["nr"] is None else it["nr"].data_ptr(),
+                       None if it["nq"] is None else it["nq"].data_ptr())
+        out.append(it)
+    return arr, out
+
+
+class Batch:
+    """A prepared batch: fixed capacity, work descriptors rewritten per set(),
+    the launch replayed as one captured HIP graph."""
+
+    def __init__(self, ctx: Context, max_items: int, max_poses: int, max_image_pixels: int):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        _check(self._lib.perch_batch_create(ctx._h, int(max_items), int(max_poses), int(max_image_pixels),
+                                            ctypes.byref(h)))
+        self._h = h
+        self.items = []
+        self._arr = None
+
+    def set(self, items):
+        arr, self.items = _work_array(items)
+        self._arr = arr
+        _check(self._lib.perch_batch_set(self._h, ctypes.byref(arr), len(self.items)))
+        return self.items
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(self._lib.perch_batch_launch(self._h, _stream_ptr(stream)))
+
+    def wait(self):
+        """Per item: (index of the minimum-cost pose, its J)."""
+        n = len(self.items)
+        bi = np.zeros(max(n, 1), np.int32)
+        bc = np.zeros(max(n, 1), np.int32)
+        _check(self._lib.perch_batch_wait(self._h, _np_ptr(bi), _np_ptr(bc)))
+        return bi[:n], bc[:n]
+
+    def close(self):
+        if getattr(self, "_h", None) and getattr(self.ctx, "_h", None):
+            _check(self._lib.perch_batch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def load_workload(ctx: Context, w, *, flags=None):

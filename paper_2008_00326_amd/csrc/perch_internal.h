@@ -16,6 +16,7 @@ struct PoseInfo {
     int tx0, ty0, tw, th;   // raster tile (clipped to the image), may be empty
     int vx0, vy0, vw, vh;   // region holding every observed pixel that may lie in V(O)
     int jx0, jy0, jw, jh;   // part of the V region within reach of a rendered point
+    int item, local;        // work item and pose index within it
 };
 
 struct SceneDev {
@@ -45,20 +46,38 @@ struct MeshDev {
     float lo[3], hi[3];      // object-frame AABB
 };
 
-struct Work {
+// One (scene, object, candidate poses) slice of a launch.
+struct ItemDev {
+    int scene, mesh;         // indices into the launch's scene and mesh tables
+    int label, n;            // object label; number of poses
+    int first;               // global index of the item's first pose in the launch
+    int key32;               // 32-bit LDS keys are exact for this scene
+    int vbox[4];             // label mode: x0, y0, w, h of the label's pixels
     const float *poses;      // n * 12
-    int n;
-    int label;
     int32_t *jr, *jo, *nr, *nq;
-    PoseInfo *info;          // n
-    int *lists;              // kNumClasses * n pose indices
+};
+
+struct LaunchHdr {
+    int n_items, n_poses;
+};
+
+// Device-resident descriptors of one launch (header, items, scenes and
+// meshes live contiguously in device memory) and its work buffers.
+struct Work {
+    const LaunchHdr *hdr;
+    const ItemDev *items;    // sorted by `first`
+    const SceneDev *scenes;
+    const MeshDev *meshes;
+    int cap_poses;           // capacity of info and each class list
+    PoseInfo *info;          // cap_poses
+    int *lists;              // kNumClasses * cap_poses global pose indices
     int *counts;             // kNumClasses counters
     uint32_t *gscratch;      // device-memory slots of classes 2 (keys) and 3 (tile + keys)
     size_t slot_base[kNumClasses];   // first word of each class's slots
     size_t slot_words[kNumClasses];  // words per work-group slot
+    size_t dev_tile_words;   // class 3: words of the slot's tile (keys follow)
     int cap_small, cap_large; // LDS words (tile + keys) of the two LDS classes
-    int key32;               // squared radius fits the 16-bit distance field of LDS keys
-    int vbox_label[4];       // label mode: x0, y0, w, h of the label's pixels
+    int32_t *best;           // n_items x {index, J} of the per-item minimum, or null
 };
 
 // Launch configuration chosen by the runtime (and the tuner).
@@ -69,6 +88,8 @@ struct LaunchCfg {
 };
 
 hipError_t upload_colour_table(const float *lin256);
+// Allow the scoring kernels up to this much dynamic LDS (set once per device).
+hipError_t prepare_score_kernels(int max_dynamic_lds_bytes);
 
 hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *oxy, float4 *olab,
                              uint32_t *oblk, hipStream_t st);
@@ -76,9 +97,12 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *ox
 // that can have an observed point within delta, then one entry per depth.
 hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st);
 hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
-hipError_t launch_setup(const SceneDev &s, const MeshDev &m, const Work &w, hipStream_t st);
-hipError_t launch_score_class(const SceneDev &s, const MeshDev &m, const Work &w, const LaunchCfg &c, int cls,
-                              hipStream_t st);
+// A launch: zero the class counters, classify every pose (grid sized for
+// `poses_grid` poses; the kernels read the real count from the header), run
+// the four scoring classes, then the per-item argmin if w.best is set.
+hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st);
+hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, hipStream_t st);
+hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st);
 
 // Kernel slots reported by the profiler (perch_profile_read).
 enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
@@ -86,7 +110,6 @@ enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n,
                          uint32_t *keys, uint16_t *depth, uint8_t *rgb, int32_t *tri,
                          hipStream_t st);
-hipError_t launch_argmin(const int32_t *jr, const int32_t *jo, int n, int32_t *out2,
-                         hipStream_t st);
+
 
 }  // namespace perch

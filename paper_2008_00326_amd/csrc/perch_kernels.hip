@@ -347,17 +347,21 @@ __device__ __forceinline__ int wave_popc(bool pred)
 // ------------------------------------------------------------------ per pose
 
 template <int BLOCK, bool G, bool KG, bool RGB>
-__device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, int p, uint32_t *tile,
-                           typename KeyOf<KG>::T *keys, int *cnt, int *queue, int *queue2, int *qn)
+__device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, int *cnt, int *queue,
+                           int *queue2, int *qn)
 {
     using K = KeyOf<KG>;
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const PoseInfo in = w.info[p];
+    const ItemDev it = w.items[in.item];
+    const SceneDev s = w.scenes[it.scene];
+    const MeshDev m = w.meshes[it.mesh];
+    const bool rgb = RGB && (s.flags & 1u) != 0;
     float P[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) P[k] = w.poses[12 * (size_t)p + k];
+    for (int k = 0; k < 12; ++k) P[k] = it.poses[12 * (size_t)in.local + k];
     const int tpx = in.tw * in.th;
     const int jpx = in.jw * in.jh;
     const bool mark = (s.flags & 2u) != 0;
@@ -393,7 +397,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                     const int pix = j * s.W + i;
                     const int dob = s.depth[pix];
                     if (dob > 0 && 16 * dob + s.dq < 16 * d) {
-                        if (!(label_mode && s.labels) || s.labels[pix] != w.label) keep = false;
+                        if (!(label_mode && s.labels) || s.labels[pix] != it.label) keep = false;
                     }
                 }
                 if (!keep) tst<G>(tile + k, kEmptyKey);
@@ -421,7 +425,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                 const int e = (int)(key >> 16) - (th.y & 0xFFFF);
                 const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? s.tnn[th.x + e] : -1;
                 miss = nn < 0;
-                if (nn >= 0 && (RGB || jpx > 0)) {
+                if (nn >= 0 && (rgb || jpx > 0)) {
                     const int slot = atomicAdd(qn, 1);
                     queue[slot] = k;
                     queue2[slot] = nn;
@@ -439,7 +443,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
                 wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, in.jy0, in.jw, in.jh, lane);
             }
         }
-        if (RGB) {
+        if (rgb) {
             bool out = false;
             if (tid < nq) {
                 const int kk = queue[tid];
@@ -461,7 +465,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     const double dl = (double)s.delta;
     for (int k0 = 0; k0 < vpx; k0 += BLOCK) {
         const int k = k0 + tid;
-        if (RGB) {
+        if (rgb) {
             if (tid == 0) *qn = 0;
             __syncthreads();
         }
@@ -473,12 +477,12 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
             const int dp = s.depth[pix];
             if (dp > 0) {
                 const int2 q = s.oxy[pix];
-                inq = label_mode ? (s.labels[pix] == w.label) : in_volume(m, P, q.x, q.y, dp, dl);
+                inq = label_mode ? (s.labels[pix] == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
                 typename K::T nk = K::kEmpty;
                 const int jx = i - in.jx0, jy = j - in.jy0;
                 if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < in.jh) nk = K::load(keys + jy * in.jw + jx);
                 out = inq && nk == K::kEmpty;
-                if (RGB && inq && nk != K::kEmpty) {
+                if (rgb && inq && nk != K::kEmpty) {
                     const int slot = atomicAdd(qn, 1);
                     queue[slot] = pix;
                     queue2[slot] = K::index(nk);
@@ -487,7 +491,7 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
         }
         cQ += wave_popc(inq);
         cO += wave_popc(out);
-        if (RGB) {
+        if (rgb) {
             __syncthreads();
             const int nq = *qn;
             bool cout = false;
@@ -512,20 +516,20 @@ __device__ void score_pose(const SceneDev &s, const MeshDev &m, const Work &w, i
     }
     __syncthreads();
     if (tid == 0) {
-        w.jr[p] = cnt[0];
-        w.jo[p] = cnt[1];
-        if (w.nr) w.nr[p] = cnt[2];
-        if (w.nq) w.nq[p] = cnt[3];
+        it.jr[in.local] = cnt[0];
+        it.jo[in.local] = cnt[1];
+        if (it.nr) it.nr[in.local] = cnt[2];
+        if (it.nq) it.nq[in.local] = cnt[3];
     }
     __syncthreads();
 }
 
 // Persistent scoring kernel for one size class.  G: the tile lives in
 // device memory instead of LDS; KG: the J_o keys live in device memory
-// (64-bit) instead of LDS (32-bit, after the tile).  Work-groups take the
-// class's poses in turn.
+// (64-bit) instead of LDS (32-bit, after the tile).  RGB: the colour term is
+// compiled in (taken per scene).  Work-groups take the class's poses in turn.
 template <int BLOCK, bool G, bool KG, bool RGB>
-__global__ __launch_bounds__(BLOCK, 4) void score_kernel(SceneDev s, MeshDev m, Work w, int cls)
+__global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
 {
     extern __shared__ uint32_t smem[];
     __shared__ int cnt[4];
@@ -534,16 +538,15 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(SceneDev s, MeshDev m, 
     __shared__ int qn;
     const int count = w.counts[cls];
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
-    for (int it = blockIdx.x; it < count; it += gridDim.x) {
-        const int p = w.lists[cls * w.n + it];
-        const PoseInfo &in = w.info[p];
+    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+        const int p = w.lists[cls * w.cap_poses + i];
         uint32_t *tile = G ? slot : smem;
         typename KeyOf<KG>::T *keys;
         if constexpr (KG)
-            keys = reinterpret_cast<unsigned long long *>(G ? slot + (((size_t)s.W * s.H + 1) & ~(size_t)1) : slot);
+            keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
         else
-            keys = smem + in.tw * in.th;
-        score_pose<BLOCK, G, KG, RGB>(s, m, w, p, tile, keys, cnt, queue, queue2, &qn);
+            keys = smem + w.info[p].tw * w.info[p].th;
+        score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, cnt, queue, queue2, &qn);
     }
 }
 
@@ -595,13 +598,25 @@ __global__ void zero_counts_kernel(int *counts)
     if (threadIdx.x < kNumClasses) counts[threadIdx.x] = 0;
 }
 
-__global__ void setup_kernel(SceneDev s, MeshDev m, Work w)
+__global__ void setup_kernel(Work w)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= w.n) return;
+    if (p >= w.hdr->n_poses) return;
+    // the item holding global pose p: the last one with first <= p
+    int lo = 0, hi = w.hdr->n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (w.items[mid].first <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    const ItemDev &it = w.items[lo];
+    const SceneDev &s = w.scenes[it.scene];
+    const MeshDev &m = w.meshes[it.mesh];
     float P[12];
-    for (int k = 0; k < 12; ++k) P[k] = w.poses[12 * (size_t)p + k];
+    for (int k = 0; k < 12; ++k) P[k] = it.poses[12 * (size_t)(p - it.first) + k];
     PoseInfo in;
+    in.item = lo;
+    in.local = p - it.first;
     double umin, umax, vmin, vmax, zmin, zmax;
     // Raster tile: every drawn vertex has Zc >= 100 and lies in the AABB.
     project_box(P, m.lo, m.hi, 0.0, s, &umin, &umax, &vmin, &vmax, &zmin, &zmax);
@@ -616,10 +631,10 @@ __global__ void setup_kernel(SceneDev s, MeshDev m, Work w)
     }
     // J_o region: observed pixels whose point may lie in the inflated AABB.
     if ((s.flags & (3u << 4)) == (2u << 4)) {
-        in.vx0 = w.vbox_label[0];
-        in.vy0 = w.vbox_label[1];
-        in.vw = w.vbox_label[2];
-        in.vh = w.vbox_label[3];
+        in.vx0 = it.vbox[0];
+        in.vy0 = it.vbox[1];
+        in.vw = it.vbox[2];
+        in.vh = it.vbox[3];
     } else {
         project_box(P, m.lo, m.hi, (double)s.delta + 0.5, s, &umin, &umax, &vmin, &vmax, &zmin, &zmax);
         if (zmin > 0.5) {
@@ -647,9 +662,9 @@ __global__ void setup_kernel(SceneDev s, MeshDev m, Work w)
     const int tile_words = in.tw * in.th;
     const int words = tile_words + in.jw * in.jh;
     int cls = tile_words <= w.cap_large ? 2 : 3;
-    if (w.key32 && words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
+    if (it.key32 && words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
     const int slot = atomicAdd(&w.counts[cls], 1);
-    w.lists[cls * w.n + slot] = p;
+    w.lists[cls * w.cap_poses + slot] = p;
 }
 
 // ------------------------------------------------------------------ scene prep
@@ -867,13 +882,17 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, MeshDev m, cons
 
 // ------------------------------------------------------------------ argmin
 
-// Minimum of J = jr + jo with the lowest index among ties; out2 = {idx, J}.
-__global__ __launch_bounds__(1024) void argmin_kernel(const int32_t *jr, const int32_t *jo, int n, int32_t *out2)
+// Per work item: the minimum of J = J_r + J_o over its poses, the lowest
+// pose index among ties; best[2 item] = index, best[2 item + 1] = J.
+__global__ __launch_bounds__(1024) void item_argmin_kernel(Work w)
 {
     __shared__ unsigned long long red[16];
+    const int item = blockIdx.x;
+    if (item >= w.hdr->n_items) return;
+    const ItemDev &it = w.items[item];
     unsigned long long best = ~0ULL;
-    for (int k = threadIdx.x; k < n; k += 1024) {
-        const unsigned long long key = ((unsigned long long)(uint32_t)(jr[k] + jo[k]) << 32) | (uint32_t)k;
+    for (int k = threadIdx.x; k < it.n; k += 1024) {
+        const unsigned long long key = ((unsigned long long)(uint32_t)(it.jr[k] + it.jo[k]) << 32) | (uint32_t)k;
         best = key < best ? key : best;
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -889,8 +908,8 @@ __global__ __launch_bounds__(1024) void argmin_kernel(const int32_t *jr, const i
             best = o < best ? o : best;
         }
         if (threadIdx.x == 0) {
-            out2[0] = (int32_t)(best & 0xFFFFFFFFu);
-            out2[1] = (int32_t)(best >> 32);
+            w.best[2 * item] = best == ~0ULL ? -1 : (int32_t)(best & 0xFFFFFFFFu);
+            w.best[2 * item + 1] = best == ~0ULL ? -1 : (int32_t)(best >> 32);
         }
     }
 }
@@ -913,54 +932,64 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *ox
 }
 
 template <int BLOCK, bool G, bool KG, bool RGB>
-static hipError_t launch_one(const SceneDev &s, const MeshDev &m, const Work &w, int cls, int grid, int lds_words,
-                             hipStream_t st)
+static hipError_t launch_one(const Work &w, int cls, int grid, int lds_words, hipStream_t st)
 {
-    const size_t lds = (size_t)lds_words * 4;
-    if (lds > 0) {
-        hipError_t e = hipFuncSetAttribute((const void *)score_kernel<BLOCK, G, KG, RGB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    score_kernel<BLOCK, G, KG, RGB><<<grid, BLOCK, lds, st>>>(s, m, w, cls);
+    score_kernel<BLOCK, G, KG, RGB><<<grid, BLOCK, (size_t)lds_words * 4, st>>>(w, cls);
     return hipGetLastError();
 }
 
 template <bool RGB>
-static hipError_t launch_class_t(const SceneDev &s, const MeshDev &m, const Work &w, const LaunchCfg &c, int cls,
-                                 hipStream_t st)
+static hipError_t prepare_t(int lds_bytes)
+{
+    const void *k[] = {(const void *)score_kernel<512, false, false, RGB>,
+                       (const void *)score_kernel<1024, false, false, RGB>,
+                       (const void *)score_kernel<1024, false, true, RGB>};
+    for (const void *f : k) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t prepare_score_kernels(int max_dynamic_lds_bytes)
+{
+    hipError_t e = prepare_t<false>(max_dynamic_lds_bytes);
+    return e == hipSuccess ? prepare_t<true>(max_dynamic_lds_bytes) : e;
+}
+
+template <bool RGB>
+static hipError_t launch_class_t(const Work &w, const LaunchCfg &c, int cls, hipStream_t st)
 {
     switch (cls) {
-    case 0: return launch_one<512, false, false, RGB>(s, m, w, 0, c.grid[0], c.cap_small, st);
-    case 1: return launch_one<1024, false, false, RGB>(s, m, w, 1, c.grid[1], c.cap_large, st);
-    case 2: return launch_one<1024, false, true, RGB>(s, m, w, 2, c.grid[2], c.cap_large, st);
-    default: return launch_one<256, true, true, RGB>(s, m, w, 3, c.grid[3], 0, st);
+    case 0: return launch_one<512, false, false, RGB>(w, 0, c.grid[0], c.cap_small, st);
+    case 1: return launch_one<1024, false, false, RGB>(w, 1, c.grid[1], c.cap_large, st);
+    case 2: return launch_one<1024, false, true, RGB>(w, 2, c.grid[2], c.cap_large, st);
+    default: return launch_one<256, true, true, RGB>(w, 3, c.grid[3], 0, st);
     }
 }
 
-hipError_t launch_setup(const SceneDev &s, const MeshDev &m, const Work &w, hipStream_t st)
+hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st)
 {
     zero_counts_kernel<<<1, 64, 0, st>>>(w.counts);
-    setup_kernel<<<(w.n + 255) / 256, 256, 0, st>>>(s, m, w);
+    setup_kernel<<<(poses_grid + 255) / 256, 256, 0, st>>>(w);
     return hipGetLastError();
 }
 
-hipError_t launch_score_class(const SceneDev &s, const MeshDev &m, const Work &w, const LaunchCfg &c, int cls,
-                              hipStream_t st)
+hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, hipStream_t st)
 {
-    return (s.flags & 1u) ? launch_class_t<true>(s, m, w, c, cls, st) : launch_class_t<false>(s, m, w, c, cls, st);
+    return any_rgb ? launch_class_t<true>(w, c, cls, st) : launch_class_t<false>(w, c, cls, st);
+}
+
+hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st)
+{
+    item_argmin_kernel<<<items_grid, 1024, 0, st>>>(w);
+    return hipGetLastError();
 }
 
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n, uint32_t *keys,
                          uint16_t *depth, uint8_t *rgb, int32_t *tri, hipStream_t st)
 {
     render_kernel<<<n, 256, 0, st>>>(s, m, poses, keys, depth, rgb, tri);
-    return hipGetLastError();
-}
-
-hipError_t launch_argmin(const int32_t *jr, const int32_t *jo, int n, int32_t *out2, hipStream_t st)
-{
-    argmin_kernel<<<1, 1024, 0, st>>>(jr, jo, n, out2);
     return hipGetLastError();
 }
 

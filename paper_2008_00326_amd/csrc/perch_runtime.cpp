@@ -67,13 +67,31 @@ struct SceneRec {
     size_t bytes = 0;
 };
 
+// Device buffers of one launch: descriptors, per-pose work, device-memory
+// slots of the large footprint classes, per-item minima.
+struct LaunchBufs {
+    DevBuf desc, info, lists, counts, scratch, best;
+};
+
+// Pinned staging of descriptors for asynchronous uploads: a ring of slots,
+// each reused only after the copy that read it has executed.
+struct Staging {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+
 struct StreamBufs {
-    DevBuf info, lists, counts, scratch, tmp;
-    int32_t last_n = 0;       // poses of the last scoring call on this stream
-    size_t bytes() const { return info.bytes + lists.bytes + counts.bytes + scratch.bytes + tmp.bytes; }
+    LaunchBufs lb;
+    DevBuf tmp;               // J_r / J_o of perch_best_poses
+    Staging ring[8];
+    int next = 0;
+    int32_t last_n = 0;       // poses of the last scoring launch on this stream
 };
 
 }  // namespace
+
+struct perch_batch;
 
 struct perch_ctx {
     int device = 0;
@@ -85,6 +103,7 @@ struct perch_ctx {
     std::map<int32_t, MeshRec> meshes;
     std::map<int32_t, SceneRec> scenes;
     std::map<hipStream_t, StreamBufs> work;
+    std::vector<perch_batch *> batches;
     std::recursive_mutex mu;
 
     // profiler: HIP events around each launch, on the launch stream
@@ -173,7 +192,42 @@ struct perch_ctx {
     }
 };
 
+// A prepared batch: device buffers, pinned descriptors and results, and a
+// captured graph (descriptor upload, classification, scoring, per-item
+// argmin, result download) whose kernels read everything through the
+// descriptors, so new work only needs new descriptors.
+struct perch_batch {
+    perch_ctx *ctx = nullptr;
+    int cap_items = 0, cap_poses = 0;
+    size_t cap_pixels = 0, desc_cap = 0;
+    LaunchCfg cfg{};
+    LaunchBufs lb;
+    void *pin_desc = nullptr, *pin_best = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false, valid = false;
+    int n_req = 0;
+    std::vector<int32_t> scene_ids, mesh_ids;
+    std::vector<int> item_of_req;
+};
+
 namespace {
+
+// A batch that references a scene or mesh: EBUSY while its launch is
+// pending, otherwise the batch is invalidated.
+perch_status release_check(perch_ctx *ctx, bool scene, int32_t id)
+{
+    for (perch_batch *b : ctx->batches) {
+        const std::vector<int32_t> &ids = scene ? b->scene_ids : b->mesh_ids;
+        if (std::find(ids.begin(), ids.end(), id) == ids.end()) continue;
+        if (b->pending && hipEventQuery(b->done) == hipErrorNotReady)
+            return fail(PERCH_EBUSY, "%s %d is used by a batch still running", scene ? "scene" : "mesh", id);
+        b->valid = false;
+    }
+    return PERCH_OK;
+}
 
 perch_status enter(perch_ctx *ctx)
 {
@@ -197,7 +251,7 @@ void colour_table(float out[256])
 // static LDS of the scoring kernels: counters and two 1024-entry work queues
 constexpr long long kStaticLds = 8 * 1024 + 256;
 
-LaunchCfg launch_cfg(const perch_ctx *ctx, const SceneDev &s)
+LaunchCfg launch_cfg(const perch_ctx *ctx)
 {
     LaunchCfg c;
     // LDS words of tile + keys; tile indices must fit the 16-bit key field
@@ -207,7 +261,6 @@ LaunchCfg launch_cfg(const perch_ctx *ctx, const SceneDev &s)
     c.grid[1] = ctx->n_cu;
     c.grid[2] = ctx->n_cu;
     c.grid[3] = std::min(ctx->n_cu, 64);
-    (void)s;
     return c;
 }
 
@@ -236,85 +289,209 @@ std::vector<int> label_box(SceneRec &r, int32_t label)
     return b;
 }
 
-perch_status prepare_work(perch_ctx *ctx, SceneRec &sr, MeshRec &mr, int32_t label, const float *poses, int32_t n,
-                          int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, hipStream_t st, Work &w,
-                          LaunchCfg &cfg)
+size_t align64(size_t x) { return (x + 63) & ~(size_t)63; }
+
+// Host image of a launch's descriptors: header | items | scenes | meshes.
+struct Built {
+    std::vector<char> bytes;
+    size_t items_off = 64, scenes_off = 0, meshes_off = 0;
+    int n_items = 0, n_poses = 0;
+    size_t max_pixels = 0;
+    bool any_rgb = false;
+    std::vector<int32_t> scene_ids, mesh_ids;
+    std::vector<int> item_of_req;   // item index of each request, -1 if it has no poses
+};
+
+size_t desc_capacity(int items)
 {
-    StreamBufs &b = ctx->work[st];
-    cfg = launch_cfg(ctx, sr.dev);
-    const SceneDev &sd = sr.dev;
-    // device-memory slots: class 2 holds 64-bit keys over at most the image,
-    // class 3 also the tile (rounded to 8 bytes)
-    const size_t img = (size_t)sd.W * sd.H;
-    size_t slot_words[kNumClasses] = {0, 0, 2 * img, ((img + 1) & ~(size_t)1) + 2 * img};
-    size_t slot_base[kNumClasses] = {0, 0, 0, 0};
-    size_t total_words = 0;
-    for (int c = 0; c < kNumClasses; ++c) {
-        slot_base[c] = total_words;
-        total_words += slot_words[c] * (size_t)cfg.grid[c];
+    return 64 + align64((size_t)items * sizeof(ItemDev)) + align64((size_t)items * sizeof(SceneDev))
+           + align64((size_t)items * sizeof(MeshDev));
+}
+
+perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_req, Built &b, int cap_items = 0)
+{
+    if (n_req < 0) return fail(PERCH_EINVAL, "negative item count");
+    if (n_req > 0 && !req) return fail(PERCH_EINVAL, "null items");
+    std::vector<ItemDev> items;
+    std::vector<SceneDev> scenes;
+    std::vector<MeshDev> meshes;
+    std::map<int32_t, int> sidx, midx;
+    long long total = 0;
+    b.item_of_req.assign((size_t)n_req, -1);
+    for (int32_t r = 0; r < n_req; ++r) {
+        const perch_work &q = req[r];
+        auto si = ctx->scenes.find(q.scene_id);
+        if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "item %d: unknown scene id %d", r, q.scene_id);
+        auto mi = ctx->meshes.find(q.mesh_id);
+        if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "item %d: unknown mesh id %d", r, q.mesh_id);
+        if ((si->second.dev.flags & PERCH_USE_RGB) && !mi->second.dev.vrgb)
+            return fail(PERCH_EINVAL, "item %d: scene uses the RGB term but mesh %d has no vertex colours", r,
+                        q.mesh_id);
+        if (q.n_poses < 0) return fail(PERCH_EINVAL, "item %d: n_poses must be >= 0", r);
+        if (q.n_poses == 0) continue;
+        if (!q.poses_dev || !q.jr_dev || !q.jo_dev) return fail(PERCH_EINVAL, "item %d: null poses, jr or jo", r);
+        if (!sidx.count(q.scene_id)) {
+            sidx[q.scene_id] = (int)scenes.size();
+            scenes.push_back(si->second.dev);
+            b.scene_ids.push_back(q.scene_id);
+        }
+        if (!midx.count(q.mesh_id)) {
+            midx[q.mesh_id] = (int)meshes.size();
+            meshes.push_back(mi->second.dev);
+            b.mesh_ids.push_back(q.mesh_id);
+        }
+        const SceneDev &sd = si->second.dev;
+        ItemDev it{};
+        it.scene = sidx[q.scene_id];
+        it.mesh = midx[q.mesh_id];
+        it.label = q.label;
+        it.n = q.n_poses;
+        it.first = (int)total;
+        it.key32 = sd.dq2 < 65536;
+        if ((sd.flags & PERCH_VOL_MASK) == PERCH_VOL_LABEL) {
+            std::vector<int> box = label_box(si->second, q.label);
+            for (int k = 0; k < 4; ++k) it.vbox[k] = box[k];
+        }
+        it.poses = q.poses_dev;
+        it.jr = q.jr_dev;
+        it.jo = q.jo_dev;
+        it.nr = q.nr_dev;
+        it.nq = q.nq_dev;
+        b.item_of_req[r] = (int)items.size();
+        items.push_back(it);
+        total += q.n_poses;
+        b.max_pixels = std::max(b.max_pixels, (size_t)sd.W * sd.H);
+        b.any_rgb |= (sd.flags & PERCH_USE_RGB) != 0;
     }
+    if (total >= (1LL << 30)) return fail(PERCH_EINVAL, "too many poses in one launch (%lld)", total);
+    b.n_items = (int)items.size();
+    b.n_poses = (int)total;
+    // tables sized for the capacity of a prepared batch, else for this launch
+    const size_t slots = cap_items > 0 ? (size_t)cap_items : std::max(items.size(), (size_t)1);
+    if (cap_items > 0 && items.size() > (size_t)cap_items)
+        return fail(PERCH_EINVAL, "%zu items exceed the batch capacity %d", items.size(), cap_items);
+    b.scenes_off = 64 + align64(slots * sizeof(ItemDev));
+    b.meshes_off = b.scenes_off + align64(slots * sizeof(SceneDev));
+    b.bytes.assign(b.meshes_off + align64(slots * sizeof(MeshDev)), 0);
+    LaunchHdr h{b.n_items, b.n_poses};
+    std::memcpy(b.bytes.data(), &h, sizeof h);
+    if (!items.empty()) std::memcpy(b.bytes.data() + 64, items.data(), items.size() * sizeof(ItemDev));
+    if (!scenes.empty()) std::memcpy(b.bytes.data() + b.scenes_off, scenes.data(), scenes.size() * sizeof(SceneDev));
+    if (!meshes.empty()) std::memcpy(b.bytes.data() + b.meshes_off, meshes.data(), meshes.size() * sizeof(MeshDev));
+    return PERCH_OK;
+}
+
+// Device-memory slot sizes (32-bit words) of the large footprint classes:
+// class 2 holds 64-bit keys over at most the image, class 3 also the tile.
+void slot_layout(const LaunchCfg &cfg, size_t max_pixels, size_t slot_words[kNumClasses],
+                 size_t slot_base[kNumClasses], size_t *total_words, size_t *tile_words)
+{
+    *tile_words = (max_pixels + 1) & ~(size_t)1;
+    slot_words[0] = slot_words[1] = 0;
+    slot_words[2] = 2 * max_pixels;
+    slot_words[3] = *tile_words + 2 * max_pixels;
+    *total_words = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        slot_base[c] = *total_words;
+        *total_words += slot_words[c] * (size_t)cfg.grid[c];
+    }
+}
+
+perch_status ensure_bufs(perch_ctx *ctx, LaunchBufs &lb, size_t desc_bytes, int cap_poses, int cap_items,
+                         size_t max_pixels, const LaunchCfg &cfg)
+{
+    size_t sw[kNumClasses], sb[kNumClasses], total = 0, tile = 0;
+    slot_layout(cfg, max_pixels, sw, sb, &total, &tile);
     perch_status s;
-    if ((s = ctx->ensure(b.info, (size_t)n * sizeof(PoseInfo)))) return s;
-    if ((s = ctx->ensure(b.lists, (size_t)kNumClasses * n * sizeof(int)))) return s;
-    if ((s = ctx->ensure(b.counts, 64))) return s;
-    if ((s = ctx->ensure(b.scratch, total_words * 4))) return s;
-    b.last_n = n;
-    w = Work{};
-    w.poses = poses;
-    w.n = n;
-    w.label = label;
-    w.jr = jr;
-    w.jo = jo;
-    w.nr = nr;
-    w.nq = nq;
-    w.info = (PoseInfo *)b.info.ptr;
-    w.lists = (int *)b.lists.ptr;
-    w.counts = (int *)b.counts.ptr;
-    w.gscratch = (uint32_t *)b.scratch.ptr;
-    for (int c = 0; c < kNumClasses; ++c) {
-        w.slot_base[c] = slot_base[c];
-        w.slot_words[c] = slot_words[c];
-    }
+    if ((s = ctx->ensure(lb.desc, desc_bytes))) return s;
+    if ((s = ctx->ensure(lb.info, (size_t)std::max(cap_poses, 1) * sizeof(PoseInfo)))) return s;
+    if ((s = ctx->ensure(lb.lists, (size_t)kNumClasses * std::max(cap_poses, 1) * sizeof(int)))) return s;
+    if ((s = ctx->ensure(lb.counts, 64))) return s;
+    if ((s = ctx->ensure(lb.scratch, total * 4))) return s;
+    if ((s = ctx->ensure(lb.best, (size_t)std::max(cap_items, 1) * 8))) return s;
+    return PERCH_OK;
+}
+
+Work make_work(const LaunchBufs &lb, const Built &b, int cap_poses, const LaunchCfg &cfg, size_t max_pixels,
+               bool want_best)
+{
+    Work w{};
+    const char *d = (const char *)lb.desc.ptr;
+    w.hdr = (const LaunchHdr *)d;
+    w.items = (const ItemDev *)(d + 64);
+    w.scenes = (const SceneDev *)(d + b.scenes_off);
+    w.meshes = (const MeshDev *)(d + b.meshes_off);
+    w.cap_poses = cap_poses;
+    w.info = (PoseInfo *)lb.info.ptr;
+    w.lists = (int *)lb.lists.ptr;
+    w.counts = (int *)lb.counts.ptr;
+    w.gscratch = (uint32_t *)lb.scratch.ptr;
+    size_t total = 0;
+    slot_layout(cfg, max_pixels, w.slot_words, w.slot_base, &total, &w.dev_tile_words);
     w.cap_small = cfg.cap_small;
     w.cap_large = cfg.cap_large;
-    w.key32 = sd.dq2 < 65536;
-    if ((sr.dev.flags & PERCH_VOL_MASK) == PERCH_VOL_LABEL) {
-        std::vector<int> box = label_box(sr, label);
-        for (int a = 0; a < 4; ++a) w.vbox_label[a] = box[a];
-    }
-    (void)mr;
-    return PERCH_OK;
+    w.best = want_best ? (int32_t *)lb.best.ptr : nullptr;
+    return w;
 }
 
-perch_status lookup(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, SceneRec **sr, MeshRec **mr)
+// Enqueue a launch: classify, score the four footprint classes, and the
+// per-item argmin when w.best is set.
+hipError_t enqueue(perch_ctx *ctx, const Work &w, const LaunchCfg &cfg, int poses_grid, int items_grid, bool any_rgb,
+                   hipStream_t st, bool timed)
 {
-    auto si = ctx->scenes.find(scene_id);
-    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
-    auto mi = ctx->meshes.find(mesh_id);
-    if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
-    if ((si->second.dev.flags & PERCH_USE_RGB) && !mi->second.dev.vrgb)
-        return fail(PERCH_EINVAL, "scene uses the RGB term but mesh %d has no vertex colours", mesh_id);
-    *sr = &si->second;
-    *mr = &mi->second;
-    return PERCH_OK;
-}
-
-perch_status score_locked(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label, const float *poses,
-                          int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, hipStream_t st)
-{
-    SceneRec *sr;
-    MeshRec *mr;
-    if (perch_status s = lookup(ctx, scene_id, mesh_id, &sr, &mr)) return s;
-    if (n < 0) return fail(PERCH_EINVAL, "n must be >= 0");
-    if (n == 0) return PERCH_OK;
-    if (!poses || !jr || !jo) return fail(PERCH_EINVAL, "null poses, jr or jo");
-    Work w;
-    LaunchCfg cfg;
-    if (perch_status s = prepare_work(ctx, *sr, *mr, label, poses, n, jr, jo, nr, nq, st, w, cfg)) return s;
-    hipError_t e = ctx->timed(kProfSetup, st, [&] { return launch_setup(sr->dev, mr->dev, w, st); });
+    auto T = [&](int slot, auto &&f) { return timed ? ctx->timed(slot, st, f) : f(); };
+    hipError_t e = T(kProfSetup, [&] { return launch_setup(w, poses_grid, st); });
     for (int cls = 0; cls < kNumClasses && e == hipSuccess; ++cls)
-        e = ctx->timed(kProfClass0 + cls, st, [&] { return launch_score_class(sr->dev, mr->dev, w, cfg, cls, st); });
+        e = T(kProfClass0 + cls, [&] { return launch_score_class(w, cfg, cls, any_rgb, st); });
+    if (e == hipSuccess && w.best) e = T(kProfArgmin, [&] { return launch_item_argmin(w, items_grid, st); });
+    return e;
+}
+
+// Copy descriptors to the device through a pinned staging slot, asynchronously.
+perch_status upload(StreamBufs &sb, const Built &b, void *dev, hipStream_t st)
+{
+    Staging &slot = sb.ring[sb.next];
+    sb.next = (sb.next + 1) % 8;
+    if (slot.done) HIP_TRY(hipEventSynchronize(slot.done));
+    else HIP_TRY(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    if (slot.bytes < b.bytes.size()) {
+        if (slot.host) HIP_TRY(hipHostFree(slot.host));
+        slot.host = nullptr;
+        slot.bytes = 0;
+        HIP_TRY(hipHostMalloc(&slot.host, b.bytes.size(), hipHostMallocDefault));
+        slot.bytes = b.bytes.size();
+    }
+    std::memcpy(slot.host, b.bytes.data(), b.bytes.size());
+    HIP_TRY(hipMemcpyAsync(dev, slot.host, b.bytes.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(slot.done, st));
+    return PERCH_OK;
+}
+
+// Direct (non-graph) launch of a list of work items on a stream.  With
+// best_host, waits and returns {index, J} per request.
+perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hipStream_t st, int32_t *best_host)
+{
+    Built b;
+    if (perch_status s = build_descriptors(ctx, req, n_req, b)) return s;
+    if (b.n_poses == 0) return PERCH_OK;
+    StreamBufs &sb = ctx->work[st];
+    const LaunchCfg cfg = launch_cfg(ctx);
+    if (perch_status s = ensure_bufs(ctx, sb.lb, b.bytes.size(), b.n_poses, b.n_items, b.max_pixels, cfg)) return s;
+    if (perch_status s = upload(sb, b, sb.lb.desc.ptr, st)) return s;
+    const Work w = make_work(sb.lb, b, b.n_poses, cfg, b.max_pixels, best_host != nullptr);
+    sb.last_n = b.n_poses;
+    hipError_t e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, st, true);
     if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
+    if (best_host) {
+        std::vector<int32_t> res((size_t)2 * b.n_items);
+        HIP_TRY(hipMemcpyAsync(res.data(), w.best, res.size() * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int32_t r = 0; r < n_req; ++r) {
+            const int it = b.item_of_req[r];
+            best_host[2 * r] = it >= 0 ? res[2 * it] : -1;
+            best_host[2 * r + 1] = it >= 0 ? res[2 * it + 1] : -1;
+        }
+    }
     return PERCH_OK;
 }
 
@@ -344,6 +521,7 @@ perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
     float lin[256];
     colour_table(lin);
     e = upload_colour_table(lin);
+    if (e == hipSuccess) e = prepare_score_kernels((int)(ctx->lds_max - kStaticLds));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete ctx;
@@ -369,9 +547,15 @@ perch_status perch_destroy(perch_ctx *ctx)
         for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
             ctx->release(*b);
     }
+    while (!ctx->batches.empty()) perch_batch_destroy(ctx->batches.back());
     for (auto &kv : ctx->work) {
         StreamBufs &w = kv.second;
-        for (DevBuf *b : {&w.info, &w.lists, &w.counts, &w.scratch, &w.tmp}) ctx->release(*b);
+        for (DevBuf *b : {&w.lb.desc, &w.lb.info, &w.lb.lists, &w.lb.counts, &w.lb.scratch, &w.lb.best, &w.tmp})
+            ctx->release(*b);
+        for (Staging &g : w.ring) {
+            if (g.host) (void)hipHostFree(g.host);
+            if (g.done) (void)hipEventDestroy(g.done);
+        }
     }
     ctx->collect();
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -455,6 +639,7 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->meshes.find(mesh_id);
     if (it == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    if (perch_status st = release_check(ctx, false, mesh_id)) return st;
     (void)hipDeviceSynchronize();
     ctx->release(it->second.verts);
     ctx->release(it->second.tris);
@@ -623,6 +808,7 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->scenes.find(scene_id);
     if (it == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    if (perch_status st = release_check(ctx, true, scene_id)) return st;
     (void)hipDeviceSynchronize();
     SceneRec &r = it->second;
     for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
@@ -637,8 +823,16 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
 {
     if (perch_status st = enter(ctx)) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    perch_status s = score_locked(ctx, scene_id, mesh_id, label, poses_dev, n, jr_dev, jo_dev, nr_dev, nq_dev,
-                                  pick_stream(ctx, hip_stream));
+    const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
+    perch_status s = run_direct(ctx, &item, 1, pick_stream(ctx, hip_stream), nullptr);
+    return s ? s : ok();
+}
+
+perch_status perch_score_batch(perch_ctx *ctx, const perch_work *items, int32_t n_items, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    perch_status s = run_direct(ctx, items, n_items, pick_stream(ctx, hip_stream), nullptr);
     return s ? s : ok();
 }
 
@@ -651,32 +845,31 @@ perch_status perch_best_poses(perch_ctx *ctx, int32_t scene_id, int32_t n_obj, c
     if (n_obj < 1) return fail(PERCH_EINVAL, "n_obj must be >= 1");
     if (!mesh_ids || !labels || !poses_dev || !n_poses || !best_idx_host || !best_cost_host)
         return fail(PERCH_EINVAL, "null argument");
-    int32_t nmax = 0;
+    int32_t total = 0;
     for (int32_t k = 0; k < n_obj; ++k) {
         if (n_poses[k] < 1) return fail(PERCH_EINVAL, "object %d has no poses", k);
-        if (!poses_dev[k]) return fail(PERCH_EINVAL, "object %d: null poses", k);
-        SceneRec *sr;
-        MeshRec *mr;
-        if (perch_status s = lookup(ctx, scene_id, mesh_ids[k], &sr, &mr)) return s;
-        nmax = std::max(nmax, n_poses[k]);
+        total = std::max(total, n_poses[k]);
     }
     hipStream_t st = pick_stream(ctx, hip_stream);
-    StreamBufs &b = ctx->work[st];
-    const size_t tmp_bytes = (size_t)2 * nmax * 4 + (size_t)2 * n_obj * 4;
-    if (perch_status s = ctx->ensure(b.tmp, tmp_bytes)) return s;
-    int32_t *jr = (int32_t *)b.tmp.ptr, *jo = jr + nmax, *res = jo + nmax;
+    // J_r / J_o land in a per-stream scratch area; only the minima return
+    StreamBufs &sb = ctx->work[st];
+    size_t need = 0;
+    for (int32_t k = 0; k < n_obj; ++k) need += (size_t)n_poses[k] * 8;
+    if (perch_status s0 = ctx->ensure(sb.tmp, need)) return s0;
+    std::vector<perch_work> items((size_t)n_obj);
+    int32_t *base = (int32_t *)sb.tmp.ptr;
+    size_t off = 0;
     for (int32_t k = 0; k < n_obj; ++k) {
-        if (perch_status s = score_locked(ctx, scene_id, mesh_ids[k], labels[k], poses_dev[k], n_poses[k], jr, jo,
-                                          nullptr, nullptr, st))
-            return s;
-        HIP_TRY(ctx->timed(kProfArgmin, st, [&] { return launch_argmin(jr, jo, n_poses[k], res + 2 * k, st); }));
+        items[k] = perch_work{scene_id, mesh_ids[k], labels[k], n_poses[k], poses_dev[k], base + off,
+                              base + off + n_poses[k], nullptr, nullptr};
+        off += 2 * (size_t)n_poses[k];
     }
-    std::vector<int32_t> host((size_t)2 * n_obj);
-    HIP_TRY(hipMemcpyAsync(host.data(), res, host.size() * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    (void)total;
+    std::vector<int32_t> best((size_t)2 * n_obj);
+    if (perch_status s = run_direct(ctx, items.data(), n_obj, st, best.data())) return s;
     for (int32_t k = 0; k < n_obj; ++k) {
-        best_idx_host[k] = host[2 * k];
-        best_cost_host[k] = host[2 * k + 1];
+        best_idx_host[k] = best[2 * k];
+        best_cost_host[k] = best[2 * k + 1];
     }
     return ok();
 }
@@ -696,10 +889,10 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, con
     hipStream_t st = pick_stream(ctx, hip_stream);
     StreamBufs &b = ctx->work[st];
     const SceneDev &s = si->second.dev;
-    if (perch_status e = ctx->ensure(b.scratch, (size_t)n * s.W * s.H * 4)) return e;
+    if (perch_status e = ctx->ensure(b.lb.scratch, (size_t)n * s.W * s.H * 4)) return e;
     HIP_TRY(ctx->timed(kProfRender, st, [&] {
-        return launch_render(s, mi->second.dev, poses_dev, n, (uint32_t *)b.scratch.ptr, depth_dev, rgb_dev, tri_dev,
-                             st);
+        return launch_render(s, mi->second.dev, poses_dev, n, (uint32_t *)b.lb.scratch.ptr, depth_dev, rgb_dev,
+                             tri_dev, st);
     }));
     return ok();
 }
@@ -738,7 +931,7 @@ perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_
     auto it = ctx->scenes.find(scene_id);
     if (it == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
     const SceneRec &r = it->second;
-    const LaunchCfg c = launch_cfg(ctx, r.dev);
+    const LaunchCfg c = launch_cfg(ctx);
     out->device_bytes = r.bytes;
     out->table_entries = (int64_t)(r.tnn.bytes / 4);
     out->window_x = r.dev.wtx;
@@ -759,14 +952,153 @@ perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int
     if (n != b.last_n || !class_host) return fail(PERCH_EINVAL, "n must equal the last call's %d poses", b.last_n);
     std::vector<int32_t> counts(kNumClasses), lists((size_t)kNumClasses * n);
     HIP_TRY(hipStreamSynchronize(st));
-    HIP_TRY(hipMemcpy(counts.data(), b.counts.ptr, kNumClasses * 4, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(lists.data(), b.lists.ptr, lists.size() * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(counts.data(), b.lb.counts.ptr, kNumClasses * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(lists.data(), b.lb.lists.ptr, lists.size() * 4, hipMemcpyDeviceToHost));
     for (int32_t i = 0; i < n; ++i) class_host[i] = -1;
     for (int c = 0; c < kNumClasses; ++c)
         for (int32_t k = 0; k < counts[c] && k < n; ++k) {
             const int32_t p = lists[(size_t)c * n + k];
             if (p >= 0 && p < n) class_host[p] = c;
         }
+    return ok();
+}
+
+perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_poses, int32_t max_image_pixels,
+                               perch_batch **out)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!out) return fail(PERCH_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (max_items < 1 || max_poses < 1 || max_image_pixels < 1 || max_poses >= (1 << 30))
+        return fail(PERCH_EINVAL, "capacities must be positive (max_poses < 2^30)");
+    auto *b = new perch_batch();
+    b->ctx = ctx;
+    b->cap_items = max_items;
+    b->cap_poses = max_poses;
+    b->cap_pixels = (size_t)max_image_pixels;
+    b->desc_cap = desc_capacity(max_items);
+    b->cfg = launch_cfg(ctx);
+    auto cleanup = [&](perch_status st, const char *what, hipError_t e) {
+        std::string msg = e != hipSuccess ? std::string(what) + ": " + hipGetErrorString(e) : g_last_error;
+        for (DevBuf *d : {&b->lb.desc, &b->lb.info, &b->lb.lists, &b->lb.counts, &b->lb.scratch, &b->lb.best})
+            ctx->release(*d);
+        if (b->pin_desc) (void)hipHostFree(b->pin_desc);
+        if (b->pin_best) (void)hipHostFree(b->pin_best);
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        if (b->done) (void)hipEventDestroy(b->done);
+        delete b;
+        return fail(st, "%s", msg.c_str());
+    };
+    if (perch_status st = ensure_bufs(ctx, b->lb, b->desc_cap, max_poses, max_items, b->cap_pixels, b->cfg))
+        return cleanup(st, "", hipSuccess);
+    hipError_t e = hipHostMalloc(&b->pin_desc, b->desc_cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&b->pin_best, (size_t)8 * max_items, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) return cleanup(PERCH_EDEVICE, "batch set-up", e);
+    std::memset(b->pin_desc, 0, b->desc_cap);   // header: no items, no poses
+    Built layout;
+    layout.scenes_off = 64 + align64((size_t)max_items * sizeof(ItemDev));
+    layout.meshes_off = layout.scenes_off + align64((size_t)max_items * sizeof(SceneDev));
+    const Work w = make_work(b->lb, layout, max_poses, b->cfg, b->cap_pixels, true);
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t c = hipMemcpyAsync(b->lb.desc.ptr, b->pin_desc, b->desc_cap, hipMemcpyHostToDevice, b->cap);
+        if (c == hipSuccess) c = enqueue(ctx, w, b->cfg, max_poses, max_items, true, b->cap, false);
+        if (c == hipSuccess)
+            c = hipMemcpyAsync(b->pin_best, b->lb.best.ptr, (size_t)8 * max_items, hipMemcpyDeviceToHost, b->cap);
+        e = hipStreamEndCapture(b->cap, &b->graph);
+        if (c != hipSuccess) e = c;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return cleanup(PERCH_EDEVICE, "batch graph capture", e);
+    ctx->batches.push_back(b);
+    *out = b;
+    return ok();
+}
+
+perch_status perch_batch_set(perch_batch *b, const perch_work *items, int32_t n_items)
+{
+    if (!b) return fail(PERCH_EINVAL, "null batch");
+    perch_ctx *ctx = b->ctx;
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (b->pending) {
+        HIP_TRY(hipEventSynchronize(b->done));
+        b->pending = false;
+    }
+    Built d;
+    if (perch_status s = build_descriptors(ctx, items, n_items, d, b->cap_items)) {
+        b->valid = false;
+        return s;
+    }
+    if (d.n_poses > b->cap_poses || d.max_pixels > b->cap_pixels) {
+        b->valid = false;
+        return fail(PERCH_EINVAL, "batch capacity exceeded (%d poses of %d, %zu pixels of %zu)", d.n_poses,
+                    b->cap_poses, d.max_pixels, b->cap_pixels);
+    }
+    std::memcpy(b->pin_desc, d.bytes.data(), std::min(d.bytes.size(), b->desc_cap));
+    b->scene_ids = d.scene_ids;
+    b->mesh_ids = d.mesh_ids;
+    b->item_of_req = d.item_of_req;
+    b->n_req = n_items;
+    b->valid = true;
+    return ok();
+}
+
+perch_status perch_batch_launch(perch_batch *b, void *hip_stream)
+{
+    if (!b) return fail(PERCH_EINVAL, "null batch");
+    perch_ctx *ctx = b->ctx;
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!b->valid) return fail(PERCH_EINVAL, "batch has no valid work (set it again)");
+    if (b->pending) HIP_TRY(hipEventSynchronize(b->done));
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    HIP_TRY(hipEventRecord(b->done, st));
+    b->pending = true;
+    return ok();
+}
+
+perch_status perch_batch_wait(perch_batch *b, int32_t *best_idx_host, int32_t *best_cost_host)
+{
+    if (!b) return fail(PERCH_EINVAL, "null batch");
+    perch_ctx *ctx = b->ctx;
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!b->pending) return fail(PERCH_EINVAL, "batch was not launched");
+    HIP_TRY(hipEventSynchronize(b->done));
+    b->pending = false;
+    const int32_t *res = (const int32_t *)b->pin_best;
+    for (int32_t r = 0; r < b->n_req; ++r) {
+        const int it = b->item_of_req[r];
+        if (best_idx_host) best_idx_host[r] = it >= 0 ? res[2 * it] : -1;
+        if (best_cost_host) best_cost_host[r] = it >= 0 ? res[2 * it + 1] : -1;
+    }
+    return ok();
+}
+
+perch_status perch_batch_destroy(perch_batch *b)
+{
+    if (!b) return ok();
+    perch_ctx *ctx = b->ctx;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    if (b->pending) (void)hipEventSynchronize(b->done);
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    (void)hipStreamDestroy(b->cap);
+    (void)hipEventDestroy(b->done);
+    (void)hipHostFree(b->pin_desc);
+    (void)hipHostFree(b->pin_best);
+    for (DevBuf *d : {&b->lb.desc, &b->lb.info, &b->lb.lists, &b->lb.counts, &b->lb.scratch, &b->lb.best})
+        ctx->release(*d);
+    ctx->batches.erase(std::find(ctx->batches.begin(), ctx->batches.end(), b));
+    delete b;
     return ok();
 }
 

@@ -312,5 +312,75 @@ def config3(seed: int = 0, tris: int = 20000, samples_per_seed: int = 256) -> Wo
                     info={"kinds": kinds, "n_tris": [m.n_tris for m in meshes]})
 
 
-def make_config(k: int, seed: int = 0, **kw) -> Workload:
-    return {1: config1, 2: config2, 3: config3}[k](seed, **kw)
+def mesh_library(seed: int = 0, n: int = 64, lo: int = 500, hi: int = 50000):
+    """n seeded meshes of the five procedural shapes with log-uniform
+    triangle counts in [lo, hi] and random per-vertex colours."""
+    rng = np.random.default_rng(1000 * 4 + 500 + seed)
+    lib = []
+    for k in range(n):
+        kind = M.SHAPES[k % len(M.SHAPES)]
+        tris = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        lib.append(M.make_shape(kind, tris, rng).with_colours(rng, name=f"{kind}_{k}"))
+    return lib
+
+
+def _cells(rng, n, spacing=140.0, grid=4, jitter=20.0):
+    cells = [(i, j) for i in range(grid) for j in range(grid)]
+    pick = rng.permutation(len(cells))[:n]
+    off = (grid - 1) / 2.0
+    return [np.array([(cells[c][0] - off) * spacing, (cells[c][1] - off) * spacing]) + rng.uniform(-jitter, jitter, 2)
+            for c in pick]
+
+
+def config4(seed: int = 0, n_scenes: int = 64, library=None):
+    """Batched uneven workload: n_scenes 640x480 RGB-D scenes, each with 1-10
+    objects drawn from a 64-mesh library (500-50k triangles, log-uniform),
+    200-8000 candidate poses per object (log-uniform), 3-DoF or 6-DoF by a
+    coin flip per scene.  Returns one Workload per scene; the meshes are
+    shared objects of the library (index = position in the library)."""
+    lib = mesh_library(seed) if library is None else library
+    K = (640, 480, 525.0, 525.0, 320.0, 240.0)
+    rig = camera_rig()
+    table = _table_mesh()
+    out = []
+    for sc in range(n_scenes):
+        rng = np.random.default_rng(1000 * 4 + 64 * seed + sc)
+        six = bool(rng.uniform() < 0.5)
+        n_obj = int(rng.integers(1, 11))
+        mesh_idx = [int(x) for x in rng.integers(0, len(lib), n_obj)]
+        pos = _cells(rng, n_obj)
+        parts = [(table, table_pose(rig, 0, 0, 0), 0)]
+        objs = []
+        rests = [np.eye(3), rot_x(np.pi / 2), rot_y(np.pi / 2)]
+        for k, (mi, xy) in enumerate(zip(mesh_idx, pos)):
+            m = lib[mi]
+            n_p = int(np.exp(rng.uniform(np.log(200), np.log(8000))))
+            if six:
+                R_wo = rot_z(rng.uniform(0, 2 * np.pi)) @ rests[int(rng.integers(0, 3))]
+                t_wo = np.array([xy[0], xy[1], _rest_pose(m, R_wo)])
+                sr = np.radians(10.0)
+                R_seeds = [R_wo @ exp_so3(rng.normal(0, sr, 3))] + [random_rotation(rng) for _ in range(3)]
+                t_seeds = [t_wo + rng.normal(0, 15.0, 3)] + [t_wo] * 3
+                per = [n_p // 4 + (1 if q < n_p % 4 else 0) for q in range(4)]
+                poses = np.concatenate([perturbed_poses(rig, [R_seeds[q]], [t_seeds[q]], per[q], rng)
+                                        for q in range(4) if per[q] > 0])
+            else:
+                yaw = rng.uniform(0, 2 * np.pi)
+                R_wo = rot_z(yaw)
+                t_wo = np.array([xy[0], xy[1], 0.0])
+                cand = [table_pose(rig, x, y, a).reshape(12) for x, y, a in
+                        zip(rng.uniform(-280, 280, n_p), rng.uniform(-280, 280, n_p), rng.uniform(0, 2 * np.pi, n_p))]
+                poses = np.asarray(cand, np.float64).astype(np.float32)
+            P = world_to_cam(rig, R_wo, t_wo)
+            parts.append((m, P, k + 1))
+            objs.append(ObjectQuery(mi, k + 1, poses, P.reshape(12).astype(np.float32)))
+        depth, rgb, labels = _observe(K, parts, rng)
+        out.append(Workload(f"cfg4-scene{sc}-{'6dof' if six else '3dof'}", 4, sc, Scene(K, depth, rgb, labels), lib,
+                            objs, delta_mm=10.0, tau_c=20.0, use_rgb=True, mark_occluders=True, volume="aabb",
+                            info={"six_dof": six, "n_objects": n_obj}))
+    return out
+
+
+def make_config(k: int, seed: int = 0, **kw):
+    """Configs 1-3 return one Workload; config 4 a list of per-scene Workloads."""
+    return {1: config1, 2: config2, 3: config3, 4: config4}[k](seed, **kw)
