@@ -66,7 +66,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload config (1, 2 or 3)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="1-3: plain path on that scene; 4: batched vs plain on the uneven many-scene workload")
+    ap.add_argument("--batched-scenes", type=int, default=64, help="scenes of the batched workload")
+    ap.add_argument("--batched-steps", type=int, default=3, help="timed passes of the batched leg of a plain run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg of a plain run")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default ~/.cache/perch)")
+    ap.add_argument("--rates", default="20,50,100", help="config 5: arrival rates, scenes/s")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="config 5: arrival window per rate")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=64, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -90,6 +97,34 @@ def main():
     if not os.path.exists(pk.library_path()):
         from paper_2008_00326_amd import build as _b
         _b.build()
+
+    if args.config == 5:
+        rates = [float(x) for x in args.rates.split(",")]
+        r = served_vs_plain(rates, args.serve_seconds, args.seed)
+        top = r["rates"][str(rates[0])]
+        line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
+                "value": top["served"]["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": len(rates),
+                "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f64/i64 geometry, i32 counts, f32 colour", "data": "synthetic",
+                "config": {"workload": r["workload"], "config": 5, "seed": args.seed, "path": "served",
+                           "rate_of_value": rates[0], "parallelism": "single GPU"},
+                "served": r, "kernel_source_sha": kernel_source_sha()}
+        print(json.dumps(line), flush=True)
+        return
+
+    if args.config == 4:
+        ctx = pk.Context(0)
+        r = batched_vs_plain(ctx, args.seed, args.steps, args.warmup, args.batched_scenes, args.tune_cache)
+        ctx.close()
+        line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
+                "value": r["batched_poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": r["batched_ms_per_step"], "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f64/i64 geometry, i32 counts, f32 colour",
+                "data": "synthetic", "config": {"workload": r["workload"], "config": 4, "seed": args.seed,
+                                                "path": "batched (one graph launch)", "parallelism": "single GPU"},
+                "batched": r, "kernel_source_sha": kernel_source_sha()}
+        print(json.dumps(line), flush=True)
+        return
 
     _log(f"[bench] generating config {args.config} seed {args.seed}")
     w = make_config(args.config, args.seed)
@@ -139,7 +174,7 @@ def main():
     value = n_poses * args.steps / elapsed
 
     # dominant kernel and its roofline
-    score_slots = ["score_lds512", "score_lds1024", "score_lds_tile", "score_device"]
+    score_slots = ["score_lds_small", "score_lds_large", "score_lds_tile", "score_device"]
     dom = max(score_slots, key=lambda k: prof[k][0])
     dom_ms, dom_launches = prof[dom]
     areas = tile_areas(w)
@@ -200,10 +235,181 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
     }
 
+    if not args.no_batched:
+        ctx.drop_scene(sid)
+        result["batched"] = batched_vs_plain(ctx, args.seed, args.batched_steps, 1, args.batched_scenes,
+                                             args.tune_cache)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
+    """The uneven many-scene workload (640x480 RGB-D scenes with 1-10 objects,
+    200-8000 candidates per object, meshes of 500-50k triangles, 3-DoF and
+    6-DoF mixed) scored two ways on identical inputs: the plain path, one
+    best_poses launch sequence per scene, and the batched path, every scene
+    in one graph-captured persistent launch with autotuned work spreading.
+    Returns poses/s of both, their ratio, the per-object agreement and the
+    tuning used."""
+    import torch
+    import paper_2008_00326_amd as pk
+    from paper_2008_00326_amd import autotune
+    from paper_2008_00326_amd.workloads import scenes
+
+    _log(f"[bench] batched: generating {n_scenes} scenes")
+    lib = scenes.mesh_library(seed)
+    ws = scenes.config4(seed, n_scenes=n_scenes, library=lib)
+    mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in lib]
+    per_scene, items = [], []
+    for w in ws:
+        sid = ctx.set_scene(w.scene.K, w.scene.depth, w.scene.rgb, delta_mm=w.delta_mm, tau_c=w.tau_c)
+        polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
+        per_scene.append((sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects], polys))
+        items += [{"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": p} for o, p in zip(w.objects, polys)]
+    n_poses = sum(it["poses"].shape[0] for it in items)
+    stream = torch.cuda.current_stream()
+
+    # the tuner times a sample: every fourth scene's items
+    sample = [it for it in items if any(it["scene"] == per_scene[k][0] for k in range(0, len(per_scene), 4))]
+    tris = np.mean([lib[o.mesh].n_tris for w in ws for o in w.objects])
+    bucket = autotune.shape_bucket(640 * 480, tris, n_poses / len(items), True)
+    _log(f"[bench] batched: autotuning on {sum(i['poses'].shape[0] for i in sample)} poses ({bucket})")
+    tuned = autotune.autotune(ctx, sample, bucket, cache_path=tune_cache or autotune.DEFAULT_CACHE, stream=stream)
+
+    def plain():
+        out = []
+        for sid, ms, ls, ps in per_scene:
+            bi, bc = ctx.best_poses(sid, ms, ls, ps, stream=stream)
+            out += list(zip(bi.tolist(), bc.tolist()))
+        return out
+
+    _log(f"[bench] batched: plain path, {len(per_scene)} scenes, {n_poses} poses")
+    for _ in range(warmup):
+        ref = plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ref = plain()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / steps
+
+    b = ctx.batch(max_items=len(items), max_poses=n_poses, max_image_pixels=640 * 480)
+    b.set(items)
+    for _ in range(warmup):
+        b.launch(stream)
+        b.wait()
+    _log("[bench] batched: graph launches")
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.launch(stream)
+        bi, bc = b.wait()
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    got = list(zip(bi.tolist(), bc.tolist()))
+    b.close()
+    for sid, *_ in per_scene:
+        ctx.drop_scene(sid)
+    for m in mids:
+        ctx.unload_mesh(m)
+    return {"workload": f"cfg4-batched-uneven ({n_scenes} scenes, {len(items)} objects, seed {seed})",
+            "poses_per_step": n_poses, "scenes": n_scenes, "objects": len(items),
+            "plain_poses_per_s": round(n_poses / plain_s, 1), "plain_ms_per_step": round(plain_s * 1e3, 3),
+            "batched_poses_per_s": round(n_poses / batched_s, 1), "batched_ms_per_step": round(batched_s * 1e3, 3),
+            "vs_plain": round(plain_s / batched_s, 3), "identical_best_poses": got == ref,
+            "tuning": tuned["tuning"], "tuning_key": tuned["key"], "tuning_cached": tuned["cached"],
+            "tuning_default_ms": tuned.get("default_ms"), "tuning_best_ms": tuned.get("ms"),
+            "kernels_ms": {k: round(v[0] / max(steps, 1), 4) for k, v in prof.items() if v[1]}}
+
+
+def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0):
+    """Poisson arrivals of 6-DoF scenes (8 objects of ~20k triangles, 8,192
+    candidates, 640x480 RGB-D; a seeded pool of generated scenes, each arrival
+    a new upload of one of them) served two ways on identical schedules: the
+    continuous-batching server and the plain loop (one scene at a time,
+    prepared and scored alone).  Arrivals run for `seconds`; what is not
+    answered `drain_s` later counts as unfinished, with its waiting time as a
+    lower bound of its latency."""
+    import threading
+    import torch
+    import paper_2008_00326_amd as pk
+    from paper_2008_00326_amd import serve
+    from paper_2008_00326_amd.workloads import make_config
+
+    _log(f"[bench] served: generating a pool of {pool_size} scenes")
+    pool = [make_config(3, seed + k) for k in range(pool_size)]
+    ctx = pk.Context(0)
+    # reference answers, each scene scored alone
+    ref = []
+    for w in pool:
+        sid, mids = pk.load_workload(ctx, w)
+        polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
+        bi, bc = ctx.best_poses(sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects], polys)
+        ref.append([(int(a), int(b)) for a, b in zip(bi, bc)])
+        ctx.drop_scene(sid)
+        for m in mids:
+            ctx.unload_mesh(m)
+    out = {"workload": f"cfg5-served (Poisson arrivals of 6-DoF 640x480 scenes, pool of {pool_size}, seed {seed})",
+           "seconds": seconds, "drain_s": drain_s, "rates": {}}
+    rng = np.random.default_rng(5000 + seed)
+    for rate in rates:
+        n = int(rng.poisson(rate * seconds))
+        offsets = np.sort(rng.uniform(0.0, seconds, n))
+        picks = rng.integers(0, pool_size, n)
+        res = {}
+        for mode in ("served", "plain"):
+            _log(f"[bench] served: {rate}/s, {n} arrivals, {mode}")
+            reqs = [serve.Request(k, pool[int(picks[k])], pool[int(picks[k])].n_poses) for k in range(n)]
+            t0 = time.perf_counter() + 0.2
+            for r, off in zip(reqs, offsets):
+                r.arrival = t0 + float(off)
+            horizon = t0 + seconds + drain_s
+            if mode == "served":
+                ex = serve.GpuExecutor(ctx, slots=2, max_items=256, max_poses=65536)
+                srv = serve.Server(ex, budget_bytes=int(budget_gb * 2**30), max_items=256, max_poses=65536)
+
+                def producer():
+                    for r in reqs:
+                        d = r.arrival - time.perf_counter()
+                        if d > 0:
+                            time.sleep(d)
+                        srv.submit(r)
+                    d = horizon - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    srv.cancel_pending()
+                    srv.close()
+
+                th = threading.Thread(target=producer, daemon=True)
+                th.start()
+                done = srv.run()
+                th.join()
+                extra = {"launches": len(srv.batches),
+                         "mean_scenes_per_launch": round(float(np.mean([b[1] for b in srv.batches])), 2)
+                         if srv.batches else 0.0, "peak_admitted_MB": round(srv.peak_bytes / 2**20, 1),
+                         "mesh_cache_hits": ex.meshes.hits, "mesh_cache_misses": ex.meshes.misses}
+                ex.close()
+            else:
+                done = serve.plain_loop(ctx, reqs, stop_at=horizon)
+                extra = {}
+            ok = [r for r in done if r.error is None and r.result is not None]
+            mismatch = sum(1 for r in ok if r.result != ref[int(picks[r.rid])])
+            end = max([r.done for r in ok], default=t0)
+            poses = sum(r.n_poses for r in ok)
+            lat = serve.latency_stats(reqs, horizon=horizon)
+            res[mode] = dict({"poses_per_s": round(poses / max(end - t0, 1e-9), 1), "answered": len(ok),
+                              "errors": sum(1 for r in done if r.error), "latency_ms": lat,
+                              "mismatches_vs_alone": mismatch}, **extra)
+        res["vs_plain"] = round(res["served"]["poses_per_s"] / max(res["plain"]["poses_per_s"], 1e-9), 3)
+        res["offered_poses_per_s"] = round(rate * float(np.mean([w.n_poses for w in pool])), 1)
+        out["rates"][str(rate)] = res
+    ctx.close()
+    return out
 
 
 def calibrate_copy():

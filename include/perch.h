@@ -27,8 +27,14 @@
  *    Host pointers are read during the call only.
  *  - Results are deterministic: the same inputs give bit-identical outputs,
  *    whatever else is queued on the device.
- *  - A context belongs to one device; calls on one context from several
- *    threads are serialised internally.
+ *  - A context belongs to one device.  Calls on one context may come from
+ *    several threads and are serialised internally, but the waits inside
+ *    perch_set_scene, perch_best_poses and perch_batch_wait are made outside
+ *    that lock, so one thread can prepare a scene while another waits for
+ *    scores.  A stream or a batch is used by one thread at a time.
+ *  - Device memory released by perch_drop_scene / perch_unload_mesh is kept
+ *    by the context and reused once every launch enqueued through it that
+ *    reads the released scene or mesh has completed; neither call waits.
  *
  * Geometry, depth, coverage, point coordinates and all depth-only counts are
  * exact integers (8 sub-pixel bits, top-left fill rule, 16-bit millimetre
@@ -81,7 +87,8 @@ typedef struct {
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
  * memory held for meshes, scenes and work buffers (0 = no cap).  The context
- * owns one HIP stream used when a call passes a NULL stream. */
+ * owns one HIP stream on which it prepares scenes.  Every call that takes a
+ * hip_stream enqueues on that stream; NULL means the HIP null stream. */
 perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out);
 
 /* Release every mesh, scene and buffer of the context, after waiting for its
@@ -115,7 +122,7 @@ typedef struct {
 perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_info *out);
 
 /* Score n poses of one mesh in one scene (Eq. 3 / Eq. 4).  Asynchronous on
- * hip_stream (NULL = the context's stream).
+ * hip_stream.
  *   label:      the object's label; used by PERCH_VOL_LABEL and, in that
  *               mode, to keep same-label pixels from occluding (Sec. V-C).
  *   poses_dev:  n*12 binary32 device array.
@@ -158,6 +165,9 @@ perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_p
 perch_status perch_batch_set(perch_batch *batch, const perch_work *items, int32_t n_items);
 perch_status perch_batch_launch(perch_batch *batch, void *hip_stream);
 perch_status perch_batch_wait(perch_batch *batch, int32_t *best_idx_host, int32_t *best_cost_host);
+/* Non-blocking: PERCH_OK when the batch's last launch has finished (or it
+ * was never launched), PERCH_EBUSY while it is still running. */
+perch_status perch_batch_query(perch_batch *batch);
 perch_status perch_batch_destroy(perch_batch *batch);
 
 /* Minimum-cost pose of each of n_obj objects (Sec. IV-A "Parallel Search"):
@@ -187,17 +197,42 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id,
  * recorded events and returns, per slot, the summed duration in
  * milliseconds and the number of launches since the last enable.  Slots:
  * 0 pose set-up/classification; scoring kernels by footprint class:
- * 1 tile and keys in LDS (512 threads), 2 tile and keys in LDS (1024
+ * 1 tile and keys in LDS (256 or 512 threads), 2 tile and keys in LDS (1024
  * threads), 3 tile in LDS and keys in device memory, 4 tile and keys in
  * device memory; 5 argmin, 6 scene preparation, 7 render. */
 perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
 
 /* Footprint class (0..3, the scoring slots 1..4 of the profiler) that the
- * last perch_score_poses call on hip_stream (NULL = the context's stream)
+ * last perch_score_poses call on hip_stream
  * assigned to each of its n poses: class_host[i] for pose i.  Blocks until
  * that call has finished.  Meant for inspection and work accounting. */
 perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int32_t *class_host);
+
+/* Launch tuning: how the poses of a launch are spread over the scoring
+ * kernels.  No setting changes any result, only which work-group scores
+ * which pose and in what order.
+ *   small_block:  threads per work-group of the smallest LDS class, 256 or
+ *                 512 (0 = 512); such work-groups get a quarter or a half of
+ *                 a compute unit's LDS.
+ *   small_words:  poses whose raster tile plus J_o key region needs at most
+ *                 this many LDS words go to that class (0 = all that fit).
+ *   grid[c]:      persistent work-groups of footprint class c (0 = as many
+ *                 as are resident at once on the device).
+ *   order:        1 = each class scores its poses in set-up order, 2 = its
+ *                 costliest poses first (0 = 2).
+ * The setting applies to launches enqueued afterwards, and to batches
+ * created afterwards (a batch keeps the setting it was created with).
+ * NULL restores the defaults.  perch_get_tuning returns the values in force,
+ * defaults resolved. */
+typedef struct {
+    int32_t small_block;
+    int32_t small_words;
+    int32_t grid[4];
+    int32_t order;
+} perch_tuning;
+perch_status perch_set_tuning(perch_ctx *ctx, const perch_tuning *tuning);
+perch_status perch_get_tuning(perch_ctx *ctx, perch_tuning *out);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char *perch_last_error(void);

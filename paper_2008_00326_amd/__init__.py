@@ -49,6 +49,11 @@ class _Work(ctypes.Structure):
                 ("jo_dev", ctypes.c_void_p), ("nr_dev", ctypes.c_void_p), ("nq_dev", ctypes.c_void_p)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("small_block", ctypes.c_int32), ("small_words", ctypes.c_int32), ("grid", ctypes.c_int32 * 4),
+                ("order", ctypes.c_int32)]
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
@@ -92,6 +97,9 @@ def load_library():
         "perch_batch_launch": ([P, VP], ctypes.c_int),
         "perch_batch_wait": ([P, P, P], ctypes.c_int),
         "perch_batch_destroy": ([P], ctypes.c_int),
+        "perch_batch_query": ([P], ctypes.c_int),
+        "perch_set_tuning": ([P, P], ctypes.c_int),
+        "perch_get_tuning": ([P, P], ctypes.c_int),
         "perch_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -228,7 +236,28 @@ class Context:
                                           _np_ptr(bi), _np_ptr(bc), _stream_ptr(stream)))
         return bi, bc
 
-    PROFILE_SLOTS = ("setup", "score_lds512", "score_lds1024", "score_lds_tile", "score_device", "argmin",
+    def set_tuning(self, tuning=None):
+        """Set the launch tuning from a dict with any of small_block,
+        small_words, grid (4 ints), order; None restores the defaults.
+        Results never depend on it."""
+        if tuning is None:
+            _check(self._lib.perch_set_tuning(self._h, None))
+            return
+        t = _Tuning()
+        t.small_block = int(tuning.get("small_block", 0))
+        t.small_words = int(tuning.get("small_words", 0))
+        for k, g in enumerate(tuning.get("grid", (0, 0, 0, 0))):
+            t.grid[k] = int(g)
+        t.order = int(tuning.get("order", 0))
+        _check(self._lib.perch_set_tuning(self._h, ctypes.byref(t)))
+
+    def tuning(self) -> dict:
+        """The launch tuning in force, defaults resolved."""
+        t = _Tuning()
+        _check(self._lib.perch_get_tuning(self._h, ctypes.byref(t)))
+        return {"small_block": t.small_block, "small_words": t.small_words, "grid": list(t.grid), "order": t.order}
+
+    PROFILE_SLOTS = ("setup", "score_lds_small", "score_lds_large", "score_lds_tile", "score_device", "argmin",
                      "scene_prep", "render")
 
     def profile(self, enable: bool = True):
@@ -338,6 +367,14 @@ class Batch:
         bc = np.zeros(max(n, 1), np.int32)
         _check(self._lib.perch_batch_wait(self._h, _np_ptr(bi), _np_ptr(bc)))
         return bi[:n], bc[:n]
+
+    def done(self) -> bool:
+        """True once the last launch has finished (non-blocking)."""
+        st = self._lib.perch_batch_query(self._h)
+        if st == -5:
+            return False
+        _check(st)
+        return True
 
     def close(self):
         if getattr(self, "_h", None) and getattr(self.ctx, "_h", None):

@@ -10,6 +10,11 @@ constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 constexpr int kBlockPx = 8;         // side of the depth-range blocks (pixels)
 constexpr int kMaxTris = 65535;     // triangle index lives in 16 bits of the key
 constexpr int kNumClasses = 4;      // LDS small, LDS large, LDS tile + device keys, device memory
+constexpr int kNumBuckets = 16;     // cost buckets of the per-class work order
+// Launch counters (ints): per-class pose counts, per-class work cursors,
+// per-(class, bucket) counts and fill cursors of the cost-ordered lists.
+constexpr int kCntClass = 0, kCntNext = 4, kCntBucket = 8, kCntFill = kCntBucket + kNumClasses * kNumBuckets;
+constexpr int kCounterInts = 256;
 
 // Per-pose screen regions, computed by the setup kernel.
 struct PoseInfo {
@@ -17,6 +22,7 @@ struct PoseInfo {
     int vx0, vy0, vw, vh;   // region holding every observed pixel that may lie in V(O)
     int jx0, jy0, jw, jh;   // part of the V region within reach of a rendered point
     int item, local;        // work item and pose index within it
+    int order;              // class * kNumBuckets + cost bucket
 };
 
 struct SceneDev {
@@ -71,7 +77,8 @@ struct Work {
     int cap_poses;           // capacity of info and each class list
     PoseInfo *info;          // cap_poses
     int *lists;              // kNumClasses * cap_poses global pose indices
-    int *counts;             // kNumClasses counters
+    int *counts;             // kCounterInts launch counters (layout above)
+    int sort;                // order each class list costliest first
     uint32_t *gscratch;      // device-memory slots of classes 2 (keys) and 3 (tile + keys)
     size_t slot_base[kNumClasses];   // first word of each class's slots
     size_t slot_words[kNumClasses];  // words per work-group slot
@@ -82,14 +89,18 @@ struct Work {
 
 // Launch configuration chosen by the runtime (and the tuner).
 struct LaunchCfg {
+    int small_block;    // threads per work-group of class 0 (256 or 512)
     int cap_small;      // LDS words per work-group (tile + keys), class 0
     int cap_large;      // classes 1 and 2 (class 2: tile only)
     int grid[kNumClasses];
+    int sort;           // cost-ordered class lists
 };
 
 hipError_t upload_colour_table(const float *lin256);
-// Allow the scoring kernels up to this much dynamic LDS (set once per device).
-hipError_t prepare_score_kernels(int max_dynamic_lds_bytes);
+// Allow each scoring kernel all the LDS a work-group can hold beside its
+// static LDS (once per device); static_bytes receives the static LDS of the
+// 256-, 512- and 1024-thread kernels (the largest over their variants).
+hipError_t prepare_score_kernels(int lds_per_group, int static_bytes[3]);
 
 hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *oxy, float4 *olab,
                              uint32_t *oblk, hipStream_t st);
@@ -97,9 +108,10 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *ox
 // that can have an observed point within delta, then one entry per depth.
 hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st);
 hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
-// A launch: zero the class counters, classify every pose (grid sized for
-// `poses_grid` poses; the kernels read the real count from the header), run
-// the four scoring classes, then the per-item argmin if w.best is set.
+// A launch: zero the counters, classify every pose (grid sized for
+// `poses_grid` poses; the kernels read the real count from the header) and,
+// with w.sort, order each class list by cost bucket; run the four scoring
+// classes, then the per-item argmin if w.best is set.
 hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st);
 hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, hipStream_t st);
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st);

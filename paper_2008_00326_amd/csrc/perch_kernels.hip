@@ -251,6 +251,16 @@ __device__ __forceinline__ int window_half(float f, float lat, float z, float dl
     return (int)bnd + 1;
 }
 
+// Row of entry q of a row-major window ww pixels wide: a binary32 estimate
+// corrected to the exact quotient.
+__device__ __forceinline__ int window_row(int q, int ww, float inv)
+{
+    int qy = (int)(((float)q + 0.5f) * inv);
+    if (qy * ww > q) --qy;
+    else if ((qy + 1) * ww <= q) ++qy;
+    return qy;
+}
+
 // Nearest-neighbour keys of the J_o region: smallest (squared distance,
 // tile index of the rendered point) over the rendered points within delta.
 // 32 bits (distance << 16 | index) in LDS, 64 bits in device memory.
@@ -274,18 +284,35 @@ template <> struct KeyOf<true> {
     __device__ static void store(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 };
 
+// Key update of observed pixel (px, py) by rendered point (X, Y, Z) with
+// tile index k, if the two lie within delta; dq < 2^13, so the 24-bit
+// products are exact.
+template <bool G>
+__device__ __forceinline__ void mark_one(const SceneDev &s, int dp, int2 xy, int X, int Y, int Z, int k,
+                                         typename KeyOf<G>::T *key)
+{
+    using K = KeyOf<G>;
+    const int dz = 16 * dp - Z;
+    const int dx = xy.x - X, dy = xy.y - Y;
+    if (dp == 0 || max(max(abs(dz), abs(dx)), abs(dy)) > s.dq) return;
+    const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
+    if (d2 > s.dq2) return;
+    K::min(key, K::make(d2, k));
+}
+
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
 // visits every observed pixel of r's window inside the J_o region: each
 // observed point within delta of r min-combines (d2, k) into its key.  This
 // marks the points that r explains (Eq. 3) and, over all r, leaves each
-// observed point's nearest rendered neighbour (Eq. 4).  Lanes stride over the
-// window in row-major order, four pixels per lane per round, and every load
-// of a round is issued before any is used.
+// observed point's nearest rendered neighbour (Eq. 4).  The lanes cover
+// whole window rows at a time (64 / width rows per round, so a lane keeps
+// its column and steps its row by a constant), two rounds per iteration
+// with every load issued before use; windows wider than a wave are walked
+// in row-major order, four pixels per lane per round.
 template <bool G>
 __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typename KeyOf<G>::T *keys, int jx0,
                           int jy0, int jw, int jh, int lane)
 {
-    using K = KeyOf<G>;
     const int X = (int)rint(s.kx[i] * (double)d);
     const int Y = (int)rint(s.ky[j] * (double)d);
     const float dl = s.delta + 0.25f;
@@ -294,17 +321,36 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
     const int i0 = max(max(i - wu, 0), jx0), i1 = min(min(i + wu, s.W - 1), jx0 + jw - 1);
     const int j0 = max(max(j - wv, 0), jy0), j1 = min(min(j + wv, s.H - 1), jy0 + jh - 1);
     if (i0 > i1 || j0 > j1) return;
-    const int ww = i1 - i0 + 1;
-    const int ws = ww * (j1 - j0 + 1);
-    const float inv = 1.0f / (float)ww;
+    const int ww = i1 - i0 + 1, wh = j1 - j0 + 1;
     const int Z = 16 * d;
+    if (ww <= 64) {
+        const int rows = 64 / ww;
+        const int r = lane / ww, c = lane - r * ww;
+        if (r >= rows) return;
+        const int step = rows * s.W, kstep = rows * jw;
+        int pix = (j0 + r) * s.W + i0 + c;
+        int kk = (j0 + r - jy0) * jw + (i0 + c - jx0);
+        int row = r;
+        for (; row + rows < wh; row += 2 * rows) {
+            const int dp0 = s.depth[pix], dp1 = s.depth[pix + step];
+            const int2 q0 = s.oxy[pix], q1 = s.oxy[pix + step];
+            mark_one<G>(s, dp0, q0, X, Y, Z, k, keys + kk);
+            mark_one<G>(s, dp1, q1, X, Y, Z, k, keys + kk + kstep);
+            pix += 2 * step;
+            kk += 2 * kstep;
+        }
+        if (row < wh) mark_one<G>(s, s.depth[pix], s.oxy[pix], X, Y, Z, k, keys + kk);
+        return;
+    }
+    const int ws = ww * wh;
+    const float inv = 1.0f / (float)ww;
     for (int q0 = 0; q0 < ws; q0 += 256) {
         int dp[4], px[4], py[4];
         int2 xy[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int q = q0 + 64 * u + lane;
-            const int qy = (int)(((float)q + 0.5f) * inv);  // exact: q < 2^20, ww <= 2^12
+            const int qy = window_row(q, ww, inv);
             px[u] = i0 + (q - qy * ww);
             py[u] = j0 + qy;
             const bool in = q < ws;
@@ -313,15 +359,8 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
             xy[u] = in ? s.oxy[pix] : make_int2(0, 0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int dz = 16 * dp[u] - Z;
-            const int dx = xy[u].x - X, dy = xy[u].y - Y;
-            if (dp[u] == 0 || dz > s.dq || dz < -s.dq || dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq)
-                continue;
-            const int d2 = dx * dx + dy * dy + dz * dz;
-            if (d2 > s.dq2) continue;
-            K::min(keys + (py[u] - jy0) * jw + (px[u] - jx0), K::make(d2, k));
-        }
+        for (int u = 0; u < 4; ++u)
+            if (dp[u] != 0) mark_one<G>(s, dp[u], xy[u], X, Y, Z, k, keys + (py[u] - jy0) * jw + (px[u] - jx0));
     }
 }
 
@@ -536,9 +575,17 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
     __shared__ int queue[BLOCK];
     __shared__ int queue2[BLOCK];
     __shared__ int qn;
-    const int count = w.counts[cls];
+    __shared__ int next;
+    const int count = w.counts[kCntClass + cls];
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
-    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    // poses are taken from the class list through a shared cursor, so a
+    // work-group that drew cheap poses takes more of them
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&w.counts[kCntNext + cls], 1);
+        __syncthreads();
+        const int i = next;
+        __syncthreads();
+        if (i >= count) break;
         const int p = w.lists[cls * w.cap_poses + i];
         uint32_t *tile = G ? slot : smem;
         typename KeyOf<KG>::T *keys;
@@ -595,7 +642,16 @@ __device__ __forceinline__ void clip_box(double umin, double umax, double vmin, 
 
 __global__ void zero_counts_kernel(int *counts)
 {
-    if (threadIdx.x < kNumClasses) counts[threadIdx.x] = 0;
+    if (threadIdx.x < kCounterInts) counts[threadIdx.x] = 0;
+}
+
+// Cost bucket of a pose from its raster tile, J_o region and triangle
+// count, weighted as the per-pose work of rasterizing and searching.
+__device__ __forceinline__ int cost_bucket(int tile_px, int j_px, int nt)
+{
+    const long long est = 3LL * tile_px + j_px + nt / 5 + 1;
+    const int lg = 63 - __clzll(est);
+    return min(max(lg - 4, 0), kNumBuckets - 1);
 }
 
 __global__ void setup_kernel(Work w)
@@ -663,7 +719,34 @@ __global__ void setup_kernel(Work w)
     const int words = tile_words + in.jw * in.jh;
     int cls = tile_words <= w.cap_large ? 2 : 3;
     if (it.key32 && words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
-    const int slot = atomicAdd(&w.counts[cls], 1);
+    if (w.sort) {
+        const int order = cls * kNumBuckets + cost_bucket(tile_words, in.jw * in.jh, m.nt);
+        w.info[p].order = order;
+        atomicAdd(&w.counts[kCntClass + cls], 1);
+        atomicAdd(&w.counts[kCntBucket + order], 1);
+    } else {
+        const int slot = atomicAdd(&w.counts[kCntClass + cls], 1);
+        w.lists[cls * w.cap_poses + slot] = p;
+    }
+}
+
+// Place each pose in its class list, costliest bucket first (order within
+// a bucket is arbitrary: every pose is scored independently).
+__global__ void order_kernel(Work w)
+{
+    __shared__ int base[kNumClasses * kNumBuckets];
+    if (threadIdx.x < kNumClasses * kNumBuckets) {
+        const int cls = threadIdx.x / kNumBuckets, b = threadIdx.x % kNumBuckets;
+        int off = 0;
+        for (int k = kNumBuckets - 1; k > b; --k) off += w.counts[kCntBucket + cls * kNumBuckets + k];
+        base[threadIdx.x] = off;
+    }
+    __syncthreads();
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= w.hdr->n_poses) return;
+    const int order = w.info[p].order;
+    const int cls = order / kNumBuckets;
+    const int slot = base[order] + atomicAdd(&w.counts[kCntFill + order], 1);
     w.lists[cls * w.cap_poses + slot] = p;
 }
 
@@ -773,59 +856,78 @@ __global__ __launch_bounds__(1024) void table_scan_kernel(int N, int2 *thdr, lon
     }
 }
 
-// One wave per pixel: each lane takes one depth of the pixel's range and
-// finds the nearest observed point within delta (ties: lower pixel index),
-// scanning the window of the chunk's smallest depth (the widest one) with
-// wave-uniform loads of the observed data.
+// Entries of one pixel's range handled per pass of the fill kernel.
+constexpr int kFillChunk = 256;
+
+// Make the LDS writes of a wave visible to all its lanes.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One wave per pixel.  An observed point q can lie within delta of a
+// rendered point at this pixel only at depths within dzmm of q's own, so the
+// lanes take the observed points of the pixel's window and each visits just
+// the depths of the range that q can reach, min-combining (squared
+// distance, pixel index) into that depth's entry in LDS.  The entries'
+// back-projected (X, Y) are computed once per pass.  Ranges longer than
+// kFillChunk are filled in several passes.
 __global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tnn)
 {
-    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (a >= s.W * s.H) return;
+    __shared__ unsigned long long acc[4][kFillChunk];
+    __shared__ int2 exy[4][kFillChunk];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = blockIdx.x * 4 + wv;
+    if (a >= s.W * s.H) return;                 // no block-wide barrier below
     const int2 th = s.thdr[a];
     const int lo = th.y & 0xFFFF, n = (int)((uint32_t)th.y >> 16);
     if (n == 0) return;
     const int j = a / s.W, i = a - j * s.W;
     const double kxi = s.kx[i], kyj = s.ky[j];
     const float dl = s.delta + 0.25f;
-    for (int e0 = 0; e0 < n; e0 += 64) {
-        const int e = e0 + lane;
-        const int d = lo + min(e, n - 1);
-        const int X = (int)rint(kxi * (double)d);
-        const int Y = (int)rint(kyj * (double)d);
-        const int Z = 16 * d;
-        const int dmin = lo + e0, dmax = lo + min(e0 + 63, n - 1);
+    for (int c0 = 0; c0 < n; c0 += kFillChunk) {
+        const int cn = min(kFillChunk, n - c0);
+        const int dmin = lo + c0, dmax = lo + c0 + cn - 1;
+        for (int e = lane; e < cn; e += 64) {
+            acc[wv][e] = ~0ULL;
+            exy[wv][e] = make_int2((int)rint(kxi * (double)(dmin + e)), (int)rint(kyj * (double)(dmin + e)));
+        }
+        wave_lds_sync();
+        // the window of the pass's smallest depth is the widest one
         const int Xmin = (int)rint(kxi * (double)dmin), Ymin = (int)rint(kyj * (double)dmin);
         const int wu = window_half(s.fx, (float)Xmin * 0.0625f, (float)dmin, dl, s.W);
-        const int wv = window_half(s.fy, (float)Ymin * 0.0625f, (float)dmin, dl, s.H);
+        const int wvv = window_half(s.fy, (float)Ymin * 0.0625f, (float)dmin, dl, s.H);
         const int i0 = max(i - wu, 0), i1 = min(i + wu, s.W - 1);
-        const int j0 = max(j - wv, 0), j1 = min(j + wv, s.H - 1);
+        const int j0 = max(j - wvv, 0), j1 = min(j + wvv, s.H - 1);
+        const int ww = i1 - i0 + 1;
+        const int ws = ww * (j1 - j0 + 1);
+        const float inv = 1.0f / (float)ww;
         const int dlo = dmin - s.dzmm, dhi = dmax + s.dzmm;
-        unsigned long long best = ~0ULL;
-        for (int by = j0 >> 3; by <= (j1 >> 3); ++by) {
-            for (int bx = i0 >> 3; bx <= (i1 >> 3); ++bx) {
-                const uint32_t blk = s.oblk[by * s.bw + bx];
-                if ((int)(blk >> 16) < dlo || (int)(blk & 0xFFFFu) > dhi) continue;
-                const int ja = max(by << 3, j0), jb = min((by << 3) + 7, j1);
-                const int ia = max(bx << 3, i0), ib = min((bx << 3) + 7, i1);
-                for (int jj = ja; jj <= jb; ++jj) {
-                    for (int ii = ia; ii <= ib; ++ii) {
-                        const int pix = jj * s.W + ii;
-                        const int dp = s.depth[pix];
-                        if (dp < dlo || dp > dhi || dp == 0) continue;
-                        const int2 q = s.oxy[pix];
-                        const int dz = 16 * dp - Z;
-                        const int dx = q.x - X, dy = q.y - Y;
-                        if (dz > s.dq || dz < -s.dq || dx > s.dq || dx < -s.dq || dy > s.dq || dy < -s.dq) continue;
-                        const int d2 = dx * dx + dy * dy + dz * dz;
-                        if (d2 > s.dq2) continue;
-                        const unsigned long long key = ((unsigned long long)d2 << 32) | (uint32_t)pix;
-                        best = key < best ? key : best;
-                    }
-                }
+        for (int q = lane; q < ws; q += 64) {
+            const int qy = window_row(q, ww, inv);
+            const int pix = (j0 + qy) * s.W + i0 + (q - qy * ww);
+            const int dp = s.depth[pix];
+            if (dp == 0 || dp < dlo || dp > dhi) continue;
+            const int2 xy = s.oxy[pix];
+            const int ea = max(dp - s.dzmm, dmin) - dmin, eb = min(dp + s.dzmm, dmax) - dmin;
+            for (int e = ea; e <= eb; ++e) {
+                const int dz = 16 * dp - 16 * (dmin + e);
+                const int2 r = exy[wv][e];
+                const int dx = xy.x - r.x, dy = xy.y - r.y;
+                if (max(max(abs(dz), abs(dx)), abs(dy)) > s.dq) continue;
+                const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
+                if (d2 > s.dq2) continue;
+                atomicMin(&acc[wv][e], ((unsigned long long)d2 << 32) | (uint32_t)pix);
             }
         }
-        if (e < n) tnn[th.x + e] = best == ~0ULL ? -1 : (int32_t)(best & 0xFFFFFFFFu);
+        wave_lds_sync();
+        for (int e = lane; e < cn; e += 64) {
+            const unsigned long long best = acc[wv][e];
+            tnn[th.x + c0 + e] = best == ~0ULL ? -1 : (int32_t)(best & 0xFFFFFFFFu);
+        }
+        wave_lds_sync();
     }
 }
 
@@ -939,29 +1041,42 @@ static hipError_t launch_one(const Work &w, int cls, int grid, int lds_words, hi
 }
 
 template <bool RGB>
-static hipError_t prepare_t(int lds_bytes)
+static hipError_t prepare_t(int lds_per_group, int static_bytes[3])
 {
-    const void *k[] = {(const void *)score_kernel<512, false, false, RGB>,
-                       (const void *)score_kernel<1024, false, false, RGB>,
-                       (const void *)score_kernel<1024, false, true, RGB>};
-    for (const void *f : k) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    struct K {
+        const void *f;
+        int slot;
+    };
+    const K ks[] = {{(const void *)score_kernel<256, false, false, RGB>, 0},
+                    {(const void *)score_kernel<512, false, false, RGB>, 1},
+                    {(const void *)score_kernel<1024, false, false, RGB>, 2},
+                    {(const void *)score_kernel<1024, false, true, RGB>, 2}};
+    for (const K &k : ks) {
+        hipFuncAttributes a{};
+        hipError_t e = hipFuncGetAttributes(&a, k.f);
+        if (e != hipSuccess) return e;
+        const int st = (int)a.sharedSizeBytes;
+        static_bytes[k.slot] = max(static_bytes[k.slot], st);
+        e = hipFuncSetAttribute(k.f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_per_group - st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t prepare_score_kernels(int max_dynamic_lds_bytes)
+hipError_t prepare_score_kernels(int lds_per_group, int static_bytes[3])
 {
-    hipError_t e = prepare_t<false>(max_dynamic_lds_bytes);
-    return e == hipSuccess ? prepare_t<true>(max_dynamic_lds_bytes) : e;
+    static_bytes[0] = static_bytes[1] = static_bytes[2] = 0;
+    hipError_t e = prepare_t<false>(lds_per_group, static_bytes);
+    return e == hipSuccess ? prepare_t<true>(lds_per_group, static_bytes) : e;
 }
 
 template <bool RGB>
 static hipError_t launch_class_t(const Work &w, const LaunchCfg &c, int cls, hipStream_t st)
 {
     switch (cls) {
-    case 0: return launch_one<512, false, false, RGB>(w, 0, c.grid[0], c.cap_small, st);
+    case 0:
+        return c.small_block == 256 ? launch_one<256, false, false, RGB>(w, 0, c.grid[0], c.cap_small, st)
+                                    : launch_one<512, false, false, RGB>(w, 0, c.grid[0], c.cap_small, st);
     case 1: return launch_one<1024, false, false, RGB>(w, 1, c.grid[1], c.cap_large, st);
     case 2: return launch_one<1024, false, true, RGB>(w, 2, c.grid[2], c.cap_large, st);
     default: return launch_one<256, true, true, RGB>(w, 3, c.grid[3], 0, st);
@@ -970,8 +1085,9 @@ static hipError_t launch_class_t(const Work &w, const LaunchCfg &c, int cls, hip
 
 hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st)
 {
-    zero_counts_kernel<<<1, 64, 0, st>>>(w.counts);
+    zero_counts_kernel<<<1, kCounterInts, 0, st>>>(w.counts);
     setup_kernel<<<(poses_grid + 255) / 256, 256, 0, st>>>(w);
+    if (w.sort) order_kernel<<<(poses_grid + 255) / 256, 256, 0, st>>>(w);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -53,10 +54,27 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Events recorded after the last launch on each stream that read a buffer;
+// a released buffer is reused only once all of them have completed.
+struct Fence {
+    std::vector<hipEvent_t> ev;
+};
+using FenceRef = std::shared_ptr<Fence>;
+
+struct CachedBlock {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    FenceRef fence;
+};
+
+// Last-use events of a resident mesh or scene, one per stream.
+using Uses = std::map<hipStream_t, hipEvent_t>;
+
 struct MeshRec {
     DevBuf verts, tris, rgb;
     MeshDev dev{};
     size_t bytes = 0;
+    Uses uses;
 };
 
 struct SceneRec {
@@ -65,7 +83,18 @@ struct SceneRec {
     std::vector<int32_t> host_labels;
     std::map<int32_t, std::vector<int>> label_boxes;
     size_t bytes = 0;
+    Uses uses;
 };
+
+// Allocation granule: 4 KiB up to 1 MiB, then an eighth of the leading
+// power of two, so that buffers of similar size can reuse each other.
+size_t round_alloc(size_t bytes)
+{
+    if (bytes <= ((size_t)1 << 20)) return (bytes + 4095) & ~(size_t)4095;
+    const int lg = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t g = (size_t)1 << (lg - 3);
+    return (bytes + g - 1) / g * g;
+}
 
 // Device buffers of one launch: descriptors, per-pose work, device-memory
 // slots of the large footprint classes, per-item minima.
@@ -105,6 +134,13 @@ struct perch_ctx {
     std::map<hipStream_t, StreamBufs> work;
     std::vector<perch_batch *> batches;
     std::recursive_mutex mu;
+    perch_tuning tune{};                  // zeros: defaults
+    int static_lds[3] = {0, 0, 0};        // static LDS bytes of the 256-, 512- and 1024-thread scoring kernels
+
+    // released device blocks awaiting reuse, and recycled use-tracking events
+    std::vector<CachedBlock> cache;
+    size_t cached = 0;
+    std::vector<hipEvent_t> ev_pool;
 
     // profiler: HIP events around each launch, on the launch stream
     bool prof = false;
@@ -154,13 +190,81 @@ struct perch_ctx {
         pending.clear();
     }
 
+    hipEvent_t use_event()
+    {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        return e;
+    }
+    // record "read by work queued so far on st" for a mesh or scene
+    void mark_use(Uses &u, hipStream_t st)
+    {
+        hipEvent_t &e = u[st];
+        if (!e) e = use_event();
+        (void)hipEventRecord(e, st);
+    }
+    FenceRef fence_of(Uses &u)
+    {
+        auto f = std::make_shared<Fence>();
+        for (auto &kv : u) f->ev.push_back(kv.second);
+        u.clear();
+        return f;
+    }
+    bool fence_done(const FenceRef &f)
+    {
+        if (!f) return true;
+        for (hipEvent_t e : f->ev)
+            if (hipEventQuery(e) != hipSuccess) return false;
+        for (hipEvent_t e : f->ev) ev_pool.push_back(e);
+        f->ev.clear();
+        return true;
+    }
+    // Free every cached block; waits for the device first.
+    void trim()
+    {
+        if (cache.empty()) return;
+        (void)hipDeviceSynchronize();
+        for (CachedBlock &c : cache) {
+            (void)hipFree(c.ptr);
+            if (c.fence) fence_done(c.fence);
+        }
+        cache.clear();
+        cached = 0;
+    }
     perch_status alloc(DevBuf &b, size_t bytes)
     {
-        if (bytes == 0) bytes = 256;
+        bytes = round_alloc(bytes == 0 ? 256 : bytes);
         if (budget && used + bytes > budget)
             return fail(PERCH_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", used, bytes, budget);
+        // the smallest released block of at most twice the size whose readers are done
+        int pick = -1;
+        for (int i = 0; i < (int)cache.size(); ++i) {
+            const CachedBlock &c = cache[i];
+            if (c.bytes < bytes || c.bytes > 2 * bytes) continue;
+            if (pick >= 0 && cache[pick].bytes <= c.bytes) continue;
+            if (!fence_done(c.fence)) continue;
+            pick = i;
+        }
+        if (pick >= 0) {
+            b.ptr = cache[pick].ptr;
+            b.bytes = cache[pick].bytes;
+            cached -= b.bytes;
+            cache.erase(cache.begin() + pick);
+            used += b.bytes;
+            return PERCH_OK;
+        }
+        if (budget && used + cached + bytes > budget) trim();
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipErrorOutOfMemory && !cache.empty()) {
+            trim();
+            e = hipMalloc(&p, bytes);
+        }
         if (e != hipSuccess)
             return fail(e == hipErrorOutOfMemory ? PERCH_ENOMEM : PERCH_EDEVICE, "hipMalloc(%zu): %s", bytes,
                         hipGetErrorString(e));
@@ -169,15 +273,19 @@ struct perch_ctx {
         used += bytes;
         return PERCH_OK;
     }
-    void release(DevBuf &b)
+    // Return a block to the cache; it is reused once `fence` has completed.
+    void release(DevBuf &b, FenceRef fence = nullptr)
     {
         if (b.ptr) {
-            (void)hipFree(b.ptr);
+            cache.push_back(CachedBlock{b.ptr, b.bytes, fence});
+            cached += b.bytes;
             used -= b.bytes;
         }
         b.ptr = nullptr;
         b.bytes = 0;
+        if (cached > kCacheMax) trim();
     }
+    static constexpr size_t kCacheMax = (size_t)16 << 30;
     // grow a per-stream buffer; waits for the device first so no queued
     // kernel still reads the old allocation
     perch_status ensure(DevBuf &b, size_t bytes)
@@ -237,7 +345,8 @@ perch_status enter(perch_ctx *ctx)
     return PERCH_OK;
 }
 
-hipStream_t pick_stream(perch_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
+// NULL is the HIP null stream (the default stream of PyTorch and of plain HIP code).
+hipStream_t pick_stream(perch_ctx *, void *s) { return (hipStream_t)s; }
 
 // sRGB8 -> linear (IEC 61966-2-1), computed in binary64 and rounded.
 void colour_table(float out[256])
@@ -248,19 +357,24 @@ void colour_table(float out[256])
     }
 }
 
-// static LDS of the scoring kernels: counters and two 1024-entry work queues
-constexpr long long kStaticLds = 8 * 1024 + 256;
-
+// Launch configuration from the context's tuning.  At 128 VGPRs a CU keeps
+// 16 waves resident: four 256-thread, two 512-thread or one 1024-thread
+// scoring work-group, and each gets that share of the CU's LDS.
 LaunchCfg launch_cfg(const perch_ctx *ctx)
 {
-    LaunchCfg c;
-    // LDS words of tile + keys; tile indices must fit the 16-bit key field
-    c.cap_large = (int)std::min<long long>(((long long)ctx->lds_max - kStaticLds) / 4, 65535);
-    c.cap_small = (int)std::min<long long>(((long long)ctx->lds_max / 2 - kStaticLds) / 4, c.cap_large);
-    c.grid[0] = ctx->n_cu * 2;
-    c.grid[1] = ctx->n_cu;
-    c.grid[2] = ctx->n_cu;
-    c.grid[3] = std::min(ctx->n_cu, 64);
+    const perch_tuning &t = ctx->tune;
+    const long long lds = (long long)ctx->lds_max;
+    LaunchCfg c{};
+    c.small_block = t.small_block == 256 ? 256 : 512;
+    const int per_cu = 1024 / c.small_block;
+    c.cap_large = (int)std::min<long long>((lds - ctx->static_lds[2]) / 4, 65535);
+    const int fit = (int)std::min<long long>((lds / per_cu - ctx->static_lds[c.small_block == 256 ? 0 : 1]) / 4,
+                                             c.cap_large);
+    c.cap_small = t.small_words > 0 ? std::min(t.small_words, fit) : fit;
+    const int def[kNumClasses] = {ctx->n_cu * per_cu, ctx->n_cu, ctx->n_cu, std::min(ctx->n_cu, 64)};
+    for (int k = 0; k < kNumClasses; ++k)
+        c.grid[k] = t.grid[k] > 0 ? std::min(t.grid[k], 16 * ctx->n_cu) : def[k];
+    c.sort = t.order != 1;
     return c;
 }
 
@@ -406,7 +520,7 @@ perch_status ensure_bufs(perch_ctx *ctx, LaunchBufs &lb, size_t desc_bytes, int 
     if ((s = ctx->ensure(lb.desc, desc_bytes))) return s;
     if ((s = ctx->ensure(lb.info, (size_t)std::max(cap_poses, 1) * sizeof(PoseInfo)))) return s;
     if ((s = ctx->ensure(lb.lists, (size_t)kNumClasses * std::max(cap_poses, 1) * sizeof(int)))) return s;
-    if ((s = ctx->ensure(lb.counts, 64))) return s;
+    if ((s = ctx->ensure(lb.counts, kCounterInts * 4))) return s;
     if ((s = ctx->ensure(lb.scratch, total * 4))) return s;
     if ((s = ctx->ensure(lb.best, (size_t)std::max(cap_items, 1) * 8))) return s;
     return PERCH_OK;
@@ -430,6 +544,7 @@ Work make_work(const LaunchBufs &lb, const Built &b, int cap_poses, const Launch
     slot_layout(cfg, max_pixels, w.slot_words, w.slot_base, &total, &w.dev_tile_words);
     w.cap_small = cfg.cap_small;
     w.cap_large = cfg.cap_large;
+    w.sort = cfg.sort;
     w.best = want_best ? (int32_t *)lb.best.ptr : nullptr;
     return w;
 }
@@ -467,31 +582,33 @@ perch_status upload(StreamBufs &sb, const Built &b, void *dev, hipStream_t st)
     return PERCH_OK;
 }
 
-// Direct (non-graph) launch of a list of work items on a stream.  With
-// best_host, waits and returns {index, J} per request.
-perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hipStream_t st, int32_t *best_host)
+void mark_uses(perch_ctx *ctx, const std::vector<int32_t> &scene_ids, const std::vector<int32_t> &mesh_ids,
+               hipStream_t st)
+{
+    for (int32_t id : scene_ids) ctx->mark_use(ctx->scenes[id].uses, st);
+    for (int32_t id : mesh_ids) ctx->mark_use(ctx->meshes[id].uses, st);
+}
+
+// Direct (non-graph) launch of a list of work items on a stream (caller
+// holds the context lock).  With want_best, the per-item minima are left in
+// the stream's buffers: *n_items_out and item_of_req say where.
+perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hipStream_t st, bool want_best,
+                        int *n_items_out = nullptr, std::vector<int> *item_of_req = nullptr)
 {
     Built b;
     if (perch_status s = build_descriptors(ctx, req, n_req, b)) return s;
+    if (n_items_out) *n_items_out = b.n_items;
+    if (item_of_req) *item_of_req = b.item_of_req;
     if (b.n_poses == 0) return PERCH_OK;
     StreamBufs &sb = ctx->work[st];
     const LaunchCfg cfg = launch_cfg(ctx);
     if (perch_status s = ensure_bufs(ctx, sb.lb, b.bytes.size(), b.n_poses, b.n_items, b.max_pixels, cfg)) return s;
     if (perch_status s = upload(sb, b, sb.lb.desc.ptr, st)) return s;
-    const Work w = make_work(sb.lb, b, b.n_poses, cfg, b.max_pixels, best_host != nullptr);
+    const Work w = make_work(sb.lb, b, b.n_poses, cfg, b.max_pixels, want_best);
     sb.last_n = b.n_poses;
     hipError_t e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, st, true);
     if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
-    if (best_host) {
-        std::vector<int32_t> res((size_t)2 * b.n_items);
-        HIP_TRY(hipMemcpyAsync(res.data(), w.best, res.size() * 4, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int32_t r = 0; r < n_req; ++r) {
-            const int it = b.item_of_req[r];
-            best_host[2 * r] = it >= 0 ? res[2 * it] : -1;
-            best_host[2 * r + 1] = it >= 0 ? res[2 * it + 1] : -1;
-        }
-    }
+    mark_uses(ctx, b.scene_ids, b.mesh_ids, st);
     return PERCH_OK;
 }
 
@@ -521,7 +638,7 @@ perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
     float lin[256];
     colour_table(lin);
     e = upload_colour_table(lin);
-    if (e == hipSuccess) e = prepare_score_kernels((int)(ctx->lds_max - kStaticLds));
+    if (e == hipSuccess) e = prepare_score_kernels((int)ctx->lds_max, ctx->static_lds);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete ctx;
@@ -538,14 +655,16 @@ perch_status perch_destroy(perch_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &kv : ctx->meshes) {
-        ctx->release(kv.second.verts);
-        ctx->release(kv.second.tris);
-        ctx->release(kv.second.rgb);
+        FenceRef f = ctx->fence_of(kv.second.uses);
+        ctx->release(kv.second.verts, f);
+        ctx->release(kv.second.tris, f);
+        ctx->release(kv.second.rgb, f);
     }
     for (auto &kv : ctx->scenes) {
         SceneRec &r = kv.second;
+        FenceRef f = ctx->fence_of(r.uses);
         for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
-            ctx->release(*b);
+            ctx->release(*b, f);
     }
     while (!ctx->batches.empty()) perch_batch_destroy(ctx->batches.back());
     for (auto &kv : ctx->work) {
@@ -558,7 +677,9 @@ perch_status perch_destroy(perch_ctx *ctx)
         }
     }
     ctx->collect();
+    ctx->trim();
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return ok();
@@ -568,7 +689,6 @@ perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz, int32_t n_verts, 
                              int32_t n_tris, const uint8_t *rgb, int32_t *mesh_id)
 {
     if (perch_status st = enter(ctx)) return st;
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!xyz || !tri || !mesh_id) return fail(PERCH_EINVAL, "null xyz, tri or mesh_id");
     if (n_verts < 1) return fail(PERCH_EINVAL, "n_verts must be >= 1 (got %d)", n_verts);
     if (n_tris < 1 || n_tris > kMaxTris)
@@ -599,22 +719,27 @@ perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz, int32_t n_verts, 
                    | ((uint32_t)rgb[3 * (size_t)k + 2] << 16);
     }
     MeshRec r;
-    perch_status st;
-    if ((st = ctx->alloc(r.verts, v.size() * sizeof(float4))) || (st = ctx->alloc(r.tris, t.size() * sizeof(int4)))
-        || (rgb && (st = ctx->alloc(r.rgb, c.size() * sizeof(uint32_t))))) {
-        std::string msg = g_last_error;
+    auto cleanup = [&]() {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         ctx->release(r.verts);
         ctx->release(r.tris);
         ctx->release(r.rgb);
-        return fail(st, "%s", msg.c_str());
+    };
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        perch_status st;
+        if ((st = ctx->alloc(r.verts, v.size() * sizeof(float4))) || (st = ctx->alloc(r.tris, t.size() * sizeof(int4)))
+            || (rgb && (st = ctx->alloc(r.rgb, c.size() * sizeof(uint32_t))))) {
+            std::string msg = g_last_error;
+            cleanup();
+            return fail(st, "%s", msg.c_str());
+        }
     }
     hipError_t e = hipMemcpy(r.verts.ptr, v.data(), v.size() * sizeof(float4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r.tris.ptr, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e == hipSuccess && rgb) e = hipMemcpy(r.rgb.ptr, c.data(), c.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        ctx->release(r.verts);
-        ctx->release(r.tris);
-        ctx->release(r.rgb);
+        cleanup();
         return fail(PERCH_EDEVICE, "mesh upload: %s", hipGetErrorString(e));
     }
     r.dev.verts = (const float4 *)r.verts.ptr;
@@ -627,6 +752,7 @@ perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz, int32_t n_verts, 
         r.dev.hi[a] = hi[a];
     }
     r.bytes = r.verts.bytes + r.tris.bytes + r.rgb.bytes;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     const int32_t id = ctx->next_mesh++;
     ctx->meshes[id] = r;
     *mesh_id = id;
@@ -640,10 +766,10 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id)
     auto it = ctx->meshes.find(mesh_id);
     if (it == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
     if (perch_status st = release_check(ctx, false, mesh_id)) return st;
-    (void)hipDeviceSynchronize();
-    ctx->release(it->second.verts);
-    ctx->release(it->second.tris);
-    ctx->release(it->second.rgb);
+    FenceRef f = ctx->fence_of(it->second.uses);
+    ctx->release(it->second.verts, f);
+    ctx->release(it->second.tris, f);
+    ctx->release(it->second.rgb, f);
     ctx->meshes.erase(it);
     return ok();
 }
@@ -651,7 +777,6 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id)
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t *scene_id)
 {
     if (perch_status st = enter(ctx)) return st;
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!d || !scene_id) return fail(PERCH_EINVAL, "null descriptor or scene_id");
     const perch_intrinsics &K = d->K;
     if (K.width < 1 || K.width > 4096 || K.height < 1 || K.height > 4096)
@@ -679,29 +804,37 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
 
     SceneRec r;
     const int bw = (W + kBlockPx - 1) / kBlockPx, bh = (H + kBlockPx - 1) / kBlockPx;
-    perch_status st = PERCH_OK;
-    auto A = [&](DevBuf &b, size_t n) {
-        if (st == PERCH_OK) st = ctx->alloc(b, n);
-    };
-    A(r.depth, N * 2);
-    A(r.oxy, N * sizeof(int2));
-    A(r.oblk, (size_t)bw * bh * 4);
-    A(r.kx, W * 8);
-    A(r.ky, H * 8);
-    if (use_rgb) {
-        A(r.rgb, N * 3);
-        A(r.olab, N * sizeof(float4));
-    }
-    if (d->labels) A(r.labels, N * 4);
     DevBuf tmp;
+    // allocation and kernel launches under the context lock; uploads and
+    // waits outside it, so scoring on other streams is not held up
     auto cleanup = [&]() {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn, &tmp})
             ctx->release(*b);
     };
-    if (st != PERCH_OK) {
-        std::string msg = g_last_error;
-        cleanup();
-        return fail(st, "%s", msg.c_str());
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        perch_status st = PERCH_OK;
+        auto A = [&](DevBuf &b, size_t n) {
+            if (st == PERCH_OK) st = ctx->alloc(b, n);
+        };
+        A(r.depth, N * 2);
+        A(r.oxy, N * sizeof(int2));
+        A(r.oblk, (size_t)bw * bh * 4);
+        A(r.kx, W * 8);
+        A(r.ky, H * 8);
+        if (use_rgb) {
+            A(r.rgb, N * 3);
+            A(r.olab, N * sizeof(float4));
+        }
+        if (d->labels) A(r.labels, N * 4);
+        A(r.thdr, N * sizeof(int2));
+        A(tmp, N * 4 + 64);
+        if (st != PERCH_OK) {
+            std::string msg = g_last_error;
+            cleanup();
+            return fail(st, "%s", msg.c_str());
+        }
     }
     hipError_t e = hipMemcpy(r.depth.ptr, d->depth_mm, N * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r.kx.ptr, kx.data(), W * 8, hipMemcpyHostToDevice);
@@ -716,6 +849,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.oblk = (const uint32_t *)r.oblk.ptr;
     s.kx = (const double *)r.kx.ptr;
     s.ky = (const double *)r.ky.ptr;
+    s.thdr = (const int2 *)r.thdr.ptr;
     s.W = W;
     s.H = H;
     s.bw = bw;
@@ -749,45 +883,41 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             s.wty = std::min(H, (int)(K.fy * dl * std::sqrt(1.0 + ry * ry) / (z - dl)) + 2);
         }
     }
-    if (e == hipSuccess)
+    // points, colours, depth blocks and the nearest-neighbour table ranges
+    long long *total_dev = (long long *)((char *)tmp.ptr + N * 4);
+    long long total = 0;
+    if (e == hipSuccess) {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
-            return launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int2 *)r.oxy.ptr, (float4 *)r.olab.ptr,
-                                     (uint32_t *)r.oblk.ptr, ctx->stream);
+            hipError_t e2 = launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int2 *)r.oxy.ptr, (float4 *)r.olab.ptr,
+                                              (uint32_t *)r.oblk.ptr, ctx->stream);
+            return e2 == hipSuccess
+                       ? launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev, ctx->stream)
+                       : e2;
         });
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, total_dev, 8, hipMemcpyDeviceToHost, ctx->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         cleanup();
         return fail(PERCH_EDEVICE, "scene upload / preparation: %s", hipGetErrorString(e));
     }
-    // nearest-neighbour table of the observed cloud
-    if ((st = ctx->alloc(r.thdr, N * sizeof(int2))) || (st = ctx->alloc(tmp, N * 4 + 64))) {
-        std::string msg = g_last_error;
-        cleanup();
-        return fail(st, "%s", msg.c_str());
-    }
-    s.thdr = (const int2 *)r.thdr.ptr;
-    long long *total_dev = (long long *)((char *)tmp.ptr + N * 4);
-    long long total = 0;
-    e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
-        return launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev, ctx->stream);
-    });
-    if (e == hipSuccess) e = hipMemcpyAsync(&total, total_dev, 8, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) {
-        cleanup();
-        return fail(PERCH_EDEVICE, "scene table ranges: %s", hipGetErrorString(e));
-    }
-    ctx->release(tmp);
     if (total >= (1LL << 31) - 1) {
         cleanup();
         return fail(PERCH_ENOMEM, "scene neighbour table too large (%lld entries)", total);
     }
-    if ((st = ctx->alloc(r.tnn, (size_t)std::max(total, 1LL) * 4))) {
-        std::string msg = g_last_error;
-        cleanup();
-        return fail(st, "%s", msg.c_str());
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        ctx->release(tmp);
+        if (perch_status st = ctx->alloc(r.tnn, (size_t)std::max(total, 1LL) * 4)) {
+            std::string msg = g_last_error;
+            cleanup();
+            return fail(st, "%s", msg.c_str());
+        }
+        s.tnn = (const int32_t *)r.tnn.ptr;
+        e = ctx->timed(kProfScenePrep, ctx->stream,
+                       [&] { return launch_table_fill(s, (int32_t *)r.tnn.ptr, ctx->stream); });
     }
-    s.tnn = (const int32_t *)r.tnn.ptr;
-    e = ctx->timed(kProfScenePrep, ctx->stream, [&] { return launch_table_fill(s, (int32_t *)r.tnn.ptr, ctx->stream); });
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         cleanup();
@@ -796,6 +926,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
     r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.oxy.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
               + r.ky.bytes + r.thdr.bytes + r.tnn.bytes;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     const int32_t id = ctx->next_scene++;
     ctx->scenes[id] = std::move(r);
     *scene_id = id;
@@ -809,10 +940,10 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     auto it = ctx->scenes.find(scene_id);
     if (it == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
     if (perch_status st = release_check(ctx, true, scene_id)) return st;
-    (void)hipDeviceSynchronize();
     SceneRec &r = it->second;
+    FenceRef f = ctx->fence_of(r.uses);
     for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
-        ctx->release(*b);
+        ctx->release(*b, f);
     ctx->scenes.erase(it);
     return ok();
 }
@@ -824,7 +955,7 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
     if (perch_status st = enter(ctx)) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
-    perch_status s = run_direct(ctx, &item, 1, pick_stream(ctx, hip_stream), nullptr);
+    perch_status s = run_direct(ctx, &item, 1, pick_stream(ctx, hip_stream), false);
     return s ? s : ok();
 }
 
@@ -832,7 +963,7 @@ perch_status perch_score_batch(perch_ctx *ctx, const perch_work *items, int32_t 
 {
     if (perch_status st = enter(ctx)) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    perch_status s = run_direct(ctx, items, n_items, pick_stream(ctx, hip_stream), nullptr);
+    perch_status s = run_direct(ctx, items, n_items, pick_stream(ctx, hip_stream), false);
     return s ? s : ok();
 }
 
@@ -841,35 +972,41 @@ perch_status perch_best_poses(perch_ctx *ctx, int32_t scene_id, int32_t n_obj, c
                               int32_t *best_idx_host, int32_t *best_cost_host, void *hip_stream)
 {
     if (perch_status st = enter(ctx)) return st;
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (n_obj < 1) return fail(PERCH_EINVAL, "n_obj must be >= 1");
     if (!mesh_ids || !labels || !poses_dev || !n_poses || !best_idx_host || !best_cost_host)
         return fail(PERCH_EINVAL, "null argument");
-    int32_t total = 0;
-    for (int32_t k = 0; k < n_obj; ++k) {
+    for (int32_t k = 0; k < n_obj; ++k)
         if (n_poses[k] < 1) return fail(PERCH_EINVAL, "object %d has no poses", k);
-        total = std::max(total, n_poses[k]);
-    }
     hipStream_t st = pick_stream(ctx, hip_stream);
-    // J_r / J_o land in a per-stream scratch area; only the minima return
-    StreamBufs &sb = ctx->work[st];
-    size_t need = 0;
-    for (int32_t k = 0; k < n_obj; ++k) need += (size_t)n_poses[k] * 8;
-    if (perch_status s0 = ctx->ensure(sb.tmp, need)) return s0;
-    std::vector<perch_work> items((size_t)n_obj);
-    int32_t *base = (int32_t *)sb.tmp.ptr;
-    size_t off = 0;
-    for (int32_t k = 0; k < n_obj; ++k) {
-        items[k] = perch_work{scene_id, mesh_ids[k], labels[k], n_poses[k], poses_dev[k], base + off,
-                              base + off + n_poses[k], nullptr, nullptr};
-        off += 2 * (size_t)n_poses[k];
+    int n_items = 0;
+    std::vector<int> item_of_req;
+    const int32_t *best_dev = nullptr;
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        // J_r / J_o land in a per-stream scratch area; only the minima return
+        StreamBufs &sb = ctx->work[st];
+        size_t need = 0;
+        for (int32_t k = 0; k < n_obj; ++k) need += (size_t)n_poses[k] * 8;
+        if (perch_status s0 = ctx->ensure(sb.tmp, need)) return s0;
+        std::vector<perch_work> items((size_t)n_obj);
+        int32_t *base = (int32_t *)sb.tmp.ptr;
+        size_t off = 0;
+        for (int32_t k = 0; k < n_obj; ++k) {
+            items[k] = perch_work{scene_id, mesh_ids[k], labels[k], n_poses[k], poses_dev[k], base + off,
+                                  base + off + n_poses[k], nullptr, nullptr};
+            off += 2 * (size_t)n_poses[k];
+        }
+        if (perch_status s = run_direct(ctx, items.data(), n_obj, st, true, &n_items, &item_of_req)) return s;
+        best_dev = (const int32_t *)sb.lb.best.ptr;
     }
-    (void)total;
-    std::vector<int32_t> best((size_t)2 * n_obj);
-    if (perch_status s = run_direct(ctx, items.data(), n_obj, st, best.data())) return s;
+    // wait without the lock, then fetch the minima
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> res((size_t)2 * n_items);
+    HIP_TRY(hipMemcpy(res.data(), best_dev, res.size() * 4, hipMemcpyDeviceToHost));
     for (int32_t k = 0; k < n_obj; ++k) {
-        best_idx_host[k] = best[2 * k];
-        best_cost_host[k] = best[2 * k + 1];
+        const int it = item_of_req[k];
+        best_idx_host[k] = it >= 0 ? res[2 * it] : -1;
+        best_cost_host[k] = it >= 0 ? res[2 * it + 1] : -1;
     }
     return ok();
 }
@@ -894,6 +1031,8 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, con
         return launch_render(s, mi->second.dev, poses_dev, n, (uint32_t *)b.lb.scratch.ptr, depth_dev, rgb_dev,
                              tri_dev, st);
     }));
+    ctx->mark_use(si->second.uses, st);
+    ctx->mark_use(mi->second.uses, st);
     return ok();
 }
 
@@ -920,6 +1059,37 @@ perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_m
         total_ms[k] = k < kNumProfSlots ? ctx->total_ms[k] : 0.0;
         launches[k] = k < kNumProfSlots ? ctx->launches[k] : 0;
     }
+    return ok();
+}
+
+perch_status perch_set_tuning(perch_ctx *ctx, const perch_tuning *t)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!t) {
+        ctx->tune = perch_tuning{};
+        return ok();
+    }
+    if (t->small_block != 0 && t->small_block != 256 && t->small_block != 512)
+        return fail(PERCH_EINVAL, "small_block must be 0, 256 or 512 (got %d)", t->small_block);
+    if (t->small_words < 0) return fail(PERCH_EINVAL, "small_words must be >= 0");
+    for (int k = 0; k < kNumClasses; ++k)
+        if (t->grid[k] < 0) return fail(PERCH_EINVAL, "grid[%d] must be >= 0", k);
+    if (t->order < 0 || t->order > 2) return fail(PERCH_EINVAL, "order must be 0, 1 or 2");
+    ctx->tune = *t;
+    return ok();
+}
+
+perch_status perch_get_tuning(perch_ctx *ctx, perch_tuning *out)
+{
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!out) return fail(PERCH_EINVAL, "null output");
+    const LaunchCfg c = launch_cfg(ctx);
+    out->small_block = c.small_block;
+    out->small_words = c.cap_small;
+    for (int k = 0; k < kNumClasses; ++k) out->grid[k] = c.grid[k];
+    out->order = c.sort ? 2 : 1;
     return ok();
 }
 
@@ -1025,11 +1195,11 @@ perch_status perch_batch_set(perch_batch *b, const perch_work *items, int32_t n_
     if (!b) return fail(PERCH_EINVAL, "null batch");
     perch_ctx *ctx = b->ctx;
     if (perch_status st = enter(ctx)) return st;
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (b->pending) {
         HIP_TRY(hipEventSynchronize(b->done));
         b->pending = false;
     }
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     Built d;
     if (perch_status s = build_descriptors(ctx, items, n_items, d, b->cap_items)) {
         b->valid = false;
@@ -1054,13 +1224,15 @@ perch_status perch_batch_launch(perch_batch *b, void *hip_stream)
     if (!b) return fail(PERCH_EINVAL, "null batch");
     perch_ctx *ctx = b->ctx;
     if (perch_status st = enter(ctx)) return st;
+    if (b->pending) HIP_TRY(hipEventSynchronize(b->done));
+    b->pending = false;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!b->valid) return fail(PERCH_EINVAL, "batch has no valid work (set it again)");
-    if (b->pending) HIP_TRY(hipEventSynchronize(b->done));
     hipStream_t st = pick_stream(ctx, hip_stream);
     HIP_TRY(hipGraphLaunch(b->exec, st));
     HIP_TRY(hipEventRecord(b->done, st));
     b->pending = true;
+    mark_uses(ctx, b->scene_ids, b->mesh_ids, st);
     return ok();
 }
 
@@ -1069,7 +1241,6 @@ perch_status perch_batch_wait(perch_batch *b, int32_t *best_idx_host, int32_t *b
     if (!b) return fail(PERCH_EINVAL, "null batch");
     perch_ctx *ctx = b->ctx;
     if (perch_status st = enter(ctx)) return st;
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!b->pending) return fail(PERCH_EINVAL, "batch was not launched");
     HIP_TRY(hipEventSynchronize(b->done));
     b->pending = false;
@@ -1080,6 +1251,19 @@ perch_status perch_batch_wait(perch_batch *b, int32_t *best_idx_host, int32_t *b
         if (best_cost_host) best_cost_host[r] = it >= 0 ? res[2 * it + 1] : -1;
     }
     return ok();
+}
+
+perch_status perch_batch_query(perch_batch *b)
+{
+    if (!b) return fail(PERCH_EINVAL, "null batch");
+    if (!b->pending) return ok();
+    const hipError_t e = hipEventQuery(b->done);
+    if (e == hipSuccess) return ok();
+    if (e == hipErrorNotReady) {
+        g_last_error = "batch still running";
+        return PERCH_EBUSY;
+    }
+    return fail(PERCH_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
 }
 
 perch_status perch_batch_destroy(perch_batch *b)

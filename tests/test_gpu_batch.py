@@ -136,3 +136,70 @@ def test_cfg4_subset_batched_equals_plain(ctx):
     bi, bc = b.wait()
     assert list(zip(bi, bc)) == plain
     b.close()
+
+
+def test_tuning_never_changes_results(ctx, mixed):
+    """Every autotuner candidate (work-group size, class threshold, grids,
+    work order) gives the default launch's outputs bit for bit."""
+    from paper_2008_00326_amd import autotune
+    say("tuning invariance")
+    def with_counts():
+        return [dict(it, nr=torch.empty(it["poses"].shape[0], dtype=torch.int32, device="cuda"),
+                     nq=torch.empty(it["poses"].shape[0], dtype=torch.int32, device="cuda")) for it in mixed]
+
+    ctx.set_tuning(None)
+    ref = [[t.cpu().numpy() for t in (o["jr"], o["jo"], o["nr"], o["nq"])] for o in ctx.score_batch(with_counts())]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for cand in autotune.candidates(ctx.tuning(), n_cu) + [{"grid": [3, 2, 1, 1], "order": 1}]:
+        ctx.set_tuning(cand)
+        out = ctx.score_batch(with_counts())
+        torch.cuda.synchronize()
+        for o, r in zip(out, ref):
+            for key, a in zip(("jr", "jo", "nr", "nq"), r):
+                assert np.array_equal(o[key].cpu().numpy(), a), (cand, key)
+    ctx.set_tuning(None)
+    with pytest.raises(pk.PerchError):
+        ctx.set_tuning({"small_block": 384})
+    with pytest.raises(pk.PerchError):
+        ctx.set_tuning({"order": 3})
+
+
+def test_scene_prepared_while_batch_runs_and_memory_reused(ctx):
+    """A scene prepared on another thread while a graph batch scores, then
+    dropped and replaced without any device-wide wait: every result equals
+    the one computed in isolation."""
+    import threading
+    say("concurrent prep / reuse")
+    w2 = make_config(2, 1)
+    w3 = make_config(3, 1)
+    sid2, mids2 = pk.load_workload(ctx, w2)
+    o = w2.objects[0]
+    poses2 = torch.from_numpy(o.poses[:3000]).cuda()
+    ref2 = alone(ctx, {"scene": sid2, "mesh": mids2[o.mesh], "label": o.label, "poses": poses2})
+    # reference of the second scene, prepared with nothing else running
+    sid3, mids3 = pk.load_workload(ctx, w3)
+    objs3 = [(mids3[q.mesh], q.label, torch.from_numpy(q.poses[:256]).cuda()) for q in w3.objects]
+    ref3 = ctx.best_poses(sid3, [m for m, _, _ in objs3], [l for _, l, _ in objs3], [p for _, _, p in objs3])
+    ctx.drop_scene(sid3)
+    b = ctx.batch(max_items=2, max_poses=4096, max_image_pixels=640 * 480)
+    items = b.set([{"scene": sid2, "mesh": mids2[o.mesh], "label": o.label, "poses": poses2}])
+    side = torch.cuda.Stream()
+    got = {}
+
+    def prep():
+        s3 = w3.scene
+        got["sid"] = ctx.set_scene(s3.K, s3.depth, s3.rgb, delta_mm=w3.delta_mm, tau_c=w3.tau_c)
+
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            b.launch(side)
+        t = threading.Thread(target=prep)
+        t.start()
+        b.wait()
+        t.join()
+        assert np.array_equal(items[0]["jr"].cpu().numpy(), ref2[0]) and np.array_equal(items[0]["jo"].cpu().numpy(), ref2[1])
+        res = ctx.best_poses(got["sid"], [m for m, _, _ in objs3], [l for _, l, _ in objs3], [p for _, _, p in objs3])
+        assert [list(r) for r in res] == [list(r) for r in ref3], rep
+        ctx.drop_scene(got["sid"])     # released without a wait; the next prep may reuse its memory
+    b.close()
+    ctx.drop_scene(sid2)

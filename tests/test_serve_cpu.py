@@ -1,0 +1,185 @@
+"""The serving loop's policy on the CPU: a fake executor stands in for the
+device (a serial device that takes a fixed time per pose, preparation that
+takes a fixed time), so admission, batching, failure isolation and latency
+bookkeeping are checked without a GPU."""
+import threading
+import time
+
+import pytest
+
+from paper_2008_00326_amd.serve import OutOfMemory, Request, Server, latency_stats
+
+
+class FakeExecutor:
+    def __init__(self, slots=2, per_pose_s=2e-6, prep_s=0.002, fail_launch_on=None):
+        self.slots = slots
+        self.per_pose_s = per_pose_s
+        self.prep_s = prep_s
+        self.fail_launch_on = fail_launch_on or set()
+        self.lock = threading.Lock()
+        self.device_free_at = 0.0
+        self.slot_end = {}
+        self.slot_handles = {}
+        self.launches = []
+        self.live_bytes = 0
+        self.max_live_bytes = 0
+        self.released = []
+        self.oom_once = set()
+
+    def footprint(self, req):
+        return req.payload["bytes"]
+
+    def prepare(self, req):
+        from paper_2008_00326_amd.serve import Prepared
+        p = req.payload
+        time.sleep(self.prep_s)
+        if p.get("fail_prepare"):
+            raise ValueError("bad scene")
+        if p.get("oom_first") and req.rid not in self.oom_once:
+            self.oom_once.add(req.rid)
+            raise OutOfMemory("device full")
+        with self.lock:
+            self.live_bytes += p["bytes"]
+            self.max_live_bytes = max(self.max_live_bytes, self.live_bytes)
+        return Prepared(req, req, len(p["answer"]), req.n_poses, p["bytes"])
+
+    def launch(self, slot, handles):
+        n = len(self.launches)
+        self.launches.append([h.rid for h in handles])
+        if n in self.fail_launch_on:
+            raise RuntimeError("launch failed")
+        now = time.perf_counter()
+        start = max(now, self.device_free_at)           # a serial device: queued behind earlier launches
+        end = start + self.per_pose_s * sum(h.n_poses for h in handles)
+        self.device_free_at = end
+        self.slot_end[slot] = end
+        self.slot_handles[slot] = handles
+
+    def done(self, slot):
+        return time.perf_counter() >= self.slot_end[slot]
+
+    def wait(self, slot):
+        d = self.slot_end[slot] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        return [list(h.payload["answer"]) for h in self.slot_handles[slot]]
+
+    def release(self, h):
+        with self.lock:
+            self.live_bytes -= h.payload["bytes"]
+        self.released.append(h.rid)
+
+
+def make_req(rid, poses=1000, nbytes=100, n_obj=3, **extra):
+    payload = {"bytes": nbytes, "answer": [(rid, 10 * rid + k) for k in range(n_obj)], **extra}
+    return Request(rid, payload, poses)
+
+
+def serve(ex, reqs, *, budget=10_000, max_items=64, max_poses=100_000, spacing=0.0):
+    srv = Server(ex, budget_bytes=budget, max_items=max_items, max_poses=max_poses)
+
+    def producer():
+        for r in reqs:
+            srv.submit(r)
+            if spacing:
+                time.sleep(spacing)
+        srv.close()
+
+    t = threading.Thread(target=producer)
+    t.start()
+    done = srv.run()
+    t.join()
+    return srv, done
+
+
+def test_every_request_answered_with_its_own_result():
+    ex = FakeExecutor()
+    reqs = [make_req(i) for i in range(40)]
+    srv, done = serve(ex, reqs, spacing=0.0005)
+    assert sorted(r.rid for r in done) == list(range(40))
+    for r in done:
+        assert r.error is None and r.result == r.payload["answer"]
+        assert r.arrival <= r.admitted <= r.ready <= r.launched <= r.done
+    assert sorted(ex.released) == list(range(40))
+    assert srv.inflight_bytes == 0 and ex.live_bytes == 0
+
+
+def test_admission_respects_budget_and_arrival_order():
+    ex = FakeExecutor(per_pose_s=2e-5)
+    reqs = [make_req(i, nbytes=300) for i in range(20)]
+    srv, done = serve(ex, reqs, budget=1000)              # at most three in flight
+    assert ex.max_live_bytes <= 1000 and srv.peak_bytes <= 1000
+    adm = sorted(done, key=lambda r: r.admitted)
+    assert [r.rid for r in adm] == list(range(20))        # first come, first admitted
+
+
+def test_arrivals_join_later_batches():
+    """With a slow device, requests arriving while a batch runs are launched
+    together: fewer launches than requests, and no launch over capacity."""
+    ex = FakeExecutor(per_pose_s=1e-5, prep_s=0.0005)
+    reqs = [make_req(i, poses=2000) for i in range(30)]
+    srv, done = serve(ex, reqs, max_poses=12_000, spacing=0.001)
+    assert len(done) == 30
+    assert len(ex.launches) < 30
+    assert max(len(g) for g in ex.launches) > 1
+    for _, n, poses in srv.batches:
+        assert poses <= 12_000
+    # each request is scored exactly once
+    assert sorted(x for g in ex.launches for x in g) == list(range(30))
+
+
+def test_failures_stay_with_their_request():
+    ex = FakeExecutor(fail_launch_on={2})
+    reqs = [make_req(i) for i in range(12)]
+    reqs[5].payload["fail_prepare"] = True
+    srv, done = serve(ex, reqs, spacing=0.002)
+    assert len(done) == 12
+    failed_launch = set(ex.launches[2])
+    for r in done:
+        if r.rid == 5:
+            assert r.error and "bad scene" in r.error
+        elif r.rid in failed_launch:
+            assert r.error and "launch failed" in r.error
+        else:
+            assert r.error is None and r.result == r.payload["answer"]
+    assert srv.inflight_bytes == 0
+
+
+def test_oversized_request_rejected_and_oom_retried():
+    ex = FakeExecutor(per_pose_s=1e-5)
+    reqs = [make_req(0), make_req(1, nbytes=50_000), make_req(2, oom_first=True), make_req(3, poses=10**6),
+            make_req(4)]
+    srv, done = serve(ex, reqs, budget=10_000, max_poses=100_000, spacing=0.003)
+    by = {r.rid: r for r in done}
+    assert len(by) == 5
+    assert by[1].error and "budget" in by[1].error
+    assert by[3].error and "capacity" in by[3].error
+    for k in (0, 4):
+        assert by[k].result == by[k].payload["answer"]
+    # the request that hit OutOfMemory is either retried after others finished, or
+    # reported when nothing in flight could free memory -- never lost
+    assert by[2].result == by[2].payload["answer"] or "OutOfMemory" in (by[2].error or "")
+
+
+def test_oom_with_work_in_flight_is_retried():
+    ex = FakeExecutor(per_pose_s=5e-5, prep_s=0.0)
+    reqs = [make_req(0, poses=4000), make_req(1, oom_first=True)]
+    srv, done = serve(ex, reqs, spacing=0.002)
+    by = {r.rid: r for r in done}
+    assert by[1].result == by[1].payload["answer"], by[1].error
+
+
+def test_latency_stats_counts_unfinished_as_lower_bounds():
+    a, b, c = Request(0, None, 1, arrival=0.0), Request(1, None, 1, arrival=0.0), Request(2, None, 1, arrival=1.0)
+    a.done, b.done = 0.010, 0.020
+    st = latency_stats([a, b, c], horizon=3.0)
+    assert st["completed"] == 2 and st["unfinished"] == 1
+    assert st["p50"] == pytest.approx(20.0) and st["p99"] > 1900.0   # the unfinished one waited >= 2 s
+    assert latency_stats([a, b])["p50"] == pytest.approx(15.0)
+
+
+def test_closed_server_refuses_submissions():
+    srv = Server(FakeExecutor(), budget_bytes=10, max_items=1, max_poses=1)
+    srv.close()
+    with pytest.raises(RuntimeError):
+        srv.submit(make_req(0))
