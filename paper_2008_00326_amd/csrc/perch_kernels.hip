@@ -1,22 +1,22 @@
 // gfx950 kernels for PERCH 2.0 pose scoring.
 //
 // Per candidate pose (Sec. IV-A "Parallel Rendering" / "Parallel Cost
-// Computation", Eq. 1-4):
-//   1. rasterize the mesh into an LDS-resident tile of 32-bit keys
-//      (depth mm << 16 | triangle index), min-combined with ds_min_u32;
+// Computation", Eq. 1-4), one work-group:
+//   1. rasterize the mesh into a tile of 32-bit keys (depth mm << 16 |
+//      triangle index) in LDS, min-combined with ds_min_u32;
 //   2. resolve: drop occluders (Eq. 3, C from the observed depth) and pixels
 //      off the downsampling grid;
-//   3. J_r: radius / nearest-neighbour search of each rendered point in the
-//      observed cloud, restricted to the pixel window that can hold a point
-//      within delta and pruned by per-8x8-block depth ranges;
-//   4. J_o: for each observed pixel inside V(O), the same search against the
-//      rendered tile;
+//   3. J_r: each rendered point's nearest observed point within delta is one
+//      lookup in the scene's nearest-neighbour table; every inlier then
+//      marks the observed points within delta of it with its (squared
+//      distance, index) key, one wave per inlier;
+//   4. J_o: an observed point inside V(O) is explained iff it was marked, and
+//      its key names its nearest rendered point;
 //   5. RGB mode: CIEDE2000 of each point against its nearest neighbour
-//      (Eq. 4), in binary32;
+//      (Eq. 4), in binary32, over dense queues;
 //   6. wave ballot + popcount of the outlier predicates.
-// Geometry and depth use integer / binary64 arithmetic that is reproduced
-// exactly by the CPU reference (no FMA contraction: built with
-// -ffp-contract=off).
+// Geometry and depth use integer / binary64 arithmetic that the oracle
+// reproduces exactly (no FMA contraction: built with -ffp-contract=off).
 
 #include "perch_internal.h"
 
@@ -25,6 +25,38 @@
 namespace perch {
 
 __constant__ float c_lin[256];   // sRGB8 -> linear, rounded from binary64
+
+// Load through a global-address-space pointer: the scene, mesh and pose
+// arrays are reached through descriptors in device memory, which the
+// compiler would otherwise access with flat instructions.
+#define PERCH_GLOBAL __attribute__((address_space(1)))
+typedef int perch_v2i __attribute__((ext_vector_type(2)));
+typedef int perch_v4i __attribute__((ext_vector_type(4)));
+typedef float perch_v4f __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T gld(const T *p)
+{
+    return *(const PERCH_GLOBAL T *)p;
+}
+template <>
+__device__ __forceinline__ int2 gld(const int2 *p)
+{
+    const perch_v2i v = *(const PERCH_GLOBAL perch_v2i *)p;
+    return make_int2(v.x, v.y);
+}
+template <>
+__device__ __forceinline__ int4 gld(const int4 *p)
+{
+    const perch_v4i v = *(const PERCH_GLOBAL perch_v4i *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+template <>
+__device__ __forceinline__ float4 gld(const float4 *p)
+{
+    const perch_v4f v = *(const PERCH_GLOBAL perch_v4f *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
 
 // ------------------------------------------------------------------ geometry
 
@@ -94,10 +126,10 @@ __device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev
                                                 int t, int tx0, int ty0, int tw, int th,
                                                 uint32_t *tile)
 {
-    const int4 ix = m.tris[t];
-    const Vtx a = project_vertex(P, m.verts[ix.x], s);
-    const Vtx b = project_vertex(P, m.verts[ix.y], s);
-    const Vtx c = project_vertex(P, m.verts[ix.z], s);
+    const int4 ix = gld(m.tris + t);
+    const Vtx a = project_vertex(P, gld(m.verts + ix.x), s);
+    const Vtx b = project_vertex(P, gld(m.verts + ix.y), s);
+    const Vtx c = project_vertex(P, gld(m.verts + ix.z), s);
     if (!(a.ok & b.ok & c.ok)) return;
     const long long area = edge_fn(a.U, a.V, b.U, b.V, c.U, c.V);
     if (area <= 0) return;
@@ -142,17 +174,17 @@ __device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev
 __device__ uint32_t triangle_colour(const SceneDev &s, const MeshDev &m, const float *P, int t, int i, int j)
 {
     if (t < 0 || t >= m.nt) return 0;
-    const int4 ix = m.tris[t];
-    const Vtx a = project_vertex(P, m.verts[ix.x], s);
-    const Vtx b = project_vertex(P, m.verts[ix.y], s);
-    const Vtx c = project_vertex(P, m.verts[ix.z], s);
+    const int4 ix = gld(m.tris + t);
+    const Vtx a = project_vertex(P, gld(m.verts + ix.x), s);
+    const Vtx b = project_vertex(P, gld(m.verts + ix.y), s);
+    const Vtx c = project_vertex(P, gld(m.verts + ix.z), s);
     const long long px = 256LL * i, py = 256LL * j;
     const long long w0 = edge_fn(b.U, b.V, c.U, c.V, px, py);
     const long long w1 = edge_fn(c.U, c.V, a.U, a.V, px, py);
     const long long w2 = edge_fn(a.U, a.V, b.U, b.V, px, py);
     const double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
     const double sum = (t0 + t1) + t2;
-    const uint32_t ca = m.vrgb[ix.x], cb = m.vrgb[ix.y], cc = m.vrgb[ix.z];
+    const uint32_t ca = gld(m.vrgb + ix.x), cb = gld(m.vrgb + ix.y), cc = gld(m.vrgb + ix.z);
     uint32_t out = 0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -294,10 +326,9 @@ __device__ __forceinline__ void mark_one(const SceneDev &s, int dp, int2 xy, int
     using K = KeyOf<G>;
     const int dz = 16 * dp - Z;
     const int dx = xy.x - X, dy = xy.y - Y;
-    if (dp == 0 || max(max(abs(dz), abs(dx)), abs(dy)) > s.dq) return;
-    const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
-    if (d2 > s.dq2) return;
-    K::min(key, K::make(d2, k));
+    const int m = max(max(abs(dz), abs(dx)), abs(dy));
+    const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);   // used only when m <= dq
+    if (dp != 0 && m <= s.dq && d2 <= s.dq2) K::min(key, K::make(d2, k));
 }
 
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
@@ -306,7 +337,7 @@ __device__ __forceinline__ void mark_one(const SceneDev &s, int dp, int2 xy, int
 // marks the points that r explains (Eq. 3) and, over all r, leaves each
 // observed point's nearest rendered neighbour (Eq. 4).  The lanes cover
 // whole window rows at a time (64 / width rows per round, so a lane keeps
-// its column and steps its row by a constant), two rounds per iteration
+// its column and steps its row by a constant), four rounds per iteration
 // with every load issued before use; windows wider than a wave are walked
 // in row-major order, four pixels per lane per round.
 template <bool G>
@@ -331,15 +362,30 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
         int pix = (j0 + r) * s.W + i0 + c;
         int kk = (j0 + r - jy0) * jw + (i0 + c - jx0);
         int row = r;
-        for (; row + rows < wh; row += 2 * rows) {
-            const int dp0 = s.depth[pix], dp1 = s.depth[pix + step];
-            const int2 q0 = s.oxy[pix], q1 = s.oxy[pix + step];
-            mark_one<G>(s, dp0, q0, X, Y, Z, k, keys + kk);
-            mark_one<G>(s, dp1, q1, X, Y, Z, k, keys + kk + kstep);
-            pix += 2 * step;
-            kk += 2 * kstep;
+        for (; row + 3 * rows < wh; row += 4 * rows) {
+            int dp[4];
+            int2 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                dp[u] = gld(s.depth + pix + u * step);
+                q[u] = gld(s.oxy + pix + u * step);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mark_one<G>(s, dp[u], q[u], X, Y, Z, k, keys + kk + u * kstep);
+            pix += 4 * step;
+            kk += 4 * kstep;
         }
-        if (row < wh) mark_one<G>(s, s.depth[pix], s.oxy[pix], X, Y, Z, k, keys + kk);
+        int dp[3];
+        int2 q[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const bool in = row + u * rows < wh;
+            dp[u] = in ? (int)gld(s.depth + pix + u * step) : 0;
+            q[u] = in ? gld(s.oxy + pix + u * step) : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            if (row + u * rows < wh) mark_one<G>(s, dp[u], q[u], X, Y, Z, k, keys + kk + u * kstep);
         return;
     }
     const int ws = ww * wh;
@@ -355,8 +401,8 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
             py[u] = j0 + qy;
             const bool in = q < ws;
             const int pix = in ? py[u] * s.W + px[u] : 0;
-            dp[u] = in ? (int)s.depth[pix] : 0;
-            xy[u] = in ? s.oxy[pix] : make_int2(0, 0);
+            dp[u] = in ? (int)gld(s.depth + pix) : 0;
+            xy[u] = in ? gld(s.oxy + pix) : make_int2(0, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -434,7 +480,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 keep = (i % s.stride == 0) && (j % s.stride == 0);
                 if (keep && mark) {
                     const int pix = j * s.W + i;
-                    const int dob = s.depth[pix];
+                    const int dob = gld(s.depth + pix);
                     if (dob > 0 && 16 * dob + s.dq < 16 * d) {
                         if (!(label_mode && s.labels) || s.labels[pix] != it.label) keep = false;
                     }
@@ -460,9 +506,9 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             const uint32_t key = tld<G>(tile + k);
             if (key != kEmptyKey) {
                 const int ty = k / in.tw, tx = k - ty * in.tw;
-                const int2 th = s.thdr[(in.ty0 + ty) * s.W + in.tx0 + tx];
+                const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
                 const int e = (int)(key >> 16) - (th.y & 0xFFFF);
-                const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? s.tnn[th.x + e] : -1;
+                const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
                 miss = nn < 0;
                 if (nn >= 0 && (rgb || jpx > 0)) {
                     const int slot = atomicAdd(qn, 1);
@@ -489,7 +535,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 const uint32_t key = tld<G>(tile + kk);
                 const int ty = kk / in.tw, tx = kk - ty * in.tw;
                 const float4 lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                out = ciede2000(lr, s.olab[queue2[tid]]) > s.tau;
+                out = ciede2000(lr, gld(s.olab + queue2[tid])) > s.tau;
             }
             cR += wave_popc(out);
         }
@@ -513,10 +559,10 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             const int vy = k / in.vw, vx = k - vy * in.vw;
             const int i = in.vx0 + vx, j = in.vy0 + vy;
             const int pix = j * s.W + i;
-            const int dp = s.depth[pix];
+            const int dp = gld(s.depth + pix);
             if (dp > 0) {
-                const int2 q = s.oxy[pix];
-                inq = label_mode ? (s.labels[pix] == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
+                const int2 q = gld(s.oxy + pix);
+                inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
                 typename K::T nk = K::kEmpty;
                 const int jx = i - in.jx0, jy = j - in.jy0;
                 if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < in.jh) nk = K::load(keys + jy * in.jw + jx);
@@ -540,7 +586,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 const int ty = kr / in.tw, tx = kr - ty * in.tw;
                 const float4 lr =
                     srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                cout = ciede2000(s.olab[pix], lr) > s.tau;
+                cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
             }
             cO += wave_popc(cout);
             __syncthreads();
@@ -908,9 +954,9 @@ __global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tn
         for (int q = lane; q < ws; q += 64) {
             const int qy = window_row(q, ww, inv);
             const int pix = (j0 + qy) * s.W + i0 + (q - qy * ww);
-            const int dp = s.depth[pix];
+            const int dp = gld(s.depth + pix);
             if (dp == 0 || dp < dlo || dp > dhi) continue;
-            const int2 xy = s.oxy[pix];
+            const int2 xy = gld(s.oxy + pix);
             const int ea = max(dp - s.dzmm, dmin) - dmin, eb = min(dp + s.dzmm, dmax) - dmin;
             for (int e = ea; e <= eb; ++e) {
                 const int dz = 16 * dp - 16 * (dmin + e);
