@@ -9,6 +9,7 @@ namespace perch {
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 constexpr int kBlockPx = 8;         // side of the depth-range blocks (pixels)
 constexpr int kMaxTris = 65535;     // triangle index lives in 16 bits of the key
+constexpr int kNoPoint = -(1 << 28); // Zq of a pixel without a depth reading: never within delta
 constexpr int kNumClasses = 4;      // LDS small, LDS large, LDS tile + device keys, device memory
 constexpr int kNumBuckets = 16;     // cost buckets of the per-class work order
 // Launch counters (ints): per-class pose counts, per-class work cursors,
@@ -27,7 +28,7 @@ struct PoseInfo {
 
 struct SceneDev {
     const uint16_t *depth;   // H*W mm
-    const int2 *oxy;         // H*W (Xq, Yq) in 1/16 mm
+    const int4 *opt;         // H*W (Xq, Yq, Zq, 0) in 1/16 mm; Zq = kNoPoint without a reading
     const float4 *olab;      // H*W CIELAB (RGB scenes) or null
     const int32_t *labels;   // H*W or null
     const uint32_t *oblk;    // bw*bh: min depth | max depth << 16 of valid pixels
@@ -102,7 +103,7 @@ hipError_t upload_colour_table(const float *lin256);
 // 256-, 512- and 1024-thread kernels (the largest over their variants).
 hipError_t prepare_score_kernels(int lds_per_group, int static_bytes[3]);
 
-hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *oxy, float4 *olab,
+hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *opt, float4 *olab,
                              uint32_t *oblk, hipStream_t st);
 // Nearest-neighbour table of the observed cloud: per pixel the depth range
 // that can have an observed point within delta, then one entry per depth.

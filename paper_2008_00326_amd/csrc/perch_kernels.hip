@@ -316,19 +316,19 @@ template <> struct KeyOf<true> {
     __device__ static void store(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 };
 
-// Key update of observed pixel (px, py) by rendered point (X, Y, Z) with
-// tile index k, if the two lie within delta; dq < 2^13, so the 24-bit
-// products are exact.
+// Key update of an observed point q by rendered point (X, Y, Z) with tile
+// index k, if the two lie within delta; dq < 2^13, so the 24-bit products
+// are exact.
 template <bool G>
-__device__ __forceinline__ void mark_one(const SceneDev &s, int dp, int2 xy, int X, int Y, int Z, int k,
+__device__ __forceinline__ void mark_one(const SceneDev &s, int4 q, int X, int Y, int Z, int k,
                                          typename KeyOf<G>::T *key)
 {
     using K = KeyOf<G>;
-    const int dz = 16 * dp - Z;
-    const int dx = xy.x - X, dy = xy.y - Y;
+    const int dz = q.z - Z;                 // pixels without a reading fail by far (kNoPoint)
+    const int dx = q.x - X, dy = q.y - Y;
     const int m = max(max(abs(dz), abs(dx)), abs(dy));
     const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);   // used only when m <= dq
-    if (dp != 0 && m <= s.dq && d2 <= s.dq2) K::min(key, K::make(d2, k));
+    if (m <= s.dq && d2 <= s.dq2) K::min(key, K::make(d2, k));
 }
 
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
@@ -363,50 +363,40 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
         int kk = (j0 + r - jy0) * jw + (i0 + c - jx0);
         int row = r;
         for (; row + 3 * rows < wh; row += 4 * rows) {
-            int dp[4];
-            int2 q[4];
+            int4 q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                dp[u] = gld(s.depth + pix + u * step);
-                q[u] = gld(s.oxy + pix + u * step);
-            }
+            for (int u = 0; u < 4; ++u) q[u] = gld(s.opt + pix + u * step);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) mark_one<G>(s, dp[u], q[u], X, Y, Z, k, keys + kk + u * kstep);
+            for (int u = 0; u < 4; ++u) mark_one<G>(s, q[u], X, Y, Z, k, keys + kk + u * kstep);
             pix += 4 * step;
             kk += 4 * kstep;
         }
-        int dp[3];
-        int2 q[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const bool in = row + u * rows < wh;
-            dp[u] = in ? (int)gld(s.depth + pix + u * step) : 0;
-            q[u] = in ? gld(s.oxy + pix + u * step) : make_int2(0, 0);
-        }
+        int4 q[3];
 #pragma unroll
         for (int u = 0; u < 3; ++u)
-            if (row + u * rows < wh) mark_one<G>(s, dp[u], q[u], X, Y, Z, k, keys + kk + u * kstep);
+            q[u] = row + u * rows < wh ? gld(s.opt + pix + u * step) : make_int4(0, 0, kNoPoint, 0);
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            if (row + u * rows < wh) mark_one<G>(s, q[u], X, Y, Z, k, keys + kk + u * kstep);
         return;
     }
     const int ws = ww * wh;
     const float inv = 1.0f / (float)ww;
     for (int q0 = 0; q0 < ws; q0 += 256) {
-        int dp[4], px[4], py[4];
-        int2 xy[4];
+        int px[4], py[4];
+        int4 qv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int q = q0 + 64 * u + lane;
             const int qy = window_row(q, ww, inv);
             px[u] = i0 + (q - qy * ww);
             py[u] = j0 + qy;
-            const bool in = q < ws;
-            const int pix = in ? py[u] * s.W + px[u] : 0;
-            dp[u] = in ? (int)gld(s.depth + pix) : 0;
-            xy[u] = in ? gld(s.oxy + pix) : make_int2(0, 0);
+            qv[u] = q < ws ? gld(s.opt + py[u] * s.W + px[u]) : make_int4(0, 0, kNoPoint, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (dp[u] != 0) mark_one<G>(s, dp[u], xy[u], X, Y, Z, k, keys + (py[u] - jy0) * jw + (px[u] - jx0));
+            if (q0 + 64 * u + lane < ws)
+                mark_one<G>(s, qv[u], X, Y, Z, k, keys + (py[u] - jy0) * jw + (px[u] - jx0));
     }
 }
 
@@ -559,9 +549,9 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             const int vy = k / in.vw, vx = k - vy * in.vw;
             const int i = in.vx0 + vx, j = in.vy0 + vy;
             const int pix = j * s.W + i;
-            const int dp = gld(s.depth + pix);
-            if (dp > 0) {
-                const int2 q = gld(s.oxy + pix);
+            const int4 q = gld(s.opt + pix);
+            if (q.z != kNoPoint) {
+                const int dp = q.z >> 4;
                 inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
                 typename K::T nk = K::kEmpty;
                 const int jx = i - in.jx0, jy = j - in.jy0;
@@ -798,18 +788,19 @@ __global__ void order_kernel(Work w)
 
 // ------------------------------------------------------------------ scene prep
 
-__global__ void scene_points_kernel(SceneDev s, const uint8_t *rgb, int2 *oxy, float4 *olab)
+__global__ void scene_points_kernel(SceneDev s, const uint8_t *rgb, int4 *opt, float4 *olab)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= s.W * s.H) return;
     const int j = k / s.W, i = k - j * s.W;
     const int d = s.depth[k];
-    int2 q = make_int2(0, 0);
+    int4 q = make_int4(0, 0, kNoPoint, 0);
     if (d > 0) {
         q.x = (int)rint(s.kx[i] * (double)d);
         q.y = (int)rint(s.ky[j] * (double)d);
+        q.z = 16 * d;
     }
-    oxy[k] = q;
+    opt[k] = q;
     if (olab) {
         const uint32_t c = (uint32_t)rgb[3 * (size_t)k] | ((uint32_t)rgb[3 * (size_t)k + 1] << 8)
                            | ((uint32_t)rgb[3 * (size_t)k + 2] << 16);
@@ -954,9 +945,9 @@ __global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tn
         for (int q = lane; q < ws; q += 64) {
             const int qy = window_row(q, ww, inv);
             const int pix = (j0 + qy) * s.W + i0 + (q - qy * ww);
-            const int dp = gld(s.depth + pix);
-            if (dp == 0 || dp < dlo || dp > dhi) continue;
-            const int2 xy = gld(s.oxy + pix);
+            const int4 xy = gld(s.opt + pix);
+            const int dp = xy.z >> 4;
+            if (xy.z == kNoPoint || dp < dlo || dp > dhi) continue;
             const int ea = max(dp - s.dzmm, dmin) - dmin, eb = min(dp + s.dzmm, dmax) - dmin;
             for (int e = ea; e <= eb; ++e) {
                 const int dz = 16 * dp - 16 * (dmin + e);
@@ -1069,11 +1060,11 @@ hipError_t upload_colour_table(const float *lin256)
     return hipMemcpyToSymbol(HIP_SYMBOL(c_lin), lin256, 256 * sizeof(float));
 }
 
-hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int2 *oxy, float4 *olab, uint32_t *oblk,
+hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *opt, float4 *olab, uint32_t *oblk,
                              hipStream_t st)
 {
     const int N = s.W * s.H;
-    scene_points_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, rgb_dev, oxy, olab);
+    scene_points_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, rgb_dev, opt, olab);
     const int nb = s.bw * s.bh;
     scene_blocks_kernel<<<(nb + 255) / 256, 256, 0, st>>>(s, oblk);
     return hipGetLastError();

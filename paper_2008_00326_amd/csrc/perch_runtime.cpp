@@ -78,7 +78,7 @@ struct MeshRec {
 };
 
 struct SceneRec {
-    DevBuf depth, rgb, labels, oxy, olab, oblk, kx, ky, thdr, tnn;
+    DevBuf depth, rgb, labels, opt, olab, oblk, kx, ky, thdr, tnn;
     SceneDev dev{};
     std::vector<int32_t> host_labels;
     std::map<int32_t, std::vector<int>> label_boxes;
@@ -663,7 +663,7 @@ perch_status perch_destroy(perch_ctx *ctx)
     for (auto &kv : ctx->scenes) {
         SceneRec &r = kv.second;
         FenceRef f = ctx->fence_of(r.uses);
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
             ctx->release(*b, f);
     }
     while (!ctx->batches.empty()) perch_batch_destroy(ctx->batches.back());
@@ -809,7 +809,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     // waits outside it, so scoring on other streams is not held up
     auto cleanup = [&]() {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn, &tmp})
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn, &tmp})
             ctx->release(*b);
     };
     {
@@ -819,7 +819,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             if (st == PERCH_OK) st = ctx->alloc(b, n);
         };
         A(r.depth, N * 2);
-        A(r.oxy, N * sizeof(int2));
+        A(r.opt, N * sizeof(int4));
         A(r.oblk, (size_t)bw * bh * 4);
         A(r.kx, W * 8);
         A(r.ky, H * 8);
@@ -843,7 +843,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (e == hipSuccess && d->labels) e = hipMemcpy(r.labels.ptr, d->labels, N * 4, hipMemcpyHostToDevice);
     SceneDev &s = r.dev;
     s.depth = (const uint16_t *)r.depth.ptr;
-    s.oxy = (const int2 *)r.oxy.ptr;
+    s.opt = (const int4 *)r.opt.ptr;
     s.olab = (const float4 *)r.olab.ptr;
     s.labels = (const int32_t *)r.labels.ptr;
     s.oblk = (const uint32_t *)r.oblk.ptr;
@@ -889,7 +889,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (e == hipSuccess) {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
-            hipError_t e2 = launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int2 *)r.oxy.ptr, (float4 *)r.olab.ptr,
+            hipError_t e2 = launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int4 *)r.opt.ptr, (float4 *)r.olab.ptr,
                                               (uint32_t *)r.oblk.ptr, ctx->stream);
             return e2 == hipSuccess
                        ? launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev, ctx->stream)
@@ -924,7 +924,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         return fail(PERCH_EDEVICE, "scene table fill: %s", hipGetErrorString(e));
     }
     if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
-    r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.oxy.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
+    r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.opt.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
               + r.ky.bytes + r.thdr.bytes + r.tnn.bytes;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     const int32_t id = ctx->next_scene++;
@@ -942,7 +942,7 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     if (perch_status st = release_check(ctx, true, scene_id)) return st;
     SceneRec &r = it->second;
     FenceRef f = ctx->fence_of(r.uses);
-    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.oxy, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
+    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
         ctx->release(*b, f);
     ctx->scenes.erase(it);
     return ok();
