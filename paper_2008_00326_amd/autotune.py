@@ -4,7 +4,8 @@ The scoring launch has a few free choices that never change a result, only
 how the poses are spread over the persistent kernels: the work-group size of
 the smallest LDS footprint class (256 or 512 threads), the LDS threshold
 that sends a pose to that class, the number of persistent work-groups per
-class, and whether each class scores its costliest poses first.  The tuner
+class, whether each class scores its costliest poses first, and whether J_o
+regions too large for LDS are keyed in device memory or in LDS row bands.  The tuner
 times a small candidate set on a sample of the caller's work and keeps the
 fastest, cached as JSON keyed by the device architecture and a shape bucket
 (image size, mean mesh size, poses per item, colour term).
@@ -48,6 +49,8 @@ def candidates(defaults: dict, n_cu: int):
                 out.append(c)
     # fewer concurrent device-key work-groups (less L2 pressure)
     out.append({"small_block": 512, "order": 2, "grid": [0, 0, max(n_cu // 2, 1), 0], "small_words": 0})
+    # large J_o regions keyed in device memory instead of LDS bands
+    out.append({"small_block": 512, "order": 2, "grid": [0, 0, 0, 0], "small_words": 0, "key_bands": 1})
     return out
 
 

@@ -317,18 +317,21 @@ template <> struct KeyOf<true> {
 };
 
 // Key update of an observed point q by rendered point (X, Y, Z) with tile
-// index k, if the two lie within delta; dq < 2^13, so the 24-bit products
-// are exact.
+// index k, if the two lie within delta; dq + 1 < 2^13, so the 24-bit
+// products are exact.
 template <bool G>
 __device__ __forceinline__ void mark_one(const SceneDev &s, int4 q, int X, int Y, int Z, int k,
                                          typename KeyOf<G>::T *key)
 {
     using K = KeyOf<G>;
-    const int dz = q.z - Z;                 // pixels without a reading fail by far (kNoPoint)
-    const int dx = q.x - X, dy = q.y - Y;
-    const int m = max(max(abs(dz), abs(dx)), abs(dy));
-    const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);   // used only when m <= dq
-    if (m <= s.dq && d2 <= s.dq2) K::min(key, K::make(d2, k));
+    // each offset clamped to [-(dq + 1), dq + 1]: a clamped one alone makes
+    // d2 exceed dq^2, and unclamped ones give the exact d2
+    const int lim = s.dq + 1;
+    const int dz = min(max(q.z - Z, -lim), lim);   // pixels without a reading clamp (kNoPoint)
+    const int dx = min(max(q.x - X, -lim), lim);
+    const int dy = min(max(q.y - Y, -lim), lim);
+    const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
+    if (d2 <= s.dq2) K::min(key, K::make(d2, k));
 }
 
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
