@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=3, help="timed passes of the batched leg of a plain run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg of a plain run")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default ~/.cache/perch)")
+    ap.add_argument("--tuning", default=None,
+                    help="launch tuning of the plain path as JSON, e.g. '{\"key_bands\": 1}' (results never change)")
     ap.add_argument("--rates", default="20,50,100", help="config 5: arrival rates, scenes/s")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="config 5: arrival window per rate")
     ap.add_argument("--seed", type=int, default=0)
@@ -130,6 +132,8 @@ def main():
     w = make_config(args.config, args.seed)
     dev = torch.device("cuda:0")
     ctx = pk.Context(0)
+    if args.tuning:
+        ctx.set_tuning(json.loads(args.tuning))
     stream = torch.cuda.current_stream(dev)
 
     t0 = time.perf_counter()
@@ -229,14 +233,19 @@ def main():
                      "unit": "TOP/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 5),
                      "traffic": measured_traffic(dom), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4), "launches": dom_launches,
-                     "hbm_achieved_GBs": round(hbm_gbs, 2), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 6)},
+                     "hbm_achieved_GBs": round(hbm_gbs, 2), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 6),
+                     "valu_issue_frac": (round(measured_counters(dom)["valu_frac_of_39.3T"], 4)
+                                         if measured_counters(dom) and "valu_frac_of_39.3T" in measured_counters(dom)
+                                         else None)},
         "kernels_ms": {k: round(v[0] / max(args.steps, 1), 4) for k, v in prof.items() if v[1]},
+        "tuning": ctx.tuning(),
         "poses_per_class": class_poses,
         "kernel_source_sha": kernel_source_sha(),
     }
 
     if not args.no_batched:
         ctx.drop_scene(sid)
+        ctx.set_tuning(None)
         result["batched"] = batched_vs_plain(ctx, args.seed, args.batched_steps, 1, args.batched_scenes,
                                              args.tune_cache)
     if not args.no_cpu_baseline:
@@ -431,17 +440,23 @@ def kernel_source_sha():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_slot):
-    """HBM bytes per launch of the kernel from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def measured_counters(kernel_slot):
+    """The committed counter record of the kernel (HBM bytes per launch from
+    FETCH_SIZE / WRITE_SIZE scaled by a plain copy, executed VALU
+    instructions), or None when the kernel source changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", "score_kernel_cfg2_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha") != kernel_source_sha():
         return None
-    k = rec.get("kernels", {}).get(kernel_slot)
-    if not k:
+    return rec.get("kernels", {}).get(kernel_slot)
+
+
+def measured_traffic(kernel_slot):
+    k = measured_counters(kernel_slot)
+    if not k or k.get("fetch_bytes_per_launch") is None or k.get("write_bytes_per_launch") is None:
         return None
     return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"], 1)
 

@@ -221,6 +221,9 @@ perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int
  *                 as are resident at once on the device).
  *   order:        1 = each class scores its poses in set-up order, 2 = its
  *                 costliest poses first (0 = 2).
+ *   key_bands:    for poses whose J_o keys do not fit in LDS beside the
+ *                 raster tile: 1 = keys in device memory, 2 = keys in LDS,
+ *                 one band of rows at a time (0 = 2).
  * The setting applies to launches enqueued afterwards, and to batches
  * created afterwards (a batch keeps the setting it was created with).
  * NULL restores the defaults.  perch_get_tuning returns the values in force,
@@ -230,6 +233,7 @@ typedef struct {
     int32_t small_words;
     int32_t grid[4];
     int32_t order;
+    int32_t key_bands;
 } perch_tuning;
 perch_status perch_set_tuning(perch_ctx *ctx, const perch_tuning *tuning);
 perch_status perch_get_tuning(perch_ctx *ctx, perch_tuning *out);

@@ -51,7 +51,7 @@ class _Work(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("small_block", ctypes.c_int32), ("small_words", ctypes.c_int32), ("grid", ctypes.c_int32 * 4),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("key_bands", ctypes.c_int32)]
 
 
 class _SceneDesc(ctypes.Structure):
@@ -249,13 +249,15 @@ class Context:
         for k, g in enumerate(tuning.get("grid", (0, 0, 0, 0))):
             t.grid[k] = int(g)
         t.order = int(tuning.get("order", 0))
+        t.key_bands = int(tuning.get("key_bands", 0))
         _check(self._lib.perch_set_tuning(self._h, ctypes.byref(t)))
 
     def tuning(self) -> dict:
         """The launch tuning in force, defaults resolved."""
         t = _Tuning()
         _check(self._lib.perch_get_tuning(self._h, ctypes.byref(t)))
-        return {"small_block": t.small_block, "small_words": t.small_words, "grid": list(t.grid), "order": t.order}
+        return {"small_block": t.small_block, "small_words": t.small_words, "grid": list(t.grid), "order": t.order,
+                "key_bands": t.key_bands}
 
     PROFILE_SLOTS = ("setup", "score_lds_small", "score_lds_large", "score_lds_tile", "score_device", "argmin",
                      "scene_prep", "render")

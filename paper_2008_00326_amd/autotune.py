@@ -5,10 +5,10 @@ how the poses are spread over the persistent kernels: the work-group size of
 the smallest LDS footprint class (256 or 512 threads), the LDS threshold
 that sends a pose to that class, the number of persistent work-groups per
 class, whether each class scores its costliest poses first, and whether J_o
-regions too large for LDS are keyed in device memory or in LDS row bands.  The tuner
-times a small candidate set on a sample of the caller's work and keeps the
-fastest, cached as JSON keyed by the device architecture and a shape bucket
-(image size, mean mesh size, poses per item, colour term).
+regions too large for LDS are keyed in device memory or in LDS row bands.
+The tuner times a small candidate set on a sample of the caller's work and
+keeps the fastest, cached as JSON keyed by the device architecture and a
+shape bucket (image size, mean mesh size, poses per item, colour term).
 """
 from __future__ import annotations
 

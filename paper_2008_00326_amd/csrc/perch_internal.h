@@ -34,6 +34,8 @@ struct SceneDev {
     const uint32_t *oblk;    // bw*bh: min depth | max depth << 16 of valid pixels
     const double *kx;        // W: 16 (i - cx) / fx
     const double *ky;        // H: 16 (j - cy) / fy
+    const float *ax;         // W: f (delta + 1/4) sqrt(1 + ((i - cx) / fx)^2), rounded up
+    const float *ay;         // H: the same for rows
     const int2 *thdr;        // H*W nearest-neighbour table header: {first entry, lo | n << 16}
     const int32_t *tnn;      // entry (pixel, lo + e): nearest observed pixel within delta, -1 none
     int W, H, bw, bh;
@@ -80,6 +82,7 @@ struct Work {
     int *lists;              // kNumClasses * cap_poses global pose indices
     int *counts;             // kCounterInts launch counters (layout above)
     int sort;                // order each class list costliest first
+    int key_bands;           // J_o regions too large for LDS are keyed in bands of rows (class 1)
     uint32_t *gscratch;      // device-memory slots of classes 2 (keys) and 3 (tile + keys)
     size_t slot_base[kNumClasses];   // first word of each class's slots
     size_t slot_words[kNumClasses];  // words per work-group slot
@@ -95,6 +98,7 @@ struct LaunchCfg {
     int cap_large;      // classes 1 and 2 (class 2: tile only)
     int grid[kNumClasses];
     int sort;           // cost-ordered class lists
+    int key_bands;      // banded J_o keys in LDS instead of device-memory keys
 };
 
 hipError_t upload_colour_table(const float *lin256);

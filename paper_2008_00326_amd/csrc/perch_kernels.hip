@@ -272,16 +272,32 @@ __device__ float ciede2000(float4 x, float4 y)
 
 // ------------------------------------------------------------------ search
 
-// Largest pixel offset along one axis between a point at lateral offset
-// `lat` mm and depth `z` mm and any point within `dl` mm of it:
-// f dl sqrt(lat^2 + z^2) / (z (z - dl)), plus one pixel of slack.
-__device__ __forceinline__ int window_half(float f, float lat, float z, float dl, int limit)
+// Largest pixel offset along one axis between a point on the ray of pixel
+// column (row) i at depth z mm and any point within dl = delta + 1/4 mm of
+// it: f dl sqrt(1 + ((i - c) / f)^2) / (z - dl) = a[i] / (z - dl), plus one
+// pixel of slack; `inv` = 1 / (z - dl).
+__device__ __forceinline__ int window_half(float a, float inv, int limit)
 {
-    if (!(z > dl + 1.0f)) return limit;
-    const float bnd = f * dl * sqrtf(lat * lat + z * z) / (z * (z - dl));
+    const float bnd = a * inv;
     if (!(bnd < (float)limit)) return limit;
     return (int)bnd + 1;
 }
+
+// 1 / (z - dl) for window_half, or infinity when z is too close to the
+// camera for a bound (window_half then returns its limit).
+__device__ __forceinline__ float window_inv(int z, float dl)
+{
+    const float den = (float)z - dl;
+    return den > 1.0f ? 1.0f / den : INFINITY;
+}
+
+// ceil(2^16 / w) for w = 1..64: lane / w = (lane * c_rcp16[w]) >> 16 exactly
+// for lane < 64.
+__constant__ uint32_t c_rcp16[65] = {
+    0,    65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554, 5958, 5462, 5042, 4682, 4370, 4096,
+    3856, 3641,  3450,  3277,  3121,  2979,  2850,  2731, 2622, 2521, 2428, 2341, 2260, 2185, 2115, 2048, 1986,
+    1928, 1873,  1821,  1772,  1725,  1681,  1639,  1599, 1561, 1525, 1490, 1457, 1425, 1395, 1366, 1338, 1311,
+    1286, 1261,  1237,  1214,  1192,  1171,  1150,  1130, 1111, 1093, 1075, 1058, 1041, 1024};
 
 // Row of entry q of a row-major window ww pixels wide: a binary32 estimate
 // corrected to the exact quotient.
@@ -319,19 +335,26 @@ template <> struct KeyOf<true> {
 // Key update of an observed point q by rendered point (X, Y, Z) with tile
 // index k, if the two lie within delta; dq + 1 < 2^13, so the 24-bit
 // products are exact.
+// v_med3_i32 as a clamp (lo <= hi).
+__device__ __forceinline__ int clamp_i32(int x, int lo, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
 template <bool G>
-__device__ __forceinline__ void mark_one(const SceneDev &s, int4 q, int X, int Y, int Z, int k,
+__device__ __forceinline__ void mark_one(int4 q, int X, int Y, int Z, int k, int lim, int dq2,
                                          typename KeyOf<G>::T *key)
 {
     using K = KeyOf<G>;
     // each offset clamped to [-(dq + 1), dq + 1]: a clamped one alone makes
     // d2 exceed dq^2, and unclamped ones give the exact d2
-    const int lim = s.dq + 1;
-    const int dz = min(max(q.z - Z, -lim), lim);   // pixels without a reading clamp (kNoPoint)
-    const int dx = min(max(q.x - X, -lim), lim);
-    const int dy = min(max(q.y - Y, -lim), lim);
+    const int dz = clamp_i32(q.z - Z, -lim, lim);   // pixels without a reading clamp (kNoPoint)
+    const int dx = clamp_i32(q.x - X, -lim, lim);
+    const int dy = clamp_i32(q.y - Y, -lim, lim);
     const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
-    if (d2 <= s.dq2) K::min(key, K::make(d2, k));
+    if (d2 <= dq2) K::min(key, K::make(d2, k));
 }
 
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
@@ -349,17 +372,19 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
 {
     const int X = (int)rint(s.kx[i] * (double)d);
     const int Y = (int)rint(s.ky[j] * (double)d);
-    const float dl = s.delta + 0.25f;
-    const int wu = window_half(s.fx, (float)X * 0.0625f, (float)d, dl, s.W);
-    const int wv = window_half(s.fy, (float)Y * 0.0625f, (float)d, dl, s.H);
+    const float iz = window_inv(d, s.delta + 0.25f);
+    const int wu = window_half(gld(s.ax + i), iz, s.W);
+    const int wv = window_half(gld(s.ay + j), iz, s.H);
     const int i0 = max(max(i - wu, 0), jx0), i1 = min(min(i + wu, s.W - 1), jx0 + jw - 1);
     const int j0 = max(max(j - wv, 0), jy0), j1 = min(min(j + wv, s.H - 1), jy0 + jh - 1);
     if (i0 > i1 || j0 > j1) return;
     const int ww = i1 - i0 + 1, wh = j1 - j0 + 1;
     const int Z = 16 * d;
+    const int lim = s.dq + 1, dq2 = s.dq2;
     if (ww <= 64) {
-        const int rows = 64 / ww;
-        const int r = lane / ww, c = lane - r * ww;
+        const uint32_t rc = c_rcp16[ww];
+        const int rows = (int)((64u * rc) >> 16);
+        const int r = (int)(((uint32_t)lane * rc) >> 16), c = lane - r * ww;
         if (r >= rows) return;
         const int step = rows * s.W, kstep = rows * jw;
         int pix = (j0 + r) * s.W + i0 + c;
@@ -370,7 +395,7 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = gld(s.opt + pix + u * step);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) mark_one<G>(s, q[u], X, Y, Z, k, keys + kk + u * kstep);
+            for (int u = 0; u < 4; ++u) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk + u * kstep);
             pix += 4 * step;
             kk += 4 * kstep;
         }
@@ -380,7 +405,7 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
             q[u] = row + u * rows < wh ? gld(s.opt + pix + u * step) : make_int4(0, 0, kNoPoint, 0);
 #pragma unroll
         for (int u = 0; u < 3; ++u)
-            if (row + u * rows < wh) mark_one<G>(s, q[u], X, Y, Z, k, keys + kk + u * kstep);
+            if (row + u * rows < wh) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk + u * kstep);
         return;
     }
     const int ws = ww * wh;
@@ -399,7 +424,7 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typenam
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (q0 + 64 * u + lane < ws)
-                mark_one<G>(s, qv[u], X, Y, Z, k, keys + (py[u] - jy0) * jw + (px[u] - jx0));
+                mark_one<G>(qv[u], X, Y, Z, k, lim, dq2, keys + (py[u] - jy0) * jw + (px[u] - jx0));
     }
 }
 
@@ -433,9 +458,9 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const PoseInfo in = w.info[p];
-    const ItemDev it = w.items[in.item];
-    const SceneDev s = w.scenes[it.scene];
-    const MeshDev m = w.meshes[it.mesh];
+    const ItemDev &it = w.items[in.item];
+    const SceneDev &s = w.scenes[it.scene];
+    const MeshDev &m = w.meshes[it.mesh];
     const bool rgb = RGB && (s.flags & 1u) != 0;
     float P[12];
 #pragma unroll
@@ -445,8 +470,9 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     const bool mark = (s.flags & 2u) != 0;
     const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
 
+    const int band0 = (!G && !KG && BLOCK == 1024 && tpx + jpx > w.cap_large) ? (w.cap_large - tpx) : jpx;
     for (int k = tid; k < tpx; k += BLOCK) tst<G>(tile + k, kEmptyKey);
-    for (int k = tid; k < jpx; k += BLOCK) K::store(keys + k, K::kEmpty);
+    for (int k = tid; k < min(jpx, band0); k += BLOCK) K::store(keys + k, K::kEmpty);
     if (tid < 4) cnt[tid] = 0;
     __syncthreads();
 
@@ -485,104 +511,127 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     }
     __syncthreads();
 
-    // 3. J_r: nearest observed neighbour from the scene table.  The inliers
-    //    of each chunk go to a workgroup queue: every wave takes queue items
-    //    in turn and marks the observed points each one explains, then the
-    //    colour test of Eq. 4 runs densely over the queue.
-    int cR = 0;
-    for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
-        const int k = k0 + tid;
-        if (tid == 0) *qn = 0;
-        __syncthreads();
-        bool miss = false;
-        if (k < tpx) {
-            const uint32_t key = tld<G>(tile + k);
-            if (key != kEmptyKey) {
-                const int ty = k / in.tw, tx = k - ty * in.tw;
-                const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
-                const int e = (int)(key >> 16) - (th.y & 0xFFFF);
-                const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
-                miss = nn < 0;
-                if (nn >= 0 && (rgb || jpx > 0)) {
-                    const int slot = atomicAdd(qn, 1);
-                    queue[slot] = k;
-                    queue2[slot] = nn;
-                }
-            }
-        }
-        cR += wave_popc(miss);
-        __syncthreads();
-        const int nq = *qn;
-        if (jpx > 0) {
-            for (int t = wave; t < nq; t += NW) {
-                const int kk = queue[t];
-                const int ty = kk / in.tw, tx = kk - ty * in.tw;
-                const int dd = (int)(tld<G>(tile + kk) >> 16);
-                wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, in.jy0, in.jw, in.jh, lane);
-            }
-        }
-        if (rgb) {
-            bool out = false;
-            if (tid < nq) {
-                const int kk = queue[tid];
-                const uint32_t key = tld<G>(tile + kk);
-                const int ty = kk / in.tw, tx = kk - ty * in.tw;
-                const float4 lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                out = ciede2000(lr, gld(s.olab + queue2[tid])) > s.tau;
-            }
-            cR += wave_popc(out);
-        }
-        __syncthreads();
-    }
-
-    // 4. J_o: observed points in V(O); explained iff some rendered point
-    //    keyed it.  In RGB mode the key names the nearest rendered point and
-    //    the explained points of each chunk are queued for a dense colour test.
-    int cQ = 0, cO = 0;
-    const int vpx = in.vw * in.vh;
+    // J_o keys held at once: the whole J_o region, or, for a pose of the
+    // 1024-thread LDS class whose region does not fit beside its tile, bands
+    // of rows; phases 3 and 4 then run once per band, every inlier marking
+    // the band's keys, and the J_r counts are taken in the first band.
+    int hb = in.jh;
+    if (!G && !KG && BLOCK == 1024 && in.jw > 0 && tpx + jpx > w.cap_large) hb = (w.cap_large - tpx) / in.jw;
+    const int nb = in.jh > 0 ? (in.jh + hb - 1) / hb : 1;
+    int cR = 0, cQ = 0, cO = 0;
     const double dl = (double)s.delta;
-    for (int k0 = 0; k0 < vpx; k0 += BLOCK) {
-        const int k = k0 + tid;
-        if (rgb) {
+    for (int b = 0; b < nb; ++b) {
+        const bool first = b == 0;
+        const int by0 = in.jy0 + b * hb;
+        const int bh = in.jh > 0 ? min(hb, in.jy0 + in.jh - by0) : 0;
+        const int bpx = in.jw * bh;
+        if (!first) {
+            __syncthreads();
+            for (int k = tid; k < bpx; k += BLOCK) K::store(keys + k, K::kEmpty);
+            __syncthreads();
+        }
+
+        // 3. J_r: nearest observed neighbour from the scene table.  The
+        //    inliers of each chunk go to a workgroup queue: every wave takes
+        //    queue items in turn and marks the observed points each one
+        //    explains, then the colour test of Eq. 4 runs densely over the queue.
+        for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
+            const int k = k0 + tid;
             if (tid == 0) *qn = 0;
             __syncthreads();
-        }
-        bool inq = false, out = false;
-        if (k < vpx) {
-            const int vy = k / in.vw, vx = k - vy * in.vw;
-            const int i = in.vx0 + vx, j = in.vy0 + vy;
-            const int pix = j * s.W + i;
-            const int4 q = gld(s.opt + pix);
-            if (q.z != kNoPoint) {
-                const int dp = q.z >> 4;
-                inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
-                typename K::T nk = K::kEmpty;
-                const int jx = i - in.jx0, jy = j - in.jy0;
-                if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < in.jh) nk = K::load(keys + jy * in.jw + jx);
-                out = inq && nk == K::kEmpty;
-                if (rgb && inq && nk != K::kEmpty) {
-                    const int slot = atomicAdd(qn, 1);
-                    queue[slot] = pix;
-                    queue2[slot] = K::index(nk);
+            bool miss = false;
+            if (k < tpx) {
+                const uint32_t key = tld<G>(tile + k);
+                if (key != kEmptyKey) {
+                    const int ty = k / in.tw, tx = k - ty * in.tw;
+                    const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
+                    const int e = (int)(key >> 16) - (th.y & 0xFFFF);
+                    const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
+                    miss = first && nn < 0;
+                    if (nn >= 0 && ((rgb && first) || bpx > 0)) {
+                        const int slot = atomicAdd(qn, 1);
+                        queue[slot] = k;
+                        queue2[slot] = nn;
+                    }
                 }
             }
-        }
-        cQ += wave_popc(inq);
-        cO += wave_popc(out);
-        if (rgb) {
+            cR += wave_popc(miss);
             __syncthreads();
             const int nq = *qn;
-            bool cout = false;
-            if (tid < nq) {
-                const int pix = queue[tid], kr = queue2[tid];
-                const uint32_t key = tld<G>(tile + kr);
-                const int ty = kr / in.tw, tx = kr - ty * in.tw;
-                const float4 lr =
-                    srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
+            if (bpx > 0) {
+                for (int t = wave; t < nq; t += NW) {
+                    const int kk = queue[t];
+                    const int ty = kk / in.tw, tx = kk - ty * in.tw;
+                    const int dd = (int)(tld<G>(tile + kk) >> 16);
+                    wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, by0, in.jw, bh, lane);
+                }
             }
-            cO += wave_popc(cout);
+            if (rgb && first) {
+                bool out = false;
+                if (tid < nq) {
+                    const int kk = queue[tid];
+                    const uint32_t key = tld<G>(tile + kk);
+                    const int ty = kk / in.tw, tx = kk - ty * in.tw;
+                    const float4 lr =
+                        srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                    out = ciede2000(lr, gld(s.olab + queue2[tid])) > s.tau;
+                }
+                cR += wave_popc(out);
+            }
             __syncthreads();
+        }
+
+        // 4. J_o: observed points in V(O); explained iff some rendered point
+        //    keyed it.  In RGB mode the key names the nearest rendered point
+        //    and the explained points of each chunk are queued for a dense
+        //    colour test.  V rows above the J_o region go with the first band,
+        //    rows below it with the last.
+        const int ra = first ? in.vy0 : by0;
+        const int rb = b == nb - 1 ? in.vy0 + in.vh : by0 + bh;
+        const int rpx = max(rb - ra, 0) * in.vw;
+        for (int k0 = 0; k0 < rpx; k0 += BLOCK) {
+            const int k = k0 + tid;
+            if (rgb) {
+                if (tid == 0) *qn = 0;
+                __syncthreads();
+            }
+            bool inq = false, out = false;
+            if (k < rpx) {
+                const int vy = k / in.vw, vx = k - vy * in.vw;
+                const int i = in.vx0 + vx, j = ra + vy;
+                const int pix = j * s.W + i;
+                const int4 q = gld(s.opt + pix);
+                if (q.z != kNoPoint) {
+                    const int dp = q.z >> 4;
+                    inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
+                    typename K::T nk = K::kEmpty;
+                    const int jx = i - in.jx0, jy = j - by0;
+                    if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < bh) nk = K::load(keys + jy * in.jw + jx);
+                    out = inq && nk == K::kEmpty;
+                    if (rgb && inq && nk != K::kEmpty) {
+                        const int slot = atomicAdd(qn, 1);
+                        queue[slot] = pix;
+                        queue2[slot] = K::index(nk);
+                    }
+                }
+            }
+            cQ += wave_popc(inq);
+            cO += wave_popc(out);
+            if (rgb) {
+                __syncthreads();
+                const int nq = *qn;
+                bool cout = false;
+                if (tid < nq) {
+                    const int pix = queue[tid], kr = queue2[tid];
+                    const uint32_t key = tld<G>(tile + kr);
+                    const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                    const float4 lr =
+                        srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                    cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
+                }
+                cO += wave_popc(cout);
+                __syncthreads();
+            }
         }
     }
 
@@ -757,7 +806,10 @@ __global__ void setup_kernel(Work w)
     const int tile_words = in.tw * in.th;
     const int words = tile_words + in.jw * in.jh;
     int cls = tile_words <= w.cap_large ? 2 : 3;
-    if (it.key32 && words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
+    if (it.key32) {
+        if (words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
+        else if (w.key_bands && tile_words + in.jw <= w.cap_large) cls = 1;   // J_o keys in bands of rows
+    }
     if (w.sort) {
         const int order = cls * kNumBuckets + cost_bucket(tile_words, in.jw * in.jh, m.nt);
         w.info[p].order = order;
@@ -936,9 +988,9 @@ __global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tn
         }
         wave_lds_sync();
         // the window of the pass's smallest depth is the widest one
-        const int Xmin = (int)rint(kxi * (double)dmin), Ymin = (int)rint(kyj * (double)dmin);
-        const int wu = window_half(s.fx, (float)Xmin * 0.0625f, (float)dmin, dl, s.W);
-        const int wvv = window_half(s.fy, (float)Ymin * 0.0625f, (float)dmin, dl, s.H);
+        const float iz = window_inv(dmin, dl);
+        const int wu = window_half(gld(s.ax + i), iz, s.W);
+        const int wvv = window_half(gld(s.ay + j), iz, s.H);
         const int i0 = max(i - wu, 0), i1 = min(i + wu, s.W - 1);
         const int j0 = max(j - wvv, 0), j1 = min(j + wvv, s.H - 1);
         const int ww = i1 - i0 + 1;

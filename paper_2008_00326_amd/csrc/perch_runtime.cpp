@@ -78,7 +78,7 @@ struct MeshRec {
 };
 
 struct SceneRec {
-    DevBuf depth, rgb, labels, opt, olab, oblk, kx, ky, thdr, tnn;
+    DevBuf depth, rgb, labels, opt, olab, oblk, kx, ky, ax, ay, thdr, tnn;
     SceneDev dev{};
     std::vector<int32_t> host_labels;
     std::map<int32_t, std::vector<int>> label_boxes;
@@ -375,6 +375,7 @@ LaunchCfg launch_cfg(const perch_ctx *ctx)
     for (int k = 0; k < kNumClasses; ++k)
         c.grid[k] = t.grid[k] > 0 ? std::min(t.grid[k], 16 * ctx->n_cu) : def[k];
     c.sort = t.order != 1;
+    c.key_bands = t.key_bands != 1;
     return c;
 }
 
@@ -545,6 +546,7 @@ Work make_work(const LaunchBufs &lb, const Built &b, int cap_poses, const Launch
     w.cap_small = cfg.cap_small;
     w.cap_large = cfg.cap_large;
     w.sort = cfg.sort;
+    w.key_bands = cfg.key_bands;
     w.best = want_best ? (int32_t *)lb.best.ptr : nullptr;
     return w;
 }
@@ -663,7 +665,8 @@ perch_status perch_destroy(perch_ctx *ctx)
     for (auto &kv : ctx->scenes) {
         SceneRec &r = kv.second;
         FenceRef f = ctx->fence_of(r.uses);
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
+                          &r.tnn})
             ctx->release(*b, f);
     }
     while (!ctx->batches.empty()) perch_batch_destroy(ctx->batches.back());
@@ -801,6 +804,22 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     std::vector<double> kx(W), ky(H);
     for (int i = 0; i < W; ++i) kx[i] = (((double)i - (double)K.cx) * 16.0) / (double)K.fx;
     for (int j = 0; j < H; ++j) ky[j] = (((double)j - (double)K.cy) * 16.0) / (double)K.fy;
+    // Window factors: a point at pixel column i and depth z has every point
+    // within delta inside ax[i] / (z - delta) + 1 columns (rows: ay).
+    std::vector<float> ax(W), ay(H);
+    auto up = [](double v) {
+        float f = (float)v;
+        return (double)f < v ? std::nextafter(f, INFINITY) : f;
+    };
+    const double dl4 = (double)d->delta_mm + 0.25;
+    for (int i = 0; i < W; ++i) {
+        const double r = ((double)i - (double)K.cx) / (double)K.fx;
+        ax[i] = up((double)K.fx * dl4 * std::sqrt(1.0 + r * r));
+    }
+    for (int j = 0; j < H; ++j) {
+        const double r = ((double)j - (double)K.cy) / (double)K.fy;
+        ay[j] = up((double)K.fy * dl4 * std::sqrt(1.0 + r * r));
+    }
 
     SceneRec r;
     const int bw = (W + kBlockPx - 1) / kBlockPx, bh = (H + kBlockPx - 1) / kBlockPx;
@@ -809,7 +828,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     // waits outside it, so scoring on other streams is not held up
     auto cleanup = [&]() {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn, &tmp})
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
+                          &r.tnn, &tmp})
             ctx->release(*b);
     };
     {
@@ -823,6 +843,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         A(r.oblk, (size_t)bw * bh * 4);
         A(r.kx, W * 8);
         A(r.ky, H * 8);
+        A(r.ax, W * 4);
+        A(r.ay, H * 4);
         if (use_rgb) {
             A(r.rgb, N * 3);
             A(r.olab, N * sizeof(float4));
@@ -839,6 +861,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     hipError_t e = hipMemcpy(r.depth.ptr, d->depth_mm, N * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r.kx.ptr, kx.data(), W * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r.ky.ptr, ky.data(), H * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r.ax.ptr, ax.data(), W * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r.ay.ptr, ay.data(), H * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess && use_rgb) e = hipMemcpy(r.rgb.ptr, d->rgb, N * 3, hipMemcpyHostToDevice);
     if (e == hipSuccess && d->labels) e = hipMemcpy(r.labels.ptr, d->labels, N * 4, hipMemcpyHostToDevice);
     SceneDev &s = r.dev;
@@ -849,6 +873,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.oblk = (const uint32_t *)r.oblk.ptr;
     s.kx = (const double *)r.kx.ptr;
     s.ky = (const double *)r.ky.ptr;
+    s.ax = (const float *)r.ax.ptr;
+    s.ay = (const float *)r.ay.ptr;
     s.thdr = (const int2 *)r.thdr.ptr;
     s.W = W;
     s.H = H;
@@ -925,7 +951,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     }
     if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
     r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.opt.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
-              + r.ky.bytes + r.thdr.bytes + r.tnn.bytes;
+              + r.ky.bytes + r.ax.bytes + r.ay.bytes + r.thdr.bytes + r.tnn.bytes;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     const int32_t id = ctx->next_scene++;
     ctx->scenes[id] = std::move(r);
@@ -942,7 +968,7 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     if (perch_status st = release_check(ctx, true, scene_id)) return st;
     SceneRec &r = it->second;
     FenceRef f = ctx->fence_of(r.uses);
-    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.thdr, &r.tnn})
+    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr, &r.tnn})
         ctx->release(*b, f);
     ctx->scenes.erase(it);
     return ok();
@@ -1076,6 +1102,7 @@ perch_status perch_set_tuning(perch_ctx *ctx, const perch_tuning *t)
     for (int k = 0; k < kNumClasses; ++k)
         if (t->grid[k] < 0) return fail(PERCH_EINVAL, "grid[%d] must be >= 0", k);
     if (t->order < 0 || t->order > 2) return fail(PERCH_EINVAL, "order must be 0, 1 or 2");
+    if (t->key_bands < 0 || t->key_bands > 2) return fail(PERCH_EINVAL, "key_bands must be 0, 1 or 2");
     ctx->tune = *t;
     return ok();
 }
@@ -1090,6 +1117,7 @@ perch_status perch_get_tuning(perch_ctx *ctx, perch_tuning *out)
     out->small_words = c.cap_small;
     for (int k = 0; k < kNumClasses; ++k) out->grid[k] = c.grid[k];
     out->order = c.sort ? 2 : 1;
+    out->key_bands = c.key_bands ? 2 : 1;
     return ok();
 }
 

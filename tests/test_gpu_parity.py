@@ -148,21 +148,37 @@ def test_sampled_poses(ctx, cfg, variant):
 
 
 def test_cfg2_full_size_sampled_outputs(ctx):
-    """All 32,000 cfg2 poses in the launch shape the benchmark uses; the
-    oracle checks a spread sample of the outputs one by one."""
+    """All 32,000 cfg2 poses in the launch shape the benchmark uses, scored
+    twice: with large J_o regions keyed in device memory (class 2) and in LDS
+    row bands (the default, class 1).  Both give identical outputs; the
+    oracle checks a spread sample one by one, including poses that take the
+    banded path."""
     w = make_config(2, 0)
     say("cfg2 full size")
     sid, mids = pk.load_workload(ctx, w)
-    outs, classes = [], []
-    for o in w.objects:
-        outs.append(gpu_score(ctx, sid, mids[o.mesh], o.poses, label=o.label))
-        classes.append(ctx.last_classes(o.poses.shape[0]))
-    seen = np.unique(np.concatenate(classes))
-    assert set(seen.tolist()) >= {0, 1, 2}, seen   # the footprint classes this workload exercises
+    runs = []
+    for bands in (1, 2):
+        ctx.set_tuning({"key_bands": bands})
+        outs, classes = [], []
+        for o in w.objects:
+            outs.append(gpu_score(ctx, sid, mids[o.mesh], o.poses, label=o.label))
+            classes.append(ctx.last_classes(o.poses.shape[0]))
+        runs.append((outs, classes))
+    ctx.set_tuning(None)
+    (outs, cls_dev), (outs_band, cls_band) = runs
+    seen = np.unique(np.concatenate(cls_dev))
+    assert set(seen.tolist()) >= {0, 1, 2}, seen      # the footprint classes this workload exercises
+    banded = [(a == 2) & (b == 1) for a, b in zip(cls_dev, cls_band)]
+    assert sum(int(x.sum()) for x in banded) > 0       # poses moved from device keys to LDS bands
+    for a, b in zip(outs, outs_band):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
     rng = np.random.default_rng(99)
-    for o, got, cls in zip(w.objects, outs, classes):
-        # two poses of every class present, plus two at random
+    for o, got, cls, bnd in zip(w.objects, outs, cls_dev, banded):
+        # two poses of every class present, up to three banded ones, plus two at random
         sel = [rng.choice(np.flatnonzero(cls == c), min(2, int((cls == c).sum())), replace=False) for c in np.unique(cls)]
+        if bnd.any():
+            sel.append(rng.choice(np.flatnonzero(bnd), min(3, int(bnd.sum())), replace=False))
         sel = np.unique(np.concatenate(sel + [rng.choice(o.poses.shape[0], 2, replace=False)]))
         exp = oracle.score(w.meshes[o.mesh], oracle_scene(w), o.poses[sel], delta_mm=w.delta_mm, tau_c=w.tau_c,
                            flags=oracle_flags(w), label=o.label, threads=THREADS)
