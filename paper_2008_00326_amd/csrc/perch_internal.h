@@ -12,10 +12,19 @@ constexpr int kMaxTris = 65535;     // triangle index lives in 16 bits of the ke
 constexpr int kNoPoint = -(1 << 28); // Zq of a pixel without a depth reading: never within delta
 constexpr int kNumClasses = 4;      // LDS small, LDS large, LDS tile + device keys, device memory
 constexpr int kNumBuckets = 16;     // cost buckets of the per-class work order
-// Launch counters (ints): per-class pose counts, per-class work cursors,
-// per-(class, bucket) counts and fill cursors of the cost-ordered lists.
-constexpr int kCntClass = 0, kCntNext = 4, kCntBucket = 8, kCntFill = kCntBucket + kNumClasses * kNumBuckets;
-constexpr int kCounterInts = 256;
+constexpr int kNumStrips = 8;       // image strips of the work order, one per XCD
+constexpr int kNumSegs = kNumClasses * kNumStrips;
+constexpr int kNumOrders = kNumSegs * kNumBuckets;
+// Launch counters (ints): per-class pose counts; per-(class, strip) work
+// cursors, segment starts and lengths in the class list; per-(class,
+// strip, bucket) counts and fill cursors of the ordered lists.
+constexpr int kCntClass = 0;
+constexpr int kCntNext = kCntClass + kNumClasses;
+constexpr int kCntSegStart = kCntNext + kNumSegs;
+constexpr int kCntSegLen = kCntSegStart + kNumSegs;
+constexpr int kCntBucket = kCntSegLen + kNumSegs;
+constexpr int kCntFill = kCntBucket + kNumOrders;
+constexpr int kCounterInts = kCntFill + kNumOrders;
 
 // Per-pose screen regions, computed by the setup kernel.
 struct PoseInfo {
@@ -23,7 +32,7 @@ struct PoseInfo {
     int vx0, vy0, vw, vh;   // region holding every observed pixel that may lie in V(O)
     int jx0, jy0, jw, jh;   // part of the V region within reach of a rendered point
     int item, local;        // work item and pose index within it
-    int order;              // class * kNumBuckets + cost bucket
+    int order;              // (class * kNumStrips + strip) * kNumBuckets + cost bucket
 };
 
 struct SceneDev {
@@ -81,7 +90,7 @@ struct Work {
     PoseInfo *info;          // cap_poses
     int *lists;              // kNumClasses * cap_poses global pose indices
     int *counts;             // kCounterInts launch counters (layout above)
-    int sort;                // order each class list costliest first
+    int sort;                // order each class list by image strip, then costliest first
     int key_bands;           // J_o regions too large for LDS are keyed in bands of rows (class 1)
     uint32_t *gscratch;      // device-memory slots of classes 2 (keys) and 3 (tile + keys)
     size_t slot_base[kNumClasses];   // first word of each class's slots

@@ -664,24 +664,39 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
     __shared__ int queue2[BLOCK];
     __shared__ int qn;
     __shared__ int next;
-    const int count = w.counts[kCntClass + cls];
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
-    // poses are taken from the class list through a shared cursor, so a
-    // work-group that drew cheap poses takes more of them
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&w.counts[kCntNext + cls], 1);
-        __syncthreads();
-        const int i = next;
-        __syncthreads();
-        if (i >= count) break;
-        const int p = w.lists[cls * w.cap_poses + i];
-        uint32_t *tile = G ? slot : smem;
-        typename KeyOf<KG>::T *keys;
-        if constexpr (KG)
-            keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
-        else
-            keys = smem + w.info[p].tw * w.info[p].th;
-        score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, cnt, queue, queue2, &qn);
+    // Ordered lists are cut into image strips, one per XCD: a work-group
+    // first takes the poses of its own XCD's strip (work-groups are
+    // dispatched to the XCDs in turn), so each XCD's L2 holds one part of
+    // the scene, then helps with the other strips.  Within a segment poses
+    // come through a shared cursor, costliest first.
+    const int home = blockIdx.x % kNumStrips;
+    for (int h = 0; h < kNumStrips; ++h) {
+        const int strip = (home + h) % kNumStrips;
+        const int seg = cls * kNumStrips + strip;
+        int start = 0, len;
+        if (w.sort) {
+            start = w.counts[kCntSegStart + seg];
+            len = w.counts[kCntSegLen + seg];
+        } else {
+            len = strip == 0 ? w.counts[kCntClass + cls] : 0;
+        }
+        if (len == 0) continue;
+        for (;;) {
+            if (threadIdx.x == 0) next = atomicAdd(&w.counts[kCntNext + seg], 1);
+            __syncthreads();
+            const int i = next;
+            __syncthreads();
+            if (i >= len) break;
+            const int p = w.lists[cls * w.cap_poses + start + i];
+            uint32_t *tile = G ? slot : smem;
+            typename KeyOf<KG>::T *keys;
+            if constexpr (KG)
+                keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
+            else
+                keys = smem + w.info[p].tw * w.info[p].th;
+            score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, cnt, queue, queue2, &qn);
+        }
     }
 }
 
@@ -730,7 +745,8 @@ __device__ __forceinline__ void clip_box(double umin, double umax, double vmin, 
 
 __global__ void zero_counts_kernel(int *counts)
 {
-    if (threadIdx.x < kCounterInts) counts[threadIdx.x] = 0;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kCounterInts) counts[k] = 0;
 }
 
 // Cost bucket of a pose from its raster tile, J_o region and triangle
@@ -742,10 +758,10 @@ __device__ __forceinline__ int cost_bucket(int tile_px, int j_px, int nt)
     return min(max(lg - 4, 0), kNumBuckets - 1);
 }
 
-__global__ void setup_kernel(Work w)
+// Regions and footprint class of global pose p; returns its order key
+// (class * kNumStrips + strip) * kNumBuckets + cost bucket.
+__device__ int classify_pose(const Work &w, int p)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= w.hdr->n_poses) return;
     // the item holding global pose p: the last one with first <= p
     int lo = 0, hi = w.hdr->n_items - 1;
     while (lo < hi) {
@@ -810,35 +826,99 @@ __global__ void setup_kernel(Work w)
         if (words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
         else if (w.key_bands && tile_words + in.jw <= w.cap_large) cls = 1;   // J_o keys in bands of rows
     }
+    const int strip = min(max(((in.tx0 + in.tw / 2) * kNumStrips) / s.W, 0), kNumStrips - 1);
+    const int order = (cls * kNumStrips + strip) * kNumBuckets + cost_bucket(tile_words, in.jw * in.jh, m.nt);
+    w.info[p].order = order;
+    return order;
+}
+
+// Classify every pose.  Counts are gathered per work-group in LDS and added
+// to the launch counters once per work-group and key.  Without ordering,
+// each class list is filled in set-up order (one segment per class).
+__global__ __launch_bounds__(256) void setup_kernel(Work w)
+{
+    __shared__ int lcnt[kNumOrders];
+    __shared__ int lcls[kNumClasses], lbase[kNumClasses];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int k = threadIdx.x; k < kNumOrders; k += blockDim.x) lcnt[k] = 0;
+    if (threadIdx.x < kNumClasses) lcls[threadIdx.x] = 0;
+    __syncthreads();
+    int order = -1, local = 0;
+    if (p < w.hdr->n_poses) {
+        order = classify_pose(w, p);
+        if (w.sort) atomicAdd(&lcnt[order], 1);
+        else local = atomicAdd(&lcls[order / (kNumStrips * kNumBuckets)], 1);
+    }
+    __syncthreads();
     if (w.sort) {
-        const int order = cls * kNumBuckets + cost_bucket(tile_words, in.jw * in.jh, m.nt);
-        w.info[p].order = order;
-        atomicAdd(&w.counts[kCntClass + cls], 1);
-        atomicAdd(&w.counts[kCntBucket + order], 1);
-    } else {
-        const int slot = atomicAdd(&w.counts[kCntClass + cls], 1);
-        w.lists[cls * w.cap_poses + slot] = p;
+        for (int k = threadIdx.x; k < kNumOrders; k += blockDim.x) {
+            const int c = lcnt[k];
+            if (c) {
+                atomicAdd(&w.counts[kCntBucket + k], c);
+                atomicAdd(&w.counts[kCntClass + k / (kNumStrips * kNumBuckets)], c);
+            }
+        }
+        return;
+    }
+    if (threadIdx.x < kNumClasses) {
+        const int c = lcls[threadIdx.x];
+        lbase[threadIdx.x] = c ? atomicAdd(&w.counts[kCntClass + threadIdx.x], c) : 0;
+    }
+    __syncthreads();
+    if (order >= 0) {
+        const int cls = order / (kNumStrips * kNumBuckets);
+        w.lists[cls * w.cap_poses + lbase[cls] + local] = p;
     }
 }
 
-// Place each pose in its class list, costliest bucket first (order within
-// a bucket is arbitrary: every pose is scored independently).
-__global__ void order_kernel(Work w)
+// Place each pose in its class list: by image strip, then costliest bucket
+// first (order within a bucket is arbitrary: every pose is scored
+// independently).  The first work-group also records each (class, strip)
+// segment.  Slots are taken per work-group and key, then handed out in LDS.
+__global__ __launch_bounds__(256) void order_kernel(Work w)
 {
-    __shared__ int base[kNumClasses * kNumBuckets];
-    if (threadIdx.x < kNumClasses * kNumBuckets) {
-        const int cls = threadIdx.x / kNumBuckets, b = threadIdx.x % kNumBuckets;
+    __shared__ int seg[kNumSegs];
+    __shared__ int base[kNumOrders], lcnt[kNumOrders], lbase[kNumOrders];
+    const int t = threadIdx.x;
+    if (t < kNumSegs) {
+        int n = 0;
+        for (int b = 0; b < kNumBuckets; ++b) n += w.counts[kCntBucket + t * kNumBuckets + b];
+        seg[t] = n;
+    }
+    for (int k = t; k < kNumOrders; k += blockDim.x) lcnt[k] = 0;
+    __syncthreads();
+    for (int k = t; k < kNumOrders; k += blockDim.x) {
+        const int sg = k / kNumBuckets, b = k % kNumBuckets;
+        const int cls = sg / kNumStrips, strip = sg % kNumStrips;
         int off = 0;
-        for (int k = kNumBuckets - 1; k > b; --k) off += w.counts[kCntBucket + cls * kNumBuckets + k];
-        base[threadIdx.x] = off;
+        for (int s2 = 0; s2 < strip; ++s2) off += seg[cls * kNumStrips + s2];
+        for (int b2 = kNumBuckets - 1; b2 > b; --b2) off += w.counts[kCntBucket + sg * kNumBuckets + b2];
+        base[k] = off;
+    }
+    if (blockIdx.x == 0 && t < kNumSegs) {
+        const int cls = t / kNumStrips, strip = t % kNumStrips;
+        int off = 0;
+        for (int s2 = 0; s2 < strip; ++s2) off += seg[cls * kNumStrips + s2];
+        w.counts[kCntSegStart + t] = off;
+        w.counts[kCntSegLen + t] = seg[t];
+    }
+    const int p = blockIdx.x * blockDim.x + t;
+    const bool valid = p < w.hdr->n_poses;
+    int order = 0, local = 0;
+    if (valid) {
+        order = w.info[p].order;
+        local = atomicAdd(&lcnt[order], 1);
     }
     __syncthreads();
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= w.hdr->n_poses) return;
-    const int order = w.info[p].order;
-    const int cls = order / kNumBuckets;
-    const int slot = base[order] + atomicAdd(&w.counts[kCntFill + order], 1);
-    w.lists[cls * w.cap_poses + slot] = p;
+    for (int k = t; k < kNumOrders; k += blockDim.x) {
+        const int c = lcnt[k];
+        lbase[k] = c ? atomicAdd(&w.counts[kCntFill + k], c) : 0;
+    }
+    __syncthreads();
+    if (valid) {
+        const int cls = order / (kNumStrips * kNumBuckets);
+        w.lists[cls * w.cap_poses + base[order] + lbase[order] + local] = p;
+    }
 }
 
 // ------------------------------------------------------------------ scene prep
@@ -1177,7 +1257,7 @@ static hipError_t launch_class_t(const Work &w, const LaunchCfg &c, int cls, hip
 
 hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st)
 {
-    zero_counts_kernel<<<1, kCounterInts, 0, st>>>(w.counts);
+    zero_counts_kernel<<<(kCounterInts + 255) / 256, 256, 0, st>>>(w.counts);
     setup_kernel<<<(poses_grid + 255) / 256, 256, 0, st>>>(w);
     if (w.sort) order_kernel<<<(poses_grid + 255) / 256, 256, 0, st>>>(w);
     return hipGetLastError();
