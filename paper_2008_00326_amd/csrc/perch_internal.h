@@ -120,7 +120,10 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *op
                              uint32_t *oblk, hipStream_t st);
 // Nearest-neighbour table of the observed cloud: per pixel the depth range
 // that can have an observed point within delta, then one entry per depth.
-hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st);
+hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, long long *blk,
+                               hipStream_t st);
+// Block sums the table scan needs (long long each).
+int table_scan_blocks(int n_pixels);
 hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
 // A launch: zero the counters, classify every pose (grid sized for
 // `poses_grid` poses; the kernels read the real count from the header) and,

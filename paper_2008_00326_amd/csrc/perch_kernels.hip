@@ -999,33 +999,77 @@ __global__ void table_cols_kernel(SceneDev s, const uint32_t *tmp, int2 *thdr)
     thdr[k] = make_int2(0, lo | (n << 16));
 }
 
-// Exclusive scan of the per-pixel entry counts into thdr[].x (one block).
-__global__ __launch_bounds__(1024) void table_scan_kernel(int N, int2 *thdr, long long *total)
+// Exclusive scan of the per-pixel entry counts (thdr[].y >> 16) into
+// thdr[].x, in three passes over blocks of kScanBlock pixels: block sums,
+// a one-work-group scan of the block sums (with the grand total), and the
+// scan inside each block offset by its block's start.
+constexpr int kScanBlock = 1024;
+
+__device__ __forceinline__ long long block_exclusive_scan256(long long v, long long *total)
 {
-    __shared__ long long part[1024];
-    const int t = threadIdx.x;
-    const int chunk = (N + 1023) / 1024;
-    const int a = t * chunk, b = min(a + chunk, N);
-    long long sum = 0;
-    for (int k = a; k < b; ++k) sum += (long long)((uint32_t)thdr[k].y >> 16);
-    part[t] = sum;
+    __shared__ long long wsum[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    long long x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    if (t == 0) {
-        long long run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const long long v = part[k];
-            part[k] = run;
-            run += v;
-        }
-        *total = run;
+    long long before = 0, all = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (k < wv) before += wsum[k];
+        all += wsum[k];
     }
     __syncthreads();
-    long long run = part[t];
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void table_block_sums_kernel(int N, const int2 *thdr, long long *blk)
+{
+    const int base = blockIdx.x * kScanBlock + 4 * threadIdx.x;
+    long long v = 0;
+    for (int u = 0; u < 4; ++u)
+        if (base + u < N) v += (long long)((uint32_t)thdr[base + u].y >> 16);
+    long long total;
+    (void)block_exclusive_scan256(v, &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void table_block_scan_kernel(int nblk, long long *blk, long long *total)
+{
+    // 256 threads, each a contiguous run of the block sums
+    const int chunk = (nblk + 255) / 256;
+    const int a = threadIdx.x * chunk, b = min(a + chunk, nblk);
+    long long v = 0;
+    for (int k = a; k < b; ++k) v += blk[k];
+    long long all;
+    long long run = block_exclusive_scan256(v, &all);
     for (int k = a; k < b; ++k) {
-        const int n = (int)((uint32_t)thdr[k].y >> 16);
-        thdr[k].x = (int)run;
-        run += n;
+        const long long x = blk[k];
+        blk[k] = run;
+        run += x;
     }
+    if (threadIdx.x == 0) *total = all;
+}
+
+__global__ __launch_bounds__(256) void table_block_apply_kernel(int N, int2 *thdr, const long long *blk)
+{
+    const int base = blockIdx.x * kScanBlock + 4 * threadIdx.x;
+    int n[4];
+    long long v = 0;
+    for (int u = 0; u < 4; ++u) {
+        n[u] = base + u < N ? (int)((uint32_t)thdr[base + u].y >> 16) : 0;
+        v += n[u];
+    }
+    long long total;
+    long long run = blk[blockIdx.x] + block_exclusive_scan256(v, &total);
+    for (int u = 0; u < 4; ++u)
+        if (base + u < N) {
+            thdr[base + u].x = (int)run;     // the total is checked to fit 31 bits before any use
+            run += n[u];
+        }
 }
 
 // Entries of one pixel's range handled per pass of the fill kernel.
@@ -1103,12 +1147,18 @@ __global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tn
     }
 }
 
-hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, hipStream_t st)
+int table_scan_blocks(int n_pixels) { return (n_pixels + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, long long *blk,
+                               hipStream_t st)
 {
     const int N = s.W * s.H;
+    const int nblk = table_scan_blocks(N);
     table_rows_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, tmp);
     table_cols_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, tmp, thdr);
-    table_scan_kernel<<<1, 1024, 0, st>>>(N, thdr, total);
+    table_block_sums_kernel<<<nblk, 256, 0, st>>>(N, thdr, blk);
+    table_block_scan_kernel<<<1, 256, 0, st>>>(nblk, blk, total);
+    table_block_apply_kernel<<<nblk, 256, 0, st>>>(N, thdr, blk);
     return hipGetLastError();
 }
 

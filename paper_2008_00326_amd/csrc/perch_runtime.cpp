@@ -823,7 +823,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
 
     SceneRec r;
     const int bw = (W + kBlockPx - 1) / kBlockPx, bh = (H + kBlockPx - 1) / kBlockPx;
-    DevBuf tmp;
+    DevBuf tmp;   // row pass output (N words), then the table total and the scan's block sums, 8-byte aligned
+    const size_t tmp_extra = (N * 4 + 7) & ~(size_t)7;
     // allocation and kernel launches under the context lock; uploads and
     // waits outside it, so scoring on other streams is not held up
     auto cleanup = [&]() {
@@ -851,7 +852,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         }
         if (d->labels) A(r.labels, N * 4);
         A(r.thdr, N * sizeof(int2));
-        A(tmp, N * 4 + 64);
+        A(tmp, tmp_extra + 64 + (size_t)table_scan_blocks((int)N) * 8);
         if (st != PERCH_OK) {
             std::string msg = g_last_error;
             cleanup();
@@ -910,7 +911,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         }
     }
     // points, colours, depth blocks and the nearest-neighbour table ranges
-    long long *total_dev = (long long *)((char *)tmp.ptr + N * 4);
+    long long *total_dev = (long long *)((char *)tmp.ptr + tmp_extra);
     long long total = 0;
     if (e == hipSuccess) {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -918,7 +919,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             hipError_t e2 = launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int4 *)r.opt.ptr, (float4 *)r.olab.ptr,
                                               (uint32_t *)r.oblk.ptr, ctx->stream);
             return e2 == hipSuccess
-                       ? launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev, ctx->stream)
+                       ? launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev,
+                                             (long long *)((char *)tmp.ptr + tmp_extra + 64), ctx->stream)
                        : e2;
         });
         if (e == hipSuccess) e = hipMemcpyAsync(&total, total_dev, 8, hipMemcpyDeviceToHost, ctx->stream);

@@ -305,6 +305,7 @@ class MeshCache:
         self.bytes = 0
         self.hits = 0
         self.misses = 0
+        self._seen = {}                              # id(mesh) -> (mesh, use_rgb, key): hash each object once
 
     @staticmethod
     def key(mesh, use_rgb: bool) -> str:
@@ -315,8 +316,21 @@ class MeshCache:
             h.update(mesh.rgb.tobytes())
         return h.hexdigest()
 
-    def acquire(self, mesh, use_rgb: bool) -> tuple:
+    def _key_of(self, mesh, use_rgb: bool) -> str:
+        # mesh arrays are treated as immutable once submitted; the memo keeps
+        # a reference, so an id is never reused while it is remembered
+        m = self._seen.get(id(mesh))
+        if m is not None and m[0] is mesh and m[1] == use_rgb:
+            return m[2]
         k = self.key(mesh, use_rgb)
+        if len(self._seen) > 4096:
+            self._seen.clear()
+        self._seen[id(mesh)] = (mesh, use_rgb, k)
+        return k
+
+    def acquire(self, mesh, use_rgb: bool) -> tuple:
+        with self.lock:
+            k = self._key_of(mesh, use_rgb)
         with self.lock:
             e = self.entries.get(k)
             if e is not None:

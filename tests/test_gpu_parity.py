@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 import paper_2008_00326_amd as pk  # noqa: E402
 from paper_2008_00326_amd.workloads import make_config  # noqa: E402
-from tiny_meshes import TMesh, TScene, box, pose_matrix  # noqa: E402
+from tiny_meshes import TMesh, TScene, box, pose_matrix, rot_z  # noqa: E402
 
 THREADS = 16
 
@@ -197,6 +197,33 @@ def test_cfg2_full_size_sampled_outputs(ctx):
 
 
 # ---------------------------------------------------------------- edges
+
+def test_odd_image_size(ctx):
+    """A 97x71 image (an odd pixel count, ragged scan blocks and strips):
+    every count bit-exact against the oracle, depth-only and with colour."""
+    say("odd image size")
+    K = (97, 71, 90.0, 95.0, 47.3, 36.6)
+    cube = box((-30, -40, -35), (30, 40, 35), n=3, rgb_seed=5)
+    d, _, c = oracle.render(cube, pose_matrix(rot_z(0.3), (4, -2, 520)), K)
+    mid = ctx.load_mesh(cube.xyz, cube.tri, cube.rgb)
+    rng = np.random.default_rng(7)
+    poses = np.stack([pose_matrix(rot_z(a), (x, y, z)) for a, x, y, z in
+                      zip(rng.uniform(0, 6.3, 40), rng.uniform(-60, 60, 40), rng.uniform(-50, 50, 40),
+                          rng.uniform(380, 700, 40))])
+    for use_rgb in (False, True):
+        sid = ctx.set_scene(K, d, c, delta_mm=8.0, tau_c=15.0, use_rgb=use_rgb)
+        got = gpu_score(ctx, sid, mid, poses)
+        flags = (oracle.USE_RGB if use_rgb else 0) | oracle.MARK_OCCLUDERS
+        exp = oracle.score(cube, TScene(K, d, c, None), poses, delta_mm=8.0, tau_c=15.0, flags=flags, threads=THREADS)
+        assert np.array_equal(got[2], exp[2]) and np.array_equal(got[3], exp[3])      # L and Q exact
+        if use_rgb:   # colour decisions: at most 0.1 % of the points per pose
+            assert np.all(np.abs(got[0] - exp[0]) <= np.ceil(0.001 * exp[2]))
+            assert np.all(np.abs(got[1] - exp[1]) <= np.ceil(0.001 * exp[3]))
+        else:
+            assert np.array_equal(got[0], exp[0]) and np.array_equal(got[1], exp[1])
+        ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
+
 
 def test_edge_cases(ctx):
     say("edge cases")

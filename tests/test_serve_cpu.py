@@ -183,3 +183,46 @@ def test_closed_server_refuses_submissions():
     srv.close()
     with pytest.raises(RuntimeError):
         srv.submit(make_req(0))
+
+
+class FakeCtx:
+    def __init__(self):
+        self.next = 1
+        self.loaded = {}
+
+    def load_mesh(self, xyz, tri, rgb=None):
+        mid = self.next
+        self.next += 1
+        self.loaded[mid] = (xyz.shape[0], tri.shape[0])
+        return mid
+
+    def unload_mesh(self, mid):
+        del self.loaded[mid]
+
+
+def test_mesh_cache_by_content_and_eviction():
+    import numpy as np
+    from types import SimpleNamespace
+    from paper_2008_00326_amd.serve import MeshCache
+
+    def mesh(seed):
+        r = np.random.default_rng(seed)
+        return SimpleNamespace(xyz=r.normal(size=(100, 3)).astype(np.float32),
+                               tri=r.integers(0, 100, (200, 3)).astype(np.int32),
+                               rgb=r.integers(0, 256, (100, 3)).astype(np.uint8))
+
+    ctx = FakeCtx()
+    one_mesh = 100 * 20 + 200 * 16
+    cache = MeshCache(ctx, max_bytes=2 * one_mesh)
+    a, a_copy, b, c = mesh(1), mesh(1), mesh(2), mesh(3)
+    ka, ma = cache.acquire(a, True)
+    kb, mb = cache.acquire(a_copy, True)              # same content, another object: a hit
+    assert (ka, ma) == (kb, mb) and cache.hits == 1 and cache.misses == 1 and len(ctx.loaded) == 1
+    k2, m2 = cache.acquire(b, True)
+    k3, m3 = cache.acquire(c, True)                    # over budget, but everything is referenced
+    assert len(ctx.loaded) == 3
+    cache.release(ka)
+    cache.release(kb)                                  # a unreferenced: evicted, oldest first
+    assert ma not in ctx.loaded and len(ctx.loaded) == 2
+    assert cache.acquire(a, True)[1] not in (ma,)      # reloaded under a new id
+    assert cache.key(a, True) != cache.key(a, False)   # colours are part of the key only when used
