@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--rates", default="20,50,100", help="config 5: arrival rates, scenes/s")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="config 5: arrival window per rate")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=64, help="poses the CPU oracle scores for the baseline")
+    ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
