@@ -97,6 +97,9 @@ struct Work {
     size_t slot_words[kNumClasses];  // words per work-group slot
     size_t dev_tile_words;   // class 3: words of the slot's tile (keys follow)
     int cap_small, cap_large; // LDS words (tile + keys) of the two LDS classes
+    float4 *lab;             // RGB: CIELAB of each inlier, one slot of tile pixels per work-group, or null
+    size_t lab_base[kNumClasses];    // first entry of each class's slots
+    size_t lab_px[kNumClasses];      // entries per work-group slot (the class's largest tile)
     int32_t *best;           // n_items x {index, J} of the per-item minimum, or null
 };
 

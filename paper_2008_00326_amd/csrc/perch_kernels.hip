@@ -450,8 +450,8 @@ __device__ __forceinline__ int wave_popc(bool pred)
 // ------------------------------------------------------------------ per pose
 
 template <int BLOCK, bool G, bool KG, bool RGB>
-__device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, int *cnt, int *queue,
-                           int *queue2, int *qn)
+__device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, float4 *labs, int *cnt,
+                           int *queue, int *queue2, int *qn)
 {
     using K = KeyOf<KG>;
     constexpr int NW = BLOCK / 64;
@@ -574,6 +574,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     const int ty = kk / in.tw, tx = kk - ty * in.tw;
                     const float4 lr =
                         srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                    if (labs) labs[kk] = lr;     // kept for the J_o test of the points this inlier keys
                     out = ciede2000(lr, gld(s.olab + queue2[tid])) > s.tau;
                 }
                 cR += wave_popc(out);
@@ -623,10 +624,14 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 bool cout = false;
                 if (tid < nq) {
                     const int pix = queue[tid], kr = queue2[tid];
-                    const uint32_t key = tld<G>(tile + kr);
-                    const int ty = kr / in.tw, tx = kr - ty * in.tw;
-                    const float4 lr =
-                        srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                    float4 lr;
+                    if (labs) {
+                        lr = gld(labs + kr);       // every keying point is an inlier of the first band
+                    } else {
+                        const uint32_t key = tld<G>(tile + kr);
+                        const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                        lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                    }
                     cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
                 }
                 cO += wave_popc(cout);
@@ -665,6 +670,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
     __shared__ int qn;
     __shared__ int next;
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
+    float4 *labs = RGB && w.lab ? w.lab + w.lab_base[cls] + (size_t)blockIdx.x * w.lab_px[cls] : nullptr;
     // Ordered lists are cut into image strips, one per XCD: a work-group
     // first takes the poses of its own XCD's strip (work-groups are
     // dispatched to the XCDs in turn), so each XCD's L2 holds one part of
@@ -695,7 +701,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
                 keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
             else
                 keys = smem + w.info[p].tw * w.info[p].th;
-            score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, cnt, queue, queue2, &qn);
+            score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, labs, cnt, queue, queue2, &qn);
         }
     }
 }

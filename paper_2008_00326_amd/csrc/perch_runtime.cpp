@@ -99,7 +99,7 @@ size_t round_alloc(size_t bytes)
 // Device buffers of one launch: descriptors, per-pose work, device-memory
 // slots of the large footprint classes, per-item minima.
 struct LaunchBufs {
-    DevBuf desc, info, lists, counts, scratch, best;
+    DevBuf desc, info, lists, counts, scratch, best, lab;
 };
 
 // Pinned staging of descriptors for asynchronous uploads: a ring of slots,
@@ -512,11 +512,28 @@ void slot_layout(const LaunchCfg &cfg, size_t max_pixels, size_t slot_words[kNum
     }
 }
 
+// Per-work-group CIELAB slots of the RGB term: one entry per pixel of the
+// class's largest tile.
+void lab_layout(const LaunchCfg &cfg, size_t max_pixels, size_t lab_px[kNumClasses], size_t lab_base[kNumClasses],
+                size_t *total)
+{
+    lab_px[0] = (size_t)cfg.cap_small;
+    lab_px[1] = lab_px[2] = (size_t)cfg.cap_large;
+    lab_px[3] = max_pixels;
+    *total = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        lab_base[c] = *total;
+        *total += lab_px[c] * (size_t)cfg.grid[c];
+    }
+}
+
 perch_status ensure_bufs(perch_ctx *ctx, LaunchBufs &lb, size_t desc_bytes, int cap_poses, int cap_items,
-                         size_t max_pixels, const LaunchCfg &cfg)
+                         size_t max_pixels, const LaunchCfg &cfg, bool rgb)
 {
     size_t sw[kNumClasses], sb[kNumClasses], total = 0, tile = 0;
     slot_layout(cfg, max_pixels, sw, sb, &total, &tile);
+    size_t lp[kNumClasses], lb0[kNumClasses], lab_total = 0;
+    lab_layout(cfg, max_pixels, lp, lb0, &lab_total);
     perch_status s;
     if ((s = ctx->ensure(lb.desc, desc_bytes))) return s;
     if ((s = ctx->ensure(lb.info, (size_t)std::max(cap_poses, 1) * sizeof(PoseInfo)))) return s;
@@ -524,6 +541,7 @@ perch_status ensure_bufs(perch_ctx *ctx, LaunchBufs &lb, size_t desc_bytes, int 
     if ((s = ctx->ensure(lb.counts, kCounterInts * 4))) return s;
     if ((s = ctx->ensure(lb.scratch, total * 4))) return s;
     if ((s = ctx->ensure(lb.best, (size_t)std::max(cap_items, 1) * 8))) return s;
+    if (rgb && (s = ctx->ensure(lb.lab, lab_total * sizeof(float4)))) return s;
     return PERCH_OK;
 }
 
@@ -548,6 +566,9 @@ Work make_work(const LaunchBufs &lb, const Built &b, int cap_poses, const Launch
     w.sort = cfg.sort;
     w.key_bands = cfg.key_bands;
     w.best = want_best ? (int32_t *)lb.best.ptr : nullptr;
+    size_t lab_total = 0;
+    lab_layout(cfg, max_pixels, w.lab_px, w.lab_base, &lab_total);
+    w.lab = lb.lab.bytes >= lab_total * sizeof(float4) ? (float4 *)lb.lab.ptr : nullptr;
     return w;
 }
 
@@ -604,7 +625,8 @@ perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hi
     if (b.n_poses == 0) return PERCH_OK;
     StreamBufs &sb = ctx->work[st];
     const LaunchCfg cfg = launch_cfg(ctx);
-    if (perch_status s = ensure_bufs(ctx, sb.lb, b.bytes.size(), b.n_poses, b.n_items, b.max_pixels, cfg)) return s;
+    if (perch_status s = ensure_bufs(ctx, sb.lb, b.bytes.size(), b.n_poses, b.n_items, b.max_pixels, cfg, b.any_rgb))
+        return s;
     if (perch_status s = upload(sb, b, sb.lb.desc.ptr, st)) return s;
     const Work w = make_work(sb.lb, b, b.n_poses, cfg, b.max_pixels, want_best);
     sb.last_n = b.n_poses;
@@ -672,7 +694,8 @@ perch_status perch_destroy(perch_ctx *ctx)
     while (!ctx->batches.empty()) perch_batch_destroy(ctx->batches.back());
     for (auto &kv : ctx->work) {
         StreamBufs &w = kv.second;
-        for (DevBuf *b : {&w.lb.desc, &w.lb.info, &w.lb.lists, &w.lb.counts, &w.lb.scratch, &w.lb.best, &w.tmp})
+        for (DevBuf *b : {&w.lb.desc, &w.lb.info, &w.lb.lists, &w.lb.counts, &w.lb.scratch, &w.lb.best, &w.lb.lab,
+                          &w.tmp})
             ctx->release(*b);
         for (Staging &g : w.ring) {
             if (g.host) (void)hipHostFree(g.host);
@@ -1181,7 +1204,8 @@ perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_p
     b->cfg = launch_cfg(ctx);
     auto cleanup = [&](perch_status st, const char *what, hipError_t e) {
         std::string msg = e != hipSuccess ? std::string(what) + ": " + hipGetErrorString(e) : g_last_error;
-        for (DevBuf *d : {&b->lb.desc, &b->lb.info, &b->lb.lists, &b->lb.counts, &b->lb.scratch, &b->lb.best})
+        for (DevBuf *d : {&b->lb.desc, &b->lb.info, &b->lb.lists, &b->lb.counts, &b->lb.scratch, &b->lb.best,
+                          &b->lb.lab})
             ctx->release(*d);
         if (b->pin_desc) (void)hipHostFree(b->pin_desc);
         if (b->pin_best) (void)hipHostFree(b->pin_best);
@@ -1192,7 +1216,7 @@ perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_p
         delete b;
         return fail(st, "%s", msg.c_str());
     };
-    if (perch_status st = ensure_bufs(ctx, b->lb, b->desc_cap, max_poses, max_items, b->cap_pixels, b->cfg))
+    if (perch_status st = ensure_bufs(ctx, b->lb, b->desc_cap, max_poses, max_items, b->cap_pixels, b->cfg, true))
         return cleanup(st, "", hipSuccess);
     hipError_t e = hipHostMalloc(&b->pin_desc, b->desc_cap, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&b->pin_best, (size_t)8 * max_items, hipHostMallocDefault);
@@ -1309,7 +1333,7 @@ perch_status perch_batch_destroy(perch_batch *b)
     (void)hipEventDestroy(b->done);
     (void)hipHostFree(b->pin_desc);
     (void)hipHostFree(b->pin_best);
-    for (DevBuf *d : {&b->lb.desc, &b->lb.info, &b->lb.lists, &b->lb.counts, &b->lb.scratch, &b->lb.best})
+    for (DevBuf *d : {&b->lb.desc, &b->lb.info, &b->lb.lists, &b->lb.counts, &b->lb.scratch, &b->lb.best, &b->lb.lab})
         ctx->release(*d);
     ctx->batches.erase(std::find(ctx->batches.begin(), ctx->batches.end(), b));
     delete b;
