@@ -357,6 +357,16 @@ __device__ __forceinline__ void mark_one(int4 q, int X, int Y, int Z, int k, int
     if (d2 <= dq2) K::min(key, K::make(d2, k));
 }
 
+// Per-inlier marking parameters, computed once by the thread that queues
+// the inlier: its point (X, Y) in 1/16 mm and its window half-sizes.
+__device__ __forceinline__ void mark_params(const SceneDev &s, int i, int j, int d, int *X, int *Y, int *wuv)
+{
+    *X = (int)rint(gld(s.kx + i) * (double)d);
+    *Y = (int)rint(gld(s.ky + j) * (double)d);
+    const float iz = window_inv(d, s.delta + 0.25f);
+    *wuv = window_half(gld(s.ax + i), iz, s.W) | (window_half(gld(s.ay + j), iz, s.H) << 16);
+}
+
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
 // visits every observed pixel of r's window inside the J_o region: each
 // observed point within delta of r min-combines (d2, k) into its key.  This
@@ -367,14 +377,10 @@ __device__ __forceinline__ void mark_one(int4 q, int X, int Y, int Z, int k, int
 // with every load issued before use; windows wider than a wave are walked
 // in row-major order, four pixels per lane per round.
 template <bool G>
-__device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, typename KeyOf<G>::T *keys, int jx0,
-                          int jy0, int jw, int jh, int lane)
+__device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, int Y, int wuv,
+                          typename KeyOf<G>::T *keys, int jx0, int jy0, int jw, int jh, int lane)
 {
-    const int X = (int)rint(s.kx[i] * (double)d);
-    const int Y = (int)rint(s.ky[j] * (double)d);
-    const float iz = window_inv(d, s.delta + 0.25f);
-    const int wu = window_half(gld(s.ax + i), iz, s.W);
-    const int wv = window_half(gld(s.ay + j), iz, s.H);
+    const int wu = wuv & 0xFFFF, wv = wuv >> 16;
     const int i0 = max(max(i - wu, 0), jx0), i1 = min(min(i + wu, s.W - 1), jx0 + jw - 1);
     const int j0 = max(max(j - wv, 0), jy0), j1 = min(min(j + wv, s.H - 1), jy0 + jh - 1);
     if (i0 > i1 || j0 > j1) return;
@@ -451,7 +457,7 @@ __device__ __forceinline__ int wave_popc(bool pred)
 
 template <int BLOCK, bool G, bool KG, bool RGB>
 __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, float4 *labs, int *cnt,
-                           int *queue, int *queue2, int *qn)
+                           int *queue, int *queue2, int *mx, int *my, int *mw, int *qn)
 {
     using K = KeyOf<KG>;
     constexpr int NW = BLOCK / 64;
@@ -552,6 +558,13 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                         const int slot = atomicAdd(qn, 1);
                         queue[slot] = k;
                         queue2[slot] = nn;
+                        if (bpx > 0) {
+                            int X, Y, wuv;
+                            mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
+                            mx[slot] = X;
+                            my[slot] = Y;
+                            mw[slot] = wuv;
+                        }
                     }
                 }
             }
@@ -563,7 +576,8 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     const int kk = queue[t];
                     const int ty = kk / in.tw, tx = kk - ty * in.tw;
                     const int dd = (int)(tld<G>(tile + kk) >> 16);
-                    wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, keys, in.jx0, by0, in.jw, bh, lane);
+                    wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, mx[t], my[t], mw[t], keys, in.jx0, by0, in.jw,
+                                  bh, lane);
                 }
             }
             if (rgb && first) {
@@ -667,6 +681,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
     __shared__ int cnt[4];
     __shared__ int queue[BLOCK];
     __shared__ int queue2[BLOCK];
+    __shared__ int mx[BLOCK], my[BLOCK], mw[BLOCK];   // marking parameters of the queued inliers
     __shared__ int qn;
     __shared__ int next;
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
@@ -701,7 +716,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
                 keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
             else
                 keys = smem + w.info[p].tw * w.info[p].th;
-            score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, labs, cnt, queue, queue2, &qn);
+            score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, labs, cnt, queue, queue2, mx, my, mw, &qn);
         }
     }
 }
