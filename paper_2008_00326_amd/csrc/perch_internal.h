@@ -32,7 +32,7 @@ struct PoseInfo {
     int vx0, vy0, vw, vh;   // region holding every observed pixel that may lie in V(O)
     int jx0, jy0, jw, jh;   // part of the V region within reach of a rendered point
     int item, local;        // work item and pose index within it
-    int order;              // (class * kNumStrips + strip) * kNumBuckets + cost bucket
+    int order;              // (class * kNumStrips + strip) * kNumBuckets + sub-key (cost or scene group)
 };
 
 struct SceneDev {
@@ -76,7 +76,7 @@ struct ItemDev {
 };
 
 struct LaunchHdr {
-    int n_items, n_poses;
+    int n_items, n_poses, n_scenes;
 };
 
 // Device-resident descriptors of one launch (header, items, scenes and

@@ -780,7 +780,7 @@ __device__ __forceinline__ int cost_bucket(int tile_px, int j_px, int nt)
 }
 
 // Regions and footprint class of global pose p; returns its order key
-// (class * kNumStrips + strip) * kNumBuckets + cost bucket.
+// (class * kNumStrips + strip) * kNumBuckets + sub-key.
 __device__ int classify_pose(const Work &w, int p)
 {
     // the item holding global pose p: the last one with first <= p
@@ -848,7 +848,12 @@ __device__ int classify_pose(const Work &w, int p)
         else if (w.key_bands && tile_words + in.jw <= w.cap_large) cls = 1;   // J_o keys in bands of rows
     }
     const int strip = min(max(((in.tx0 + in.tw / 2) * kNumStrips) / s.W, 0), kNumStrips - 1);
-    const int order = (cls * kNumStrips + strip) * kNumBuckets + cost_bucket(tile_words, in.jw * in.jh, m.nt);
+    // within a strip: costliest first for one scene; by scene group when the
+    // launch spans several scenes, so an XCD works through a few scenes' data
+    // at a time
+    const int ns = w.hdr->n_scenes;
+    const int sub = ns > 1 ? (it.scene * kNumBuckets) / ns : kNumBuckets - 1 - cost_bucket(tile_words, in.jw * in.jh, m.nt);
+    const int order = (cls * kNumStrips + strip) * kNumBuckets + sub;
     w.info[p].order = order;
     return order;
 }
@@ -892,9 +897,9 @@ __global__ __launch_bounds__(256) void setup_kernel(Work w)
     }
 }
 
-// Place each pose in its class list: by image strip, then costliest bucket
-// first (order within a bucket is arbitrary: every pose is scored
-// independently).  The first work-group also records each (class, strip)
+// Place each pose in its class list: by image strip, then by the sub-key
+// (cost bucket, costliest first, or scene group), ascending (order within a
+// key is arbitrary: every pose is scored independently).  The first work-group also records each (class, strip)
 // segment.  Slots are taken per work-group and key, then handed out in LDS.
 __global__ __launch_bounds__(256) void order_kernel(Work w)
 {
@@ -913,7 +918,7 @@ __global__ __launch_bounds__(256) void order_kernel(Work w)
         const int cls = sg / kNumStrips, strip = sg % kNumStrips;
         int off = 0;
         for (int s2 = 0; s2 < strip; ++s2) off += seg[cls * kNumStrips + s2];
-        for (int b2 = kNumBuckets - 1; b2 > b; --b2) off += w.counts[kCntBucket + sg * kNumBuckets + b2];
+        for (int b2 = 0; b2 < b; ++b2) off += w.counts[kCntBucket + sg * kNumBuckets + b2];
         base[k] = off;
     }
     if (blockIdx.x == 0 && t < kNumSegs) {

@@ -488,7 +488,7 @@ perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_
     b.scenes_off = 64 + align64(slots * sizeof(ItemDev));
     b.meshes_off = b.scenes_off + align64(slots * sizeof(SceneDev));
     b.bytes.assign(b.meshes_off + align64(slots * sizeof(MeshDev)), 0);
-    LaunchHdr h{b.n_items, b.n_poses};
+    LaunchHdr h{b.n_items, b.n_poses, (int)b.scene_ids.size()};
     std::memcpy(b.bytes.data(), &h, sizeof h);
     if (!items.empty()) std::memcpy(b.bytes.data() + 64, items.data(), items.size() * sizeof(ItemDev));
     if (!scenes.empty()) std::memcpy(b.bytes.data() + b.scenes_off, scenes.data(), scenes.size() * sizeof(SceneDev));
