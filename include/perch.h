@@ -104,9 +104,12 @@ perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz_mm, int32_t n_vert
                              int32_t *mesh_id);
 perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id);
 
-/* Copy an observed RGB-D image to the device and prepare it for scoring:
- * back-projection to points in 1/16 mm, CIELAB colours, and per-8x8-block
- * depth ranges for the radius search (the input cloud I of Sec. III-B). */
+/* Copy an observed RGB-D image to the device and prepare it for scoring (the
+ * input cloud I of Sec. III-B): back-projection to points in 1/16 mm, CIELAB
+ * colours, and a nearest-neighbour table -- for every pixel and every depth
+ * a rendered point there could have, the nearest observed point within
+ * delta (Eq. 2), ties to the lower pixel index.  Returns when the scene is
+ * ready; the preparation runs on the context's own stream. */
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *desc, int32_t *scene_id);
 perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id);
 
@@ -204,9 +207,9 @@ perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
 
 /* Footprint class (0..3, the scoring slots 1..4 of the profiler) that the
- * last perch_score_poses call on hip_stream
- * assigned to each of its n poses: class_host[i] for pose i.  Blocks until
- * that call has finished.  Meant for inspection and work accounting. */
+ * last perch_score_poses call on hip_stream assigned to each of its n poses:
+ * class_host[i] for pose i.  Blocks until that call has finished.  Meant for
+ * inspection and work accounting. */
 perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int32_t *class_host);
 
 /* Launch tuning: how the poses of a launch are spread over the scoring
@@ -219,8 +222,10 @@ perch_status perch_last_classes(perch_ctx *ctx, void *hip_stream, int32_t n, int
  *                 this many LDS words go to that class (0 = all that fit).
  *   grid[c]:      persistent work-groups of footprint class c (0 = as many
  *                 as are resident at once on the device).
- *   order:        1 = each class scores its poses in set-up order, 2 = its
- *                 costliest poses first (0 = 2).
+ *   order:        1 = each class scores its poses in set-up order; 2 = by
+ *                 image strip (one per XCD, each work-group starting on its
+ *                 own XCD's strip), then costliest first -- or, in launches
+ *                 over several scenes, scene by scene (0 = 2).
  *   key_bands:    for poses whose J_o keys do not fit in LDS beside the
  *                 raster tile: 1 = keys in device memory, 2 = keys in LDS,
  *                 one band of rows at a time (0 = 2).
