@@ -7,7 +7,6 @@
 namespace perch {
 
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-constexpr int kBlockPx = 8;         // side of the depth-range blocks (pixels)
 constexpr int kMaxTris = 65535;     // triangle index lives in 16 bits of the key
 constexpr int kNoPoint = -(1 << 28); // Zq of a pixel without a depth reading: never within delta
 constexpr int kNumClasses = 4;      // LDS small, LDS large, LDS tile + device keys, device memory
@@ -40,14 +39,13 @@ struct SceneDev {
     const int4 *opt;         // H*W (Xq, Yq, Zq, 0) in 1/16 mm; Zq = kNoPoint without a reading
     const float4 *olab;      // H*W CIELAB (RGB scenes) or null
     const int32_t *labels;   // H*W or null
-    const uint32_t *oblk;    // bw*bh: min depth | max depth << 16 of valid pixels
     const double *kx;        // W: 16 (i - cx) / fx
     const double *ky;        // H: 16 (j - cy) / fy
     const float *ax;         // W: f (delta + 1/4) sqrt(1 + ((i - cx) / fx)^2), rounded up
     const float *ay;         // H: the same for rows
     const int2 *thdr;        // H*W nearest-neighbour table header: {first entry, lo | n << 16}
     const int32_t *tnn;      // entry (pixel, lo + e): nearest observed pixel within delta, -1 none
-    int W, H, bw, bh;
+    int W, H;
     int wtx, wty;            // window half-sizes that contain every neighbour pair of the scene
     float fx, fy, cx, cy;
     int dq, dq2, dzmm;       // delta in 1/16 mm, its square, floor(dq / 16)
@@ -119,8 +117,7 @@ hipError_t upload_colour_table(const float *lin256);
 // 256-, 512- and 1024-thread kernels (the largest over their variants).
 hipError_t prepare_score_kernels(int lds_per_group, int static_bytes[3]);
 
-hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *opt, float4 *olab,
-                             uint32_t *oblk, hipStream_t st);
+hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *opt, float4 *olab, hipStream_t st);
 // Nearest-neighbour table of the observed cloud: per pixel the depth range
 // that can have an observed point within delta, then one entry per depth.
 hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, long long *total, long long *blk,

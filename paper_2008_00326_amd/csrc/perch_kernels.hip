@@ -969,22 +969,6 @@ __global__ void scene_points_kernel(SceneDev s, const uint8_t *rgb, int4 *opt, f
     }
 }
 
-__global__ void scene_blocks_kernel(SceneDev s, uint32_t *oblk)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= s.bw * s.bh) return;
-    const int by = b / s.bw, bx = b - by * s.bw;
-    int mn = 0xFFFF, mx = 0;
-    for (int j = by * 8; j < min(by * 8 + 8, s.H); ++j)
-        for (int i = bx * 8; i < min(bx * 8 + 8, s.W); ++i) {
-            const int d = s.depth[j * s.W + i];
-            if (d == 0) continue;
-            mn = min(mn, d);
-            mx = max(mx, d);
-        }
-    oblk[b] = (uint32_t)mn | ((uint32_t)mx << 16);
-}
-
 // ------------------------------------------------------------------ NN table
 
 // Row pass of the window min/max of valid observed depths: min | max << 16.
@@ -1271,13 +1255,10 @@ hipError_t upload_colour_table(const float *lin256)
     return hipMemcpyToSymbol(HIP_SYMBOL(c_lin), lin256, 256 * sizeof(float));
 }
 
-hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *opt, float4 *olab, uint32_t *oblk,
-                             hipStream_t st)
+hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *opt, float4 *olab, hipStream_t st)
 {
     const int N = s.W * s.H;
     scene_points_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, rgb_dev, opt, olab);
-    const int nb = s.bw * s.bh;
-    scene_blocks_kernel<<<(nb + 255) / 256, 256, 0, st>>>(s, oblk);
     return hipGetLastError();
 }
 

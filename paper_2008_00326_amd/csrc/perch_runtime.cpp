@@ -78,7 +78,7 @@ struct MeshRec {
 };
 
 struct SceneRec {
-    DevBuf depth, rgb, labels, opt, olab, oblk, kx, ky, ax, ay, thdr, tnn;
+    DevBuf depth, rgb, labels, opt, olab, kx, ky, ax, ay, thdr, tnn;
     SceneDev dev{};
     std::vector<int32_t> host_labels;
     std::map<int32_t, std::vector<int>> label_boxes;
@@ -687,7 +687,7 @@ perch_status perch_destroy(perch_ctx *ctx)
     for (auto &kv : ctx->scenes) {
         SceneRec &r = kv.second;
         FenceRef f = ctx->fence_of(r.uses);
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
                           &r.tnn})
             ctx->release(*b, f);
     }
@@ -845,14 +845,13 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     }
 
     SceneRec r;
-    const int bw = (W + kBlockPx - 1) / kBlockPx, bh = (H + kBlockPx - 1) / kBlockPx;
     DevBuf tmp;   // row pass output (N words), then the table total and the scan's block sums, 8-byte aligned
     const size_t tmp_extra = (N * 4 + 7) & ~(size_t)7;
     // allocation and kernel launches under the context lock; uploads and
     // waits outside it, so scoring on other streams is not held up
     auto cleanup = [&]() {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
+        for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
                           &r.tnn, &tmp})
             ctx->release(*b);
     };
@@ -864,7 +863,6 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         };
         A(r.depth, N * 2);
         A(r.opt, N * sizeof(int4));
-        A(r.oblk, (size_t)bw * bh * 4);
         A(r.kx, W * 8);
         A(r.ky, H * 8);
         A(r.ax, W * 4);
@@ -894,7 +892,6 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.opt = (const int4 *)r.opt.ptr;
     s.olab = (const float4 *)r.olab.ptr;
     s.labels = (const int32_t *)r.labels.ptr;
-    s.oblk = (const uint32_t *)r.oblk.ptr;
     s.kx = (const double *)r.kx.ptr;
     s.ky = (const double *)r.ky.ptr;
     s.ax = (const float *)r.ax.ptr;
@@ -902,8 +899,6 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.thdr = (const int2 *)r.thdr.ptr;
     s.W = W;
     s.H = H;
-    s.bw = bw;
-    s.bh = bh;
     s.fx = K.fx;
     s.fy = K.fy;
     s.cx = K.cx;
@@ -939,8 +934,8 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (e == hipSuccess) {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
-            hipError_t e2 = launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int4 *)r.opt.ptr, (float4 *)r.olab.ptr,
-                                              (uint32_t *)r.oblk.ptr, ctx->stream);
+            hipError_t e2 =
+                launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int4 *)r.opt.ptr, (float4 *)r.olab.ptr, ctx->stream);
             return e2 == hipSuccess
                        ? launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev,
                                              (long long *)((char *)tmp.ptr + tmp_extra + 64), ctx->stream)
@@ -975,7 +970,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         return fail(PERCH_EDEVICE, "scene table fill: %s", hipGetErrorString(e));
     }
     if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
-    r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.opt.bytes + r.olab.bytes + r.oblk.bytes + r.kx.bytes
+    r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.opt.bytes + r.olab.bytes + r.kx.bytes
               + r.ky.bytes + r.ax.bytes + r.ay.bytes + r.thdr.bytes + r.tnn.bytes;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     const int32_t id = ctx->next_scene++;
@@ -993,7 +988,7 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     if (perch_status st = release_check(ctx, true, scene_id)) return st;
     SceneRec &r = it->second;
     FenceRef f = ctx->fence_of(r.uses);
-    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.oblk, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr, &r.tnn})
+    for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr, &r.tnn})
         ctx->release(*b, f);
     ctx->scenes.erase(it);
     return ok();
