@@ -21,7 +21,9 @@ import numpy as np
 USE_RGB = 1
 MARK_OCCLUDERS = 2
 VOL_AABB = 0 << 4
+VOL_CYL = 1 << 4
 VOL_LABEL = 2 << 4
+JO_NN = 1 << 6
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")

@@ -57,7 +57,17 @@
  *      > tau_c is taken in binary32, the precision of the GPU path; the
  *      binary64 colour functions exist to pin the binary32 ones.
  *   R10 Volume: the object-frame AABB of the mesh, inflated by delta, tested
- *      in binary64 on q = R^T (P - t) with P = (Xq, Yq, Zq) / 16.
+ *      in binary64 on q = R^T (P - t) with P = (Xq, Yq, Zq) / 16.  The
+ *      inscribed-cylinder volume (Sec. III-A's conservative V) takes the
+ *      cylinder whose axis is the object z axis through the AABB's centre in
+ *      x and y, with radius the smaller half-extent in x and y and the AABB's
+ *      z range; it is inflated by delta like the box: (q0 - c0)^2 +
+ *      (q1 - c1)^2 <= (rho + delta)^2 and lo2 - delta <= q2 <= hi2 + delta.
+ *   R12 Nearest-neighbour marking of J_o (the paper's own J_o kernel, Sec.
+ *      IV-A "Parallel Cost Computation"): optionally an observed point inside
+ *      V is explained iff it is the nearest observed point (R9) within delta
+ *      of some point of R minus C that passes its own colour test; otherwise
+ *      it is an outlier.  No further colour test applies to it.
  *   R11 Selection: lowest J; ties go to the lowest pose index.
  *
  * Colour: sRGB8 is linearised with the IEC 61966-2-1 piecewise curve (256-
@@ -79,7 +89,9 @@
 #define OR_MARK_OCCLUDERS 2u
 #define OR_VOL_MASK (3u << 4)
 #define OR_VOL_AABB (0u << 4)
+#define OR_VOL_CYL (1u << 4)
 #define OR_VOL_LABEL (2u << 4)
+#define OR_JO_NN (1u << 6)
 
 #define OR_NEAR_MM 100.0
 #define OR_COORD_LIMIT 16777216.0
@@ -493,6 +505,7 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     const int use_rgb = (sc->flags & OR_USE_RGB) != 0;
     const int mark = (sc->flags & OR_MARK_OCCLUDERS) != 0;
     const uint32_t vol = sc->flags & OR_VOL_MASK;
+    const int nn_mark = (sc->flags & OR_JO_NN) != 0;
     const int64_t dq = (int64_t)nearbyint(16.0 * (double)sc->delta_mm);
     const int64_t dq2 = dq * dq;
     const int stride = sc->stride;
@@ -500,9 +513,10 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
 
     uint16_t *dren = (uint16_t *)malloc(N * sizeof(uint16_t));
     uint8_t *cren = use_rgb ? (uint8_t *)malloc(N * 3) : NULL;
+    uint8_t *marked = nn_mark ? (uint8_t *)calloc(obs->n ? (size_t)obs->n : 1, 1) : NULL;
     or_cloud R;
-    if (!dren || (use_rgb && !cren) || or_cloud_alloc(&R, N, use_rgb)) {
-        free(dren); free(cren); return -2;
+    if (!dren || (use_rgb && !cren) || (nn_mark && !marked) || or_cloud_alloc(&R, N, use_rgb)) {
+        free(dren); free(cren); free(marked); return -2;
     }
     if (oracle_render(m, pose, K, dren, NULL, cren) != 0) { rc = -1; goto done; }
 
@@ -532,11 +546,12 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     int32_t jr = 0;
     for (int32_t r = 0; r < R.n; ++r) {
         int32_t nn = -1;
-        int found = or_search(obs, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb, &nn);
+        int found = or_search(obs, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb || nn_mark, &nn);
         int flag = 1;
         if (!found) flag = 2;
         else if (use_rgb && oracle_ciede2000_32(R.lab + 3 * (size_t)r, obs->lab + 3 * (size_t)nn) > sc->tau_c) flag = 3;
         if (flag != 1) jr++;
+        else if (nn_mark) marked[nn] = 1;          /* R12 */
         if (r_flag) r_flag[R.pix[r]] = (uint8_t)flag;
     }
 
@@ -557,6 +572,18 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
         int in;
         if (vol == OR_VOL_LABEL) {
             in = sc->labels && sc->labels[k] == label;
+        } else if (vol == OR_VOL_CYL) {
+            double e0 = (double)obs->x[p] / 16.0 - (double)pose[3];
+            double e1 = (double)obs->y[p] / 16.0 - (double)pose[7];
+            double e2 = (double)obs->z[p] / 16.0 - (double)pose[11];
+            double q0 = ((double)pose[0] * e0 + (double)pose[4] * e1) + (double)pose[8] * e2;
+            double q1 = ((double)pose[1] * e0 + (double)pose[5] * e1) + (double)pose[9] * e2;
+            double q2 = ((double)pose[2] * e0 + (double)pose[6] * e1) + (double)pose[10] * e2;
+            double c0 = (lo[0] + hi[0]) / 2.0, c1 = (lo[1] + hi[1]) / 2.0;
+            double h0 = (hi[0] - lo[0]) / 2.0, h1 = (hi[1] - lo[1]) / 2.0;
+            double rho = (h0 < h1 ? h0 : h1) + dl;
+            double a = q0 - c0, b = q1 - c1;
+            in = (a * a + b * b <= rho * rho) && (lo[2] - dl <= q2) && (q2 <= hi[2] + dl);
         } else {
             double e0 = (double)obs->x[p] / 16.0 - (double)pose[3];
             double e1 = (double)obs->y[p] / 16.0 - (double)pose[7];
@@ -569,17 +596,22 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
         }
         if (!in) continue;
         q++;
-        int32_t nn = -1;
-        int found = or_search(&R, obs->x[p], obs->y[p], obs->z[p], dq2, dq, use_rgb, &nn);
         int flag = 1;
-        if (!found) flag = 2;
-        else if (use_rgb && oracle_ciede2000_32(obs->lab + 3 * (size_t)p, R.lab + 3 * (size_t)nn) > sc->tau_c) flag = 3;
+        if (nn_mark) {
+            if (!marked[p]) flag = 2;
+        } else {
+            int32_t nn = -1;
+            int found = or_search(&R, obs->x[p], obs->y[p], obs->z[p], dq2, dq, use_rgb, &nn);
+            if (!found) flag = 2;
+            else if (use_rgb && oracle_ciede2000_32(obs->lab + 3 * (size_t)p, R.lab + 3 * (size_t)nn) > sc->tau_c)
+                flag = 3;
+        }
         if (flag != 1) jo++;
         if (o_flag) o_flag[k] = (uint8_t)flag;
     }
     out[0] = jr; out[1] = jo; out[2] = R.n; out[3] = q;
 done:
-    free(dren); free(cren); or_cloud_free(&R);
+    free(dren); free(cren); free(marked); or_cloud_free(&R);
     return rc;
 }
 
@@ -589,7 +621,8 @@ static int or_scene_valid(const oracle_mesh *m, const oracle_scene *sc)
     if (!(sc->delta_mm > 0.0f) || sc->stride < 1) return 0;
     if ((sc->flags & OR_USE_RGB) && (!sc->rgb || !m->rgb)) return 0;
     uint32_t vol = sc->flags & OR_VOL_MASK;
-    if (vol != OR_VOL_AABB && vol != OR_VOL_LABEL) return 0;
+    if (vol != OR_VOL_AABB && vol != OR_VOL_CYL && vol != OR_VOL_LABEL) return 0;
+    if (sc->flags & ~(OR_USE_RGB | OR_MARK_OCCLUDERS | OR_VOL_MASK | OR_JO_NN)) return 0;
     if (vol == OR_VOL_LABEL && !sc->labels) return 0;
     for (int32_t t = 0; t < 3 * m->n_tris; ++t)
         if (m->tri[t] < 0 || m->tri[t] >= m->n_verts) return 0;

@@ -1,0 +1,137 @@
+"""Pins for the oracle's paper-faithful variants (CPU only): the inscribed-
+cylinder volume V(O) (Sec. III-A's conservative volume) and nearest-
+neighbour marking of J_o (the paper's J_o kernel, Sec. IV-A "Parallel Cost
+Computation").
+
+Cylinder: a cylinder mesh is its own inscribed cylinder, so every point of
+it lies inside; a box seen with its corners in view loses exactly its
+corner points; the volume grows with delta and never exceeds the box volume.
+NN marking: it explains a subset of what the exact Eq. 3 test explains; for a
+delta below the point spacing, where no point has two neighbours, the two
+coincide; every marked point needs its own inlier; a noiseless self-render
+marks every observed point.
+"""
+import numpy as np
+
+import oracle
+from paper_2008_00326_amd.workloads import meshes
+from tiny_meshes import TScene, box, pose_matrix, rot_x, rot_z
+
+K = (96, 72, 110.0, 110.0, 48.0, 36.0)
+
+
+def _alone(mesh, pose, Kc=K):
+    d, _, c = oracle.render(mesh, pose, Kc)
+    return TScene(Kc, d, c, None)
+
+
+def _score(mesh, scene, poses, delta, flags, tau=20.0, stride=1):
+    return oracle.score(mesh, scene, np.asarray(poses, np.float32).reshape(-1, 12), delta_mm=delta, tau_c=tau,
+                        flags=flags, stride=stride, threads=4)
+
+
+def _poses_around(pose, n, seed, spread=(15, 15, 25)):
+    rng = np.random.default_rng(seed)
+    P = pose.reshape(3, 4).astype(np.float64)
+    out = []
+    for _ in range(n):
+        R = rot_z(rng.normal(0, 0.3)) @ rot_x(rng.normal(0, 0.2)) @ P[:, :3]
+        out.append(pose_matrix(R, P[:, 3] + rng.normal(0, spread)))
+    return np.stack(out)
+
+
+def _cylinder_mesh():
+    m = meshes.cylinder(40.0, 90.0, 600)
+    return m.with_colours(np.random.default_rng(3), name="cyl")
+
+
+# ------------------------------------------------------------ inscribed cylinder
+
+def test_cylinder_mesh_lies_inside_its_own_cylinder():
+    cyl = _cylinder_mesh()
+    pose = pose_matrix(rot_x(2.2) @ rot_z(0.4), (5, -3, 520))
+    scene = _alone(cyl, pose)
+    n_obj = int((scene.depth > 0).sum())
+    # delta covers the depth rounding (0.5 mm along the ray) and the polygon's
+    # shortfall from its circle (r (1 - cos(pi / 21)) = 0.45 mm)
+    for delta in (2.0, 10.0):
+        _, _, _, q_cyl = _score(cyl, scene, [pose], delta, oracle.VOL_CYL)
+        _, _, _, q_box = _score(cyl, scene, [pose], delta, oracle.VOL_AABB)
+        assert q_cyl[0] == q_box[0] == n_obj
+
+
+def test_box_corners_fall_outside_the_cylinder():
+    cube = box((-40, -40, 0), (40, 40, 80), n=4, rgb_seed=2)
+    pose = pose_matrix(rot_x(2.5) @ rot_z(0.785), (0, 0, 480))      # a vertical edge faces the camera
+    scene = _alone(cube, pose)
+    n_obj = int((scene.depth > 0).sum())
+    _, _, _, q_box = _score(cube, scene, [pose], 1.0, oracle.VOL_AABB)
+    _, _, _, q_cyl = _score(cube, scene, [pose], 1.0, oracle.VOL_CYL)
+    assert q_box[0] == n_obj
+    assert 0 < q_cyl[0] < n_obj
+    # with delta past the corner distance (40 sqrt2 - 40 = 16.6 mm) every box point is inside again
+    _, _, _, q_wide = _score(cube, scene, [pose], 17.5, oracle.VOL_CYL)
+    assert q_wide[0] == n_obj
+
+
+def test_cylinder_volume_monotone_and_inside_box():
+    cube = box((-30, -50, 0), (30, 50, 70), n=3, rgb_seed=4)
+    pose = pose_matrix(rot_x(2.3) @ rot_z(0.2), (8, 4, 500))
+    scene = _alone(cube, pose)
+    poses = _poses_around(pose, 12, 1)
+    prev = None
+    for delta in (2.0, 6.0, 12.0, 24.0):
+        _, _, _, qc = _score(cube, scene, poses, delta, oracle.VOL_CYL)
+        _, _, _, qb = _score(cube, scene, poses, delta, oracle.VOL_AABB)
+        assert np.all(qc <= qb)
+        if prev is not None:
+            assert np.all(qc >= prev)
+        prev = qc
+
+
+# ------------------------------------------------------------ NN marking of J_o
+
+def _noisy_scene(seed):
+    rng = np.random.default_rng(seed)
+    m = meshes.make_shape(meshes.SHAPES[seed % len(meshes.SHAPES)], 400, rng).with_colours(rng, name="m")
+    pose = pose_matrix(rot_x(2.4) @ rot_z(rng.uniform(0, 6)), (rng.uniform(-20, 20), rng.uniform(-20, 20), 560))
+    d, _, c = oracle.render(m, pose, K)
+    valid = d > 0
+    d = np.where(valid, np.clip(np.rint(d + rng.normal(0, 2.0, d.shape)), 1, 65534), 0).astype(np.uint16)
+    c = np.clip(np.rint(c + rng.normal(0, 5.0, c.shape)), 0, 255).astype(np.uint8)
+    return m, TScene(K, d, c, None), _poses_around(pose, 10, seed + 1)
+
+
+def test_nn_marking_explains_a_subset():
+    differ = 0
+    for seed in range(4):
+        m, scene, poses = _noisy_scene(seed)
+        for delta in (4.0, 12.0, 20.0):
+            jr_e, jo_e, nr_e, nq_e = _score(m, scene, poses, delta, oracle.MARK_OCCLUDERS)
+            jr_n, jo_n, nr_n, nq_n = _score(m, scene, poses, delta, oracle.MARK_OCCLUDERS | oracle.JO_NN)
+            assert np.array_equal(jr_e, jr_n) and np.array_equal(nr_e, nr_n) and np.array_equal(nq_e, nq_n)
+            assert np.all(jo_n >= jo_e)
+            assert np.all(nq_n - jo_n <= nr_n - jr_n)          # every marked point has its own inlier
+            differ += int(np.sum(jo_n > jo_e))
+            # with the colour term as well
+            jr_c, jo_c, nr_c, nq_c = _score(m, scene, poses, delta, oracle.USE_RGB | oracle.JO_NN, tau=15.0)
+            assert np.all(nq_c - jo_c <= nr_c - jr_c)
+    assert differ > 0             # where points have several neighbours the variants differ
+
+
+def test_nn_marking_equals_exact_below_point_spacing():
+    # at 560 mm one pixel spans ~5 mm, so delta = 1 mm never holds two points of either cloud
+    for seed in range(3):
+        m, scene, poses = _noisy_scene(10 + seed)
+        _, jo_e, _, _ = _score(m, scene, poses, 1.0, oracle.MARK_OCCLUDERS)
+        _, jo_n, _, _ = _score(m, scene, poses, 1.0, oracle.MARK_OCCLUDERS | oracle.JO_NN)
+        assert np.array_equal(jo_e, jo_n)
+
+
+def test_nn_marking_self_render_explains_everything():
+    cyl = _cylinder_mesh()
+    pose = pose_matrix(rot_x(2.2) @ rot_z(0.4), (5, -3, 520))
+    scene = _alone(cyl, pose)
+    for flags in (oracle.JO_NN, oracle.JO_NN | oracle.USE_RGB):
+        jr, jo, nr, nq = _score(cyl, scene, [pose], 10.0, flags)
+        assert jr[0] == 0 and jo[0] == 0 and nr[0] == nq[0] > 0
