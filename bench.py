@@ -77,6 +77,10 @@ def main():
     ap.add_argument("--rates", default="20,50,100", help="config 5: arrival rates, scenes/s")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="config 5: arrival window per rate")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--volume", choices=["aabb", "cyl", "label"], default=None,
+                    help="V(O) of the plain run (default: the workload's)")
+    ap.add_argument("--jo", choices=["exact", "nn"], default=None,
+                    help="J_o of the plain run: the exact Eq. 3 test or nearest-neighbour marking")
     ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -130,6 +134,10 @@ def main():
 
     _log(f"[bench] generating config {args.config} seed {args.seed}")
     w = make_config(args.config, args.seed)
+    if args.volume:
+        w.volume = args.volume
+    if args.jo:
+        w.jo = args.jo
     dev = torch.device("cuda:0")
     ctx = pk.Context(0)
     if args.tuning:
@@ -224,6 +232,7 @@ def main():
         "config": {"workload": w.name, "config": args.config, "seed": args.seed, "objects": len(w.objects),
                    "poses_per_step": n_poses, "image": [int(W), int(H)], "triangles": [m.n_tris for m in w.meshes],
                    "delta_mm": w.delta_mm, "tau_c": w.tau_c if w.use_rgb else None, "path": "plain",
+                   "volume": w.volume, "jo": w.jo,
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "set_scene_and_meshes": round(scene_ms, 3)},
@@ -468,7 +477,8 @@ def cpu_baseline(w, sample):
     rng = np.random.default_rng(12345)
     per = max(1, sample // len(w.objects))
     flags = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0)
-    flags |= oracle.VOL_LABEL if w.volume == "label" else oracle.VOL_AABB
+    flags |= {"aabb": oracle.VOL_AABB, "cyl": oracle.VOL_CYL, "label": oracle.VOL_LABEL}[w.volume]
+    flags |= oracle.JO_NN if w.jo == "nn" else 0
     n = 0
     t0 = time.perf_counter()
     for o in w.objects:

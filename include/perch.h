@@ -66,8 +66,17 @@ typedef struct perch_ctx perch_ctx;
 #define PERCH_USE_RGB 1u           /* Eq. 4 colour term (needs scene and mesh colours) */
 #define PERCH_MARK_OCCLUDERS 2u    /* Eq. 3 occluders C from the observed depth */
 #define PERCH_VOL_AABB (0u << 4)   /* V(O): object-frame mesh AABB inflated by delta */
+#define PERCH_VOL_CYL (1u << 4)    /* V(O): cylinder about the object z axis through the centre of the
+                                    * AABB's xy extent, radius the smaller xy half-extent plus delta,
+                                    * z range of the AABB inflated by delta (Sec. III-A's conservative
+                                    * volume taken as an inscribed cylinder) */
 #define PERCH_VOL_LABEL (2u << 4)  /* V(O): observed pixels carrying the object's label (Sec. V-C) */
 #define PERCH_VOL_MASK (3u << 4)
+#define PERCH_JO_NN (1u << 6)      /* J_o by nearest-neighbour marking (Sec. IV-A, parallel cost
+                                    * computation): an observed point of V(O) is explained only when it
+                                    * is the nearest observed neighbour of a rendered inlier that passed
+                                    * the colour test; without it, any rendered point within delta (with
+                                    * a matching colour, Eq. 4) explains it, as Eq. 3 states */
 
 typedef struct {
     int32_t width, height;   /* pixels, 1 .. 4096 */
@@ -81,7 +90,7 @@ typedef struct {
     const int32_t *labels;    /* H*W host array, or NULL (required for PERCH_VOL_LABEL) */
     float delta_mm;           /* sensor resolution delta, 0 < delta <= 500 */
     float tau_c;              /* CIEDE2000 threshold tau_c >= 0, used with PERCH_USE_RGB */
-    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* */
+    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* | PERCH_JO_NN */
     int32_t stride;           /* image-space downsampling of the render, >= 1 (Sec. IV-A) */
 } perch_scene_desc;
 

@@ -434,9 +434,33 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, 
     }
 }
 
-// Is observed point (X, Y, Z in 1/16 mm) inside the object's AABB at pose P,
-// inflated by delta?  q = R^T (p - t), tested in binary64.
-__device__ __forceinline__ bool in_volume(const MeshDev &m, const float *P, int X, int Y, int dp, double dl)
+// Nearest-neighbour marks of the J_o region (J_o by marking): one bit per
+// pixel, set when the pixel's observed point is the nearest neighbour of a
+// rendered inlier.  G: the bitmap lives in device memory.
+template <bool G> struct Marks;
+template <> struct Marks<false> {
+    __device__ static void clear(uint32_t *w) { *w = 0u; }
+    __device__ static void set(uint32_t *b, int k) { atomicOr(b + (k >> 5), 1u << (k & 31)); }
+    __device__ static bool test(const uint32_t *b, int k) { return (b[k >> 5] >> (k & 31)) & 1u; }
+};
+template <> struct Marks<true> {
+    __device__ static void clear(uint32_t *w) { __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ static void set(uint32_t *b, int k)
+    {
+        __hip_atomic_fetch_or(b + (k >> 5), 1u << (k & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static bool test(const uint32_t *b, int k)
+    {
+        return (__hip_atomic_load(b + (k >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (k & 31)) & 1u;
+    }
+};
+
+// Is observed point (X, Y, Z in 1/16 mm) inside V(O) at pose P?  q = R^T (p - t)
+// in binary64, tested against the object's AABB inflated by delta or, for
+// the cylinder volume, against the cylinder about the object z axis through
+// the centre of the AABB's xy extent, of radius the smaller xy half-extent
+// plus delta, over the AABB's z range inflated by delta.
+__device__ __forceinline__ bool in_volume(const MeshDev &m, const float *P, int X, int Y, int dp, double dl, bool cyl)
 {
     const double e0 = (double)X / 16.0 - (double)P[3];
     const double e1 = (double)Y / 16.0 - (double)P[7];
@@ -444,8 +468,26 @@ __device__ __forceinline__ bool in_volume(const MeshDev &m, const float *P, int 
     const double q0 = ((double)P[0] * e0 + (double)P[4] * e1) + (double)P[8] * e2;
     const double q1 = ((double)P[1] * e0 + (double)P[5] * e1) + (double)P[9] * e2;
     const double q2 = ((double)P[2] * e0 + (double)P[6] * e1) + (double)P[10] * e2;
+    const bool inz = ((double)m.lo[2] - dl <= q2) && (q2 <= (double)m.hi[2] + dl);
+    if (cyl) {
+        const double c0 = ((double)m.lo[0] + (double)m.hi[0]) / 2.0, c1 = ((double)m.lo[1] + (double)m.hi[1]) / 2.0;
+        const double h0 = ((double)m.hi[0] - (double)m.lo[0]) / 2.0, h1 = ((double)m.hi[1] - (double)m.lo[1]) / 2.0;
+        const double rho = (h0 < h1 ? h0 : h1) + dl;
+        const double a = q0 - c0, b = q1 - c1;
+        return (a * a + b * b <= rho * rho) && inz;
+    }
     return ((double)m.lo[0] - dl <= q0) && (q0 <= (double)m.hi[0] + dl) && ((double)m.lo[1] - dl <= q1)
-           && (q1 <= (double)m.hi[1] + dl) && ((double)m.lo[2] - dl <= q2) && (q2 <= (double)m.hi[2] + dl);
+           && (q1 <= (double)m.hi[1] + dl) && inz;
+}
+
+// Marks observed pixel nn (the nearest neighbour of a rendered inlier) in
+// the bitmap of the J_o region; pixels outside the region lie outside V(O).
+template <bool KG>
+__device__ __forceinline__ void mark_nn(uint32_t *bits, int nn, int W, int jx0, int jy0, int jw, int jh)
+{
+    const int ny = nn / W;
+    const int jx = nn - ny * W - jx0, jy = ny - jy0;
+    if (jx >= 0 && jx < jw && jy >= 0 && jy < jh) Marks<KG>::set(bits, jy * jw + jx);
 }
 
 __device__ __forceinline__ int wave_popc(bool pred)
@@ -475,10 +517,21 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     const int jpx = in.jw * in.jh;
     const bool mark = (s.flags & 2u) != 0;
     const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
+    const bool cyl = (s.flags & (3u << 4)) == (1u << 4);
+    // J_o by nearest-neighbour marking: a bitmap over the J_o region instead
+    // of keys, set by the inliers (after their colour test), with no search
+    // and no colour test of its own.  Its poses are never banded.
+    const bool nnm = (s.flags & 64u) != 0;
+    uint32_t *bits = reinterpret_cast<uint32_t *>(keys);
+    const bool ocol = rgb && !nnm;
 
-    const int band0 = (!G && !KG && BLOCK == 1024 && tpx + jpx > w.cap_large) ? (w.cap_large - tpx) : jpx;
+    const int band0 = (!nnm && !G && !KG && BLOCK == 1024 && tpx + jpx > w.cap_large) ? (w.cap_large - tpx) : jpx;
     for (int k = tid; k < tpx; k += BLOCK) tst<G>(tile + k, kEmptyKey);
-    for (int k = tid; k < min(jpx, band0); k += BLOCK) K::store(keys + k, K::kEmpty);
+    if (nnm) {
+        for (int k = tid; k < (jpx + 31) >> 5; k += BLOCK) Marks<KG>::clear(bits + k);
+    } else {
+        for (int k = tid; k < min(jpx, band0); k += BLOCK) K::store(keys + k, K::kEmpty);
+    }
     if (tid < 4) cnt[tid] = 0;
     __syncthreads();
 
@@ -522,7 +575,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     // of rows; phases 3 and 4 then run once per band, every inlier marking
     // the band's keys, and the J_r counts are taken in the first band.
     int hb = in.jh;
-    if (!G && !KG && BLOCK == 1024 && in.jw > 0 && tpx + jpx > w.cap_large) hb = (w.cap_large - tpx) / in.jw;
+    if (!nnm && !G && !KG && BLOCK == 1024 && in.jw > 0 && tpx + jpx > w.cap_large) hb = (w.cap_large - tpx) / in.jw;
     const int nb = in.jh > 0 ? (in.jh + hb - 1) / hb : 1;
     int cR = 0, cQ = 0, cO = 0;
     const double dl = (double)s.delta;
@@ -554,11 +607,12 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     const int e = (int)(key >> 16) - (th.y & 0xFFFF);
                     const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
                     miss = first && nn < 0;
-                    if (nn >= 0 && ((rgb && first) || bpx > 0)) {
+                    if (nnm && !rgb && nn >= 0) mark_nn<KG>(bits, nn, s.W, in.jx0, in.jy0, in.jw, in.jh);
+                    if (nn >= 0 && ((rgb && first) || (bpx > 0 && !nnm))) {
                         const int slot = atomicAdd(qn, 1);
                         queue[slot] = k;
                         queue2[slot] = nn;
-                        if (bpx > 0) {
+                        if (bpx > 0 && !nnm) {
                             int X, Y, wuv;
                             mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
                             mx[slot] = X;
@@ -571,7 +625,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             cR += wave_popc(miss);
             __syncthreads();
             const int nq = *qn;
-            if (bpx > 0) {
+            if (bpx > 0 && !nnm) {
                 for (int t = wave; t < nq; t += NW) {
                     const int kk = queue[t];
                     const int ty = kk / in.tw, tx = kk - ty * in.tw;
@@ -590,6 +644,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                         srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
                     if (labs) labs[kk] = lr;     // kept for the J_o test of the points this inlier keys
                     out = ciede2000(lr, gld(s.olab + queue2[tid])) > s.tau;
+                    if (nnm && !out) mark_nn<KG>(bits, queue2[tid], s.W, in.jx0, in.jy0, in.jw, in.jh);
                 }
                 cR += wave_popc(out);
             }
@@ -606,7 +661,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
         const int rpx = max(rb - ra, 0) * in.vw;
         for (int k0 = 0; k0 < rpx; k0 += BLOCK) {
             const int k = k0 + tid;
-            if (rgb) {
+            if (ocol) {
                 if (tid == 0) *qn = 0;
                 __syncthreads();
             }
@@ -618,12 +673,20 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 const int4 q = gld(s.opt + pix);
                 if (q.z != kNoPoint) {
                     const int dp = q.z >> 4;
-                    inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl);
+                    inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl, cyl);
                     typename K::T nk = K::kEmpty;
+                    bool expl = false;
                     const int jx = i - in.jx0, jy = j - by0;
-                    if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < bh) nk = K::load(keys + jy * in.jw + jx);
-                    out = inq && nk == K::kEmpty;
-                    if (rgb && inq && nk != K::kEmpty) {
+                    if (inq && jx >= 0 && jx < in.jw && jy >= 0 && jy < bh) {
+                        if (nnm) {
+                            expl = Marks<KG>::test(bits, jy * in.jw + jx);
+                        } else {
+                            nk = K::load(keys + jy * in.jw + jx);
+                            expl = nk != K::kEmpty;
+                        }
+                    }
+                    out = inq && !expl;
+                    if (ocol && inq && expl) {
                         const int slot = atomicAdd(qn, 1);
                         queue[slot] = pix;
                         queue2[slot] = K::index(nk);
@@ -632,7 +695,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             }
             cQ += wave_popc(inq);
             cO += wave_popc(out);
-            if (rgb) {
+            if (ocol) {
                 __syncthreads();
                 const int nq = *qn;
                 bool cout = false;
@@ -840,12 +903,15 @@ __device__ int classify_pose(const Work &w, int p)
     w.info[p] = in;
     // LDS words: tile + 32-bit keys; 32-bit keys need d2 < 2^16 and tile
     // indices < 2^16, otherwise the pose is scored from device memory
+    // (J_o by nearest-neighbour marking: a bitmap, one bit per pixel, with
+    // no index to hold and no bands)
+    const bool nnm = (s.flags & 64u) != 0;
     const int tile_words = in.tw * in.th;
-    const int words = tile_words + in.jw * in.jh;
+    const int words = tile_words + (nnm ? (in.jw * in.jh + 31) / 32 : in.jw * in.jh);
     int cls = tile_words <= w.cap_large ? 2 : 3;
-    if (it.key32) {
+    if (it.key32 || nnm) {
         if (words <= w.cap_large) cls = words <= w.cap_small ? 0 : 1;
-        else if (w.key_bands && tile_words + in.jw <= w.cap_large) cls = 1;   // J_o keys in bands of rows
+        else if (!nnm && w.key_bands && tile_words + in.jw <= w.cap_large) cls = 1;   // J_o keys in bands of rows
     }
     const int strip = min(max(((in.tx0 + in.tw / 2) * kNumStrips) / s.W, 0), kNumStrips - 1);
     // within a strip: costliest first for one scene; by scene group when the

@@ -814,10 +814,11 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (!(d->delta_mm > 0.0f) || !(d->delta_mm <= 500.0f)) return fail(PERCH_EINVAL, "delta_mm must be in (0, 500]");
     if (!(d->tau_c >= 0.0f) || !std::isfinite(d->tau_c)) return fail(PERCH_EINVAL, "tau_c must be finite and >= 0");
     if (d->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
-    const uint32_t known = PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK;
+    const uint32_t known = PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN;
     if (d->flags & ~known) return fail(PERCH_EINVAL, "unknown flag bits 0x%x", d->flags & ~known);
     const uint32_t vol = d->flags & PERCH_VOL_MASK;
-    if (vol != PERCH_VOL_AABB && vol != PERCH_VOL_LABEL) return fail(PERCH_EINVAL, "unsupported volume mode");
+    if (vol != PERCH_VOL_AABB && vol != PERCH_VOL_CYL && vol != PERCH_VOL_LABEL)
+        return fail(PERCH_EINVAL, "unsupported volume mode");
     if ((d->flags & PERCH_USE_RGB) && !d->rgb) return fail(PERCH_EINVAL, "PERCH_USE_RGB needs scene rgb");
     if (vol == PERCH_VOL_LABEL && !d->labels) return fail(PERCH_EINVAL, "PERCH_VOL_LABEL needs labels");
     const int W = K.width, H = K.height;

@@ -55,7 +55,8 @@ class Workload:
     tau_c: float = 20.0
     use_rgb: bool = True
     mark_occluders: bool = True
-    volume: str = "aabb"           # "aabb" | "label"
+    volume: str = "aabb"           # "aabb" | "cyl" | "label"
+    jo: str = "exact"              # "exact" (Eq. 3) | "nn" (nearest-neighbour marking)
     stride: int = 1
     info: dict = field(default_factory=dict)
 
