@@ -497,7 +497,7 @@ __device__ __forceinline__ int wave_popc(bool pred)
 
 // ------------------------------------------------------------------ per pose
 
-template <int BLOCK, bool G, bool KG, bool RGB>
+template <int BLOCK, bool G, bool KG, bool RGB, bool NN>
 __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, float4 *labs, int *cnt,
                            int *queue, int *queue2, int *mx, int *my, int *mw, int *qn)
 {
@@ -521,7 +521,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     // J_o by nearest-neighbour marking: a bitmap over the J_o region instead
     // of keys, set by the inliers (after their colour test), with no search
     // and no colour test of its own.  Its poses are never banded.
-    const bool nnm = (s.flags & 64u) != 0;
+    const bool nnm = NN && (s.flags & 64u) != 0;
     uint32_t *bits = reinterpret_cast<uint32_t *>(keys);
     const bool ocol = rgb && !nnm;
 
@@ -735,9 +735,10 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
 
 // Persistent scoring kernel for one size class.  G: the tile lives in
 // device memory instead of LDS; KG: the J_o keys live in device memory
-// (64-bit) instead of LDS (32-bit, after the tile).  RGB: the colour term is
-// compiled in (taken per scene).  Work-groups take the class's poses in turn.
-template <int BLOCK, bool G, bool KG, bool RGB>
+// (64-bit) instead of LDS (32-bit, after the tile).  RGB, NN: the colour
+// term and J_o by nearest-neighbour marking are compiled in (each taken per
+// scene).  Work-groups take the class's poses in turn.
+template <int BLOCK, bool G, bool KG, bool RGB, bool NN>
 __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
 {
     extern __shared__ uint32_t smem[];
@@ -779,7 +780,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
                 keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
             else
                 keys = smem + w.info[p].tw * w.info[p].th;
-            score_pose<BLOCK, G, KG, RGB>(w, p, tile, keys, labs, cnt, queue, queue2, mx, my, mw, &qn);
+            score_pose<BLOCK, G, KG, RGB, NN>(w, p, tile, keys, labs, cnt, queue, queue2, mx, my, mw, &qn);
         }
     }
 }
@@ -1328,24 +1329,24 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *op
     return hipGetLastError();
 }
 
-template <int BLOCK, bool G, bool KG, bool RGB>
+template <int BLOCK, bool G, bool KG, bool RGB, bool NN>
 static hipError_t launch_one(const Work &w, int cls, int grid, int lds_words, hipStream_t st)
 {
-    score_kernel<BLOCK, G, KG, RGB><<<grid, BLOCK, (size_t)lds_words * 4, st>>>(w, cls);
+    score_kernel<BLOCK, G, KG, RGB, NN><<<grid, BLOCK, (size_t)lds_words * 4, st>>>(w, cls);
     return hipGetLastError();
 }
 
-template <bool RGB>
+template <bool RGB, bool NN>
 static hipError_t prepare_t(int lds_per_group, int static_bytes[3])
 {
     struct K {
         const void *f;
         int slot;
     };
-    const K ks[] = {{(const void *)score_kernel<256, false, false, RGB>, 0},
-                    {(const void *)score_kernel<512, false, false, RGB>, 1},
-                    {(const void *)score_kernel<1024, false, false, RGB>, 2},
-                    {(const void *)score_kernel<1024, false, true, RGB>, 2}};
+    const K ks[] = {{(const void *)score_kernel<256, false, false, RGB, NN>, 0},
+                    {(const void *)score_kernel<512, false, false, RGB, NN>, 1},
+                    {(const void *)score_kernel<1024, false, false, RGB, NN>, 2},
+                    {(const void *)score_kernel<1024, false, true, RGB, NN>, 2}};
     for (const K &k : ks) {
         hipFuncAttributes a{};
         hipError_t e = hipFuncGetAttributes(&a, k.f);
@@ -1361,20 +1362,22 @@ static hipError_t prepare_t(int lds_per_group, int static_bytes[3])
 hipError_t prepare_score_kernels(int lds_per_group, int static_bytes[3])
 {
     static_bytes[0] = static_bytes[1] = static_bytes[2] = 0;
-    hipError_t e = prepare_t<false>(lds_per_group, static_bytes);
-    return e == hipSuccess ? prepare_t<true>(lds_per_group, static_bytes) : e;
+    hipError_t e = prepare_t<false, false>(lds_per_group, static_bytes);
+    if (e == hipSuccess) e = prepare_t<true, false>(lds_per_group, static_bytes);
+    if (e == hipSuccess) e = prepare_t<false, true>(lds_per_group, static_bytes);
+    return e == hipSuccess ? prepare_t<true, true>(lds_per_group, static_bytes) : e;
 }
 
-template <bool RGB>
+template <bool RGB, bool NN>
 static hipError_t launch_class_t(const Work &w, const LaunchCfg &c, int cls, hipStream_t st)
 {
     switch (cls) {
     case 0:
-        return c.small_block == 256 ? launch_one<256, false, false, RGB>(w, 0, c.grid[0], c.cap_small, st)
-                                    : launch_one<512, false, false, RGB>(w, 0, c.grid[0], c.cap_small, st);
-    case 1: return launch_one<1024, false, false, RGB>(w, 1, c.grid[1], c.cap_large, st);
-    case 2: return launch_one<1024, false, true, RGB>(w, 2, c.grid[2], c.cap_large, st);
-    default: return launch_one<256, true, true, RGB>(w, 3, c.grid[3], 0, st);
+        return c.small_block == 256 ? launch_one<256, false, false, RGB, NN>(w, 0, c.grid[0], c.cap_small, st)
+                                    : launch_one<512, false, false, RGB, NN>(w, 0, c.grid[0], c.cap_small, st);
+    case 1: return launch_one<1024, false, false, RGB, NN>(w, 1, c.grid[1], c.cap_large, st);
+    case 2: return launch_one<1024, false, true, RGB, NN>(w, 2, c.grid[2], c.cap_large, st);
+    default: return launch_one<256, true, true, RGB, NN>(w, 3, c.grid[3], 0, st);
     }
 }
 
@@ -1386,9 +1389,11 @@ hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, hipStream_t st)
+hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_nn, hipStream_t st)
 {
-    return any_rgb ? launch_class_t<true>(w, c, cls, st) : launch_class_t<false>(w, c, cls, st);
+    if (any_nn)
+        return any_rgb ? launch_class_t<true, true>(w, c, cls, st) : launch_class_t<false, true>(w, c, cls, st);
+    return any_rgb ? launch_class_t<true, false>(w, c, cls, st) : launch_class_t<false, false>(w, c, cls, st);
 }
 
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st)

@@ -312,10 +312,12 @@ struct perch_batch {
     LaunchBufs lb;
     void *pin_desc = nullptr, *pin_best = nullptr;
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // the launch captured twice: [1] with J_o by nearest-neighbour marking
+    // compiled in, [0] without it (the set's scenes pick one)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
-    bool pending = false, valid = false;
+    bool pending = false, valid = false, any_nn = false;
     int n_req = 0;
     std::vector<int32_t> scene_ids, mesh_ids;
     std::vector<int> item_of_req;
@@ -413,6 +415,7 @@ struct Built {
     int n_items = 0, n_poses = 0;
     size_t max_pixels = 0;
     bool any_rgb = false;
+    bool any_nn = false;   // some scene takes J_o by nearest-neighbour marking
     std::vector<int32_t> scene_ids, mesh_ids;
     std::vector<int> item_of_req;   // item index of each request, -1 if it has no poses
 };
@@ -477,6 +480,7 @@ perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_
         total += q.n_poses;
         b.max_pixels = std::max(b.max_pixels, (size_t)sd.W * sd.H);
         b.any_rgb |= (sd.flags & PERCH_USE_RGB) != 0;
+        b.any_nn |= (sd.flags & PERCH_JO_NN) != 0;
     }
     if (total >= (1LL << 30)) return fail(PERCH_EINVAL, "too many poses in one launch (%lld)", total);
     b.n_items = (int)items.size();
@@ -575,12 +579,12 @@ Work make_work(const LaunchBufs &lb, const Built &b, int cap_poses, const Launch
 // Enqueue a launch: classify, score the four footprint classes, and the
 // per-item argmin when w.best is set.
 hipError_t enqueue(perch_ctx *ctx, const Work &w, const LaunchCfg &cfg, int poses_grid, int items_grid, bool any_rgb,
-                   hipStream_t st, bool timed)
+                   bool any_nn, hipStream_t st, bool timed)
 {
     auto T = [&](int slot, auto &&f) { return timed ? ctx->timed(slot, st, f) : f(); };
     hipError_t e = T(kProfSetup, [&] { return launch_setup(w, poses_grid, st); });
     for (int cls = 0; cls < kNumClasses && e == hipSuccess; ++cls)
-        e = T(kProfClass0 + cls, [&] { return launch_score_class(w, cfg, cls, any_rgb, st); });
+        e = T(kProfClass0 + cls, [&] { return launch_score_class(w, cfg, cls, any_rgb, any_nn, st); });
     if (e == hipSuccess && w.best) e = T(kProfArgmin, [&] { return launch_item_argmin(w, items_grid, st); });
     return e;
 }
@@ -630,7 +634,7 @@ perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hi
     if (perch_status s = upload(sb, b, sb.lb.desc.ptr, st)) return s;
     const Work w = make_work(sb.lb, b, b.n_poses, cfg, b.max_pixels, want_best);
     sb.last_n = b.n_poses;
-    hipError_t e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, st, true);
+    hipError_t e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, b.any_nn, st, true);
     if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
     mark_uses(ctx, b.scene_ids, b.mesh_ids, st);
     return PERCH_OK;
@@ -1205,8 +1209,10 @@ perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_p
             ctx->release(*d);
         if (b->pin_desc) (void)hipHostFree(b->pin_desc);
         if (b->pin_best) (void)hipHostFree(b->pin_best);
-        if (b->exec) (void)hipGraphExecDestroy(b->exec);
-        if (b->graph) (void)hipGraphDestroy(b->graph);
+        for (int g = 0; g < 2; ++g) {
+            if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+            if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+        }
         if (b->cap) (void)hipStreamDestroy(b->cap);
         if (b->done) (void)hipEventDestroy(b->done);
         delete b;
@@ -1224,16 +1230,18 @@ perch_status perch_batch_create(perch_ctx *ctx, int32_t max_items, int32_t max_p
     layout.scenes_off = 64 + align64((size_t)max_items * sizeof(ItemDev));
     layout.meshes_off = layout.scenes_off + align64((size_t)max_items * sizeof(SceneDev));
     const Work w = make_work(b->lb, layout, max_poses, b->cfg, b->cap_pixels, true);
-    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t c = hipMemcpyAsync(b->lb.desc.ptr, b->pin_desc, b->desc_cap, hipMemcpyHostToDevice, b->cap);
-        if (c == hipSuccess) c = enqueue(ctx, w, b->cfg, max_poses, max_items, true, b->cap, false);
-        if (c == hipSuccess)
-            c = hipMemcpyAsync(b->pin_best, b->lb.best.ptr, (size_t)8 * max_items, hipMemcpyDeviceToHost, b->cap);
-        e = hipStreamEndCapture(b->cap, &b->graph);
-        if (c != hipSuccess) e = c;
+    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t c = hipMemcpyAsync(b->lb.desc.ptr, b->pin_desc, b->desc_cap, hipMemcpyHostToDevice, b->cap);
+            if (c == hipSuccess) c = enqueue(ctx, w, b->cfg, max_poses, max_items, true, g == 1, b->cap, false);
+            if (c == hipSuccess)
+                c = hipMemcpyAsync(b->pin_best, b->lb.best.ptr, (size_t)8 * max_items, hipMemcpyDeviceToHost, b->cap);
+            e = hipStreamEndCapture(b->cap, &b->graph[g]);
+            if (c != hipSuccess) e = c;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[g], b->graph[g], nullptr, nullptr, 0);
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return cleanup(PERCH_EDEVICE, "batch graph capture", e);
     ctx->batches.push_back(b);
     *out = b;
@@ -1265,6 +1273,7 @@ perch_status perch_batch_set(perch_batch *b, const perch_work *items, int32_t n_
     b->mesh_ids = d.mesh_ids;
     b->item_of_req = d.item_of_req;
     b->n_req = n_items;
+    b->any_nn = d.any_nn;
     b->valid = true;
     return ok();
 }
@@ -1279,7 +1288,7 @@ perch_status perch_batch_launch(perch_batch *b, void *hip_stream)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!b->valid) return fail(PERCH_EINVAL, "batch has no valid work (set it again)");
     hipStream_t st = pick_stream(ctx, hip_stream);
-    HIP_TRY(hipGraphLaunch(b->exec, st));
+    HIP_TRY(hipGraphLaunch(b->exec[b->any_nn ? 1 : 0], st));
     HIP_TRY(hipEventRecord(b->done, st));
     b->pending = true;
     mark_uses(ctx, b->scene_ids, b->mesh_ids, st);
@@ -1323,8 +1332,10 @@ perch_status perch_batch_destroy(perch_batch *b)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     (void)hipSetDevice(ctx->device);
     if (b->pending) (void)hipEventSynchronize(b->done);
-    (void)hipGraphExecDestroy(b->exec);
-    (void)hipGraphDestroy(b->graph);
+    for (int g = 0; g < 2; ++g) {
+        (void)hipGraphExecDestroy(b->exec[g]);
+        (void)hipGraphDestroy(b->graph[g]);
+    }
     (void)hipStreamDestroy(b->cap);
     (void)hipEventDestroy(b->done);
     (void)hipHostFree(b->pin_desc);
