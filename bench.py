@@ -81,6 +81,10 @@ def main():
                     help="V(O) of the plain run (default: the workload's)")
     ap.add_argument("--jo", choices=["exact", "nn"], default=None,
                     help="J_o of the plain run: the exact Eq. 3 test or nearest-neighbour marking")
+    ap.add_argument("--search", choices=["table", "knn2"], default="table",
+                    help="J_r neighbour search of the plain run: the scene table or the paper's kNN II scan")
+    ap.add_argument("--poses-per-object", type=int, default=0,
+                    help="score only the first N candidates of each object (0 = all)")
     ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -138,6 +142,10 @@ def main():
         w.volume = args.volume
     if args.jo:
         w.jo = args.jo
+    w.search = args.search
+    if args.poses_per_object > 0:
+        for o in w.objects:
+            o.poses = np.ascontiguousarray(o.poses[:args.poses_per_object])
     dev = torch.device("cuda:0")
     ctx = pk.Context(0)
     if args.tuning:
@@ -232,7 +240,7 @@ def main():
         "config": {"workload": w.name, "config": args.config, "seed": args.seed, "objects": len(w.objects),
                    "poses_per_step": n_poses, "image": [int(W), int(H)], "triangles": [m.n_tris for m in w.meshes],
                    "delta_mm": w.delta_mm, "tau_c": w.tau_c if w.use_rgb else None, "path": "plain",
-                   "volume": w.volume, "jo": w.jo,
+                   "volume": w.volume, "jo": w.jo, "search": w.search,
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "set_scene_and_meshes": round(scene_ms, 3)},
@@ -475,7 +483,7 @@ def cpu_baseline(w, sample):
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     rng = np.random.default_rng(12345)
-    per = max(1, sample // len(w.objects))
+    per = max(1, min(sample // len(w.objects), min(o.poses.shape[0] for o in w.objects)))
     flags = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0)
     flags |= {"aabb": oracle.VOL_AABB, "cyl": oracle.VOL_CYL, "label": oracle.VOL_LABEL}[w.volume]
     flags |= oracle.JO_NN if w.jo == "nn" else 0

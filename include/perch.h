@@ -77,6 +77,10 @@ typedef struct perch_ctx perch_ctx;
                                     * is the nearest observed neighbour of a rendered inlier that passed
                                     * the colour test; without it, any rendered point within delta (with
                                     * a matching colour, Eq. 4) explains it, as Eq. 3 states */
+#define PERCH_KNN2 (1u << 7)       /* J_r's nearest observed neighbours by the paper's kNN II search
+                                    * (Sec. IV-A): each rendered point scans the whole observed cloud
+                                    * instead of reading the scene's neighbour table.  Same results;
+                                    * orders of magnitude slower (an in-house comparison baseline) */
 
 typedef struct {
     int32_t width, height;   /* pixels, 1 .. 4096 */
@@ -90,7 +94,7 @@ typedef struct {
     const int32_t *labels;    /* H*W host array, or NULL (required for PERCH_VOL_LABEL) */
     float delta_mm;           /* sensor resolution delta, 0 < delta <= 500 */
     float tau_c;              /* CIEDE2000 threshold tau_c >= 0, used with PERCH_USE_RGB */
-    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* | PERCH_JO_NN */
+    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* | PERCH_JO_NN | PERCH_KNN2 */
     int32_t stride;           /* image-space downsampling of the render, >= 1 (Sec. IV-A) */
 } perch_scene_desc;
 

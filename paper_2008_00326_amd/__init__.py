@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["Context", "PerchError", "load_library", "library_path", "USE_RGB", "MARK_OCCLUDERS",
-           "VOL_AABB", "VOL_CYL", "VOL_LABEL", "JO_NN"]
+           "VOL_AABB", "VOL_CYL", "VOL_LABEL", "JO_NN", "KNN2"]
 
 USE_RGB = 1
 MARK_OCCLUDERS = 2
@@ -22,8 +22,10 @@ VOL_AABB = 0 << 4
 VOL_CYL = 1 << 4
 VOL_LABEL = 2 << 4
 JO_NN = 1 << 6
+KNN2 = 1 << 7
 _VOLUMES = {"aabb": VOL_AABB, "cyl": VOL_CYL, "label": VOL_LABEL}
 _JO_MODES = {"exact": 0, "nn": JO_NN}
+_SEARCHES = {"table": 0, "knn2": KNN2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _STATUS = {0: "PERCH_OK", -1: "PERCH_EINVAL", -2: "PERCH_ENOMEM", -3: "PERCH_EDEVICE",
@@ -175,12 +177,15 @@ class Context:
         _check(self._lib.perch_unload_mesh(self._h, int(mesh_id)))
 
     def set_scene(self, K, depth, rgb=None, labels=None, *, delta_mm=10.0, tau_c=20.0, flags=None,
-                  use_rgb=None, mark_occluders=True, volume="aabb", jo="exact", stride=1) -> int:
+                  use_rgb=None, mark_occluders=True, volume="aabb", jo="exact", search="table",
+                  stride=1) -> int:
         """Upload an observed scene.  volume: "aabb", "cyl" or "label" (V(O));
         jo: "exact" (any rendered point within delta explains an observed
         point) or "nn" (only the points that are some inlier's nearest
-        neighbour are explained).  `flags`, when given, overrides use_rgb,
-        mark_occluders, volume and jo."""
+        neighbour are explained); search: "table" (the scene's neighbour
+        table) or "knn2" (the paper's scan of the whole cloud, a slow
+        baseline with the same results).  `flags`, when given, overrides
+        use_rgb, mark_occluders, volume, jo and search."""
         depth = np.ascontiguousarray(depth, np.uint16)
         rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
         labels = None if labels is None else np.ascontiguousarray(labels, np.int32)
@@ -188,9 +193,10 @@ class Context:
             if use_rgb is None:
                 use_rgb = rgb is not None
             flags = (USE_RGB if use_rgb else 0) | (MARK_OCCLUDERS if mark_occluders else 0)
-            if volume not in _VOLUMES or jo not in _JO_MODES:
-                raise ValueError(f"volume must be one of {sorted(_VOLUMES)}, jo one of {sorted(_JO_MODES)}")
-            flags |= _VOLUMES[volume] | _JO_MODES[jo]
+            if volume not in _VOLUMES or jo not in _JO_MODES or search not in _SEARCHES:
+                raise ValueError(f"volume must be one of {sorted(_VOLUMES)}, jo one of {sorted(_JO_MODES)}, "
+                                 f"search one of {sorted(_SEARCHES)}")
+            flags |= _VOLUMES[volume] | _JO_MODES[jo] | _SEARCHES[search]
         w, h, fx, fy, cx, cy = K
         desc = _SceneDesc(_Intrinsics(int(w), int(h), float(fx), float(fy), float(cx), float(cy)),
                           _np_ptr(depth), _np_ptr(rgb), _np_ptr(labels), float(delta_mm), float(tau_c),
@@ -408,6 +414,6 @@ def load_workload(ctx: Context, w, *, flags=None):
                         s.labels if w.volume == "label" else None,
                         delta_mm=w.delta_mm, tau_c=w.tau_c, flags=flags, use_rgb=w.use_rgb,
                         mark_occluders=w.mark_occluders, volume=w.volume, jo=getattr(w, "jo", "exact"),
-                        stride=w.stride)
+                        search=getattr(w, "search", "table"), stride=w.stride)
     mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb if w.use_rgb else None) for m in w.meshes]
     return sid, mids

@@ -130,7 +130,7 @@ hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
 // with w.sort, order each class list by cost bucket; run the four scoring
 // classes, then the per-item argmin if w.best is set.
 hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st);
-hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_nn, hipStream_t st);
+hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_pv, hipStream_t st);
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st);
 
 // Kernel slots reported by the profiler (perch_profile_read).

@@ -480,6 +480,47 @@ __device__ __forceinline__ bool in_volume(const MeshDev &m, const float *P, int 
            && (q1 <= (double)m.hi[1] + dl) && inz;
 }
 
+// kNN II (Sec. IV-A, parallel cost computation): the nearest observed point
+// of rendered point (X, Y, Z) found by one thread scanning the whole observed
+// cloud, as the paper's reduced-parallelism search does.  Same result as the
+// scene table: the smallest (d², pixel index) within delta, or -1.  The scan
+// address is uniform, so the points come through the scalar cache.
+__device__ __noinline__ int scan_nn(const SceneDev &s, int X, int Y, int Z)
+{
+    const int lim = s.dq + 1, dq2 = s.dq2;
+    const int n = s.W * s.H;
+    int best = dq2 + 1, nn = -1;
+    int p = 0;
+    for (; p + 4 <= n; p += 4) {
+        int4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = gld(s.opt + p + u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int dx = clamp_i32(q[u].x - X, -lim, lim);
+            const int dy = clamp_i32(q[u].y - Y, -lim, lim);
+            const int dz = clamp_i32(q[u].z - Z, -lim, lim);
+            const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
+            if (d2 < best) {
+                best = d2;
+                nn = p + u;
+            }
+        }
+    }
+    for (; p < n; ++p) {
+        const int4 q = gld(s.opt + p);
+        const int dx = clamp_i32(q.x - X, -lim, lim);
+        const int dy = clamp_i32(q.y - Y, -lim, lim);
+        const int dz = clamp_i32(q.z - Z, -lim, lim);
+        const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
+        if (d2 < best) {
+            best = d2;
+            nn = p;
+        }
+    }
+    return nn;
+}
+
 // Marks observed pixel nn (the nearest neighbour of a rendered inlier) in
 // the bitmap of the J_o region; pixels outside the region lie outside V(O).
 template <bool KG>
@@ -497,7 +538,7 @@ __device__ __forceinline__ int wave_popc(bool pred)
 
 // ------------------------------------------------------------------ per pose
 
-template <int BLOCK, bool G, bool KG, bool RGB, bool NN>
+template <int BLOCK, bool G, bool KG, bool RGB, bool PV>
 __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, float4 *labs, int *cnt,
                            int *queue, int *queue2, int *mx, int *my, int *mw, int *qn)
 {
@@ -521,7 +562,8 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     // J_o by nearest-neighbour marking: a bitmap over the J_o region instead
     // of keys, set by the inliers (after their colour test), with no search
     // and no colour test of its own.  Its poses are never banded.
-    const bool nnm = NN && (s.flags & 64u) != 0;
+    const bool nnm = PV && (s.flags & 64u) != 0;
+    const bool knn2 = PV && (s.flags & 128u) != 0;     // J_r neighbours by the kNN II scan
     uint32_t *bits = reinterpret_cast<uint32_t *>(keys);
     const bool ocol = rgb && !nnm;
 
@@ -603,9 +645,16 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 const uint32_t key = tld<G>(tile + k);
                 if (key != kEmptyKey) {
                     const int ty = k / in.tw, tx = k - ty * in.tw;
-                    const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
-                    const int e = (int)(key >> 16) - (th.y & 0xFFFF);
-                    const int nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
+                    int nn;
+                    if (knn2) {
+                        int X, Y, wuv;
+                        mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
+                        nn = scan_nn(s, X, Y, 16 * (int)(key >> 16));
+                    } else {
+                        const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
+                        const int e = (int)(key >> 16) - (th.y & 0xFFFF);
+                        nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
+                    }
                     miss = first && nn < 0;
                     if (nnm && !rgb && nn >= 0) mark_nn<KG>(bits, nn, s.W, in.jx0, in.jy0, in.jw, in.jh);
                     if (nn >= 0 && ((rgb && first) || (bpx > 0 && !nnm))) {
@@ -735,10 +784,11 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
 
 // Persistent scoring kernel for one size class.  G: the tile lives in
 // device memory instead of LDS; KG: the J_o keys live in device memory
-// (64-bit) instead of LDS (32-bit, after the tile).  RGB, NN: the colour
-// term and J_o by nearest-neighbour marking are compiled in (each taken per
-// scene).  Work-groups take the class's poses in turn.
-template <int BLOCK, bool G, bool KG, bool RGB, bool NN>
+// (64-bit) instead of LDS (32-bit, after the tile).  RGB: the colour term is
+// compiled in; PV: the paper's own variants, J_o by nearest-neighbour marking
+// and the kNN II scan, are compiled in (each taken per scene).  Work-groups
+// take the class's poses in turn.
+template <int BLOCK, bool G, bool KG, bool RGB, bool PV>
 __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
 {
     extern __shared__ uint32_t smem[];
@@ -780,7 +830,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
                 keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
             else
                 keys = smem + w.info[p].tw * w.info[p].th;
-            score_pose<BLOCK, G, KG, RGB, NN>(w, p, tile, keys, labs, cnt, queue, queue2, mx, my, mw, &qn);
+            score_pose<BLOCK, G, KG, RGB, PV>(w, p, tile, keys, labs, cnt, queue, queue2, mx, my, mw, &qn);
         }
     }
 }
@@ -1329,24 +1379,24 @@ hipError_t launch_scene_prep(const SceneDev &s, const uint8_t *rgb_dev, int4 *op
     return hipGetLastError();
 }
 
-template <int BLOCK, bool G, bool KG, bool RGB, bool NN>
+template <int BLOCK, bool G, bool KG, bool RGB, bool PV>
 static hipError_t launch_one(const Work &w, int cls, int grid, int lds_words, hipStream_t st)
 {
-    score_kernel<BLOCK, G, KG, RGB, NN><<<grid, BLOCK, (size_t)lds_words * 4, st>>>(w, cls);
+    score_kernel<BLOCK, G, KG, RGB, PV><<<grid, BLOCK, (size_t)lds_words * 4, st>>>(w, cls);
     return hipGetLastError();
 }
 
-template <bool RGB, bool NN>
+template <bool RGB, bool PV>
 static hipError_t prepare_t(int lds_per_group, int static_bytes[3])
 {
     struct K {
         const void *f;
         int slot;
     };
-    const K ks[] = {{(const void *)score_kernel<256, false, false, RGB, NN>, 0},
-                    {(const void *)score_kernel<512, false, false, RGB, NN>, 1},
-                    {(const void *)score_kernel<1024, false, false, RGB, NN>, 2},
-                    {(const void *)score_kernel<1024, false, true, RGB, NN>, 2}};
+    const K ks[] = {{(const void *)score_kernel<256, false, false, RGB, PV>, 0},
+                    {(const void *)score_kernel<512, false, false, RGB, PV>, 1},
+                    {(const void *)score_kernel<1024, false, false, RGB, PV>, 2},
+                    {(const void *)score_kernel<1024, false, true, RGB, PV>, 2}};
     for (const K &k : ks) {
         hipFuncAttributes a{};
         hipError_t e = hipFuncGetAttributes(&a, k.f);
@@ -1368,16 +1418,16 @@ hipError_t prepare_score_kernels(int lds_per_group, int static_bytes[3])
     return e == hipSuccess ? prepare_t<true, true>(lds_per_group, static_bytes) : e;
 }
 
-template <bool RGB, bool NN>
+template <bool RGB, bool PV>
 static hipError_t launch_class_t(const Work &w, const LaunchCfg &c, int cls, hipStream_t st)
 {
     switch (cls) {
     case 0:
-        return c.small_block == 256 ? launch_one<256, false, false, RGB, NN>(w, 0, c.grid[0], c.cap_small, st)
-                                    : launch_one<512, false, false, RGB, NN>(w, 0, c.grid[0], c.cap_small, st);
-    case 1: return launch_one<1024, false, false, RGB, NN>(w, 1, c.grid[1], c.cap_large, st);
-    case 2: return launch_one<1024, false, true, RGB, NN>(w, 2, c.grid[2], c.cap_large, st);
-    default: return launch_one<256, true, true, RGB, NN>(w, 3, c.grid[3], 0, st);
+        return c.small_block == 256 ? launch_one<256, false, false, RGB, PV>(w, 0, c.grid[0], c.cap_small, st)
+                                    : launch_one<512, false, false, RGB, PV>(w, 0, c.grid[0], c.cap_small, st);
+    case 1: return launch_one<1024, false, false, RGB, PV>(w, 1, c.grid[1], c.cap_large, st);
+    case 2: return launch_one<1024, false, true, RGB, PV>(w, 2, c.grid[2], c.cap_large, st);
+    default: return launch_one<256, true, true, RGB, PV>(w, 3, c.grid[3], 0, st);
     }
 }
 
@@ -1389,9 +1439,9 @@ hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_nn, hipStream_t st)
+hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_pv, hipStream_t st)
 {
-    if (any_nn)
+    if (any_pv)
         return any_rgb ? launch_class_t<true, true>(w, c, cls, st) : launch_class_t<false, true>(w, c, cls, st);
     return any_rgb ? launch_class_t<true, false>(w, c, cls, st) : launch_class_t<false, false>(w, c, cls, st);
 }

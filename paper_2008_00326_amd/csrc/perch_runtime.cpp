@@ -312,12 +312,13 @@ struct perch_batch {
     LaunchBufs lb;
     void *pin_desc = nullptr, *pin_best = nullptr;
     hipStream_t cap = nullptr;
-    // the launch captured twice: [1] with J_o by nearest-neighbour marking
-    // compiled in, [0] without it (the set's scenes pick one)
+    // the launch captured twice: [1] with the paper's variants (J_o by
+    // nearest-neighbour marking, the kNN II scan) compiled in, [0] without
+    // them (the set's scenes pick one)
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
-    bool pending = false, valid = false, any_nn = false;
+    bool pending = false, valid = false, any_pv = false;
     int n_req = 0;
     std::vector<int32_t> scene_ids, mesh_ids;
     std::vector<int> item_of_req;
@@ -415,7 +416,7 @@ struct Built {
     int n_items = 0, n_poses = 0;
     size_t max_pixels = 0;
     bool any_rgb = false;
-    bool any_nn = false;   // some scene takes J_o by nearest-neighbour marking
+    bool any_pv = false;   // some scene takes one of the paper's variants (NN marking, kNN II)
     std::vector<int32_t> scene_ids, mesh_ids;
     std::vector<int> item_of_req;   // item index of each request, -1 if it has no poses
 };
@@ -480,7 +481,7 @@ perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_
         total += q.n_poses;
         b.max_pixels = std::max(b.max_pixels, (size_t)sd.W * sd.H);
         b.any_rgb |= (sd.flags & PERCH_USE_RGB) != 0;
-        b.any_nn |= (sd.flags & PERCH_JO_NN) != 0;
+        b.any_pv |= (sd.flags & (PERCH_JO_NN | PERCH_KNN2)) != 0;
     }
     if (total >= (1LL << 30)) return fail(PERCH_EINVAL, "too many poses in one launch (%lld)", total);
     b.n_items = (int)items.size();
@@ -579,12 +580,12 @@ Work make_work(const LaunchBufs &lb, const Built &b, int cap_poses, const Launch
 // Enqueue a launch: classify, score the four footprint classes, and the
 // per-item argmin when w.best is set.
 hipError_t enqueue(perch_ctx *ctx, const Work &w, const LaunchCfg &cfg, int poses_grid, int items_grid, bool any_rgb,
-                   bool any_nn, hipStream_t st, bool timed)
+                   bool any_pv, hipStream_t st, bool timed)
 {
     auto T = [&](int slot, auto &&f) { return timed ? ctx->timed(slot, st, f) : f(); };
     hipError_t e = T(kProfSetup, [&] { return launch_setup(w, poses_grid, st); });
     for (int cls = 0; cls < kNumClasses && e == hipSuccess; ++cls)
-        e = T(kProfClass0 + cls, [&] { return launch_score_class(w, cfg, cls, any_rgb, any_nn, st); });
+        e = T(kProfClass0 + cls, [&] { return launch_score_class(w, cfg, cls, any_rgb, any_pv, st); });
     if (e == hipSuccess && w.best) e = T(kProfArgmin, [&] { return launch_item_argmin(w, items_grid, st); });
     return e;
 }
@@ -634,7 +635,7 @@ perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hi
     if (perch_status s = upload(sb, b, sb.lb.desc.ptr, st)) return s;
     const Work w = make_work(sb.lb, b, b.n_poses, cfg, b.max_pixels, want_best);
     sb.last_n = b.n_poses;
-    hipError_t e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, b.any_nn, st, true);
+    hipError_t e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, b.any_pv, st, true);
     if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
     mark_uses(ctx, b.scene_ids, b.mesh_ids, st);
     return PERCH_OK;
@@ -818,7 +819,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (!(d->delta_mm > 0.0f) || !(d->delta_mm <= 500.0f)) return fail(PERCH_EINVAL, "delta_mm must be in (0, 500]");
     if (!(d->tau_c >= 0.0f) || !std::isfinite(d->tau_c)) return fail(PERCH_EINVAL, "tau_c must be finite and >= 0");
     if (d->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
-    const uint32_t known = PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN;
+    const uint32_t known = PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN | PERCH_KNN2;
     if (d->flags & ~known) return fail(PERCH_EINVAL, "unknown flag bits 0x%x", d->flags & ~known);
     const uint32_t vol = d->flags & PERCH_VOL_MASK;
     if (vol != PERCH_VOL_AABB && vol != PERCH_VOL_CYL && vol != PERCH_VOL_LABEL)
@@ -1273,7 +1274,7 @@ perch_status perch_batch_set(perch_batch *b, const perch_work *items, int32_t n_
     b->mesh_ids = d.mesh_ids;
     b->item_of_req = d.item_of_req;
     b->n_req = n_items;
-    b->any_nn = d.any_nn;
+    b->any_pv = d.any_pv;
     b->valid = true;
     return ok();
 }
@@ -1288,7 +1289,7 @@ perch_status perch_batch_launch(perch_batch *b, void *hip_stream)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!b->valid) return fail(PERCH_EINVAL, "batch has no valid work (set it again)");
     hipStream_t st = pick_stream(ctx, hip_stream);
-    HIP_TRY(hipGraphLaunch(b->exec[b->any_nn ? 1 : 0], st));
+    HIP_TRY(hipGraphLaunch(b->exec[b->any_pv ? 1 : 0], st));
     HIP_TRY(hipEventRecord(b->done, st));
     b->pending = true;
     mark_uses(ctx, b->scene_ids, b->mesh_ids, st);

@@ -1,6 +1,7 @@
 """GPU parity of the paper-faithful variants against the oracle: the
-inscribed-cylinder volume V(O) (Sec. III-A's conservative volume) and J_o by
-nearest-neighbour marking (Sec. IV-A, parallel cost computation).
+inscribed-cylinder volume V(O) (Sec. III-A's conservative volume), J_o by
+nearest-neighbour marking and the kNN II search (Sec. IV-A, parallel cost
+computation).
 
 L, Q and every depth-only count are bit-exact.  With the colour term, J_r is
 within ceil(0.001 L) as elsewhere; under nearest-neighbour marking an
@@ -160,14 +161,62 @@ def test_batch_mixes_variants(ctx):
         ctx.unload_mesh(mid)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_knn2_scan_equals_table(ctx, seed):
+    """The paper's kNN II search (every rendered point scans the whole
+    observed cloud) gives the outputs of the neighbour table, bit for bit,
+    under both J_o modes; and the oracle's counts."""
+    mesh, scene, poses, p = random_case(40 + seed)
+    mid = ctx.load_mesh(mesh.xyz, mesh.tri, mesh.rgb)
+    t = torch.from_numpy(poses).cuda()
+    for jo in ("exact", "nn"):
+        outs = []
+        for search in ("table", "knn2"):
+            say(f"case {40 + seed} {jo} {search}: image {scene.K[0]}x{scene.K[1]}, {p}")
+            sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, delta_mm=p["delta"], tau_c=p["tau"],
+                                use_rgb=p["rgb"], mark_occluders=p["occl"], stride=p["stride"], jo=jo, search=search)
+            outs.append([a.cpu().numpy() for a in ctx.score_poses(sid, mid, t)])
+            torch.cuda.synchronize()
+            ctx.drop_scene(sid)
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
+        exp = oracle.score(mesh, scene, poses, delta_mm=p["delta"], tau_c=p["tau"],
+                           flags=oflags(p["rgb"], p["occl"], "aabb", jo), stride=p["stride"], threads=THREADS)
+        check(outs[1], exp, p["rgb"], jo, f"case {40 + seed} {jo} knn2")
+    ctx.unload_mesh(mid)
+
+
+def test_knn2_full_size_sample(ctx):
+    """kNN II on the 640x480 cfg2 scene for a few poses per object (each
+    rendered point scans all 307,200 pixels): the table's outputs exactly."""
+    w = make_config(2, 0)
+    s = w.scene
+    say("cfg2 kNN II sample")
+    sids = [ctx.set_scene(s.K, s.depth, s.rgb, delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=True, jo="nn", search=x)
+            for x in ("table", "knn2")]
+    rng = np.random.default_rng(11)
+    for o in w.objects:
+        mid = ctx.load_mesh(w.meshes[o.mesh].xyz, w.meshes[o.mesh].tri, w.meshes[o.mesh].rgb)
+        poses = np.concatenate([o.gt_pose[None], o.poses[rng.choice(o.poses.shape[0], 3, replace=False)]])
+        a, b = (gpu_score(ctx, sid, mid, poses, label=o.label) for sid in sids)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        assert a[2].min() > 0
+        ctx.unload_mesh(mid)
+    for sid in sids:
+        ctx.drop_scene(sid)
+
+
 def test_flag_validation(ctx):
     K = (32, 24, 30.0, 30.0, 16.0, 12.0)
     depth = np.zeros((24, 32), np.uint16)
     with pytest.raises(pk.PerchError):
         ctx.set_scene(K, depth, flags=3 << 4)             # no such volume mode
     with pytest.raises(pk.PerchError):
-        ctx.set_scene(K, depth, flags=1 << 7)             # unknown bit
+        ctx.set_scene(K, depth, flags=1 << 8)             # unknown bit
     with pytest.raises(ValueError):
         ctx.set_scene(K, depth, volume="sphere")
-    sid = ctx.set_scene(K, depth, flags=pk.VOL_CYL | pk.JO_NN | pk.MARK_OCCLUDERS)
+    with pytest.raises(ValueError):
+        ctx.set_scene(K, depth, search="kd-tree")
+    sid = ctx.set_scene(K, depth, flags=pk.VOL_CYL | pk.JO_NN | pk.KNN2 | pk.MARK_OCCLUDERS)
     ctx.drop_scene(sid)
