@@ -74,6 +74,9 @@ def _load():
         lib.oracle_score_detail.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
         lib.oracle_score_detail.restype = ctypes.c_int
         lib.oracle_best.argtypes = [P, P, ctypes.c_int32, P, P, P]
+        lib.oracle_icp.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32]
+        lib.oracle_icp_pairs.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P]
         lib.oracle_best.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -227,3 +230,42 @@ def best(jr, jo):
     if rc != 0:
         raise ValueError("oracle_best: empty input")
     return int(bi[0]), int(bc[0]), int(nt[0])
+
+
+def icp(mesh, scene, poses, *, delta_mm, flags=MARK_OCCLUDERS, label=0, rho_mm=20.0, iterations=10, stride=2,
+        dof=3, min_points=16, threads=0):
+    """ICP refinement of every pose against the observed cloud (readings
+    I1-I8 of the oracle source; Sec. IV-A "Parallel M2M GICP").
+
+    Returns (refined n x 12 float32, updates applied int32, matches of the
+    last iteration examined int32)."""
+    lib = _load()
+    m = _MeshArgs(mesh)
+    s = _SceneArgs(scene, delta_mm, 0.0, flags & ~USE_RGB, 1)
+    poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
+    n = poses.shape[0]
+    out = np.zeros((n, 12), np.float32)
+    it = np.zeros(n, np.int32)
+    mt = np.zeros(n, np.int32)
+    rc = lib.oracle_icp(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(poses), n, float(rho_mm),
+                        int(iterations), int(stride), int(dof), int(min_points), _ptr(out), _ptr(it), _ptr(mt),
+                        int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_icp failed ({rc})")
+    return out, it, mt
+
+
+def icp_pairs(src, dst, *, dof=6, axis=(0.0, 0.0, 1.0), iterations=1):
+    """The ICP update loop on fixed correspondences (dst[i] matches src[i],
+    int32 1/16 mm).  Returns (A 3x3, b 3) with dst ~ A src + b."""
+    lib = _load()
+    src = np.ascontiguousarray(src, dtype=np.int32).reshape(-1, 3)
+    dst = np.ascontiguousarray(dst, dtype=np.int32).reshape(-1, 3)
+    u = np.ascontiguousarray(axis, dtype=np.float64)
+    A = np.zeros(9, np.float64)
+    b = np.zeros(3, np.float64)
+    rc = lib.oracle_icp_pairs(_ptr(src), _ptr(dst), src.shape[0], int(dof), _ptr(u), int(iterations), _ptr(A),
+                              _ptr(b))
+    if rc != 0:
+        raise ValueError(f"oracle_icp_pairs failed ({rc})")
+    return A.reshape(3, 3), b

@@ -70,6 +70,41 @@
  *      it is an outlier.  No further colour test applies to it.
  *   R11 Selection: lowest J; ties go to the lowest pose index.
  *
+ * ICP refinement (Sec. IV-A "Parallel M2M GICP" and Sec. V-A: each pose is
+ * aligned to the observed cloud by ICP, then rendered and scored again; the
+ * 3-DoF experiments use point-to-point ICP).  The paper gives no
+ * correspondence rule, update or stopping rule; this oracle reads them as:
+ *   I1 Source: R minus C of the pose (R6, R7) on the ICP stride grid; target:
+ *      every valid observed point.  Integer 1/16 mm points.
+ *   I2 Iteration k holds a camera-frame transform (A, b), b in 1/16 mm,
+ *      starting at the identity.  Source point s maps to q with
+ *      q_a = rint(((A_a0 sx + A_a1 sy) + A_a2 sz) + b_a).
+ *   I3 The match c of q is its nearest observed point within rho: with
+ *      rq = rint(16 rho), dx^2 + dy^2 + dz^2 <= rq^2 in exact integers, ties to
+ *      the lower pixel index.  Unmatched points take no part.
+ *   I4 Exact int64 sums over the matches: n, Sq, Sc, Sqq, Sqc.  Then, in
+ *      binary64 in this order: mq = Sq / n, mc = Sc / n,
+ *      S_ab = Sqq_ab - (Sq_a Sq_b) / n, H_ab = Sqc_ab - (Sq_a Sc_b) / n,
+ *      w = (H12 - H21, H20 - H02, H01 - H10).
+ *   I5 Update, a rotation Rc about mq and the image m' of mq:
+ *      3-DoF (rotation about the pose's object z axis u, translation normal to
+ *      u): the exact planar Procrustes solution, A' = (H00 + H11) + H22 - u.Hu,
+ *      B = u.w, h = sqrt(A'^2 + B^2), (cos, sin) = (A'/h, B/h) (no rotation
+ *      when h = 0), Rc = cos I + sin [u]x + (1 - cos) u u^T,
+ *      m' = mq + (d - (u.d) u) with d = mc - mq.
+ *      6-DoF: one Gauss-Newton step of the linearised rotation about mq,
+ *      M w' = w with M = tr(S) I - S, solved by the adjugate (stop when
+ *      det M <= 0), Rc from the unit quaternion (1, w'/2) / sqrt(1 + |w'/2|^2),
+ *      m' = mc.
+ *   I6 (A, b) <- (Rc A, Rc (b - mq) + m').
+ *   I7 Before each iteration k > 0 ICP stops when the quantised q equal
+ *      those of the previous iteration (the update would repeat); it stops
+ *      after K iterations, and when fewer than min_points points match.
+ *   I8 Refined pose: R' = A R_P, t' = (A (16 t_P) + b) / 16, rounded to
+ *      binary32.
+ * Products and sums are written left to right as above; no fused
+ * multiply-add (as R1).
+ *
  * Colour: sRGB8 is linearised with the IEC 61966-2-1 piecewise curve (256-
  * entry table computed in binary64), mapped to XYZ with the four-digit sRGB
  * matrix, and to CIELAB with the white point equal to the matrix row sums
@@ -692,6 +727,260 @@ int oracle_score_detail(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     int rc = or_score_one(m, sc, label, pose, &obs, out, r_flag, o_flag);
     or_cloud_free(&obs);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* ICP refinement (readings I1-I8)                                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n, sq[3], sc[3], sqq[3][3], sqc[3][3];
+} or_icp_sums;
+
+static void or_icp_add(or_icp_sums *z, const int64_t q[3], const int64_t c[3])
+{
+    z->n++;
+    for (int a = 0; a < 3; ++a) {
+        z->sq[a] += q[a];
+        z->sc[a] += c[a];
+        for (int b = 0; b < 3; ++b) {
+            z->sqq[a][b] += q[a] * q[b];
+            z->sqc[a][b] += q[a] * c[b];
+        }
+    }
+}
+
+/* q = rint(A s + b) (I2). */
+static void or_icp_map(const double A[9], const double b[3], const int32_t s[3], int64_t q[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double v = ((A[3 * a] * (double)s[0] + A[3 * a + 1] * (double)s[1]) + A[3 * a + 2] * (double)s[2]) + b[a];
+        q[a] = (int64_t)nearbyint(v);
+    }
+}
+
+/* One update from the sums (I4-I6): composes the increment into (A, b).
+ * Returns 0, or 1 when the 6-DoF system is singular (nothing changes). */
+static int or_icp_update(const or_icp_sums *z, int dof, const double u[3], double A[9], double b[3])
+{
+    const double n = (double)z->n;
+    double mq[3], mc[3], S[3][3], H[3][3];
+    for (int a = 0; a < 3; ++a) {
+        mq[a] = (double)z->sq[a] / n;
+        mc[a] = (double)z->sc[a] / n;
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) {
+            S[a][c] = (double)z->sqq[a][c] - ((double)z->sq[a] * (double)z->sq[c]) / n;
+            H[a][c] = (double)z->sqc[a][c] - ((double)z->sq[a] * (double)z->sc[c]) / n;
+        }
+    const double w[3] = {H[1][2] - H[2][1], H[2][0] - H[0][2], H[0][1] - H[1][0]};
+    double R[3][3], mp[3];
+    if (dof == 3) {
+        double Hu[3];
+        for (int a = 0; a < 3; ++a) Hu[a] = (H[a][0] * u[0] + H[a][1] * u[1]) + H[a][2] * u[2];
+        const double uHu = (u[0] * Hu[0] + u[1] * Hu[1]) + u[2] * Hu[2];
+        const double Ap = ((H[0][0] + H[1][1]) + H[2][2]) - uHu;
+        const double B = (u[0] * w[0] + u[1] * w[1]) + u[2] * w[2];
+        const double h = sqrt(Ap * Ap + B * B);
+        double co = 1.0, si = 0.0;
+        if (h > 0.0) { co = Ap / h; si = B / h; }
+        const double K[3][3] = {{0.0, -u[2], u[1]}, {u[2], 0.0, -u[0]}, {-u[1], u[0], 0.0}};
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                R[a][c] = ((a == c ? co : 0.0) + si * K[a][c]) + ((1.0 - co) * u[a]) * u[c];
+        const double d[3] = {mc[0] - mq[0], mc[1] - mq[1], mc[2] - mq[2]};
+        const double ud = (u[0] * d[0] + u[1] * d[1]) + u[2] * d[2];
+        for (int a = 0; a < 3; ++a) mp[a] = mq[a] + (d[a] - ud * u[a]);
+    } else {
+        const double tr = (S[0][0] + S[1][1]) + S[2][2];
+        double M[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) M[a][c] = (a == c ? tr : 0.0) - S[a][c];
+        double adj[3][3];
+        adj[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+        adj[0][1] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+        adj[0][2] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+        adj[1][0] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+        adj[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+        adj[1][2] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+        adj[2][0] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+        adj[2][1] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+        adj[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+        const double det = (M[0][0] * adj[0][0] + M[0][1] * adj[1][0]) + M[0][2] * adj[2][0];
+        if (!(det > 0.0)) return 1;
+        double h[3];
+        for (int a = 0; a < 3; ++a)
+            h[a] = (((adj[a][0] * w[0] + adj[a][1] * w[1]) + adj[a][2] * w[2]) / det) / 2.0;
+        const double r = sqrt(1.0 + ((h[0] * h[0] + h[1] * h[1]) + h[2] * h[2]));
+        const double qw = 1.0 / r, qx = h[0] / r, qy = h[1] / r, qz = h[2] / r;
+        R[0][0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+        R[0][1] = 2.0 * (qx * qy - qz * qw);
+        R[0][2] = 2.0 * (qx * qz + qy * qw);
+        R[1][0] = 2.0 * (qx * qy + qz * qw);
+        R[1][1] = 1.0 - 2.0 * (qx * qx + qz * qz);
+        R[1][2] = 2.0 * (qy * qz - qx * qw);
+        R[2][0] = 2.0 * (qx * qz - qy * qw);
+        R[2][1] = 2.0 * (qy * qz + qx * qw);
+        R[2][2] = 1.0 - 2.0 * (qx * qx + qy * qy);
+        for (int a = 0; a < 3; ++a) mp[a] = mc[a];
+    }
+    double An[9], bn[3];
+    const double e[3] = {b[0] - mq[0], b[1] - mq[1], b[2] - mq[2]};
+    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c) An[3 * a + c] = (R[a][0] * A[c] + R[a][1] * A[3 + c]) + R[a][2] * A[6 + c];
+        bn[a] = ((R[a][0] * e[0] + R[a][1] * e[1]) + R[a][2] * e[2]) + mp[a];
+    }
+    memcpy(A, An, sizeof(An));
+    memcpy(b, bn, sizeof(bn));
+    return 0;
+}
+
+/* The object z axis of a pose, normalised (I5, 3-DoF). */
+static void or_pose_axis(const float *pose, double u[3])
+{
+    const double v[3] = {(double)pose[2], (double)pose[6], (double)pose[10]};
+    const double nrm = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    for (int a = 0; a < 3; ++a) u[a] = v[a] / nrm;
+}
+
+/* The refined pose (I8). */
+static void or_icp_pose(const float *pose, const double A[9], const double b[3], float *out)
+{
+    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c)
+            out[4 * a + c] = (float)((A[3 * a] * (double)pose[c] + A[3 * a + 1] * (double)pose[4 + c])
+                                     + A[3 * a + 2] * (double)pose[8 + c]);
+        const double t = ((A[3 * a] * (16.0 * (double)pose[3]) + A[3 * a + 1] * (16.0 * (double)pose[7]))
+                          + A[3 * a + 2] * (16.0 * (double)pose[11])) + b[a];
+        out[4 * a + 3] = (float)(t / 16.0);
+    }
+}
+
+/* ICP of one pose against the observed cloud (I1-I8). */
+static int or_icp_one(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
+                      const or_cloud *obs, double rho, int32_t iterations, int32_t stride, int32_t dof,
+                      int32_t min_points, float *out, int32_t *iters_out, int32_t *matched_out)
+{
+    const oracle_intrinsics *K = &sc->K;
+    const int W = K->width, H = K->height;
+    const size_t N = (size_t)W * H;
+    const int mark = (sc->flags & OR_MARK_OCCLUDERS) != 0;
+    const uint32_t vol = sc->flags & OR_VOL_MASK;
+    const int64_t dq = (int64_t)nearbyint(16.0 * (double)sc->delta_mm);
+    const int64_t rq = (int64_t)nearbyint(16.0 * rho);
+    const int64_t rq2 = rq * rq;
+    uint16_t *dren = (uint16_t *)malloc(N * sizeof(uint16_t));
+    int32_t *src = (int32_t *)malloc(3 * N * sizeof(int32_t));
+    int64_t *qprev = (int64_t *)malloc(3 * N * sizeof(int64_t));
+    int64_t *qcur = (int64_t *)malloc(3 * N * sizeof(int64_t));
+    int rc = 0;
+    if (!dren || !src || !qprev || !qcur) { rc = -2; goto done; }
+    if (oracle_render(m, pose, K, dren, NULL, NULL) != 0) { rc = -1; goto done; }
+
+    /* I1: the source cloud */
+    size_t ns = 0;
+    for (int32_t j = 0; j < H; ++j)
+        for (int32_t i = 0; i < W; ++i) {
+            size_t k = (size_t)j * W + i;
+            int32_t d = dren[k];
+            if (d == 0 || i % stride != 0 || j % stride != 0) continue;
+            int32_t dob = sc->depth[k];
+            if (mark && dob > 0 && 16 * (int64_t)dob + dq < 16 * (int64_t)d) {
+                int other = !(vol == OR_VOL_LABEL && sc->labels) || sc->labels[k] != label;
+                if (other) continue;
+            }
+            oracle_backproject(K, i, j, d, src + 3 * ns);
+            ns++;
+        }
+
+    double A[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, b[3] = {0, 0, 0}, u[3];
+    or_pose_axis(pose, u);
+    int32_t iters = 0, matched = 0;
+    for (int32_t k = 0; k < iterations; ++k) {
+        for (size_t p = 0; p < ns; ++p) or_icp_map(A, b, src + 3 * p, qcur + 3 * p);
+        if (k > 0 && memcmp(qcur, qprev, 3 * ns * sizeof(int64_t)) == 0) break;   /* I7 */
+        or_icp_sums z;
+        memset(&z, 0, sizeof(z));
+        for (size_t p = 0; p < ns; ++p) {
+            const int64_t *q = qcur + 3 * p;
+            int64_t best_d2 = 0;
+            int32_t best = -1;
+            for (int32_t t = 0; t < obs->n; ++t) {   /* I3: brute force, pixel order */
+                int64_t dx = (int64_t)obs->x[t] - q[0], dy = (int64_t)obs->y[t] - q[1], dz = (int64_t)obs->z[t] - q[2];
+                int64_t d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 <= rq2 && (best < 0 || d2 < best_d2)) { best_d2 = d2; best = t; }
+            }
+            if (best >= 0) {
+                const int64_t c[3] = {obs->x[best], obs->y[best], obs->z[best]};
+                or_icp_add(&z, q, c);
+            }
+        }
+        matched = (int32_t)z.n;
+        if (z.n < min_points) break;
+        if (or_icp_update(&z, dof, u, A, b)) break;
+        iters = k + 1;
+        int64_t *tmp = qprev; qprev = qcur; qcur = tmp;
+    }
+    or_icp_pose(pose, A, b, out);
+    *iters_out = iters;
+    *matched_out = matched;
+done:
+    free(dren); free(src); free(qprev); free(qcur);
+    return rc;
+}
+
+/* ICP refinement of n poses (readings I1-I8): refined poses (n x 12
+ * binary32), the updates applied and the matches of the last iteration
+ * examined.  dof is 3 or 6; rho in (0, 100] mm; min_points >= 3. */
+int oracle_icp(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses, int32_t n,
+               double rho, int32_t iterations, int32_t stride, int32_t dof, int32_t min_points,
+               float *refined, int32_t *iters, int32_t *matched, int32_t n_threads)
+{
+    if (n < 0 || !or_scene_valid(m, sc) || m->n_tris > 65536) return -1;
+    if (!(rho > 0.0 && rho <= 100.0) || iterations < 1 || stride < 1 || (dof != 3 && dof != 6) || min_points < 3)
+        return -1;
+    or_cloud obs;
+    oracle_scene s2 = *sc;
+    s2.flags &= ~OR_USE_RGB;
+    if (or_observed_cloud(&s2, &obs)) return -2;
+    int err = 0;
+#ifdef _OPENMP
+    int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : err)
+#endif
+    for (int32_t p = 0; p < n; ++p) {
+        if (or_icp_one(m, sc, label, poses + 12 * (size_t)p, &obs, rho, iterations, stride, dof, min_points,
+                       refined + 12 * (size_t)p, iters + p, matched + p))
+            err |= 1;
+    }
+    (void)n_threads;
+    or_cloud_free(&obs);
+    return err ? -2 : 0;
+}
+
+/* The ICP update loop on fixed correspondences: dst[i] is the match of
+ * src[i] (n x 3 int32, 1/16 mm); u is the 3-DoF axis.  Runs `iterations`
+ * updates (I2, I4-I6) and returns the transform (A row-major, b). */
+int oracle_icp_pairs(const int32_t *src, const int32_t *dst, int32_t n, int32_t dof, const double *u,
+                     int32_t iterations, double *A, double *b)
+{
+    if (n < 3 || (dof != 3 && dof != 6)) return -1;
+    const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    memcpy(A, I, sizeof(I));
+    b[0] = b[1] = b[2] = 0.0;
+    for (int32_t k = 0; k < iterations; ++k) {
+        or_icp_sums z;
+        memset(&z, 0, sizeof(z));
+        for (int32_t p = 0; p < n; ++p) {
+            int64_t q[3];
+            or_icp_map(A, b, src + 3 * (size_t)p, q);
+            const int64_t c[3] = {dst[3 * (size_t)p], dst[3 * (size_t)p + 1], dst[3 * (size_t)p + 2]};
+            or_icp_add(&z, q, c);
+        }
+        if (or_icp_update(&z, dof, u, A, b)) return 1;
+    }
+    return 0;
 }
 
 /* Minimum of J = jr + jo; ties go to the lowest index.  n_ties counts the
