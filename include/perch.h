@@ -207,6 +207,43 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id,
                           const float *poses_dev, int32_t n, uint16_t *depth_dev,
                           uint8_t *rgb_dev, int32_t *tri_dev, void *hip_stream);
 
+/* ICP refinement parameters (perch_refine_poses). */
+typedef struct {
+    int32_t iterations;   /* at most this many updates, 1 .. 1000 */
+    float max_corr_mm;    /* correspondence radius rho, 0 < rho <= 100 mm */
+    int32_t stride;       /* image-space downsampling of the rendered (source) cloud, >= 1 */
+    int32_t dof;          /* 3: rotation about the pose's object z axis and translation normal to it
+                           *    (the 3-DoF table-top search); 6: any rigid motion */
+    int32_t min_points;   /* stop when fewer points match, >= 3 */
+} perch_icp_params;
+
+/* ICP refinement of candidate poses (Sec. IV-A "Parallel M2M GICP"; the
+ * point-to-point ICP of the 3-DoF experiments, Sec. V-A), the step before
+ * rendering and scoring the adjusted poses again.  Per pose: the rendered
+ * points that the scorer keeps (occluders removed as the scene's flags say,
+ * here on the ICP stride grid) are aligned to the observed cloud — with
+ * PERCH_VOL_LABEL, to the observed pixels carrying `label` (Sec. V-C).  Each
+ * iteration maps them by the current camera-frame transform, rounded to
+ * 1/16 mm; matches each with its nearest observed point within rho (ties:
+ * lower pixel index; exact integers); sums the pairs exactly; and takes
+ * the update about the source centroid.  For 3-DoF that is the planar
+ * least-squares rotation about the axis and the in-plane translation; for
+ * 6-DoF, one Gauss-Newton step of the linearised rotation, applied as a unit
+ * quaternion.  ICP stops after `iterations` updates, when fewer than
+ * min_points match, when no mapped point moved, or (6-DoF) on a singular
+ * system.
+ *   poses_dev:   n*12 binary32 [R|t] object -> camera, mm (device, read)
+ *   refined_dev: n*12 binary32 refined poses (device, written; may not alias
+ *                poses_dev)
+ *   iters_dev:   n int32 updates applied, or NULL
+ *   matched_dev: n int32 matches in the last iteration examined, or NULL
+ * Asynchronous on hip_stream.  Device scratch of the stream: a W*H tile and
+ * 2*W*H points per work-group (one per compute unit, at most n). */
+perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                const float *poses_dev, int32_t n, const perch_icp_params *params,
+                                float *refined_dev, int32_t *iters_dev, int32_t *matched_dev,
+                                void *hip_stream);
+
 /* Kernel timing.  perch_profile_enable(ctx, 1) clears the record and from
  * then on brackets every kernel launch of the context with HIP events on the
  * launch stream; 0 stops recording.  perch_profile_read waits for the
@@ -215,7 +252,7 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id,
  * 0 pose set-up/classification; scoring kernels by footprint class:
  * 1 tile and keys in LDS (256 or 512 threads), 2 tile and keys in LDS (1024
  * threads), 3 tile in LDS and keys in device memory, 4 tile and keys in
- * device memory; 5 argmin, 6 scene preparation, 7 render. */
+ * device memory; 5 argmin, 6 scene preparation, 7 render, 8 ICP refinement. */
 perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
 

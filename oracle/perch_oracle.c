@@ -75,7 +75,9 @@
  * 3-DoF experiments use point-to-point ICP).  The paper gives no
  * correspondence rule, update or stopping rule; this oracle reads them as:
  *   I1 Source: R minus C of the pose (R6, R7) on the ICP stride grid; target:
- *      every valid observed point.  Integer 1/16 mm points.
+ *      every valid observed point or, with label volumes (Sec. V-C: the 6-DoF
+ *      pipeline segments each object first), those carrying the object's
+ *      label.  Integer 1/16 mm points.
  *   I2 Iteration k holds a camera-frame transform (A, b), b in 1/16 mm,
  *      starting at the identity.  Source point s maps to q with
  *      q_a = rint(((A_a0 sx + A_a1 sy) + A_a2 sz) + b_a).
@@ -944,6 +946,15 @@ int oracle_icp(const oracle_mesh *m, const oracle_scene *sc, int32_t label, cons
     oracle_scene s2 = *sc;
     s2.flags &= ~OR_USE_RGB;
     if (or_observed_cloud(&s2, &obs)) return -2;
+    if ((sc->flags & OR_VOL_MASK) == OR_VOL_LABEL) {   /* I1: the object's labelled points only */
+        int32_t k = 0;
+        for (int32_t t = 0; t < obs.n; ++t) {
+            if (sc->labels[obs.pix[t]] != label) continue;
+            obs.x[k] = obs.x[t]; obs.y[k] = obs.y[t]; obs.z[k] = obs.z[t]; obs.pix[k] = obs.pix[t];
+            k++;
+        }
+        obs.n = k;
+    }
     int err = 0;
 #ifdef _OPENMP
     int nt = n_threads > 0 ? n_threads : omp_get_max_threads();

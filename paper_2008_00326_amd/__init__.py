@@ -60,6 +60,11 @@ class _Tuning(ctypes.Structure):
                 ("order", ctypes.c_int32), ("key_bands", ctypes.c_int32)]
 
 
+class _IcpParams(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("max_corr_mm", ctypes.c_float), ("stride", ctypes.c_int32),
+                ("dof", ctypes.c_int32), ("min_points", ctypes.c_int32)]
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
@@ -93,6 +98,7 @@ def load_library():
         "perch_score_poses": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP], ctypes.c_int),
         "perch_best_poses": ([P, I32, I32, P, P, P, P, P, P, VP], ctypes.c_int),
         "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
+        "perch_refine_poses": ([P, I32, I32, I32, VP, I32, P, VP, VP, VP, VP], ctypes.c_int),
         "perch_scene_info_get": ([P, I32, P], ctypes.c_int),
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
@@ -277,7 +283,7 @@ class Context:
                 "key_bands": t.key_bands}
 
     PROFILE_SLOTS = ("setup", "score_lds_small", "score_lds_large", "score_lds_tile", "score_device", "argmin",
-                     "scene_prep", "render")
+                     "scene_prep", "render", "icp")
 
     def profile(self, enable: bool = True):
         """Start (clearing the record) or stop bracketing kernel launches with HIP events."""
@@ -316,6 +322,26 @@ class Context:
             stream = torch.cuda.current_stream()
         _check(self._lib.perch_last_classes(self._h, _stream_ptr(stream), int(n), _np_ptr(out)))
         return out
+
+    def refine_poses(self, scene_id, mesh_id, poses, *, label=0, rho_mm=20.0, iterations=10, stride=2, dof=3,
+                     min_points=16, out=None, stream=None):
+        """ICP refinement of a (n, 12) float32 CUDA tensor of poses against the
+        scene.  Returns (refined (n, 12) float32, updates applied int32,
+        matches of the last iteration int32) CUDA tensors.  Asynchronous."""
+        import torch
+        if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
+            raise ValueError("poses must be a contiguous float32 CUDA tensor")
+        n = poses.numel() // 12
+        refined = out if out is not None else torch.empty((n, 12), dtype=torch.float32, device=poses.device)
+        iters = torch.empty(n, dtype=torch.int32, device=poses.device)
+        matched = torch.empty(n, dtype=torch.int32, device=poses.device)
+        prm = _IcpParams(int(iterations), float(rho_mm), int(stride), int(dof), int(min_points))
+        if stream is None:
+            stream = torch.cuda.current_stream(poses.device)
+        _check(self._lib.perch_refine_poses(self._h, int(scene_id), int(mesh_id), int(label), _dev_ptr(poses), n,
+                                            ctypes.byref(prm), _dev_ptr(refined), _dev_ptr(iters), _dev_ptr(matched),
+                                            _stream_ptr(stream)))
+        return refined, iters, matched
 
     def render(self, scene_id, mesh_id, poses, K, *, rgb=False, tri=False, stream=None):
         """Full-image renders of (n, 12) poses: (depth u16, rgb u8 or None, tri i32 or None) tensors."""

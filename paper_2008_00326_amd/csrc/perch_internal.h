@@ -133,9 +133,26 @@ hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st);
 hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_pv, hipStream_t st);
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st);
 
+// ICP refinement of candidate poses: arguments of one launch.
+struct IcpArgs {
+    SceneDev s;
+    MeshDev m;
+    const float *poses;      // n * 12
+    int n, label;
+    int iterations, stride, dof, min_points;
+    int rq, rq2;             // correspondence radius in 1/16 mm and its square
+    float *refined;          // n * 12
+    int32_t *iters, *matched; // or null
+    uint32_t *tiles;         // per work-group: W*H tile words
+    int4 *pts;               // per work-group: pts_cap source points, then pts_cap mapped points
+    size_t pts_cap;
+    int *cursor;             // pose cursor, zeroed by the launch
+};
+hipError_t launch_icp(const IcpArgs &a, int grid, hipStream_t st);
+
 // Kernel slots reported by the profiler (perch_profile_read).
 enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
-                kNumProfSlots = 8 };
+                kProfIcp = 8, kNumProfSlots = 9 };
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n,
                          uint32_t *keys, uint16_t *depth, uint8_t *rgb, int32_t *tri,
                          hipStream_t st);

@@ -113,6 +113,7 @@ struct Staging {
 struct StreamBufs {
     LaunchBufs lb;
     DevBuf tmp;               // J_r / J_o of perch_best_poses
+    DevBuf icp;               // ICP: pose cursor, per-work-group tiles and point lists
     Staging ring[8];
     int next = 0;
     int32_t last_n = 0;       // poses of the last scoring launch on this stream
@@ -700,7 +701,7 @@ perch_status perch_destroy(perch_ctx *ctx)
     for (auto &kv : ctx->work) {
         StreamBufs &w = kv.second;
         for (DevBuf *b : {&w.lb.desc, &w.lb.info, &w.lb.lists, &w.lb.counts, &w.lb.scratch, &w.lb.best, &w.lb.lab,
-                          &w.tmp})
+                          &w.tmp, &w.icp})
             ctx->release(*b);
         for (Staging &g : w.ring) {
             if (g.host) (void)hipHostFree(g.host);
@@ -1083,6 +1084,60 @@ perch_status perch_render(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, con
         return launch_render(s, mi->second.dev, poses_dev, n, (uint32_t *)b.lb.scratch.ptr, depth_dev, rgb_dev,
                              tri_dev, st);
     }));
+    ctx->mark_use(si->second.uses, st);
+    ctx->mark_use(mi->second.uses, st);
+    return ok();
+}
+
+perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                const float *poses_dev, int32_t n, const perch_icp_params *prm, float *refined_dev,
+                                int32_t *iters_dev, int32_t *matched_dev, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    if (!prm) return fail(PERCH_EINVAL, "null ICP parameters");
+    if (prm->iterations < 1 || prm->iterations > 1000) return fail(PERCH_EINVAL, "iterations must be in [1, 1000]");
+    if (!(prm->max_corr_mm > 0.0f && prm->max_corr_mm <= 100.0f))
+        return fail(PERCH_EINVAL, "max_corr_mm must be in (0, 100]");
+    if (prm->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
+    if (prm->dof != 3 && prm->dof != 6) return fail(PERCH_EINVAL, "dof must be 3 or 6");
+    if (prm->min_points < 3) return fail(PERCH_EINVAL, "min_points must be >= 3");
+    if (n < 0) return fail(PERCH_EINVAL, "n must be >= 0");
+    if (n > 0 && (!poses_dev || !refined_dev)) return fail(PERCH_EINVAL, "null poses or output");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    auto mi = ctx->meshes.find(mesh_id);
+    if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    if (n == 0) return ok();
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    StreamBufs &b = ctx->work[st];
+    const SceneDev &s = si->second.dev;
+    const int grid = std::min(n, std::max(ctx->n_cu, 1));
+    const size_t px = (size_t)s.W * s.H;
+    const size_t tiles_off = 256, pts_off = tiles_off + (size_t)grid * px * 4;
+    const size_t bytes = pts_off + (size_t)grid * 2 * px * sizeof(int4);
+    if (perch_status e = ctx->ensure(b.icp, bytes)) return e;
+    IcpArgs a{};
+    a.s = s;
+    a.m = mi->second.dev;
+    a.poses = poses_dev;
+    a.n = n;
+    a.label = label;
+    a.iterations = prm->iterations;
+    a.stride = prm->stride;
+    a.dof = prm->dof;
+    a.min_points = prm->min_points;
+    a.rq = (int)std::nearbyint(16.0 * (double)prm->max_corr_mm);
+    a.rq2 = a.rq * a.rq;
+    a.refined = refined_dev;
+    a.iters = iters_dev;
+    a.matched = matched_dev;
+    char *base = (char *)b.icp.ptr;
+    a.cursor = (int *)base;
+    a.tiles = (uint32_t *)(base + tiles_off);
+    a.pts = (int4 *)(base + pts_off);
+    a.pts_cap = px;
+    HIP_TRY(ctx->timed(kProfIcp, st, [&] { return launch_icp(a, grid, st); }));
     ctx->mark_use(si->second.uses, st);
     ctx->mark_use(mi->second.uses, st);
     return ok();

@@ -6,7 +6,8 @@ alignment that scipy's Rotation.align_vectors computes (6-DoF), and the
 planar Procrustes solution written with atan2 (3-DoF), ignoring motion along
 the axis.  On rendered scenes ICP returns perturbed poses to the true pose,
 leaves the true pose where it is, matches exactly the source points that a
-k-d tree finds within rho, and leaves a pose with nothing in reach unchanged.
+k-d tree finds within rho (with label volumes, among the object's labelled
+points), and leaves a pose with nothing in reach unchanged.
 """
 import numpy as np
 import pytest
@@ -188,6 +189,29 @@ def test_icp_first_matches_equal_kdtree():
                                                     < 16 * int(d[j, i]))], np.float64)
             dist, _ = tree.query(src, distance_upper_bound=rq + 1.0 / (4 * rq))
             assert mt[k] == int(np.isfinite(dist).sum())
+
+
+def test_icp_label_target_is_the_labelled_points():
+    m, scene, gt = _scene_and_gt(6)
+    W, H = K[0], K[1]
+    labels = np.where(np.arange(W)[None, :] < W // 2, 3, 1).astype(np.int32).repeat(H, 0)
+    lscene = TScene(K, scene.depth, None, labels)
+    rng = np.random.default_rng(6)
+    poses = np.stack([_yaw_shift(gt, rng.normal(0, 0.1), *rng.normal(0, 6.0, 2)) for _ in range(3)])
+    pts = [(oracle.backproject(K, i, j, int(scene.depth[j, i])), labels[j, i])
+           for j in range(H) for i in range(W) if scene.depth[j, i] > 0]
+    rq = 16 * 12
+    for label in (1, 3):
+        tree = cKDTree(np.array([p for p, lab in pts if lab == label], np.float64))
+        _, _, mt = oracle.icp(m, lscene, poses, delta_mm=5.0, flags=oracle.VOL_LABEL, label=label, rho_mm=12.0,
+                              iterations=1, stride=2, dof=3)
+        for k in range(poses.shape[0]):
+            d, _, _ = oracle.render(m, poses[k], K)
+            src = np.array([oracle.backproject(K, i, j, int(d[j, i])) for j in range(0, H, 2) for i in range(0, W, 2)
+                            if d[j, i] > 0], np.float64)
+            dist, _ = tree.query(src, distance_upper_bound=rq + 1.0 / (4 * rq))
+            assert mt[k] == int(np.isfinite(dist).sum())
+        assert mt.sum() > 0
 
 
 def test_icp_out_of_reach_is_unchanged():
