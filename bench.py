@@ -85,6 +85,8 @@ def main():
                     help="J_r neighbour search of the plain run: the scene table or the paper's kNN II scan")
     ap.add_argument("--poses-per-object", type=int, default=0,
                     help="score only the first N candidates of each object (0 = all)")
+    ap.add_argument("--no-refine", action="store_true", help="skip the ICP refine-and-rescore leg of a plain run")
+    ap.add_argument("--refine-steps", type=int, default=2, help="timed passes of the refine leg")
     ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -260,6 +262,8 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
     }
 
+    if not args.no_refine:
+        result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
     if not args.no_batched:
         ctx.drop_scene(sid)
         ctx.set_tuning(None)
@@ -269,6 +273,83 @@ def main():
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def refine_leg(ctx, w, mids, steps, cpu_sample):
+    """ICP refinement (point-to-point, 3-DoF, rho 20 mm, at most 10 updates,
+    source stride 2) of every candidate against its object's labelled pixels,
+    then every refined pose rendered and scored again, as the segmented
+    pipeline of the paper does before selecting poses.  Returns poses/s of
+    the refinement and of refinement plus rescoring, the costs before and
+    after, and the CPU oracle's refinement rate on a small sample."""
+    import torch
+    s = w.scene
+    _log("[bench] refine: ICP + rescore")
+    sid = ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels, delta_mm=w.delta_mm, tau_c=w.tau_c,
+                        use_rgb=w.use_rgb, mark_occluders=w.mark_occluders, volume="label")
+    prm = dict(rho_mm=20.0, iterations=10, stride=2, dof=3)
+    meshes = [mids[o.mesh] for o in w.objects]
+    labels = [o.label for o in w.objects]
+    polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
+    outs = [torch.empty_like(p) for p in polys]
+    n = sum(p.shape[0] for p in polys)
+    stats = []
+
+    def refine():
+        stats.clear()
+        for mid, lab, p, out in zip(meshes, labels, polys, outs):
+            stats.append(ctx.refine_poses(sid, mid, p, label=lab, out=out, **prm)[1:])
+
+    refine()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        refine()
+    torch.cuda.synchronize()
+    t_ref = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bi_after, bc_after = ctx.best_poses(sid, meshes, labels, outs)
+    t_score = (time.perf_counter() - t0) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    bi_before, bc_before = ctx.best_poses(sid, meshes, labels, polys)
+    j0, j1 = [], []
+    for mid, lab, p, out in zip(meshes, labels, polys, outs):
+        a = ctx.score_poses(sid, mid, p, label=lab)
+        b = ctx.score_poses(sid, mid, out, label=lab)
+        j0.append((a[0] + a[1]).cpu().numpy())
+        j1.append((b[0] + b[1]).cpu().numpy())
+    j0, j1 = np.concatenate(j0), np.concatenate(j1)
+    it = np.concatenate([x[0].cpu().numpy() for x in stats])
+    mt = np.concatenate([x[1].cpu().numpy() for x in stats])
+    out = {"workload": f"{w.name}, label volumes, every candidate refined", "icp": dict(prm, min_points=16),
+           "poses": n, "refine_poses_per_s": round(n / t_ref, 1), "refine_ms": round(t_ref * 1e3, 3),
+           "rescore_ms": round(t_score * 1e3, 3), "refine_and_rescore_poses_per_s": round(n / (t_ref + t_score), 1),
+           "icp_kernel_ms": round(prof["icp"][0] / max(prof["icp"][1], 1) * len(polys), 3),
+           "mean_updates": round(float(it.mean()), 2), "mean_matches_last": round(float(mt.mean()), 1),
+           "mean_J_before": round(float(j0.mean()), 1), "mean_J_after": round(float(j1.mean()), 1),
+           "fraction_J_lower": round(float(np.mean(j1 < j0)), 4),
+           "best_J_before": [int(x) for x in bc_before], "best_J_after": [int(x) for x in bc_after]}
+    if cpu_sample:
+        import oracle
+        rng = np.random.default_rng(7)
+        per = max(1, cpu_sample // len(w.objects))
+        threads = min(os.cpu_count() or 1, 16)
+        flags = (oracle.MARK_OCCLUDERS if w.mark_occluders else 0) | oracle.VOL_LABEL
+        k = 0
+        t0 = time.perf_counter()
+        for o in w.objects:
+            sel = np.sort(rng.choice(o.poses.shape[0], per, replace=False))
+            oracle.icp(w.meshes[o.mesh], s, o.poses[sel], delta_mm=w.delta_mm, flags=flags,
+                       label=o.label, threads=threads, **prm)
+            k += len(sel)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"poses_per_s": round(k / dt, 3), "cores": threads,
+                             "sample": f"{k} poses ({per} per object, seeded uniform), brute-force matches, {dt:.1f} s"}
+    ctx.drop_scene(sid)
+    return out
 
 
 def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):

@@ -141,6 +141,8 @@ struct IcpArgs {
     int n, label;
     int iterations, stride, dof, min_points;
     int rq, rq2;             // correspondence radius in 1/16 mm and its square
+    int box[4];              // x0, y0, x1, y1 (inclusive) holding every target pixel (label volumes:
+                             // the label's pixels; x1 < x0 when there are none)
     float *refined;          // n * 12
     int32_t *iters, *matched; // or null
     uint32_t *tiles;         // per work-group: W*H tile words

@@ -1353,13 +1353,15 @@ __device__ __forceinline__ long long icp_term(int j, int4 q, int4 c)
 
 // Nearest observed point of q (1/16 mm) within rq, ties to the lower pixel
 // index, or -1; with `labels`, only pixels carrying `label` count (label
-// volumes: the object's segment is the target).  The whole wave searches,
-// lanes over a pixel window that
+// volumes: the object's segment is the target), and `box` (inside the
+// image) holds every pixel that can count.  The whole wave searches, lanes
+// over a pixel window that
 // holds every candidate: an observed point at depth d (mm) with
 // |Xq - qx| <= rq has rint(kx[i] d) in [qx - rq, qx + rq], so
 // kx[i] d lies within half a unit of that range, for d in
 // [(qz - rq) / 16, (qz + rq) / 16]; one pixel of margin on each side.
-__device__ int icp_nn(const SceneDev &s, int4 q, int rq, int rq2, const int32_t *labels, int label, int lane)
+__device__ int icp_nn(const SceneDev &s, int4 q, int rq, int rq2, const int32_t *labels, int label, const int *box,
+                      int lane)
 {
     const int dlo = q.z - rq <= 16 ? 1 : (q.z - rq + 15) / 16;
     const int dhi = min(65534, (q.z + rq) / 16);
@@ -1374,7 +1376,7 @@ __device__ int icp_nn(const SceneDev &s, int4 q, int rq, int rq2, const int32_t 
         b[2 * ax] = (int)floor(fmax(fmin(a, 1e8), -1e8)) - 1;
         b[2 * ax + 1] = (int)ceil(fmax(fmin(z, 1e8), -1e8)) + 1;
     }
-    const int i0 = max(b[0], 0), i1 = min(b[1], s.W - 1), j0 = max(b[2], 0), j1 = min(b[3], s.H - 1);
+    const int i0 = max(b[0], box[0]), i1 = min(b[1], box[2]), j0 = max(b[2], box[1]), j1 = min(b[3], box[3]);
     if (i0 > i1 || j0 > j1) return -1;
     const int ww = i1 - i0 + 1, n = ww * (j1 - j0 + 1);
     const float inv = 1.0f / (float)ww;
@@ -1601,7 +1603,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             long long acc = 0;
             for (int t = wave; t < ns; t += NW) {
                 const int4 q = qb[t];
-                const int nn = icp_nn(s, q, a.rq, a.rq2, label_mode ? s.labels : nullptr, a.label, lane);
+                const int nn = icp_nn(s, q, a.rq, a.rq2, label_mode ? s.labels : nullptr, a.label, a.box, lane);
                 if (nn >= 0) {
                     const int4 c = gld(s.opt + nn);
                     if (lane < kIcpSums) acc += icp_term(lane, q, c);

@@ -1129,6 +1129,17 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     a.min_points = prm->min_points;
     a.rq = (int)std::nearbyint(16.0 * (double)prm->max_corr_mm);
     a.rq2 = a.rq * a.rq;
+    a.box[0] = 0;
+    a.box[1] = 0;
+    a.box[2] = s.W - 1;
+    a.box[3] = s.H - 1;
+    if ((s.flags & PERCH_VOL_MASK) == PERCH_VOL_LABEL) {   // only the label's pixels can match
+        const std::vector<int> lb = label_box(si->second, label);
+        a.box[0] = lb[0];
+        a.box[1] = lb[1];
+        a.box[2] = lb[0] + lb[2] - 1;
+        a.box[3] = lb[1] + lb[3] - 1;
+    }
     a.refined = refined_dev;
     a.iters = iters_dev;
     a.matched = matched_dev;
