@@ -68,7 +68,7 @@ typedef struct perch_ctx perch_ctx;
 #define PERCH_VOL_AABB (0u << 4)   /* V(O): object-frame mesh AABB inflated by delta */
 #define PERCH_VOL_CYL (1u << 4)    /* V(O): cylinder about the object z axis through the centre of the
                                     * AABB's xy extent, radius the smaller xy half-extent plus delta,
-                                    * z range of the AABB inflated by delta (Sec. III-A's conservative
+                                    * z range of the AABB inflated by delta (Table I's conservative
                                     * volume taken as an inscribed cylinder) */
 #define PERCH_VOL_LABEL (2u << 4)  /* V(O): observed pixels carrying the object's label (Sec. V-C) */
 #define PERCH_VOL_MASK (3u << 4)
@@ -218,7 +218,7 @@ typedef struct {
 } perch_icp_params;
 
 /* ICP refinement of candidate poses (Sec. IV-A "Parallel M2M GICP"; the
- * point-to-point ICP of the 3-DoF experiments, Sec. V-A), the step before
+ * point-to-point ICP of the 3-DoF experiments, Sec. VI-A), the step before
  * rendering and scoring the adjusted poses again.  Per pose: the rendered
  * points that the scorer keeps (occluders removed as the scene's flags say,
  * here on the ICP stride grid) are aligned to the observed cloud — with
@@ -243,6 +243,34 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
                                 const float *poses_dev, int32_t n, const perch_icp_params *params,
                                 float *refined_dev, int32_t *iters_dev, int32_t *matched_dev,
                                 void *hip_stream);
+
+/* 6-DoF pose proposal parameters (perch_propose_poses). */
+typedef struct {
+    int32_t viewpoints;   /* M >= 1 viewpoints on the unit sphere */
+    int32_t inplane;      /* N >= 1 in-plane angles 2 pi k / N */
+    float z_step_mm;      /* spacing of the depth proposals, > 0 */
+    int32_t max_depths;   /* at most this many depths T >= 1 (then spread evenly over the range) */
+} perch_proposal_params;
+
+/* 6-DoF pose proposals of one object (Sec. V-B "Pose Proposal Generation"):
+ * every combination of M rotation viewpoints, N in-plane angles and T depths,
+ * pose p = (i N + k) T + t.  Viewpoint i sits on the Fibonacci lattice of
+ * the unit sphere (z = 1 - (2i + 1)/M, longitude i pi (3 - sqrt 5)): the
+ * nearest to equidistant for any M; the rotation turns it to face the
+ * camera, then by 2 pi k / N about the optical axis.  The translation puts
+ * the object's centre (the centre of the mesh's object-frame AABB) on the
+ * ray through the centre of the label's pixel box (the scene's labels stand
+ * in for the segmentation masks) at depth
+ * z_t = z_min + t * z_step_mm, with [z_min, z_max] the range of valid
+ * observed depths under the label; when that gives more than max_depths,
+ * T = max_depths depths spread evenly over the range.  Needs scene labels.
+ *   poses_dev: capacity*12 binary32 (device, written), or NULL to count only
+ *   n_out:     host int32, the number of proposals M*N*T (0 when the label
+ *              has no pixel with a depth reading)
+ * Asynchronous on hip_stream; PERCH_EINVAL when capacity < M*N*T. */
+perch_status perch_propose_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                 const perch_proposal_params *params, float *poses_dev,
+                                 int32_t capacity, int32_t *n_out, void *hip_stream);
 
 /* Kernel timing.  perch_profile_enable(ctx, 1) clears the record and from
  * then on brackets every kernel launch of the context with HIP events on the

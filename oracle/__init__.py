@@ -269,3 +269,72 @@ def icp_pairs(src, dst, *, dof=6, axis=(0.0, 0.0, 1.0), iterations=1):
     if rc != 0:
         raise ValueError(f"oracle_icp_pairs failed ({rc})")
     return A.reshape(3, 3), b
+
+
+def propose(scene, mesh, label, *, viewpoints, inplane, z_step_mm, max_depths):
+    """6-DoF pose proposals of one labelled object (Sec. V-B "Pose Proposal
+    Generation"), in plain binary64 numpy.  Readings of the paper:
+
+    P1 Rotations: M viewpoints "equidistant" on the unit sphere, taken as the
+       Fibonacci lattice, z_i = 1 - (2i + 1)/M at longitude i pi (3 - sqrt 5);
+       the camera sits in direction v_i from the object, so the rotation maps
+       v_i to the camera's -z axis: rows b1, b2, b3 with b3 = -v_i,
+       b1 = a x b3 / |a x b3| (a = object z axis, or object y axis when
+       |z_i| > 0.999), b2 = b3 x b1.
+    P2 In-plane angles 2 pi k / N: the rotation above, turned about the
+       optical axis, rows (cos b1 - sin b2, sin b1 + cos b2, b3).
+    P3 Translations: the object's centre c (the centre of the mesh's
+       object-frame AABB) on the ray through the centre of the label's pixel
+       box (the visible box; the labels stand in for the segmentation masks),
+       u_c = x0 + (w - 1)/2, so t = z_t ((u_c - cx)/fx, (v_c - cy)/fy, 1) - R c,
+       at depths z_t = z_min +
+       t step, t = 0 .. floor((z_max - z_min)/step), [z_min, z_max] the range
+       of valid observed depths under the label; when that is more than
+       max_depths depths, max_depths of them spread evenly from z_min to
+       z_max.
+    P4 Order: pose p = (i N + k) T + t; binary32 [R|t] rows.
+
+    Returns an (M N T, 12) float32 array (empty when the label has no pixel
+    with a depth reading)."""
+    labels = np.asarray(scene.labels)
+    depth = np.asarray(scene.depth)
+    mask = labels == label
+    ys, xs = np.nonzero(mask)
+    d = depth[mask]
+    d = d[d > 0]
+    if xs.size == 0 or d.size == 0:
+        return np.zeros((0, 12), np.float32)
+    x0, x1, y0, y1 = int(xs.min()), int(xs.max()), int(ys.min()), int(ys.max())
+    zmin, zmax = float(d.min()), float(d.max())
+    T = int(np.floor((zmax - zmin) / float(np.float32(z_step_mm)))) + 1
+    if T > max_depths:
+        T = max_depths
+        step = (zmax - zmin) / (T - 1) if T > 1 else 0.0
+    else:
+        step = float(np.float32(z_step_mm))
+    _, _, fx, fy, cx, cy = [float(np.float32(v)) for v in scene.K]
+    xyz = np.asarray(mesh.xyz, np.float32).astype(np.float64)
+    centre = (xyz.min(0) + xyz.max(0)) / 2.0
+    uc = x0 + (x1 - x0) / 2.0
+    vc = y0 + (y1 - y0) / 2.0
+    out = np.zeros((viewpoints, inplane, T, 12), np.float64)
+    golden = np.pi * (3.0 - np.sqrt(5.0))
+    for i in range(viewpoints):
+        vz = 1.0 - (2 * i + 1) / viewpoints
+        r = np.sqrt(max(0.0, 1.0 - vz * vz))
+        v = np.array([r * np.cos(i * golden), r * np.sin(i * golden), vz])
+        b3 = -v
+        a = np.array([0.0, 1.0, 0.0]) if abs(vz) > 0.999 else np.array([0.0, 0.0, 1.0])
+        b1 = np.cross(a, b3)
+        b1 = b1 / np.linalg.norm(b1)
+        b2 = np.cross(b3, b1)
+        for k in range(inplane):
+            th = 2.0 * np.pi * k / inplane
+            R = np.stack([np.cos(th) * b1 - np.sin(th) * b2, np.sin(th) * b1 + np.cos(th) * b2, b3])
+            for t in range(T):
+                z = zmin + t * step
+                ray = np.array([z * ((uc - cx) / fx), z * ((vc - cy) / fy), z])
+                tr = np.array([ray[r] - ((R[r, 0] * centre[0] + R[r, 1] * centre[1]) + R[r, 2] * centre[2])
+                               for r in range(3)])
+                out[i, k, t] = np.concatenate([R, tr[:, None]], axis=1).reshape(12)
+    return out.reshape(-1, 12).astype(np.float32)

@@ -58,7 +58,7 @@
  *      binary64 colour functions exist to pin the binary32 ones.
  *   R10 Volume: the object-frame AABB of the mesh, inflated by delta, tested
  *      in binary64 on q = R^T (P - t) with P = (Xq, Yq, Zq) / 16.  The
- *      inscribed-cylinder volume (Sec. III-A's conservative V) takes the
+ *      inscribed-cylinder volume (Table I's conservative V) takes the
  *      cylinder whose axis is the object z axis through the AABB's centre in
  *      x and y, with radius the smaller half-extent in x and y and the AABB's
  *      z range; it is inflated by delta like the box: (q0 - c0)^2 +
@@ -70,7 +70,7 @@
  *      it is an outlier.  No further colour test applies to it.
  *   R11 Selection: lowest J; ties go to the lowest pose index.
  *
- * ICP refinement (Sec. IV-A "Parallel M2M GICP" and Sec. V-A: each pose is
+ * ICP refinement (Sec. IV-A "Parallel M2M GICP" and Sec. VI-A: each pose is
  * aligned to the observed cloud by ICP, then rendered and scored again; the
  * 3-DoF experiments use point-to-point ICP).  The paper gives no
  * correspondence rule, update or stopping rule; this oracle reads them as:

@@ -65,6 +65,11 @@ class _IcpParams(ctypes.Structure):
                 ("dof", ctypes.c_int32), ("min_points", ctypes.c_int32)]
 
 
+class _ProposalParams(ctypes.Structure):
+    _fields_ = [("viewpoints", ctypes.c_int32), ("inplane", ctypes.c_int32), ("z_step_mm", ctypes.c_float),
+                ("max_depths", ctypes.c_int32)]
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
@@ -99,6 +104,7 @@ def load_library():
         "perch_best_poses": ([P, I32, I32, P, P, P, P, P, P, VP], ctypes.c_int),
         "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
         "perch_refine_poses": ([P, I32, I32, I32, VP, I32, P, VP, VP, VP, VP], ctypes.c_int),
+        "perch_propose_poses": ([P, I32, I32, I32, P, VP, I32, P, VP], ctypes.c_int),
         "perch_scene_info_get": ([P, I32, P], ctypes.c_int),
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
@@ -342,6 +348,24 @@ class Context:
                                             ctypes.byref(prm), _dev_ptr(refined), _dev_ptr(iters), _dev_ptr(matched),
                                             _stream_ptr(stream)))
         return refined, iters, matched
+
+    def propose_poses(self, scene_id, mesh_id, label, *, viewpoints=64, inplane=12, z_step_mm=10.0, max_depths=16,
+                      stream=None):
+        """6-DoF proposals of one labelled object: a (M*N*T, 12) float32 CUDA
+        tensor (asynchronous; the count is known at return)."""
+        import torch
+        prm = _ProposalParams(int(viewpoints), int(inplane), float(z_step_mm), int(max_depths))
+        n = ctypes.c_int32()
+        _check(self._lib.perch_propose_poses(self._h, int(scene_id), int(mesh_id), int(label), ctypes.byref(prm), None,
+                                             0, ctypes.byref(n), None))
+        out = torch.empty((n.value, 12), dtype=torch.float32, device=f"cuda:{self.device}")
+        if n.value == 0:
+            return out
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        _check(self._lib.perch_propose_poses(self._h, int(scene_id), int(mesh_id), int(label), ctypes.byref(prm),
+                                             _dev_ptr(out), n.value, ctypes.byref(n), _stream_ptr(stream)))
+        return out
 
     def render(self, scene_id, mesh_id, poses, K, *, rgb=False, tri=False, stream=None):
         """Full-image renders of (n, 12) poses: (depth u16, rgb u8 or None, tri i32 or None) tensors."""

@@ -152,6 +152,17 @@ struct IcpArgs {
 };
 hipError_t launch_icp(const IcpArgs &a, int grid, hipStream_t st);
 
+// 6-DoF pose proposals of one object: viewpoint x in-plane angle x depth.
+struct ProposalArgs {
+    int M, N, T, n;
+    double zmin, zmax, step;   // depth of proposal t: zmin + t * step
+    double uc, vc;             // the label box centre (pixels)
+    double centre[3];          // object-frame centre of the mesh's AABB
+    float fx, fy, cx, cy;
+    float *out;                // n * 12
+};
+hipError_t launch_proposals(const ProposalArgs &a, hipStream_t st);
+
 // Kernel slots reported by the profiler (perch_profile_read).
 enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
                 kProfIcp = 8, kNumProfSlots = 9 };

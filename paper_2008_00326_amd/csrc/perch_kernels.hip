@@ -1645,6 +1645,51 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
     }
 }
 
+// ------------------------------------------------------------------ pose proposals
+
+// 6-DoF pose proposals (Sec. V-B "Pose Proposal Generation"): pose p is
+// viewpoint i, in-plane angle k and depth t, p = (i N + k) T + t.  Viewpoint
+// i of M on the Fibonacci lattice, z_i = 1 - (2 i + 1) / M at longitude
+// i pi (3 - sqrt 5): the camera sits in direction v_i from the object, so
+// the rotation takes v_i to the camera's -z axis (rows b1, b2, b3 with
+// b3 = -v_i and b1 along z_obj x b3, or y_obj x b3 near the poles), then
+// turns by 2 pi k / N about the optical axis.  The translation puts the
+// object's centre (its mesh's AABB centre c) on the ray through the label
+// box centre at depth z_t: t = z_t ray - R c.
+__global__ void proposal_kernel(ProposalArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int t = p % a.T, k = (p / a.T) % a.N, i = p / (a.T * a.N);
+    const double pi = 3.14159265358979323846;
+    const double vz = 1.0 - (double)(2 * i + 1) / (double)a.M;
+    const double r = sqrt(fmax(0.0, 1.0 - vz * vz));
+    const double phi = (double)i * (pi * (3.0 - sqrt(5.0)));
+    const double v[3] = {r * cos(phi), r * sin(phi), vz};
+    const double b3[3] = {-v[0], -v[1], -v[2]};
+    const double up[3] = {0.0, fabs(vz) > 0.999 ? 1.0 : 0.0, fabs(vz) > 0.999 ? 0.0 : 1.0};
+    double b1[3] = {up[1] * b3[2] - up[2] * b3[1], up[2] * b3[0] - up[0] * b3[2], up[0] * b3[1] - up[1] * b3[0]};
+    const double nb = sqrt((b1[0] * b1[0] + b1[1] * b1[1]) + b1[2] * b1[2]);
+    for (int c = 0; c < 3; ++c) b1[c] = b1[c] / nb;
+    const double b2[3] = {b3[1] * b1[2] - b3[2] * b1[1], b3[2] * b1[0] - b3[0] * b1[2], b3[0] * b1[1] - b3[1] * b1[0]};
+    const double th = 2.0 * pi * (double)k / (double)a.N;
+    const double co = cos(th), si = sin(th);
+    const double z = a.zmin + (double)t * a.step;
+    float *o = a.out + 12 * (size_t)p;
+    for (int c = 0; c < 3; ++c) {
+        o[c] = (float)(co * b1[c] - si * b2[c]);
+        o[4 + c] = (float)(si * b1[c] + co * b2[c]);
+        o[8 + c] = (float)b3[c];
+    }
+    const double ray[3] = {z * ((a.uc - (double)a.cx) / (double)a.fx), z * ((a.vc - (double)a.cy) / (double)a.fy), z};
+    for (int r = 0; r < 3; ++r) {
+        const double R0 = r == 0 ? co * b1[0] - si * b2[0] : (r == 1 ? si * b1[0] + co * b2[0] : b3[0]);
+        const double R1 = r == 0 ? co * b1[1] - si * b2[1] : (r == 1 ? si * b1[1] + co * b2[1] : b3[1]);
+        const double R2 = r == 0 ? co * b1[2] - si * b2[2] : (r == 1 ? si * b1[2] + co * b2[2] : b3[2]);
+        o[4 * r + 3] = (float)(ray[r] - ((R0 * a.centre[0] + R1 * a.centre[1]) + R2 * a.centre[2]));
+    }
+}
+
 // ------------------------------------------------------------------ argmin
 
 // Per work item: the minimum of J = J_r + J_o over its poses, the lowest
@@ -1763,6 +1808,12 @@ hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool a
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st)
 {
     item_argmin_kernel<<<items_grid, 1024, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+hipError_t launch_proposals(const ProposalArgs &a, hipStream_t st)
+{
+    if (a.n > 0) proposal_kernel<<<(a.n + 255) / 256, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -81,6 +81,7 @@ struct SceneRec {
     DevBuf depth, rgb, labels, opt, olab, kx, ky, ax, ay, thdr, tnn;
     SceneDev dev{};
     std::vector<int32_t> host_labels;
+    std::vector<uint16_t> host_depth;   // kept with labels: per-label depth ranges (pose proposals)
     std::map<int32_t, std::vector<int>> label_boxes;
     size_t bytes = 0;
     Uses uses;
@@ -389,12 +390,15 @@ bool finite3(const float *p) { return std::isfinite(p[0]) && std::isfinite(p[1])
 
 namespace {
 
+// The label's pixels: {x0, y0, w, h} of their bounding box (all 0 when
+// there are none), then the least and greatest valid depth among them (mm;
+// 1, 0 when none has a reading).
 std::vector<int> label_box(SceneRec &r, int32_t label)
 {
     auto it = r.label_boxes.find(label);
     if (it != r.label_boxes.end()) return it->second;
     const int W = r.dev.W, H = r.dev.H;
-    int x0 = W, y0 = H, x1 = -1, y1 = -1;
+    int x0 = W, y0 = H, x1 = -1, y1 = -1, zmin = 65536, zmax = 0;
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i)
             if (r.host_labels[(size_t)j * W + i] == label) {
@@ -402,8 +406,15 @@ std::vector<int> label_box(SceneRec &r, int32_t label)
                 x1 = std::max(x1, i);
                 y0 = std::min(y0, j);
                 y1 = std::max(y1, j);
+                const int d = r.host_depth.empty() ? 0 : r.host_depth[(size_t)j * W + i];
+                if (d > 0) {
+                    zmin = std::min(zmin, d);
+                    zmax = std::max(zmax, d);
+                }
             }
     std::vector<int> b = x1 < 0 ? std::vector<int>{0, 0, 0, 0} : std::vector<int>{x0, y0, x1 - x0 + 1, y1 - y0 + 1};
+    b.push_back(zmax > 0 ? zmin : 1);
+    b.push_back(zmax);
     r.label_boxes[label] = b;
     return b;
 }
@@ -976,7 +987,10 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         cleanup();
         return fail(PERCH_EDEVICE, "scene table fill: %s", hipGetErrorString(e));
     }
-    if (d->labels) r.host_labels.assign(d->labels, d->labels + N);
+    if (d->labels) {
+        r.host_labels.assign(d->labels, d->labels + N);
+        r.host_depth.assign(d->depth_mm, d->depth_mm + N);
+    }
     r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.opt.bytes + r.olab.bytes + r.kx.bytes
               + r.ky.bytes + r.ax.bytes + r.ay.bytes + r.thdr.bytes + r.tnn.bytes;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -1151,6 +1165,54 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     HIP_TRY(ctx->timed(kProfIcp, st, [&] { return launch_icp(a, grid, st); }));
     ctx->mark_use(si->second.uses, st);
     ctx->mark_use(mi->second.uses, st);
+    return ok();
+}
+
+perch_status perch_propose_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                 const perch_proposal_params *prm, float *poses_dev, int32_t capacity, int32_t *n_out,
+                                 void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    if (!prm || !n_out) return fail(PERCH_EINVAL, "null parameters or count");
+    if (prm->viewpoints < 1 || prm->inplane < 1 || prm->max_depths < 1)
+        return fail(PERCH_EINVAL, "viewpoints, inplane and max_depths must be >= 1");
+    if (!(prm->z_step_mm > 0.0f)) return fail(PERCH_EINVAL, "z_step_mm must be > 0");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    if (si->second.host_labels.empty()) return fail(PERCH_EINVAL, "scene %d has no labels", scene_id);
+    auto mi = ctx->meshes.find(mesh_id);
+    if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    const std::vector<int> lb = label_box(si->second, label);
+    *n_out = 0;
+    if (lb[2] == 0 || lb[5] < lb[4]) return ok();      // no labelled pixel with a depth reading
+    long long T = (long long)std::floor((double)(lb[5] - lb[4]) / (double)prm->z_step_mm) + 1;
+    const bool spread = T > prm->max_depths;
+    if (spread) T = prm->max_depths;
+    const long long n = (long long)prm->viewpoints * prm->inplane * T;
+    if (n > (1LL << 30)) return fail(PERCH_EINVAL, "too many proposals (%lld)", n);
+    *n_out = (int32_t)n;
+    if (!poses_dev) return ok();                       // count only
+    if (capacity < n) return fail(PERCH_EINVAL, "capacity %d < %lld proposals", capacity, n);
+    const SceneDev &s = si->second.dev;
+    ProposalArgs a{};
+    a.M = prm->viewpoints;
+    a.N = prm->inplane;
+    a.T = (int)T;
+    a.zmin = (double)lb[4];
+    a.zmax = (double)lb[5];
+    a.step = spread ? (T > 1 ? (a.zmax - a.zmin) / (double)(T - 1) : 0.0) : (double)prm->z_step_mm;
+    a.uc = (double)lb[0] + (double)(lb[2] - 1) / 2.0;
+    a.vc = (double)lb[1] + (double)(lb[3] - 1) / 2.0;
+    a.fx = s.fx;
+    a.fy = s.fy;
+    a.cx = s.cx;
+    a.cy = s.cy;
+    for (int c = 0; c < 3; ++c)
+        a.centre[c] = ((double)mi->second.dev.lo[c] + (double)mi->second.dev.hi[c]) / 2.0;
+    a.out = poses_dev;
+    a.n = (int)n;
+    HIP_TRY(launch_proposals(a, pick_stream(ctx, hip_stream)));
     return ok();
 }
 
