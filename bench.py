@@ -621,9 +621,13 @@ def calibrate_copy():
 
 
 def kernel_source_sha():
+    """Hash of the scoring kernels' source (the kernel file and the device
+    helpers it includes), which the committed counter record must match."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2008_00326_amd", "csrc", "perch_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("perch_kernels.hip", "perch_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_2008_00326_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_counters(kernel_slot):

@@ -18,7 +18,7 @@
 // Geometry and depth use integer / binary64 arithmetic that the oracle
 // reproduces exactly (no FMA contraction: built with -ffp-contract=off).
 
-#include "perch_internal.h"
+#include "perch_device.h"
 
 #include <math.h>
 
@@ -26,149 +26,7 @@ namespace perch {
 
 __constant__ float c_lin[256];   // sRGB8 -> linear, rounded from binary64
 
-// Load through a global-address-space pointer: the scene, mesh and pose
-// arrays are reached through descriptors in device memory, which the
-// compiler would otherwise access with flat instructions.
-#define PERCH_GLOBAL __attribute__((address_space(1)))
-typedef int perch_v2i __attribute__((ext_vector_type(2)));
-typedef int perch_v4i __attribute__((ext_vector_type(4)));
-typedef float perch_v4f __attribute__((ext_vector_type(4)));
-
-template <class T>
-__device__ __forceinline__ T gld(const T *p)
-{
-    return *(const PERCH_GLOBAL T *)p;
-}
-template <>
-__device__ __forceinline__ int2 gld(const int2 *p)
-{
-    const perch_v2i v = *(const PERCH_GLOBAL perch_v2i *)p;
-    return make_int2(v.x, v.y);
-}
-template <>
-__device__ __forceinline__ int4 gld(const int4 *p)
-{
-    const perch_v4i v = *(const PERCH_GLOBAL perch_v4i *)p;
-    return make_int4(v.x, v.y, v.z, v.w);
-}
-template <>
-__device__ __forceinline__ float4 gld(const float4 *p)
-{
-    const perch_v4f v = *(const PERCH_GLOBAL perch_v4f *)p;
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-
-// ------------------------------------------------------------------ geometry
-
-struct Vtx {
-    int U, V;      // 24.8 fixed point
-    double iz;     // 1 / Zc
-    int ok;
-};
-
-__device__ __forceinline__ Vtx project_vertex(const float *P, float4 v, const SceneDev &s)
-{
-    const double x = v.x, y = v.y, z = v.z;
-    const double X = (((double)P[0] * x + (double)P[1] * y) + (double)P[2] * z) + (double)P[3];
-    const double Y = (((double)P[4] * x + (double)P[5] * y) + (double)P[6] * z) + (double)P[7];
-    const double Z = (((double)P[8] * x + (double)P[9] * y) + (double)P[10] * z) + (double)P[11];
-    Vtx o;
-    o.ok = 0;
-    o.U = 0;
-    o.V = 0;
-    o.iz = 0.0;
-    if (!(Z >= 100.0)) return o;
-    o.iz = 1.0 / Z;
-    const double u = (((double)s.fx * X) * o.iz) + (double)s.cx;
-    const double w = (((double)s.fy * Y) * o.iz) + (double)s.cy;
-    const double su = 256.0 * u, sv = 256.0 * w;
-    if (!(fabs(su) <= 16777216.0) || !(fabs(sv) <= 16777216.0)) return o;
-    o.U = (int)rint(su);
-    o.V = (int)rint(sv);
-    o.ok = 1;
-    return o;
-}
-
-__device__ __forceinline__ long long edge_fn(int ax, int ay, int bx, int by, long long px, long long py)
-{
-    return (long long)(by - ay) * (px - ax) - (long long)(bx - ax) * (py - ay);
-}
-
-// covered iff E > 0, or E == 0 on a top-left edge  <=>  E >= bias
-__device__ __forceinline__ long long edge_bias(int ax, int ay, int bx, int by)
-{
-    const int dy = by - ay, dx = bx - ax;
-    return (dy > 0 || (dy == 0 && dx < 0)) ? 0 : 1;
-}
-
-// tile accessors: plain LDS traffic, or agent-scope atomics for global tiles
-template <bool G>
-__device__ __forceinline__ uint32_t tld(const uint32_t *p)
-{
-    if constexpr (G) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else return *p;
-}
-template <bool G>
-__device__ __forceinline__ void tst(uint32_t *p, uint32_t v)
-{
-    if constexpr (G) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else *p = v;
-}
-template <bool G>
-__device__ __forceinline__ void tmin(uint32_t *p, uint32_t v)
-{
-    if constexpr (G) __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else atomicMin(p, v);
-}
-// Rasterize triangle t into the tile covering pixels [tx0, tx0+tw) x [ty0, ty0+th).
-template <bool G>
-__device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev &m, const float *P,
-                                                int t, int tx0, int ty0, int tw, int th,
-                                                uint32_t *tile)
-{
-    const int4 ix = gld(m.tris + t);
-    const Vtx a = project_vertex(P, gld(m.verts + ix.x), s);
-    const Vtx b = project_vertex(P, gld(m.verts + ix.y), s);
-    const Vtx c = project_vertex(P, gld(m.verts + ix.z), s);
-    if (!(a.ok & b.ok & c.ok)) return;
-    const long long area = edge_fn(a.U, a.V, b.U, b.V, c.U, c.V);
-    if (area <= 0) return;
-    const int minU = min(a.U, min(b.U, c.U)), maxU = max(a.U, max(b.U, c.U));
-    const int minV = min(a.V, min(b.V, c.V)), maxV = max(a.V, max(b.V, c.V));
-    const int i0 = max(-((-minU) >> 8), tx0), i1 = min(maxU >> 8, tx0 + tw - 1);
-    const int j0 = max(-((-minV) >> 8), ty0), j1 = min(maxV >> 8, ty0 + th - 1);
-    if (i0 > i1 || j0 > j1) return;
-    const long long px0 = 256LL * i0, py0 = 256LL * j0;
-    long long r0 = edge_fn(b.U, b.V, c.U, c.V, px0, py0);
-    long long r1 = edge_fn(c.U, c.V, a.U, a.V, px0, py0);
-    long long r2 = edge_fn(a.U, a.V, b.U, b.V, px0, py0);
-    const long long sx0 = 256LL * (c.V - b.V), sy0 = -256LL * (c.U - b.U);
-    const long long sx1 = 256LL * (a.V - c.V), sy1 = -256LL * (a.U - c.U);
-    const long long sx2 = 256LL * (b.V - a.V), sy2 = -256LL * (b.U - a.U);
-    const long long b0 = edge_bias(b.U, b.V, c.U, c.V);
-    const long long b1 = edge_bias(c.U, c.V, a.U, a.V);
-    const long long b2 = edge_bias(a.U, a.V, b.U, b.V);
-    const double farea = (double)area;
-    for (int j = j0; j <= j1; ++j) {
-        long long w0 = r0, w1 = r1, w2 = r2;
-        uint32_t *row = tile + (size_t)(j - ty0) * tw;
-        for (int i = i0; i <= i1; ++i) {
-            if (w0 >= b0 && w1 >= b1 && w2 >= b2) {
-                const double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
-                const double sum = (t0 + t1) + t2;
-                const double d = rint(farea / sum);
-                if (d >= 1.0 && d <= 65534.0)
-                    tmin<G>(row + (i - tx0), ((uint32_t)d << 16) | (uint32_t)t);
-            }
-            w0 += sx0;
-            w1 += sx1;
-            w2 += sx2;
-        }
-        r0 += sy0;
-        r1 += sy1;
-        r2 += sy2;
-    }
-}
+// ------------------------------------------------------------------ colour of a pixel
 
 // Perspective-correct vertex colour of triangle t at pixel (i, j), rounded to sRGB8.
 __device__ uint32_t triangle_colour(const SceneDev &s, const MeshDev &m, const float *P, int t, int i, int j)
@@ -299,16 +157,6 @@ __constant__ uint32_t c_rcp16[65] = {
     1928, 1873,  1821,  1772,  1725,  1681,  1639,  1599, 1561, 1525, 1490, 1457, 1425, 1395, 1366, 1338, 1311,
     1286, 1261,  1237,  1214,  1192,  1171,  1150,  1130, 1111, 1093, 1075, 1058, 1041, 1024};
 
-// Row of entry q of a row-major window ww pixels wide: a binary32 estimate
-// corrected to the exact quotient.
-__device__ __forceinline__ int window_row(int q, int ww, float inv)
-{
-    int qy = (int)(((float)q + 0.5f) * inv);
-    if (qy * ww > q) --qy;
-    else if ((qy + 1) * ww <= q) ++qy;
-    return qy;
-}
-
 // Nearest-neighbour keys of the J_o region: smallest (squared distance,
 // tile index of the rendered point) over the rendered points within delta.
 // 32 bits (distance << 16 | index) in LDS, 64 bits in device memory.
@@ -335,14 +183,6 @@ template <> struct KeyOf<true> {
 // Key update of an observed point q by rendered point (X, Y, Z) with tile
 // index k, if the two lie within delta; dq + 1 < 2^13, so the 24-bit
 // products are exact.
-// v_med3_i32 as a clamp (lo <= hi).
-__device__ __forceinline__ int clamp_i32(int x, int lo, int hi)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
-    return r;
-}
-
 template <bool G>
 __device__ __forceinline__ void mark_one(int4 q, int X, int Y, int Z, int k, int lim, int dq2,
                                          typename KeyOf<G>::T *key)
@@ -837,47 +677,6 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
 
 // ------------------------------------------------------------------ setup
 
-__device__ __forceinline__ void project_box(const float *P, const float lo[3], const float hi[3], double pad,
-                                            const SceneDev &s, double *umin, double *umax, double *vmin,
-                                            double *vmax, double *zmin, double *zmax)
-{
-    *umin = *vmin = *zmin = 1e300;
-    *umax = *vmax = *zmax = -1e300;
-    for (int c = 0; c < 8; ++c) {
-        const double x = (c & 1) ? (double)hi[0] + pad : (double)lo[0] - pad;
-        const double y = (c & 2) ? (double)hi[1] + pad : (double)lo[1] - pad;
-        const double z = (c & 4) ? (double)hi[2] + pad : (double)lo[2] - pad;
-        const double X = (((double)P[0] * x + (double)P[1] * y) + (double)P[2] * z) + (double)P[3];
-        const double Y = (((double)P[4] * x + (double)P[5] * y) + (double)P[6] * z) + (double)P[7];
-        const double Z = (((double)P[8] * x + (double)P[9] * y) + (double)P[10] * z) + (double)P[11];
-        *zmin = fmin(*zmin, Z);
-        *zmax = fmax(*zmax, Z);
-        if (Z > 0.0) {
-            const double u = (double)s.fx * X / Z + (double)s.cx;
-            const double v = (double)s.fy * Y / Z + (double)s.cy;
-            *umin = fmin(*umin, u);
-            *umax = fmax(*umax, u);
-            *vmin = fmin(*vmin, v);
-            *vmax = fmax(*vmax, v);
-        }
-    }
-}
-
-__device__ __forceinline__ void clip_box(double umin, double umax, double vmin, double vmax, int W, int H, int *x0,
-                                         int *y0, int *w, int *h)
-{
-    const double a = fmax(floor(umin) - 1.0, 0.0), b = fmin(ceil(umax) + 1.0, (double)(W - 1));
-    const double c = fmax(floor(vmin) - 1.0, 0.0), d = fmin(ceil(vmax) + 1.0, (double)(H - 1));
-    if (a > b || c > d) {
-        *x0 = *y0 = *w = *h = 0;
-        return;
-    }
-    *x0 = (int)a;
-    *y0 = (int)c;
-    *w = (int)b - (int)a + 1;
-    *h = (int)d - (int)c + 1;
-}
-
 __global__ void zero_counts_kernel(int *counts)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1331,365 +1130,6 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev s, MeshDev m, cons
     }
 }
 
-// ------------------------------------------------------------------ ICP refinement
-
-// Per-iteration ICP sums over the matched pairs (q, c), one component per
-// lane: n, q (3), c (3), q q^T (9, row-major), q c^T (9, row-major).
-constexpr int kIcpSums = 25;
-
-__device__ __forceinline__ long long icp_pick(int a, long long x, long long y, long long z)
-{
-    return a == 0 ? x : (a == 1 ? y : z);
-}
-
-__device__ __forceinline__ long long icp_term(int j, int4 q, int4 c)
-{
-    if (j == 0) return 1;
-    if (j < 4) return icp_pick(j - 1, q.x, q.y, q.z);
-    if (j < 7) return icp_pick(j - 4, c.x, c.y, c.z);
-    if (j < 16) return icp_pick((j - 7) / 3, q.x, q.y, q.z) * icp_pick((j - 7) % 3, q.x, q.y, q.z);
-    return icp_pick((j - 16) / 3, q.x, q.y, q.z) * icp_pick((j - 16) % 3, c.x, c.y, c.z);
-}
-
-// Nearest observed point of q (1/16 mm) within rq, ties to the lower pixel
-// index, or -1; with `labels`, only pixels carrying `label` count (label
-// volumes: the object's segment is the target), and `box` (inside the
-// image) holds every pixel that can count.  The whole wave searches, lanes
-// over a pixel window that
-// holds every candidate: an observed point at depth d (mm) with
-// |Xq - qx| <= rq has rint(kx[i] d) in [qx - rq, qx + rq], so
-// kx[i] d lies within half a unit of that range, for d in
-// [(qz - rq) / 16, (qz + rq) / 16]; one pixel of margin on each side.
-__device__ int icp_nn(const SceneDev &s, int4 q, int rq, int rq2, const int32_t *labels, int label, const int *box,
-                      int lane)
-{
-    const int dlo = q.z - rq <= 16 ? 1 : (q.z - rq + 15) / 16;
-    const int dhi = min(65534, (q.z + rq) / 16);
-    if (q.z + rq < 16 || dlo > dhi) return -1;
-    const double lo_d = (double)dlo, hi_d = (double)dhi;
-    int b[4];
-    const int qv[2] = {q.x, q.y};
-    for (int ax = 0; ax < 2; ++ax) {
-        const double f16 = (double)(ax == 0 ? s.fx : s.fy) / 16.0, c = (double)(ax == 0 ? s.cx : s.cy);
-        const double lo = (double)(qv[ax] - rq) - 0.5, hi = (double)(qv[ax] + rq) + 0.5;
-        const double a = c + f16 * fmin(lo / lo_d, lo / hi_d), z = c + f16 * fmax(hi / lo_d, hi / hi_d);
-        b[2 * ax] = (int)floor(fmax(fmin(a, 1e8), -1e8)) - 1;
-        b[2 * ax + 1] = (int)ceil(fmax(fmin(z, 1e8), -1e8)) + 1;
-    }
-    const int i0 = max(b[0], box[0]), i1 = min(b[1], box[2]), j0 = max(b[2], box[1]), j1 = min(b[3], box[3]);
-    if (i0 > i1 || j0 > j1) return -1;
-    const int ww = i1 - i0 + 1, n = ww * (j1 - j0 + 1);
-    const float inv = 1.0f / (float)ww;
-    const int lim = rq + 1;
-    unsigned long long best = ~0ULL;
-    for (int k0 = 0; k0 < n; k0 += 64) {
-        const int k = k0 + lane;
-        if (k < n) {
-            const int r = window_row(k, ww, inv);
-            const int pix = (j0 + r) * s.W + i0 + (k - r * ww);
-            const int4 o = gld(s.opt + pix);
-            const int dx = clamp_i32(o.x - q.x, -lim, lim);
-            const int dy = clamp_i32(o.y - q.y, -lim, lim);
-            const int dz = clamp_i32(o.z - q.z, -lim, lim);
-            const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
-            if (d2 <= rq2 && (!labels || gld(labels + pix) == label)) {
-                const unsigned long long key = ((unsigned long long)(uint32_t)d2 << 32) | (uint32_t)pix;
-                best = key < best ? key : best;
-            }
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(best, off);
-        best = o < best ? o : best;
-    }
-    return best == ~0ULL ? -1 : (int)(best & 0xFFFFFFFFu);
-}
-
-// One ICP update from the sums (n, q, c, q q^T, q c^T): the increment about
-// the source centroid mq composed into (A, b), b in 1/16 mm.  3-DoF: the
-// planar Procrustes rotation about the unit axis u and the centroid moved
-// within the plane normal to u; 6-DoF: a Gauss-Newton step of the
-// linearised rotation, (tr(S) I - S) w' = w, mapped to a rotation by the
-// unit quaternion (1, w'/2) and the centroid moved onto mc.  Every step
-// uses + - * / and sqrt only, left to right.  Returns 1 when the 6-DoF
-// system is singular (nothing changes).
-__device__ int icp_update(const long long *z, int dof, const double u[3], double *A, double *b)
-{
-    const double n = (double)z[0];
-    double mq[3], mc[3], S[3][3], H[3][3];
-    for (int a = 0; a < 3; ++a) {
-        mq[a] = (double)z[1 + a] / n;
-        mc[a] = (double)z[4 + a] / n;
-    }
-    for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) {
-            S[a][c] = (double)z[7 + 3 * a + c] - ((double)z[1 + a] * (double)z[1 + c]) / n;
-            H[a][c] = (double)z[16 + 3 * a + c] - ((double)z[1 + a] * (double)z[4 + c]) / n;
-        }
-    const double w[3] = {H[1][2] - H[2][1], H[2][0] - H[0][2], H[0][1] - H[1][0]};
-    double R[3][3], mp[3];
-    if (dof == 3) {
-        double Hu[3];
-        for (int a = 0; a < 3; ++a) Hu[a] = (H[a][0] * u[0] + H[a][1] * u[1]) + H[a][2] * u[2];
-        const double uHu = (u[0] * Hu[0] + u[1] * Hu[1]) + u[2] * Hu[2];
-        const double Ap = ((H[0][0] + H[1][1]) + H[2][2]) - uHu;
-        const double B = (u[0] * w[0] + u[1] * w[1]) + u[2] * w[2];
-        const double h = sqrt(Ap * Ap + B * B);
-        double co = 1.0, si = 0.0;
-        if (h > 0.0) {
-            co = Ap / h;
-            si = B / h;
-        }
-        const double Kx[3][3] = {{0.0, -u[2], u[1]}, {u[2], 0.0, -u[0]}, {-u[1], u[0], 0.0}};
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c) R[a][c] = ((a == c ? co : 0.0) + si * Kx[a][c]) + ((1.0 - co) * u[a]) * u[c];
-        const double d[3] = {mc[0] - mq[0], mc[1] - mq[1], mc[2] - mq[2]};
-        const double ud = (u[0] * d[0] + u[1] * d[1]) + u[2] * d[2];
-        for (int a = 0; a < 3; ++a) mp[a] = mq[a] + (d[a] - ud * u[a]);
-    } else {
-        const double tr = (S[0][0] + S[1][1]) + S[2][2];
-        double M[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c) M[a][c] = (a == c ? tr : 0.0) - S[a][c];
-        double adj[3][3];
-        adj[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
-        adj[0][1] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
-        adj[0][2] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
-        adj[1][0] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
-        adj[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
-        adj[1][2] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
-        adj[2][0] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
-        adj[2][1] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
-        adj[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
-        const double det = (M[0][0] * adj[0][0] + M[0][1] * adj[1][0]) + M[0][2] * adj[2][0];
-        if (!(det > 0.0)) return 1;
-        double h[3];
-        for (int a = 0; a < 3; ++a) h[a] = (((adj[a][0] * w[0] + adj[a][1] * w[1]) + adj[a][2] * w[2]) / det) / 2.0;
-        const double r = sqrt(1.0 + ((h[0] * h[0] + h[1] * h[1]) + h[2] * h[2]));
-        const double qw = 1.0 / r, qx = h[0] / r, qy = h[1] / r, qz = h[2] / r;
-        R[0][0] = 1.0 - 2.0 * (qy * qy + qz * qz);
-        R[0][1] = 2.0 * (qx * qy - qz * qw);
-        R[0][2] = 2.0 * (qx * qz + qy * qw);
-        R[1][0] = 2.0 * (qx * qy + qz * qw);
-        R[1][1] = 1.0 - 2.0 * (qx * qx + qz * qz);
-        R[1][2] = 2.0 * (qy * qz - qx * qw);
-        R[2][0] = 2.0 * (qx * qz - qy * qw);
-        R[2][1] = 2.0 * (qy * qz + qx * qw);
-        R[2][2] = 1.0 - 2.0 * (qx * qx + qy * qy);
-        for (int a = 0; a < 3; ++a) mp[a] = mc[a];
-    }
-    double An[9], bn[3];
-    const double e[3] = {b[0] - mq[0], b[1] - mq[1], b[2] - mq[2]};
-    for (int a = 0; a < 3; ++a) {
-        for (int c = 0; c < 3; ++c) An[3 * a + c] = (R[a][0] * A[c] + R[a][1] * A[3 + c]) + R[a][2] * A[6 + c];
-        bn[a] = ((R[a][0] * e[0] + R[a][1] * e[1]) + R[a][2] * e[2]) + mp[a];
-    }
-    for (int k = 0; k < 9; ++k) A[k] = An[k];
-    for (int k = 0; k < 3; ++k) b[k] = bn[k];
-    return 0;
-}
-
-__global__ void icp_zero_kernel(int *cursor)
-{
-    if (threadIdx.x == 0) cursor[threadIdx.x] = 0;
-}
-
-// ICP refinement (Sec. IV-A "Parallel M2M GICP"; point-to-point): one pose
-// per work-group at a time, taken through a cursor.  The pose is rendered
-// into the work-group's device tile, its rendered points (R minus C on the
-// ICP stride grid) collected, then each iteration maps them by the current
-// transform (rounded to 1/16 mm), stops when no mapped point moved, matches
-// each to its nearest observed point within rho (one wave per point), sums
-// the pairs exactly in int64 and updates the transform on one thread.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
-{
-    constexpr int NW = BLOCK / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const SceneDev &s = a.s;
-    const MeshDev &m = a.m;
-    __shared__ int s_pose, s_n, s_box[4], s_changed, s_stop;
-    __shared__ long long s_red[NW][kIcpSums];
-    __shared__ double s_A[9], s_b[3];
-    uint32_t *tile = a.tiles + (size_t)blockIdx.x * s.W * s.H;
-    int4 *src = a.pts + (size_t)blockIdx.x * 2 * a.pts_cap;
-    int4 *qb = src + a.pts_cap;
-    const bool mark = (s.flags & 2u) != 0;
-    const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
-    for (;;) {
-        if (tid == 0) s_pose = atomicAdd(a.cursor, 1);
-        __syncthreads();
-        const int p = s_pose;
-        if (p >= a.n) break;
-        float P[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) P[k] = a.poses[12 * (size_t)p + k];
-        if (tid == 0) {
-            double umin, umax, vmin, vmax, zmin, zmax;
-            int x0 = 0, y0 = 0, w = 0, h = 0;
-            project_box(P, m.lo, m.hi, 0.0, s, &umin, &umax, &vmin, &vmax, &zmin, &zmax);
-            if (zmin >= 100.0) {
-                clip_box(umin, umax, vmin, vmax, s.W, s.H, &x0, &y0, &w, &h);
-            } else if (!(zmax < 99.999)) {
-                w = s.W;
-                h = s.H;
-            }
-            s_box[0] = x0;
-            s_box[1] = y0;
-            s_box[2] = w;
-            s_box[3] = h;
-            s_n = 0;
-            for (int k = 0; k < 9; ++k) s_A[k] = (k % 4 == 0) ? 1.0 : 0.0;
-            s_b[0] = s_b[1] = s_b[2] = 0.0;
-        }
-        __syncthreads();
-        const int tx0 = s_box[0], ty0 = s_box[1], tw = s_box[2], th = s_box[3];
-        const int tpx = tw * th;
-        for (int k = tid; k < tpx; k += BLOCK) tst<true>(tile + k, kEmptyKey);
-        __syncthreads();
-        if (tpx > 0)
-            for (int t0 = 0; t0 < m.nt; t0 += BLOCK)
-                if (t0 + tid < m.nt) raster_triangle<true>(s, m, P, t0 + tid, tx0, ty0, tw, th, tile);
-        __syncthreads();
-        for (int k = tid; k < tpx; k += BLOCK) {
-            const uint32_t key = tld<true>(tile + k);
-            if (key == kEmptyKey) continue;
-            const int ty = k / tw, tx = k - ty * tw;
-            const int i = tx0 + tx, j = ty0 + ty, d = (int)(key >> 16);
-            if (i % a.stride != 0 || j % a.stride != 0) continue;
-            const int pix = j * s.W + i;
-            if (mark) {
-                const int dob = gld(s.depth + pix);
-                if (dob > 0 && 16 * dob + s.dq < 16 * d && (!(label_mode && s.labels) || s.labels[pix] != a.label))
-                    continue;
-            }
-            const int slot = atomicAdd(&s_n, 1);
-            src[slot] = make_int4((int)rint(gld(s.kx + i) * (double)d), (int)rint(gld(s.ky + j) * (double)d), 16 * d, 0);
-        }
-        __syncthreads();
-        const int ns = s_n;
-        double u[3] = {0.0, 0.0, 0.0};
-        int iters = 0, matched = 0;
-        if (tid == 0) {
-            const double v[3] = {(double)P[2], (double)P[6], (double)P[10]};
-            const double nrm = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
-            for (int c = 0; c < 3; ++c) u[c] = v[c] / nrm;
-        }
-        for (int it = 0; it < a.iterations; ++it) {
-            if (tid == 0) s_changed = 0;
-            __syncthreads();
-            bool ch = false;
-            for (int t = tid; t < ns; t += BLOCK) {
-                const int4 sp = src[t];
-                int qv[3];
-                for (int c = 0; c < 3; ++c) {
-                    // beyond 2^28 units (16 km) nothing can match; the clamp keeps the search in int range
-                    const double v = rint(((s_A[3 * c] * (double)sp.x + s_A[3 * c + 1] * (double)sp.y)
-                                           + s_A[3 * c + 2] * (double)sp.z) + s_b[c]);
-                    qv[c] = (int)fmax(fmin(v, 268435456.0), -268435456.0);
-                }
-                const int4 q = make_int4(qv[0], qv[1], qv[2], 0);
-                if (it == 0) {
-                    ch = true;
-                } else {
-                    const int4 o = qb[t];
-                    ch |= o.x != q.x || o.y != q.y || o.z != q.z;
-                }
-                qb[t] = q;
-            }
-            if (ch) s_changed = 1;
-            __syncthreads();
-            if (!s_changed) break;
-            long long acc = 0;
-            for (int t = wave; t < ns; t += NW) {
-                const int4 q = qb[t];
-                const int nn = icp_nn(s, q, a.rq, a.rq2, label_mode ? s.labels : nullptr, a.label, a.box, lane);
-                if (nn >= 0) {
-                    const int4 c = gld(s.opt + nn);
-                    if (lane < kIcpSums) acc += icp_term(lane, q, c);
-                }
-            }
-            if (lane < kIcpSums) s_red[wave][lane] = acc;
-            __syncthreads();
-            if (tid < kIcpSums) {
-                long long z = 0;
-                for (int v = 0; v < NW; ++v) z += s_red[v][tid];
-                s_red[0][tid] = z;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int stop = 0;
-                matched = (int)s_red[0][0];
-                if (s_red[0][0] < a.min_points) stop = 1;
-                else if (icp_update(s_red[0], a.dof, u, s_A, s_b)) stop = 1;
-                else iters = it + 1;
-                s_stop = stop;
-            }
-            __syncthreads();
-            if (s_stop) break;
-        }
-        if (tid == 0) {
-            float *out = a.refined + 12 * (size_t)p;
-            for (int r = 0; r < 3; ++r) {
-                for (int c = 0; c < 3; ++c)
-                    out[4 * r + c] = (float)((s_A[3 * r] * (double)P[c] + s_A[3 * r + 1] * (double)P[4 + c])
-                                             + s_A[3 * r + 2] * (double)P[8 + c]);
-                const double t = ((s_A[3 * r] * (16.0 * (double)P[3]) + s_A[3 * r + 1] * (16.0 * (double)P[7]))
-                                  + s_A[3 * r + 2] * (16.0 * (double)P[11])) + s_b[r];
-                out[4 * r + 3] = (float)(t / 16.0);
-            }
-            if (a.iters) a.iters[p] = iters;
-            if (a.matched) a.matched[p] = matched;
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ pose proposals
-
-// 6-DoF pose proposals (Sec. V-B "Pose Proposal Generation"): pose p is
-// viewpoint i, in-plane angle k and depth t, p = (i N + k) T + t.  Viewpoint
-// i of M on the Fibonacci lattice, z_i = 1 - (2 i + 1) / M at longitude
-// i pi (3 - sqrt 5): the camera sits in direction v_i from the object, so
-// the rotation takes v_i to the camera's -z axis (rows b1, b2, b3 with
-// b3 = -v_i and b1 along z_obj x b3, or y_obj x b3 near the poles), then
-// turns by 2 pi k / N about the optical axis.  The translation puts the
-// object's centre (its mesh's AABB centre c) on the ray through the label
-// box centre at depth z_t: t = z_t ray - R c.
-__global__ void proposal_kernel(ProposalArgs a)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const int t = p % a.T, k = (p / a.T) % a.N, i = p / (a.T * a.N);
-    const double pi = 3.14159265358979323846;
-    const double vz = 1.0 - (double)(2 * i + 1) / (double)a.M;
-    const double r = sqrt(fmax(0.0, 1.0 - vz * vz));
-    const double phi = (double)i * (pi * (3.0 - sqrt(5.0)));
-    const double v[3] = {r * cos(phi), r * sin(phi), vz};
-    const double b3[3] = {-v[0], -v[1], -v[2]};
-    const double up[3] = {0.0, fabs(vz) > 0.999 ? 1.0 : 0.0, fabs(vz) > 0.999 ? 0.0 : 1.0};
-    double b1[3] = {up[1] * b3[2] - up[2] * b3[1], up[2] * b3[0] - up[0] * b3[2], up[0] * b3[1] - up[1] * b3[0]};
-    const double nb = sqrt((b1[0] * b1[0] + b1[1] * b1[1]) + b1[2] * b1[2]);
-    for (int c = 0; c < 3; ++c) b1[c] = b1[c] / nb;
-    const double b2[3] = {b3[1] * b1[2] - b3[2] * b1[1], b3[2] * b1[0] - b3[0] * b1[2], b3[0] * b1[1] - b3[1] * b1[0]};
-    const double th = 2.0 * pi * (double)k / (double)a.N;
-    const double co = cos(th), si = sin(th);
-    const double z = a.zmin + (double)t * a.step;
-    float *o = a.out + 12 * (size_t)p;
-    for (int c = 0; c < 3; ++c) {
-        o[c] = (float)(co * b1[c] - si * b2[c]);
-        o[4 + c] = (float)(si * b1[c] + co * b2[c]);
-        o[8 + c] = (float)b3[c];
-    }
-    const double ray[3] = {z * ((a.uc - (double)a.cx) / (double)a.fx), z * ((a.vc - (double)a.cy) / (double)a.fy), z};
-    for (int r = 0; r < 3; ++r) {
-        const double R0 = r == 0 ? co * b1[0] - si * b2[0] : (r == 1 ? si * b1[0] + co * b2[0] : b3[0]);
-        const double R1 = r == 0 ? co * b1[1] - si * b2[1] : (r == 1 ? si * b1[1] + co * b2[1] : b3[1]);
-        const double R2 = r == 0 ? co * b1[2] - si * b2[2] : (r == 1 ? si * b1[2] + co * b2[2] : b3[2]);
-        o[4 * r + 3] = (float)(ray[r] - ((R0 * a.centre[0] + R1 * a.centre[1]) + R2 * a.centre[2]));
-    }
-}
-
 // ------------------------------------------------------------------ argmin
 
 // Per work item: the minimum of J = J_r + J_o over its poses, the lowest
@@ -1808,19 +1248,6 @@ hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool a
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st)
 {
     item_argmin_kernel<<<items_grid, 1024, 0, st>>>(w);
-    return hipGetLastError();
-}
-
-hipError_t launch_proposals(const ProposalArgs &a, hipStream_t st)
-{
-    if (a.n > 0) proposal_kernel<<<(a.n + 255) / 256, 256, 0, st>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_icp(const IcpArgs &a, int grid, hipStream_t st)
-{
-    icp_zero_kernel<<<1, 1, 0, st>>>(a.cursor);
-    icp_kernel<1024><<<grid, 1024, 0, st>>>(a);
     return hipGetLastError();
 }
 
