@@ -105,16 +105,41 @@ __device__ __forceinline__ void tmin(uint32_t *p, uint32_t v)
     if constexpr (G) __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else atomicMin(p, v);
 }
+// A projected vertex packed in 16 bytes (U, V, iz), for a per-pose cache in
+// LDS; iz < 0 marks a vertex that takes part in no drawn triangle.
+__device__ __forceinline__ int4 pack_vtx(const Vtx &v)
+{
+    const long long b = __double_as_longlong(v.ok ? v.iz : -1.0);
+    return make_int4(v.U, v.V, (int)(uint32_t)b, (int)(uint32_t)(b >> 32));
+}
+__device__ __forceinline__ Vtx unpack_vtx(int4 q)
+{
+    Vtx v;
+    v.U = q.x;
+    v.V = q.y;
+    v.iz = __longlong_as_double(((long long)(uint32_t)q.w << 32) | (uint32_t)q.z);
+    v.ok = v.iz > 0.0;
+    return v;
+}
+
 // Rasterize triangle t into the tile covering pixels [tx0, tx0+tw) x [ty0, ty0+th).
+// vcache, when given, holds every vertex projected at this pose.
 template <bool G>
 __device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev &m, const float *P,
                                                 int t, int tx0, int ty0, int tw, int th,
-                                                uint32_t *tile)
+                                                uint32_t *tile, const int4 *vcache = nullptr)
 {
     const int4 ix = gld(m.tris + t);
-    const Vtx a = project_vertex(P, gld(m.verts + ix.x), s);
-    const Vtx b = project_vertex(P, gld(m.verts + ix.y), s);
-    const Vtx c = project_vertex(P, gld(m.verts + ix.z), s);
+    Vtx a, b, c;
+    if (vcache) {
+        a = unpack_vtx(vcache[ix.x]);
+        b = unpack_vtx(vcache[ix.y]);
+        c = unpack_vtx(vcache[ix.z]);
+    } else {
+        a = project_vertex(P, gld(m.verts + ix.x), s);
+        b = project_vertex(P, gld(m.verts + ix.y), s);
+        c = project_vertex(P, gld(m.verts + ix.z), s);
+    }
     if (!(a.ok & b.ok & c.ok)) return;
     const long long area = edge_fn(a.U, a.V, b.U, b.V, c.U, c.V);
     if (area <= 0) return;

@@ -409,22 +409,31 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
 
     const int band0 = (!nnm && !G && !KG && BLOCK == 1024 && tpx + jpx > w.cap_large) ? (w.cap_large - tpx) : jpx;
     for (int k = tid; k < tpx; k += BLOCK) tst<G>(tile + k, kEmptyKey);
-    if (nnm) {
-        for (int k = tid; k < (jpx + 31) >> 5; k += BLOCK) Marks<KG>::clear(bits + k);
-    } else {
-        for (int k = tid; k < min(jpx, band0); k += BLOCK) K::store(keys + k, K::kEmpty);
-    }
     if (tid < 4) cnt[tid] = 0;
+    // 0. with LDS to spare beyond the tile (the J_o keys are cleared only
+    //    after the raster), every vertex is projected once for the pose
+    const int tile_q = (tpx + 3) & ~3;
+    const int4 *vcache = nullptr;
+    if (!G && tpx > 0 && 4 * m.nv <= (BLOCK == 1024 ? w.cap_large : w.cap_small) - tile_q) {
+        int4 *vc = reinterpret_cast<int4 *>(tile + tile_q);
+        for (int v = tid; v < m.nv; v += BLOCK) vc[v] = pack_vtx(project_vertex(P, gld(m.verts + v), s));
+        vcache = vc;
+    }
     __syncthreads();
 
     // 1. raster
     if (tpx > 0) {
         for (int t0 = 0; t0 < m.nt; t0 += BLOCK) {
             const int t = t0 + tid;
-            if (t < m.nt) raster_triangle<G>(s, m, P, t, in.tx0, in.ty0, in.tw, in.th, tile);
+            if (t < m.nt) raster_triangle<G>(s, m, P, t, in.tx0, in.ty0, in.tw, in.th, tile, vcache);
         }
     }
     __syncthreads();
+    if (nnm) {
+        for (int k = tid; k < (jpx + 31) >> 5; k += BLOCK) Marks<KG>::clear(bits + k);
+    } else {
+        for (int k = tid; k < min(jpx, band0); k += BLOCK) K::store(keys + k, K::kEmpty);
+    }
 
     // 2. resolve: occluders (Eq. 3) and the downsampling stride
     int cL = 0;
@@ -548,6 +557,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
         const int ra = first ? in.vy0 : by0;
         const int rb = b == nb - 1 ? in.vy0 + in.vh : by0 + bh;
         const int rpx = max(rb - ra, 0) * in.vw;
+        const float vinv = 1.0f / (float)max(in.vw, 1);
         for (int k0 = 0; k0 < rpx; k0 += BLOCK) {
             const int k = k0 + tid;
             if (ocol) {
@@ -556,7 +566,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             }
             bool inq = false, out = false;
             if (k < rpx) {
-                const int vy = k / in.vw, vx = k - vy * in.vw;
+                const int vy = window_row(k, in.vw, vinv), vx = k - vy * in.vw;
                 const int i = in.vx0 + vx, j = ra + vy;
                 const int pix = j * s.W + i;
                 const int4 q = gld(s.opt + pix);

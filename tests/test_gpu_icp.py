@@ -1,5 +1,5 @@
 """GPU parity of the ICP refinement (Sec. IV-A "Parallel M2M GICP"; the
-point-to-point ICP of Sec. V-A) against the oracle.
+point-to-point ICP of Sec. VI-A) against the oracle.
 
 Both sides map the source points in binary64, round them to 1/16 mm, match
 in exact integers, sum exactly in int64 and update with the same sequence of

@@ -1,5 +1,5 @@
 """GPU parity of the paper-faithful variants against the oracle: the
-inscribed-cylinder volume V(O) (Sec. III-A's conservative volume), J_o by
+inscribed-cylinder volume V(O) (Table I's conservative volume), J_o by
 nearest-neighbour marking and the kNN II search (Sec. IV-A, parallel cost
 computation).
 

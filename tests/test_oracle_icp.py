@@ -1,5 +1,5 @@
 """Pins for the oracle's ICP refinement (CPU only; Sec. IV-A "Parallel M2M
-GICP" and the point-to-point ICP of the 3-DoF experiments, Sec. V-A).
+GICP" and the point-to-point ICP of the 3-DoF experiments, Sec. VI-A).
 
 The update loop on fixed correspondences reaches the least-squares rigid
 alignment that scipy's Rotation.align_vectors computes (6-DoF), and the

@@ -1,5 +1,5 @@
 """Pins for the oracle's paper-faithful variants (CPU only): the inscribed-
-cylinder volume V(O) (Sec. III-A's conservative volume) and nearest-
+cylinder volume V(O) (Table I's conservative volume) and nearest-
 neighbour marking of J_o (the paper's J_o kernel, Sec. IV-A "Parallel Cost
 Computation").
 
