@@ -112,8 +112,19 @@ __device__ float ciede2000(float4 x, float4 y)
     else if (fabsf(h1p - h2p) <= 180.0f) hmp = (h1p + h2p) * 0.5f;
     else if (h1p + h2p < 360.0f) hmp = (h1p + h2p + 360.0f) * 0.5f;
     else hmp = (h1p + h2p - 360.0f) * 0.5f;
-    const float T = 1.0f - 0.17f * cosf((hmp - 30.0f) * D2R) + 0.24f * cosf(2.0f * hmp * D2R)
-                    + 0.32f * cosf((3.0f * hmp + 6.0f) * D2R) - 0.20f * cosf((4.0f * hmp - 63.0f) * D2R);
+    // T from one sine and cosine of the mean hue: the multiple angles by
+    // the double- and triple-angle formulas, the offsets (30, 6 and 63
+    // degrees) by angle addition with constant sines and cosines
+    float s1, c1;
+    sincosf(hmp * D2R, &s1, &c1);
+    const float c2 = c1 * c1 - s1 * s1, s2 = 2.0f * s1 * c1;
+    const float c3 = c1 * (c2 - 2.0f * s1 * s1), s3 = s1 * (2.0f * c1 * c1 + c2);
+    const float c4 = c2 * c2 - s2 * s2, s4 = 2.0f * s2 * c2;
+    const float C30 = 0.8660254037844386f, S30 = 0.5f;
+    const float C6 = 0.9945218953682733f, S6 = 0.10452846326765347f;
+    const float C63 = 0.45399049973954675f, S63 = 0.8910065241883679f;
+    const float T = 1.0f - 0.17f * (c1 * C30 + s1 * S30) + 0.24f * c2 + 0.32f * (c3 * C6 - s3 * S6)
+                    - 0.20f * (c4 * C63 + s4 * S63);
     const float hq = (hmp - 275.0f) / 25.0f;
     const float dth = 30.0f * expf(-(hq * hq));
     const float Cmp2 = Cmp * Cmp;
