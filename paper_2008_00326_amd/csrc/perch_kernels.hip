@@ -562,19 +562,21 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
 
         // 4. J_o: observed points in V(O); explained iff some rendered point
         //    keyed it.  In RGB mode the key names the nearest rendered point
-        //    and the explained points of each chunk are queued for a dense
-        //    colour test.  V rows above the J_o region go with the first band,
-        //    rows below it with the last.
+        //    and the explained points are queued for a dense colour test,
+        //    run whenever a work-group's worth has gathered (the queue holds
+        //    two: `queue`/`queue2`, then the marking arrays `mx`/`my`, idle
+        //    now) and at the band's end.  V rows above the J_o region go with
+        //    the first band, rows below it with the last.
         const int ra = first ? in.vy0 : by0;
         const int rb = b == nb - 1 ? in.vy0 + in.vh : by0 + bh;
         const int rpx = max(rb - ra, 0) * in.vw;
         const float vinv = 1.0f / (float)max(in.vw, 1);
+        if (ocol) {
+            if (tid == 0) *qn = 0;
+            __syncthreads();
+        }
         for (int k0 = 0; k0 < rpx; k0 += BLOCK) {
             const int k = k0 + tid;
-            if (ocol) {
-                if (tid == 0) *qn = 0;
-                __syncthreads();
-            }
             bool inq = false, out = false;
             if (k < rpx) {
                 const int vy = window_row(k, in.vw, vinv), vx = k - vy * in.vw;
@@ -597,9 +599,14 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     }
                     out = inq && !expl;
                     if (ocol && inq && expl) {
-                        const int slot = atomicAdd(qn, 1);
-                        queue[slot] = pix;
-                        queue2[slot] = K::index(nk);
+                        const int slot = atomicAdd(qn, 1);       // < 2 BLOCK: flushed below at BLOCK
+                        if (slot < BLOCK) {
+                            queue[slot] = pix;
+                            queue2[slot] = K::index(nk);
+                        } else {
+                            mx[slot - BLOCK] = pix;
+                            my[slot - BLOCK] = K::index(nk);
+                        }
                     }
                 }
             }
@@ -607,22 +614,33 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             cO += wave_popc(out);
             if (ocol) {
                 __syncthreads();
-                const int nq = *qn;
-                bool cout = false;
-                if (tid < nq) {
-                    const int pix = queue[tid], kr = queue2[tid];
-                    float4 lr;
-                    if (labs) {
-                        lr = gld(labs + kr);       // every keying point is an inlier of the first band
-                    } else {
-                        const uint32_t key = tld<G>(tile + kr);
-                        const int ty = kr / in.tw, tx = kr - ty * in.tw;
-                        lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                int n = *qn;
+                // flush a full work-group's worth; at the band's end, everything
+                while (n >= BLOCK || (n > 0 && k0 + BLOCK >= rpx)) {
+                    const int nt = min(n, BLOCK);
+                    bool cout = false;
+                    if (tid < nt) {
+                        const int pix = queue[tid], kr = queue2[tid];
+                        float4 lr;
+                        if (labs) {
+                            lr = gld(labs + kr);       // every keying point is an inlier of the first band
+                        } else {
+                            const uint32_t key = tld<G>(tile + kr);
+                            const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                            lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                        }
+                        cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
                     }
-                    cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
+                    cO += wave_popc(cout);
+                    __syncthreads();
+                    if (tid < n - nt) {                // the overflow moves to the front
+                        queue[tid] = mx[tid];
+                        queue2[tid] = my[tid];
+                    }
+                    if (tid == 0) *qn = n - nt;
+                    n -= nt;
+                    __syncthreads();
                 }
-                cO += wave_popc(cout);
-                __syncthreads();
             }
         }
     }
