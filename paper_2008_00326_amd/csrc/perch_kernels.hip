@@ -143,13 +143,17 @@ __device__ float ciede2000(float4 x, float4 y)
 
 // Largest pixel offset along one axis between a point on the ray of pixel
 // column (row) i at depth z mm and any point within dl = delta + 1/4 mm of
-// it: f dl sqrt(1 + ((i - c) / f)^2) / (z - dl) = a[i] / (z - dl), plus one
-// pixel of slack; `inv` = 1 / (z - dl).
+// it: f dl sqrt(1 + ((i - c) / f)^2) / (z - dl) = a[i] / (z - dl), with
+// `inv` = 1 / (z - dl).  Every point here is the back-projection of a pixel
+// centre at an integer depth, rounded to 1/16 mm: two points within delta in
+// those units lie within delta + 0.12 mm before rounding, and their pixel
+// offset, an integer, is at most the bound's floor.  a[i] is rounded up; the
+// factor covers the binary32 rounding of the quotient (a few ulps).
 __device__ __forceinline__ int window_half(float a, float inv, int limit)
 {
-    const float bnd = a * inv;
+    const float bnd = a * inv * 1.000002f;
     if (!(bnd < (float)limit)) return limit;
-    return (int)bnd + 1;
+    return (int)bnd;
 }
 
 // 1 / (z - dl) for window_half, or infinity when z is too close to the
