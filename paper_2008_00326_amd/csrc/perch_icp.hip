@@ -185,6 +185,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const SceneDev &s = a.s;
     const MeshDev &m = a.m;
+    extern __shared__ uint32_t icp_lds[];
     __shared__ int s_pose, s_n, s_box[4], s_changed, s_stop;
     __shared__ long long s_red[NW][kIcpSums];
     __shared__ double s_A[9], s_b[3];
@@ -207,6 +208,25 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             project_box(P, m.lo, m.hi, 0.0, s, &umin, &umax, &vmin, &vmax, &zmin, &zmax);
             if (zmin >= 100.0) {
                 clip_box(umin, umax, vmin, vmax, s.W, s.H, &x0, &y0, &w, &h);
+                // Nothing in reach: every rendered point lies on a pixel of the
+                // tile at depth >= zmin - 1/2 (depths are rounded to whole mm),
+                // and a match lies within rho + 1/4 mm of it (points are rounded
+                // to 1/16 mm), so its pixel is within
+                // f (rho + 1/4) sqrt(1 + t^2) / (zmin - 1/2 - rho - 1/4) of the
+                // tile (t the tile's largest ray slope), plus one.  When that
+                // grown tile misses the target box, no point can match: the
+                // pose comes back unchanged, as the iteration would return it.
+                const double rp = (double)a.rq / 16.0 + 0.25;
+                const double zn = zmin - 0.5;
+                if (w > 0 && zn - rp > 1.0) {
+                    const double tx = fmax(fabs((double)x0 - (double)s.cx), fabs((double)(x0 + w - 1) - (double)s.cx)) / (double)s.fx;
+                    const double ty = fmax(fabs((double)y0 - (double)s.cy), fabs((double)(y0 + h - 1) - (double)s.cy)) / (double)s.fy;
+                    const double du = (double)s.fx * rp * sqrt(1.0 + tx * tx) / (zn - rp) + 1.0;
+                    const double dv = (double)s.fy * rp * sqrt(1.0 + ty * ty) / (zn - rp) + 1.0;
+                    if ((double)(x0 + w - 1) + du < (double)a.box[0] || (double)x0 - du > (double)a.box[2]
+                        || (double)(y0 + h - 1) + dv < (double)a.box[1] || (double)y0 - dv > (double)a.box[3])
+                        w = h = 0;
+                }
             } else if (!(zmax < 99.999)) {
                 w = s.W;
                 h = s.H;
@@ -222,14 +242,31 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
         __syncthreads();
         const int tx0 = s_box[0], ty0 = s_box[1], tw = s_box[2], th = s_box[3];
         const int tpx = tw * th;
-        for (int k = tid; k < tpx; k += BLOCK) tst<true>(tile + k, kEmptyKey);
+        // the tile in LDS when it fits (then, with room to spare, every
+        // vertex projected once for the pose), else in device memory
+        const bool in_lds = tpx <= a.lds_words;
+        const int tile_q = (tpx + 3) & ~3;
+        const int4 *vcache = nullptr;
+        if (in_lds) {
+            for (int k = tid; k < tpx; k += BLOCK) icp_lds[k] = kEmptyKey;
+            if (tpx > 0 && 4 * m.nv <= a.lds_words - tile_q) {
+                int4 *vc = reinterpret_cast<int4 *>(icp_lds + tile_q);
+                for (int v = tid; v < m.nv; v += BLOCK) vc[v] = pack_vtx(project_vertex(P, gld(m.verts + v), s));
+                vcache = vc;
+            }
+        } else {
+            for (int k = tid; k < tpx; k += BLOCK) tst<true>(tile + k, kEmptyKey);
+        }
         __syncthreads();
         if (tpx > 0)
             for (int t0 = 0; t0 < m.nt; t0 += BLOCK)
-                if (t0 + tid < m.nt) raster_triangle<true>(s, m, P, t0 + tid, tx0, ty0, tw, th, tile);
+                if (t0 + tid < m.nt) {
+                    if (in_lds) raster_triangle<false>(s, m, P, t0 + tid, tx0, ty0, tw, th, icp_lds, vcache);
+                    else raster_triangle<true>(s, m, P, t0 + tid, tx0, ty0, tw, th, tile);
+                }
         __syncthreads();
         for (int k = tid; k < tpx; k += BLOCK) {
-            const uint32_t key = tld<true>(tile + k);
+            const uint32_t key = in_lds ? icp_lds[k] : tld<true>(tile + k);
             if (key == kEmptyKey) continue;
             const int ty = k / tw, tx = k - ty * tw;
             const int i = tx0 + tx, j = ty0 + ty, d = (int)(key >> 16);
@@ -378,8 +415,20 @@ hipError_t launch_proposals(const ProposalArgs &a, hipStream_t st)
 hipError_t launch_icp(const IcpArgs &a, int grid, hipStream_t st)
 {
     icp_zero_kernel<<<1, 1, 0, st>>>(a.cursor);
-    icp_kernel<1024><<<grid, 1024, 0, st>>>(a);
+    icp_kernel<1024><<<grid, 1024, (size_t)a.lds_words * 4, st>>>(a);
     return hipGetLastError();
+}
+
+hipError_t prepare_icp_kernel(int lds_per_group, int *lds_words)
+{
+    const void *f = (const void *)icp_kernel<1024>;
+    hipFuncAttributes at{};
+    hipError_t e = hipFuncGetAttributes(&at, f);
+    if (e != hipSuccess) return e;
+    const int dyn = lds_per_group - (int)at.sharedSizeBytes;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    *lds_words = e == hipSuccess ? dyn / 4 : 0;
+    return e;
 }
 
 }  // namespace perch

@@ -145,12 +145,16 @@ struct IcpArgs {
                              // the label's pixels; x1 < x0 when there are none)
     float *refined;          // n * 12
     int32_t *iters, *matched; // or null
-    uint32_t *tiles;         // per work-group: W*H tile words
+    int lds_words;           // dynamic LDS per work-group: the tile when it fits, then projected vertices
+    uint32_t *tiles;         // per work-group: W*H tile words (tiles larger than the LDS)
     int4 *pts;               // per work-group: pts_cap source points, then pts_cap mapped points
     size_t pts_cap;
     int *cursor;             // pose cursor, zeroed by the launch
 };
 hipError_t launch_icp(const IcpArgs &a, int grid, hipStream_t st);
+// Allow the ICP kernel all the LDS a work-group can hold beside its static
+// LDS (once per device); *lds_words receives that dynamic capacity.
+hipError_t prepare_icp_kernel(int lds_per_group, int *lds_words);
 
 // 6-DoF pose proposals of one object: viewpoint x in-plane angle x depth.
 struct ProposalArgs {

@@ -138,6 +138,7 @@ struct perch_ctx {
     std::recursive_mutex mu;
     perch_tuning tune{};                  // zeros: defaults
     int static_lds[3] = {0, 0, 0};        // static LDS bytes of the 256-, 512- and 1024-thread scoring kernels
+    int icp_lds_words = 0;                // dynamic LDS words of the ICP kernel
 
     // released device blocks awaiting reuse, and recycled use-tracking events
     std::vector<CachedBlock> cache;
@@ -680,6 +681,7 @@ perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
     colour_table(lin);
     e = upload_colour_table(lin);
     if (e == hipSuccess) e = prepare_score_kernels((int)ctx->lds_max, ctx->static_lds);
+    if (e == hipSuccess) e = prepare_icp_kernel((int)ctx->lds_max, &ctx->icp_lds_words);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete ctx;
@@ -1154,6 +1156,7 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
         a.box[2] = lb[0] + lb[2] - 1;
         a.box[3] = lb[1] + lb[3] - 1;
     }
+    a.lds_words = ctx->icp_lds_words;
     a.refined = refined_dev;
     a.iters = iters_dev;
     a.matched = matched_dev;
