@@ -77,6 +77,10 @@ def _load():
         lib.oracle_icp.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32]
         lib.oracle_icp_pairs.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P]
+        lib.oracle_gicp.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32]
+        lib.oracle_gicp_pairs.argtypes = [P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P]
+        lib.oracle_normal_image.argtypes = [P, P, ctypes.c_int32, P]
         lib.oracle_best.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -338,3 +342,58 @@ def propose(scene, mesh, label, *, viewpoints, inplane, z_step_mm, max_depths):
                                for r in range(3)])
                 out[i, k, t] = np.concatenate([R, tr[:, None]], axis=1).reshape(12)
     return out.reshape(-1, 12).astype(np.float32)
+
+
+def gicp(mesh, scene, poses, *, delta_mm, flags=MARK_OCCLUDERS, label=0, rho_mm=20.0, iterations=10, stride=2,
+         min_points=16, threads=0):
+    """Plane-to-plane GICP refinement (readings G1-G6 of the oracle source;
+    Sec. IV-A "Parallel M2M GICP"), 6-DoF.  Returns as `icp`."""
+    lib = _load()
+    m = _MeshArgs(mesh)
+    s = _SceneArgs(scene, delta_mm, 0.0, flags & ~USE_RGB, 1)
+    poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
+    n = poses.shape[0]
+    out = np.zeros((n, 12), np.float32)
+    it = np.zeros(n, np.int32)
+    mt = np.zeros(n, np.int32)
+    rc = lib.oracle_gicp(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(poses), n, float(rho_mm),
+                         int(iterations), int(stride), int(min_points), _ptr(out), _ptr(it), _ptr(mt), int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_gicp failed ({rc})")
+    return out, it, mt
+
+
+def gicp_pairs(src, dst, src_normals=None, dst_normals=None, *, iterations=1):
+    """GICP updates on fixed correspondences (dst[i] matches src[i], int32
+    1/16 mm) with unit normals per point (rows of NaN or None: no normal).
+    Returns (A 3x3, b 3)."""
+    lib = _load()
+    src = np.ascontiguousarray(src, dtype=np.int32).reshape(-1, 3)
+    dst = np.ascontiguousarray(dst, dtype=np.int32).reshape(-1, 3)
+    n = src.shape[0]
+
+    def norms(x):
+        if x is None:
+            return np.zeros((n, 3)), np.zeros(n, np.uint8)
+        x = np.asarray(x, np.float64).reshape(n, 3)
+        has = np.isfinite(x).all(1)
+        return np.ascontiguousarray(np.where(has[:, None], x, 0.0)), has.astype(np.uint8)
+    sn, sh = norms(src_normals)
+    dn, dh = norms(dst_normals)
+    A = np.zeros(9, np.float64)
+    b = np.zeros(3, np.float64)
+    rc = lib.oracle_gicp_pairs(_ptr(src), _ptr(dst), _ptr(sn), _ptr(sh), _ptr(dn), _ptr(dh), n, int(iterations),
+                               _ptr(A), _ptr(b))
+    if rc != 0:
+        raise ValueError(f"oracle_gicp_pairs failed ({rc})")
+    return A.reshape(3, 3), b
+
+
+def normal_image(depth, K, gap_mm):
+    """G1 normals of a depth image: H x W x 3 unit vectors, NaN where none."""
+    lib = _load()
+    depth = np.ascontiguousarray(depth, dtype=np.uint16)
+    k = _intr(K)
+    out = np.zeros(depth.shape + (3,), np.float64)
+    lib.oracle_normal_image(_ptr(depth), ctypes.byref(k), int(gap_mm), _ptr(out))
+    return out

@@ -107,6 +107,31 @@
  * Products and sums are written left to right as above; no fused
  * multiply-add (as R1).
  *
+ * GICP (Sec. IV-A "Parallel M2M GICP": each point's surface as a Gaussian),
+ * 6-DoF, read as plane-to-plane GICP on image-structured clouds:
+ *   G1 Normal of the point at pixel (i, j) of a depth image (the render for
+ *      source points, the observed image for targets): with all four
+ *      neighbours (i +- 1, j), (i, j +- 1) inside the image, with a reading,
+ *      and within g = floor(rq / 16) mm of the pixel's depth, c = ex x ey
+ *      where ex, ey are the differences of the neighbours' 1/16 mm points
+ *      (R7) along the row and the column (exact integers; none when any
+ *      component of ex or ey exceeds 2^14 or c = 0); n = c / |c|.
+ *   G2 Covariance I - (1 - e) n n^T with e = 1/1024 (unit variance in the
+ *      surface, e across it); I without a normal.
+ *   G3 Matches as I2-I3 (mapped points rounded to 1/16 mm).
+ *   G4 Centre mu = rint(sum q / n) per axis (exact integer sums).  Per match:
+ *      q~ = q - mu, e = c - q, the source normal turned by the current
+ *      rotation A, S = C_a + C_b, M = adj(S) / det(S), K = -[q~]x, and the
+ *      Gauss-Newton terms of the increment (w, t) with q' = q + w x q~ + t:
+ *      H = [[K^T M K, K^T M], [M K, M]], g = [K^T M e; M e].  The 21 upper
+ *      entries of H and the 6 of g, each times 1024 and rounded, are summed
+ *      exactly in 64 bits.
+ *   G5 H w = g by Cholesky (pivots in order; a pivot <= 0 stops GICP), the
+ *      rotation the unit quaternion (1, w/2) / sqrt(1 + |w/2|^2), and
+ *      (A, b) <- (Rc A, Rc (b - mu) + mu + t).
+ *   G6 Stops as I7 (no mapped point moved, fewer than min_points matches,
+ *      K updates) and on a failed pivot; refined pose as I8.
+ *
  * Colour: sRGB8 is linearised with the IEC 61966-2-1 piecewise curve (256-
  * entry table computed in binary64), mapped to XYZ with the four-digit sRGB
  * matrix, and to CIELAB with the white point equal to the matrix row sums
@@ -930,6 +955,340 @@ static int or_icp_one(const oracle_mesh *m, const oracle_scene *sc, int32_t labe
 done:
     free(dren); free(src); free(qprev); free(qcur);
     return rc;
+}
+
+/* G1: the integer normal direction c of the point at pixel (i, j); 0 when
+ * there is none. */
+static int or_normal(const uint16_t *depth, const oracle_intrinsics *K, int32_t i, int32_t j, int32_t gap,
+                     int64_t c[3])
+{
+    const int W = K->width, H = K->height;
+    if (i < 1 || j < 1 || i > W - 2 || j > H - 2) return 0;
+    const int32_t d = depth[(size_t)j * W + i];
+    const int32_t nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    int32_t p[4][3];
+    for (int k = 0; k < 4; ++k) {
+        const int32_t dn = depth[(size_t)nb[k][1] * W + nb[k][0]];
+        if (d == 0 || dn == 0 || dn - d > gap || d - dn > gap) return 0;
+        oracle_backproject(K, nb[k][0], nb[k][1], dn, p[k]);
+    }
+    int64_t ex[3], ey[3];
+    for (int a = 0; a < 3; ++a) {
+        ex[a] = (int64_t)p[1][a] - p[0][a];
+        ey[a] = (int64_t)p[3][a] - p[2][a];
+        if (ex[a] > 16384 || ex[a] < -16384 || ey[a] > 16384 || ey[a] < -16384) return 0;
+    }
+    c[0] = ex[1] * ey[2] - ex[2] * ey[1];
+    c[1] = ex[2] * ey[0] - ex[0] * ey[2];
+    c[2] = ex[0] * ey[1] - ex[1] * ey[0];
+    return c[0] != 0 || c[1] != 0 || c[2] != 0;
+}
+
+static void or_unit(const int64_t c[3], double n[3])
+{
+    const double x = (double)c[0], y = (double)c[1], z = (double)c[2];
+    const double l = sqrt((x * x + y * y) + z * z);
+    n[0] = x / l;
+    n[1] = y / l;
+    n[2] = z / l;
+}
+
+/* G4: the 27 fixed-point terms of one match. */
+static void or_gicp_terms(const int64_t q[3], const int64_t c[3], const int64_t mu[3], int has_a, const double na[3],
+                          int has_b, const double nb[3], const double A[9], uint64_t acc[27])
+{
+    const double eps = 1.0 / 1024.0;
+    double ra[3] = {0.0, 0.0, 0.0};
+    if (has_a)
+        for (int r = 0; r < 3; ++r) ra[r] = (A[3 * r] * na[0] + A[3 * r + 1] * na[1]) + A[3 * r + 2] * na[2];
+    const double ka = has_a ? 1.0 - eps : 0.0, kb = has_b ? 1.0 - eps : 0.0;
+    double S[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            const double sa = (r == k ? 1.0 : 0.0) - ka * (ra[r] * ra[k]);
+            const double sb = (r == k ? 1.0 : 0.0) - kb * (nb[r] * nb[k]);
+            S[r][k] = sa + sb;
+        }
+    double adj[3][3];
+    adj[0][0] = S[1][1] * S[2][2] - S[1][2] * S[2][1];
+    adj[0][1] = S[0][2] * S[2][1] - S[0][1] * S[2][2];
+    adj[0][2] = S[0][1] * S[1][2] - S[0][2] * S[1][1];
+    adj[1][0] = S[1][2] * S[2][0] - S[1][0] * S[2][2];
+    adj[1][1] = S[0][0] * S[2][2] - S[0][2] * S[2][0];
+    adj[1][2] = S[0][2] * S[1][0] - S[0][0] * S[1][2];
+    adj[2][0] = S[1][0] * S[2][1] - S[1][1] * S[2][0];
+    adj[2][1] = S[0][1] * S[2][0] - S[0][0] * S[2][1];
+    adj[2][2] = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+    const double det = (S[0][0] * adj[0][0] + S[0][1] * adj[1][0]) + S[0][2] * adj[2][0];
+    double M[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) M[r][k] = adj[r][k] / det;
+    const double x = (double)(q[0] - mu[0]), y = (double)(q[1] - mu[1]), z = (double)(q[2] - mu[2]);
+    const double Kq[3][3] = {{0.0, z, -y}, {-z, 0.0, x}, {y, -x, 0.0}};
+    const double e[3] = {(double)(c[0] - q[0]), (double)(c[1] - q[1]), (double)(c[2] - q[2])};
+    double MK[3][3], Me[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) MK[r][k] = (M[r][0] * Kq[0][k] + M[r][1] * Kq[1][k]) + M[r][2] * Kq[2][k];
+        Me[r] = (M[r][0] * e[0] + M[r][1] * e[1]) + M[r][2] * e[2];
+    }
+    double Hf[6][6];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            Hf[r][k] = (Kq[0][r] * MK[0][k] + Kq[1][r] * MK[1][k]) + Kq[2][r] * MK[2][k];
+            Hf[r][3 + k] = MK[k][r];
+            Hf[3 + r][3 + k] = M[r][k];
+        }
+    double g[6];
+    for (int r = 0; r < 3; ++r) {
+        g[r] = (Kq[0][r] * Me[0] + Kq[1][r] * Me[1]) + Kq[2][r] * Me[2];
+        g[3 + r] = Me[r];
+    }
+    int t = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int k = r; k < 6; ++k) acc[t++] += (uint64_t)(int64_t)nearbyint(Hf[r][k] * 1024.0);
+    for (int r = 0; r < 6; ++r) acc[t++] += (uint64_t)(int64_t)nearbyint(g[r] * 1024.0);
+}
+
+/* G5: solve and update; 1 when a pivot fails (nothing changes). */
+static int or_gicp_update(const uint64_t acc[27], const int64_t mu[3], double A[9], double b[3])
+{
+    double Hm[6][6], g[6];
+    int t = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int k = r; k < 6; ++k) {
+            Hm[r][k] = (double)(int64_t)acc[t++] / 1024.0;
+            Hm[k][r] = Hm[r][k];
+        }
+    for (int r = 0; r < 6; ++r) g[r] = (double)(int64_t)acc[t++] / 1024.0;
+    double L[6][6] = {{0}};
+    for (int j = 0; j < 6; ++j) {
+        double sjj = Hm[j][j];
+        for (int k = 0; k < j; ++k) sjj = sjj - L[j][k] * L[j][k];
+        if (!(sjj > 0.0)) return 1;
+        L[j][j] = sqrt(sjj);
+        for (int i = j + 1; i < 6; ++i) {
+            double sij = Hm[i][j];
+            for (int k = 0; k < j; ++k) sij = sij - L[i][k] * L[j][k];
+            L[i][j] = sij / L[j][j];
+        }
+    }
+    double yv[6], xv[6];
+    for (int i = 0; i < 6; ++i) {
+        double v = g[i];
+        for (int k = 0; k < i; ++k) v = v - L[i][k] * yv[k];
+        yv[i] = v / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double v = yv[i];
+        for (int k = i + 1; k < 6; ++k) v = v - L[k][i] * xv[k];
+        xv[i] = v / L[i][i];
+    }
+    const double h[3] = {xv[0] / 2.0, xv[1] / 2.0, xv[2] / 2.0};
+    const double r = sqrt(1.0 + ((h[0] * h[0] + h[1] * h[1]) + h[2] * h[2]));
+    const double qw = 1.0 / r, qx = h[0] / r, qy = h[1] / r, qz = h[2] / r;
+    double R[3][3];
+    R[0][0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+    R[0][1] = 2.0 * (qx * qy - qz * qw);
+    R[0][2] = 2.0 * (qx * qz + qy * qw);
+    R[1][0] = 2.0 * (qx * qy + qz * qw);
+    R[1][1] = 1.0 - 2.0 * (qx * qx + qz * qz);
+    R[1][2] = 2.0 * (qy * qz - qx * qw);
+    R[2][0] = 2.0 * (qx * qz - qy * qw);
+    R[2][1] = 2.0 * (qy * qz + qx * qw);
+    R[2][2] = 1.0 - 2.0 * (qx * qx + qy * qy);
+    double An[9], bn[3];
+    const double m[3] = {(double)mu[0], (double)mu[1], (double)mu[2]};
+    const double e[3] = {b[0] - m[0], b[1] - m[1], b[2] - m[2]};
+    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c) An[3 * a + c] = (R[a][0] * A[c] + R[a][1] * A[3 + c]) + R[a][2] * A[6 + c];
+        bn[a] = (((R[a][0] * e[0] + R[a][1] * e[1]) + R[a][2] * e[2]) + m[a]) + xv[3 + a];
+    }
+    memcpy(A, An, sizeof(An));
+    memcpy(b, bn, sizeof(bn));
+    return 0;
+}
+
+/* GICP of one pose (G1-G6). */
+static int or_gicp_one(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
+                       const or_cloud *obs, const int64_t *obs_c, const uint8_t *obs_has, double rho,
+                       int32_t iterations, int32_t stride, int32_t min_points, float *out, int32_t *iters_out,
+                       int32_t *matched_out)
+{
+    const oracle_intrinsics *K = &sc->K;
+    const int W = K->width, H = K->height;
+    const size_t N = (size_t)W * H;
+    const int mark = (sc->flags & OR_MARK_OCCLUDERS) != 0;
+    const uint32_t vol = sc->flags & OR_VOL_MASK;
+    const int64_t dq = (int64_t)nearbyint(16.0 * (double)sc->delta_mm);
+    const int64_t rq = (int64_t)nearbyint(16.0 * rho);
+    const int64_t rq2 = rq * rq;
+    const int32_t gap = (int32_t)(rq / 16);
+    uint16_t *dren = (uint16_t *)malloc(N * sizeof(uint16_t));
+    int32_t *src = (int32_t *)malloc(3 * N * sizeof(int32_t));
+    double *srcn = (double *)malloc(3 * N * sizeof(double));
+    uint8_t *srch = (uint8_t *)malloc(N);
+    int64_t *qprev = (int64_t *)malloc(3 * N * sizeof(int64_t));
+    int64_t *qcur = (int64_t *)malloc(3 * N * sizeof(int64_t));
+    int32_t *match = (int32_t *)malloc(N * sizeof(int32_t));
+    int rc = 0;
+    if (!dren || !src || !srcn || !srch || !qprev || !qcur || !match) { rc = -2; goto done; }
+    if (oracle_render(m, pose, K, dren, NULL, NULL) != 0) { rc = -1; goto done; }
+
+    size_t ns = 0;
+    for (int32_t j = 0; j < H; ++j)
+        for (int32_t i = 0; i < W; ++i) {
+            size_t k = (size_t)j * W + i;
+            int32_t d = dren[k];
+            if (d == 0 || i % stride != 0 || j % stride != 0) continue;
+            int32_t dob = sc->depth[k];
+            if (mark && dob > 0 && 16 * (int64_t)dob + dq < 16 * (int64_t)d) {
+                int other = !(vol == OR_VOL_LABEL && sc->labels) || sc->labels[k] != label;
+                if (other) continue;
+            }
+            oracle_backproject(K, i, j, d, src + 3 * ns);
+            int64_t c[3];
+            srch[ns] = (uint8_t)or_normal(dren, K, i, j, gap, c);
+            if (srch[ns]) or_unit(c, srcn + 3 * ns);
+            ns++;
+        }
+
+    double A[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, b[3] = {0, 0, 0};
+    int32_t iters = 0, matched = 0;
+    for (int32_t k = 0; k < iterations; ++k) {
+        for (size_t p = 0; p < ns; ++p) or_icp_map(A, b, src + 3 * p, qcur + 3 * p);
+        if (k > 0 && memcmp(qcur, qprev, 3 * ns * sizeof(int64_t)) == 0) break;
+        int64_t n = 0, sq[3] = {0, 0, 0};
+        for (size_t p = 0; p < ns; ++p) {
+            const int64_t *q = qcur + 3 * p;
+            int64_t best_d2 = 0;
+            int32_t best = -1;
+            for (int32_t t = 0; t < obs->n; ++t) {
+                int64_t dx = (int64_t)obs->x[t] - q[0], dy = (int64_t)obs->y[t] - q[1], dz = (int64_t)obs->z[t] - q[2];
+                int64_t d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 <= rq2 && (best < 0 || d2 < best_d2)) { best_d2 = d2; best = t; }
+            }
+            match[p] = best;
+            if (best >= 0) {
+                n++;
+                for (int a = 0; a < 3; ++a) sq[a] += q[a];
+            }
+        }
+        matched = (int32_t)n;
+        if (n < min_points) break;
+        int64_t mu[3];
+        for (int a = 0; a < 3; ++a) mu[a] = (int64_t)nearbyint((double)sq[a] / (double)n);
+        uint64_t acc[27];
+        memset(acc, 0, sizeof(acc));
+        for (size_t p = 0; p < ns; ++p) {
+            if (match[p] < 0) continue;
+            const int32_t t = match[p];
+            const int64_t c[3] = {obs->x[t], obs->y[t], obs->z[t]};
+            double nb[3] = {0.0, 0.0, 0.0};
+            if (obs_has[t]) or_unit(obs_c + 3 * (size_t)t, nb);
+            or_gicp_terms(qcur + 3 * p, c, mu, srch[p], srcn + 3 * p, obs_has[t], nb, A, acc);
+        }
+        if (or_gicp_update(acc, mu, A, b)) break;
+        iters = k + 1;
+        int64_t *tmp = qprev; qprev = qcur; qcur = tmp;
+    }
+    or_icp_pose(pose, A, b, out);
+    *iters_out = iters;
+    *matched_out = matched;
+done:
+    free(dren); free(src); free(srcn); free(srch); free(qprev); free(qcur); free(match);
+    return rc;
+}
+
+/* G1 normals of every pixel of a depth image: H*W*3 binary64 unit vectors,
+ * NaN where there is none. */
+int oracle_normal_image(const uint16_t *depth, const oracle_intrinsics *K, int32_t gap, double *out)
+{
+    for (int32_t j = 0; j < K->height; ++j)
+        for (int32_t i = 0; i < K->width; ++i) {
+            double *o = out + 3 * ((size_t)j * K->width + i);
+            int64_t c[3];
+            if (or_normal(depth, K, i, j, gap, c)) or_unit(c, o);
+            else o[0] = o[1] = o[2] = NAN;
+        }
+    return 0;
+}
+
+/* Plane-to-plane GICP refinement of n poses (G1-G6; 6-DoF).  Arguments as
+ * oracle_icp without dof. */
+int oracle_gicp(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses, int32_t n,
+                double rho, int32_t iterations, int32_t stride, int32_t min_points, float *refined, int32_t *iters,
+                int32_t *matched, int32_t n_threads)
+{
+    if (n < 0 || !or_scene_valid(m, sc) || m->n_tris > 65536) return -1;
+    if (!(rho > 0.0 && rho <= 100.0) || iterations < 1 || stride < 1 || min_points < 3) return -1;
+    or_cloud obs;
+    oracle_scene s2 = *sc;
+    s2.flags &= ~OR_USE_RGB;
+    if (or_observed_cloud(&s2, &obs)) return -2;
+    if ((sc->flags & OR_VOL_MASK) == OR_VOL_LABEL) {
+        int32_t k = 0;
+        for (int32_t t = 0; t < obs.n; ++t) {
+            if (sc->labels[obs.pix[t]] != label) continue;
+            obs.x[k] = obs.x[t]; obs.y[k] = obs.y[t]; obs.z[k] = obs.z[t]; obs.pix[k] = obs.pix[t];
+            k++;
+        }
+        obs.n = k;
+    }
+    const int32_t gap = (int32_t)((int64_t)nearbyint(16.0 * rho) / 16);
+    int64_t *obs_c = (int64_t *)malloc(3 * (size_t)(obs.n ? obs.n : 1) * sizeof(int64_t));
+    uint8_t *obs_has = (uint8_t *)malloc((size_t)(obs.n ? obs.n : 1));
+    if (!obs_c || !obs_has) { free(obs_c); free(obs_has); or_cloud_free(&obs); return -2; }
+    for (int32_t t = 0; t < obs.n; ++t) {
+        const int32_t W = sc->K.width;
+        obs_has[t] = (uint8_t)or_normal(sc->depth, &sc->K, obs.pix[t] % W, obs.pix[t] / W, gap, obs_c + 3 * (size_t)t);
+    }
+    int err = 0;
+#ifdef _OPENMP
+    int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : err)
+#endif
+    for (int32_t p = 0; p < n; ++p) {
+        if (or_gicp_one(m, sc, label, poses + 12 * (size_t)p, &obs, obs_c, obs_has, rho, iterations, stride,
+                        min_points, refined + 12 * (size_t)p, iters + p, matched + p))
+            err |= 1;
+    }
+    (void)n_threads;
+    free(obs_c);
+    free(obs_has);
+    or_cloud_free(&obs);
+    return err ? -2 : 0;
+}
+
+/* GICP updates on fixed correspondences with given normals (n x 3 binary64
+ * unit vectors; has_* flags 0 for none): dst[i] is the match of src[i]. */
+int oracle_gicp_pairs(const int32_t *src, const int32_t *dst, const double *src_n, const uint8_t *src_has,
+                      const double *dst_n, const uint8_t *dst_has, int32_t n, int32_t iterations, double *A, double *b)
+{
+    if (n < 3) return -1;
+    const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    memcpy(A, I, sizeof(I));
+    b[0] = b[1] = b[2] = 0.0;
+    for (int32_t k = 0; k < iterations; ++k) {
+        int64_t sq[3] = {0, 0, 0};
+        int64_t *qs = (int64_t *)malloc(3 * (size_t)n * sizeof(int64_t));
+        if (!qs) return -2;
+        for (int32_t p = 0; p < n; ++p) {
+            or_icp_map(A, b, src + 3 * (size_t)p, qs + 3 * (size_t)p);
+            for (int a = 0; a < 3; ++a) sq[a] += qs[3 * (size_t)p + a];
+        }
+        int64_t mu[3];
+        for (int a = 0; a < 3; ++a) mu[a] = (int64_t)nearbyint((double)sq[a] / (double)n);
+        uint64_t acc[27];
+        memset(acc, 0, sizeof(acc));
+        for (int32_t p = 0; p < n; ++p) {
+            const int64_t c[3] = {dst[3 * (size_t)p], dst[3 * (size_t)p + 1], dst[3 * (size_t)p + 2]};
+            or_gicp_terms(qs + 3 * (size_t)p, c, mu, src_has[p], src_n + 3 * (size_t)p, dst_has[p], dst_n + 3 * (size_t)p,
+                          A, acc);
+        }
+        free(qs);
+        if (or_gicp_update(acc, mu, A, b)) return 1;
+    }
+    return 0;
 }
 
 /* ICP refinement of n poses (readings I1-I8): refined poses (n x 12
