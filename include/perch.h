@@ -215,7 +215,16 @@ typedef struct {
     int32_t dof;          /* 3: rotation about the pose's object z axis and translation normal to it
                            *    (the 3-DoF table-top search); 6: any rigid motion */
     int32_t min_points;   /* stop when fewer points match, >= 3 */
+    int32_t method;       /* PERCH_ICP_POINT or PERCH_ICP_PLANE (GICP; needs dof 6) */
 } perch_icp_params;
+
+#define PERCH_ICP_POINT 0   /* point-to-point: the update aligns the matched pairs */
+#define PERCH_ICP_PLANE 1   /* plane-to-plane GICP (Sec. IV-A "Parallel M2M GICP"): each point's
+                             * surface a Gaussian, covariance I - (1 - 1/1024) n n^T with the normal n
+                             * from the cross product of its pixel neighbours' points (none at depth
+                             * steps over floor(rho) mm: covariance I); one Gauss-Newton step of the
+                             * rigid motion about the matches' rounded centre per iteration, its terms
+                             * summed exactly in 64-bit fixed point (times 1024), solved by Cholesky */
 
 /* ICP refinement of candidate poses (Sec. IV-A "Parallel M2M GICP"; the
  * point-to-point ICP of the 3-DoF experiments, Sec. VI-A), the step before

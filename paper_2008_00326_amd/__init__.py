@@ -62,7 +62,7 @@ class _Tuning(ctypes.Structure):
 
 class _IcpParams(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("max_corr_mm", ctypes.c_float), ("stride", ctypes.c_int32),
-                ("dof", ctypes.c_int32), ("min_points", ctypes.c_int32)]
+                ("dof", ctypes.c_int32), ("min_points", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class _ProposalParams(ctypes.Structure):
@@ -330,10 +330,11 @@ class Context:
         return out
 
     def refine_poses(self, scene_id, mesh_id, poses, *, label=0, rho_mm=20.0, iterations=10, stride=2, dof=3,
-                     min_points=16, out=None, stream=None):
+                     min_points=16, method="point", out=None, stream=None):
         """ICP refinement of a (n, 12) float32 CUDA tensor of poses against the
-        scene.  Returns (refined (n, 12) float32, updates applied int32,
-        matches of the last iteration int32) CUDA tensors.  Asynchronous."""
+        scene; method "point" (point-to-point) or "plane" (GICP, dof 6).
+        Returns (refined (n, 12) float32, updates applied int32, matches of
+        the last iteration int32) CUDA tensors.  Asynchronous."""
         import torch
         if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
             raise ValueError("poses must be a contiguous float32 CUDA tensor")
@@ -341,7 +342,10 @@ class Context:
         refined = out if out is not None else torch.empty((n, 12), dtype=torch.float32, device=poses.device)
         iters = torch.empty(n, dtype=torch.int32, device=poses.device)
         matched = torch.empty(n, dtype=torch.int32, device=poses.device)
-        prm = _IcpParams(int(iterations), float(rho_mm), int(stride), int(dof), int(min_points))
+        if method not in ("point", "plane"):
+            raise ValueError('method must be "point" or "plane"')
+        prm = _IcpParams(int(iterations), float(rho_mm), int(stride), int(dof), int(min_points),
+                         1 if method == "plane" else 0)
         if stream is None:
             stream = torch.cuda.current_stream(poses.device)
         _check(self._lib.perch_refine_poses(self._h, int(scene_id), int(mesh_id), int(label), _dev_ptr(poses), n,

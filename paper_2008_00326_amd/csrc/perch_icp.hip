@@ -13,6 +13,10 @@ namespace perch {
 // Per-iteration ICP sums over the matched pairs (q, c), one component per
 // lane: n, q (3), c (3), q q^T (9, row-major), q c^T (9, row-major).
 constexpr int kIcpSums = 25;
+// GICP: 21 upper entries of the 6x6 Gauss-Newton matrix, then 6 of its
+// right-hand side, in 64-bit fixed point (times 1024, rounded).
+constexpr int kGicpSums = 27;
+constexpr int kRedSums = 28;
 
 __device__ __forceinline__ long long icp_pick(int a, long long x, long long y, long long z)
 {
@@ -166,6 +170,179 @@ __device__ int icp_update(const long long *z, int dof, const double u[3], double
     return 0;
 }
 
+// ------------------------------------------------------------------ GICP
+
+// int4 arrays per work-group slot: source points, mapped points (with the
+// match), and for GICP the source normals.
+__host__ __device__ constexpr int gicp_slots(int method) { return method == 1 ? 3 : 2; }
+
+// Integer normal direction of the point at pixel (i, j) of a depth image
+// (depth(i', j') in mm, 0 = none): the cross product of the differences of
+// the 1/16 mm points of the row and column neighbours, when all four exist
+// inside the image, lie within `gap` mm of the pixel's depth and differ by
+// at most 2^14 units per axis; 0 when there is none.
+template <class Depth>
+__device__ int pixel_normal(const SceneDev &s, int i, int j, int gap, Depth depth, int c[3])
+{
+    if (i < 1 || j < 1 || i > s.W - 2 || j > s.H - 2) return 0;
+    const int d = depth(i, j);
+    const int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+    int p[4][3];
+    for (int k = 0; k < 4; ++k) {
+        const int dn = depth(ni[k], nj[k]);
+        if (d == 0 || dn == 0 || dn - d > gap || d - dn > gap) return 0;
+        p[k][0] = (int)rint(gld(s.kx + ni[k]) * (double)dn);
+        p[k][1] = (int)rint(gld(s.ky + nj[k]) * (double)dn);
+        p[k][2] = 16 * dn;
+    }
+    int ex[3], ey[3];
+    for (int a = 0; a < 3; ++a) {
+        ex[a] = p[1][a] - p[0][a];
+        ey[a] = p[3][a] - p[2][a];
+        if (ex[a] > 16384 || ex[a] < -16384 || ey[a] > 16384 || ey[a] < -16384) return 0;
+    }
+    c[0] = ex[1] * ey[2] - ex[2] * ey[1];
+    c[1] = ex[2] * ey[0] - ex[0] * ey[2];
+    c[2] = ex[0] * ey[1] - ex[1] * ey[0];
+    return c[0] != 0 || c[1] != 0 || c[2] != 0;
+}
+
+__device__ __forceinline__ void unit_of(const int c[3], double n[3])
+{
+    const double x = (double)c[0], y = (double)c[1], z = (double)c[2];
+    const double l = sqrt((x * x + y * y) + z * z);
+    n[0] = x / l;
+    n[1] = y / l;
+    n[2] = z / l;
+}
+
+// Term j (of kGicpSums) of one match q -> c: with the plane covariances
+// I - (1 - 1/1024) n n^T of the source normal turned by A and of the target
+// normal (I without one), M = (C_a + C_b)^-1 by the adjugate, K = -[q - mu]x
+// and e = c - q, the Gauss-Newton matrix [[K^T M K, K^T M], [M K, M]] (upper
+// entries row by row) and right-hand side [K^T M e; M e], times 1024, rounded.
+__device__ long long gicp_term(int j, int4 q, int4 c, const long long mu[3], int has_a, const double na[3],
+                               int has_b, const double nb[3], const double *A)
+{
+    const double eps = 1.0 / 1024.0;
+    double ra[3] = {0.0, 0.0, 0.0};
+    if (has_a)
+        for (int r = 0; r < 3; ++r) ra[r] = (A[3 * r] * na[0] + A[3 * r + 1] * na[1]) + A[3 * r + 2] * na[2];
+    const double ka = has_a ? 1.0 - eps : 0.0, kb = has_b ? 1.0 - eps : 0.0;
+    double S[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            const double sa = (r == k ? 1.0 : 0.0) - ka * (ra[r] * ra[k]);
+            const double sb = (r == k ? 1.0 : 0.0) - kb * (nb[r] * nb[k]);
+            S[r][k] = sa + sb;
+        }
+    double adj[3][3];
+    adj[0][0] = S[1][1] * S[2][2] - S[1][2] * S[2][1];
+    adj[0][1] = S[0][2] * S[2][1] - S[0][1] * S[2][2];
+    adj[0][2] = S[0][1] * S[1][2] - S[0][2] * S[1][1];
+    adj[1][0] = S[1][2] * S[2][0] - S[1][0] * S[2][2];
+    adj[1][1] = S[0][0] * S[2][2] - S[0][2] * S[2][0];
+    adj[1][2] = S[0][2] * S[1][0] - S[0][0] * S[1][2];
+    adj[2][0] = S[1][0] * S[2][1] - S[1][1] * S[2][0];
+    adj[2][1] = S[0][1] * S[2][0] - S[0][0] * S[2][1];
+    adj[2][2] = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+    const double det = (S[0][0] * adj[0][0] + S[0][1] * adj[1][0]) + S[0][2] * adj[2][0];
+    double M[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) M[r][k] = adj[r][k] / det;
+    const double x = (double)((long long)q.x - mu[0]), y = (double)((long long)q.y - mu[1]),
+                 z = (double)((long long)q.z - mu[2]);
+    const double Kq[3][3] = {{0.0, z, -y}, {-z, 0.0, x}, {y, -x, 0.0}};
+    const double e[3] = {(double)(c.x - q.x), (double)(c.y - q.y), (double)(c.z - q.z)};
+    double MK[3][3], Me[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) MK[r][k] = (M[r][0] * Kq[0][k] + M[r][1] * Kq[1][k]) + M[r][2] * Kq[2][k];
+        Me[r] = (M[r][0] * e[0] + M[r][1] * e[1]) + M[r][2] * e[2];
+    }
+    double v;
+    if (j < 21) {
+        // (r, k) of upper entry j, row by row
+        int r = 0, k = j;
+        while (k >= 6 - r) {
+            k -= 6 - r;
+            ++r;
+        }
+        k += r;
+        if (r < 3 && k < 3) v = (Kq[0][r] * MK[0][k] + Kq[1][r] * MK[1][k]) + Kq[2][r] * MK[2][k];
+        else if (r < 3) v = MK[k - 3][r];
+        else v = M[r - 3][k - 3];
+    } else if (j < 24) {
+        const int r = j - 21;
+        v = (Kq[0][r] * Me[0] + Kq[1][r] * Me[1]) + Kq[2][r] * Me[2];
+    } else {
+        v = Me[j - 24];
+    }
+    return (long long)rint(v * 1024.0);
+}
+
+// The GICP update from the fixed-point sums: H w = g by Cholesky (a pivot
+// <= 0 returns 1, nothing changes), the rotation the unit quaternion
+// (1, w/2) normalised, and (A, b) <- (Rc A, Rc (b - mu) + mu + t).
+__device__ int gicp_update(const long long *z, const long long mu[3], double *A, double *b)
+{
+    double Hm[6][6], g[6];
+    int t = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int k = r; k < 6; ++k) {
+            Hm[r][k] = (double)z[t++] / 1024.0;
+            Hm[k][r] = Hm[r][k];
+        }
+    for (int r = 0; r < 6; ++r) g[r] = (double)z[t++] / 1024.0;
+    double L[6][6];
+    for (int r = 0; r < 6; ++r)
+        for (int k = 0; k < 6; ++k) L[r][k] = 0.0;
+    for (int jj = 0; jj < 6; ++jj) {
+        double sjj = Hm[jj][jj];
+        for (int k = 0; k < jj; ++k) sjj = sjj - L[jj][k] * L[jj][k];
+        if (!(sjj > 0.0)) return 1;
+        L[jj][jj] = sqrt(sjj);
+        for (int i = jj + 1; i < 6; ++i) {
+            double sij = Hm[i][jj];
+            for (int k = 0; k < jj; ++k) sij = sij - L[i][k] * L[jj][k];
+            L[i][jj] = sij / L[jj][jj];
+        }
+    }
+    double yv[6], xv[6];
+    for (int i = 0; i < 6; ++i) {
+        double v = g[i];
+        for (int k = 0; k < i; ++k) v = v - L[i][k] * yv[k];
+        yv[i] = v / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double v = yv[i];
+        for (int k = i + 1; k < 6; ++k) v = v - L[k][i] * xv[k];
+        xv[i] = v / L[i][i];
+    }
+    const double h[3] = {xv[0] / 2.0, xv[1] / 2.0, xv[2] / 2.0};
+    const double r = sqrt(1.0 + ((h[0] * h[0] + h[1] * h[1]) + h[2] * h[2]));
+    const double qw = 1.0 / r, qx = h[0] / r, qy = h[1] / r, qz = h[2] / r;
+    double R[3][3];
+    R[0][0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+    R[0][1] = 2.0 * (qx * qy - qz * qw);
+    R[0][2] = 2.0 * (qx * qz + qy * qw);
+    R[1][0] = 2.0 * (qx * qy + qz * qw);
+    R[1][1] = 1.0 - 2.0 * (qx * qx + qz * qz);
+    R[1][2] = 2.0 * (qy * qz - qx * qw);
+    R[2][0] = 2.0 * (qx * qz - qy * qw);
+    R[2][1] = 2.0 * (qy * qz + qx * qw);
+    R[2][2] = 1.0 - 2.0 * (qx * qx + qy * qy);
+    double An[9], bn[3];
+    const double m[3] = {(double)mu[0], (double)mu[1], (double)mu[2]};
+    const double e[3] = {b[0] - m[0], b[1] - m[1], b[2] - m[2]};
+    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c) An[3 * a + c] = (R[a][0] * A[c] + R[a][1] * A[3 + c]) + R[a][2] * A[6 + c];
+        bn[a] = (((R[a][0] * e[0] + R[a][1] * e[1]) + R[a][2] * e[2]) + m[a]) + xv[3 + a];
+    }
+    for (int k = 0; k < 9; ++k) A[k] = An[k];
+    for (int k = 0; k < 3; ++k) b[k] = bn[k];
+    return 0;
+}
+
 __global__ void icp_zero_kernel(int *cursor)
 {
     if (threadIdx.x == 0) cursor[threadIdx.x] = 0;
@@ -187,11 +364,15 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
     const MeshDev &m = a.m;
     extern __shared__ uint32_t icp_lds[];
     __shared__ int s_pose, s_n, s_box[4], s_changed, s_stop;
-    __shared__ long long s_red[NW][kIcpSums];
+    __shared__ long long s_red[NW][kRedSums];
     __shared__ double s_A[9], s_b[3];
+    __shared__ long long s_mu[3];
     uint32_t *tile = a.tiles + (size_t)blockIdx.x * s.W * s.H;
-    int4 *src = a.pts + (size_t)blockIdx.x * 2 * a.pts_cap;
+    int4 *src = a.pts + (size_t)blockIdx.x * (gicp_slots(a.method)) * a.pts_cap;
     int4 *qb = src + a.pts_cap;
+    int4 *nrm = qb + a.pts_cap;            // GICP: integer source normals (x, y, z, has)
+    const bool gicp = a.method == 1;
+    const int gap = a.rq >> 4;
     const bool mark = (s.flags & 2u) != 0;
     const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
     for (;;) {
@@ -279,6 +460,18 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             }
             const int slot = atomicAdd(&s_n, 1);
             src[slot] = make_int4((int)rint(gld(s.kx + i) * (double)d), (int)rint(gld(s.ky + j) * (double)d), 16 * d, 0);
+            if (gicp) {
+                // the render's own neighbours (any rendered pixel, on or off the stride grid)
+                auto rdepth = [&](int ii, int jj) -> int {
+                    if (ii < tx0 || jj < ty0 || ii >= tx0 + tw || jj >= ty0 + th) return 0;
+                    const int kk = (jj - ty0) * tw + (ii - tx0);
+                    const uint32_t kv = in_lds ? icp_lds[kk] : tld<true>(tile + kk);
+                    return kv == kEmptyKey ? 0 : (int)(kv >> 16);
+                };
+                int c[3];
+                const int has = pixel_normal(s, i, j, gap, rdepth, c);
+                nrm[slot] = has ? make_int4(c[0], c[1], c[2], 1) : make_int4(0, 0, 0, 0);
+            }
         }
         __syncthreads();
         const int ns = s_n;
@@ -318,6 +511,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             for (int t = wave; t < ns; t += NW) {
                 const int4 q = qb[t];
                 const int nn = icp_nn(s, q, a.rq, a.rq2, label_mode ? s.labels : nullptr, a.label, a.box, lane);
+                if (gicp && lane == 0) qb[t].w = nn;     // the match, for the second pass
                 if (nn >= 0) {
                     const int4 c = gld(s.opt + nn);
                     if (lane < kIcpSums) acc += icp_term(lane, q, c);
@@ -335,12 +529,54 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
                 int stop = 0;
                 matched = (int)s_red[0][0];
                 if (s_red[0][0] < a.min_points) stop = 1;
-                else if (icp_update(s_red[0], a.dof, u, s_A, s_b)) stop = 1;
-                else iters = it + 1;
+                else if (gicp) {
+                    // the centre of the matched points, rounded: exact integer sums
+                    for (int c = 0; c < 3; ++c) s_mu[c] = (long long)rint((double)s_red[0][1 + c] / (double)s_red[0][0]);
+                } else if (icp_update(s_red[0], a.dof, u, s_A, s_b)) {
+                    stop = 1;
+                } else {
+                    iters = it + 1;
+                }
                 s_stop = stop;
             }
             __syncthreads();
             if (s_stop) break;
+            if (gicp) {
+                // second pass: the Gauss-Newton terms of every match, one
+                // wave per match, lane j summing term j
+                const long long mu[3] = {s_mu[0], s_mu[1], s_mu[2]};
+                long long gacc = 0;
+                for (int t = wave; t < ns; t += NW) {
+                    const int4 q = qb[t];
+                    if (q.w < 0) continue;
+                    const int4 c = gld(s.opt + q.w);
+                    const int4 cs = nrm[t];
+                    double na[3] = {0.0, 0.0, 0.0}, nb[3] = {0.0, 0.0, 0.0};
+                    const int csv[3] = {cs.x, cs.y, cs.z};
+                    if (cs.w) unit_of(csv, na);
+                    const int pi = q.w % s.W, pj = q.w / s.W;
+                    auto odepth = [&](int ii, int jj) -> int { return gld(s.depth + jj * s.W + ii); };
+                    int cb[3];
+                    const int has_b = pixel_normal(s, pi, pj, gap, odepth, cb);
+                    if (has_b) unit_of(cb, nb);
+                    if (lane < kGicpSums) gacc += gicp_term(lane, q, c, mu, cs.w, na, has_b, nb, s_A);
+                }
+                if (lane < kGicpSums) s_red[wave][lane] = gacc;
+                __syncthreads();
+                if (tid < kGicpSums) {
+                    long long z = 0;
+                    for (int v = 0; v < NW; ++v) z += s_red[v][tid];
+                    s_red[0][tid] = z;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    const int stop = gicp_update(s_red[0], mu, s_A, s_b);
+                    if (!stop) iters = it + 1;
+                    s_stop = stop;
+                }
+                __syncthreads();
+                if (s_stop) break;
+            }
         }
         if (tid == 0) {
             float *out = a.refined + 12 * (size_t)p;

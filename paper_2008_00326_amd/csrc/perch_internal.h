@@ -140,6 +140,7 @@ struct IcpArgs {
     const float *poses;      // n * 12
     int n, label;
     int iterations, stride, dof, min_points;
+    int method;              // 0 point-to-point, 1 plane-to-plane GICP (6-DoF)
     int rq, rq2;             // correspondence radius in 1/16 mm and its square
     int box[4];              // x0, y0, x1, y1 (inclusive) holding every target pixel (label volumes:
                              // the label's pixels; x1 < x0 when there are none)
@@ -147,7 +148,8 @@ struct IcpArgs {
     int32_t *iters, *matched; // or null
     int lds_words;           // dynamic LDS per work-group: the tile when it fits, then projected vertices
     uint32_t *tiles;         // per work-group: W*H tile words (tiles larger than the LDS)
-    int4 *pts;               // per work-group: pts_cap source points, then pts_cap mapped points
+    int4 *pts;               // per work-group: pts_cap source points, pts_cap mapped points (w: the match),
+                             // and for GICP pts_cap source normals
     size_t pts_cap;
     int *cursor;             // pose cursor, zeroed by the launch
 };

@@ -1117,6 +1117,9 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     if (prm->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
     if (prm->dof != 3 && prm->dof != 6) return fail(PERCH_EINVAL, "dof must be 3 or 6");
     if (prm->min_points < 3) return fail(PERCH_EINVAL, "min_points must be >= 3");
+    if (prm->method != PERCH_ICP_POINT && prm->method != PERCH_ICP_PLANE)
+        return fail(PERCH_EINVAL, "method must be PERCH_ICP_POINT or PERCH_ICP_PLANE");
+    if (prm->method == PERCH_ICP_PLANE && prm->dof != 6) return fail(PERCH_EINVAL, "GICP (PERCH_ICP_PLANE) is 6-DoF");
     if (n < 0) return fail(PERCH_EINVAL, "n must be >= 0");
     if (n > 0 && (!poses_dev || !refined_dev)) return fail(PERCH_EINVAL, "null poses or output");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -1131,7 +1134,8 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     const int grid = std::min(n, std::max(ctx->n_cu, 1));
     const size_t px = (size_t)s.W * s.H;
     const size_t tiles_off = 256, pts_off = tiles_off + (size_t)grid * px * 4;
-    const size_t bytes = pts_off + (size_t)grid * 2 * px * sizeof(int4);
+    const int slots = prm->method == PERCH_ICP_PLANE ? 3 : 2;   // source, mapped (+ normals for GICP)
+    const size_t bytes = pts_off + (size_t)grid * slots * px * sizeof(int4);
     if (perch_status e = ctx->ensure(b.icp, bytes)) return e;
     IcpArgs a{};
     a.s = s;
@@ -1143,6 +1147,7 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     a.stride = prm->stride;
     a.dof = prm->dof;
     a.min_points = prm->min_points;
+    a.method = prm->method;
     a.rq = (int)std::nearbyint(16.0 * (double)prm->max_corr_mm);
     a.rq2 = a.rq * a.rq;
     a.box[0] = 0;

@@ -155,3 +155,64 @@ def test_icp_edges(ctx):
         ctx.refine_poses(sid + 1000, mid, t)
     ctx.drop_scene(sid)
     ctx.unload_mesh(mid)
+
+
+# ------------------------------------------------------------------ GICP
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_case_gicp_matches_oracle(ctx, seed):
+    """Plane-to-plane GICP: refined poses, update and match counts equal the
+    oracle's (readings G1-G6: integer normals, exact fixed-point sums)."""
+    mesh, scene, poses, p = random_case(seed)
+    rng = np.random.default_rng(700 + seed)
+    prm = dict(rho_mm=float(rng.choice([8.0, 20.0, 40.0])), iterations=int(rng.choice([1, 5, 12])),
+               stride=int(rng.choice([1, 2])), min_points=8)
+    say(f"gicp case {seed}: image {scene.K[0]}x{scene.K[1]}, {mesh.tri.shape[0]} tris, {p}, {prm}")
+    sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, delta_mm=p["delta"], tau_c=p["tau"], use_rgb=p["rgb"],
+                        mark_occluders=p["occl"], stride=p["stride"])
+    mid = ctx.load_mesh(mesh.xyz, mesh.tri, mesh.rgb)
+    poses = poses[:16]
+    got = gpu_refine(ctx, sid, mid, poses, dof=6, method="plane", **prm)
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
+    exp = oracle.gicp(mesh, scene, poses, delta_mm=p["delta"], flags=oracle.MARK_OCCLUDERS if p["occl"] else 0,
+                      threads=THREADS, **prm)
+    check(got, exp, f"gicp case {seed}")
+
+
+@pytest.mark.parametrize("volume", ["aabb", "label"])
+def test_cfg2_sampled_gicp(ctx, volume):
+    w = make_config(2, 0)
+    s = w.scene
+    say(f"cfg2 gicp sample, {volume}")
+    lab = s.labels if volume == "label" else None
+    sid = ctx.set_scene(s.K, s.depth, s.rgb, lab, delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=True, volume=volume)
+    oflags = oracle.MARK_OCCLUDERS | (oracle.VOL_LABEL if volume == "label" else 0)
+    rng = np.random.default_rng(41)
+    for o in w.objects:
+        m = w.meshes[o.mesh]
+        mid = ctx.load_mesh(m.xyz, m.tri, m.rgb)
+        poses = np.concatenate([o.gt_pose[None], o.poses[rng.choice(o.poses.shape[0], 2, replace=False)]])
+        got = gpu_refine(ctx, sid, mid, poses, label=o.label, rho_mm=20.0, iterations=8, stride=2, dof=6,
+                         method="plane")
+        exp = oracle.gicp(m, TScene(s.K, s.depth, None, lab), poses, delta_mm=w.delta_mm, flags=oflags,
+                          label=o.label, rho_mm=20.0, iterations=8, stride=2, threads=THREADS)
+        check(got, exp, f"cfg2 gicp {volume} object {o.label}")
+        ctx.unload_mesh(mid)
+    ctx.drop_scene(sid)
+
+
+def test_gicp_needs_six_dof(ctx):
+    K = (96, 72, 110.0, 110.0, 48.0, 36.0)
+    cube = box((-20, -20, 0), (20, 20, 40), n=2, rgb_seed=1)
+    gt = pose_matrix(rot_x(2.4), (0, 0, 500))
+    d, _, c = oracle.render(cube, gt, K)
+    sid = ctx.set_scene(K, d, c, delta_mm=5.0)
+    mid = ctx.load_mesh(cube.xyz, cube.tri, cube.rgb)
+    t = torch.from_numpy(gt[None].astype(np.float32)).cuda()
+    with pytest.raises(pk.PerchError):
+        ctx.refine_poses(sid, mid, t, dof=3, method="plane")
+    with pytest.raises(ValueError):
+        ctx.refine_poses(sid, mid, t, method="surface")
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
