@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the ICP refine-and-rescore leg of a plain run")
     ap.add_argument("--pipeline6d", action="store_true",
                     help="add the 6-DoF leg: proposals, scoring, ICP of the best, rescoring (cfg3 scene)")
+    ap.add_argument("--icp-method", choices=("plane", "point", "both"), default="plane",
+                    help="refinement of the 6-DoF leg: plane-to-plane GICP (the paper's), point-to-point ICP, or both")
     ap.add_argument("--refine-steps", type=int, default=2, help="timed passes of the refine leg")
     ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,7 +269,9 @@ def main():
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
     if args.pipeline6d:
-        result["pipeline6d"] = pipeline6d_leg(ctx, args.seed)
+        methods = ("plane", "point") if args.icp_method == "both" else (args.icp_method,)
+        legs = {m: pipeline6d_leg(ctx, args.seed, method=m) for m in methods}
+        result["pipeline6d"] = legs[methods[0]] if len(methods) == 1 else legs
     if not args.no_batched:
         ctx.drop_scene(sid)
         ctx.set_tuning(None)
@@ -285,7 +289,8 @@ def refine_leg(ctx, w, mids, steps, cpu_sample):
     then every refined pose rendered and scored again, as the segmented
     pipeline of the paper does before selecting poses.  Returns poses/s of
     the refinement and of refinement plus rescoring, the costs before and
-    after, and the CPU oracle's refinement rate on a small sample."""
+    after, and the CPU oracle's refinement rate on a small sample.  The same
+    candidates are also refined by plane-to-plane GICP (6-DoF) and timed."""
     import torch
     s = w.scene
     _log("[bench] refine: ICP + rescore")
@@ -336,6 +341,23 @@ def refine_leg(ctx, w, mids, steps, cpu_sample):
            "mean_J_before": round(float(j0.mean()), 1), "mean_J_after": round(float(j1.mean()), 1),
            "fraction_J_lower": round(float(np.mean(j1 < j0)), 4),
            "best_J_before": [int(x) for x in bc_before], "best_J_after": [int(x) for x in bc_after]}
+    # the same candidates through plane-to-plane GICP (6-DoF, the paper's refinement of its 6-DoF pipeline)
+    gprm = dict(prm, dof=6, method="plane")
+    gstats = [ctx.refine_poses(sid, mid, p, label=lab, out=o, **gprm)[1:]
+              for mid, lab, p, o in zip(meshes, labels, polys, outs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gstats = [ctx.refine_poses(sid, mid, p, label=lab, out=o, **gprm)[1:]
+                  for mid, lab, p, o in zip(meshes, labels, polys, outs)]
+    torch.cuda.synchronize()
+    t_g = (time.perf_counter() - t0) / steps
+    jg = np.concatenate([sum(ctx.score_poses(sid, mid, o, label=lab)[:2]).cpu().numpy()
+                         for mid, lab, o in zip(meshes, labels, outs)])
+    out["gicp"] = {"icp": dict(gprm, min_points=16), "refine_poses_per_s": round(n / t_g, 1),
+                   "refine_ms": round(t_g * 1e3, 3),
+                   "mean_updates": round(float(np.concatenate([x[0].cpu().numpy() for x in gstats]).mean()), 2),
+                   "mean_J_after": round(float(jg.mean()), 1), "fraction_J_lower": round(float(np.mean(jg < j0)), 4)}
     if cpu_sample:
         import oracle
         rng = np.random.default_rng(7)
@@ -364,12 +386,13 @@ def _pose_errors(a, b):
     return float(np.linalg.norm(A[:, 3] - B[:, 3])), ang
 
 
-def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depths=12, top=128):
+def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depths=12, top=128, method="plane"):
     """The 6-DoF pipeline of the paper (Sec. V-C) on the cfg3 scene with its
     labels standing in for the segmentation: per object, rotation x
     translation proposals (Sec. V-B), every proposal rendered and scored with
-    label volumes, the `top` cheapest refined by 6-DoF ICP against the
-    object's labelled pixels, rendered and scored again, and the cheapest
+    label volumes, the `top` cheapest refined against the object's labelled
+    pixels (plane-to-plane GICP, or 6-DoF point-to-point ICP with method
+    "point"), rendered and scored again, and the cheapest
     kept.  Reports the time of each stage, poses/s over the whole pipeline
     and the final pose's distance to the generating pose (rotation error is
     only meaningful for shapes without symmetry), with the cost of the final
@@ -378,11 +401,11 @@ def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depth
     from paper_2008_00326_amd.workloads import make_config
     w = make_config(3, seed)
     s = w.scene
-    _log("[bench] 6-DoF pipeline: proposals, scoring, ICP, rescoring")
+    _log(f"[bench] 6-DoF pipeline: proposals, scoring, {'GICP' if method == 'plane' else 'ICP'}, rescoring")
     sid = ctx.set_scene(s.K, s.depth, s.rgb, s.labels, delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=True,
                         volume="label")
     mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in w.meshes]
-    icp = dict(rho_mm=20.0, iterations=15, stride=2, dof=6)
+    icp = dict(rho_mm=20.0, iterations=15, stride=2, dof=6, method=method)
 
     def run():
         t = {}
