@@ -81,6 +81,9 @@ def _load():
                                     ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32]
         lib.oracle_gicp_pairs.argtypes = [P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P]
         lib.oracle_normal_image.argtypes = [P, P, ctypes.c_int32, P]
+        lib.oracle_msg_expand.argtypes = [P, P, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32,
+                                          P, P, P, P, P, ctypes.c_int32]
+        lib.oracle_msg_expand.restype = ctypes.c_int
         lib.oracle_best.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -397,3 +400,60 @@ def normal_image(depth, K, gap_mm):
     out = np.zeros(depth.shape + (3,), np.float64)
     lib.oracle_normal_image(_ptr(depth), ctypes.byref(k), int(gap_mm), _ptr(out))
     return out
+
+
+def msg_expand(scene, state, mesh, poses, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1, label=0,
+               threads=0):
+    """Edges of the Monotone Scene Generation tree (readings M1-M3) from one
+    state to one object at each of its candidate poses.
+
+    state: a sequence of (mesh, label, pose) already placed, in order.
+    Returns five int32 arrays (valid, jr, jo, nr, nq); a successor that
+    would occlude a placed object has valid 0 and zero costs."""
+    lib = _load()
+    s = _SceneArgs(scene, delta_mm, tau_c, flags, stride)
+    m = _MeshArgs(mesh)
+    sm = [_MeshArgs(x[0]) for x in state]
+    arr = (ctypes.POINTER(_Mesh) * max(1, len(sm)))(*[ctypes.pointer(a.s) for a in sm])
+    sl = np.array([int(x[1]) for x in state] or [0], np.int32)
+    sp = np.ascontiguousarray(np.array([np.asarray(x[2], np.float32).reshape(12) for x in state]
+                                       or [np.zeros(12, np.float32)]), dtype=np.float32)
+    poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
+    n = poses.shape[0]
+    out = [np.zeros(n, np.int32) for _ in range(5)]
+    rc = lib.oracle_msg_expand(ctypes.byref(s.s), ctypes.cast(arr, ctypes.c_void_p), _ptr(sl), _ptr(sp),
+                               len(state), ctypes.byref(m.s), int(label), _ptr(poses), n,
+                               *[_ptr(a) for a in out], int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_msg_expand failed ({rc})")
+    return tuple(out)
+
+
+def msg_search(scene, objects, *, beam, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1, threads=0):
+    """Beam search over the Monotone Scene Generation tree (reading M4).
+
+    objects: a sequence of (mesh, label, poses (n_k x 12)).  beam: states kept
+    per level (0 = all, an exhaustive search).  Returns (cost, sequence) of
+    the goal of least (cost, sequence), the sequence a tuple of
+    (object, pose index) pairs in placement order, or None when no monotone
+    goal exists; also the number of successors scored."""
+    level = [(0, ())]
+    scored = 0
+    for _ in range(len(objects)):
+        cand = []
+        for cost, seq in level:
+            placed = {o for o, _ in seq}
+            state = [(objects[o][0], objects[o][1], objects[o][2][k]) for o, k in seq]
+            for o, (mesh, label, poses) in enumerate(objects):
+                if o in placed:
+                    continue
+                valid, jr, jo, _, _ = msg_expand(scene, state, mesh, poses, delta_mm=delta_mm, tau_c=tau_c,
+                                                 flags=flags, stride=stride, label=label, threads=threads)
+                scored += len(valid)
+                for k in np.flatnonzero(valid):
+                    cand.append((cost + int(jr[k]) + int(jo[k]), seq + ((o, int(k)),)))
+        cand.sort()
+        level = cand if beam <= 0 else cand[:beam]
+        if not level:
+            return None, scored
+    return level[0], scored

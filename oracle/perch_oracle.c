@@ -132,6 +132,35 @@
  *   G6 Stops as I7 (no mapped point moved, fewer than min_points matches,
  *      K updates) and on a failed pivot; refined pose as I8.
  *
+ * Monotone Scene Generation tree (the sequential search of the original
+ * PERCH that the variant 2.0-B keeps, Sec. III-B and its tree figure, Sec.
+ * VI-A), read as:
+ *   M1 A state is a sequence of placed objects (object, candidate pose), each
+ *      object at most once.  The root is empty; a successor appends one
+ *      object not yet placed, in one of its candidate poses; states with
+ *      every object placed are goals.
+ *   M2 A state's render is its objects' renders (R4) composed in order: a
+ *      pixel keeps the first object that draws it.  A successor is monotone
+ *      iff the new object occludes none already placed: no pixel that both
+ *      draw with the new depth strictly smaller.  Only monotone successors
+ *      enter the tree.
+ *   M3 The edge cost of appending object O at pose P to state S is J_r over
+ *      O's own points dR (its pixels that no object of S draws, on the
+ *      stride grid, less occluders by R6 with O's label) plus J_o over the
+ *      observed points inside V(O) (R10) and inside no volume of S's
+ *      objects, each tested against the points R \ C of the composed render
+ *      (every object's own points, R6 with each object's own label), as
+ *      Eq. 3 and Eq. 4 with R8-R9.  An edge from the root is the plain score.
+ *   M4 A state's cost is the sum of its edge costs; a goal's J_r part is the
+ *      J_r of the composed scene, since no pixel changes owner down a path.
+ *      The search keeps, level by level, the B states of least (cost,
+ *      sequence), sequences compared lexicographically as (object, pose
+ *      index) pairs, and expands each into all its monotone successors; it
+ *      returns the goal of least (cost, sequence).  When B is at least the
+ *      size of every level the search is exhaustive and returns the
+ *      least-cost goal of the whole tree.
+ *   M5 Nearest-neighbour marking of J_o (R12) is not combined with the tree.
+ *
  * Colour: sRGB8 is linearised with the IEC 61966-2-1 piecewise curve (256-
  * entry table computed in binary64), mapped to XYZ with the four-digit sRGB
  * matrix, and to CIELAB with the white point equal to the matrix row sums
@@ -554,6 +583,44 @@ static int or_search(const or_cloud *c, int64_t px, int64_t py, int64_t pz, int6
     return found;
 }
 
+/* The object-frame AABB of a mesh. */
+static void or_mesh_box(const oracle_mesh *m, double lo[3], double hi[3])
+{
+    for (int a = 0; a < 3; ++a) { lo[a] = (double)m->xyz[a]; hi[a] = (double)m->xyz[a]; }
+    for (int32_t v = 1; v < m->n_verts; ++v)
+        for (int a = 0; a < 3; ++a) {
+            double c = (double)m->xyz[3 * (size_t)v + a];
+            if (c < lo[a]) lo[a] = c;
+            if (c > hi[a]) hi[a] = c;
+        }
+}
+
+/* Is observed point p inside V(O) of the object at `pose` (box lo, hi):
+ * its label (label volumes), or the inscribed cylinder or the AABB grown by
+ * delta (R10). */
+static int or_in_volume(const oracle_scene *sc, int32_t label, const float *pose, const double lo[3],
+                        const double hi[3], const or_cloud *obs, int32_t p)
+{
+    const uint32_t vol = sc->flags & OR_VOL_MASK;
+    const double dl = (double)sc->delta_mm;
+    if (vol == OR_VOL_LABEL) return sc->labels && sc->labels[obs->pix[p]] == label;
+    double e0 = (double)obs->x[p] / 16.0 - (double)pose[3];
+    double e1 = (double)obs->y[p] / 16.0 - (double)pose[7];
+    double e2 = (double)obs->z[p] / 16.0 - (double)pose[11];
+    double q0 = ((double)pose[0] * e0 + (double)pose[4] * e1) + (double)pose[8] * e2;
+    double q1 = ((double)pose[1] * e0 + (double)pose[5] * e1) + (double)pose[9] * e2;
+    double q2 = ((double)pose[2] * e0 + (double)pose[6] * e1) + (double)pose[10] * e2;
+    if (vol == OR_VOL_CYL) {
+        double c0 = (lo[0] + hi[0]) / 2.0, c1 = (lo[1] + hi[1]) / 2.0;
+        double h0 = (hi[0] - lo[0]) / 2.0, h1 = (hi[1] - lo[1]) / 2.0;
+        double rho = (h0 < h1 ? h0 : h1) + dl;
+        double a = q0 - c0, b = q1 - c1;
+        return (a * a + b * b <= rho * rho) && (lo[2] - dl <= q2) && (q2 <= hi[2] + dl);
+    }
+    return (lo[0] - dl <= q0) && (q0 <= hi[0] + dl) && (lo[1] - dl <= q1) && (q1 <= hi[1] + dl)
+           && (lo[2] - dl <= q2) && (q2 <= hi[2] + dl);
+}
+
 /* Score one pose; optionally fill per-pixel detail images:
  *  r_flag[k]: 0 not in R, 1 inlier, 2 outlier (distance), 3 outlier (colour), 4 occluded
  *  o_flag[k]: 0 not in Vset, 1 explained, 2 outlier (distance), 3 outlier (colour) */
@@ -619,43 +686,12 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
 
     /* J_o: every observed point inside V(O) against the whole render. */
     double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) { lo[a] = (double)m->xyz[a]; hi[a] = (double)m->xyz[a]; }
-    for (int32_t v = 1; v < m->n_verts; ++v)
-        for (int a = 0; a < 3; ++a) {
-            double c = (double)m->xyz[3 * (size_t)v + a];
-            if (c < lo[a]) lo[a] = c;
-            if (c > hi[a]) hi[a] = c;
-        }
-    const double dl = (double)sc->delta_mm;
+    or_mesh_box(m, lo, hi);
     int32_t jo = 0, q = 0;
     for (int32_t p = 0; p < obs->n; ++p) {
         int32_t k = obs->pix[p];
         if (o_flag) o_flag[k] = 0;
-        int in;
-        if (vol == OR_VOL_LABEL) {
-            in = sc->labels && sc->labels[k] == label;
-        } else if (vol == OR_VOL_CYL) {
-            double e0 = (double)obs->x[p] / 16.0 - (double)pose[3];
-            double e1 = (double)obs->y[p] / 16.0 - (double)pose[7];
-            double e2 = (double)obs->z[p] / 16.0 - (double)pose[11];
-            double q0 = ((double)pose[0] * e0 + (double)pose[4] * e1) + (double)pose[8] * e2;
-            double q1 = ((double)pose[1] * e0 + (double)pose[5] * e1) + (double)pose[9] * e2;
-            double q2 = ((double)pose[2] * e0 + (double)pose[6] * e1) + (double)pose[10] * e2;
-            double c0 = (lo[0] + hi[0]) / 2.0, c1 = (lo[1] + hi[1]) / 2.0;
-            double h0 = (hi[0] - lo[0]) / 2.0, h1 = (hi[1] - lo[1]) / 2.0;
-            double rho = (h0 < h1 ? h0 : h1) + dl;
-            double a = q0 - c0, b = q1 - c1;
-            in = (a * a + b * b <= rho * rho) && (lo[2] - dl <= q2) && (q2 <= hi[2] + dl);
-        } else {
-            double e0 = (double)obs->x[p] / 16.0 - (double)pose[3];
-            double e1 = (double)obs->y[p] / 16.0 - (double)pose[7];
-            double e2 = (double)obs->z[p] / 16.0 - (double)pose[11];
-            double q0 = ((double)pose[0] * e0 + (double)pose[4] * e1) + (double)pose[8] * e2;
-            double q1 = ((double)pose[1] * e0 + (double)pose[5] * e1) + (double)pose[9] * e2;
-            double q2 = ((double)pose[2] * e0 + (double)pose[6] * e1) + (double)pose[10] * e2;
-            in = (lo[0] - dl <= q0) && (q0 <= hi[0] + dl) && (lo[1] - dl <= q1) && (q1 <= hi[1] + dl)
-                 && (lo[2] - dl <= q2) && (q2 <= hi[2] + dl);
-        }
+        int in = or_in_volume(sc, label, pose, lo, hi, obs, p);
         if (!in) continue;
         q++;
         int flag = 1;
@@ -1371,4 +1407,172 @@ int oracle_best(const int32_t *jr, const int32_t *jo, int32_t n, int32_t *best_i
     *best_cost = (int32_t)bc;
     if (n_ties) *n_ties = ties;
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Monotone Scene Generation tree (readings M1-M5)                     */
+/* ------------------------------------------------------------------ */
+
+/* M2: compose the renders of a state's objects in order.  depth and own
+ * (owner index, -1 none) are W*H, rgb W*H*3 or NULL.  Returns 1 when an
+ * object occludes an earlier one (the state is not monotone). */
+static int or_compose(const oracle_scene *sc, const oracle_mesh *const *meshes, const float *poses, int32_t n,
+                      uint16_t *depth, uint8_t *rgb, int32_t *own)
+{
+    const size_t N = (size_t)sc->K.width * sc->K.height;
+    uint16_t *d = (uint16_t *)malloc(N * sizeof(uint16_t));
+    uint8_t *c = rgb ? (uint8_t *)malloc(3 * N) : NULL;
+    if (!d || (rgb && !c)) { free(d); free(c); return -2; }
+    memset(depth, 0, N * sizeof(uint16_t));
+    if (rgb) memset(rgb, 0, 3 * N);
+    for (size_t k = 0; k < N; ++k) own[k] = -1;
+    int nonmono = 0, rc = 0;
+    for (int32_t o = 0; o < n && !rc; ++o) {
+        if (oracle_render(meshes[o], poses + 12 * (size_t)o, &sc->K, d, NULL, c) != 0) { rc = -1; break; }
+        for (size_t k = 0; k < N; ++k) {
+            if (d[k] == 0) continue;
+            if (depth[k] > 0) {
+                if (d[k] < depth[k]) nonmono = 1;
+                continue;
+            }
+            depth[k] = d[k];
+            own[k] = o;
+            if (rgb) memcpy(rgb + 3 * k, c + 3 * k, 3);
+        }
+    }
+    free(d); free(c);
+    return rc ? rc : nonmono;
+}
+
+/* Append pixel k at depth d to cloud R if it is a point of R \ C: on the
+ * stride grid and not an occluder (R6 with the owner's label). */
+static void or_add_point(const oracle_scene *sc, int32_t label, size_t k, int32_t d, const uint8_t *rgb, or_cloud *R)
+{
+    const int W = sc->K.width;
+    const int32_t i = (int32_t)(k % (size_t)W), j = (int32_t)(k / (size_t)W);
+    if (i % sc->stride != 0 || j % sc->stride != 0) return;
+    const int64_t dq = (int64_t)nearbyint(16.0 * (double)sc->delta_mm);
+    const int32_t dob = sc->depth[k];
+    if ((sc->flags & OR_MARK_OCCLUDERS) && dob > 0 && 16 * (int64_t)dob + dq < 16 * (int64_t)d) {
+        int other = !((sc->flags & OR_VOL_MASK) == OR_VOL_LABEL && sc->labels) || sc->labels[k] != label;
+        if (other) return;
+    }
+    int32_t p[3];
+    oracle_backproject(&sc->K, i, j, d, p);
+    R->x[R->n] = p[0]; R->y[R->n] = p[1]; R->z[R->n] = p[2]; R->pix[R->n] = (int32_t)k;
+    if (R->lab) oracle_srgb_to_lab32(rgb + 3 * k, R->lab + 3 * (size_t)R->n);
+    R->n++;
+}
+
+/* M3: the edges from one state (n_state objects: meshes, labels, poses)
+ * to object m (label) at each of n poses.  Per pose: valid (M2), jr, jo,
+ * nr (|dR \ C|) and nq (observed points charged to the edge); all zero for
+ * a successor that is not monotone.  Returns -1 on invalid arguments or a
+ * state that is not monotone itself. */
+int oracle_msg_expand(const oracle_scene *sc, const oracle_mesh *const *state_meshes, const int32_t *state_labels,
+                      const float *state_poses, int32_t n_state, const oracle_mesh *m, int32_t label,
+                      const float *poses, int32_t n, int32_t *valid, int32_t *jr, int32_t *jo, int32_t *nr,
+                      int32_t *nq, int32_t n_threads)
+{
+    if (n < 0 || n_state < 0 || !or_scene_valid(m, sc) || m->n_tris > 65536 || (sc->flags & OR_JO_NN)) return -1;
+    for (int32_t o = 0; o < n_state; ++o)
+        if (!or_scene_valid(state_meshes[o], sc) || state_meshes[o]->n_tris > 65536) return -1;
+    or_lin32_init();
+    const oracle_intrinsics *K = &sc->K;
+    const size_t N = (size_t)K->width * K->height;
+    const int use_rgb = (sc->flags & OR_USE_RGB) != 0;
+    const int64_t dq = (int64_t)nearbyint(16.0 * (double)sc->delta_mm);
+    const int64_t dq2 = dq * dq;
+    uint16_t *cd = (uint16_t *)malloc(N * sizeof(uint16_t));
+    uint8_t *cc = use_rgb ? (uint8_t *)malloc(3 * N) : NULL;
+    int32_t *own = (int32_t *)malloc(N * sizeof(int32_t));
+    uint8_t *covered = NULL;
+    or_cloud obs, Rs;
+    memset(&obs, 0, sizeof(obs));
+    memset(&Rs, 0, sizeof(Rs));
+    int rc = 0;
+    if (!cd || (use_rgb && !cc) || !own || or_observed_cloud(sc, &obs) || or_cloud_alloc(&Rs, N, use_rgb)) {
+        rc = -2; goto out;
+    }
+    rc = or_compose(sc, state_meshes, state_poses, n_state, cd, cc, own);
+    if (rc) { rc = rc == 1 ? -1 : rc; goto out; }
+    /* the state's own points R_S \ C, and the observed points inside some
+     * volume of the state's objects */
+    Rs.n = 0;
+    for (size_t k = 0; k < N; ++k)
+        if (cd[k] > 0) or_add_point(sc, state_labels[own[k]], k, cd[k], cc, &Rs);
+    covered = (uint8_t *)calloc(obs.n ? (size_t)obs.n : 1, 1);
+    if (!covered) { rc = -2; goto out; }
+    for (int32_t o = 0; o < n_state; ++o) {
+        double lo[3], hi[3];
+        or_mesh_box(state_meshes[o], lo, hi);
+        for (int32_t p = 0; p < obs.n; ++p)
+            if (!covered[p] && or_in_volume(sc, state_labels[o], state_poses + 12 * (size_t)o, lo, hi, &obs, p))
+                covered[p] = 1;
+    }
+    {
+        double lo[3], hi[3];
+        or_mesh_box(m, lo, hi);
+        int err = 0;
+#ifdef _OPENMP
+        int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : err)
+#endif
+        for (int32_t e = 0; e < n; ++e) {
+            const float *P = poses + 12 * (size_t)e;
+            valid[e] = 0; jr[e] = 0; jo[e] = 0;
+            if (nr) nr[e] = 0;
+            if (nq) nq[e] = 0;
+            uint16_t *d = (uint16_t *)malloc(N * sizeof(uint16_t));
+            uint8_t *c = use_rgb ? (uint8_t *)malloc(3 * N) : NULL;
+            or_cloud R;
+            if (!d || (use_rgb && !c) || or_cloud_alloc(&R, (size_t)Rs.n + N, use_rgb)) {
+                free(d); free(c); err |= 1; continue;
+            }
+            if (oracle_render(m, P, K, d, NULL, c) != 0) { free(d); free(c); or_cloud_free(&R); err |= 1; continue; }
+            int mono = 1;
+            for (size_t k = 0; k < N && mono; ++k)
+                if (d[k] > 0 && cd[k] > 0 && d[k] < cd[k]) mono = 0;
+            if (mono) {
+                /* dR \ C, then J_r of each of its points against the observed cloud */
+                R.n = 0;
+                for (size_t k = 0; k < N; ++k)
+                    if (d[k] > 0 && cd[k] == 0) or_add_point(sc, label, k, d[k], c, &R);
+                const int32_t n_new = R.n;
+                int32_t cr = 0;
+                for (int32_t r = 0; r < n_new; ++r) {
+                    int32_t nn = -1;
+                    int found = or_search(&obs, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb, &nn);
+                    if (!found) cr++;
+                    else if (use_rgb && oracle_ciede2000_32(R.lab + 3 * (size_t)r, obs.lab + 3 * (size_t)nn) > sc->tau_c)
+                        cr++;
+                }
+                /* the composed render's points: the state's, then the new object's */
+                for (int32_t r = 0; r < Rs.n; ++r) {
+                    R.x[R.n] = Rs.x[r]; R.y[R.n] = Rs.y[r]; R.z[R.n] = Rs.z[r]; R.pix[R.n] = Rs.pix[r];
+                    if (use_rgb) memcpy(R.lab + 3 * (size_t)R.n, Rs.lab + 3 * (size_t)r, 3 * sizeof(float));
+                    R.n++;
+                }
+                int32_t co = 0, q = 0;
+                for (int32_t p = 0; p < obs.n; ++p) {
+                    if (covered[p] || !or_in_volume(sc, label, P, lo, hi, &obs, p)) continue;
+                    q++;
+                    int32_t nn = -1;
+                    int found = or_search(&R, obs.x[p], obs.y[p], obs.z[p], dq2, dq, use_rgb, &nn);
+                    if (!found) co++;
+                    else if (use_rgb && oracle_ciede2000_32(obs.lab + 3 * (size_t)p, R.lab + 3 * (size_t)nn) > sc->tau_c)
+                        co++;
+                }
+                valid[e] = 1; jr[e] = cr; jo[e] = co;
+                if (nr) nr[e] = n_new;
+                if (nq) nq[e] = q;
+            }
+            free(d); free(c); or_cloud_free(&R);
+        }
+        if (err) rc = -2;
+    }
+out:
+    free(cd); free(cc); free(own); free(covered);
+    or_cloud_free(&obs); or_cloud_free(&Rs);
+    return rc;
 }
