@@ -281,6 +281,63 @@ perch_status perch_propose_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_
                                  const perch_proposal_params *params, float *poses_dev,
                                  int32_t capacity, int32_t *n_out, void *hip_stream);
 
+/* Monotone Scene Generation tree (the sequential search of the original
+ * PERCH that the variant 2.0-B of PERCH 2.0 keeps, Sec. III-B and its tree
+ * figure, Sec. VI-A).  A state is a sequence of placed objects; its render
+ * is their renders composed in order (a pixel keeps the first object that
+ * draws it).  A successor appends one object in one candidate pose and is
+ * monotone iff that object is nearer than the state's render on no pixel
+ * both draw.  Its edge cost is J_r over the object's own points dR (its
+ * pixels the state leaves empty, on the stride grid, less occluders) plus
+ * J_o over the observed points inside its volume V(O) and inside no placed
+ * object's volume, each tested against the composed render's points R \ C
+ * (Eq. 3, Eq. 4).  Nearest-neighbour J_o marking (PERCH_JO_NN) is refused;
+ * PERCH_KNN2 does not apply (the scene's table gives the same neighbours). */
+typedef struct {
+    int32_t mesh_id, label;
+    float pose[12];       /* object -> camera [R|t], mm, row-major binary32 */
+} perch_placed;
+
+/* The edges from one state (n_state placed objects, host array, in placement
+ * order) to object mesh_id (label) at each of n candidate poses:
+ *   poses_dev:  n*12 binary32 (device)
+ *   valid_dev:  n int32, 1 when the successor is monotone (device, written)
+ *   jr_dev, jo_dev: n int32 edge costs, 0 for a successor that is not
+ *               monotone (device, written)
+ *   nr_dev, nq_dev: n int32 |dR \ C| and the observed points charged, or
+ *               NULL (device, written)
+ * The state's planes are composed on hip_stream at each call; with
+ * n_state > 0 the call blocks until the composition has checked that the
+ * state is monotone itself (PERCH_EINVAL when not), then scores
+ * asynchronously. */
+perch_status perch_msg_expand(perch_ctx *ctx, int32_t scene_id, const perch_placed *state, int32_t n_state,
+                              int32_t mesh_id, int32_t label, const float *poses_dev, int32_t n,
+                              int32_t *valid_dev, int32_t *jr_dev, int32_t *jo_dev, int32_t *nr_dev,
+                              int32_t *nq_dev, void *hip_stream);
+
+/* One object of a tree search: its mesh, label and n_poses candidate poses
+ * (n_poses*12 binary32, device). */
+typedef struct {
+    int32_t mesh_id, label, n_poses;
+    const float *poses_dev;
+} perch_msg_object;
+
+/* Beam search over the tree of n_obj objects (1..32).  Level by level it
+ * keeps the `beam` states of least (cost, sequence) -- a state's cost is
+ * the sum of its edge costs, sequences compare lexicographically as
+ * (object index, pose index) pairs -- and scores every successor of each
+ * on the GPU; beam 0 keeps every state (an exhaustive search, refused with
+ * PERCH_ENOMEM when a level's states do not fit the HBM budget).  Returns
+ * the goal of least (cost, sequence):
+ *   order_host[l], pose_host[l]: n_obj int32 each, the object placed at
+ *               level l and its pose index (-1 when no monotone goal exists)
+ *   cost_host:  its cost (-1 when none)
+ *   scored_host: successors scored, or NULL
+ * Synchronous. */
+perch_status perch_msg_search(perch_ctx *ctx, int32_t scene_id, const perch_msg_object *objects, int32_t n_obj,
+                              int32_t beam, int32_t *order_host, int32_t *pose_host, int64_t *cost_host,
+                              int64_t *scored_host, void *hip_stream);
+
 /* Kernel timing.  perch_profile_enable(ctx, 1) clears the record and from
  * then on brackets every kernel launch of the context with HIP events on the
  * launch stream; 0 stops recording.  perch_profile_read waits for the
@@ -289,7 +346,8 @@ perch_status perch_propose_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_
  * 0 pose set-up/classification; scoring kernels by footprint class:
  * 1 tile and keys in LDS (256 or 512 threads), 2 tile and keys in LDS (1024
  * threads), 3 tile in LDS and keys in device memory, 4 tile and keys in
- * device memory; 5 argmin, 6 scene preparation, 7 render, 8 ICP refinement. */
+ * device memory; 5 argmin, 6 scene preparation, 7 render, 8 ICP refinement,
+ * 9 tree successors. */
 perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
 

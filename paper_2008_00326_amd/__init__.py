@@ -70,6 +70,15 @@ class _ProposalParams(ctypes.Structure):
                 ("max_depths", ctypes.c_int32)]
 
 
+class _Placed(ctypes.Structure):
+    _fields_ = [("mesh_id", ctypes.c_int32), ("label", ctypes.c_int32), ("pose", ctypes.c_float * 12)]
+
+
+class _MsgObject(ctypes.Structure):
+    _fields_ = [("mesh_id", ctypes.c_int32), ("label", ctypes.c_int32), ("n_poses", ctypes.c_int32),
+                ("poses_dev", ctypes.c_void_p)]
+
+
 class _SceneDesc(ctypes.Structure):
     _fields_ = [("K", _Intrinsics), ("depth_mm", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("delta_mm", ctypes.c_float), ("tau_c", ctypes.c_float),
@@ -105,6 +114,8 @@ def load_library():
         "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
         "perch_refine_poses": ([P, I32, I32, I32, VP, I32, P, VP, VP, VP, VP], ctypes.c_int),
         "perch_propose_poses": ([P, I32, I32, I32, P, VP, I32, P, VP], ctypes.c_int),
+        "perch_msg_expand": ([P, I32, P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP, VP], ctypes.c_int),
+        "perch_msg_search": ([P, I32, P, I32, I32, P, P, P, P, VP], ctypes.c_int),
         "perch_scene_info_get": ([P, I32, P], ctypes.c_int),
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
@@ -289,7 +300,7 @@ class Context:
                 "key_bands": t.key_bands}
 
     PROFILE_SLOTS = ("setup", "score_lds_small", "score_lds_large", "score_lds_tile", "score_device", "argmin",
-                     "scene_prep", "render", "icp")
+                     "scene_prep", "render", "icp", "msg")
 
     def profile(self, enable: bool = True):
         """Start (clearing the record) or stop bracketing kernel launches with HIP events."""
@@ -370,6 +381,57 @@ class Context:
         _check(self._lib.perch_propose_poses(self._h, int(scene_id), int(mesh_id), int(label), ctypes.byref(prm),
                                              _dev_ptr(out), n.value, ctypes.byref(n), _stream_ptr(stream)))
         return out
+
+    def msg_expand(self, scene_id, state, mesh_id, poses, *, label=0, stream=None):
+        """Edges of the Monotone Scene Generation tree from one state to one
+        object at each of its (n, 12) float32 CUDA poses.  state: a sequence
+        of (mesh_id, label, pose (12 floats)) already placed, in order.
+        Returns (valid, jr, jo, nr, nq) int32 CUDA tensors; blocks while a
+        non-empty state is composed and checked."""
+        import torch
+        if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
+            raise ValueError("poses must be a contiguous float32 CUDA tensor")
+        n = poses.numel() // 12
+        arr = (_Placed * max(1, len(state)))()
+        for k, (mid, lab, pose) in enumerate(state):
+            arr[k].mesh_id = int(mid)
+            arr[k].label = int(lab)
+            arr[k].pose[:] = [float(x) for x in np.asarray(pose, np.float32).reshape(12)]
+        out = [torch.empty(n, dtype=torch.int32, device=poses.device) for _ in range(5)]
+        if stream is None:
+            stream = torch.cuda.current_stream(poses.device)
+        _check(self._lib.perch_msg_expand(self._h, int(scene_id), arr, len(state), int(mesh_id), int(label),
+                                          _dev_ptr(poses), n, *[_dev_ptr(t) for t in out], _stream_ptr(stream)))
+        return tuple(out)
+
+    def msg_search(self, scene_id, objects, *, beam, stream=None):
+        """Beam search over the Monotone Scene Generation tree.  objects: a
+        sequence of (mesh_id, label, poses (n, 12) float32 CUDA tensor);
+        beam: states kept per level (0 = all).  Returns ((cost, sequence) or
+        None, successors scored), the sequence a tuple of (object, pose
+        index) pairs in placement order.  Synchronous."""
+        import torch
+        k = len(objects)
+        arr = (_MsgObject * max(1, k))()
+        for o, (mid, lab, poses) in enumerate(objects):
+            if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
+                raise ValueError("poses must be contiguous float32 CUDA tensors")
+            arr[o].mesh_id = int(mid)
+            arr[o].label = int(lab)
+            arr[o].n_poses = poses.numel() // 12
+            arr[o].poses_dev = _dev_ptr(poses)
+        order = (ctypes.c_int32 * max(1, k))()
+        pose = (ctypes.c_int32 * max(1, k))()
+        cost = ctypes.c_int64()
+        scored = ctypes.c_int64()
+        dev = objects[0][2].device if k else torch.device("cuda", self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(self._lib.perch_msg_search(self._h, int(scene_id), arr, k, int(beam), order, pose,
+                                          ctypes.byref(cost), ctypes.byref(scored), _stream_ptr(stream)))
+        if cost.value < 0:
+            return None, scored.value
+        return (cost.value, tuple((order[q], pose[q]) for q in range(k))), scored.value
 
     def render(self, scene_id, mesh_id, poses, K, *, rgb=False, tri=False, stream=None):
         """Full-image renders of (n, 12) poses: (depth u16, rgb u8 or None, tri i32 or None) tensors."""

@@ -169,9 +169,70 @@ struct ProposalArgs {
 };
 hipError_t launch_proposals(const ProposalArgs &a, hipStream_t st);
 
+// Monotone Scene Generation tree: the full-image planes of one state.
+struct MsgState {
+    uint16_t *depth;          // composed depth in mm, 0 where no placed object draws
+    uint16_t *pts;            // depth where the pixel is a point of the composed R \ C, else 0
+    uint32_t *rgb;            // packed sRGB8 of the composed render (RGB scenes), else null
+    uint8_t *cov;             // 1 where the observed point lies in a placed object's volume
+    unsigned long long *near; // per observed pixel: min (d2 << 32 | pixel) over R \ C within delta, ~0 none
+};
+// Bytes of the planes of one state of n pixels, each plane 256-byte aligned.
+inline size_t msg_state_bytes(size_t n)
+{
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return up(2 * n) + up(2 * n) + up(4 * n) + up(n) + up(8 * n);
+}
+inline MsgState msg_state_at(void *base, size_t n, bool rgb)
+{
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *p = (char *)base;
+    MsgState st;
+    st.depth = (uint16_t *)p;
+    p += up(2 * n);
+    st.pts = (uint16_t *)p;
+    p += up(2 * n);
+    st.rgb = rgb ? (uint32_t *)p : nullptr;
+    p += up(4 * n);
+    st.cov = (uint8_t *)p;
+    p += up(n);
+    st.near = (unsigned long long *)p;
+    return st;
+}
+// Append one object (mesh m at pose P) to a state in place.
+struct MsgAddArgs {
+    SceneDev s;
+    MeshDev m;
+    const float *pose;        // 12 binary32 (device)
+    int label;
+    MsgState st;
+    uint32_t *keys;           // W*H raster keys
+    int *flag;                // set to 1 when the object occludes the state (not monotone)
+};
+// Score every successor of one state: one object at each of n poses.
+struct MsgArgs {
+    SceneDev s;
+    MeshDev m;
+    const float *poses;       // n * 12
+    int n, label;
+    int vbox[4];              // label volumes: x0, y0, w, h of the label's pixels
+    MsgState st;
+    int32_t *valid, *jr, *jo, *nr, *nq;   // nr, nq may be null
+    int lds_words;            // dynamic LDS per work-group: the tile when it fits, then projected vertices
+    uint32_t *tiles;          // per work-group: W*H tile words (tiles larger than the LDS)
+    int *cursor;              // pose cursor, zeroed by the launch
+};
+hipError_t upload_msg_colour_table(const float *lin256);
+hipError_t msg_state_clear(const SceneDev &s, const MsgState &st, hipStream_t stream);
+hipError_t msg_state_add(const MsgAddArgs &a, hipStream_t stream);
+// The per-observed-pixel nearest state point, after the last msg_state_add.
+hipError_t msg_state_near(const SceneDev &s, const MsgState &st, hipStream_t stream);
+hipError_t launch_msg(const MsgArgs &a, int grid, hipStream_t stream);
+hipError_t prepare_msg_kernel(int lds_per_group, int *lds_words);
+
 // Kernel slots reported by the profiler (perch_profile_read).
 enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
-                kProfIcp = 8, kNumProfSlots = 9 };
+                kProfIcp = 8, kProfMsg = 9, kNumProfSlots = 10 };
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n,
                          uint32_t *keys, uint16_t *depth, uint8_t *rgb, int32_t *tri,
                          hipStream_t st);

@@ -24,145 +24,7 @@
 
 namespace perch {
 
-__constant__ float c_lin[256];   // sRGB8 -> linear, rounded from binary64
-
-// ------------------------------------------------------------------ colour of a pixel
-
-// Perspective-correct vertex colour of triangle t at pixel (i, j), rounded to sRGB8.
-__device__ uint32_t triangle_colour(const SceneDev &s, const MeshDev &m, const float *P, int t, int i, int j)
-{
-    if (t < 0 || t >= m.nt) return 0;
-    const int4 ix = gld(m.tris + t);
-    const Vtx a = project_vertex(P, gld(m.verts + ix.x), s);
-    const Vtx b = project_vertex(P, gld(m.verts + ix.y), s);
-    const Vtx c = project_vertex(P, gld(m.verts + ix.z), s);
-    const long long px = 256LL * i, py = 256LL * j;
-    const long long w0 = edge_fn(b.U, b.V, c.U, c.V, px, py);
-    const long long w1 = edge_fn(c.U, c.V, a.U, a.V, px, py);
-    const long long w2 = edge_fn(a.U, a.V, b.U, b.V, px, py);
-    const double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
-    const double sum = (t0 + t1) + t2;
-    const uint32_t ca = gld(m.vrgb + ix.x), cb = gld(m.vrgb + ix.y), cc = gld(m.vrgb + ix.z);
-    uint32_t out = 0;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        const double c0 = (double)((ca >> (8 * ch)) & 255u);
-        const double c1 = (double)((cb >> (8 * ch)) & 255u);
-        const double c2 = (double)((cc >> (8 * ch)) & 255u);
-        double v = rint(((t0 * c0 + t1 * c1) + t2 * c2) / sum);
-        v = v < 0.0 ? 0.0 : (v > 255.0 ? 255.0 : v);
-        out |= (uint32_t)v << (8 * ch);
-    }
-    return out;
-}
-
-// ------------------------------------------------------------------ colour
-
-__device__ __forceinline__ float lab_f(float t)
-{
-    const float e = 216.0f / 24389.0f;
-    const float k = 841.0f / 108.0f;
-    return t > e ? cbrtf(t) : t * k + 4.0f / 29.0f;
-}
-
-__device__ __forceinline__ float4 srgb_to_lab(uint32_t c)
-{
-    const float r = c_lin[c & 255u], g = c_lin[(c >> 8) & 255u], b = c_lin[(c >> 16) & 255u];
-    const float X = (0.4124f * r + 0.3576f * g) + 0.1805f * b;
-    const float Y = (0.2126f * r + 0.7152f * g) + 0.0722f * b;
-    const float Z = (0.0193f * r + 0.1192f * g) + 0.9505f * b;
-    const float Xn = (0.4124f + 0.3576f) + 0.1805f;
-    const float Yn = (0.2126f + 0.7152f) + 0.0722f;
-    const float Zn = (0.0193f + 0.1192f) + 0.9505f;
-    const float fx = lab_f(X / Xn), fy = lab_f(Y / Yn), fz = lab_f(Z / Zn);
-    return make_float4(116.0f * fy - 16.0f, 500.0f * (fx - fy), 200.0f * (fy - fz), 0.0f);
-}
-
-// CIEDE2000 (kL = kC = kH = 1), binary32; x is the point, y its match.
-__device__ float ciede2000(float4 x, float4 y)
-{
-    const float D2R = 0.017453292519943295f, R2D = 57.29577951308232f;
-    const float P25 = 6103515625.0f;
-    const float L1 = x.x, a1 = x.y, b1 = x.z;
-    const float L2 = y.x, a2 = y.y, b2 = y.z;
-    const float C1 = sqrtf(a1 * a1 + b1 * b1), C2 = sqrtf(a2 * a2 + b2 * b2);
-    const float Cm = (C1 + C2) * 0.5f;
-    const float Cm2 = Cm * Cm;
-    const float Cm7 = ((Cm2 * Cm2) * Cm2) * Cm;
-    const float G = 0.5f * (1.0f - sqrtf(Cm7 / (Cm7 + P25)));
-    const float a1p = (1.0f + G) * a1, a2p = (1.0f + G) * a2;
-    const float C1p = sqrtf(a1p * a1p + b1 * b1), C2p = sqrtf(a2p * a2p + b2 * b2);
-    float h1p = (a1p == 0.0f && b1 == 0.0f) ? 0.0f : atan2f(b1, a1p) * R2D;
-    float h2p = (a2p == 0.0f && b2 == 0.0f) ? 0.0f : atan2f(b2, a2p) * R2D;
-    if (h1p < 0.0f) h1p += 360.0f;
-    if (h2p < 0.0f) h2p += 360.0f;
-    const float dLp = L2 - L1;
-    const float dCp = C2p - C1p;
-    const float CC = C1p * C2p;
-    float dhp;
-    if (CC == 0.0f) dhp = 0.0f;
-    else if (fabsf(h2p - h1p) <= 180.0f) dhp = h2p - h1p;
-    else if (h2p - h1p > 180.0f) dhp = h2p - h1p - 360.0f;
-    else dhp = h2p - h1p + 360.0f;
-    const float dHp = 2.0f * sqrtf(CC) * sinf(dhp * D2R * 0.5f);
-    const float Lmp = (L1 + L2) * 0.5f;
-    const float Cmp = (C1p + C2p) * 0.5f;
-    float hmp;
-    if (CC == 0.0f) hmp = h1p + h2p;
-    else if (fabsf(h1p - h2p) <= 180.0f) hmp = (h1p + h2p) * 0.5f;
-    else if (h1p + h2p < 360.0f) hmp = (h1p + h2p + 360.0f) * 0.5f;
-    else hmp = (h1p + h2p - 360.0f) * 0.5f;
-    // T from one sine and cosine of the mean hue: the multiple angles by
-    // the double- and triple-angle formulas, the offsets (30, 6 and 63
-    // degrees) by angle addition with constant sines and cosines
-    float s1, c1;
-    sincosf(hmp * D2R, &s1, &c1);
-    const float c2 = c1 * c1 - s1 * s1, s2 = 2.0f * s1 * c1;
-    const float c3 = c1 * (c2 - 2.0f * s1 * s1), s3 = s1 * (2.0f * c1 * c1 + c2);
-    const float c4 = c2 * c2 - s2 * s2, s4 = 2.0f * s2 * c2;
-    const float C30 = 0.8660254037844386f, S30 = 0.5f;
-    const float C6 = 0.9945218953682733f, S6 = 0.10452846326765347f;
-    const float C63 = 0.45399049973954675f, S63 = 0.8910065241883679f;
-    const float T = 1.0f - 0.17f * (c1 * C30 + s1 * S30) + 0.24f * c2 + 0.32f * (c3 * C6 - s3 * S6)
-                    - 0.20f * (c4 * C63 + s4 * S63);
-    const float hq = (hmp - 275.0f) / 25.0f;
-    const float dth = 30.0f * expf(-(hq * hq));
-    const float Cmp2 = Cmp * Cmp;
-    const float Cmp7 = ((Cmp2 * Cmp2) * Cmp2) * Cmp;
-    const float RC = 2.0f * sqrtf(Cmp7 / (Cmp7 + P25));
-    const float Lm50 = (Lmp - 50.0f) * (Lmp - 50.0f);
-    const float SL = 1.0f + 0.015f * Lm50 / sqrtf(20.0f + Lm50);
-    const float SC = 1.0f + 0.045f * Cmp;
-    const float SH = 1.0f + 0.015f * Cmp * T;
-    const float RT = -sinf(2.0f * dth * D2R) * RC;
-    const float tL = dLp / SL, tC = dCp / SC, tH = dHp / SH;
-    return sqrtf(tL * tL + tC * tC + tH * tH + RT * tC * tH);
-}
-
 // ------------------------------------------------------------------ search
-
-// Largest pixel offset along one axis between a point on the ray of pixel
-// column (row) i at depth z mm and any point within dl = delta + 1/4 mm of
-// it: f dl sqrt(1 + ((i - c) / f)^2) / (z - dl) = a[i] / (z - dl), with
-// `inv` = 1 / (z - dl).  Every point here is the back-projection of a pixel
-// centre at an integer depth, rounded to 1/16 mm: two points within delta in
-// those units lie within delta + 0.12 mm before rounding, and their pixel
-// offset, an integer, is at most the bound's floor.  a[i] is rounded up; the
-// factor covers the binary32 rounding of the quotient (a few ulps).
-__device__ __forceinline__ int window_half(float a, float inv, int limit)
-{
-    const float bnd = a * inv * 1.000002f;
-    if (!(bnd < (float)limit)) return limit;
-    return (int)bnd;
-}
-
-// 1 / (z - dl) for window_half, or infinity when z is too close to the
-// camera for a bound (window_half then returns its limit).
-__device__ __forceinline__ float window_inv(int z, float dl)
-{
-    const float den = (float)z - dl;
-    return den > 1.0f ? 1.0f / den : INFINITY;
-}
 
 // ceil(2^16 / w) for w = 1..64: lane / w = (lane * c_rcp16[w]) >> 16 exactly
 // for lane < 64.
@@ -309,31 +171,6 @@ template <> struct Marks<true> {
         return (__hip_atomic_load(b + (k >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> (k & 31)) & 1u;
     }
 };
-
-// Is observed point (X, Y, Z in 1/16 mm) inside V(O) at pose P?  q = R^T (p - t)
-// in binary64, tested against the object's AABB inflated by delta or, for
-// the cylinder volume, against the cylinder about the object z axis through
-// the centre of the AABB's xy extent, of radius the smaller xy half-extent
-// plus delta, over the AABB's z range inflated by delta.
-__device__ __forceinline__ bool in_volume(const MeshDev &m, const float *P, int X, int Y, int dp, double dl, bool cyl)
-{
-    const double e0 = (double)X / 16.0 - (double)P[3];
-    const double e1 = (double)Y / 16.0 - (double)P[7];
-    const double e2 = (double)dp - (double)P[11];
-    const double q0 = ((double)P[0] * e0 + (double)P[4] * e1) + (double)P[8] * e2;
-    const double q1 = ((double)P[1] * e0 + (double)P[5] * e1) + (double)P[9] * e2;
-    const double q2 = ((double)P[2] * e0 + (double)P[6] * e1) + (double)P[10] * e2;
-    const bool inz = ((double)m.lo[2] - dl <= q2) && (q2 <= (double)m.hi[2] + dl);
-    if (cyl) {
-        const double c0 = ((double)m.lo[0] + (double)m.hi[0]) / 2.0, c1 = ((double)m.lo[1] + (double)m.hi[1]) / 2.0;
-        const double h0 = ((double)m.hi[0] - (double)m.lo[0]) / 2.0, h1 = ((double)m.hi[1] - (double)m.lo[1]) / 2.0;
-        const double rho = (h0 < h1 ? h0 : h1) + dl;
-        const double a = q0 - c0, b = q1 - c1;
-        return (a * a + b * b <= rho * rho) && inz;
-    }
-    return ((double)m.lo[0] - dl <= q0) && (q0 <= (double)m.hi[0] + dl) && ((double)m.lo[1] - dl <= q1)
-           && (q1 <= (double)m.hi[1] + dl) && inz;
-}
 
 // kNN II (Sec. IV-A, parallel cost computation): the nearest observed point
 // of rendered point (X, Y, Z) found by one thread scanning the whole observed

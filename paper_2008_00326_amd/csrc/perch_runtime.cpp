@@ -115,6 +115,8 @@ struct StreamBufs {
     LaunchBufs lb;
     DevBuf tmp;               // J_r / J_o of perch_best_poses
     DevBuf icp;               // ICP: pose cursor, per-work-group tiles and point lists
+    DevBuf msg;               // tree: cursor, flag, raster keys, poses, per-work-group tiles, outputs
+    DevBuf msg_states[2];     // tree: the planes of the states of two consecutive levels
     Staging ring[8];
     int next = 0;
     int32_t last_n = 0;       // poses of the last scoring launch on this stream
@@ -139,6 +141,7 @@ struct perch_ctx {
     perch_tuning tune{};                  // zeros: defaults
     int static_lds[3] = {0, 0, 0};        // static LDS bytes of the 256-, 512- and 1024-thread scoring kernels
     int icp_lds_words = 0;                // dynamic LDS words of the ICP kernel
+    int msg_lds_words = 0;                // dynamic LDS words of the tree's successor kernel
 
     // released device blocks awaiting reuse, and recycled use-tracking events
     std::vector<CachedBlock> cache;
@@ -682,6 +685,8 @@ perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
     e = upload_colour_table(lin);
     if (e == hipSuccess) e = prepare_score_kernels((int)ctx->lds_max, ctx->static_lds);
     if (e == hipSuccess) e = prepare_icp_kernel((int)ctx->lds_max, &ctx->icp_lds_words);
+    if (e == hipSuccess) e = upload_msg_colour_table(lin);
+    if (e == hipSuccess) e = prepare_msg_kernel((int)ctx->lds_max, &ctx->msg_lds_words);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete ctx;
@@ -1173,6 +1178,272 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     HIP_TRY(ctx->timed(kProfIcp, st, [&] { return launch_icp(a, grid, st); }));
     ctx->mark_use(si->second.uses, st);
     ctx->mark_use(mi->second.uses, st);
+    return ok();
+}
+
+namespace {
+
+// Layout of a stream's tree buffer: cursor and flag, then the raster keys of
+// a composition, the placed poses, the per-work-group tiles and the scores.
+struct MsgLayout {
+    size_t keys, poses, tiles, out, bytes;
+};
+static MsgLayout msg_layout(size_t px, int grid, size_t n_poses, size_t n_out)
+{
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    MsgLayout l;
+    l.keys = 512;
+    l.poses = l.keys + up(px * 4);
+    l.tiles = l.poses + up(n_poses * 12 * sizeof(float));
+    l.out = l.tiles + up((size_t)grid * px * 4);
+    l.bytes = l.out + up(n_out * 3 * sizeof(int32_t));
+    return l;
+}
+
+static perch_status msg_check_scene(const SceneRec &sr)
+{
+    if (sr.dev.flags & PERCH_JO_NN) return fail(PERCH_EINVAL, "the tree search does not take PERCH_JO_NN");
+    return PERCH_OK;
+}
+
+static MsgArgs msg_args(perch_ctx *ctx, SceneRec &sr, const MeshRec &mr, int32_t label, const MsgState &st,
+                 const float *poses_dev, int n, char *base, const MsgLayout &l)
+{
+    MsgArgs a{};
+    a.s = sr.dev;
+    a.m = mr.dev;
+    a.poses = poses_dev;
+    a.n = n;
+    a.label = label;
+    if ((sr.dev.flags & PERCH_VOL_MASK) == PERCH_VOL_LABEL) {
+        const std::vector<int> lb = label_box(sr, label);
+        for (int c = 0; c < 4; ++c) a.vbox[c] = lb[c];
+    }
+    a.st = st;
+    a.lds_words = ctx->msg_lds_words;
+    a.tiles = (uint32_t *)(base + l.tiles);
+    a.cursor = (int *)base;
+    return a;
+}
+
+}  // namespace
+
+perch_status perch_msg_expand(perch_ctx *ctx, int32_t scene_id, const perch_placed *state, int32_t n_state,
+                              int32_t mesh_id, int32_t label, const float *poses_dev, int32_t n,
+                              int32_t *valid_dev, int32_t *jr_dev, int32_t *jo_dev, int32_t *nr_dev,
+                              int32_t *nq_dev, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    if (n < 0 || n_state < 0 || n_state > 32) return fail(PERCH_EINVAL, "n must be >= 0 and n_state in [0, 32]");
+    if (n_state > 0 && !state) return fail(PERCH_EINVAL, "null state");
+    if (n > 0 && (!poses_dev || !valid_dev || !jr_dev || !jo_dev)) return fail(PERCH_EINVAL, "null poses or output");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    SceneRec &sr = si->second;
+    if (perch_status e = msg_check_scene(sr)) return e;
+    auto mi = ctx->meshes.find(mesh_id);
+    if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+    for (int k = 0; k < n_state; ++k) {
+        if (!ctx->meshes.count(state[k].mesh_id)) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", state[k].mesh_id);
+        for (int c = 0; c < 12; ++c)
+            if (!std::isfinite(state[k].pose[c])) return fail(PERCH_EINVAL, "state pose %d is not finite", k);
+    }
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    StreamBufs &b = ctx->work[st];
+    const SceneDev &s = sr.dev;
+    const size_t px = (size_t)s.W * s.H;
+    const int grid = std::max(1, std::min(n, std::max(ctx->n_cu, 1)));
+    const MsgLayout l = msg_layout(px, grid, (size_t)n_state, 0);
+    if (perch_status e = ctx->ensure(b.msg, l.bytes)) return e;
+    if (perch_status e = ctx->ensure(b.msg_states[0], msg_state_bytes(px))) return e;
+    char *base = (char *)b.msg.ptr;
+    const bool rgb = (s.flags & PERCH_USE_RGB) != 0;
+    const MsgState ms = msg_state_at(b.msg_states[0].ptr, px, rgb);
+    int *flag = (int *)(base + 256);
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+    HIP_TRY(msg_state_clear(s, ms, st));
+    if (n_state > 0) {
+        std::vector<float> hp((size_t)n_state * 12);
+        for (int k = 0; k < n_state; ++k) std::memcpy(&hp[(size_t)k * 12], state[k].pose, 12 * sizeof(float));
+        float *dp = (float *)(base + l.poses);
+        HIP_TRY(hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        for (int k = 0; k < n_state; ++k) {
+            MsgAddArgs a{};
+            a.s = s;
+            a.m = ctx->meshes[state[k].mesh_id].dev;
+            a.pose = dp + 12 * (size_t)k;
+            a.label = state[k].label;
+            a.st = ms;
+            a.keys = (uint32_t *)(base + l.keys);
+            a.flag = flag;
+            HIP_TRY(msg_state_add(a, st));
+        }
+        HIP_TRY(msg_state_near(s, ms, st));
+        int hflag = 0;
+        HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hflag) return fail(PERCH_EINVAL, "the state is not monotone: an object occludes one placed before it");
+    }
+    if (n > 0) {
+        MsgArgs a = msg_args(ctx, sr, mi->second, label, ms, poses_dev, n, base, l);
+        a.valid = valid_dev;
+        a.jr = jr_dev;
+        a.jo = jo_dev;
+        a.nr = nr_dev;
+        a.nq = nq_dev;
+        HIP_TRY(ctx->timed(kProfMsg, st, [&] { return launch_msg(a, grid, st); }));
+    }
+    ctx->mark_use(sr.uses, st);
+    ctx->mark_use(mi->second.uses, st);
+    for (int k = 0; k < n_state; ++k) ctx->mark_use(ctx->meshes[state[k].mesh_id].uses, st);
+    return ok();
+}
+
+perch_status perch_msg_search(perch_ctx *ctx, int32_t scene_id, const perch_msg_object *objects, int32_t n_obj,
+                              int32_t beam, int32_t *order_host, int32_t *pose_host, int64_t *cost_host,
+                              int64_t *scored_host, void *hip_stream)
+{
+    if (perch_status st = enter(ctx)) return st;
+    if (n_obj < 1 || n_obj > 32) return fail(PERCH_EINVAL, "n_obj must be in [1, 32]");
+    if (!objects || !order_host || !pose_host || !cost_host) return fail(PERCH_EINVAL, "null argument");
+    if (beam < 0) return fail(PERCH_EINVAL, "beam must be >= 0");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    SceneRec &sr = si->second;
+    if (perch_status e = msg_check_scene(sr)) return e;
+    size_t max_n = 0;
+    for (int o = 0; o < n_obj; ++o) {
+        if (!ctx->meshes.count(objects[o].mesh_id))
+            return fail(PERCH_ENOTFOUND, "unknown mesh id %d", objects[o].mesh_id);
+        if (objects[o].n_poses < 0 || (objects[o].n_poses > 0 && !objects[o].poses_dev))
+            return fail(PERCH_EINVAL, "object %d: bad poses", o);
+        max_n = std::max(max_n, (size_t)objects[o].n_poses);
+    }
+    for (int l = 0; l < n_obj; ++l) order_host[l] = pose_host[l] = -1;
+    *cost_host = -1;
+    if (scored_host) *scored_host = 0;
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    StreamBufs &b = ctx->work[st];
+    const SceneDev &s = sr.dev;
+    const size_t px = (size_t)s.W * s.H;
+    const size_t sb = msg_state_bytes(px);
+    const bool rgb = (s.flags & PERCH_USE_RGB) != 0;
+    const int grid = std::max(1, std::min((int)std::max<size_t>(max_n, 1), std::max(ctx->n_cu, 1)));
+
+    struct Node {
+        int64_t cost;
+        std::vector<std::pair<int, int>> seq;   // (object, pose index) in placement order
+        uint32_t placed;
+    };
+    std::vector<Node> cur(1, Node{0, {}, 0u});
+    int cur_buf = 0;
+    if (perch_status e = ctx->ensure(b.msg_states[cur_buf], sb)) return e;
+    HIP_TRY(msg_state_clear(s, msg_state_at(b.msg_states[cur_buf].ptr, px, rgb), st));
+    int64_t scored = 0;
+    for (int level = 0; level < n_obj; ++level) {
+        // every successor of every state, scored into one output array
+        size_t total = 0;
+        for (const Node &nd : cur)
+            for (int o = 0; o < n_obj; ++o)
+                if (!(nd.placed >> o & 1u)) total += (size_t)objects[o].n_poses;
+        const MsgLayout l = msg_layout(px, grid, 0, total);
+        if (perch_status e = ctx->ensure(b.msg, l.bytes)) return e;
+        char *base = (char *)b.msg.ptr;
+        int32_t *outd = (int32_t *)(base + l.out);
+        size_t off = 0;
+        for (size_t c = 0; c < cur.size(); ++c) {
+            const MsgState ms = msg_state_at((char *)b.msg_states[cur_buf].ptr + c * sb, px, rgb);
+            for (int o = 0; o < n_obj; ++o) {
+                if (cur[c].placed >> o & 1u) continue;
+                const int n = objects[o].n_poses;
+                if (n == 0) continue;
+                MsgArgs a = msg_args(ctx, sr, ctx->meshes[objects[o].mesh_id], objects[o].label, ms,
+                                     objects[o].poses_dev, n, base, l);
+                a.valid = outd + off;
+                a.jr = outd + total + off;
+                a.jo = outd + 2 * total + off;
+                HIP_TRY(ctx->timed(kProfMsg, st, [&] { return launch_msg(a, std::min(grid, n), st); }));
+                off += (size_t)n;
+            }
+        }
+        std::vector<int32_t> h(3 * total);
+        if (total > 0) HIP_TRY(hipMemcpyAsync(h.data(), outd, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        scored += (int64_t)total;
+        // the states' lexicographic ranks; children compare as (cost, parent rank, object, pose)
+        std::vector<int> idx(cur.size()), rank(cur.size());
+        for (size_t c = 0; c < cur.size(); ++c) idx[c] = (int)c;
+        std::sort(idx.begin(), idx.end(), [&](int x, int y) { return cur[x].seq < cur[y].seq; });
+        for (size_t r = 0; r < idx.size(); ++r) rank[idx[r]] = (int)r;
+        struct Cand {
+            int64_t cost;
+            int prank, o, k, parent;
+        };
+        std::vector<Cand> cand;
+        off = 0;
+        for (size_t c = 0; c < cur.size(); ++c)
+            for (int o = 0; o < n_obj; ++o) {
+                if (cur[c].placed >> o & 1u) continue;
+                for (int k = 0; k < objects[o].n_poses; ++k, ++off)
+                    if (h[off]) cand.push_back(Cand{cur[c].cost + h[total + off] + h[2 * total + off], rank[c], o, k, (int)c});
+            }
+        auto less = [](const Cand &x, const Cand &y) {
+            if (x.cost != y.cost) return x.cost < y.cost;
+            if (x.prank != y.prank) return x.prank < y.prank;
+            if (x.o != y.o) return x.o < y.o;
+            return x.k < y.k;
+        };
+        const size_t keep = beam > 0 ? std::min(cand.size(), (size_t)beam) : cand.size();
+        std::partial_sort(cand.begin(), cand.begin() + keep, cand.end(), less);
+        cand.resize(keep);
+        if (cand.empty()) break;                       // every state is a dead end
+        std::vector<Node> next(keep);
+        for (size_t c = 0; c < keep; ++c) {
+            const Node &par = cur[cand[c].parent];
+            next[c].cost = cand[c].cost;
+            next[c].seq = par.seq;
+            next[c].seq.emplace_back(cand[c].o, cand[c].k);
+            next[c].placed = par.placed | (1u << cand[c].o);
+        }
+        if (level == n_obj - 1) {
+            for (int q = 0; q < n_obj; ++q) {
+                order_host[q] = next[0].seq[q].first;
+                pose_host[q] = next[0].seq[q].second;
+            }
+            *cost_host = next[0].cost;
+            break;
+        }
+        // the kept states' planes: the parent's, with the new object appended
+        const int nb = 1 - cur_buf;
+        if (beam == 0 && ctx->budget && ctx->used + keep * sb > ctx->budget)
+            return fail(PERCH_ENOMEM, "exhaustive search: %zu states of %zu bytes exceed the budget", keep, sb);
+        if (perch_status e = ctx->ensure(b.msg_states[nb], keep * sb)) return e;
+        char *base2 = (char *)b.msg.ptr;
+        for (size_t c = 0; c < keep; ++c) {
+            char *dst = (char *)b.msg_states[nb].ptr + c * sb;
+            HIP_TRY(hipMemcpyAsync(dst, (char *)b.msg_states[cur_buf].ptr + (size_t)cand[c].parent * sb, sb,
+                                   hipMemcpyDeviceToDevice, st));
+            const MsgState ms = msg_state_at(dst, px, rgb);
+            MsgAddArgs a{};
+            a.s = s;
+            a.m = ctx->meshes[objects[cand[c].o].mesh_id].dev;
+            a.pose = objects[cand[c].o].poses_dev + 12 * (size_t)cand[c].k;
+            a.label = objects[cand[c].o].label;
+            a.st = ms;
+            a.keys = (uint32_t *)(base2 + l.keys);
+            a.flag = (int *)(base2 + 256);
+            HIP_TRY(msg_state_add(a, st));
+            HIP_TRY(msg_state_near(s, ms, st));
+        }
+        cur.swap(next);
+        cur_buf = nb;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (scored_host) *scored_host = scored;
+    ctx->mark_use(sr.uses, st);
+    for (int o = 0; o < n_obj; ++o) ctx->mark_use(ctx->meshes[objects[o].mesh_id].uses, st);
     return ok();
 }
 

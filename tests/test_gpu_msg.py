@@ -1,0 +1,196 @@
+"""GPU parity of the Monotone Scene Generation tree (readings M1-M5 of the
+oracle source; the variant 2.0-B, Sec. III-B and Sec. VI-A) against the
+oracle.
+
+Edges: monotonicity, |dR \\ C| and the observed points charged are integer
+results and must agree exactly, as must J_r and J_o without colour; with
+colour the counts may differ by the binary32 colour decisions, within
+ceil(0.001 L) for J_r and ceil(0.001 Q) + ceil(0.001 L) for J_o.  Searches
+(integer costs without colour) must return the same goal and score the same
+number of successors.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2008_00326_amd as pk  # noqa: E402
+from paper_2008_00326_amd.workloads import make_config  # noqa: E402
+from test_oracle_msg import DELTA, _world  # noqa: E402
+
+THREADS = 16
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def check_edges(got, exp, rgb, what):
+    v, jr, jo, nr, nq = [t.cpu().numpy() for t in got]
+    ev, ejr, ejo, enr, enq = exp
+    assert np.array_equal(v, ev), f"{what}: monotone flags differ at {np.flatnonzero(v != ev)[:8]}"
+    assert np.array_equal(nr, enr), f"{what}: |dR \\ C| differs at {np.flatnonzero(nr != enr)[:8]}"
+    assert np.array_equal(nq, enq), f"{what}: charged points differ at {np.flatnonzero(nq != enq)[:8]}"
+    if not rgb:
+        assert np.array_equal(jr, ejr), f"{what}: J_r differs at {np.flatnonzero(jr != ejr)[:8]}"
+        assert np.array_equal(jo, ejo), f"{what}: J_o differs at {np.flatnonzero(jo != ejo)[:8]}"
+        return
+    tl = np.array([math.ceil(0.001 * x) for x in enr])
+    tq = np.array([math.ceil(0.001 * x) for x in enq])
+    assert np.all(np.abs(jr - ejr) <= tl), f"{what}: J_r beyond tolerance"
+    assert np.all(np.abs(jo - ejo) <= tq + tl), f"{what}: J_o beyond tolerance"
+
+
+FLAGS = [oracle.MARK_OCCLUDERS, oracle.MARK_OCCLUDERS | oracle.USE_RGB, oracle.MARK_OCCLUDERS | oracle.VOL_LABEL,
+         oracle.VOL_CYL | oracle.USE_RGB, oracle.VOL_LABEL | oracle.USE_RGB]
+STATES = [(), ((0, 0),), ((0, 0), (1, 1)), ((2, 1), (0, 3)), ((1, 2),), ((0, 2), (2, 3))]
+
+
+@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("stride", [1, 2])
+def test_edges_match_oracle(ctx, flags, stride):
+    meshes, scene, gt, cands = _world(seed=3)
+    rgb = bool(flags & oracle.USE_RGB)
+    say(f"msg edges: flags {flags}, stride {stride}")
+    sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, scene.labels, delta_mm=DELTA, tau_c=20.0, flags=flags,
+                        stride=stride)
+    mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in meshes]
+    tc = [_cuda(c) for c in cands]
+    torch.cuda.synchronize()
+    say("  scene and meshes resident")
+    checked = 0
+    for seq in STATES:
+        placed = {o for o, _ in seq}
+        ostate = [(meshes[o], o + 1, cands[o][k]) for o, k in seq]
+        # only monotone states can be composed
+        ok = True
+        for n, (o, k) in enumerate(seq):
+            v = oracle.msg_expand(scene, ostate[:n], meshes[o], cands[o][k:k + 1], label=o + 1, delta_mm=DELTA,
+                                  tau_c=20.0, flags=flags, stride=stride)[0]
+            ok &= bool(v[0])
+            if not ok:
+                break
+        if not ok:
+            continue
+        gstate = [(mids[o], o + 1, cands[o][k]) for o, k in seq]
+        for o in range(3):
+            if o in placed:
+                continue
+            say(f"  state {seq}, object {o}: GPU edges")
+            got = ctx.msg_expand(sid, gstate, mids[o], tc[o], label=o + 1)
+            torch.cuda.synchronize()
+            say("  oracle edges")
+            exp = oracle.msg_expand(scene, ostate, meshes[o], cands[o], label=o + 1, delta_mm=DELTA, tau_c=20.0,
+                                    flags=flags, stride=stride, threads=THREADS)
+            check_edges(got, exp, rgb, f"state {seq} object {o}")
+            checked += 1
+    for m in mids:
+        ctx.unload_mesh(m)
+    ctx.drop_scene(sid)
+    assert checked >= 8
+
+
+@pytest.mark.parametrize("beam", [0, 1, 4])
+@pytest.mark.parametrize("flags", [oracle.MARK_OCCLUDERS, oracle.VOL_LABEL])
+def test_search_matches_oracle(ctx, beam, flags):
+    meshes, scene, gt, cands = _world(seed=5, colours=False)
+    rng = np.random.default_rng(6)
+    depth = scene.depth.astype(np.int32)
+    noisy = np.where(depth > 0, np.clip(depth + np.rint(rng.normal(0, 2.0, depth.shape)), 1, 65534), 0)
+    scene.depth = noisy.astype(np.uint16)
+    say(f"msg search: beam {beam}, flags {flags}")
+    sid = ctx.set_scene(scene.K, scene.depth, None, scene.labels, delta_mm=DELTA, flags=flags)
+    mids = [ctx.load_mesh(m.xyz, m.tri, None) for m in meshes]
+    objs = [(mids[o], o + 1, _cuda(cands[o])) for o in range(3)]
+    got = ctx.msg_search(sid, objs, beam=beam)
+    say(f"  GPU search done: {got}")
+    exp = oracle.msg_search(scene, [(meshes[o], o + 1, cands[o]) for o in range(3)], beam=beam, delta_mm=DELTA,
+                            flags=flags, threads=THREADS)
+    for m in mids:
+        ctx.unload_mesh(m)
+    ctx.drop_scene(sid)
+    assert got == exp, (got, exp)
+
+
+def test_search_recovers_the_generating_scene(ctx):
+    meshes, scene, gt, cands = _world(seed=2)
+    sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, scene.labels, delta_mm=DELTA, tau_c=20.0,
+                        flags=oracle.MARK_OCCLUDERS | oracle.USE_RGB)
+    mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in meshes]
+    (cost, seq), scored = ctx.msg_search(sid, [(mids[o], o + 1, _cuda(cands[o])) for o in range(3)], beam=0)
+    for m in mids:
+        ctx.unload_mesh(m)
+    ctx.drop_scene(sid)
+    assert sorted(seq) == [(0, 0), (1, 0), (2, 0)]
+    assert [o for o, _ in seq].index(0) < [o for o, _ in seq].index(1)
+    assert scored > 12
+
+
+def test_refuses_bad_states_and_flags(ctx):
+    meshes, scene, gt, cands = _world()
+    sid = ctx.set_scene(scene.K, scene.depth, None, scene.labels, delta_mm=DELTA, flags=oracle.MARK_OCCLUDERS)
+    mids = [ctx.load_mesh(m.xyz, m.tri, None) for m in meshes]
+    t1 = _cuda(cands[2])
+    # object 0 stands in front of object 1: placing 1 first, then 0, is not monotone
+    with pytest.raises(pk.PerchError, match="monotone"):
+        ctx.msg_expand(sid, [(mids[1], 2, gt[1]), (mids[0], 1, gt[0])], mids[2], t1, label=3)
+    sid2 = ctx.set_scene(scene.K, scene.depth, None, scene.labels, delta_mm=DELTA, jo="nn")
+    with pytest.raises(pk.PerchError, match="JO_NN"):
+        ctx.msg_expand(sid2, [], mids[2], t1, label=3)
+    for m in mids:
+        ctx.unload_mesh(m)
+    ctx.drop_scene(sid)
+    ctx.drop_scene(sid2)
+
+
+@pytest.mark.parametrize("volume", ["aabb", "label"])
+def test_cfg2_sampled_edges(ctx, volume):
+    """640x480 cfg2 scene: two objects placed at their generating poses, the
+    third object's 6,400 candidates scored on the GPU; a seeded sample of
+    them (and the generating pose) against the oracle."""
+    w = make_config(2, 0)
+    s = w.scene
+    flags = oracle.USE_RGB | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0) | \
+        (oracle.VOL_LABEL if volume == "label" else 0)
+    say(f"msg cfg2 sampled edges: {volume}")
+    sid = ctx.set_scene(s.K, s.depth, s.rgb, s.labels, delta_mm=w.delta_mm, tau_c=w.tau_c, flags=flags)
+    mids = {k: ctx.load_mesh(m.xyz, m.tri, m.rgb) for k, m in enumerate(w.meshes)}
+    objs = w.objects
+    placed = [(objs[0].mesh, objs[0].label, objs[0].gt_pose), (objs[1].mesh, objs[1].label, objs[1].gt_pose)]
+    o = objs[2]
+    got = ctx.msg_expand(sid, [(mids[m], lab, p) for m, lab, p in placed], mids[o.mesh], _cuda(o.poses), label=o.label)
+    got = [t.cpu().numpy() for t in got]
+    rng = np.random.default_rng(9)
+    sel = np.sort(rng.choice(o.poses.shape[0], 14, replace=False))
+    poses = np.concatenate([o.poses[sel], o.gt_pose.reshape(1, 12).astype(np.float32)])
+    exp = oracle.msg_expand(s, [(w.meshes[m], lab, p) for m, lab, p in placed], w.meshes[o.mesh], poses,
+                            label=o.label, delta_mm=w.delta_mm, tau_c=w.tau_c, flags=flags, threads=THREADS)
+    g_gt = ctx.msg_expand(sid, [(mids[m], lab, p) for m, lab, p in placed], mids[o.mesh],
+                          _cuda(o.gt_pose.reshape(1, 12)), label=o.label)
+    g_gt = [t.cpu().numpy() for t in g_gt]
+    for m in mids.values():
+        ctx.unload_mesh(m)
+    ctx.drop_scene(sid)
+    sub = [np.concatenate([a[sel], b]) for a, b in zip(got, g_gt)]
+    check_edges([torch.from_numpy(a) for a in sub], exp, True, f"cfg2 {volume}")
+    assert exp[0].sum() > 0 and exp[3].max() > 100
