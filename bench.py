@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--icp-method", choices=("plane", "point", "both"), default="plane",
                     help="refinement of the 6-DoF leg: plane-to-plane GICP (the paper's), point-to-point ICP, or both")
     ap.add_argument("--refine-steps", type=int, default=2, help="timed passes of the refine leg")
+    ap.add_argument("--no-msg", action="store_true", help="skip the Monotone Scene Generation tree leg")
+    ap.add_argument("--msg-beam", type=int, default=4, help="states kept per level by the tree leg's search")
     ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -268,6 +270,8 @@ def main():
 
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
+    if not args.no_msg:
+        result["msg"] = msg_leg(ctx, w, mids, args.msg_beam, 0 if args.no_cpu_baseline else 4)
     if args.pipeline6d:
         methods = ("plane", "point") if args.icp_method == "both" else (args.icp_method,)
         legs = {m: pipeline6d_leg(ctx, args.seed, method=m) for m in methods}
@@ -374,6 +378,60 @@ def refine_leg(ctx, w, mids, steps, cpu_sample):
         dt = time.perf_counter() - t0
         out["cpu_oracle"] = {"poses_per_s": round(k / dt, 3), "cores": threads,
                              "sample": f"{k} poses ({per} per object, seeded uniform), brute-force matches, {dt:.1f} s"}
+    ctx.drop_scene(sid)
+    return out
+
+
+def msg_leg(ctx, w, mids, beam, cpu_sample):
+    """The Monotone Scene Generation tree (the sequential variant 2.0-B) on
+    the same scene and candidates: a beam search of width `beam` over all
+    objects, every successor of every kept state scored on the GPU.  Reports
+    successors scored per second, the tree kernel's time, the goal's cost and
+    placement order, and each object's pose against the one the flat search
+    (every object scored alone, 2.0-C) picks; the CPU oracle's edge rate on a
+    small sample."""
+    import torch
+    s = w.scene
+    _log(f"[bench] tree: beam {beam}")
+    sid = ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels, delta_mm=w.delta_mm, tau_c=w.tau_c,
+                        use_rgb=w.use_rgb, mark_occluders=w.mark_occluders, volume="label")
+    objs = [(mids[o.mesh], o.label, torch.from_numpy(o.poses).cuda()) for o in w.objects]
+    ctx.msg_search(sid, objs, beam=beam)                       # warm-up
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    goal, scored = ctx.msg_search(sid, objs, beam=beam)
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    flat_idx, flat_cost = ctx.best_poses(sid, [m for m, _, _ in objs], [lab for _, lab, _ in objs],
+                                         [p for _, _, p in objs])
+    out = {"workload": f"{w.name}, label volumes, beam search over the tree", "beam": beam,
+           "successors_scored": int(scored), "search_ms": round(dt * 1e3, 3),
+           "successors_per_s": round(scored / dt, 1),
+           "msg_kernel_ms": round(prof["msg"][0], 3), "msg_launches": prof["msg"][1]}
+    if goal is not None:
+        cost, seq = goal
+        pick = dict(seq)
+        out.update({"goal_cost": int(cost), "order": [int(o) for o, _ in seq],
+                    "same_pose_as_flat": [bool(pick[o] == int(flat_idx[o])) for o in range(len(w.objects))],
+                    "flat_sum_cost": int(sum(int(c) for c in flat_cost))})
+    if cpu_sample:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        o = w.objects[-1]
+        flags = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0) | \
+            oracle.VOL_LABEL
+        state = [(w.meshes[q.mesh], q.label, q.gt_pose) for q in w.objects[:2]]
+        rng = np.random.default_rng(8)
+        sel = np.sort(rng.choice(o.poses.shape[0], cpu_sample, replace=False))
+        t0 = time.perf_counter()
+        oracle.msg_expand(s, state, w.meshes[o.mesh], o.poses[sel], label=o.label, delta_mm=w.delta_mm,
+                          tau_c=w.tau_c, flags=flags, threads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"successors_per_s": round(len(sel) / dt, 3), "cores": threads,
+                             "sample": f"{len(sel)} successors of a two-object state (seeded uniform), "
+                                       f"brute force, {dt:.1f} s"}
     ctx.drop_scene(sid)
     return out
 
