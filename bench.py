@@ -92,6 +92,9 @@ def main():
                     help="refinement of the 6-DoF leg: plane-to-plane GICP (the paper's), point-to-point ICP, or both")
     ap.add_argument("--refine-steps", type=int, default=2, help="timed passes of the refine leg")
     ap.add_argument("--no-msg", action="store_true", help="skip the Monotone Scene Generation tree leg")
+    ap.add_argument("--knn-sample", type=int, default=0,
+                    help="add the search comparison leg: this many poses per object scored with the neighbour "
+                         "table, the paper's kNN II scan and its kNN I distance array (0 = skip)")
     ap.add_argument("--msg-beam", type=int, default=4, help="states kept per level by the tree leg's search")
     ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -270,6 +273,8 @@ def main():
 
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
+    if args.knn_sample > 0:
+        result["knn"] = knn_leg(ctx, w, mids, args.knn_sample)
     if not args.no_msg:
         result["msg"] = msg_leg(ctx, w, mids, args.msg_beam, 0 if args.no_cpu_baseline else 4)
     if args.pipeline6d:
@@ -379,6 +384,50 @@ def refine_leg(ctx, w, mids, steps, cpu_sample):
         out["cpu_oracle"] = {"poses_per_s": round(k / dt, 3), "cores": threads,
                              "sample": f"{k} poses ({per} per object, seeded uniform), brute-force matches, {dt:.1f} s"}
     ctx.drop_scene(sid)
+    return out
+
+
+def knn_leg(ctx, w, mids, per_object):
+    """The paper's two neighbour searches against the scene's table on a
+    sample of the same workload (the first `per_object` candidates of each
+    object): kNN II, each rendered point scanning the whole observed cloud,
+    and kNN I, every rendered-observed distance of a pose in one array (one
+    pose at a time).  Same outputs by construction, checked here; reports
+    poses/s of each and kNN I's array size per pose."""
+    import torch
+    s = w.scene
+    _log(f"[bench] search comparison: {per_object} poses per object")
+    polys = [torch.from_numpy(np.ascontiguousarray(o.poses[:per_object])).cuda() for o in w.objects]
+    n = sum(p.shape[0] for p in polys)
+    out = {"workload": f"{w.name}, first {per_object} candidates per object", "poses": n}
+    ref = None
+    for search in ("table", "knn2", "knn1"):
+        sid = ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels, delta_mm=w.delta_mm,
+                            tau_c=w.tau_c, use_rgb=w.use_rgb, mark_occluders=w.mark_occluders, volume=w.volume,
+                            jo=w.jo, search=search)
+        for o, p in zip(w.objects, polys):                          # warm-up
+            ctx.score_poses(sid, mids[o.mesh], p[:1], label=o.label)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        res = [ctx.score_poses(sid, mids[o.mesh], p, label=o.label) for o, p in zip(w.objects, polys)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        got = [np.concatenate([r[k].cpu().numpy() for r in res]) for k in range(4)]
+        if ref is None:
+            ref = got
+        leg = {"poses_per_s": round(n / dt, 2), "ms": round(dt * 1e3, 3),
+               "identical_to_table": all(np.array_equal(a, b) for a, b in zip(got, ref))}
+        if search == "knn1":
+            n_obs = int((s.depth > 0).sum())
+            arr = got[2].astype(np.float64) * n_obs * 4
+            leg.update({"observed_points": n_obs, "mean_L": round(float(got[2].mean()), 1),
+                        "array_bytes_mean": round(float(arr.mean())), "array_bytes_max": round(float(arr.max())),
+                        "kernel_ms": round(prof["knn1"][0] + prof["render"][0], 3)})
+        out[search] = leg
+        ctx.drop_scene(sid)
     return out
 
 

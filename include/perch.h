@@ -81,6 +81,13 @@ typedef struct perch_ctx perch_ctx;
                                     * (Sec. IV-A): each rendered point scans the whole observed cloud
                                     * instead of reading the scene's neighbour table.  Same results;
                                     * orders of magnitude slower (an in-house comparison baseline) */
+#define PERCH_KNN1 (1u << 8)       /* Both searches by the paper's kNN I (Sec. IV-A): every distance
+                                    * between a pose's rendered points and the observed cloud goes
+                                    * into one L x I array (4 bytes a pair) that is then reduced by
+                                    * rows (J_r) and by columns (J_o).  Same results as the table;
+                                    * one pose at a time, a comparison baseline scored by
+                                    * perch_score_poses only (refused by the batched, best-pose and
+                                    * tree entry points); not combined with PERCH_KNN2 */
 
 typedef struct {
     int32_t width, height;   /* pixels, 1 .. 4096 */
@@ -94,7 +101,8 @@ typedef struct {
     const int32_t *labels;    /* H*W host array, or NULL (required for PERCH_VOL_LABEL) */
     float delta_mm;           /* sensor resolution delta, 0 < delta <= 500 */
     float tau_c;              /* CIEDE2000 threshold tau_c >= 0, used with PERCH_USE_RGB */
-    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* | PERCH_JO_NN | PERCH_KNN2 */
+    uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* | PERCH_JO_NN | PERCH_KNN2 |
+                                 PERCH_KNN1 */
     int32_t stride;           /* image-space downsampling of the render, >= 1 (Sec. IV-A) */
 } perch_scene_desc;
 
@@ -291,8 +299,9 @@ perch_status perch_propose_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_
  * pixels the state leaves empty, on the stride grid, less occluders) plus
  * J_o over the observed points inside its volume V(O) and inside no placed
  * object's volume, each tested against the composed render's points R \ C
- * (Eq. 3, Eq. 4).  Nearest-neighbour J_o marking (PERCH_JO_NN) is refused;
- * PERCH_KNN2 does not apply (the scene's table gives the same neighbours). */
+ * (Eq. 3, Eq. 4).  Nearest-neighbour J_o marking (PERCH_JO_NN) and PERCH_KNN1
+ * scenes are refused; PERCH_KNN2 does not apply (the scene's table gives the
+ * same neighbours). */
 typedef struct {
     int32_t mesh_id, label;
     float pose[12];       /* object -> camera [R|t], mm, row-major binary32 */
@@ -346,8 +355,8 @@ perch_status perch_msg_search(perch_ctx *ctx, int32_t scene_id, const perch_msg_
  * 0 pose set-up/classification; scoring kernels by footprint class:
  * 1 tile and keys in LDS (256 or 512 threads), 2 tile and keys in LDS (1024
  * threads), 3 tile in LDS and keys in device memory, 4 tile and keys in
- * device memory; 5 argmin, 6 scene preparation, 7 render, 8 ICP refinement,
- * 9 tree successors. */
+ * device memory; 5 argmin, 6 scene preparation, 7 render (and kNN I's rasterization),
+ * 8 ICP refinement, 9 tree successors, 10 kNN I distances and reductions. */
 perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
 

@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["Context", "PerchError", "load_library", "library_path", "USE_RGB", "MARK_OCCLUDERS",
-           "VOL_AABB", "VOL_CYL", "VOL_LABEL", "JO_NN", "KNN2"]
+           "VOL_AABB", "VOL_CYL", "VOL_LABEL", "JO_NN", "KNN2", "KNN1"]
 
 USE_RGB = 1
 MARK_OCCLUDERS = 2
@@ -23,9 +23,10 @@ VOL_CYL = 1 << 4
 VOL_LABEL = 2 << 4
 JO_NN = 1 << 6
 KNN2 = 1 << 7
+KNN1 = 1 << 8
 _VOLUMES = {"aabb": VOL_AABB, "cyl": VOL_CYL, "label": VOL_LABEL}
 _JO_MODES = {"exact": 0, "nn": JO_NN}
-_SEARCHES = {"table": 0, "knn2": KNN2}
+_SEARCHES = {"table": 0, "knn2": KNN2, "knn1": KNN1}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _STATUS = {0: "PERCH_OK", -1: "PERCH_EINVAL", -2: "PERCH_ENOMEM", -3: "PERCH_EDEVICE",
@@ -206,8 +207,9 @@ class Context:
         jo: "exact" (any rendered point within delta explains an observed
         point) or "nn" (only the points that are some inlier's nearest
         neighbour are explained); search: "table" (the scene's neighbour
-        table) or "knn2" (the paper's scan of the whole cloud, a slow
-        baseline with the same results).  `flags`, when given, overrides
+        table), "knn2" (the paper's scan of the whole cloud, a slow
+        baseline with the same results) or "knn1" (the paper's full
+        distance array, one pose at a time, scored by score_poses only).  `flags`, when given, overrides
         use_rgb, mark_occluders, volume, jo and search."""
         depth = np.ascontiguousarray(depth, np.uint16)
         rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
@@ -300,7 +302,7 @@ class Context:
                 "key_bands": t.key_bands}
 
     PROFILE_SLOTS = ("setup", "score_lds_small", "score_lds_large", "score_lds_tile", "score_device", "argmin",
-                     "scene_prep", "render", "icp", "msg")
+                     "scene_prep", "render", "icp", "msg", "knn1")
 
     def profile(self, enable: bool = True):
         """Start (clearing the record) or stop bracketing kernel launches with HIP events."""

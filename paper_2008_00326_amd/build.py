@@ -19,7 +19,8 @@ HIPCC_FLAGS = [
 
 def build_hip(verbose: bool = False) -> str:
     src = [os.path.join(HERE, "csrc", "perch_runtime.cpp"), os.path.join(HERE, "csrc", "perch_kernels.hip"),
-           os.path.join(HERE, "csrc", "perch_icp.hip"), os.path.join(HERE, "csrc", "perch_msg.hip")]
+           os.path.join(HERE, "csrc", "perch_icp.hip"), os.path.join(HERE, "csrc", "perch_msg.hip"),
+           os.path.join(HERE, "csrc", "perch_knn1.hip")]
     tmp = LIB + ".tmp"
     cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(HERE, "csrc"), "-o", tmp, *src]

@@ -230,9 +230,33 @@ hipError_t msg_state_near(const SceneDev &s, const MsgState &st, hipStream_t str
 hipError_t launch_msg(const MsgArgs &a, int grid, hipStream_t stream);
 hipError_t prepare_msg_kernel(int lds_per_group, int *lds_words);
 
+// kNN I (the paper's fully parallel neighbour search): one pose at a time,
+// with every (rendered, observed) distance in a two-dimensional array.
+struct Knn1Args {
+    SceneDev s;
+    MeshDev m;
+    const float *poses;       // n * 12
+    int label;
+    uint32_t *keys;           // W*H raster keys
+    int4 *pts;                // R \ C: (X, Y, Z, pixel), at most W*H
+    uint32_t *pcol;           // W*H packed sRGB8 of the rendered points (RGB scenes)
+    const int *obs;           // n_obs pixels with a reading
+    int n_obs;
+    uint32_t *dist;           // L * n_obs squared distances (saturated)
+    uint8_t *marked;          // W*H marks of nearest-neighbour J_o, or null
+    int *counts;              // L, J_r, J_o, Q of the current pose
+    int32_t *jr, *jo, *nr, *nq;
+};
+hipError_t upload_knn1_colour_table(const float *lin256);
+hipError_t knn1_observed(const SceneDev &s, int *obs, int *n_obs, hipStream_t st);
+// Render pose p and list its R \ C points (count in counts[0]).
+hipError_t knn1_render(const Knn1Args &a, int p, hipStream_t st);
+// Distances, rows and columns of pose p with L rendered points; writes its outputs.
+hipError_t knn1_score(const Knn1Args &a, int p, int L, hipStream_t st);
+
 // Kernel slots reported by the profiler (perch_profile_read).
 enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
-                kProfIcp = 8, kProfMsg = 9, kNumProfSlots = 10 };
+                kProfIcp = 8, kProfMsg = 9, kProfKnn1 = 10, kNumProfSlots = 11 };
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n,
                          uint32_t *keys, uint16_t *depth, uint8_t *rgb, int32_t *tri,
                          hipStream_t st);

@@ -117,6 +117,7 @@ struct StreamBufs {
     DevBuf icp;               // ICP: pose cursor, per-work-group tiles and point lists
     DevBuf msg;               // tree: cursor, flag, raster keys, poses, per-work-group tiles, outputs
     DevBuf msg_states[2];     // tree: the planes of the states of two consecutive levels
+    DevBuf knn1, knn1_dist;   // kNN I: keys, points, colours, observed list, marks, counts; the distance array
     Staging ring[8];
     int next = 0;
     int32_t last_n = 0;       // poses of the last scoring launch on this stream
@@ -498,6 +499,8 @@ perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_
         b.max_pixels = std::max(b.max_pixels, (size_t)sd.W * sd.H);
         b.any_rgb |= (sd.flags & PERCH_USE_RGB) != 0;
         b.any_pv |= (sd.flags & (PERCH_JO_NN | PERCH_KNN2)) != 0;
+        if (sd.flags & PERCH_KNN1)
+            return fail(PERCH_EINVAL, "PERCH_KNN1 scenes are scored by perch_score_poses only");
     }
     if (total >= (1LL << 30)) return fail(PERCH_EINVAL, "too many poses in one launch (%lld)", total);
     b.n_items = (int)items.size();
@@ -686,6 +689,7 @@ perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
     if (e == hipSuccess) e = prepare_score_kernels((int)ctx->lds_max, ctx->static_lds);
     if (e == hipSuccess) e = prepare_icp_kernel((int)ctx->lds_max, &ctx->icp_lds_words);
     if (e == hipSuccess) e = upload_msg_colour_table(lin);
+    if (e == hipSuccess) e = upload_knn1_colour_table(lin);
     if (e == hipSuccess) e = prepare_msg_kernel((int)ctx->lds_max, &ctx->msg_lds_words);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -838,8 +842,11 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (!(d->delta_mm > 0.0f) || !(d->delta_mm <= 500.0f)) return fail(PERCH_EINVAL, "delta_mm must be in (0, 500]");
     if (!(d->tau_c >= 0.0f) || !std::isfinite(d->tau_c)) return fail(PERCH_EINVAL, "tau_c must be finite and >= 0");
     if (d->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
-    const uint32_t known = PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN | PERCH_KNN2;
+    const uint32_t known =
+        PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN | PERCH_KNN2 | PERCH_KNN1;
     if (d->flags & ~known) return fail(PERCH_EINVAL, "unknown flag bits 0x%x", d->flags & ~known);
+    if ((d->flags & PERCH_KNN1) && (d->flags & PERCH_KNN2))
+        return fail(PERCH_EINVAL, "PERCH_KNN1 and PERCH_KNN2 are two searches; pass one");
     const uint32_t vol = d->flags & PERCH_VOL_MASK;
     if (vol != PERCH_VOL_AABB && vol != PERCH_VOL_CYL && vol != PERCH_VOL_LABEL)
         return fail(PERCH_EINVAL, "unsupported volume mode");
@@ -1022,12 +1029,81 @@ perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id)
     return ok();
 }
 
+namespace {
+
+// kNN I: one pose at a time, every (rendered, observed) distance in one array.
+perch_status score_knn1(perch_ctx *ctx, SceneRec &sr, const MeshRec &mr, int32_t label, const float *poses_dev,
+                        int32_t n, int32_t *jr_dev, int32_t *jo_dev, int32_t *nr_dev, int32_t *nq_dev, hipStream_t st)
+{
+    if (n < 0) return fail(PERCH_EINVAL, "n must be >= 0");
+    if (n > 0 && (!poses_dev || !jr_dev || !jo_dev)) return fail(PERCH_EINVAL, "null poses or output");
+    if (n == 0) return PERCH_OK;
+    StreamBufs &b = ctx->work[st];
+    const SceneDev &s = sr.dev;
+    const size_t N = (size_t)s.W * s.H;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const bool nnm = (s.flags & PERCH_JO_NN) != 0;
+    const size_t o_keys = 256, o_pts = o_keys + up(N * 4), o_pcol = o_pts + up(N * 16), o_obs = o_pcol + up(N * 4),
+                 o_mark = o_obs + up(N * 4), bytes = o_mark + up(nnm ? N : 1);
+    if (perch_status e = ctx->ensure(b.knn1, bytes)) return e;
+    char *base = (char *)b.knn1.ptr;
+    Knn1Args a{};
+    a.s = s;
+    a.m = mr.dev;
+    a.poses = poses_dev;
+    a.label = label;
+    a.keys = (uint32_t *)(base + o_keys);
+    a.pts = (int4 *)(base + o_pts);
+    a.pcol = (uint32_t *)(base + o_pcol);
+    a.obs = (const int *)(base + o_obs);
+    a.marked = nnm ? (uint8_t *)(base + o_mark) : nullptr;
+    a.counts = (int *)base;
+    a.jr = jr_dev;
+    a.jo = jo_dev;
+    a.nr = nr_dev;
+    a.nq = nq_dev;
+    int *n_obs_dev = (int *)base + 16;
+    HIP_TRY(hipMemsetAsync(n_obs_dev, 0, sizeof(int), st));
+    HIP_TRY(knn1_observed(s, (int *)(base + o_obs), n_obs_dev, st));
+    int host[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&host[1], n_obs_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    a.n_obs = host[1];
+    for (int32_t p = 0; p < n; ++p) {
+        HIP_TRY(ctx->timed(kProfRender, st, [&] { return knn1_render(a, p, st); }));
+        HIP_TRY(hipMemcpyAsync(&host[0], a.counts, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const int L = host[0];
+        const size_t need = (size_t)L * (size_t)a.n_obs * 4;
+        if (ctx->ensure(b.knn1_dist, std::max(need, (size_t)256)) != PERCH_OK)
+            return fail(PERCH_ENOMEM, "kNN I: the %d x %d distance array of pose %d (%zu bytes) does not fit", L,
+                        a.n_obs, p, need);
+        a.dist = (uint32_t *)b.knn1_dist.ptr;
+        HIP_TRY(ctx->timed(kProfKnn1, st, [&] { return knn1_score(a, p, L, st); }));
+    }
+    ctx->mark_use(sr.uses, st);
+    return PERCH_OK;
+}
+
+}  // namespace
+
 perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
                                const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
                                int32_t *nr_dev, int32_t *nq_dev, void *hip_stream)
 {
     if (perch_status st = enter(ctx)) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    {
+        auto si = ctx->scenes.find(scene_id);
+        if (si != ctx->scenes.end() && (si->second.dev.flags & PERCH_KNN1)) {
+            auto mi = ctx->meshes.find(mesh_id);
+            if (mi == ctx->meshes.end()) return fail(PERCH_ENOTFOUND, "unknown mesh id %d", mesh_id);
+            perch_status s = score_knn1(ctx, si->second, mi->second, label, poses_dev, n, jr_dev, jo_dev, nr_dev,
+                                        nq_dev, pick_stream(ctx, hip_stream));
+            if (s == PERCH_OK) ctx->mark_use(mi->second.uses, pick_stream(ctx, hip_stream));
+            return s ? s : ok();
+        }
+    }
     const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
     perch_status s = run_direct(ctx, &item, 1, pick_stream(ctx, hip_stream), false);
     return s ? s : ok();
@@ -1203,6 +1279,7 @@ static MsgLayout msg_layout(size_t px, int grid, size_t n_poses, size_t n_out)
 static perch_status msg_check_scene(const SceneRec &sr)
 {
     if (sr.dev.flags & PERCH_JO_NN) return fail(PERCH_EINVAL, "the tree search does not take PERCH_JO_NN");
+    if (sr.dev.flags & PERCH_KNN1) return fail(PERCH_EINVAL, "the tree search does not take PERCH_KNN1");
     return PERCH_OK;
 }
 

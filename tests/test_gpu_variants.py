@@ -207,13 +207,79 @@ def test_knn2_full_size_sample(ctx):
         ctx.drop_scene(sid)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_knn1_array_equals_table(ctx, seed):
+    """The paper's kNN I search (every rendered-observed distance in one
+    array, reduced by rows and columns) gives the neighbour table's outputs
+    bit for bit, under both J_o modes and all three volumes; and the
+    oracle's counts."""
+    mesh, scene, poses, p = random_case(60 + seed)
+    volume = ("aabb", "cyl", "aabb")[seed % 3]
+    mid = ctx.load_mesh(mesh.xyz, mesh.tri, mesh.rgb)
+    t = torch.from_numpy(poses[:12]).cuda()
+    for jo in ("exact", "nn"):
+        outs = []
+        for search in ("table", "knn1"):
+            say(f"case {60 + seed} {jo} {search} {volume}: image {scene.K[0]}x{scene.K[1]}, {p}")
+            sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, delta_mm=p["delta"], tau_c=p["tau"],
+                                use_rgb=p["rgb"], mark_occluders=p["occl"], stride=p["stride"], jo=jo, search=search,
+                                volume=volume)
+            outs.append([a.cpu().numpy() for a in ctx.score_poses(sid, mid, t)])
+            torch.cuda.synchronize()
+            ctx.drop_scene(sid)
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
+        exp = oracle.score(mesh, scene, poses[:12], delta_mm=p["delta"], tau_c=p["tau"],
+                           flags=oflags(p["rgb"], p["occl"], volume, jo), stride=p["stride"], threads=THREADS)
+        check(outs[1], exp, p["rgb"], jo, f"case {60 + seed} {jo} knn1")
+    ctx.unload_mesh(mid)
+
+
+@pytest.mark.parametrize("volume", ["aabb", "label"])
+def test_knn1_full_size_sample(ctx, volume):
+    """kNN I on the 640x480 cfg2 scene, two poses per object (each pose's
+    distance array holds L x ~300,000 entries, gigabytes): the table's
+    outputs exactly."""
+    w = make_config(2, 0)
+    s = w.scene
+    say(f"cfg2 kNN I sample, {volume}")
+    sids = [ctx.set_scene(s.K, s.depth, s.rgb, s.labels, delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=True,
+                          volume=volume, search=x) for x in ("table", "knn1")]
+    rng = np.random.default_rng(12)
+    for o in w.objects:
+        mid = ctx.load_mesh(w.meshes[o.mesh].xyz, w.meshes[o.mesh].tri, w.meshes[o.mesh].rgb)
+        poses = np.concatenate([o.gt_pose[None], o.poses[rng.choice(o.poses.shape[0], 1, replace=False)]])
+        a, b = (gpu_score(ctx, sid, mid, poses, label=o.label) for sid in sids)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        assert a[2].min() > 0
+        ctx.unload_mesh(mid)
+    for sid in sids:
+        ctx.drop_scene(sid)
+
+
+def test_knn1_scored_by_score_poses_only(ctx):
+    mesh, scene, poses, p = random_case(70)
+    mid = ctx.load_mesh(mesh.xyz, mesh.tri, mesh.rgb)
+    sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, delta_mm=p["delta"], search="knn1")
+    t = torch.from_numpy(poses[:4]).cuda()
+    with pytest.raises(pk.PerchError, match="KNN1"):
+        ctx.best_poses(sid, [mid], [0], [t])
+    with pytest.raises(pk.PerchError, match="KNN1"):
+        ctx.msg_expand(sid, [], mid, t)
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
+
+
 def test_flag_validation(ctx):
     K = (32, 24, 30.0, 30.0, 16.0, 12.0)
     depth = np.zeros((24, 32), np.uint16)
     with pytest.raises(pk.PerchError):
         ctx.set_scene(K, depth, flags=3 << 4)             # no such volume mode
     with pytest.raises(pk.PerchError):
-        ctx.set_scene(K, depth, flags=1 << 8)             # unknown bit
+        ctx.set_scene(K, depth, flags=1 << 9)             # unknown bit
+    with pytest.raises(pk.PerchError):
+        ctx.set_scene(K, depth, flags=pk.KNN1 | pk.KNN2)  # two searches
     with pytest.raises(ValueError):
         ctx.set_scene(K, depth, volume="sphere")
     with pytest.raises(ValueError):
