@@ -10,8 +10,8 @@ CIEDE2000 gate) and the best pose of each object reduced on the device and
 returned to the host.  The scene, meshes and poses are resident in HBM
 before the timed region.
 
-Prints one JSON line.  With --gpus above 1 it exits: this build runs on one
-GPU.
+Prints one JSON line.  With --gpus above 1 it exits: the library scores
+poses on one GPU.
 """
 from __future__ import annotations
 
@@ -107,7 +107,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build scores poses on one GPU only; run with --gpus 1",
+        print(json.dumps({"error": "the library scores poses on one GPU only; run with --gpus 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
