@@ -132,6 +132,88 @@ def test_search_matches_oracle(ctx, beam, flags):
     assert got == exp, (got, exp)
 
 
+def _random_world(seed):
+    """Three boxes of random sizes at random nearby table positions and yaws
+    (some touching or hiding one another), each with four random candidates
+    around its generating pose."""
+    from paper_2008_00326_amd.workloads.scenes import camera_rig, table_pose
+    from test_oracle_msg import _compose
+    from tiny_meshes import TScene, box
+    rng = np.random.default_rng(900 + seed)
+    rig = camera_rig(float(rng.uniform(650, 950)), float(rng.uniform(35, 60)))
+    meshes, gt, cands, placed = [], [], [], []
+    for k in range(3):
+        half = rng.uniform(15, 40, 2)
+        meshes.append(box((-half[0], -half[1], 0), (half[0], half[1], rng.uniform(30, 90)), n=int(rng.integers(2, 4)),
+                          rgb_seed=int(rng.integers(1 << 30))))
+        rad = float(np.hypot(*half))
+        while True:            # footprints may touch but hardly interpenetrate
+            x, y = rng.uniform(-90, 90, 2)
+            if all(np.hypot(x - px, y - py) >= 0.85 * (rad + pr) for px, py, pr in placed):
+                break
+        placed.append((x, y, rad))
+        a = rng.uniform(0, 6.28)
+        gt.append(table_pose(rig, x, y, a).reshape(12).astype(np.float32))
+        cands.append(np.stack([table_pose(rig, x + dx, y + dy, a + da).reshape(12).astype(np.float32)
+                               for dx, dy, da in [(0, 0, 0)] + [tuple(rng.normal(0, [12, 12, 0.25])) for _ in range(3)]]))
+    depth, rgb, own = _compose(meshes, gt)
+    noisy = np.where(depth > 0, np.clip(depth.astype(np.int32) + np.rint(rng.normal(0, 1.5, depth.shape)), 1, 65534), 0)
+    return meshes, TScene((160, 120, 300.0, 300.0, 80.0, 60.0), noisy.astype(np.uint16), rgb, own + 1), gt, cands
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_worlds_match_oracle(ctx, seed):
+    """Random worlds, flags, strides and deltas: every edge from every
+    monotone state of up to two placed objects, and a beam-2 search
+    without colour, against the oracle."""
+    meshes, scene, gt, cands = _random_world(seed)
+    rng = np.random.default_rng(950 + seed)
+    flags = int(rng.choice([oracle.MARK_OCCLUDERS, 0])) | int(rng.choice([0, oracle.USE_RGB])) | \
+        int(rng.choice([oracle.VOL_AABB, oracle.VOL_CYL, oracle.VOL_LABEL]))
+    stride, delta = int(rng.choice([1, 2, 3])), float(rng.choice([4.0, 7.5, 12.0]))
+    rgb = bool(flags & oracle.USE_RGB)
+    say(f"msg random world {seed}: flags {flags}, stride {stride}, delta {delta}")
+    sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, scene.labels, delta_mm=delta, tau_c=15.0, flags=flags,
+                        stride=stride)
+    mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in meshes]
+    tc = [_cuda(c) for c in cands]
+    kw = dict(delta_mm=delta, tau_c=15.0, flags=flags, stride=stride)
+    states = [()]
+    for o in range(3):
+        v = oracle.msg_expand(scene, [], meshes[o], cands[o], label=o + 1, **kw)[0]
+        states += [((o, int(k)),) for k in np.flatnonzero(v)[:2]]
+    for (o1, k1) in [st[0] for st in states[1:4]]:
+        for o in range(3):
+            if o == o1:
+                continue
+            v = oracle.msg_expand(scene, [(meshes[o1], o1 + 1, cands[o1][k1])], meshes[o], cands[o], label=o + 1,
+                                  **kw)[0]
+            states += [((o1, k1), (o, int(k))) for k in np.flatnonzero(v)[:1]]
+    checked = 0
+    for seq in states:
+        placed = {o for o, _ in seq}
+        gstate = [(mids[o], o + 1, cands[o][k]) for o, k in seq]
+        ostate = [(meshes[o], o + 1, cands[o][k]) for o, k in seq]
+        for o in range(3):
+            if o in placed:
+                continue
+            got = ctx.msg_expand(sid, gstate, mids[o], tc[o], label=o + 1)
+            exp = oracle.msg_expand(scene, ostate, meshes[o], cands[o], label=o + 1, threads=THREADS, **kw)
+            check_edges(got, exp, rgb, f"world {seed} state {seq} object {o}")
+            checked += 1
+    ctx.drop_scene(sid)
+    sid = ctx.set_scene(scene.K, scene.depth, None, scene.labels, delta_mm=delta, flags=flags & ~oracle.USE_RGB,
+                        stride=stride)
+    got = ctx.msg_search(sid, [(mids[o], o + 1, tc[o]) for o in range(3)], beam=2)
+    exp = oracle.msg_search(scene, [(meshes[o], o + 1, cands[o]) for o in range(3)], beam=2, delta_mm=delta,
+                            flags=flags & ~oracle.USE_RGB, stride=stride, threads=THREADS)
+    ctx.drop_scene(sid)
+    for m in mids:
+        ctx.unload_mesh(m)
+    assert got == exp, (got, exp)
+    assert checked >= 6
+
+
 def test_search_recovers_the_generating_scene(ctx):
     meshes, scene, gt, cands = _world(seed=2)
     sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, scene.labels, delta_mm=DELTA, tau_c=20.0,
