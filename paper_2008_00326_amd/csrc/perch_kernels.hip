@@ -104,6 +104,26 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, 
     const int ww = i1 - i0 + 1, wh = j1 - j0 + 1;
     const int Z = 16 * d;
     const int lim = s.dq + 1, dq2 = s.dq2;
+    const int ws = ww * wh;
+    if (ws <= 256 && ww <= 64) {
+        // the whole window in at most four row-major rounds of 64 pixels,
+        // every load issued first; (q * ceil(2^16 / ww)) >> 16 is q / ww
+        // exactly for q < 256
+        const uint32_t rc = c_rcp16[ww];
+        int4 q[4];
+        int kk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = 64 * u + lane;
+            const int fy = (int)(((uint32_t)f * rc) >> 16), fx = f - fy * ww;
+            kk[u] = (j0 + fy - jy0) * jw + (i0 + fx - jx0);
+            q[u] = f < ws ? gld(s.opt + (j0 + fy) * s.W + i0 + fx) : make_int4(0, 0, kNoPoint, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (64 * u + lane < ws) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk[u]);
+        return;
+    }
     if (ww <= 64) {
         const uint32_t rc = c_rcp16[ww];
         const int rows = (int)((64u * rc) >> 16);
@@ -131,7 +151,6 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, 
             if (row + u * rows < wh) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk + u * kstep);
         return;
     }
-    const int ws = ww * wh;
     const float inv = 1.0f / (float)ww;
     for (int q0 = 0; q0 < ws; q0 += 256) {
         int px[4], py[4];
