@@ -26,8 +26,8 @@ namespace perch {
 
 // ------------------------------------------------------------------ search
 
-// ceil(2^16 / w) for w = 1..64: lane / w = (lane * c_rcp16[w]) >> 16 exactly
-// for lane < 64.
+// ceil(2^16 / w) for w = 1..64: q / w = (q * c_rcp16[w]) >> 16 exactly for
+// q < 256 (the error term q (c - 2^16 / w) / 2^16 stays below 1 / w).
 __constant__ uint32_t c_rcp16[65] = {
     0,    65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554, 5958, 5462, 5042, 4682, 4370, 4096,
     3856, 3641,  3450,  3277,  3121,  2979,  2850,  2731, 2622, 2521, 2428, 2341, 2260, 2185, 2115, 2048, 1986,
@@ -88,11 +88,12 @@ __device__ __forceinline__ void mark_params(const SceneDev &s, int i, int j, int
 // visits every observed pixel of r's window inside the J_o region: each
 // observed point within delta of r min-combines (d2, k) into its key.  This
 // marks the points that r explains (Eq. 3) and, over all r, leaves each
-// observed point's nearest rendered neighbour (Eq. 4).  The lanes cover
-// whole window rows at a time (64 / width rows per round, so a lane keeps
-// its column and steps its row by a constant), four rounds per iteration
-// with every load issued before use; windows wider than a wave are walked
-// in row-major order, four pixels per lane per round.
+// observed point's nearest rendered neighbour (Eq. 4).  A window of at most
+// 256 pixels goes in at most four row-major rounds of 64, every load issued
+// first; a larger one no wider than a wave in whole rows per round (64 /
+// width rows, a lane keeps its column and steps its row by a constant),
+// four rounds per iteration; a wider one in row-major order, four pixels
+// per lane per round.
 template <bool G>
 __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, int Y, int wuv,
                           typename KeyOf<G>::T *keys, int jx0, int jy0, int jw, int jh, int lane)
