@@ -513,6 +513,7 @@ def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depth
                         volume="label")
     mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in w.meshes]
     icp = dict(rho_mm=20.0, iterations=15, stride=2, dof=6, method=method)
+    streams = [torch.cuda.Stream() for _ in range(4)]
 
     def run():
         t = {}
@@ -532,7 +533,13 @@ def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depth
         a = time.perf_counter()
         best = [torch.topk(c, min(top, c.numel()), largest=False).indices for c in costs]
         cand = [p[b].contiguous() for p, b in zip(props, best)]
-        refined = [ctx.refine_poses(sid, mids[o.mesh], c, label=o.label, **icp)[0] for o, c in zip(w.objects, cand)]
+        # one launch per object holds only `top` poses (a work-group each), so
+        # the objects' refinements go to separate streams and run side by side
+        refined = []
+        for k, (o, c) in enumerate(zip(w.objects, cand)):
+            sk = streams[k % len(streams)]
+            sk.wait_stream(torch.cuda.current_stream())
+            refined.append(ctx.refine_poses(sid, mids[o.mesh], c, label=o.label, stream=sk, **icp)[0])
         torch.cuda.synchronize()
         t["refine"] = time.perf_counter() - a
         a = time.perf_counter()
