@@ -524,10 +524,10 @@ def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depth
         torch.cuda.synchronize()
         t["propose"] = time.perf_counter() - a
         a = time.perf_counter()
-        costs = []
-        for o, p in zip(w.objects, props):
-            jr, jo, _, _ = ctx.score_poses(sid, mids[o.mesh], p, label=o.label, counts=False)
-            costs.append(jr + jo)
+        # every object's proposals in one launch sequence (per-pose costs back)
+        items = ctx.score_batch([{"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": p}
+                                 for o, p in zip(w.objects, props)])
+        costs = [it["jr"] + it["jo"] for it in items]
         torch.cuda.synchronize()
         t["score"] = time.perf_counter() - a
         a = time.perf_counter()
