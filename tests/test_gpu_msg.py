@@ -276,3 +276,27 @@ def test_cfg2_sampled_edges(ctx, volume):
     sub = [np.concatenate([a[sel], b]) for a, b in zip(got, g_gt)]
     check_edges([torch.from_numpy(a) for a in sub], exp, True, f"cfg2 {volume}")
     assert exp[0].sum() > 0 and exp[3].max() > 100
+
+
+def test_cfg2_search_matches_oracle(ctx):
+    """A width-2 search at full resolution: the 640x480 cfg2 scene, its first
+    three objects with six seeded candidates each, depth only with label
+    volumes (exact costs): the oracle's goal and successor count."""
+    w = make_config(2, 0)
+    s = w.scene
+    flags = oracle.MARK_OCCLUDERS | oracle.VOL_LABEL
+    rng = np.random.default_rng(21)
+    objs = w.objects[:3]
+    cands = [np.ascontiguousarray(o.poses[np.sort(rng.choice(o.poses.shape[0], 6, replace=False))]) for o in objs]
+    say("msg cfg2 search, beam 2")
+    sid = ctx.set_scene(s.K, s.depth, None, s.labels, delta_mm=w.delta_mm, flags=flags)
+    mids = [ctx.load_mesh(w.meshes[o.mesh].xyz, w.meshes[o.mesh].tri, None) for o in objs]
+    got = ctx.msg_search(sid, [(m, o.label, _cuda(c)) for m, o, c in zip(mids, objs, cands)], beam=2)
+    for m in mids:
+        ctx.unload_mesh(m)
+    ctx.drop_scene(sid)
+    say(f"  GPU: {got}; oracle search")
+    exp = oracle.msg_search(s, [(w.meshes[o.mesh], o.label, c) for o, c in zip(objs, cands)], beam=2,
+                            delta_mm=w.delta_mm, flags=flags, threads=THREADS)
+    assert got == exp, (got, exp)
+    assert got[0] is not None
