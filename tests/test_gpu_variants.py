@@ -286,3 +286,29 @@ def test_flag_validation(ctx):
         ctx.set_scene(K, depth, search="kd-tree")
     sid = ctx.set_scene(K, depth, flags=pk.VOL_CYL | pk.JO_NN | pk.KNN2 | pk.MARK_OCCLUDERS)
     ctx.drop_scene(sid)
+
+
+def test_knn1_array_beyond_the_budget_is_refused():
+    """kNN I with a distance array larger than the context's HBM budget (a
+    320x240 self-render: 4,798 x 4,798 pairs, 88 MB, against 48 MB): a
+    clean PERCH_ENOMEM naming the array; the context then scores a farther
+    pose, whose array fits, as the oracle does."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from test_oracle_icp import K_HI, _scene_and_gt
+    m, scene, gt = _scene_and_gt(0, K_HI)
+    with pk.Context(0, hbm_budget_bytes=48 << 20) as small:
+        mid = small.load_mesh(m.xyz, m.tri, m.rgb)
+        sid = small.set_scene(scene.K, scene.depth, delta_mm=5.0, mark_occluders=False, search="knn1")
+        say("kNN I under a 48 MB budget")
+        t = torch.from_numpy(gt.reshape(1, 12).astype(np.float32)).cuda()
+        with pytest.raises(pk.PerchError, match="does not fit"):
+            small.score_poses(sid, mid, t)
+        # the context goes on: a pose 3 m further back has a small array
+        far = gt.reshape(1, 12).astype(np.float32).copy()
+        far[0, 11] += 3000.0
+        got = [a.cpu().numpy() for a in small.score_poses(sid, mid, torch.from_numpy(far).cuda())]
+        exp = oracle.score(m, scene, far, delta_mm=5.0, flags=0)
+        for a, b in zip(got, exp):
+            assert np.array_equal(a, b)
+        assert 0 < got[2][0] < 1000
