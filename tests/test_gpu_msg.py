@@ -300,3 +300,38 @@ def test_cfg2_search_matches_oracle(ctx):
                             delta_mm=w.delta_mm, flags=flags, threads=THREADS)
     assert got == exp, (got, exp)
     assert got[0] is not None
+
+
+def test_device_tile_successors_match_oracle(ctx):
+    """Successors whose raster tile exceeds the LDS (an object 170-200 mm from
+    the camera over a 320x240 image) take the device-memory tile: as root
+    edges, as the placed state with the far object behind it, and as
+    successors that would occlude the far object (not monotone)."""
+    from test_oracle_icp import K_HI, _scene_and_gt
+    m, scene, gt = _scene_and_gt(0, K_HI)
+    near = []
+    for tz in (170.0, 200.0):
+        P = gt.reshape(12).astype(np.float32).copy()
+        P[11] = tz
+        near.append(P)
+    near = np.stack(near)
+    far = gt.reshape(1, 12).astype(np.float32)
+    flags = oracle.MARK_OCCLUDERS | oracle.USE_RGB
+    say("msg device-tile successors")
+    sid = ctx.set_scene(scene.K, scene.depth, scene.rgb, delta_mm=5.0, tau_c=20.0, flags=flags)
+    mid = ctx.load_mesh(m.xyz, m.tri, m.rgb)
+    kw = dict(delta_mm=5.0, tau_c=20.0, flags=flags, threads=THREADS)
+    cases = [([], near, "root edges"), ([(near[0], 1)], far, "far object behind a near state"),
+             ([(far[0], 1)], near, "near successors of the far state")]
+    for state, cands, what in cases:
+        got = ctx.msg_expand(sid, [(mid, lab, p) for p, lab in state], mid, _cuda(cands), label=2)
+        exp = oracle.msg_expand(scene, [(m, lab, p) for p, lab in state], m, cands, label=2, **kw)
+        check_edges(got, exp, True, what)
+        if what == "root edges":
+            assert exp[0].all() and exp[3].min() > 20000           # |dR \ C|: tiles beyond the LDS
+        elif what == "far object behind a near state":
+            assert exp[0].all() and exp[2][0] > 0
+        else:
+            assert not exp[0].any()
+    ctx.unload_mesh(mid)
+    ctx.drop_scene(sid)
