@@ -216,3 +216,29 @@ def test_gicp_needs_six_dof(ctx):
         ctx.refine_poses(sid, mid, t, method="surface")
     ctx.drop_scene(sid)
     ctx.unload_mesh(mid)
+
+
+@pytest.mark.parametrize("method", ["point", "plane"])
+def test_device_tile_refinement_matches_oracle(ctx, method):
+    """Poses 200 mm from the camera over a 320x240 image: the raster tile
+    exceeds the LDS, so the ICP kernel renders into its device-memory tile;
+    refined poses, update and match counts equal the oracle's."""
+    from test_oracle_icp import K_HI, _scene_and_gt, _yaw_shift
+    m, _, gt = _scene_and_gt(0, K_HI)
+    P = gt.reshape(12).astype(np.float32).copy()
+    P[11] = 200.0
+    d, _, c = oracle.render(m, P, K_HI)
+    scene = TScene(K_HI, d, c, None)
+    starts = np.stack([_yaw_shift(P, 0.03, 2.0, -1.5), _yaw_shift(P, -0.02, -1.5, 1.0)]).astype(np.float32)
+    say(f"icp device tile: {method}, {int((d > 0).sum())} observed points")
+    sid = ctx.set_scene(K_HI, d, c, delta_mm=5.0, mark_occluders=False)
+    mid = ctx.load_mesh(m.xyz, m.tri, m.rgb)
+    prm = dict(rho_mm=10.0, iterations=5, stride=2, dof=6)
+    got = gpu_refine(ctx, sid, mid, starts, method=method, **prm)
+    ctx.drop_scene(sid)
+    ctx.unload_mesh(mid)
+    run = oracle.gicp if method == "plane" else oracle.icp
+    kw = {} if method == "plane" else {"dof": 6}
+    exp = run(m, scene, starts, delta_mm=5.0, flags=0, rho_mm=10.0, iterations=5, stride=2, threads=THREADS, **kw)
+    check(got, exp, f"device tile {method}")
+    assert exp[2].min() > 1000 and exp[1].min() >= 1
