@@ -266,3 +266,29 @@ def test_best_ties_lowest_index():
     jo = np.array([0, 1, 2, 0, 3], np.int32)
     assert oracle.best(jr, jo) == (1, 4, 4)
     assert oracle.best(np.array([7], np.int32), np.array([0], np.int32)) == (0, 7, 1)
+
+
+def test_rgb_term_separates_objects_of_the_same_shape():
+    """Two boxes of one shape and different colours (Sec. IV-B: depth alone
+    cannot tell same-shape objects apart, the RGB term can): object A costs
+    nothing at either box's pose by depth, and only at its own with colour."""
+    from paper_2008_00326_amd.workloads.scenes import camera_rig, table_pose
+    K = (160, 120, 300.0, 300.0, 80.0, 60.0)
+    rig = camera_rig(800.0, 45.0)
+    a = box((-30, -20, 0), (30, 20, 40), n=3, rgb_seed=1)
+    b = box((-30, -20, 0), (30, 20, 40), n=3, rgb_seed=2)
+    pa = table_pose(rig, -60.0, 0.0, 0.0).reshape(12).astype(np.float32)
+    pb = table_pose(rig, 60.0, 0.0, 0.0).reshape(12).astype(np.float32)
+    da, _, ca = oracle.render(a, pa, K)
+    db, _, cb = oracle.render(b, pb, K)
+    depth = np.where(da > 0, da, db).astype(np.uint16)
+    rgb = np.where((da > 0)[..., None], ca, cb).astype(np.uint8)
+    assert (da > 0).sum() > 500 and (db > 0).sum() > 500 and not ((da > 0) & (db > 0)).any()
+    scene = TScene(K, depth, rgb, None)
+    poses = np.stack([pa, pb])
+    jr, jo, nr, _ = oracle.score(a, scene, poses, delta_mm=5.0, flags=oracle.MARK_OCCLUDERS)
+    assert (jr + jo).tolist() == [0, 0] and nr.min() > 500            # depth: a tie
+    jr, jo, _, _ = oracle.score(a, scene, poses, delta_mm=5.0, tau_c=20.0,
+                                flags=oracle.MARK_OCCLUDERS | oracle.USE_RGB)
+    j = (jr + jo).tolist()
+    assert j[0] == 0 and j[1] > 100                                    # colour breaks it
