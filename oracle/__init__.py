@@ -26,7 +26,9 @@ VOL_LABEL = 2 << 4
 JO_NN = 1 << 6
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# PERCH_ORACLE_LIBRARY selects another build of the same source (the
+# sanitizer test loads an AddressSanitizer / UBSan build this way)
+_LIB_PATH = os.environ.get("PERCH_ORACLE_LIBRARY", os.path.join(_HERE, "liboracle.so"))
 
 
 class _Intrinsics(ctypes.Structure):

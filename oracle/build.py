@@ -24,5 +24,18 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """The same library built with AddressSanitizer and UBSan (host gcc),
+    for the sanitizer test; load it with the ASan runtime preloaded."""
+    src = os.path.join(_HERE, "perch_oracle.c")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           "-o", out, src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
