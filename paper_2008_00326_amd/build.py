@@ -23,7 +23,8 @@ def build_hip(verbose: bool = False) -> str:
            os.path.join(HERE, "csrc", "perch_knn1.hip")]
     tmp = LIB + ".tmp"
     cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *src]
+           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *src,
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

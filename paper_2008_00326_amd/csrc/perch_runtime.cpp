@@ -6,6 +6,7 @@
 #include "perch_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -662,6 +663,20 @@ perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hi
 
 }  // namespace
 
+namespace {
+
+// A roctx range over one entry point (named as the entry point), seen by
+// rocprofv3 --marker-trace; without a profiler attached it is a call that
+// returns at once.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
+}  // namespace
+
 extern "C" {
 
 const char *perch_last_error(void) { return g_last_error.c_str(); }
@@ -742,6 +757,7 @@ perch_status perch_destroy(perch_ctx *ctx)
 perch_status perch_load_mesh(perch_ctx *ctx, const float *xyz, int32_t n_verts, const int32_t *tri,
                              int32_t n_tris, const uint8_t *rgb, int32_t *mesh_id)
 {
+    const Range range_("perch_load_mesh");
     if (perch_status st = enter(ctx)) return st;
     if (!xyz || !tri || !mesh_id) return fail(PERCH_EINVAL, "null xyz, tri or mesh_id");
     if (n_verts < 1) return fail(PERCH_EINVAL, "n_verts must be >= 1 (got %d)", n_verts);
@@ -830,6 +846,7 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id)
 
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t *scene_id)
 {
+    const Range range_("perch_set_scene");
     if (perch_status st = enter(ctx)) return st;
     if (!d || !scene_id) return fail(PERCH_EINVAL, "null descriptor or scene_id");
     const perch_intrinsics &K = d->K;
@@ -1091,6 +1108,7 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
                                const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
                                int32_t *nr_dev, int32_t *nq_dev, void *hip_stream)
 {
+    const Range range_("perch_score_poses");
     if (perch_status st = enter(ctx)) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     {
@@ -1111,6 +1129,7 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
 
 perch_status perch_score_batch(perch_ctx *ctx, const perch_work *items, int32_t n_items, void *hip_stream)
 {
+    const Range range_("perch_score_batch");
     if (perch_status st = enter(ctx)) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     perch_status s = run_direct(ctx, items, n_items, pick_stream(ctx, hip_stream), false);
@@ -1121,6 +1140,7 @@ perch_status perch_best_poses(perch_ctx *ctx, int32_t scene_id, int32_t n_obj, c
                               const int32_t *labels, const float *const *poses_dev, const int32_t *n_poses,
                               int32_t *best_idx_host, int32_t *best_cost_host, void *hip_stream)
 {
+    const Range range_("perch_best_poses");
     if (perch_status st = enter(ctx)) return st;
     if (n_obj < 1) return fail(PERCH_EINVAL, "n_obj must be >= 1");
     if (!mesh_ids || !labels || !poses_dev || !n_poses || !best_idx_host || !best_cost_host)
@@ -1190,6 +1210,7 @@ perch_status perch_refine_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
                                 const float *poses_dev, int32_t n, const perch_icp_params *prm, float *refined_dev,
                                 int32_t *iters_dev, int32_t *matched_dev, void *hip_stream)
 {
+    const Range range_("perch_refine_poses");
     if (perch_status st = enter(ctx)) return st;
     if (!prm) return fail(PERCH_EINVAL, "null ICP parameters");
     if (prm->iterations < 1 || prm->iterations > 1000) return fail(PERCH_EINVAL, "iterations must be in [1, 1000]");
@@ -1310,6 +1331,7 @@ perch_status perch_msg_expand(perch_ctx *ctx, int32_t scene_id, const perch_plac
                               int32_t *valid_dev, int32_t *jr_dev, int32_t *jo_dev, int32_t *nr_dev,
                               int32_t *nq_dev, void *hip_stream)
 {
+    const Range range_("perch_msg_expand");
     if (perch_status st = enter(ctx)) return st;
     if (n < 0 || n_state < 0 || n_state > 32) return fail(PERCH_EINVAL, "n must be >= 0 and n_state in [0, 32]");
     if (n_state > 0 && !state) return fail(PERCH_EINVAL, "null state");
@@ -1381,6 +1403,7 @@ perch_status perch_msg_search(perch_ctx *ctx, int32_t scene_id, const perch_msg_
                               int32_t beam, int32_t *order_host, int32_t *pose_host, int64_t *cost_host,
                               int64_t *scored_host, void *hip_stream)
 {
+    const Range range_("perch_msg_search");
     if (perch_status st = enter(ctx)) return st;
     if (n_obj < 1 || n_obj > 32) return fail(PERCH_EINVAL, "n_obj must be in [1, 32]");
     if (!objects || !order_host || !pose_host || !cost_host) return fail(PERCH_EINVAL, "null argument");
@@ -1528,6 +1551,7 @@ perch_status perch_propose_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_
                                  const perch_proposal_params *prm, float *poses_dev, int32_t capacity, int32_t *n_out,
                                  void *hip_stream)
 {
+    const Range range_("perch_propose_poses");
     if (perch_status st = enter(ctx)) return st;
     if (!prm || !n_out) return fail(PERCH_EINVAL, "null parameters or count");
     if (prm->viewpoints < 1 || prm->inplane < 1 || prm->max_depths < 1)
@@ -1765,6 +1789,7 @@ perch_status perch_batch_set(perch_batch *b, const perch_work *items, int32_t n_
 
 perch_status perch_batch_launch(perch_batch *b, void *hip_stream)
 {
+    const Range range_("perch_batch_launch");
     if (!b) return fail(PERCH_EINVAL, "null batch");
     perch_ctx *ctx = b->ctx;
     if (perch_status st = enter(ctx)) return st;
