@@ -73,6 +73,8 @@ def _load():
         lib.oracle_ciede2000_32.restype = ctypes.c_float
         lib.oracle_score.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P, ctypes.c_int32]
         lib.oracle_score.restype = ctypes.c_int
+        lib.oracle_score_windowed.argtypes = lib.oracle_score.argtypes
+        lib.oracle_score_windowed.restype = ctypes.c_int
         lib.oracle_score_detail.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
         lib.oracle_score_detail.restype = ctypes.c_int
         lib.oracle_best.argtypes = [P, P, ctypes.c_int32, P, P, P]
@@ -182,13 +184,19 @@ def ciede2000_32(lab1, lab2):
 
 
 def score(mesh, scene, poses, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1, label=0,
-          threads=0):
-    """Brute-force J_r, J_o, L, Q for every pose (Eq. 3, Eq. 4).
+          threads=0, search="brute"):
+    """J_r, J_o, L, Q for every pose (Eq. 3, Eq. 4).
 
     poses: n x 12 float32 row-major [R|t], object -> camera, mm.
+    search: "brute" compares every point with the whole other cloud (the
+    definition); "window" only with the pixels of the window that provably
+    holds all its neighbours (same result, for large workloads).
     Returns four int32 arrays (jr, jo, nr, nq).
     """
     lib = _load()
+    if search not in ("brute", "window"):
+        raise ValueError(f"unknown search {search!r}")
+    fn = lib.oracle_score if search == "brute" else lib.oracle_score_windowed
     m = _MeshArgs(mesh)
     s = _SceneArgs(scene, delta_mm, tau_c, flags, stride)
     poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
@@ -197,8 +205,8 @@ def score(mesh, scene, poses, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stri
     jo = np.zeros(n, np.int32)
     nr = np.zeros(n, np.int32)
     nq = np.zeros(n, np.int32)
-    rc = lib.oracle_score(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(poses), n,
-                          _ptr(jr), _ptr(jo), _ptr(nr), _ptr(nq), int(threads))
+    rc = fn(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(poses), n,
+            _ptr(jr), _ptr(jo), _ptr(nr), _ptr(nq), int(threads))
     if rc != 0:
         raise ValueError(f"oracle_score failed ({rc})")
     return jr, jo, nr, nq

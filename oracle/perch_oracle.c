@@ -165,8 +165,16 @@
  * entry table computed in binary64), mapped to XYZ with the four-digit sRGB
  * matrix, and to CIELAB with the white point equal to the matrix row sums
  * (so sRGB white maps to L* = 100, a* = b* = 0).  CIEDE2000 uses
- * kL = kC = kH = 1.  Its rotation term R_T is parity unpinned: the tests pin
- * it only where it vanishes and through symmetry.
+ * kL = kC = kH = 1.  Parity unpinned: the rotation term R_T, the phase
+ * offsets of the hue weighting T (30, 6 and 63 degrees) and the branch that
+ * wraps the mean hue across 0/360 degrees.  The tests pin CIEDE2000 only
+ * where these vanish or cancel (neutral colours, pure chroma on a*, mirror
+ * hue pairs, symmetry), and no published table of test pairs is at hand.
+ *
+ * Search: the counts are defined by brute force (each point against the
+ * whole other cloud).  oracle_score_windowed reaches the same counts by
+ * scanning only the pixels of a window that provably holds every neighbour
+ * (or_window); the tests pin it equal to brute force.
  */
 #include <math.h>
 #include <stdint.h>
@@ -583,6 +591,66 @@ static int or_search(const or_cloud *c, int64_t px, int64_t py, int64_t pz, int6
     return found;
 }
 
+/* Windowed exact search (a faster route to the same result, for large
+ * workloads; the tests pin it equal to or_search).  Every point here is the
+ * back-projection of a pixel centre (i, j) at an integer depth Z mm: in exact
+ * arithmetic X = (i - cx) Z / fx, and the stored 1/16 mm coordinates differ
+ * from the exact ones by at most 1/32 mm per axis.  Two points within dq
+ * (1/16 mm units) therefore lie within e = dq/16 + 1/4 mm of each other
+ * before rounding.  For such a pair (X, Z), (X', Z') with |X' - X|, |Z' - Z|
+ * <= e, Cauchy-Schwarz on (X' - X) Z - X (Z' - Z) gives
+ *   |i' - i| = fx |X'/Z' - X/Z| <= fx e sqrt(1 + ((i - cx)/fx)^2) / (Z - e),
+ * and likewise for rows with fy, cy.  The window below is that bound's
+ * floor plus one pixel (so rounding in binary64 cannot make it too small),
+ * or the whole image when Z - e <= 1 mm. */
+static void or_window(const oracle_intrinsics *K, int64_t dq, int32_t i, int32_t j, int32_t z_mm, int32_t win[4])
+{
+    const int W = K->width, H = K->height;
+    const double e = (double)dq / 16.0 + 0.25;
+    const double den = (double)z_mm - e;
+    int32_t wu = W, wv = H;
+    if (den > 1.0) {
+        const double tx = ((double)i - (double)K->cx) / (double)K->fx;
+        const double ty = ((double)j - (double)K->cy) / (double)K->fy;
+        const double bu = (double)K->fx * e * sqrt(1.0 + tx * tx) / den;
+        const double bv = (double)K->fy * e * sqrt(1.0 + ty * ty) / den;
+        if (bu < (double)W) wu = (int32_t)floor(bu) + 1;
+        if (bv < (double)H) wv = (int32_t)floor(bv) + 1;
+    }
+    win[0] = i - wu < 0 ? 0 : i - wu;
+    win[1] = i + wu > W - 1 ? W - 1 : i + wu;
+    win[2] = j - wv < 0 ? 0 : j - wv;
+    win[3] = j + wv > H - 1 ? H - 1 : j + wv;
+}
+
+/* or_search restricted to the points of cloud c whose pixels lie in the
+ * window win; at[k] is the cloud index of pixel k or -1. */
+static int or_search_window(const or_cloud *c, const int32_t *at, int W, const int32_t win[4], int64_t px,
+                            int64_t py, int64_t pz, int64_t dq2, int64_t dq, int want_nn, int32_t *nn)
+{
+    int found = 0;
+    int64_t best_d2 = 0;
+    int32_t best_pix = 0, best = -1;
+    for (int32_t j = win[2]; j <= win[3]; ++j) {
+        for (int32_t i = win[0]; i <= win[1]; ++i) {
+            const int32_t k = at[(size_t)j * W + i];
+            if (k < 0) continue;
+            int64_t dz = (int64_t)c->z[k] - pz;
+            if (dz > dq || dz < -dq) continue;
+            int64_t dx = (int64_t)c->x[k] - px, dy = (int64_t)c->y[k] - py;
+            int64_t d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 > dq2) continue;
+            if (!want_nn) { if (nn) *nn = k; return 1; }
+            if (!found || d2 < best_d2 || (d2 == best_d2 && c->pix[k] < best_pix)) {
+                best_d2 = d2; best_pix = c->pix[k]; best = k;
+            }
+            found = 1;
+        }
+    }
+    if (nn) *nn = best;
+    return found;
+}
+
 /* The object-frame AABB of a mesh. */
 static void or_mesh_box(const oracle_mesh *m, double lo[3], double hi[3])
 {
@@ -625,7 +693,7 @@ static int or_in_volume(const oracle_scene *sc, int32_t label, const float *pose
  *  r_flag[k]: 0 not in R, 1 inlier, 2 outlier (distance), 3 outlier (colour), 4 occluded
  *  o_flag[k]: 0 not in Vset, 1 explained, 2 outlier (distance), 3 outlier (colour) */
 static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t label,
-                        const float *pose, const or_cloud *obs, int32_t out[4],
+                        const float *pose, const or_cloud *obs, const int32_t *obs_at, int32_t out[4],
                         uint8_t *r_flag, uint8_t *o_flag)
 {
     const oracle_intrinsics *K = &sc->K;
@@ -643,10 +711,12 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     uint16_t *dren = (uint16_t *)malloc(N * sizeof(uint16_t));
     uint8_t *cren = use_rgb ? (uint8_t *)malloc(N * 3) : NULL;
     uint8_t *marked = nn_mark ? (uint8_t *)calloc(obs->n ? (size_t)obs->n : 1, 1) : NULL;
+    int32_t *r_at = obs_at ? (int32_t *)malloc(N * sizeof(int32_t)) : NULL;   /* windowed search: pixel -> R */
     or_cloud R;
-    if (!dren || (use_rgb && !cren) || (nn_mark && !marked) || or_cloud_alloc(&R, N, use_rgb)) {
-        free(dren); free(cren); free(marked); return -2;
+    if (!dren || (use_rgb && !cren) || (nn_mark && !marked) || (obs_at && !r_at) || or_cloud_alloc(&R, N, use_rgb)) {
+        free(dren); free(cren); free(marked); free(r_at); return -2;
     }
+    if (r_at) for (size_t k = 0; k < N; ++k) r_at[k] = -1;
     if (oracle_render(m, pose, K, dren, NULL, cren) != 0) { rc = -1; goto done; }
 
     /* R \ C : rendered, on the stride grid, not occluded (R6, R7). */
@@ -666,6 +736,7 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
             int32_t p[3];
             oracle_backproject(K, i, j, d, p);
             R.x[R.n] = p[0]; R.y[R.n] = p[1]; R.z[R.n] = p[2]; R.pix[R.n] = (int32_t)k;
+            if (r_at) r_at[k] = R.n;
             if (use_rgb) oracle_srgb_to_lab32(cren + 3 * k, R.lab + 3 * (size_t)R.n);
             R.n++;
         }
@@ -675,7 +746,14 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     int32_t jr = 0;
     for (int32_t r = 0; r < R.n; ++r) {
         int32_t nn = -1;
-        int found = or_search(obs, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb || nn_mark, &nn);
+        int found;
+        if (obs_at) {
+            int32_t win[4];
+            or_window(K, dq, R.pix[r] % W, R.pix[r] / W, R.z[r] / 16, win);
+            found = or_search_window(obs, obs_at, W, win, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb || nn_mark, &nn);
+        } else {
+            found = or_search(obs, R.x[r], R.y[r], R.z[r], dq2, dq, use_rgb || nn_mark, &nn);
+        }
         int flag = 1;
         if (!found) flag = 2;
         else if (use_rgb && oracle_ciede2000_32(R.lab + 3 * (size_t)r, obs->lab + 3 * (size_t)nn) > sc->tau_c) flag = 3;
@@ -699,7 +777,14 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
             if (!marked[p]) flag = 2;
         } else {
             int32_t nn = -1;
-            int found = or_search(&R, obs->x[p], obs->y[p], obs->z[p], dq2, dq, use_rgb, &nn);
+            int found;
+            if (obs_at) {
+                int32_t win[4];
+                or_window(K, dq, k % W, k / W, obs->z[p] / 16, win);
+                found = or_search_window(&R, r_at, W, win, obs->x[p], obs->y[p], obs->z[p], dq2, dq, use_rgb, &nn);
+            } else {
+                found = or_search(&R, obs->x[p], obs->y[p], obs->z[p], dq2, dq, use_rgb, &nn);
+            }
             if (!found) flag = 2;
             else if (use_rgb && oracle_ciede2000_32(obs->lab + 3 * (size_t)p, R.lab + 3 * (size_t)nn) > sc->tau_c)
                 flag = 3;
@@ -709,7 +794,7 @@ static int or_score_one(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     }
     out[0] = jr; out[1] = jo; out[2] = R.n; out[3] = q;
 done:
-    free(dren); free(cren); free(marked); or_cloud_free(&R);
+    free(dren); free(cren); free(marked); free(r_at); or_cloud_free(&R);
     return rc;
 }
 
@@ -749,16 +834,23 @@ static int or_observed_cloud(const oracle_scene *sc, or_cloud *obs)
     return 0;
 }
 
-/* Score n poses (n x 12 binary32, row-major [R|t], object -> camera, mm).
- * Outputs jr, jo, nr (= L, the size of R \ C) and nq (= Q, the size of the
- * observed set inside V).  n_threads <= 0 uses the OpenMP default. */
-int oracle_score(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses,
-                 int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, int32_t n_threads)
+/* Score n poses over OpenMP threads, by brute force or windowed search. */
+static int or_score_many(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses,
+                         int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, int32_t n_threads,
+                         int windowed)
 {
     if (n < 0 || !or_scene_valid(m, sc) || m->n_tris > 65536) return -1;
     or_lin32_init();
     or_cloud obs;
     if (or_observed_cloud(sc, &obs)) return -2;
+    int32_t *obs_at = NULL;
+    if (windowed) {
+        const size_t N = (size_t)sc->K.width * sc->K.height;
+        obs_at = (int32_t *)malloc(N * sizeof(int32_t));
+        if (!obs_at) { or_cloud_free(&obs); return -2; }
+        for (size_t k = 0; k < N; ++k) obs_at[k] = -1;
+        for (int32_t p = 0; p < obs.n; ++p) obs_at[obs.pix[p]] = p;
+    }
     int err = 0;
 #ifdef _OPENMP
     int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -766,15 +858,35 @@ int oracle_score(const oracle_mesh *m, const oracle_scene *sc, int32_t label, co
 #endif
     for (int32_t p = 0; p < n; ++p) {
         int32_t out[4] = {0, 0, 0, 0};
-        int rc = or_score_one(m, sc, label, poses + 12 * (size_t)p, &obs, out, NULL, NULL);
+        int rc = or_score_one(m, sc, label, poses + 12 * (size_t)p, &obs, obs_at, out, NULL, NULL);
         if (rc) err |= 1;
         jr[p] = out[0]; jo[p] = out[1];
         if (nr) nr[p] = out[2];
         if (nq) nq[p] = out[3];
     }
     (void)n_threads;
+    free(obs_at);
     or_cloud_free(&obs);
     return err ? -2 : 0;
+}
+
+/* Score n poses by brute force (n x 12 binary32, row-major [R|t], object ->
+ * camera, mm).  Outputs jr, jo, nr (= L, the size of R \ C) and nq (= Q, the
+ * size of the observed set inside V).  n_threads <= 0 uses the OpenMP
+ * default. */
+int oracle_score(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses,
+                 int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, int32_t n_threads)
+{
+    return or_score_many(m, sc, label, poses, n, jr, jo, nr, nq, n_threads, 0);
+}
+
+/* The same counts by the windowed exact search (or_window): each point is
+ * compared only with the other cloud's points whose pixels lie within the
+ * window that provably contains all its neighbours. */
+int oracle_score_windowed(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses,
+                          int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, int32_t n_threads)
+{
+    return or_score_many(m, sc, label, poses, n, jr, jo, nr, nq, n_threads, 1);
 }
 
 /* One pose, with per-pixel classification images (see or_score_one). */
@@ -787,7 +899,7 @@ int oracle_score_detail(const oracle_mesh *m, const oracle_scene *sc, int32_t la
     if (or_observed_cloud(sc, &obs)) return -2;
     size_t N = (size_t)sc->K.width * sc->K.height;
     if (o_flag) memset(o_flag, 0, N);
-    int rc = or_score_one(m, sc, label, pose, &obs, out, r_flag, o_flag);
+    int rc = or_score_one(m, sc, label, pose, &obs, NULL, out, r_flag, o_flag);
     or_cloud_free(&obs);
     return rc;
 }
