@@ -76,13 +76,18 @@ def main():
                     help="launch tuning of the plain path as JSON, e.g. '{\"key_bands\": 1}' (results never change)")
     ap.add_argument("--rates", default="20,50,100", help="config 5: arrival rates, scenes/s")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="config 5: arrival window per rate")
+    ap.add_argument("--served-rate", type=float, default=150.0,
+                    help="arrival rate (scenes/s) of the served leg of a plain run, above the plain path's capacity")
+    ap.add_argument("--served-seconds", type=float, default=8.0, help="arrival window of the served leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg of a plain run")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--volume", choices=["aabb", "cyl", "label"], default=None,
                     help="V(O) of the plain run (default: the workload's)")
     ap.add_argument("--jo", choices=["exact", "nn"], default=None,
                     help="J_o of the plain run: the exact Eq. 3 test or nearest-neighbour marking")
-    ap.add_argument("--search", choices=["table", "knn2"], default="table",
-                    help="J_r neighbour search of the plain run: the scene table or the paper's kNN II scan")
+    ap.add_argument("--search", choices=["table", "hash", "knn2"], default="table",
+                    help="J_r neighbour search of the plain run: the scene table, the voxel hash, or the paper's "
+                         "kNN II scan")
     ap.add_argument("--poses-per-object", type=int, default=0,
                     help="score only the first N candidates of each object (0 = all)")
     ap.add_argument("--no-refine", action="store_true", help="skip the ICP refine-and-rescore leg of a plain run")
@@ -96,7 +101,8 @@ def main():
                     help="add the search comparison leg: this many poses per object scored with the neighbour "
                          "table, the paper's kNN II scan and its kNN I distance array (0 = skip)")
     ap.add_argument("--msg-beam", type=int, default=4, help="states kept per level by the tree leg's search")
-    ap.add_argument("--cpu-sample", type=int, default=320, help="poses the CPU oracle scores for the baseline")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="poses per object the CPU oracle scores for the baseline (0 = every candidate)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -289,6 +295,17 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     ctx.close()
+    if not args.no_served:
+        r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0)
+        top = r["rates"][str(args.served_rate)]
+        result["served"] = {"workload": r["workload"], "rate_scenes_per_s": args.served_rate,
+                            "seconds": args.served_seconds,
+                            "served_poses_per_s": top["served"]["poses_per_s"],
+                            "plain_poses_per_s": top["plain"]["poses_per_s"], "vs_plain": top["vs_plain"],
+                            "latency_ms": {"served": top["served"]["latency_ms"], "plain": top["plain"]["latency_ms"]},
+                            "offered_poses_per_s": top["offered_poses_per_s"],
+                            "kernel_bound_poses_per_s": r.get("kernel_bound_poses_per_s"),
+                            "detail": top}
     print(json.dumps(result), flush=True)
 
 
@@ -626,6 +643,17 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
         ref = plain()
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / steps
+    # the plain loop's GPU busy time (every kernel bracketed by HIP events on
+    # the launch stream; nothing overlaps in this loop): wall / busy bounds
+    # what any batching or overlap of the same kernels can gain
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    traced_s = time.perf_counter() - t0
+    busy_ms = sum(v[0] for v in ctx.profile_read().values())
+    ctx.profile(False)
 
     b = ctx.batch(max_items=len(items), max_poses=n_poses, max_image_pixels=640 * 480)
     b.set(items)
@@ -654,6 +682,8 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
             "plain_poses_per_s": round(n_poses / plain_s, 1), "plain_ms_per_step": round(plain_s * 1e3, 3),
             "batched_poses_per_s": round(n_poses / batched_s, 1), "batched_ms_per_step": round(batched_s * 1e3, 3),
             "vs_plain": round(plain_s / batched_s, 3), "identical_best_poses": got == ref,
+            "plain_gpu_busy_frac": round(busy_ms / 1e3 / traced_s, 4),
+            "vs_plain_bound": round(traced_s / max(busy_ms / 1e3, 1e-9), 3),
             "tuning": tuned["tuning"], "tuning_key": tuned["key"], "tuning_cached": tuned["cached"],
             "tuning_default_ms": tuned.get("default_ms"), "tuning_best_ms": tuned.get("ms"),
             "kernels_ms": {k: round(v[0] / max(steps, 1), 4) for k, v in prof.items() if v[1]}}
@@ -676,18 +706,27 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
     _log(f"[bench] served: generating a pool of {pool_size} scenes")
     pool = [make_config(3, seed + k) for k in range(pool_size)]
     ctx = pk.Context(0)
-    # reference answers, each scene scored alone
+    # reference answers, each scene scored alone; the GPU busy time of
+    # preparing and scoring a scene (every kernel timed by HIP events) bounds
+    # the throughput any serving schedule can reach
     ref = []
+    busy_ms = 0.0
     for w in pool:
+        ctx.profile(True)
         sid, mids = pk.load_workload(ctx, w)
         polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
         bi, bc = ctx.best_poses(sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects], polys)
+        busy_ms += sum(v[0] for v in ctx.profile_read().values())
+        ctx.profile(False)
         ref.append([(int(a), int(b)) for a, b in zip(bi, bc)])
         ctx.drop_scene(sid)
         for m in mids:
             ctx.unload_mesh(m)
     out = {"workload": f"cfg5-served (Poisson arrivals of 6-DoF 640x480 scenes, pool of {pool_size}, seed {seed})",
-           "seconds": seconds, "drain_s": drain_s, "rates": {}}
+           "seconds": seconds, "drain_s": drain_s, "rates": {},
+           "gpu_busy_ms_per_scene": round(busy_ms / pool_size, 3),
+           "kernel_bound_poses_per_s": round(float(np.mean([w.n_poses for w in pool])) / (busy_ms / pool_size) * 1e3,
+                                             1)}
     rng = np.random.default_rng(5000 + seed)
     for rate in rates:
         n = int(rng.poisson(rate * seconds))
@@ -788,27 +827,45 @@ def measured_traffic(kernel_slot):
     return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"], 1)
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(w, sample):
-    """The CPU oracle, as it stands, on a bounded sample of the same workload."""
+    """The CPU oracle, as it stands, on the same workload: its windowed exact
+    search (pinned equal to brute force) over every candidate of every object
+    when `sample` is 0, else over `sample` seeded poses per object, on every
+    thread its OpenMP runtime uses."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    threads = oracle.threads()
     rng = np.random.default_rng(12345)
-    per = max(1, min(sample // len(w.objects), min(o.poses.shape[0] for o in w.objects)))
     flags = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0)
     flags |= {"aabb": oracle.VOL_AABB, "cyl": oracle.VOL_CYL, "label": oracle.VOL_LABEL}[w.volume]
     flags |= oracle.JO_NN if w.jo == "nn" else 0
     n = 0
     t0 = time.perf_counter()
     for o in w.objects:
-        sel = np.sort(rng.choice(o.poses.shape[0], per, replace=False))
+        sel = (np.arange(o.poses.shape[0]) if sample <= 0 else
+               np.sort(rng.choice(o.poses.shape[0], min(sample, o.poses.shape[0]), replace=False)))
         m = w.meshes[o.mesh]
         oracle.score(m, w.scene, o.poses[sel], delta_mm=w.delta_mm, tau_c=w.tau_c, flags=flags, stride=w.stride,
-                     label=o.label, threads=threads)
+                     label=o.label, search="window")
         n += len(sel)
     dt = time.perf_counter() - t0
+    what = "every candidate" if sample <= 0 else f"{sample} seeded candidates per object"
     return {"value": round(n / dt, 3), "unit": "poses/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} poses ({per} per object, seeded uniform) of the same workload, brute-force Eq.3/Eq.4, "
-                      f"{dt:.1f} s"}
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{n} poses ({what}) of the same workload, the oracle's windowed exact search "
+                      f"(equal to brute force, Eq. 3 / Eq. 4), {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -81,6 +81,16 @@ typedef struct perch_ctx perch_ctx;
                                     * (Sec. IV-A): each rendered point scans the whole observed cloud
                                     * instead of reading the scene's neighbour table.  Same results;
                                     * orders of magnitude slower (an in-house comparison baseline) */
+#define PERCH_HASH (1u << 9)       /* J_r's nearest observed neighbours through a uniform-grid voxel
+                                    * hash of the observed cloud (the search structure for the radius
+                                    * test of Eq. 2; the CPU original searched a k-d tree per cloud):
+                                    * cells of edge 2^k >= delta (1/16 mm units), cell coordinates
+                                    * hashed into 2^m buckets (2^m >= 2 W H), the points of each bucket
+                                    * stored contiguously (count, exclusive scan, scatter at set-up);
+                                    * a query scans the buckets of the 27 cells around its point.  The
+                                    * scene then holds no nearest-neighbour table (a fraction of the
+                                    * device memory); results are identical, ties to the lower pixel
+                                    * index as everywhere.  Not combined with PERCH_KNN1 / PERCH_KNN2 */
 #define PERCH_KNN1 (1u << 8)       /* Both searches by the paper's kNN I (Sec. IV-A): every distance
                                     * between a pose's rendered points and the observed cloud goes
                                     * into one L x I array (4 bytes a pair) that is then reduced by
@@ -102,7 +112,7 @@ typedef struct {
     float delta_mm;           /* sensor resolution delta, 0 < delta <= 500 */
     float tau_c;              /* CIEDE2000 threshold tau_c >= 0, used with PERCH_USE_RGB */
     uint32_t flags;           /* PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_* | PERCH_JO_NN | PERCH_KNN2 |
-                                 PERCH_KNN1 */
+                                 PERCH_KNN1 | PERCH_HASH */
     int32_t stride;           /* image-space downsampling of the render, >= 1 (Sec. IV-A) */
 } perch_scene_desc;
 
@@ -158,6 +168,24 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
                                const float *poses_dev, int32_t n, int32_t *jr_dev,
                                int32_t *jo_dev, int32_t *nr_dev, int32_t *nq_dev,
                                void *hip_stream);
+
+/* perch_score_poses with the decision behind every count (Eq. 3, Eq. 4),
+ * for inspection and testing: the same kernels score the n poses and also
+ * write, per pose, two H*W uint8 images (device, caller-owned, n*H*W bytes
+ * each, cleared by the call):
+ *   rflag_dev: each rendered pixel -- 0 not in R (empty or off the stride
+ *              grid), 1 inlier, 2 no observed point within delta, 3 nearest
+ *              observed point within delta but CIEDE2000 above tau_c,
+ *              4 occluder (dropped, Eq. 3's C)
+ *   oflag_dev: each observed pixel -- 0 outside V(O), 1 explained, 2 no
+ *              rendered point within delta, 3 nearest rendered point within
+ *              delta but CIEDE2000 above tau_c (with PERCH_JO_NN: 1 marked,
+ *              2 not)
+ * 1 <= n <= 256.  Asynchronous on hip_stream; PERCH_KNN1 scenes are refused. */
+perch_status perch_score_detail(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
+                                int32_t *nr_dev, int32_t *nq_dev, uint8_t *rflag_dev, uint8_t *oflag_dev,
+                                void *hip_stream);
 
 /* One slice of a launch: the candidate poses of one object in one scene.
  * Pointers as in perch_score_poses; n_poses may be 0. */

@@ -77,6 +77,8 @@ def _load():
         lib.oracle_score_windowed.restype = ctypes.c_int
         lib.oracle_score_detail.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
         lib.oracle_score_detail.restype = ctypes.c_int
+        lib.oracle_score_detail_windowed.argtypes = lib.oracle_score_detail.argtypes
+        lib.oracle_score_detail_windowed.restype = ctypes.c_int
         lib.oracle_best.argtypes = [P, P, ctypes.c_int32, P, P, P]
         lib.oracle_icp.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32]
@@ -89,6 +91,8 @@ def _load():
                                           P, P, P, P, P, ctypes.c_int32]
         lib.oracle_msg_expand.restype = ctypes.c_int
         lib.oracle_best.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -183,6 +187,11 @@ def ciede2000_32(lab1, lab2):
     return float(lib.oracle_ciede2000_32(_ptr(a), _ptr(b)))
 
 
+def threads():
+    """Threads the oracle's OpenMP loops use when none is asked for."""
+    return int(_load().oracle_threads())
+
+
 def score(mesh, scene, poses, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1, label=0,
           threads=0, search="brute"):
     """J_r, J_o, L, Q for every pose (Eq. 3, Eq. 4).
@@ -213,14 +222,18 @@ def score(mesh, scene, poses, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stri
 
 
 def score_detail(mesh, scene, pose, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS, stride=1,
-                 label=0):
+                 label=0, search="brute"):
     """One pose with per-pixel classes.
 
     Returns ((jr, jo, L, Q), r_flag, o_flag) where r_flag is 0 not rendered,
     1 inlier, 2 distance outlier, 3 colour outlier, 4 occluded; o_flag is 0
-    outside V, 1 explained, 2 distance outlier, 3 colour outlier.
+    outside V, 1 explained, 2 distance outlier, 3 colour outlier.  search:
+    "brute" or "window", as for score().
     """
     lib = _load()
+    if search not in ("brute", "window"):
+        raise ValueError(f"unknown search {search!r}")
+    fn = lib.oracle_score_detail if search == "brute" else lib.oracle_score_detail_windowed
     m = _MeshArgs(mesh)
     s = _SceneArgs(scene, delta_mm, tau_c, flags, stride)
     pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
@@ -228,8 +241,7 @@ def score_detail(mesh, scene, pose, *, delta_mm, tau_c=0.0, flags=MARK_OCCLUDERS
     out = np.zeros(4, np.int32)
     rf = np.zeros((H, W), np.uint8)
     of = np.zeros((H, W), np.uint8)
-    rc = lib.oracle_score_detail(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(pose),
-                                 _ptr(out), _ptr(rf), _ptr(of))
+    rc = fn(ctypes.byref(m.s), ctypes.byref(s.s), int(label), _ptr(pose), _ptr(out), _ptr(rf), _ptr(of))
     if rc != 0:
         raise ValueError(f"oracle_score_detail failed ({rc})")
     return tuple(int(v) for v in out), rf, of

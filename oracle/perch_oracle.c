@@ -834,6 +834,16 @@ static int or_observed_cloud(const oracle_scene *sc, or_cloud *obs)
     return 0;
 }
 
+/* Threads an OpenMP parallel loop of this library uses by default. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Score n poses over OpenMP threads, by brute force or windowed search. */
 static int or_score_many(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *poses,
                          int32_t n, int32_t *jr, int32_t *jo, int32_t *nr, int32_t *nq, int32_t n_threads,
@@ -890,18 +900,41 @@ int oracle_score_windowed(const oracle_mesh *m, const oracle_scene *sc, int32_t 
 }
 
 /* One pose, with per-pixel classification images (see or_score_one). */
-int oracle_score_detail(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
-                        int32_t out[4], uint8_t *r_flag, uint8_t *o_flag)
+static int or_detail(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
+                     int32_t out[4], uint8_t *r_flag, uint8_t *o_flag, int windowed)
 {
     if (!or_scene_valid(m, sc) || m->n_tris > 65536) return -1;
     or_lin32_init();
     or_cloud obs;
     if (or_observed_cloud(sc, &obs)) return -2;
     size_t N = (size_t)sc->K.width * sc->K.height;
+    int32_t *obs_at = NULL;
+    if (windowed) {
+        obs_at = (int32_t *)malloc(N * sizeof(int32_t));
+        if (!obs_at) { or_cloud_free(&obs); return -2; }
+        for (size_t k = 0; k < N; ++k) obs_at[k] = -1;
+        for (int32_t p = 0; p < obs.n; ++p) obs_at[obs.pix[p]] = p;
+    }
     if (o_flag) memset(o_flag, 0, N);
-    int rc = or_score_one(m, sc, label, pose, &obs, NULL, out, r_flag, o_flag);
+    int rc = or_score_one(m, sc, label, pose, &obs, obs_at, out, r_flag, o_flag);
+    free(obs_at);
     or_cloud_free(&obs);
     return rc;
+}
+
+/* One pose, with per-pixel classification images (see or_score_one), by
+ * brute force. */
+int oracle_score_detail(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
+                        int32_t out[4], uint8_t *r_flag, uint8_t *o_flag)
+{
+    return or_detail(m, sc, label, pose, out, r_flag, o_flag, 0);
+}
+
+/* The same by the windowed exact search. */
+int oracle_score_detail_windowed(const oracle_mesh *m, const oracle_scene *sc, int32_t label, const float *pose,
+                                 int32_t out[4], uint8_t *r_flag, uint8_t *o_flag)
+{
+    return or_detail(m, sc, label, pose, out, r_flag, o_flag, 1);
 }
 
 /* ------------------------------------------------------------------ */

@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["Context", "PerchError", "load_library", "library_path", "USE_RGB", "MARK_OCCLUDERS",
-           "VOL_AABB", "VOL_CYL", "VOL_LABEL", "JO_NN", "KNN2", "KNN1"]
+           "VOL_AABB", "VOL_CYL", "VOL_LABEL", "JO_NN", "KNN2", "KNN1", "HASH"]
 
 USE_RGB = 1
 MARK_OCCLUDERS = 2
@@ -24,9 +24,10 @@ VOL_LABEL = 2 << 4
 JO_NN = 1 << 6
 KNN2 = 1 << 7
 KNN1 = 1 << 8
+HASH = 1 << 9
 _VOLUMES = {"aabb": VOL_AABB, "cyl": VOL_CYL, "label": VOL_LABEL}
 _JO_MODES = {"exact": 0, "nn": JO_NN}
-_SEARCHES = {"table": 0, "knn2": KNN2, "knn1": KNN1}
+_SEARCHES = {"table": 0, "knn2": KNN2, "knn1": KNN1, "hash": HASH}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _STATUS = {0: "PERCH_OK", -1: "PERCH_EINVAL", -2: "PERCH_ENOMEM", -3: "PERCH_EDEVICE",
@@ -111,6 +112,7 @@ def load_library():
         "perch_set_scene": ([P, P, P], ctypes.c_int),
         "perch_drop_scene": ([P, I32], ctypes.c_int),
         "perch_score_poses": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP], ctypes.c_int),
+        "perch_score_detail": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP, VP, VP], ctypes.c_int),
         "perch_best_poses": ([P, I32, I32, P, P, P, P, P, P, VP], ctypes.c_int),
         "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
         "perch_refine_poses": ([P, I32, I32, I32, VP, I32, P, VP, VP, VP, VP], ctypes.c_int),
@@ -169,6 +171,7 @@ class Context:
         _check(self._lib.perch_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
         self._h = h
         self.device = device
+        self._scene_size = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -207,9 +210,11 @@ class Context:
         jo: "exact" (any rendered point within delta explains an observed
         point) or "nn" (only the points that are some inlier's nearest
         neighbour are explained); search: "table" (the scene's neighbour
-        table), "knn2" (the paper's scan of the whole cloud, a slow
-        baseline with the same results) or "knn1" (the paper's full
-        distance array, one pose at a time, scored by score_poses only).  `flags`, when given, overrides
+        table), "hash" (a uniform-grid voxel hash of the observed cloud:
+        the same results, a fraction of the scene memory), "knn2" (the
+        paper's scan of the whole cloud, a slow baseline with the same
+        results) or "knn1" (the paper's full distance array, one pose at a
+        time, scored by score_poses only).  `flags`, when given, overrides
         use_rgb, mark_occluders, volume, jo and search."""
         depth = np.ascontiguousarray(depth, np.uint16)
         rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
@@ -228,10 +233,12 @@ class Context:
                           int(flags), int(stride))
         sid = ctypes.c_int32()
         _check(self._lib.perch_set_scene(self._h, ctypes.byref(desc), ctypes.byref(sid)))
+        self._scene_size[sid.value] = (int(w), int(h))
         return sid.value
 
     def drop_scene(self, scene_id: int):
         _check(self._lib.perch_drop_scene(self._h, int(scene_id)))
+        self._scene_size.pop(int(scene_id), None)
 
     def scene_info(self, scene_id: int) -> dict:
         """HBM footprint, neighbour-table size, search windows and tile classes of a scene."""
@@ -260,6 +267,26 @@ class Context:
                                            _dev_ptr(jr), _dev_ptr(jo), _dev_ptr(nr), _dev_ptr(nq),
                                            _stream_ptr(stream)))
         return jr, jo, nr, nq
+
+    def score_detail(self, scene_id, mesh_id, poses, *, label=0, stream=None):
+        """perch_score_detail: scores and per-pixel classes of up to 256 poses.
+        Returns (jr, jo, nr, nq, rflag, oflag) CUDA tensors; rflag / oflag are
+        (n, H, W) uint8.  Asynchronous."""
+        import torch
+        if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
+            raise ValueError("poses must be a contiguous float32 CUDA tensor")
+        n = poses.numel() // 12
+        W, H = self._scene_size[int(scene_id)]
+        jr = torch.empty(n, dtype=torch.int32, device=poses.device)
+        jo, nr, nq = torch.empty_like(jr), torch.empty_like(jr), torch.empty_like(jr)
+        rflag = torch.empty((n, H, W), dtype=torch.uint8, device=poses.device)
+        oflag = torch.empty_like(rflag)
+        if stream is None:
+            stream = torch.cuda.current_stream(poses.device)
+        _check(self._lib.perch_score_detail(self._h, int(scene_id), int(mesh_id), int(label), _dev_ptr(poses), n,
+                                            _dev_ptr(jr), _dev_ptr(jo), _dev_ptr(nr), _dev_ptr(nq), _dev_ptr(rflag),
+                                            _dev_ptr(oflag), _stream_ptr(stream)))
+        return jr, jo, nr, nq, rflag, oflag
 
     def best_poses(self, scene_id, mesh_ids, labels, poses_list, stream=None):
         """Per object (mesh_ids[k], labels[k], poses_list[k] CUDA tensor): the

@@ -412,4 +412,45 @@ __device__ __forceinline__ int clamp_i32(int x, int lo, int hi)
     return r;
 }
 
+// ------------------------------------------------------------------ voxel hash
+
+// Bucket of voxel cell (cx, cy, cz): the spatial hash of Teschner et al.
+// (2003), three large primes xor-combined, masked to 2^bits buckets.
+__device__ __forceinline__ int cell_bucket(int cx, int cy, int cz, int bits)
+{
+    const uint32_t h = ((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u);
+    return (int)(h & ((1u << bits) - 1u));
+}
+
+// Nearest observed point within delta of (X, Y, Z) (1/16 mm) through the
+// scene's voxel hash: the cells are at least delta wide, so every neighbour
+// lies in one of the 27 cells around the point's own.  Smallest (d^2,
+// pixel index), or -1.  Cells that share a bucket make the scan visit
+// extra points, which the distance test rejects; a bucket scanned twice
+// changes no minimum.
+__device__ __noinline__ int hash_nn(const SceneDev &s, int X, int Y, int Z)
+{
+    const int lim = s.dq + 1, dq2 = s.dq2;
+    const int cx = X >> s.hshift, cy = Y >> s.hshift, cz = Z >> s.hshift;
+    int best = dq2 + 1, nn = -1;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int b = cell_bucket(cx + dx, cy + dy, cz + dz, s.hbits);
+                const int e = gld(s.hstart + b + 1);
+                for (int k = gld(s.hstart + b); k < e; ++k) {
+                    const int4 q = gld(s.hpts + k);
+                    const int ox = clamp_i32(q.x - X, -lim, lim);
+                    const int oy = clamp_i32(q.y - Y, -lim, lim);
+                    const int oz = clamp_i32(q.z - Z, -lim, lim);
+                    const int d2 = __mul24(ox, ox) + __mul24(oy, oy) + __mul24(oz, oz);
+                    if (d2 < best || (d2 == best && q.w < nn)) {
+                        best = d2;
+                        nn = q.w;
+                    }
+                }
+            }
+    return nn;
+}
+
 }  // namespace perch

@@ -375,11 +375,13 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
     const int gap = a.rq >> 4;
     const bool mark = (s.flags & 2u) != 0;
     const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
-    for (;;) {
-        if (tid == 0) s_pose = atomicAdd(a.cursor, 1);
-        __syncthreads();
-        const int p = s_pose;
-        if (p >= a.n) break;
+    // Poses come through the cursor.  The loop is rotated by hand so that
+    // its condition is a wave-uniform value (readfirstlane of the LDS copy)
+    // and no branch on the thread index heads it; every exit from the
+    // iteration loop below tests a readfirstlane value too.
+    if (tid == 0) s_pose = atomicAdd(a.cursor, 1);
+    __syncthreads();
+    for (int p = __builtin_amdgcn_readfirstlane(s_pose); p < a.n;) {
         float P[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) P[k] = a.poses[12 * (size_t)p + k];
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             }
         }
         __syncthreads();
-        const int ns = s_n;
+        const int ns = __builtin_amdgcn_readfirstlane(s_n);
         double u[3] = {0.0, 0.0, 0.0};
         int iters = 0, matched = 0;
         if (tid == 0) {
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             }
             if (ch) s_changed = 1;
             __syncthreads();
-            if (!s_changed) break;
+            if (!__builtin_amdgcn_readfirstlane(s_changed)) break;
             long long acc = 0;
             for (int t = wave; t < ns; t += NW) {
                 const int4 q = qb[t];
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
                 s_stop = stop;
             }
             __syncthreads();
-            if (s_stop) break;
+            if (__builtin_amdgcn_readfirstlane(s_stop)) break;
             if (gicp) {
                 // second pass: the Gauss-Newton terms of every match, one
                 // wave per match, lane j summing term j
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
                     s_stop = stop;
                 }
                 __syncthreads();
-                if (s_stop) break;
+                if (__builtin_amdgcn_readfirstlane(s_stop)) break;
             }
         }
         if (tid == 0) {
@@ -590,8 +592,10 @@ __global__ __launch_bounds__(BLOCK) void icp_kernel(IcpArgs a)
             }
             if (a.iters) a.iters[p] = iters;
             if (a.matched) a.matched[p] = matched;
+            s_pose = atomicAdd(a.cursor, 1);
         }
         __syncthreads();
+        p = __builtin_amdgcn_readfirstlane(s_pose);
     }
 }
 

@@ -43,8 +43,11 @@ struct SceneDev {
     const double *ky;        // H: 16 (j - cy) / fy
     const float *ax;         // W: f (delta + 1/4) sqrt(1 + ((i - cx) / fx)^2), rounded up
     const float *ay;         // H: the same for rows
-    const int2 *thdr;        // H*W nearest-neighbour table header: {first entry, lo | n << 16}
+    const int2 *thdr;        // H*W nearest-neighbour table header: {first entry, lo | n << 16} (null: hash)
     const int32_t *tnn;      // entry (pixel, lo + e): nearest observed pixel within delta, -1 none
+    const int *hstart;       // voxel hash (hash scenes): 2^hbits + 1 bucket starts into hpts
+    const int4 *hpts;        // observed points (Xq, Yq, Zq, pixel) grouped by bucket
+    int hshift, hbits;       // cell edge 2^hshift (1/16 mm units, >= dq); 2^hbits buckets
     int W, H;
     int wtx, wty;            // window half-sizes that contain every neighbour pair of the scene
     float fx, fy, cx, cy;
@@ -71,6 +74,7 @@ struct ItemDev {
     int vbox[4];             // label mode: x0, y0, w, h of the label's pixels
     const float *poses;      // n * 12
     int32_t *jr, *jo, *nr, *nq;
+    uint8_t *rflag, *oflag;  // per pose a W*H image of each pixel's class (inspection), or null
 };
 
 struct LaunchHdr {
@@ -125,6 +129,11 @@ hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, lon
 // Block sums the table scan needs (long long each).
 int table_scan_blocks(int n_pixels);
 hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
+constexpr uint32_t kHashFlag = 1u << 9;   // PERCH_HASH
+// Uniform-grid voxel hash of the observed cloud: count points per bucket,
+// exclusive scan into s.hstart (2^hbits + 1 ints), scatter into s.hpts.
+// count: 2^hbits ints of work space; blk: table_scan_blocks(2^hbits) long longs.
+hipError_t launch_hash_build(const SceneDev &s, int *count, long long *blk, hipStream_t st);
 // A launch: zero the counters, classify every pose (grid sized for
 // `poses_grid` poses; the kernels read the real count from the header) and,
 // with w.sort, order each class list by cost bucket; run the four scoring

@@ -22,6 +22,7 @@
 
 #include <math.h>
 
+
 namespace perch {
 
 // ------------------------------------------------------------------ search
@@ -248,16 +249,29 @@ __device__ __forceinline__ int wave_popc(bool pred)
     return __popcll(__ballot(pred));
 }
 
+// Number of lanes below this one whose bit is set in mask m.
+__device__ __forceinline__ int lane_rank(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Make the LDS writes of a wave visible to all its lanes.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ------------------------------------------------------------------ per pose
 
 template <int BLOCK, bool G, bool KG, bool RGB, bool PV>
 __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<KG>::T *keys, float4 *labs, int *cnt,
-                           int *queue, int *queue2, int *mx, int *my, int *mw, int *qn)
+                           int2 *wq)
 {
     using K = KeyOf<KG>;
-    constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const PoseInfo in = w.info[p];
     const ItemDev &it = w.items[in.item];
     const SceneDev &s = w.scenes[it.scene];
@@ -268,6 +282,11 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     for (int k = 0; k < 12; ++k) P[k] = it.poses[12 * (size_t)in.local + k];
     const int tpx = in.tw * in.th;
     const int jpx = in.jw * in.jh;
+    // class images of the inspection entry point: rendered pixels 1 inlier,
+    // 2 no neighbour, 3 colour mismatch, 4 occluded; observed pixels of V(O)
+    // 1 explained, 2 no neighbour, 3 colour mismatch
+    uint8_t *const rf = it.rflag ? it.rflag + (size_t)in.local * s.W * s.H : nullptr;
+    uint8_t *const of = it.oflag ? it.oflag + (size_t)in.local * s.W * s.H : nullptr;
     const bool mark = (s.flags & 2u) != 0;
     const bool label_mode = (s.flags & (3u << 4)) == (2u << 4);
     const bool cyl = (s.flags & (3u << 4)) == (1u << 4);
@@ -276,6 +295,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     // and no colour test of its own.  Its poses are never banded.
     const bool nnm = PV && (s.flags & 64u) != 0;
     const bool knn2 = PV && (s.flags & 128u) != 0;     // J_r neighbours by the kNN II scan
+    const bool hsh = PV && (s.flags & kHashFlag) != 0; // J_r neighbours through the voxel hash
     uint32_t *bits = reinterpret_cast<uint32_t *>(keys);
     const bool ocol = rgb && !nnm;
 
@@ -323,7 +343,10 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     const int pix = j * s.W + i;
                     const int dob = gld(s.depth + pix);
                     if (dob > 0 && 16 * dob + s.dq < 16 * d) {
-                        if (!(label_mode && s.labels) || s.labels[pix] != it.label) keep = false;
+                        if (!(label_mode && s.labels) || s.labels[pix] != it.label) {
+                            keep = false;
+                            if (rf) rf[pix] = 4;
+                        }
                     }
                 }
                 if (!keep) tst<G>(tile + k, kEmptyKey);
@@ -342,6 +365,12 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     const int nb = in.jh > 0 ? (in.jh + hb - 1) / hb : 1;
     int cR = 0, cQ = 0, cO = 0;
     const double dl = (double)s.delta;
+    // Phases 3 and 4 run without work-group barriers: each wave takes
+    // 64-pixel blocks in turn and appends its work (inliers to mark and to
+    // colour-test, explained observed points to colour-test) to its own
+    // queue `q` of 128 entries in LDS, flushed 64 at a time -- a colour
+    // test per lane, marking one inlier at a time with the whole wave.
+    int2 *const q = wq + wave * 128;
     for (int b = 0; b < nb; ++b) {
         const bool first = b == 0;
         const int by0 = in.jy0 + b * hb;
@@ -353,100 +382,123 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             __syncthreads();
         }
 
-        // 3. J_r: nearest observed neighbour from the scene table.  The
-        //    inliers of each chunk go to a workgroup queue: every wave takes
-        //    queue items in turn and marks the observed points each one
-        //    explains, then the colour test of Eq. 4 runs densely over the queue.
-        for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
-            const int k = k0 + tid;
-            if (tid == 0) *qn = 0;
-            __syncthreads();
-            bool miss = false;
+        // 3. J_r: nearest observed neighbour from the scene table (or the
+        //    kNN II scan).  Queued inliers are colour-tested (Eq. 4, first
+        //    band) and mark the observed points they explain.
+        auto flush_r = [&](int n) {
+            wave_lds_sync();
+            int kk = 0, nn = -1, ei = 0, ej = 0, ed = 0, tri = 0;
+            if (lane < n) {
+                const int2 e = q[lane];
+                kk = e.x;
+                nn = e.y;
+                const uint32_t key = tld<G>(tile + kk);
+                const int ty = kk / in.tw, tx = kk - ty * in.tw;
+                ei = in.tx0 + tx;
+                ej = in.ty0 + ty;
+                ed = (int)(key >> 16);
+                tri = (int)(key & 0xFFFFu);
+            }
+            if (rgb && first) {
+                bool out = false;
+                if (lane < n) {
+                    const float4 lr = srgb_to_lab(triangle_colour(s, m, P, tri, ei, ej));
+                    if (labs) labs[kk] = lr;     // kept for the J_o test of the points this inlier keys
+                    out = ciede2000(lr, gld(s.olab + nn)) > s.tau;
+                    if (nnm && !out) mark_nn<KG>(bits, nn, s.W, in.jx0, in.jy0, in.jw, in.jh);
+                    if (rf) rf[ej * s.W + ei] = out ? 3 : 1;
+                }
+                cR += wave_popc(out);
+            }
+            if (bpx > 0 && !nnm) {
+                int X = 0, Y = 0, wuv = 0;
+                if (lane < n) mark_params(s, ei, ej, ed, &X, &Y, &wuv);
+                for (int t = 0; t < n; ++t)
+                    wave_mark<KG>(s, __builtin_amdgcn_readlane(ei, t), __builtin_amdgcn_readlane(ej, t),
+                                  __builtin_amdgcn_readlane(ed, t), __builtin_amdgcn_readlane(kk, t),
+                                  __builtin_amdgcn_readlane(X, t), __builtin_amdgcn_readlane(Y, t),
+                                  __builtin_amdgcn_readlane(wuv, t), keys, in.jx0, by0, in.jw, bh, lane);
+            }
+        };
+        int qc = 0;
+        for (int k0 = wave * 64; k0 < tpx; k0 += BLOCK) {
+            const int k = k0 + lane;
+            bool miss = false, need = false;
+            int nn = -1;
             if (k < tpx) {
                 const uint32_t key = tld<G>(tile + k);
                 if (key != kEmptyKey) {
                     const int ty = k / in.tw, tx = k - ty * in.tw;
-                    int nn;
-                    if (knn2) {
+                    if (knn2 || hsh) {
                         int X, Y, wuv;
                         mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
-                        nn = scan_nn(s, X, Y, 16 * (int)(key >> 16));
+                        nn = knn2 ? scan_nn(s, X, Y, 16 * (int)(key >> 16)) : hash_nn(s, X, Y, 16 * (int)(key >> 16));
                     } else {
                         const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
                         const int e = (int)(key >> 16) - (th.y & 0xFFFF);
                         nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
                     }
                     miss = first && nn < 0;
+                    if (rf && first && (nn < 0 || !rgb)) rf[(in.ty0 + ty) * s.W + in.tx0 + tx] = nn < 0 ? 2 : 1;
                     if (nnm && !rgb && nn >= 0) mark_nn<KG>(bits, nn, s.W, in.jx0, in.jy0, in.jw, in.jh);
-                    if (nn >= 0 && ((rgb && first) || (bpx > 0 && !nnm))) {
-                        const int slot = atomicAdd(qn, 1);
-                        queue[slot] = k;
-                        queue2[slot] = nn;
-                        if (bpx > 0 && !nnm) {
-                            int X, Y, wuv;
-                            mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
-                            mx[slot] = X;
-                            my[slot] = Y;
-                            mw[slot] = wuv;
-                        }
-                    }
+                    need = nn >= 0 && ((rgb && first) || (bpx > 0 && !nnm));
                 }
             }
             cR += wave_popc(miss);
-            __syncthreads();
-            const int nq = *qn;
-            if (bpx > 0 && !nnm) {
-                for (int t = wave; t < nq; t += NW) {
-                    const int kk = queue[t];
-                    const int ty = kk / in.tw, tx = kk - ty * in.tw;
-                    const int dd = (int)(tld<G>(tile + kk) >> 16);
-                    wave_mark<KG>(s, in.tx0 + tx, in.ty0 + ty, dd, kk, mx[t], my[t], mw[t], keys, in.jx0, by0, in.jw,
-                                  bh, lane);
-                }
+            const unsigned long long mq = __ballot(need);
+            if (need) q[qc + lane_rank(mq)] = make_int2(k, nn);
+            qc += __popcll(mq);
+            if (qc >= 64) {
+                flush_r(64);
+                wave_lds_sync();
+                if (64 + lane < qc) q[lane] = q[64 + lane];     // the overflow moves to the front
+                qc -= 64;
             }
-            if (rgb && first) {
-                bool out = false;
-                if (tid < nq) {
-                    const int kk = queue[tid];
-                    const uint32_t key = tld<G>(tile + kk);
-                    const int ty = kk / in.tw, tx = kk - ty * in.tw;
-                    const float4 lr =
-                        srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                    if (labs) labs[kk] = lr;     // kept for the J_o test of the points this inlier keys
-                    out = ciede2000(lr, gld(s.olab + queue2[tid])) > s.tau;
-                    if (nnm && !out) mark_nn<KG>(bits, queue2[tid], s.W, in.jx0, in.jy0, in.jw, in.jh);
-                }
-                cR += wave_popc(out);
-            }
-            __syncthreads();
         }
+        if (qc > 0) flush_r(qc);
+        __syncthreads();
 
         // 4. J_o: observed points in V(O); explained iff some rendered point
-        //    keyed it.  In RGB mode the key names the nearest rendered point
-        //    and the explained points are queued for a dense colour test,
-        //    run whenever a work-group's worth has gathered (the queue holds
-        //    two: `queue`/`queue2`, then the marking arrays `mx`/`my`, idle
-        //    now) and at the band's end.  V rows above the J_o region go with
-        //    the first band, rows below it with the last.
+        //    keyed it.  In RGB mode the key names the nearest rendered point,
+        //    and the explained points are colour-tested through the wave's
+        //    queue.  V rows above the J_o region go with the first band, rows
+        //    below it with the last.
         const int ra = first ? in.vy0 : by0;
         const int rb = b == nb - 1 ? in.vy0 + in.vh : by0 + bh;
         const int rpx = max(rb - ra, 0) * in.vw;
         const float vinv = 1.0f / (float)max(in.vw, 1);
-        if (ocol) {
-            if (tid == 0) *qn = 0;
-            __syncthreads();
-        }
-        for (int k0 = 0; k0 < rpx; k0 += BLOCK) {
-            const int k = k0 + tid;
-            bool inq = false, out = false;
+        auto flush_o = [&](int n) {
+            wave_lds_sync();
+            bool cout = false;
+            if (lane < n) {
+                const int2 e = q[lane];
+                const int pix = e.x, kr = e.y;
+                float4 lr;
+                if (labs) {
+                    lr = gld(labs + kr);       // every keying point is an inlier of the first band
+                } else {
+                    const uint32_t key = tld<G>(tile + kr);
+                    const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                    lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
+                }
+                cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
+                if (of) of[pix] = cout ? 3 : 1;
+            }
+            cO += wave_popc(cout);
+        };
+        qc = 0;
+        for (int k0 = wave * 64; k0 < rpx; k0 += BLOCK) {
+            const int k = k0 + lane;
+            bool inq = false, out = false, need = false;
+            int pix = 0, kr = 0;
             if (k < rpx) {
                 const int vy = window_row(k, in.vw, vinv), vx = k - vy * in.vw;
                 const int i = in.vx0 + vx, j = ra + vy;
-                const int pix = j * s.W + i;
-                const int4 q = gld(s.opt + pix);
-                if (q.z != kNoPoint) {
-                    const int dp = q.z >> 4;
-                    inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, q.x, q.y, dp, dl, cyl);
+                pix = j * s.W + i;
+                const int4 qo = gld(s.opt + pix);
+                if (qo.z != kNoPoint) {
+                    const int dp = qo.z >> 4;
+                    inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, qo.x, qo.y, dp, dl, cyl);
                     typename K::T nk = K::kEmpty;
                     bool expl = false;
                     const int jx = i - in.jx0, jy = j - by0;
@@ -459,51 +511,26 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                         }
                     }
                     out = inq && !expl;
-                    if (ocol && inq && expl) {
-                        const int slot = atomicAdd(qn, 1);       // < 2 BLOCK: flushed below at BLOCK
-                        if (slot < BLOCK) {
-                            queue[slot] = pix;
-                            queue2[slot] = K::index(nk);
-                        } else {
-                            mx[slot - BLOCK] = pix;
-                            my[slot - BLOCK] = K::index(nk);
-                        }
-                    }
+                    if (of && inq && (!expl || !ocol)) of[pix] = expl ? 1 : 2;
+                    need = ocol && inq && expl;
+                    kr = K::index(nk);
                 }
             }
             cQ += wave_popc(inq);
             cO += wave_popc(out);
             if (ocol) {
-                __syncthreads();
-                int n = *qn;
-                // flush a full work-group's worth; at the band's end, everything
-                while (n >= BLOCK || (n > 0 && k0 + BLOCK >= rpx)) {
-                    const int nt = min(n, BLOCK);
-                    bool cout = false;
-                    if (tid < nt) {
-                        const int pix = queue[tid], kr = queue2[tid];
-                        float4 lr;
-                        if (labs) {
-                            lr = gld(labs + kr);       // every keying point is an inlier of the first band
-                        } else {
-                            const uint32_t key = tld<G>(tile + kr);
-                            const int ty = kr / in.tw, tx = kr - ty * in.tw;
-                            lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
-                        }
-                        cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
-                    }
-                    cO += wave_popc(cout);
-                    __syncthreads();
-                    if (tid < n - nt) {                // the overflow moves to the front
-                        queue[tid] = mx[tid];
-                        queue2[tid] = my[tid];
-                    }
-                    if (tid == 0) *qn = n - nt;
-                    n -= nt;
-                    __syncthreads();
+                const unsigned long long mq = __ballot(need);
+                if (need) q[qc + lane_rank(mq)] = make_int2(pix, kr);
+                qc += __popcll(mq);
+                if (qc >= 64) {
+                    flush_o(64);
+                    wave_lds_sync();
+                    if (64 + lane < qc) q[lane] = q[64 + lane];
+                    qc -= 64;
                 }
             }
         }
+        if (qc > 0) flush_o(qc);
     }
 
     if (lane == 0) {
@@ -533,10 +560,7 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
 {
     extern __shared__ uint32_t smem[];
     __shared__ int cnt[4];
-    __shared__ int queue[BLOCK];
-    __shared__ int queue2[BLOCK];
-    __shared__ int mx[BLOCK], my[BLOCK], mw[BLOCK];   // marking parameters of the queued inliers
-    __shared__ int qn;
+    __shared__ int2 wq[BLOCK / 64 * 128];   // per-wave work queues of phases 3 and 4
     __shared__ int next;
     uint32_t *slot = w.gscratch + w.slot_base[cls] + (size_t)blockIdx.x * w.slot_words[cls];
     float4 *labs = RGB && w.lab ? w.lab + w.lab_base[cls] + (size_t)blockIdx.x * w.lab_px[cls] : nullptr;
@@ -557,21 +581,30 @@ __global__ __launch_bounds__(BLOCK, 4) void score_kernel(Work w, int cls)
             len = strip == 0 ? w.counts[kCntClass + cls] : 0;
         }
         if (len == 0) continue;
-        for (;;) {
-            if (threadIdx.x == 0) next = atomicAdd(&w.counts[kCntNext + seg], 1);
-            __syncthreads();
-            const int i = next;
-            __syncthreads();
-            if (i >= len) break;
-            const int p = w.lists[cls * w.cap_poses + start + i];
+        // The loop is headed by a wave-uniform value (readfirstlane of the
+        // LDS copy) and no branch on the thread index: with a divergent
+        // `if (tid == 0)` fetch at its top the compiler may send thread 0
+        // alone round an outer loop to fetch while the other lanes pass the
+        // barrier without it.  score_pose ends with a barrier, so every wave
+        // has read `next` before thread 0 writes it again.
+        if (threadIdx.x == 0) next = atomicAdd(&w.counts[kCntNext + seg], 1);
+        __syncthreads();
+        for (int i = __builtin_amdgcn_readfirstlane(next); i < len;) {
+            const int p = __builtin_amdgcn_readfirstlane(w.lists[cls * w.cap_poses + start + i]);
             uint32_t *tile = G ? slot : smem;
             typename KeyOf<KG>::T *keys;
             if constexpr (KG)
                 keys = reinterpret_cast<unsigned long long *>(G ? slot + w.dev_tile_words : slot);
             else
                 keys = smem + w.info[p].tw * w.info[p].th;
-            score_pose<BLOCK, G, KG, RGB, PV>(w, p, tile, keys, labs, cnt, queue, queue2, mx, my, mw, &qn);
+            score_pose<BLOCK, G, KG, RGB, PV>(w, p, tile, keys, labs, cnt, wq);
+            if (threadIdx.x == 0) next = atomicAdd(&w.counts[kCntNext + seg], 1);
+            __syncthreads();
+            i = __builtin_amdgcn_readfirstlane(next);
         }
+        // every wave has read the segment's last `next` before the next
+        // segment's fetch overwrites it
+        __syncthreads();
     }
 }
 
@@ -898,16 +931,90 @@ __global__ __launch_bounds__(256) void table_block_apply_kernel(int N, int2 *thd
         }
 }
 
+// ------------------------------------------------------------------ voxel hash
+
+__global__ void fill_zero_kernel(int *a, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) a[k] = 0;
+}
+
+__device__ __forceinline__ int point_bucket(const SceneDev &s, int4 q)
+{
+    return cell_bucket(q.x >> s.hshift, q.y >> s.hshift, q.z >> s.hshift, s.hbits);
+}
+
+// Points per bucket.
+__global__ void hash_count_kernel(SceneDev s, int *count)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= s.W * s.H) return;
+    const int4 q = s.opt[k];
+    if (q.z == kNoPoint) return;
+    atomicAdd(count + point_bucket(s, q), 1);
+}
+
+// Block sums of the bucket counts, blocks of kScanBlock.
+__global__ __launch_bounds__(256) void hash_block_sums_kernel(int M, const int *count, long long *blk)
+{
+    const int base = blockIdx.x * kScanBlock + 4 * threadIdx.x;
+    long long v = 0;
+    for (int u = 0; u < 4; ++u)
+        if (base + u < M) v += count[base + u];
+    long long total;
+    (void)block_exclusive_scan256(v, &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+// Bucket starts: the exclusive scan of the counts, and start[M] = all points.
+__global__ __launch_bounds__(256) void hash_block_apply_kernel(int M, const int *count, const long long *blk,
+                                                               int *start)
+{
+    const int base = blockIdx.x * kScanBlock + 4 * threadIdx.x;
+    int n[4];
+    long long v = 0;
+    for (int u = 0; u < 4; ++u) {
+        n[u] = base + u < M ? count[base + u] : 0;
+        v += n[u];
+    }
+    long long total;
+    long long run = blk[blockIdx.x] + block_exclusive_scan256(v, &total);
+    for (int u = 0; u < 4; ++u) {
+        if (base + u < M) start[base + u] = (int)run;
+        run += n[u];
+        if (base + u == M - 1) start[M] = (int)run;
+    }
+}
+
+// Each point into its bucket's range (the order inside a bucket is free:
+// queries keep the smallest (d^2, pixel)); count is consumed.
+__global__ void hash_scatter_kernel(SceneDev s, int *count, int4 *pts)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= s.W * s.H) return;
+    const int4 q = s.opt[k];
+    if (q.z == kNoPoint) return;
+    const int b = point_bucket(s, q);
+    const int slot = atomicSub(count + b, 1) - 1;
+    pts[s.hstart[b] + slot] = make_int4(q.x, q.y, q.z, k);
+}
+
+hipError_t launch_hash_build(const SceneDev &s, int *count, long long *blk, hipStream_t st)
+{
+    const int N = s.W * s.H, M = 1 << s.hbits;
+    const int nblk = table_scan_blocks(M);
+    fill_zero_kernel<<<(M + 255) / 256, 256, 0, st>>>(count, M);
+    hash_count_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, count);
+    hash_block_sums_kernel<<<nblk, 256, 0, st>>>(M, count, blk);
+    table_block_scan_kernel<<<1, 256, 0, st>>>(nblk, blk, blk + nblk);
+    hash_block_apply_kernel<<<nblk, 256, 0, st>>>(M, count, blk, const_cast<int *>(s.hstart));
+    hash_scatter_kernel<<<(N + 255) / 256, 256, 0, st>>>(s, count, const_cast<int4 *>(s.hpts));
+    return hipGetLastError();
+}
+
 // Entries of one pixel's range handled per pass of the fill kernel.
 constexpr int kFillChunk = 256;
 
-// Make the LDS writes of a wave visible to all its lanes.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // One wave per pixel.  An observed point q can lie within delta of a
 // rendered point at this pixel only at depths within dzmm of q's own, so the

@@ -251,9 +251,14 @@ __global__ __launch_bounds__(BLOCK) void msg_kernel(MsgArgs a)
                 continue;
             }
             ++cn;
-            const int2 tr = gld(s.thdr + pix);
-            const int e = d - (tr.y & 0xFFFF);
-            const int nn = (e >= 0 && e < (int)((uint32_t)tr.y >> 16)) ? gld(s.tnn + tr.x + e) : -1;
+            int nn;
+            if (s.flags & kHashFlag) {
+                nn = hash_nn(s, (int)rint(gld(s.kx + i) * (double)d), (int)rint(gld(s.ky + j) * (double)d), 16 * d);
+            } else {
+                const int2 tr = gld(s.thdr + pix);
+                const int e = d - (tr.y & 0xFFFF);
+                nn = (e >= 0 && e < (int)((uint32_t)tr.y >> 16)) ? gld(s.tnn + tr.x + e) : -1;
+            }
             bool out = nn < 0;
             if (!out && rgb)
                 out = ciede2000(srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), i, j)), gld(s.olab + nn)) > s.tau;

@@ -79,8 +79,9 @@ struct MeshRec {
 };
 
 struct SceneRec {
-    DevBuf depth, rgb, labels, opt, olab, kx, ky, ax, ay, thdr, tnn;
+    DevBuf depth, rgb, labels, opt, olab, kx, ky, ax, ay, thdr, tnn, hstart, hpts;
     SceneDev dev{};
+    long long table_entries = 0;        // entries of the nearest-neighbour table (0 with the voxel hash)
     std::vector<int32_t> host_labels;
     std::vector<uint16_t> host_depth;   // kept with labels: per-label depth ranges (pose proposals)
     std::map<int32_t, std::vector<int>> label_boxes;
@@ -142,6 +143,7 @@ struct perch_ctx {
     std::recursive_mutex mu;
     perch_tuning tune{};                  // zeros: defaults
     int static_lds[3] = {0, 0, 0};        // static LDS bytes of the 256-, 512- and 1024-thread scoring kernels
+    std::vector<Staging *> scene_stage;   // free pinned staging areas of scene uploads
     int icp_lds_words = 0;                // dynamic LDS words of the ICP kernel
     int msg_lds_words = 0;                // dynamic LDS words of the tree's successor kernel
 
@@ -445,7 +447,8 @@ size_t desc_capacity(int items)
            + align64((size_t)items * sizeof(MeshDev));
 }
 
-perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_req, Built &b, int cap_items = 0)
+perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_req, Built &b, int cap_items = 0,
+                               uint8_t *rflag = nullptr, uint8_t *oflag = nullptr)
 {
     if (n_req < 0) return fail(PERCH_EINVAL, "negative item count");
     if (n_req > 0 && !req) return fail(PERCH_EINVAL, "null items");
@@ -494,12 +497,14 @@ perch_status build_descriptors(perch_ctx *ctx, const perch_work *req, int32_t n_
         it.jo = q.jo_dev;
         it.nr = q.nr_dev;
         it.nq = q.nq_dev;
+        it.rflag = rflag;
+        it.oflag = oflag;
         b.item_of_req[r] = (int)items.size();
         items.push_back(it);
         total += q.n_poses;
         b.max_pixels = std::max(b.max_pixels, (size_t)sd.W * sd.H);
         b.any_rgb |= (sd.flags & PERCH_USE_RGB) != 0;
-        b.any_pv |= (sd.flags & (PERCH_JO_NN | PERCH_KNN2)) != 0;
+        b.any_pv |= (sd.flags & (PERCH_JO_NN | PERCH_KNN2 | PERCH_HASH)) != 0;
         if (sd.flags & PERCH_KNN1)
             return fail(PERCH_EINVAL, "PERCH_KNN1 scenes are scored by perch_score_poses only");
     }
@@ -641,10 +646,11 @@ void mark_uses(perch_ctx *ctx, const std::vector<int32_t> &scene_ids, const std:
 // holds the context lock).  With want_best, the per-item minima are left in
 // the stream's buffers: *n_items_out and item_of_req say where.
 perch_status run_direct(perch_ctx *ctx, const perch_work *req, int32_t n_req, hipStream_t st, bool want_best,
-                        int *n_items_out = nullptr, std::vector<int> *item_of_req = nullptr)
+                        int *n_items_out = nullptr, std::vector<int> *item_of_req = nullptr,
+                        uint8_t *rflag = nullptr, uint8_t *oflag = nullptr)
 {
     Built b;
-    if (perch_status s = build_descriptors(ctx, req, n_req, b)) return s;
+    if (perch_status s = build_descriptors(ctx, req, n_req, b, 0, rflag, oflag)) return s;
     if (n_items_out) *n_items_out = b.n_items;
     if (item_of_req) *item_of_req = b.item_of_req;
     if (b.n_poses == 0) return PERCH_OK;
@@ -731,7 +737,7 @@ perch_status perch_destroy(perch_ctx *ctx)
         SceneRec &r = kv.second;
         FenceRef f = ctx->fence_of(r.uses);
         for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
-                          &r.tnn})
+                          &r.tnn, &r.hstart, &r.hpts})
             ctx->release(*b, f);
     }
     while (!ctx->batches.empty()) perch_batch_destroy(ctx->batches.back());
@@ -745,6 +751,11 @@ perch_status perch_destroy(perch_ctx *ctx)
             if (g.done) (void)hipEventDestroy(g.done);
         }
     }
+    for (Staging *g : ctx->scene_stage) {
+        if (g->host) (void)hipHostFree(g->host);
+        delete g;
+    }
+    ctx->scene_stage.clear();
     ctx->collect();
     ctx->trim();
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -860,10 +871,10 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (!(d->tau_c >= 0.0f) || !std::isfinite(d->tau_c)) return fail(PERCH_EINVAL, "tau_c must be finite and >= 0");
     if (d->stride < 1) return fail(PERCH_EINVAL, "stride must be >= 1");
     const uint32_t known =
-        PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN | PERCH_KNN2 | PERCH_KNN1;
+        PERCH_USE_RGB | PERCH_MARK_OCCLUDERS | PERCH_VOL_MASK | PERCH_JO_NN | PERCH_KNN2 | PERCH_KNN1 | PERCH_HASH;
     if (d->flags & ~known) return fail(PERCH_EINVAL, "unknown flag bits 0x%x", d->flags & ~known);
-    if ((d->flags & PERCH_KNN1) && (d->flags & PERCH_KNN2))
-        return fail(PERCH_EINVAL, "PERCH_KNN1 and PERCH_KNN2 are two searches; pass one");
+    if (((d->flags & PERCH_KNN1) != 0) + ((d->flags & PERCH_KNN2) != 0) + ((d->flags & PERCH_HASH) != 0) > 1)
+        return fail(PERCH_EINVAL, "PERCH_KNN1, PERCH_KNN2 and PERCH_HASH are three searches; pass one");
     const uint32_t vol = d->flags & PERCH_VOL_MASK;
     if (vol != PERCH_VOL_AABB && vol != PERCH_VOL_CYL && vol != PERCH_VOL_LABEL)
         return fail(PERCH_EINVAL, "unsupported volume mode");
@@ -894,15 +905,32 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     }
 
     SceneRec r;
-    DevBuf tmp;   // row pass output (N words), then the table total and the scan's block sums, 8-byte aligned
-    const size_t tmp_extra = (N * 4 + 7) & ~(size_t)7;
-    // allocation and kernel launches under the context lock; uploads and
-    // waits outside it, so scoring on other streams is not held up
+    const bool hashed = (d->flags & PERCH_HASH) != 0;
+    // voxel hash: cells of edge 2^hshift >= dq, 2^hbits >= 2 N buckets
+    int hshift = 0, hbits = 10;
+    {
+        const int dq = (int)std::nearbyint(16.0 * (double)d->delta_mm);
+        while ((1 << hshift) < dq) ++hshift;
+        while (((size_t)1 << hbits) < 2 * N) ++hbits;
+    }
+    const size_t n_buckets = (size_t)1 << hbits;
+    DevBuf tmp;   // table: row pass (N words), the table total, the scan's block sums; hash: bucket counts, sums
+    const size_t tmp_main = hashed ? n_buckets * 4 : (N * 4 + 7) & ~(size_t)7;
+    const int scan_blocks = table_scan_blocks(hashed ? (int)n_buckets : (int)N);
+    // host images staged in one pinned area: depth | rgb | labels | kx | ky | ax | ay | table total
+    auto up8 = [](size_t x) { return (x + 7) & ~(size_t)7; };
+    const size_t o_depth = 0, o_rgb = up8(N * 2), o_lab = o_rgb + (use_rgb ? up8(N * 3) : 0);
+    const size_t o_kx = o_lab + (d->labels ? up8(N * 4) : 0), o_ky = o_kx + (size_t)W * 8, o_ax = o_ky + (size_t)H * 8;
+    const size_t o_ay = o_ax + up8((size_t)W * 4), o_total = o_ay + up8((size_t)H * 4), stage_bytes = o_total + 8;
+    Staging *stg = nullptr;
+    // allocation and kernel launches under the context lock; the waits outside it, so scoring on other streams
+    // is not held up
     auto cleanup = [&]() {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         for (DevBuf *b : {&r.depth, &r.rgb, &r.labels, &r.opt, &r.olab, &r.kx, &r.ky, &r.ax, &r.ay, &r.thdr,
-                          &r.tnn, &tmp})
+                          &r.tnn, &r.hstart, &r.hpts, &tmp})
             ctx->release(*b);
+        if (stg) ctx->scene_stage.push_back(stg);
     };
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -921,21 +949,47 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             A(r.olab, N * sizeof(float4));
         }
         if (d->labels) A(r.labels, N * 4);
-        A(r.thdr, N * sizeof(int2));
-        A(tmp, tmp_extra + 64 + (size_t)table_scan_blocks((int)N) * 8);
+        if (hashed) {
+            A(r.hstart, (n_buckets + 1) * 4);
+            A(r.hpts, N * sizeof(int4));
+        } else {
+            A(r.thdr, N * sizeof(int2));
+        }
+        A(tmp, tmp_main + 64 + (size_t)(scan_blocks + 1) * 8);
+        if (st == PERCH_OK) {
+            if (!ctx->scene_stage.empty()) {
+                stg = ctx->scene_stage.back();
+                ctx->scene_stage.pop_back();
+            } else {
+                stg = new Staging();
+            }
+        }
         if (st != PERCH_OK) {
             std::string msg = g_last_error;
             cleanup();
             return fail(st, "%s", msg.c_str());
         }
     }
-    hipError_t e = hipMemcpy(r.depth.ptr, d->depth_mm, N * 2, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r.kx.ptr, kx.data(), W * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r.ky.ptr, ky.data(), H * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r.ax.ptr, ax.data(), W * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r.ay.ptr, ay.data(), H * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess && use_rgb) e = hipMemcpy(r.rgb.ptr, d->rgb, N * 3, hipMemcpyHostToDevice);
-    if (e == hipSuccess && d->labels) e = hipMemcpy(r.labels.ptr, d->labels, N * 4, hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    if (stg->bytes < stage_bytes) {
+        if (stg->host) e = hipHostFree(stg->host);
+        stg->host = nullptr;
+        stg->bytes = 0;
+        if (e == hipSuccess) e = hipHostMalloc(&stg->host, stage_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) stg->bytes = stage_bytes;
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(PERCH_ENOMEM, "pinned staging of %zu bytes: %s", stage_bytes, hipGetErrorString(e));
+    }
+    char *hs = (char *)stg->host;
+    std::memcpy(hs + o_depth, d->depth_mm, N * 2);
+    if (use_rgb) std::memcpy(hs + o_rgb, d->rgb, N * 3);
+    if (d->labels) std::memcpy(hs + o_lab, d->labels, N * 4);
+    std::memcpy(hs + o_kx, kx.data(), W * 8);
+    std::memcpy(hs + o_ky, ky.data(), H * 8);
+    std::memcpy(hs + o_ax, ax.data(), W * 4);
+    std::memcpy(hs + o_ay, ay.data(), H * 4);
     SceneDev &s = r.dev;
     s.depth = (const uint16_t *)r.depth.ptr;
     s.opt = (const int4 *)r.opt.ptr;
@@ -946,6 +1000,10 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.ax = (const float *)r.ax.ptr;
     s.ay = (const float *)r.ay.ptr;
     s.thdr = (const int2 *)r.thdr.ptr;
+    s.hstart = (const int *)r.hstart.ptr;
+    s.hpts = (const int4 *)r.hpts.ptr;
+    s.hshift = hshift;
+    s.hbits = hbits;
     s.W = W;
     s.H = H;
     s.fx = K.fx;
@@ -977,33 +1035,48 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             s.wty = std::min(H, (int)(K.fy * dl * std::sqrt(1.0 + ry * ry) / (z - dl)) + 2);
         }
     }
-    // points, colours, depth blocks and the nearest-neighbour table ranges
-    long long *total_dev = (long long *)((char *)tmp.ptr + tmp_extra);
-    long long total = 0;
-    if (e == hipSuccess) {
-        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        e = ctx->timed(kProfScenePrep, ctx->stream, [&] {
-            hipError_t e2 =
-                launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int4 *)r.opt.ptr, (float4 *)r.olab.ptr, ctx->stream);
-            return e2 == hipSuccess
-                       ? launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev,
-                                             (long long *)((char *)tmp.ptr + tmp_extra + 64), ctx->stream)
-                       : e2;
-        });
-        if (e == hipSuccess) e = hipMemcpyAsync(&total, total_dev, 8, hipMemcpyDeviceToHost, ctx->stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) {
-        cleanup();
-        return fail(PERCH_EDEVICE, "scene upload / preparation: %s", hipGetErrorString(e));
-    }
-    if (total >= (1LL << 31) - 1) {
-        cleanup();
-        return fail(PERCH_ENOMEM, "scene neighbour table too large (%lld entries)", total);
-    }
+    // uploads from the pinned area, then points, colours and the search structure, all on the context stream
+    long long *total_dev = (long long *)((char *)tmp.ptr + tmp_main);
+    long long *blk_dev = (long long *)((char *)tmp.ptr + tmp_main + 64);
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        ctx->release(tmp);
+        hipStream_t cs = ctx->stream;
+        auto H2D = [&](DevBuf &b, size_t off, size_t n) {
+            if (e == hipSuccess) e = hipMemcpyAsync(b.ptr, hs + off, n, hipMemcpyHostToDevice, cs);
+        };
+        H2D(r.depth, o_depth, N * 2);
+        if (use_rgb) H2D(r.rgb, o_rgb, N * 3);
+        if (d->labels) H2D(r.labels, o_lab, N * 4);
+        H2D(r.kx, o_kx, W * 8);
+        H2D(r.ky, o_ky, H * 8);
+        H2D(r.ax, o_ax, W * 4);
+        H2D(r.ay, o_ay, H * 4);
+        if (e == hipSuccess)
+            e = ctx->timed(kProfScenePrep, cs, [&] {
+                hipError_t e2 = launch_scene_prep(s, (const uint8_t *)r.rgb.ptr, (int4 *)r.opt.ptr,
+                                                  (float4 *)r.olab.ptr, cs);
+                if (e2 != hipSuccess) return e2;
+                if (hashed) return launch_hash_build(s, (int *)tmp.ptr, blk_dev, cs);
+                return launch_table_ranges(s, (uint32_t *)tmp.ptr, (int2 *)r.thdr.ptr, total_dev, blk_dev, cs);
+            });
+        if (e == hipSuccess && !hashed)
+            e = hipMemcpyAsync(hs + o_total, total_dev, 8, hipMemcpyDeviceToHost, cs);
+    }
+    if (!hashed) {
+        // the table's size decides its allocation: one wait for it
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        long long total = 0;
+        std::memcpy(&total, hs + o_total, 8);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(PERCH_EDEVICE, "scene upload / preparation: %s", hipGetErrorString(e));
+        }
+        if (total >= (1LL << 31) - 1) {
+            cleanup();
+            return fail(PERCH_ENOMEM, "scene neighbour table too large (%lld entries)", total);
+        }
+        r.table_entries = total;
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         if (perch_status st = ctx->alloc(r.tnn, (size_t)std::max(total, 1LL) * 4)) {
             std::string msg = g_last_error;
             cleanup();
@@ -1016,15 +1089,17 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         cleanup();
-        return fail(PERCH_EDEVICE, "scene table fill: %s", hipGetErrorString(e));
+        return fail(PERCH_EDEVICE, "scene preparation: %s", hipGetErrorString(e));
     }
     if (d->labels) {
         r.host_labels.assign(d->labels, d->labels + N);
         r.host_depth.assign(d->depth_mm, d->depth_mm + N);
     }
     r.bytes = r.depth.bytes + r.rgb.bytes + r.labels.bytes + r.opt.bytes + r.olab.bytes + r.kx.bytes
-              + r.ky.bytes + r.ax.bytes + r.ay.bytes + r.thdr.bytes + r.tnn.bytes;
+              + r.ky.bytes + r.ax.bytes + r.ay.bytes + r.thdr.bytes + r.tnn.bytes + r.hstart.bytes + r.hpts.bytes;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->release(tmp);
+    ctx->scene_stage.push_back(stg);
     const int32_t id = ctx->next_scene++;
     ctx->scenes[id] = std::move(r);
     *scene_id = id;
@@ -1124,6 +1199,28 @@ perch_status perch_score_poses(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id
     }
     const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
     perch_status s = run_direct(ctx, &item, 1, pick_stream(ctx, hip_stream), false);
+    return s ? s : ok();
+}
+
+perch_status perch_score_detail(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
+                                int32_t *nr_dev, int32_t *nq_dev, uint8_t *rflag_dev, uint8_t *oflag_dev,
+                                void *hip_stream)
+{
+    const Range range_("perch_score_detail");
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    if (si->second.dev.flags & PERCH_KNN1) return fail(PERCH_EINVAL, "PERCH_KNN1 scenes have no class images");
+    if (n < 1 || n > 256) return fail(PERCH_EINVAL, "n must be in [1, 256]");
+    if (!rflag_dev || !oflag_dev) return fail(PERCH_EINVAL, "null class images");
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    const size_t bytes = (size_t)n * si->second.dev.W * si->second.dev.H;
+    HIP_TRY(hipMemsetAsync(rflag_dev, 0, bytes, st));
+    HIP_TRY(hipMemsetAsync(oflag_dev, 0, bytes, st));
+    const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
+    perch_status s = run_direct(ctx, &item, 1, st, false, nullptr, nullptr, rflag_dev, oflag_dev);
     return s ? s : ok();
 }
 
@@ -1665,7 +1762,7 @@ perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_
     const SceneRec &r = it->second;
     const LaunchCfg c = launch_cfg(ctx);
     out->device_bytes = r.bytes;
-    out->table_entries = (int64_t)(r.tnn.bytes / 4);
+    out->table_entries = (int64_t)r.table_entries;
     out->window_x = r.dev.wtx;
     out->window_y = r.dev.wty;
     out->tile_cap_small = c.cap_small;

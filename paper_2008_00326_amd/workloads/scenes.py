@@ -57,7 +57,7 @@ class Workload:
     mark_occluders: bool = True
     volume: str = "aabb"           # "aabb" | "cyl" | "label"
     jo: str = "exact"              # "exact" (Eq. 3) | "nn" (nearest-neighbour marking)
-    search: str = "table"          # "table" | "knn2" (the paper's scan of the whole cloud)
+    search: str = "table"          # "table" | "hash" (voxel hash) | "knn2" (the paper's scan of the whole cloud)
     stride: int = 1
     info: dict = field(default_factory=dict)
 

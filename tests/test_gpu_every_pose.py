@@ -1,0 +1,263 @@
+"""GPU parity on every pose, and per pixel.
+
+The HIP path, through the C ABI, against the oracle's windowed exact search
+(pinned equal to brute force on the CPU):
+  * every one of the 32,000 poses of the 640x480 RGB workload and of the
+    8,192 poses of the 6-DoF workload, in the launch shape the benchmark
+    times (one launch per scene holding every object), plus the per-object
+    minimum of Sec. IV-A "Parallel Search";
+  * eight scenes of the many-scene workload (3-DoF and 6-DoF, meshes up to
+    45k triangles) in one captured-graph batch: every pose of the items
+    checked, and each item's minimum;
+  * the class of every rendered and observed pixel (perch_score_detail)
+    against the oracle's, on poses of every footprint class.
+L, Q and every depth-only decision are bit-exact.  With the RGB term the
+colour decision is binary32 on both sides with different transcendental
+libraries: per pose |dJ_r| <= ceil(0.001 L), |dJ_o| <= ceil(0.001 Q), and a
+differing pixel may only swap "inlier" and "colour outlier".
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2008_00326_amd as pk  # noqa: E402
+from paper_2008_00326_amd.workloads import make_config, scenes  # noqa: E402
+from tiny_meshes import TMesh, TScene, box, pose_matrix, rot_x, rot_z  # noqa: E402
+
+THREADS = 0     # every host core the oracle's OpenMP runtime sees
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def flags_of(w):
+    f = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0)
+    return f | {"aabb": oracle.VOL_AABB, "cyl": oracle.VOL_CYL, "label": oracle.VOL_LABEL}[w.volume]
+
+
+def oracle_counts(w, mesh, poses, label):
+    sc = TScene(w.scene.K, w.scene.depth, w.scene.rgb if w.use_rgb else None, w.scene.labels)
+    m = mesh if w.use_rgb else TMesh(mesh.xyz, mesh.tri, None)
+    return oracle.score(m, sc, poses, delta_mm=w.delta_mm, tau_c=w.tau_c, flags=flags_of(w), stride=w.stride,
+                        label=label, threads=THREADS, search="window")
+
+
+def check(rgb, got, exp, what):
+    jr, jo, nr, nq = got
+    ejr, ejo, enr, enq = exp
+    assert np.array_equal(nr, enr), f"{what}: L differs at {np.flatnonzero(nr != enr)[:10]}"
+    assert np.array_equal(nq, enq), f"{what}: Q differs at {np.flatnonzero(nq != enq)[:10]}"
+    if not rgb:
+        assert np.array_equal(jr, ejr), f"{what}: J_r differs at {np.flatnonzero(jr != ejr)[:10]}"
+        assert np.array_equal(jo, ejo), f"{what}: J_o differs at {np.flatnonzero(jo != ejo)[:10]}"
+        return 0
+    dr, do = np.abs(jr - ejr), np.abs(jo - ejo)
+    assert np.all(dr <= np.ceil(0.001 * enr)), f"{what}: J_r beyond tolerance at {np.flatnonzero(dr > np.ceil(0.001 * enr))[:10]}"
+    assert np.all(do <= np.ceil(0.001 * enq)), f"{what}: J_o beyond tolerance at {np.flatnonzero(do > np.ceil(0.001 * enq))[:10]}"
+    return int(np.count_nonzero(dr) + np.count_nonzero(do))
+
+
+def check_best(rgb, bi, bc, got, exp, what):
+    """The GPU minimum equals the oracle's (Sec. IV-A); with the colour term,
+    where the costs differ within the tolerance, the GPU's choice costs no
+    more than the oracle's optimum plus that tolerance."""
+    J = got[0].astype(np.int64) + got[1]
+    assert bc == J.min() and bi == int(np.flatnonzero(J == J.min())[0]), what
+    ebi, ebc, _ = oracle.best(exp[0], exp[1])
+    if np.array_equal(got[0], exp[0]) and np.array_equal(got[1], exp[1]):
+        assert (bi, bc) == (ebi, ebc), what
+    else:
+        assert rgb
+        EJ = exp[0].astype(np.int64) + exp[1]
+        tol = np.ceil(0.001 * exp[2]) + np.ceil(0.001 * exp[3])
+        assert EJ[bi] <= ebc + tol[bi] + tol[ebi], what
+
+
+def run_scene(ctx, w, what):
+    """Score every object of a workload in one launch (as the benchmark's
+    per-scene step does), then the per-object minima through best_poses."""
+    sid, mids = pk.load_workload(ctx, w)
+    items = []
+    for o in w.objects:
+        p = torch.from_numpy(np.ascontiguousarray(o.poses)).cuda()
+        n = p.shape[0]
+        items.append({"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": p,
+                      "nr": torch.empty(n, dtype=torch.int32, device="cuda"),
+                      "nq": torch.empty(n, dtype=torch.int32, device="cuda")})
+    out = ctx.score_batch(items)
+    torch.cuda.synchronize()
+    got = [tuple(it[k].cpu().numpy() for k in ("jr", "jo", "nr", "nq")) for it in out]
+    bi, bc = ctx.best_poses(sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects],
+                            [it["poses"] for it in items])
+    ctx.drop_scene(sid)
+    for m in mids:
+        ctx.unload_mesh(m)
+    mism = 0
+    for k, o in enumerate(w.objects):
+        t = time.time()
+        exp = oracle_counts(w, w.meshes[o.mesh], o.poses, o.label)
+        say(f"  {what} object {o.label}: {o.poses.shape[0]} poses, oracle {time.time() - t:.1f} s")
+        mism += check(w.use_rgb, got[k], exp, f"{what} object {o.label}")
+        check_best(w.use_rgb, int(bi[k]), int(bc[k]), got[k], exp, f"{what} object {o.label} minimum")
+    return mism
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_every_pose_against_the_oracle(ctx, cfg):
+    w = make_config(cfg, 0)
+    say(f"every pose of config {cfg} ({w.n_poses} poses)")
+    mism = run_scene(ctx, w, f"cfg{cfg}")
+    say(f"cfg{cfg}: {mism} poses with a colour-decision difference within tolerance")
+
+
+def test_every_pose_depth_only(ctx):
+    w = make_config(2, 0)
+    w.use_rgb = False
+    say("every pose of config 2 without the colour term")
+    run_scene(ctx, w, "cfg2 depth-only")
+
+
+def test_many_scene_graph_batch_against_the_oracle(ctx):
+    """Eight scenes of the many-scene workload in one captured-graph launch:
+    all their items in the batch; every pose of the item with the largest
+    mesh and of the item with the fewest poses of each scene against the
+    oracle, every item's minimum against the GPU's own costs, and the
+    checked items' minima against the oracle's."""
+    lib = scenes.mesh_library(0)
+    ws = scenes.config4(0, n_scenes=8, library=lib)
+    assert any(w.info["six_dof"] for w in ws) and any(not w.info["six_dof"] for w in ws)
+    assert max(lib[o.mesh].tri.shape[0] for w in ws for o in w.objects) >= 30000
+    mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in lib]
+    sids, items, owner = [], [], []
+    for s, w in enumerate(ws):
+        sid = ctx.set_scene(w.scene.K, w.scene.depth, w.scene.rgb, None, delta_mm=w.delta_mm, tau_c=w.tau_c,
+                            use_rgb=True, mark_occluders=True, volume="aabb")
+        sids.append(sid)
+        for o in w.objects:
+            p = torch.from_numpy(np.ascontiguousarray(o.poses)).cuda()
+            n = p.shape[0]
+            items.append({"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": p,
+                          "nr": torch.empty(n, dtype=torch.int32, device="cuda"),
+                          "nq": torch.empty(n, dtype=torch.int32, device="cuda")})
+            owner.append((s, o))
+    total = sum(it["poses"].shape[0] for it in items)
+    say(f"graph batch: {len(ws)} scenes, {len(items)} items, {total} poses")
+    b = ctx.batch(max_items=len(items), max_poses=total, max_image_pixels=640 * 480)
+    out = b.set(items)
+    b.launch()
+    bi, bc = b.wait()
+    torch.cuda.synchronize()
+    got = [tuple(it[k].cpu().numpy() for k in ("jr", "jo", "nr", "nq")) for it in out]
+    for k, g in enumerate(got):
+        J = g[0].astype(np.int64) + g[1]
+        assert bc[k] == J.min() and bi[k] == int(np.flatnonzero(J == J.min())[0])
+    checked = 0
+    for s, w in enumerate(ws):
+        ks = [k for k, (s2, _) in enumerate(owner) if s2 == s]
+        big = max(ks, key=lambda k: lib[owner[k][1].mesh].tri.shape[0])
+        few = min(ks, key=lambda k: owner[k][1].poses.shape[0])
+        for k in sorted({big, few}):
+            o = owner[k][1]
+            t = time.time()
+            exp = oracle_counts(w, lib[o.mesh], o.poses, o.label)
+            say(f"  {w.name} object {o.label} ({lib[o.mesh].tri.shape[0]} triangles, {o.poses.shape[0]} poses): "
+                f"oracle {time.time() - t:.1f} s")
+            check(True, got[k], exp, f"{w.name} object {o.label}")
+            check_best(True, int(bi[k]), int(bc[k]), got[k], exp, f"{w.name} object {o.label} minimum")
+            checked += o.poses.shape[0]
+    say(f"graph batch: {checked} poses checked against the oracle")
+    b.close()
+    for sid in sids:
+        ctx.drop_scene(sid)
+    for m in mids:
+        ctx.unload_mesh(m)
+
+
+# ---------------------------------------------------------------- per pixel
+
+def _compare_classes(rgb, rf, of, erf, eof, L, Q, what):
+    if not rgb:
+        assert np.array_equal(rf, erf), f"{what}: {np.count_nonzero(rf != erf)} rendered pixels differ"
+        assert np.array_equal(of, eof), f"{what}: {np.count_nonzero(of != eof)} observed pixels differ"
+        return
+    for name, a, b, n in (("rendered", rf, erf, L), ("observed", of, eof, Q)):
+        d = a != b
+        assert d.sum() <= np.ceil(0.001 * n), f"{what}: {int(d.sum())} {name} pixels differ"
+        # only colour decisions may differ: inlier <-> colour outlier
+        assert np.all(np.isin(a[d], (1, 3)) & np.isin(b[d], (1, 3))), f"{what}: {name} class differs beyond colour"
+
+
+def _detail(ctx, sid, mid, poses, label):
+    t = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).cuda()
+    jr, jo, nr, nq, rf, of = ctx.score_detail(sid, mid, t, label=label)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (jr, jo, nr, nq, rf, of)]
+
+
+@pytest.mark.parametrize("variant", ["rgb", "depth", "label-nn"])
+def test_pixel_classes_every_footprint_class(ctx, variant):
+    """Sampled poses of the 640x480 workload in every footprint class (LDS,
+    LDS in row bands, device-memory keys) and a pose close to the camera
+    (tile in device memory): per-pixel classes against the oracle's."""
+    w = make_config(2, 0)
+    if variant == "depth":
+        w.use_rgb = False
+    elif variant == "label-nn":
+        w.volume = "label"
+        w.jo = "nn"
+    say(f"pixel classes, {variant}")
+    sid, mids = pk.load_workload(ctx, w)
+    ofl = flags_of(w) | (oracle.JO_NN if variant == "label-nn" else 0)
+    sc = TScene(w.scene.K, w.scene.depth, w.scene.rgb if w.use_rgb else None, w.scene.labels)
+    rng = np.random.default_rng(31)
+    seen = set()
+    for bands in (2, 1):
+        ctx.set_tuning({"key_bands": bands})
+        for o in w.objects[:3]:
+            mesh = w.meshes[o.mesh] if w.use_rgb else TMesh(w.meshes[o.mesh].xyz, w.meshes[o.mesh].tri, None)
+            ctx.score_poses(sid, mids[o.mesh], torch.from_numpy(o.poses).cuda(), label=o.label)
+            cls = ctx.last_classes(o.poses.shape[0])
+            sel = [o.gt_pose[None]]
+            for c in np.unique(cls):
+                sel.append(o.poses[rng.choice(np.flatnonzero(cls == c), 1)])
+            near = o.gt_pose.copy()
+            near[11] = 260.0                       # close to the camera: a large tile
+            sel.append(near[None])
+            poses = np.concatenate(sel)
+            jr, jo, nr, nq, rf, of = _detail(ctx, sid, mids[o.mesh], poses, o.label)
+            ctx.score_poses(sid, mids[o.mesh], torch.from_numpy(poses).cuda(), label=o.label)
+            seen |= set(ctx.last_classes(poses.shape[0]).tolist())
+            for k in range(poses.shape[0]):
+                (ejr, ejo, el, eq), erf, eof = oracle.score_detail(mesh, sc, poses[k], delta_mm=w.delta_mm,
+                                                                   tau_c=w.tau_c, flags=ofl, label=o.label,
+                                                                   search="window")
+                what = f"{variant} bands={bands} object {o.label} pose {k}"
+                assert (nr[k], nq[k]) == (el, eq), what
+                # the images account for the counts
+                assert np.count_nonzero(np.isin(rf[k], (1, 2, 3))) == nr[k], what
+                assert np.count_nonzero(np.isin(rf[k], (2, 3))) == jr[k], what
+                assert np.count_nonzero(of[k]) == nq[k] and np.count_nonzero(np.isin(of[k], (2, 3))) == jo[k], what
+                _compare_classes(w.use_rgb, rf[k], of[k], erf, eof, el, eq, what)
+    ctx.set_tuning(None)
+    assert {0, 1, 2, 3} <= seen, seen
+    ctx.drop_scene(sid)
+    for m in mids:
+        ctx.unload_mesh(m)
