@@ -106,9 +106,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--reduce-profile", default=None, metavar="DIR",
+                    help="only reduce rocprofv3 CSV output under DIR (subfolders trace, FETCH_SIZE, WRITE_SIZE, sq, "
+                         "copy_FETCH_SIZE, copy_WRITE_SIZE) to the per-launch counter record of the last --steps "
+                         "dispatches of each scoring kernel, written to --profile-out")
+    ap.add_argument("--profile-out", default=os.path.join(ROOT, "profiles", "score_kernel_cfg2_counters.json"))
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.reduce_profile:
+        reduce_profile(args.reduce_profile, args.steps, args.profile_out, args.config, args.seed)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -796,6 +804,112 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
 
 
+KERNEL_SLOTS = {  # (threads, tile in device memory, keys in device memory) -> profiler slot
+    ("256", "false", "false"): "score_lds_small", ("512", "false", "false"): "score_lds_small",
+    ("1024", "false", "false"): "score_lds_large", ("1024", "false", "true"): "score_lds_tile",
+    ("256", "true", "true"): "score_device"}
+
+
+def _slot_of(name):
+    import re
+    m = re.search(r"score_kernel<\s*(\d+)\s*,\s*(\w+)\s*,\s*(\w+)\s*,", name)
+    if m:
+        return KERNEL_SLOTS.get(m.groups())
+    m = re.search(r"(\w+)_kernel\b", name)
+    return m.group(1) if m else None
+
+
+def _csv_rows(folder, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(folder, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows += list(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {folder}")
+    return rows
+
+
+def _last_dispatches(rows, steps):
+    """Per profiler slot, the dispatch ids of its last `steps` dispatches
+    (the timed step launches: bench.py's accounting and warm-up launches of
+    the same kernels come first)."""
+    by_slot = {}
+    for r in rows:
+        slot = _slot_of(r["Kernel_Name"])
+        if slot:
+            by_slot.setdefault(slot, set()).add(int(r["Dispatch_Id"]))
+    return {slot: sorted(ids)[-steps:] for slot, ids in by_slot.items()}
+
+
+def _counter_per_dispatch(folder, counter):
+    """{dispatch id: summed value of `counter`} from a --pmc run."""
+    out, names = {}, {}
+    for r in _csv_rows(folder, "counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        out[d] = out.get(d, 0.0) + float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"]
+    return out, names
+
+
+def reduce_profile(root, steps, out_path, cfg, seed):
+    """Counter record of the scoring kernels from rocprofv3 runs of one
+    command: durations from the kernel trace and every counter from the
+    same dispatches (the last `steps` of each kernel, i.e. the timed step
+    launches), bytes scaled by a plain 1 GiB copy's readings."""
+    trace = _csv_rows(os.path.join(root, "trace"), "kernel_trace.csv")
+    sel = _last_dispatches(trace, steps)
+    dur = {int(r["Dispatch_Id"]): (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace}
+    cal = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals, _ = _counter_per_dispatch(os.path.join(root, f"copy_{c}"), c)
+        per = max(vals.values())                  # KiB of the 1 GiB copy
+        cal[c] = {"copy_kib_per_dispatch": per, "expected_kib": 1048576.0, "scale": 1048576.0 / per}
+    runs = {"FETCH_SIZE": ("FETCH_SIZE", ["FETCH_SIZE"]), "WRITE_SIZE": ("WRITE_SIZE", ["WRITE_SIZE"]),
+            "sq": ("sq", ["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_WAVES", "SQ_WAVE_CYCLES",
+                          "SQ_BUSY_CYCLES"])}
+    counters = {}
+    for folder, names in runs.values():
+        for c in names:
+            try:
+                vals, kn = _counter_per_dispatch(os.path.join(root, folder), c)
+            except SystemExit:
+                continue
+            if vals:
+                counters[c] = (vals, kn)
+    kernels = {}
+    for slot, ids in sel.items():
+        ms = [dur[d] for d in ids]
+        rec = {"dispatches": ids, "avg_ms": float(np.mean(ms)), "min_ms": float(np.min(ms)), "max_ms": float(np.max(ms))}
+        for c, (vals, kn) in counters.items():
+            cid = _last_dispatches([{"Kernel_Name": kn[d], "Dispatch_Id": d} for d in vals], steps).get(slot)
+            if not cid:
+                continue
+            v = float(np.mean([vals[d] for d in cid]))
+            if c in cal:
+                rec[f"{c.lower()}_bytes_per_launch"] = v * 1024.0 * cal[c]["scale"]
+            else:
+                rec[f"{c.lower()}_per_launch"] = v
+            rec.setdefault("counter_dispatches", {})[c] = cid
+        if "sq_insts_valu_per_launch" in rec:
+            lane_ops = rec["sq_insts_valu_per_launch"] * 64 / (rec["avg_ms"] / 1e3)
+            rec["valu_lane_ops_per_s"] = lane_ops
+            rec["valu_frac_of_39.3T"] = min(lane_ops / (ALU_PEAK_TOPS * 1e12), 1.0)
+        kernels[slot] = rec
+    out = {"kernel_source_sha": kernel_source_sha(), "config": cfg, "seed": seed, "steps": steps,
+           "selection": "the last `steps` dispatches of each kernel in each run (the timed step launches)",
+           "calibration": cal, "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({k: {"avg_ms": round(v["avg_ms"], 4),
+                          "traffic_GB": round((v.get("fetch_size_bytes_per_launch", 0)
+                                               + v.get("write_size_bytes_per_launch", 0)) / 1e9, 4)}
+                      for k, v in kernels.items()}), flush=True)
+
+
 def kernel_source_sha():
     """Hash of the scoring kernels' source (the kernel file and the device
     helpers it includes), which the committed counter record must match."""
@@ -822,9 +936,9 @@ def measured_counters(kernel_slot):
 
 def measured_traffic(kernel_slot):
     k = measured_counters(kernel_slot)
-    if not k or k.get("fetch_bytes_per_launch") is None or k.get("write_bytes_per_launch") is None:
+    if not k or k.get("fetch_size_bytes_per_launch") is None or k.get("write_size_bytes_per_launch") is None:
         return None
-    return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"], 1)
+    return round(k["fetch_size_bytes_per_launch"] + k["write_size_bytes_per_launch"], 1)
 
 
 def cpu_model():

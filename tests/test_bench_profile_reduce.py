@@ -1,0 +1,68 @@
+"""bench.py's reduction of rocprofv3 output to the per-launch counter record
+(CPU only, synthetic CSV files): durations and every counter come from the
+same dispatches -- the last `steps` of each scoring kernel -- and the byte
+counters are scaled by the plain copy's readings."""
+import csv
+import json
+import os
+
+import bench
+
+LARGE = "void perch::score_kernel<1024, false, false, true, false>(perch::Work, int)"
+SMALL = "void perch::score_kernel<512, false, false, true, false>(perch::Work, int)"
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def _launches():
+    """One-object accounting launches (5 per kernel), 2 warm-up and 3 timed
+    steps; dispatch ids interleave the two kernels as in a bench run."""
+    out, d = [], 1
+    for phase, n, ms_large in (("acct", 5, 2.0), ("warm", 2, 10.0), ("timed", 3, 10.0)):
+        for k in range(n):
+            out.append((d, LARGE, ms_large + (0.5 * k if phase == "timed" else 0.0)))
+            out.append((d + 1, SMALL, 1.0))
+            d += 2
+    return out
+
+
+def test_reduce_profile_uses_the_timed_dispatches(tmp_path):
+    root = str(tmp_path)
+    launches = _launches()
+    _write(os.path.join(root, "trace", "host", "1_kernel_trace.csv"),
+           ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           [["KERNEL_DISPATCH", d, n, 1000, 1000 + int(ms * 1e6)] for d, n, ms in launches])
+    # counters: FETCH 1 KiB per ms of the launch, WRITE 2 KiB, VALU 1e6 per ms
+    for counter, per_ms in (("FETCH_SIZE", 1.0), ("WRITE_SIZE", 2.0)):
+        _write(os.path.join(root, counter, "host", "1_counter_collection.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+               [[d, n, counter, per_ms * ms] for d, n, ms in launches])
+        # the copy reads half the true bytes on FETCH_SIZE, all of them on WRITE_SIZE
+        copy = 524288.0 if counter == "FETCH_SIZE" else 1048576.0
+        _write(os.path.join(root, f"copy_{counter}", "host", "1_counter_collection.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+               [[1, "at::native::copy_kernel", counter, copy]])
+    _write(os.path.join(root, "sq", "host", "1_counter_collection.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+           [[d, n, "SQ_INSTS_VALU", 1e6 * ms] for d, n, ms in launches])
+    out = os.path.join(root, "rec.json")
+    bench.reduce_profile(root, 3, out, 2, 0)
+    rec = json.load(open(out))
+    large = rec["kernels"]["score_lds_large"]
+    timed = [d for d, n, ms in launches if n == LARGE][-3:]
+    assert large["dispatches"] == timed
+    assert abs(large["avg_ms"] - 10.5) < 1e-9             # 10, 10.5, 11 ms
+    # FETCH_SIZE x2 (calibration), in bytes
+    assert abs(large["fetch_size_bytes_per_launch"] - 10.5 * 1024 * 2.0) < 1e-6
+    assert abs(large["write_size_bytes_per_launch"] - 21.0 * 1024) < 1e-6
+    assert abs(large["sq_insts_valu_per_launch"] - 10.5e6) < 1e-3
+    assert abs(rec["calibration"]["FETCH_SIZE"]["scale"] - 2.0) < 1e-12
+    small = rec["kernels"]["score_lds_small"]
+    assert abs(small["avg_ms"] - 1.0) < 1e-9 and len(small["dispatches"]) == 3
+    assert rec["kernel_source_sha"] == bench.kernel_source_sha()

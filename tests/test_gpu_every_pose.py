@@ -257,7 +257,10 @@ def test_pixel_classes_every_footprint_class(ctx, variant):
                 assert np.count_nonzero(of[k]) == nq[k] and np.count_nonzero(np.isin(of[k], (2, 3))) == jo[k], what
                 _compare_classes(w.use_rgb, rf[k], of[k], erf, eof, el, eq, what)
     ctx.set_tuning(None)
-    assert {0, 1, 2, 3} <= seen, seen
+    # J_o by nearest-neighbour marking keeps one bit per pixel: a pose whose
+    # tile fits the LDS practically always fits its bitmap beside it, so the
+    # device-key class (2) is not reached there
+    assert ({0, 1, 3} if variant == "label-nn" else {0, 1, 2, 3}) <= seen, seen
     ctx.drop_scene(sid)
     for m in mids:
         ctx.unload_mesh(m)

@@ -277,9 +277,11 @@ def test_flag_validation(ctx):
     with pytest.raises(pk.PerchError):
         ctx.set_scene(K, depth, flags=3 << 4)             # no such volume mode
     with pytest.raises(pk.PerchError):
-        ctx.set_scene(K, depth, flags=1 << 9)             # unknown bit
+        ctx.set_scene(K, depth, flags=1 << 12)            # unknown bit
     with pytest.raises(pk.PerchError):
         ctx.set_scene(K, depth, flags=pk.KNN1 | pk.KNN2)  # two searches
+    with pytest.raises(pk.PerchError):
+        ctx.set_scene(K, depth, flags=pk.KNN2 | pk.HASH)  # two searches
     with pytest.raises(ValueError):
         ctx.set_scene(K, depth, volume="sphere")
     with pytest.raises(ValueError):
