@@ -187,6 +187,25 @@ perch_status perch_score_detail(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
                                 int32_t *nr_dev, int32_t *nq_dev, uint8_t *rflag_dev, uint8_t *oflag_dev,
                                 void *hip_stream);
 
+/* perch_score_poses for callers that cannot allocate memory (code that may
+ * be captured into a HIP graph, tight serving loops, hosts that forbid
+ * allocation during a request): the same kernels, with every launch buffer
+ * -- descriptors, per-pose work, class lists, counters and the device-memory
+ * slots of the largest footprints -- carved from one 48 MiB array that each
+ * device holds for the life of the process.  The call allocates no device
+ * or host-pinned memory; the caller passes poses and outputs as for
+ * perch_score_poses, and the outputs are bit-identical to its.
+ * Limits: 0 <= n <= 65536 poses, scenes of at most 640 * 480 pixels, no
+ * PERCH_KNN1 scenes; beyond them PERCH_EINVAL and nothing is launched.
+ * Every call on a device, from any context of the process, shares that
+ * device's array and the last call leaves its contents there: two calls
+ * whose device work overlaps (different streams without an ordering
+ * between them) race and their results are undefined.  Calls queued on one
+ * stream are ordered and safe.  Asynchronous on hip_stream. */
+perch_status perch_score_poses_noalloc(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                       const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
+                                       int32_t *nr_dev, int32_t *nq_dev, void *hip_stream);
+
 /* One slice of a launch: the candidate poses of one object in one scene.
  * Pointers as in perch_score_poses; n_poses may be 0. */
 typedef struct {

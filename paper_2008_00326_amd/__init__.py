@@ -113,6 +113,7 @@ def load_library():
         "perch_drop_scene": ([P, I32], ctypes.c_int),
         "perch_score_poses": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP], ctypes.c_int),
         "perch_score_detail": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP, VP, VP], ctypes.c_int),
+        "perch_score_poses_noalloc": ([P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP], ctypes.c_int),
         "perch_best_poses": ([P, I32, I32, P, P, P, P, P, P, VP], ctypes.c_int),
         "perch_render": ([P, I32, I32, VP, I32, VP, VP, VP, VP], ctypes.c_int),
         "perch_refine_poses": ([P, I32, I32, I32, VP, I32, P, VP, VP, VP, VP], ctypes.c_int),
@@ -266,6 +267,22 @@ class Context:
         _check(self._lib.perch_score_poses(self._h, int(scene_id), int(mesh_id), int(label), _dev_ptr(poses), n,
                                            _dev_ptr(jr), _dev_ptr(jo), _dev_ptr(nr), _dev_ptr(nq),
                                            _stream_ptr(stream)))
+        return jr, jo, nr, nq
+
+    def score_poses_noalloc(self, scene_id, mesh_id, poses, out, *, label=0, stream=None):
+        """perch_score_poses_noalloc: score_poses into caller-provided outputs
+        out = (jr, jo, nr, nq) (int32 CUDA tensors; nr, nq may be None) with
+        no allocation by the library.  Asynchronous."""
+        import torch
+        if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()):
+            raise ValueError("poses must be a contiguous float32 CUDA tensor")
+        n = poses.numel() // 12
+        jr, jo, nr, nq = out
+        if stream is None:
+            stream = torch.cuda.current_stream(poses.device)
+        _check(self._lib.perch_score_poses_noalloc(self._h, int(scene_id), int(mesh_id), int(label), _dev_ptr(poses),
+                                                   n, _dev_ptr(jr), _dev_ptr(jo), _dev_ptr(nr), _dev_ptr(nq),
+                                                   _stream_ptr(stream)))
         return jr, jo, nr, nq
 
     def score_detail(self, scene_id, mesh_id, poses, *, label=0, stream=None):

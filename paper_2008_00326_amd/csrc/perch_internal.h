@@ -141,6 +141,10 @@ hipError_t launch_hash_build(const SceneDev &s, int *count, long long *blk, hipS
 hipError_t launch_setup(const Work &w, int poses_grid, hipStream_t st);
 hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool any_rgb, bool any_pv, hipStream_t st);
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st);
+// Descriptor block of a launch written by a kernel that takes the bytes by
+// value (no host staging); at most kDescArgBytes bytes.
+constexpr int kDescArgBytes = 512;
+hipError_t launch_desc_write(const void *bytes, size_t n, void *dst, hipStream_t st);
 
 // ICP refinement of candidate poses: arguments of one launch.
 struct IcpArgs {

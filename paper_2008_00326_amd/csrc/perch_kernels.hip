@@ -21,7 +21,7 @@
 #include "perch_device.h"
 
 #include <math.h>
-
+#include <string.h>
 
 namespace perch {
 
@@ -1255,6 +1255,24 @@ hipError_t launch_score_class(const Work &w, const LaunchCfg &c, int cls, bool a
 hipError_t launch_item_argmin(const Work &w, int items_grid, hipStream_t st)
 {
     item_argmin_kernel<<<items_grid, 1024, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+struct DescArg {
+    uint4 w[kDescArgBytes / 16];
+};
+
+__global__ void desc_write_kernel(DescArg a, int n16, uint4 *dst)
+{
+    if ((int)threadIdx.x < n16) dst[threadIdx.x] = a.w[threadIdx.x];
+}
+
+hipError_t launch_desc_write(const void *bytes, size_t n, void *dst, hipStream_t st)
+{
+    if (n > (size_t)kDescArgBytes) return hipErrorInvalidValue;
+    DescArg a{};
+    memcpy(&a, bytes, n);
+    desc_write_kernel<<<1, kDescArgBytes / 16, 0, st>>>(a, (int)((n + 15) / 16), (uint4 *)dst);
     return hipGetLastError();
 }
 

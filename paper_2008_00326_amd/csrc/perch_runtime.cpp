@@ -25,6 +25,37 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Scratch of perch_score_poses_noalloc: launch descriptors, per-pose work,
+// class lists, counters and the device-memory slots of the two largest
+// footprint classes, in one array that each device holds for the life of
+// the process.  Host code uses only the device address that
+// hipGetSymbolAddress returns for it (kept per device), never the name.
+constexpr size_t kNoAllocScratchBytes = (size_t)48 << 20;
+constexpr int kNoAllocMaxPoses = 65536;
+constexpr int kNoAllocMaxPixels = 640 * 480;
+constexpr int kNoAllocGrid2 = 8, kNoAllocGrid3 = 4;   // work-groups of the device-memory classes
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = p;
+    *out = p;
+    return hipSuccess;
+}
+
 perch_status fail(perch_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -146,6 +177,7 @@ struct perch_ctx {
     std::vector<Staging *> scene_stage;   // free pinned staging areas of scene uploads
     int icp_lds_words = 0;                // dynamic LDS words of the ICP kernel
     int msg_lds_words = 0;                // dynamic LDS words of the tree's successor kernel
+    void *noalloc = nullptr;              // this device's address of the allocation-free path's scratch
 
     // released device blocks awaiting reuse, and recycled use-tracking events
     std::vector<CachedBlock> cache;
@@ -712,6 +744,7 @@ perch_status perch_create(int device, size_t hbm_budget_bytes, perch_ctx **out)
     if (e == hipSuccess) e = upload_msg_colour_table(lin);
     if (e == hipSuccess) e = upload_knn1_colour_table(lin);
     if (e == hipSuccess) e = prepare_msg_kernel((int)ctx->lds_max, &ctx->msg_lds_words);
+    if (e == hipSuccess) e = scratch_address(device, &ctx->noalloc);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete ctx;
@@ -1222,6 +1255,62 @@ perch_status perch_score_detail(perch_ctx *ctx, int32_t scene_id, int32_t mesh_i
     const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
     perch_status s = run_direct(ctx, &item, 1, st, false, nullptr, nullptr, rflag_dev, oflag_dev);
     return s ? s : ok();
+}
+
+perch_status perch_score_poses_noalloc(perch_ctx *ctx, int32_t scene_id, int32_t mesh_id, int32_t label,
+                                       const float *poses_dev, int32_t n, int32_t *jr_dev, int32_t *jo_dev,
+                                       int32_t *nr_dev, int32_t *nq_dev, void *hip_stream)
+{
+    const Range range_("perch_score_poses_noalloc");
+    if (perch_status st = enter(ctx)) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (!ctx->noalloc) return fail(PERCH_EDEVICE, "no scratch address on device %d", ctx->device);
+    if (n < 0 || n > kNoAllocMaxPoses)
+        return fail(PERCH_EINVAL, "n = %d: the allocation-free path scores 0 to %d poses per call", n,
+                    kNoAllocMaxPoses);
+    auto si = ctx->scenes.find(scene_id);
+    if (si == ctx->scenes.end()) return fail(PERCH_ENOTFOUND, "unknown scene id %d", scene_id);
+    const SceneDev &sd = si->second.dev;
+    if (sd.flags & PERCH_KNN1)
+        return fail(PERCH_EINVAL, "PERCH_KNN1 scenes need a distance array per pose; use perch_score_poses");
+    if ((long long)sd.W * sd.H > kNoAllocMaxPixels)
+        return fail(PERCH_EINVAL, "scene of %d x %d pixels: the allocation-free path takes at most %d pixels", sd.W,
+                    sd.H, kNoAllocMaxPixels);
+    const perch_work item{scene_id, mesh_id, label, n, poses_dev, jr_dev, jo_dev, nr_dev, nq_dev};
+    Built b;
+    if (perch_status s = build_descriptors(ctx, &item, 1, b)) return s;
+    if (b.n_poses == 0) return ok();
+    if (b.bytes.size() > (size_t)kDescArgBytes)
+        return fail(PERCH_EINVAL, "descriptor block of %zu bytes exceeds %d", b.bytes.size(), kDescArgBytes);
+    LaunchCfg cfg = launch_cfg(ctx);
+    cfg.grid[2] = std::min(cfg.grid[2], kNoAllocGrid2);
+    cfg.grid[3] = std::min(cfg.grid[3], kNoAllocGrid3);
+    size_t sw[kNumClasses], sb[kNumClasses], slot_words = 0, tile_words = 0;
+    slot_layout(cfg, b.max_pixels, sw, sb, &slot_words, &tile_words);
+    // carve the scratch: descriptors | pose info | class lists | counters | slots
+    LaunchBufs lb;
+    size_t off = 0;
+    auto carve = [&](DevBuf &d, size_t bytes) {
+        d.ptr = (char *)ctx->noalloc + off;
+        d.bytes = bytes;
+        off += (bytes + 255) & ~(size_t)255;
+    };
+    carve(lb.desc, kDescArgBytes);
+    carve(lb.info, (size_t)b.n_poses * sizeof(PoseInfo));
+    carve(lb.lists, (size_t)kNumClasses * b.n_poses * sizeof(int));
+    carve(lb.counts, kCounterInts * 4);
+    carve(lb.scratch, slot_words * 4);
+    if (off > kNoAllocScratchBytes)
+        return fail(PERCH_EINVAL, "launch needs %zu scratch bytes, more than %zu", off, kNoAllocScratchBytes);
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    hipError_t e = launch_desc_write(b.bytes.data(), b.bytes.size(), lb.desc.ptr, st);
+    if (e != hipSuccess) return fail(PERCH_EDEVICE, "descriptor write: %s", hipGetErrorString(e));
+    // no CIELAB slots (lb.lab is empty): the J_o colour tests recompute the rendered colours
+    const Work w = make_work(lb, b, b.n_poses, cfg, b.max_pixels, false);
+    e = enqueue(ctx, w, cfg, b.n_poses, b.n_items, b.any_rgb, b.any_pv, st, false);
+    if (e != hipSuccess) return fail(PERCH_EDEVICE, "score launch: %s", hipGetErrorString(e));
+    mark_uses(ctx, b.scene_ids, b.mesh_ids, st);
+    return ok();
 }
 
 perch_status perch_score_batch(perch_ctx *ctx, const perch_work *items, int32_t n_items, void *hip_stream)
