@@ -403,7 +403,10 @@ perch_status perch_msg_search(perch_ctx *ctx, int32_t scene_id, const perch_msg_
  * 1 tile and keys in LDS (256 or 512 threads), 2 tile and keys in LDS (1024
  * threads), 3 tile in LDS and keys in device memory, 4 tile and keys in
  * device memory; 5 argmin, 6 scene preparation, 7 render (and kNN I's rasterization),
- * 8 ICP refinement, 9 tree successors, 10 kNN I distances and reductions. */
+ * 8 ICP refinement, 9 tree successors, 10 kNN I distances and reductions,
+ * 11 a prepared batch's whole graph replay (perch_batch_launch: descriptor
+ * upload, set-up, the four scoring classes, argmin, result download; the
+ * kernels inside a graph are not bracketed one by one). */
 perch_status perch_profile_enable(perch_ctx *ctx, int32_t enable);
 perch_status perch_profile_read(perch_ctx *ctx, int32_t n_slots, double *total_ms, int32_t *launches);
 

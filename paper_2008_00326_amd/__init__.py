@@ -346,7 +346,7 @@ class Context:
                 "key_bands": t.key_bands}
 
     PROFILE_SLOTS = ("setup", "score_lds_small", "score_lds_large", "score_lds_tile", "score_device", "argmin",
-                     "scene_prep", "render", "icp", "msg", "knn1")
+                     "scene_prep", "render", "icp", "msg", "knn1", "batch_graph")
 
     def profile(self, enable: bool = True):
         """Start (clearing the record) or stop bracketing kernel launches with HIP events."""

@@ -45,6 +45,17 @@ __device__ __forceinline__ float4 gld(const float4 *p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Observed point (Xq, Yq, Zq) of scene pixel `pix`: a 12-byte load (the
+// image's fourth word is padding, and a wider load would leave a dead
+// destination register that the allocator reuses before the load lands,
+// forcing a wait) at a 32-bit byte offset from the image base.
+__device__ __forceinline__ int3 opt_at(const int4 *opt, uint32_t pix)
+{
+    typedef int v3i __attribute__((ext_vector_type(3)));
+    const v3i v = *(const PERCH_GLOBAL v3i *)((const PERCH_GLOBAL char *)opt + pix * 16u);
+    return make_int3(v.x, v.y, v.z);
+}
+
 // ------------------------------------------------------------------ geometry
 
 struct Vtx {
@@ -124,6 +135,45 @@ __device__ __forceinline__ Vtx unpack_vtx(int4 q)
     return v;
 }
 
+// Scan of a triangle's pixel box [i0, i1] x [j0, j1]: edge functions
+// stepped incrementally in integer type E (exact either way; see
+// raster_triangle for when 32 bits suffice), covered pixels' binary64
+// perspective depth min-combined into the tile.
+template <bool G, class E>
+__device__ __forceinline__ void raster_box(const Vtx &a, const Vtx &b, const Vtx &c, double farea, int t, int i0,
+                                           int i1, int j0, int j1, int tx0, int ty0, int tw, uint32_t *tile)
+{
+    const E px0 = (E)256 * i0, py0 = (E)256 * j0;
+    E r0 = (E)(c.V - b.V) * (px0 - b.U) - (E)(c.U - b.U) * (py0 - b.V);
+    E r1 = (E)(a.V - c.V) * (px0 - c.U) - (E)(a.U - c.U) * (py0 - c.V);
+    E r2 = (E)(b.V - a.V) * (px0 - a.U) - (E)(b.U - a.U) * (py0 - a.V);
+    const E sx0 = (E)256 * (c.V - b.V), sy0 = (E)-256 * (c.U - b.U);
+    const E sx1 = (E)256 * (a.V - c.V), sy1 = (E)-256 * (a.U - c.U);
+    const E sx2 = (E)256 * (b.V - a.V), sy2 = (E)-256 * (b.U - a.U);
+    const E b0 = (E)edge_bias(b.U, b.V, c.U, c.V);
+    const E b1 = (E)edge_bias(c.U, c.V, a.U, a.V);
+    const E b2 = (E)edge_bias(a.U, a.V, b.U, b.V);
+    for (int j = j0; j <= j1; ++j) {
+        E w0 = r0, w1 = r1, w2 = r2;
+        uint32_t *row = tile + (size_t)(j - ty0) * tw;
+        for (int i = i0; i <= i1; ++i) {
+            if (w0 >= b0 && w1 >= b1 && w2 >= b2) {
+                const double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
+                const double sum = (t0 + t1) + t2;
+                const double d = rint(farea / sum);
+                if (d >= 1.0 && d <= 65534.0)
+                    tmin<G>(row + (i - tx0), ((uint32_t)d << 16) | (uint32_t)t);
+            }
+            w0 += sx0;
+            w1 += sx1;
+            w2 += sx2;
+        }
+        r0 += sy0;
+        r1 += sy1;
+        r2 += sy2;
+    }
+}
+
 // Rasterize triangle t into the tile covering pixels [tx0, tx0+tw) x [ty0, ty0+th).
 // vcache, when given, holds every vertex projected at this pose.
 template <bool G>
@@ -150,36 +200,14 @@ __device__ __forceinline__ void raster_triangle(const SceneDev &s, const MeshDev
     const int i0 = max(-((-minU) >> 8), tx0), i1 = min(maxU >> 8, tx0 + tw - 1);
     const int j0 = max(-((-minV) >> 8), ty0), j1 = min(maxV >> 8, ty0 + th - 1);
     if (i0 > i1 || j0 > j1) return;
-    const long long px0 = 256LL * i0, py0 = 256LL * j0;
-    long long r0 = edge_fn(b.U, b.V, c.U, c.V, px0, py0);
-    long long r1 = edge_fn(c.U, c.V, a.U, a.V, px0, py0);
-    long long r2 = edge_fn(a.U, a.V, b.U, b.V, px0, py0);
-    const long long sx0 = 256LL * (c.V - b.V), sy0 = -256LL * (c.U - b.U);
-    const long long sx1 = 256LL * (a.V - c.V), sy1 = -256LL * (a.U - c.U);
-    const long long sx2 = 256LL * (b.V - a.V), sy2 = -256LL * (b.U - a.U);
-    const long long b0 = edge_bias(b.U, b.V, c.U, c.V);
-    const long long b1 = edge_bias(c.U, c.V, a.U, a.V);
-    const long long b2 = edge_bias(a.U, a.V, b.U, b.V);
-    const double farea = (double)area;
-    for (int j = j0; j <= j1; ++j) {
-        long long w0 = r0, w1 = r1, w2 = r2;
-        uint32_t *row = tile + (size_t)(j - ty0) * tw;
-        for (int i = i0; i <= i1; ++i) {
-            if (w0 >= b0 && w1 >= b1 && w2 >= b2) {
-                const double t0 = (double)w0 * a.iz, t1 = (double)w1 * b.iz, t2 = (double)w2 * c.iz;
-                const double sum = (t0 + t1) + t2;
-                const double d = rint(farea / sum);
-                if (d >= 1.0 && d <= 65534.0)
-                    tmin<G>(row + (i - tx0), ((uint32_t)d << 16) | (uint32_t)t);
-            }
-            w0 += sx0;
-            w1 += sx1;
-            w2 += sx2;
-        }
-        r0 += sy0;
-        r1 += sy1;
-        r2 += sy2;
-    }
+    // Every pixel sample the scan evaluates, one step past the box included,
+    // lies within 256 sub-pixel units of the triangle's box, so each edge
+    // function is bounded by 2 (du + 256)(dv + 256) for box extents du, dv:
+    // below 2^31 when both are under 2^15 - 256, the common case.
+    if (maxU - minU < 32512 && maxV - minV < 32512)
+        raster_box<G, int>(a, b, c, (double)area, t, i0, i1, j0, j1, tx0, ty0, tw, tile);
+    else
+        raster_box<G, long long>(a, b, c, (double)area, t, i0, i1, j0, j1, tx0, ty0, tw, tile);
 }
 
 // ------------------------------------------------------------------ screen boxes

@@ -269,7 +269,7 @@ hipError_t knn1_score(const Knn1Args &a, int p, int L, hipStream_t st);
 
 // Kernel slots reported by the profiler (perch_profile_read).
 enum ProfSlot { kProfSetup = 0, kProfClass0 = 1, kProfArgmin = 5, kProfScenePrep = 6, kProfRender = 7,
-                kProfIcp = 8, kProfMsg = 9, kProfKnn1 = 10, kNumProfSlots = 11 };
+                kProfIcp = 8, kProfMsg = 9, kProfKnn1 = 10, kProfGraph = 11, kNumProfSlots = 12 };
 hipError_t launch_render(const SceneDev &s, const MeshDev &m, const float *poses, int n,
                          uint32_t *keys, uint16_t *depth, uint8_t *rgb, int32_t *tri,
                          hipStream_t st);

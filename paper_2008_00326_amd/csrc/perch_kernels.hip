@@ -59,20 +59,19 @@ template <> struct KeyOf<true> {
 };
 
 // Key update of an observed point q by rendered point (X, Y, Z) with tile
-// index k, if the two lie within delta; dq + 1 < 2^13, so the 24-bit
-// products are exact.
+// index k, if the two lie within delta.  The three offsets saturate to 16
+// bits (v_cvt_pk_i16_i32) and two v_dot2_i32_i16 sum their squares: at most
+// 3 * 2^30 < 2^32, so the sum read unsigned is exact when no offset
+// saturated and exceeds dq^2 (dq < 2^13) when one did.
+typedef short perch_s2 __attribute__((ext_vector_type(2)));
 template <bool G>
-__device__ __forceinline__ void mark_one(int4 q, int X, int Y, int Z, int k, int lim, int dq2,
-                                         typename KeyOf<G>::T *key)
+__device__ __forceinline__ void mark_one(int3 q, int X, int Y, int Z, int k, int dq2, typename KeyOf<G>::T *key)
 {
     using K = KeyOf<G>;
-    // each offset clamped to [-(dq + 1), dq + 1]: a clamped one alone makes
-    // d2 exceed dq^2, and unclamped ones give the exact d2
-    const int dz = clamp_i32(q.z - Z, -lim, lim);   // pixels without a reading clamp (kNoPoint)
-    const int dx = clamp_i32(q.x - X, -lim, lim);
-    const int dy = clamp_i32(q.y - Y, -lim, lim);
-    const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
-    if (d2 <= dq2) K::min(key, K::make(d2, k));
+    const perch_s2 xy = __builtin_amdgcn_cvt_pk_i16(q.x - X, q.y - Y);
+    const perch_s2 z0 = __builtin_amdgcn_cvt_pk_i16(q.z - Z, 0);
+    const uint32_t d2 = (uint32_t)__builtin_amdgcn_sdot2(xy, xy, __builtin_amdgcn_sdot2(z0, z0, 0, false), false);
+    if (d2 <= (uint32_t)dq2) K::min(key, K::make((int)d2, k));
 }
 
 // Per-inlier marking parameters, computed once by the thread that queues
@@ -85,6 +84,31 @@ __device__ __forceinline__ void mark_params(const SceneDev &s, int i, int j, int
     *wuv = window_half(gld(s.ax + i), iz, s.W) | (window_half(gld(s.ay + j), iz, s.H) << 16);
 }
 
+// Scene values the marking loop reads, held in scalar registers for a pose.
+struct MarkScene {
+    const int4 *opt;
+    int W, H, dq2;
+};
+
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ MarkScene mark_scene(const SceneDev &s)
+{
+    MarkScene m;
+    m.opt = uniform_ptr(s.opt);
+    m.W = __builtin_amdgcn_readfirstlane(s.W);
+    m.H = __builtin_amdgcn_readfirstlane(s.H);
+    m.dq2 = __builtin_amdgcn_readfirstlane(s.dq2);
+    return m;
+}
+
 // The whole wave takes one rendered inlier r = (i, j, d), tile index k, and
 // visits every observed pixel of r's window inside the J_o region: each
 // observed point within delta of r min-combines (d2, k) into its key.  This
@@ -94,9 +118,10 @@ __device__ __forceinline__ void mark_params(const SceneDev &s, int i, int j, int
 // first; a larger one no wider than a wave in whole rows per round (64 /
 // width rows, a lane keeps its column and steps its row by a constant),
 // four rounds per iteration; a wider one in row-major order, four pixels
-// per lane per round.
+// per lane per round.  Image and key offsets are 32-bit, products 24-bit
+// (every index here is below 2^24).
 template <bool G>
-__device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, int Y, int wuv,
+__device__ void wave_mark(const MarkScene &s, int i, int j, int d, int k, int X, int Y, int wuv,
                           typename KeyOf<G>::T *keys, int jx0, int jy0, int jw, int jh, int lane)
 {
     const int wu = wuv & 0xFFFF, wv = wuv >> 16;
@@ -105,70 +130,138 @@ __device__ void wave_mark(const SceneDev &s, int i, int j, int d, int k, int X, 
     if (i0 > i1 || j0 > j1) return;
     const int ww = i1 - i0 + 1, wh = j1 - j0 + 1;
     const int Z = 16 * d;
-    const int lim = s.dq + 1, dq2 = s.dq2;
+    const int dq2 = s.dq2;
     const int ws = ww * wh;
+    const int W = s.W;
+    const int pbase = j0 * W + i0;                     // window origin in the image
+    const int kbase = (j0 - jy0) * jw + (i0 - jx0);    // and among the keys
     if (ws <= 256 && ww <= 64) {
         // the whole window in at most four row-major rounds of 64 pixels,
-        // every load issued first; (q * ceil(2^16 / ww)) >> 16 is q / ww
+        // every load issued first (lanes past the window's end load its last
+        // pixel and mark nothing); (q * ceil(2^16 / ww)) >> 16 is q / ww
         // exactly for q < 256
         const uint32_t rc = c_rcp16[ww];
-        int4 q[4];
+        const int4 *wopt = s.opt + pbase;
+        typename KeyOf<G>::T *wkey = keys + kbase;
+        int3 q[4];
         int kk[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int f = 64 * u + lane;
-            const int fy = (int)(((uint32_t)f * rc) >> 16), fx = f - fy * ww;
-            kk[u] = (j0 + fy - jy0) * jw + (i0 + fx - jx0);
-            q[u] = f < ws ? gld(s.opt + (j0 + fy) * s.W + i0 + fx) : make_int4(0, 0, kNoPoint, 0);
+            if (64 * u < ws) {
+                const int f = min(64 * u + lane, ws - 1);
+                const int fy = (int)(__umul24((uint32_t)f, rc) >> 16), fx = __mul24(fy, -ww) + f;
+                kk[u] = __mul24(fy, jw) + fx;
+                q[u] = opt_at(wopt, (uint32_t)(__mul24(fy, W) + fx));
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (64 * u + lane < ws) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk[u]);
+            if (64 * u + lane < ws) mark_one<G>(q[u], X, Y, Z, k, dq2, wkey + kk[u]);
         return;
     }
     if (ww <= 64) {
         const uint32_t rc = c_rcp16[ww];
         const int rows = (int)((64u * rc) >> 16);
-        const int r = (int)(((uint32_t)lane * rc) >> 16), c = lane - r * ww;
+        const int r = (int)(__umul24((uint32_t)lane, rc) >> 16), c = lane - __mul24(r, ww);
         if (r >= rows) return;
-        const int step = rows * s.W, kstep = rows * jw;
-        int pix = (j0 + r) * s.W + i0 + c;
-        int kk = (j0 + r - jy0) * jw + (i0 + c - jx0);
+        const int step = __mul24(rows, W), kstep = __mul24(rows, jw);
+        int pix = pbase + __mul24(r, W) + c;
+        int kk = kbase + __mul24(r, jw) + c;
         int row = r;
         for (; row + 3 * rows < wh; row += 4 * rows) {
-            int4 q[4];
+            int3 q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = gld(s.opt + pix + u * step);
+            for (int u = 0; u < 4; ++u) q[u] = opt_at(s.opt, (uint32_t)(pix + u * step));
 #pragma unroll
-            for (int u = 0; u < 4; ++u) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk + u * kstep);
+            for (int u = 0; u < 4; ++u) mark_one<G>(q[u], X, Y, Z, k, dq2, keys + kk + u * kstep);
             pix += 4 * step;
             kk += 4 * kstep;
         }
-        int4 q[3];
+        int3 q[3];
 #pragma unroll
         for (int u = 0; u < 3; ++u)
-            q[u] = row + u * rows < wh ? gld(s.opt + pix + u * step) : make_int4(0, 0, kNoPoint, 0);
+            q[u] = row + u * rows < wh ? opt_at(s.opt, (uint32_t)(pix + u * step)) : make_int3(0, 0, kNoPoint);
 #pragma unroll
         for (int u = 0; u < 3; ++u)
-            if (row + u * rows < wh) mark_one<G>(q[u], X, Y, Z, k, lim, dq2, keys + kk + u * kstep);
+            if (row + u * rows < wh) mark_one<G>(q[u], X, Y, Z, k, dq2, keys + kk + u * kstep);
         return;
     }
     const float inv = 1.0f / (float)ww;
     for (int q0 = 0; q0 < ws; q0 += 256) {
-        int px[4], py[4];
-        int4 qv[4];
+        int kk[4];
+        int3 qv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int q = q0 + 64 * u + lane;
-            const int qy = window_row(q, ww, inv);
-            px[u] = i0 + (q - qy * ww);
-            py[u] = j0 + qy;
-            qv[u] = q < ws ? gld(s.opt + py[u] * s.W + px[u]) : make_int4(0, 0, kNoPoint, 0);
+            const int qy = window_row(q, ww, inv), qx = q - qy * ww;
+            kk[u] = kbase + qy * jw + qx;
+            qv[u] = q < ws ? opt_at(s.opt, (uint32_t)(pbase + qy * W + qx)) : make_int3(0, 0, kNoPoint);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (q0 + 64 * u + lane < ws)
-                mark_one<G>(qv[u], X, Y, Z, k, lim, dq2, keys + (py[u] - jy0) * jw + (px[u] - jx0));
+            if (q0 + 64 * u + lane < ws) mark_one<G>(qv[u], X, Y, Z, k, dq2, keys + kk[u]);
+    }
+}
+
+// Wave-wide minimum and maximum of a lane value.
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Inliers a wave marks together, one per lane, at least: below it each
+// inlier takes the whole wave (wave_mark), since the lanes' shared offset
+// loop costs the same for few inliers as for 64.
+constexpr int kLanesMin = 32;
+
+// Marking of up to 64 inliers at once, one per lane (`act`): the wave steps
+// through the union of the lanes' windows as offsets (dx, dy) from each
+// lane's own pixel, four offsets per step with every load issued first, and
+// a lane whose own window (clipped to the image and to the band
+// [jx0, jx0 + jw) x [jy0, jy0 + jh)) holds the offset marks that observed
+// pixel.  Queued inliers come from neighbouring tile pixels, so one
+// offset's loads and key updates fall on neighbouring pixels.  Offsets
+// outside a lane's window re-read a pixel of it and mark nothing.
+template <bool G>
+__device__ void wave_mark_lanes(const MarkScene &s, bool act, int i, int j, int d, int k, int X, int Y, int wuv,
+                                typename KeyOf<G>::T *keys, int jx0, int jy0, int jw, int jh)
+{
+    const int wu = wuv & 0xFFFF, wv = wuv >> 16;
+    int x0 = max(max(-wu, -i), jx0 - i), x1 = min(min(wu, s.W - 1 - i), jx0 + jw - 1 - i);
+    int y0 = max(max(-wv, -j), jy0 - j), y1 = min(min(wv, s.H - 1 - j), jy0 + jh - 1 - j);
+    const bool live = act && x0 <= x1 && y0 <= y1;
+    const int DX0 = __builtin_amdgcn_readfirstlane(wave_min(live ? x0 : 1 << 20));
+    const int DX1 = __builtin_amdgcn_readfirstlane(wave_max(live ? x1 : -(1 << 20)));
+    const int DY0 = __builtin_amdgcn_readfirstlane(wave_min(live ? y0 : 1 << 20));
+    const int DY1 = __builtin_amdgcn_readfirstlane(wave_max(live ? y1 : -(1 << 20)));
+    if (DX0 > DX1) return;
+    if (!live) x0 = x1 = y0 = y1 = 0;                 // idle lanes re-read their own pixel
+    const int Z = 16 * d;
+    const int dq2 = s.dq2;
+    const int pix = live ? j * s.W + i : 0;
+    const int kp = (j - jy0) * jw + (i - jx0);
+    for (int dy = DY0; dy <= DY1; ++dy) {
+        const int cy = min(max(dy, y0), y1);
+        const bool rowok = live && cy == dy;
+        const int prow = pix + cy * s.W, krow = kp + cy * jw;
+        for (int dx = DX0; dx <= DX1; dx += 4) {
+            int3 qv[4];
+            int cx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cx[u] = min(max(dx + u, x0), x1);
+                qv[u] = opt_at(s.opt, (uint32_t)(prow + cx[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (rowok && cx[u] == dx + u) mark_one<G>(qv[u], X, Y, Z, k, dq2, keys + krow + cx[u]);
+        }
     }
 }
 
@@ -263,6 +356,18 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Row of tile index k in a tile tw pixels wide (inv = 1 / tw in binary32).
+// An LDS tile holds fewer than 2^16 pixels: there (k + 1/2) / tw, whose
+// fraction lies at least 1 / (2 tw) from an integer, is computed with a
+// relative error below 2^-22 and truncates to the exact quotient.  A
+// device-memory tile can be larger and divides.
+template <bool G>
+__device__ __forceinline__ int tile_row(int k, int tw, float inv)
+{
+    if constexpr (G) return k / tw;
+    else return (int)(((float)k + 0.5f) * inv);
+}
+
 // ------------------------------------------------------------------ per pose
 
 template <int BLOCK, bool G, bool KG, bool RGB, bool PV>
@@ -282,6 +387,8 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
     for (int k = 0; k < 12; ++k) P[k] = it.poses[12 * (size_t)in.local + k];
     const int tpx = in.tw * in.th;
     const int jpx = in.jw * in.jh;
+    const float tinv = 1.0f / (float)max(in.tw, 1);
+    const MarkScene ms = mark_scene(s);
     // class images of the inspection entry point: rendered pixels 1 inlier,
     // 2 no neighbour, 3 colour mismatch, 4 occluded; observed pixels of V(O)
     // 1 explained, 2 no neighbour, 3 colour mismatch
@@ -335,10 +442,10 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
         if (k < tpx) {
             const uint32_t key = tld<G>(tile + k);
             if (key != kEmptyKey) {
-                const int ty = k / in.tw, tx = k - ty * in.tw;
+                const int ty = tile_row<G>(k, in.tw, tinv), tx = k - __mul24(ty, in.tw);
                 const int i = in.tx0 + tx, j = in.ty0 + ty;
                 const int d = (int)(key >> 16);
-                keep = (i % s.stride == 0) && (j % s.stride == 0);
+                keep = s.stride == 1 || ((i % s.stride == 0) && (j % s.stride == 0));
                 if (keep && mark) {
                     const int pix = j * s.W + i;
                     const int dob = gld(s.depth + pix);
@@ -393,7 +500,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 kk = e.x;
                 nn = e.y;
                 const uint32_t key = tld<G>(tile + kk);
-                const int ty = kk / in.tw, tx = kk - ty * in.tw;
+                const int ty = tile_row<G>(kk, in.tw, tinv), tx = kk - __mul24(ty, in.tw);
                 ei = in.tx0 + tx;
                 ej = in.ty0 + ty;
                 ed = (int)(key >> 16);
@@ -413,11 +520,15 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             if (bpx > 0 && !nnm) {
                 int X = 0, Y = 0, wuv = 0;
                 if (lane < n) mark_params(s, ei, ej, ed, &X, &Y, &wuv);
-                for (int t = 0; t < n; ++t)
-                    wave_mark<KG>(s, __builtin_amdgcn_readlane(ei, t), __builtin_amdgcn_readlane(ej, t),
-                                  __builtin_amdgcn_readlane(ed, t), __builtin_amdgcn_readlane(kk, t),
-                                  __builtin_amdgcn_readlane(X, t), __builtin_amdgcn_readlane(Y, t),
-                                  __builtin_amdgcn_readlane(wuv, t), keys, in.jx0, by0, in.jw, bh, lane);
+                if (n >= kLanesMin) {
+                    wave_mark_lanes<KG>(ms, lane < n, ei, ej, ed, kk, X, Y, wuv, keys, in.jx0, by0, in.jw, bh);
+                } else {
+                    for (int t = 0; t < n; ++t)
+                        wave_mark<KG>(ms, __builtin_amdgcn_readlane(ei, t), __builtin_amdgcn_readlane(ej, t),
+                                      __builtin_amdgcn_readlane(ed, t), __builtin_amdgcn_readlane(kk, t),
+                                      __builtin_amdgcn_readlane(X, t), __builtin_amdgcn_readlane(Y, t),
+                                      __builtin_amdgcn_readlane(wuv, t), keys, in.jx0, by0, in.jw, bh, lane);
+                }
             }
         };
         int qc = 0;
@@ -428,15 +539,15 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             if (k < tpx) {
                 const uint32_t key = tld<G>(tile + k);
                 if (key != kEmptyKey) {
-                    const int ty = k / in.tw, tx = k - ty * in.tw;
+                    const int ty = tile_row<G>(k, in.tw, tinv), tx = k - __mul24(ty, in.tw);
                     if (knn2 || hsh) {
                         int X, Y, wuv;
                         mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
                         nn = knn2 ? scan_nn(s, X, Y, 16 * (int)(key >> 16)) : hash_nn(s, X, Y, 16 * (int)(key >> 16));
                     } else {
-                        const int2 th = gld(s.thdr + (in.ty0 + ty) * s.W + in.tx0 + tx);
+                        const int2 th = gld(s.thdr + (uint32_t)((in.ty0 + ty) * s.W + in.tx0 + tx));
                         const int e = (int)(key >> 16) - (th.y & 0xFFFF);
-                        nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + th.x + e) : -1;
+                        nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + (uint32_t)(th.x + e)) : -1;
                     }
                     miss = first && nn < 0;
                     if (rf && first && (nn < 0 || !rgb)) rf[(in.ty0 + ty) * s.W + in.tx0 + tx] = nn < 0 ? 2 : 1;
@@ -478,7 +589,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     lr = gld(labs + kr);       // every keying point is an inlier of the first band
                 } else {
                     const uint32_t key = tld<G>(tile + kr);
-                    const int ty = kr / in.tw, tx = kr - ty * in.tw;
+                    const int ty = tile_row<G>(kr, in.tw, tinv), tx = kr - __mul24(ty, in.tw);
                     lr = srgb_to_lab(triangle_colour(s, m, P, (int)(key & 0xFFFFu), in.tx0 + tx, in.ty0 + ty));
                 }
                 cout = ciede2000(gld(s.olab + pix), lr) > s.tau;
@@ -495,7 +606,7 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 const int vy = window_row(k, in.vw, vinv), vx = k - vy * in.vw;
                 const int i = in.vx0 + vx, j = ra + vy;
                 pix = j * s.W + i;
-                const int4 qo = gld(s.opt + pix);
+                const int3 qo = opt_at(ms.opt, (uint32_t)pix);
                 if (qo.z != kNoPoint) {
                     const int dp = qo.z >> 4;
                     inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, qo.x, qo.y, dp, dl, cyl);

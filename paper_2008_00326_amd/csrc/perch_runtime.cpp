@@ -1984,7 +1984,7 @@ perch_status perch_batch_launch(perch_batch *b, void *hip_stream)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     if (!b->valid) return fail(PERCH_EINVAL, "batch has no valid work (set it again)");
     hipStream_t st = pick_stream(ctx, hip_stream);
-    HIP_TRY(hipGraphLaunch(b->exec[b->any_pv ? 1 : 0], st));
+    HIP_TRY(ctx->timed(kProfGraph, st, [&] { return hipGraphLaunch(b->exec[b->any_pv ? 1 : 0], st); }));
     HIP_TRY(hipEventRecord(b->done, st));
     b->pending = true;
     mark_uses(ctx, b->scene_ids, b->mesh_ids, st);
