@@ -876,16 +876,14 @@ def reduce_profile(root, steps, out_path, cfg, seed):
         vals, _ = _counter_per_dispatch(os.path.join(root, f"copy_{c}"), c)
         per = max(vals.values())                  # KiB of the 1 GiB copy
         cal[c] = {"copy_kib_per_dispatch": per, "expected_kib": 1048576.0, "scale": 1048576.0 / per}
-    runs = {"FETCH_SIZE": ("FETCH_SIZE", ["FETCH_SIZE"]), "WRITE_SIZE": ("WRITE_SIZE", ["WRITE_SIZE"]),
-            "sq": ("sq", ["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_WAVES", "SQ_WAVE_CYCLES",
-                          "SQ_LDS_BANK_CONFLICT"])}
+    # every counter of every --pmc run folder (all but the trace and the copies)
     counters = {}
-    for folder, names in runs.values():
+    for folder in sorted(os.listdir(root)):
+        if folder == "trace" or folder.startswith("copy_") or not os.path.isdir(os.path.join(root, folder)):
+            continue
+        names = sorted({r["Counter_Name"] for r in _csv_rows(os.path.join(root, folder), "counter_collection.csv")})
         for c in names:
-            try:
-                vals, kn = _counter_per_dispatch(os.path.join(root, folder), c)
-            except SystemExit:
-                continue
+            vals, kn = _counter_per_dispatch(os.path.join(root, folder), c)
             if vals:
                 counters[c] = (vals, kn)
     kernels = {}
