@@ -701,6 +701,7 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
             "vs_plain_bound": round(traced_s / max(busy_ms / 1e3, 1e-9), 3),
             "tuning": tuned["tuning"], "tuning_key": tuned["key"], "tuning_cached": tuned["cached"],
             "tuning_default_ms": tuned.get("default_ms"), "tuning_best_ms": tuned.get("ms"),
+            "tuning_fastest_ms": tuned.get("fastest_ms"),
             "kernels_ms": {k: round(v[0] / max(steps, 1), 4) for k, v in prof.items() if v[1]},
             "direct_launch_kernels_ms": {k: round(v[0], 4) for k, v in direct.items() if v[1]}}
 

@@ -35,3 +35,11 @@ def test_cache_round_trip(tmp_path):
     assert autotune.load_cache(path) == rec
     (tmp_path / "sub" / "tune.json").write_text("{not json")
     assert autotune.load_cache(path) == {}
+
+
+def test_a_candidate_must_beat_the_default_by_five_per_cent():
+    trials = [{"tuning": "default", "ms": 100.0}, {"tuning": "a", "ms": 97.0}, {"tuning": "b", "ms": 99.0}]
+    assert autotune.choose(trials)["tuning"] == "default"       # 3 % is within the spread
+    trials.append({"tuning": "c", "ms": 94.0})
+    assert autotune.choose(trials)["tuning"] == "c"             # 6 % faster
+    assert autotune.choose(trials, min_gain=0.10)["tuning"] == "default"
