@@ -80,6 +80,7 @@ def main():
                     help="arrival rate (scenes/s) of the served leg of a plain run, above the plain path's capacity")
     ap.add_argument("--served-seconds", type=float, default=8.0, help="arrival window of the served leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg of a plain run")
+    ap.add_argument("--prep-workers", type=int, default=2, help="preparation threads of the server")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--volume", choices=["aabb", "cyl", "label"], default=None,
                     help="V(O) of the plain run (default: the workload's)")
@@ -116,7 +117,8 @@ def main():
         calibrate_copy()
         return
     if args.reduce_profile:
-        reduce_profile(args.reduce_profile, args.steps, args.profile_out, args.config, args.seed)
+        reduce_profile(args.reduce_profile, args.steps, args.profile_out, args.config, args.seed,
+                       variant=counter_variant(args.volume, args.jo, args.search))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -135,7 +137,7 @@ def main():
 
     if args.config == 5:
         rates = [float(x) for x in args.rates.split(",")]
-        r = served_vs_plain(rates, args.serve_seconds, args.seed)
+        r = served_vs_plain(rates, args.serve_seconds, args.seed, prep_workers=args.prep_workers)
         top = r["rates"][str(rates[0])]
         line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
                 "value": top["served"]["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": len(rates),
@@ -248,6 +250,9 @@ def main():
     avg_s = dom_ms / max(dom_launches, 1) / 1e3
     achieved_tops = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
     hbm_gbs = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    # counters apply only to the workload they were taken on
+    wvar = counter_variant(w.volume, w.jo, w.search)
+    mc = measured_counters(dom, args.config, wvar)
 
     result = {
         "metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
@@ -273,13 +278,11 @@ def main():
                   "window": [info["window_x"], info["window_y"]], "tile_caps": list(caps)},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved_tops, 4), "peak": round(ALU_PEAK_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 5),
-                     "traffic": measured_traffic(dom), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
+                     "traffic": measured_traffic(dom, args.config, wvar), "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 4), "launches": dom_launches,
                      "hbm_achieved_GBs": round(hbm_gbs, 2), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 6),
-                     "valu_issue_frac": (round(measured_counters(dom)["valu_frac_of_39.3T"], 4)
-                                         if measured_counters(dom)
-                                         and measured_counters(dom).get("valu_frac_of_39.3T") is not None
-                                         else None)},
+                     "valu_issue_frac": (round(mc["valu_frac_of_39.3T"], 4)
+                                         if mc and mc.get("valu_frac_of_39.3T") is not None else None)},
         "kernels_ms": {k: round(v[0] / max(args.steps, 1), 4) for k, v in prof.items() if v[1]},
         "tuning": ctx.tuning(),
         "poses_per_class": class_poses,
@@ -301,11 +304,10 @@ def main():
         ctx.set_tuning(None)
         result["batched"] = batched_vs_plain(ctx, args.seed, args.batched_steps, 1, args.batched_scenes,
                                              args.tune_cache)
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     ctx.close()
     if not args.no_served:
-        r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0)
+        r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0,
+                            prep_workers=args.prep_workers)
         top = r["rates"][str(args.served_rate)]
         result["served"] = {"workload": r["workload"], "rate_scenes_per_s": args.served_rate,
                             "seconds": args.served_seconds,
@@ -315,6 +317,9 @@ def main():
                             "offered_poses_per_s": top["offered_poses_per_s"],
                             "kernel_bound_poses_per_s": r.get("kernel_bound_poses_per_s"),
                             "detail": top}
+    # the CPU oracle last: its worker threads share the host with the server's threads
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(result), flush=True)
 
 
@@ -706,7 +711,7 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
             "direct_launch_kernels_ms": {k: round(v[0], 4) for k, v in direct.items() if v[1]}}
 
 
-def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0):
+def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0, prep_workers=2):
     """Poisson arrivals of 6-DoF scenes (8 objects of ~20k triangles, 8,192
     candidates, 640x480 RGB-D; a seeded pool of generated scenes, each arrival
     a new upload of one of them) served two ways on identical schedules: the
@@ -759,7 +764,8 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
             horizon = t0 + seconds + drain_s
             if mode == "served":
                 ex = serve.GpuExecutor(ctx, slots=2, max_items=256, max_poses=65536)
-                srv = serve.Server(ex, budget_bytes=int(budget_gb * 2**30), max_items=256, max_poses=65536)
+                srv = serve.Server(ex, budget_bytes=int(budget_gb * 2**30), max_items=256, max_poses=65536,
+                                   prep_workers=prep_workers)
 
                 def producer():
                     for r in reqs:
@@ -777,7 +783,17 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
                 th.start()
                 done = srv.run()
                 th.join()
-                extra = {"launches": len(srv.batches),
+                def stage(a, b):
+                    v = [(getattr(r, b) - getattr(r, a)) * 1e3 for r in reqs
+                         if getattr(r, a) is not None and getattr(r, b) is not None]
+                    return ({"p50": round(float(np.percentile(v, 50)), 3), "p99": round(float(np.percentile(v, 99)), 3)}
+                            if v else None)
+
+                extra = {"prep_workers": prep_workers,
+                         "stage_ms": {"admission": stage("arrival", "admitted"), "preparation": stage("admitted", "ready"),
+                                      "ready_to_launch": stage("ready", "launched"),
+                                      "launch_to_answer": stage("launched", "done")},
+                         "launches": len(srv.batches),
                          "mean_scenes_per_launch": round(float(np.mean([b[1] for b in srv.batches])), 2)
                          if srv.batches else 0.0, "peak_admitted_MB": round(srv.peak_bytes / 2**20, 1),
                          "mesh_cache_hits": ex.meshes.hits, "mesh_cache_misses": ex.meshes.misses}
@@ -864,7 +880,7 @@ def _counter_per_dispatch(folder, counter):
     return out, names
 
 
-def reduce_profile(root, steps, out_path, cfg, seed):
+def reduce_profile(root, steps, out_path, cfg, seed, variant=None):
     """Counter record of the scoring kernels from rocprofv3 runs of one
     command: durations from the kernel trace and every counter from the
     same dispatches (the last `steps` of each kernel, i.e. the timed step
@@ -909,7 +925,8 @@ def reduce_profile(root, steps, out_path, cfg, seed):
             # wave64 per 4 clocks; no fraction is reported then
             rec["valu_frac_of_39.3T"] = frac if frac <= 1.0 else None
         kernels[slot] = rec
-    out = {"kernel_source_sha": kernel_source_sha(), "config": cfg, "seed": seed, "steps": steps,
+    out = {"kernel_source_sha": kernel_source_sha(), "config": cfg, "seed": seed,
+           "variant": variant or counter_variant(None, None, None), "steps": steps,
            "selection": "the last `steps` dispatches of each kernel in each run (the timed step launches)",
            "calibration": cal, "kernels": kernels}
     with open(out_path, "w") as f:
@@ -930,22 +947,29 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_counters(kernel_slot):
+def counter_variant(volume, jo, search):
+    """The scene options a counter record was taken with (None: the default)."""
+    return {"volume": volume or "aabb", "jo": jo or "exact", "search": search or "table"}
+
+
+def measured_counters(kernel_slot, cfg=2, variant=None):
     """The committed counter record of the kernel (HBM bytes per launch from
     FETCH_SIZE / WRITE_SIZE scaled by a plain copy, executed VALU
-    instructions), or None when the kernel source changed since the
-    counters were taken."""
+    instructions) when it was taken on this workload (configuration and
+    scene options) with this kernel source, else None."""
     path = os.path.join(ROOT, "profiles", "score_kernel_cfg2_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha") != kernel_source_sha():
         return None
+    if rec.get("config") != cfg or rec.get("variant") != (variant or counter_variant(None, None, None)):
+        return None
     return rec.get("kernels", {}).get(kernel_slot)
 
 
-def measured_traffic(kernel_slot):
-    k = measured_counters(kernel_slot)
+def measured_traffic(kernel_slot, cfg=2, variant=None):
+    k = measured_counters(kernel_slot, cfg, variant)
     if not k or k.get("fetch_size_bytes_per_launch") is None or k.get("write_size_bytes_per_launch") is None:
         return None
     return round(k["fetch_size_bytes_per_launch"] + k["write_size_bytes_per_launch"], 1)

@@ -7,9 +7,13 @@ Search").  The server
 * admits requests in arrival order while the device memory they will hold
   (scene images and neighbour table, poses, cost arrays) fits a budget;
   when the next request does not fit it waits for results to free memory;
-* prepares admitted requests on a worker thread -- meshes come from a
-  resident cache keyed by content hash, the scene is uploaded and prepared
-  on the library's own stream -- while the device scores earlier requests;
+* prepares admitted requests on worker threads (one by default) -- meshes
+  come from a resident cache keyed by content hash, the scene is uploaded
+  and prepared on the library's own stream -- while the device scores
+  earlier requests; a preparation waits for the device twice (the table
+  size, the finished scene), and each wait can last as long as a scoring
+  launch that holds every compute unit, so two workers keep the ready
+  queue filled where one cannot;
 * launches prepared requests in batches on a small set of launch slots (two
   by default): a request that becomes ready while a batch runs joins the
   next launch, which is queued behind the running one, so the device never
@@ -74,9 +78,14 @@ class Server:
     budget_bytes:   device memory that admitted, unfinished requests may hold.
     slots:          launch slots of the executor (batches in flight at once).
     max_items, max_poses: capacity of one launch.
+    prep_workers:   threads preparing admitted requests (admission stays in
+                    arrival order; prepared requests are launched oldest first).
     """
 
-    def __init__(self, executor, *, budget_bytes: int, max_items: int, max_poses: int, clock=time.perf_counter):
+    def __init__(self, executor, *, budget_bytes: int, max_items: int, max_poses: int, clock=time.perf_counter,
+                 prep_workers: int = 1):
+        if prep_workers < 1:
+            raise ValueError("prep_workers must be >= 1")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_items = int(max_items)
@@ -93,7 +102,8 @@ class Server:
         self.batches = []                    # (sequence, number of requests, poses)
         self._seq = 0
         self.n_inflight = 0                  # requests launched, not finished
-        self._prep = threading.Thread(target=self._prep_loop, name="perch-prep", daemon=True)
+        self._prep = [threading.Thread(target=self._prep_loop, name=f"perch-prep-{k}", daemon=True)
+                      for k in range(prep_workers)]
         self._prep_error = None
 
     # -- producer side ------------------------------------------------------
@@ -181,7 +191,11 @@ class Server:
                     self.peak_bytes = max(self.peak_bytes, self.inflight_bytes)
                     self.preparing -= 1
                     req.ready = self.clock()
-                    self.ready.append(prep)
+                    # oldest first: a later arrival prepared sooner by another worker waits behind it
+                    k = len(self.ready)
+                    while k > 0 and self.ready[k - 1].req.arrival > req.arrival:
+                        k -= 1
+                    self.ready.insert(k, prep)
                     self.cv.notify_all()
         except BaseException as e:                         # pragma: no cover - surfaced by run()
             with self.cv:
@@ -209,7 +223,8 @@ class Server:
         Returns the completed requests in completion order."""
         free = list(range(self.ex.slots))
         self._inflight = collections.deque()          # (slot, [Prepared], seq)
-        self._prep.start()
+        for t in self._prep:
+            t.start()
         while True:
             with self.cv:
                 if self._prep_error is not None:
@@ -256,7 +271,8 @@ class Server:
             with self.cv:
                 if not (self.ready or (self.closed and not self.queue and not self.preparing)):
                     self.cv.wait(timeout=0.05)
-        self._prep.join()
+        for t in self._prep:
+            t.join()
         return self.completed
 
     def _finish(self, group, results, error):

@@ -66,3 +66,16 @@ def test_reduce_profile_uses_the_timed_dispatches(tmp_path):
     small = rec["kernels"]["score_lds_small"]
     assert abs(small["avg_ms"] - 1.0) < 1e-9 and len(small["dispatches"]) == 3
     assert rec["kernel_source_sha"] == bench.kernel_source_sha()
+    assert rec["variant"] == {"volume": "aabb", "jo": "exact", "search": "table"}
+
+
+def test_counters_apply_only_to_their_workload():
+    """The committed record was taken on the default 640x480 five-object
+    workload; another configuration or scene option reports no counters."""
+    rec = json.load(open(os.path.join(bench.ROOT, "profiles", "score_kernel_cfg2_counters.json")))
+    if rec.get("kernel_source_sha") != bench.kernel_source_sha():
+        return                                    # stale record: None everywhere, checked by the bench itself
+    assert bench.measured_counters("score_lds_large") is not None
+    assert bench.measured_counters("score_lds_large", 3) is None
+    assert bench.measured_traffic("score_lds_large", 2, bench.counter_variant("cyl", None, None)) is None
+    assert bench.measured_traffic("score_lds_small", 2, bench.counter_variant(None, "nn", None)) is None

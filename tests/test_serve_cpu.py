@@ -75,8 +75,8 @@ def make_req(rid, poses=1000, nbytes=100, n_obj=3, **extra):
     return Request(rid, payload, poses)
 
 
-def serve(ex, reqs, *, budget=10_000, max_items=64, max_poses=100_000, spacing=0.0):
-    srv = Server(ex, budget_bytes=budget, max_items=max_items, max_poses=max_poses)
+def serve(ex, reqs, *, budget=10_000, max_items=64, max_poses=100_000, spacing=0.0, prep_workers=1):
+    srv = Server(ex, budget_bytes=budget, max_items=max_items, max_poses=max_poses, prep_workers=prep_workers)
 
     def producer():
         for r in reqs:
@@ -126,6 +126,28 @@ def test_arrivals_join_later_batches():
         assert poses <= 12_000
     # each request is scored exactly once
     assert sorted(x for g in ex.launches for x in g) == list(range(30))
+
+
+def test_two_preparation_workers():
+    """Preparation-bound (preparing takes longer than scoring): a second
+    worker roughly halves the time to answer everything, admission stays in
+    arrival order and every launch takes its requests oldest first."""
+    spans = {}
+    for workers in (1, 2):
+        ex = FakeExecutor(per_pose_s=1e-7, prep_s=0.01)
+        reqs = [make_req(i) for i in range(24)]
+        t0 = time.perf_counter()
+        srv, done = serve(ex, reqs, prep_workers=workers)
+        spans[workers] = time.perf_counter() - t0
+        assert sorted(r.rid for r in done) == list(range(24))
+        assert all(r.error is None and r.result == r.payload["answer"] for r in done)
+        assert [r.rid for r in sorted(done, key=lambda r: r.admitted)] == list(range(24))
+        for g in ex.launches:
+            assert g == sorted(g)
+        assert srv.inflight_bytes == 0 and ex.live_bytes == 0
+    assert spans[2] < 0.8 * spans[1]
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(), budget_bytes=1, max_items=1, max_poses=1, prep_workers=0)
 
 
 def test_failures_stay_with_their_request():
