@@ -532,28 +532,15 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             }
         };
         int qc = 0;
-        for (int k0 = wave * 64; k0 < tpx; k0 += BLOCK) {
-            const int k = k0 + lane;
+        // the queue step of one tile pixel: misses counted, flags, the
+        // inliers queued (whole wave)
+        auto rstep = [&](bool keyed, int k, int pix, int nn) {
             bool miss = false, need = false;
-            int nn = -1;
-            if (k < tpx) {
-                const uint32_t key = tld<G>(tile + k);
-                if (key != kEmptyKey) {
-                    const int ty = tile_row<G>(k, in.tw, tinv), tx = k - __mul24(ty, in.tw);
-                    if (knn2 || hsh) {
-                        int X, Y, wuv;
-                        mark_params(s, in.tx0 + tx, in.ty0 + ty, (int)(key >> 16), &X, &Y, &wuv);
-                        nn = knn2 ? scan_nn(s, X, Y, 16 * (int)(key >> 16)) : hash_nn(s, X, Y, 16 * (int)(key >> 16));
-                    } else {
-                        const int2 th = gld(s.thdr + (uint32_t)((in.ty0 + ty) * s.W + in.tx0 + tx));
-                        const int e = (int)(key >> 16) - (th.y & 0xFFFF);
-                        nn = (e >= 0 && e < (int)((uint32_t)th.y >> 16)) ? gld(s.tnn + (uint32_t)(th.x + e)) : -1;
-                    }
-                    miss = first && nn < 0;
-                    if (rf && first && (nn < 0 || !rgb)) rf[(in.ty0 + ty) * s.W + in.tx0 + tx] = nn < 0 ? 2 : 1;
-                    if (nnm && !rgb && nn >= 0) mark_nn<KG>(bits, nn, s.W, in.jx0, in.jy0, in.jw, in.jh);
-                    need = nn >= 0 && ((rgb && first) || (bpx > 0 && !nnm));
-                }
+            if (keyed) {
+                miss = first && nn < 0;
+                if (rf && first && (nn < 0 || !rgb)) rf[pix] = nn < 0 ? 2 : 1;
+                if (nnm && !rgb && nn >= 0) mark_nn<KG>(bits, nn, s.W, in.jx0, in.jy0, in.jw, in.jh);
+                need = nn >= 0 && ((rgb && first) || (bpx > 0 && !nnm));
             }
             cR += wave_popc(miss);
             const unsigned long long mq = __ballot(need);
@@ -565,6 +552,47 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 if (64 + lane < qc) q[lane] = q[64 + lane];     // the overflow moves to the front
                 qc -= 64;
             }
+        };
+        // tile pixel of index k (clamped into the tile): key and image pixel
+        auto tpixel = [&](int k, uint32_t &key, int &pix) {
+            const int kc = min(k, tpx - 1);
+            key = k < tpx ? tld<G>(tile + kc) : kEmptyKey;
+            const int ty = tile_row<G>(kc, in.tw, tinv), tx = kc - __mul24(ty, in.tw);
+            pix = (in.ty0 + ty) * s.W + in.tx0 + tx;
+        };
+        // two chunks a turn: both chunks' table entries are loaded before
+        // either is queued
+        for (int k0 = wave * 64; k0 < tpx; k0 += 2 * BLOCK) {
+            const int kA = k0 + lane, kB = k0 + BLOCK + lane;
+            uint32_t keyA, keyB;
+            int pA, pB;
+            tpixel(kA, keyA, pA);
+            tpixel(kB, keyB, pB);
+            const bool hA = keyA != kEmptyKey, hB = keyB != kEmptyKey;
+            int nnA = -1, nnB = -1;
+            if (knn2 || hsh) {
+                auto search = [&](uint32_t key, int pix) {
+                    int X, Y, wuv;
+                    const int j = pix / s.W;
+                    mark_params(s, pix - j * s.W, j, (int)(key >> 16), &X, &Y, &wuv);
+                    return knn2 ? scan_nn(s, X, Y, 16 * (int)(key >> 16)) : hash_nn(s, X, Y, 16 * (int)(key >> 16));
+                };
+                if (hA) nnA = search(keyA, pA);
+                if (hB) nnB = search(keyB, pB);
+            } else {
+                // every lane loads (a clamped pixel, entry 0 of the table when
+                // the depth has no entry) and keeps what its key selects
+                const int2 thA = gld(s.thdr + (uint32_t)pA), thB = gld(s.thdr + (uint32_t)pB);
+                const int eA = (int)(keyA >> 16) - (thA.y & 0xFFFF), eB = (int)(keyB >> 16) - (thB.y & 0xFFFF);
+                const bool okA = hA && eA >= 0 && eA < (int)((uint32_t)thA.y >> 16);
+                const bool okB = hB && eB >= 0 && eB < (int)((uint32_t)thB.y >> 16);
+                const int tA = gld(s.tnn + (uint32_t)(okA ? thA.x + eA : 0));
+                const int tB = gld(s.tnn + (uint32_t)(okB ? thB.x + eB : 0));
+                nnA = okA ? tA : -1;
+                nnB = okB ? tB : -1;
+            }
+            rstep(hA, kA, pA, nnA);
+            if (k0 + BLOCK < tpx) rstep(hB, kB, pB, nnB);
         }
         if (qc > 0) flush_r(qc);
         __syncthreads();
@@ -597,16 +625,18 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             }
             cO += wave_popc(cout);
         };
-        qc = 0;
-        for (int k0 = wave * 64; k0 < rpx; k0 += BLOCK) {
-            const int k = k0 + lane;
+        // V pixel of the region's index k (clamped into the region) and its point
+        auto vpixel = [&](int k, int &i, int &j) {
+            const int kc = min(k, rpx - 1);
+            const int vy = window_row(kc, in.vw, vinv), vx = kc - vy * in.vw;
+            i = in.vx0 + vx;
+            j = ra + vy;
+            return j * s.W + i;
+        };
+        auto vtest = [&](bool live, int i, int j, int pix, int3 qo) {
             bool inq = false, out = false, need = false;
-            int pix = 0, kr = 0;
-            if (k < rpx) {
-                const int vy = window_row(k, in.vw, vinv), vx = k - vy * in.vw;
-                const int i = in.vx0 + vx, j = ra + vy;
-                pix = j * s.W + i;
-                const int3 qo = opt_at(ms.opt, (uint32_t)pix);
+            int kr = 0;
+            if (live) {
                 if (qo.z != kNoPoint) {
                     const int dp = qo.z >> 4;
                     inq = label_mode ? (gld(s.labels + pix) == it.label) : in_volume(m, P, qo.x, qo.y, dp, dl, cyl);
@@ -640,6 +670,15 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     qc -= 64;
                 }
             }
+        };
+        qc = 0;
+        // two chunks a turn, both points loaded before either is tested
+        for (int k0 = wave * 64; k0 < rpx; k0 += 2 * BLOCK) {
+            int iA, jA, iB, jB;
+            const int pA = vpixel(k0 + lane, iA, jA), pB = vpixel(k0 + BLOCK + lane, iB, jB);
+            const int3 qA = opt_at(ms.opt, (uint32_t)pA), qB = opt_at(ms.opt, (uint32_t)pB);
+            vtest(k0 + lane < rpx, iA, jA, pA, qA);
+            if (k0 + BLOCK < rpx) vtest(k0 + BLOCK + lane < rpx, iB, jB, pB, qB);
         }
         if (qc > 0) flush_o(qc);
     }
