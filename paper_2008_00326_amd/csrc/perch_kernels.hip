@@ -436,30 +436,44 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
 
     // 2. resolve: occluders (Eq. 3) and the downsampling stride
     int cL = 0;
-    for (int k0 = 0; k0 < tpx; k0 += BLOCK) {
-        const int k = k0 + tid;
-        bool keep = false;
-        if (k < tpx) {
-            const uint32_t key = tld<G>(tile + k);
+    {
+        // tile pixel of index k (clamped into the tile): key and image position
+        auto rpixel = [&](int k, uint32_t &key, int &i, int &j) {
+            const int kc = min(k, tpx - 1);
+            key = k < tpx ? tld<G>(tile + kc) : kEmptyKey;
+            const int ty = tile_row<G>(kc, in.tw, tinv), tx = kc - __mul24(ty, in.tw);
+            i = in.tx0 + tx;
+            j = in.ty0 + ty;
+        };
+        auto resolve = [&](int k, uint32_t key, int i, int j, int dob) {
+            bool keep = false;
             if (key != kEmptyKey) {
-                const int ty = tile_row<G>(k, in.tw, tinv), tx = k - __mul24(ty, in.tw);
-                const int i = in.tx0 + tx, j = in.ty0 + ty;
                 const int d = (int)(key >> 16);
                 keep = s.stride == 1 || ((i % s.stride == 0) && (j % s.stride == 0));
-                if (keep && mark) {
+                if (keep && mark && dob > 0 && 16 * dob + s.dq < 16 * d) {
                     const int pix = j * s.W + i;
-                    const int dob = gld(s.depth + pix);
-                    if (dob > 0 && 16 * dob + s.dq < 16 * d) {
-                        if (!(label_mode && s.labels) || s.labels[pix] != it.label) {
-                            keep = false;
-                            if (rf) rf[pix] = 4;
-                        }
+                    if (!(label_mode && s.labels) || s.labels[pix] != it.label) {
+                        keep = false;
+                        if (rf) rf[pix] = 4;
                     }
                 }
                 if (!keep) tst<G>(tile + k, kEmptyKey);
             }
+            cL += wave_popc(keep);
+        };
+        // two chunks a turn, both observed depths loaded first (every lane
+        // loads, at a clamped pixel)
+        for (int k0 = 0; k0 < tpx; k0 += 2 * BLOCK) {
+            const int kA = k0 + tid, kB = k0 + BLOCK + tid;
+            uint32_t keyA, keyB;
+            int iA, jA, iB, jB;
+            rpixel(kA, keyA, iA, jA);
+            rpixel(kB, keyB, iB, jB);
+            const int dA = mark ? (int)gld(s.depth + (uint32_t)(jA * s.W + iA)) : 0;
+            const int dB = mark ? (int)gld(s.depth + (uint32_t)(jB * s.W + iB)) : 0;
+            resolve(kA, keyA, iA, jA, dA);
+            if (k0 + BLOCK < tpx) resolve(kB, keyB, iB, jB, dB);
         }
-        cL += wave_popc(keep);
     }
     __syncthreads();
 
@@ -560,16 +574,13 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             const int ty = tile_row<G>(kc, in.tw, tinv), tx = kc - __mul24(ty, in.tw);
             pix = (in.ty0 + ty) * s.W + in.tx0 + tx;
         };
-        // two chunks a turn: both chunks' table entries are loaded before
-        // either is queued
-        for (int k0 = wave * 64; k0 < tpx; k0 += 2 * BLOCK) {
-            const int kA = k0 + lane, kB = k0 + BLOCK + lane;
-            uint32_t keyA, keyB;
-            int pA, pB;
-            tpixel(kA, keyA, pA);
-            tpixel(kB, keyB, pB);
-            const bool hA = keyA != kEmptyKey, hB = keyB != kEmptyKey;
-            int nnA = -1, nnB = -1;
+        // four chunks a turn: every chunk's table entries are loaded before
+        // any is queued
+        for (int k0 = wave * 64; k0 < tpx; k0 += 4 * BLOCK) {
+            uint32_t key[4];
+            int pp[4], nn[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) tpixel(k0 + u * BLOCK + lane, key[u], pp[u]);
             if (knn2 || hsh) {
                 auto search = [&](uint32_t key, int pix) {
                     int X, Y, wuv;
@@ -577,22 +588,29 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                     mark_params(s, pix - j * s.W, j, (int)(key >> 16), &X, &Y, &wuv);
                     return knn2 ? scan_nn(s, X, Y, 16 * (int)(key >> 16)) : hash_nn(s, X, Y, 16 * (int)(key >> 16));
                 };
-                if (hA) nnA = search(keyA, pA);
-                if (hB) nnB = search(keyB, pB);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) nn[u] = key[u] != kEmptyKey ? search(key[u], pp[u]) : -1;
             } else {
                 // every lane loads (a clamped pixel, entry 0 of the table when
                 // the depth has no entry) and keeps what its key selects
-                const int2 thA = gld(s.thdr + (uint32_t)pA), thB = gld(s.thdr + (uint32_t)pB);
-                const int eA = (int)(keyA >> 16) - (thA.y & 0xFFFF), eB = (int)(keyB >> 16) - (thB.y & 0xFFFF);
-                const bool okA = hA && eA >= 0 && eA < (int)((uint32_t)thA.y >> 16);
-                const bool okB = hB && eB >= 0 && eB < (int)((uint32_t)thB.y >> 16);
-                const int tA = gld(s.tnn + (uint32_t)(okA ? thA.x + eA : 0));
-                const int tB = gld(s.tnn + (uint32_t)(okB ? thB.x + eB : 0));
-                nnA = okA ? tA : -1;
-                nnB = okB ? tB : -1;
+                int2 th[4];
+                bool ok[4];
+                int e[4], t[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) th[u] = gld(s.thdr + (uint32_t)pp[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    e[u] = (int)(key[u] >> 16) - (th[u].y & 0xFFFF);
+                    ok[u] = key[u] != kEmptyKey && e[u] >= 0 && e[u] < (int)((uint32_t)th[u].y >> 16);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) t[u] = gld(s.tnn + (uint32_t)(ok[u] ? th[u].x + e[u] : 0));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) nn[u] = ok[u] ? t[u] : -1;
             }
-            rstep(hA, kA, pA, nnA);
-            if (k0 + BLOCK < tpx) rstep(hB, kB, pB, nnB);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k0 + u * BLOCK < tpx) rstep(key[u] != kEmptyKey, k0 + u * BLOCK + lane, pp[u], nn[u]);
         }
         if (qc > 0) flush_r(qc);
         __syncthreads();
@@ -672,13 +690,17 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
             }
         };
         qc = 0;
-        // two chunks a turn, both points loaded before either is tested
-        for (int k0 = wave * 64; k0 < rpx; k0 += 2 * BLOCK) {
-            int iA, jA, iB, jB;
-            const int pA = vpixel(k0 + lane, iA, jA), pB = vpixel(k0 + BLOCK + lane, iB, jB);
-            const int3 qA = opt_at(ms.opt, (uint32_t)pA), qB = opt_at(ms.opt, (uint32_t)pB);
-            vtest(k0 + lane < rpx, iA, jA, pA, qA);
-            if (k0 + BLOCK < rpx) vtest(k0 + BLOCK + lane < rpx, iB, jB, pB, qB);
+        // four chunks a turn, every point loaded before any is tested
+        for (int k0 = wave * 64; k0 < rpx; k0 += 4 * BLOCK) {
+            int ii[4], jj[4], pp[4];
+            int3 qq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pp[u] = vpixel(k0 + u * BLOCK + lane, ii[u], jj[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qq[u] = opt_at(ms.opt, (uint32_t)pp[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k0 + u * BLOCK < rpx) vtest(k0 + u * BLOCK + lane < rpx, ii[u], jj[u], pp[u], qq[u]);
         }
         if (qc > 0) flush_o(qc);
     }
