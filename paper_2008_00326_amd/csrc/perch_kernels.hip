@@ -84,6 +84,27 @@ __device__ __forceinline__ void mark_params(const SceneDev &s, int i, int j, int
     *wuv = window_half(gld(s.ax + i), iz, s.W) | (window_half(gld(s.ay + j), iz, s.H) << 16);
 }
 
+// Squared pixel radius of the ellipse that holds every observed neighbour
+// of rendered point r = (i, j, d), in column units: an observed point within
+// delta of r sits at column and row offsets (di, dj) with
+// di^2 + (fx/fy)^2 dj^2 <= fx^2 (1 + xh^2 + yh^2) e^2 / (d - e)^2, where
+// e = delta + 1/4 mm (the 1/16 mm rounding of both points inside it) and
+// (xh, yh) = ((i - cx)/fx, (j - cy)/fy).  With o - r = v, |v| <= e, the
+// column offset is fx (v_x - xh v_z) / (d + v_z): the numerators of both
+// offsets are M v with M = [1 0 -xh; 0 1 -yh], whose largest singular value
+// is sqrt(1 + xh^2 + yh^2), and d + v_z >= d - e.  The binary32 value is
+// raised by 1e-5 relative, above its rounding; infinity when d - e <= 1 mm,
+// where no bound is taken.
+__device__ __forceinline__ float mark_ellipse(const SceneDev &s, int i, int j, int d)
+{
+    const float e = s.delta + 0.25f;
+    const float den = (float)d - e;
+    if (!(den > 1.0f)) return INFINITY;
+    const float xh = ((float)i - s.cx) / s.fx, yh = ((float)j - s.cy) / s.fy;
+    const float r = s.fx * e / den;
+    return r * r * (1.0f + xh * xh + yh * yh) * 1.00001f;
+}
+
 // Scene values the marking loop reads, held in scalar registers for a pose.
 struct MarkScene {
     const int4 *opt;
@@ -225,12 +246,14 @@ constexpr int kLanesMin = 32;
 // lane's own pixel, four offsets per step with every load issued first, and
 // a lane whose own window (clipped to the image and to the band
 // [jx0, jx0 + jw) x [jy0, jy0 + jh)) holds the offset marks that observed
-// pixel.  Queued inliers come from neighbouring tile pixels, so one
-// offset's loads and key updates fall on neighbouring pixels.  Offsets
+// pixel.  Each row of offsets is cut to the chord of the largest of the
+// lanes' neighbour ellipses (E: mark_ellipse; c2 = (fx/fy)^2), which holds
+// every lane's own.  Queued inliers come from neighbouring tile pixels, so
+// one offset's loads and key updates fall on neighbouring pixels.  Offsets
 // outside a lane's window re-read a pixel of it and mark nothing.
 template <bool G>
 __device__ void wave_mark_lanes(const MarkScene &s, bool act, int i, int j, int d, int k, int X, int Y, int wuv,
-                                typename KeyOf<G>::T *keys, int jx0, int jy0, int jw, int jh)
+                                float E, float c2, typename KeyOf<G>::T *keys, int jx0, int jy0, int jw, int jh)
 {
     const int wu = wuv & 0xFFFF, wv = wuv >> 16;
     int x0 = max(max(-wu, -i), jx0 - i), x1 = min(min(wu, s.W - 1 - i), jx0 + jw - 1 - i);
@@ -241,16 +264,24 @@ __device__ void wave_mark_lanes(const MarkScene &s, bool act, int i, int j, int 
     const int DY0 = __builtin_amdgcn_readfirstlane(wave_min(live ? y0 : 1 << 20));
     const int DY1 = __builtin_amdgcn_readfirstlane(wave_max(live ? y1 : -(1 << 20)));
     if (DX0 > DX1) return;
+    // non-negative binary32 values order as their bit patterns
+    const float Em = __int_as_float(__builtin_amdgcn_readfirstlane(wave_max(live ? __float_as_int(E) : 0)));
     if (!live) x0 = x1 = y0 = y1 = 0;                 // idle lanes re-read their own pixel
     const int Z = 16 * d;
     const int dq2 = s.dq2;
     const int pix = live ? j * s.W + i : 0;
     const int kp = (j - jy0) * jw + (i - jx0);
     for (int dy = DY0; dy <= DY1; ++dy) {
+        // the chord's half-width, rounded up past the binary32 error (the
+        // row term lowered by 1e-5 relative, the root raised)
+        const float t = Em - c2 * (float)(dy * dy) * 0.99999f;
+        if (!(t >= 0.0f)) continue;
+        const int hw = __builtin_amdgcn_readfirstlane((int)fminf(sqrtf(t) * 1.00001f, 65536.0f));
+        const int rx0 = max(DX0, -hw), rx1 = min(DX1, hw);
         const int cy = min(max(dy, y0), y1);
         const bool rowok = live && cy == dy;
         const int prow = pix + cy * s.W, krow = kp + cy * jw;
-        for (int dx = DX0; dx <= DX1; dx += 4) {
+        for (int dx = rx0; dx <= rx1; dx += 4) {
             int3 qv[4];
             int cx[4];
 #pragma unroll
@@ -535,7 +566,9 @@ __device__ void score_pose(const Work &w, int p, uint32_t *tile, typename KeyOf<
                 int X = 0, Y = 0, wuv = 0;
                 if (lane < n) mark_params(s, ei, ej, ed, &X, &Y, &wuv);
                 if (n >= kLanesMin) {
-                    wave_mark_lanes<KG>(ms, lane < n, ei, ej, ed, kk, X, Y, wuv, keys, in.jx0, by0, in.jw, bh);
+                    const float E = lane < n ? mark_ellipse(s, ei, ej, ed) : 0.0f;
+                    const float c2 = (s.fx / s.fy) * (s.fx / s.fy);
+                    wave_mark_lanes<KG>(ms, lane < n, ei, ej, ed, kk, X, Y, wuv, E, c2, keys, in.jx0, by0, in.jw, bh);
                 } else {
                     for (int t = 0; t < n; ++t)
                         wave_mark<KG>(ms, __builtin_amdgcn_readlane(ei, t), __builtin_amdgcn_readlane(ej, t),

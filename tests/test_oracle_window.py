@@ -11,7 +11,10 @@ The bound behind every window in this repository (oracle and HIP path alike)
 is checked separately by enumerating neighbour pairs: two back-projected pixel
 centres whose 1/16 mm points lie within delta are at most
 floor(f e sqrt(1 + ((i - c)/f)^2) / (Z - e)) pixels apart along each axis,
-with e = delta + 1/4 mm, (i, Z) the pixel and depth of either point.
+with e = delta + 1/4 mm, (i, Z) the pixel and depth of either point.  The
+HIP path's marking also cuts each row of a window to the joint bound
+(di/fx)^2 + (dj/fy)^2 <= (1 + xh^2 + yh^2) e^2 / (Z - e)^2, with
+(xh, yh) = ((i - cx)/fx, (j - cy)/fy): checked on the same pairs.
 """
 import numpy as np
 import pytest
@@ -141,7 +144,7 @@ def test_window_bound_holds_for_every_neighbour_pair(K, delta):
     rng = np.random.default_rng(int(fx * 7 + delta))
     dq = int(np.rint(16.0 * delta))
     e = delta + 0.25
-    checked = edge = 0
+    checked = edge = ell_edge = 0
     for depth in _surfaces(rng, K, 6):
         X, Y, Z = _points(K, depth)
         valid = depth > 0
@@ -152,6 +155,9 @@ def test_window_bound_holds_for_every_neighbour_pair(K, delta):
         bu = np.where(ok, fx * e * np.sqrt(1.0 + ((ii - cx) / fx) ** 2) / np.where(ok, den, 1.0), np.inf)
         bv = np.where(ok, fy * e * np.sqrt(1.0 + ((jj - cy) / fy) ** 2) / np.where(ok, den, 1.0), np.inf)
         fu, fv = np.floor(bu), np.floor(bv)
+        # joint (ellipse) bound: squared normalised radius of every neighbour
+        r2 = np.where(ok, (1.0 + ((ii - cx) / fx) ** 2 + ((jj - cy) / fy) ** 2) * e * e
+                      / np.where(ok, den, 1.0) ** 2, np.inf)
         R = int(min(np.nanmax(np.where(ok, fu, 0)), W - 1)) + 3
         Rv = int(min(np.nanmax(np.where(ok, fv, 0)), H - 1)) + 3
         for dj in range(-Rv, Rv + 1):
@@ -176,9 +182,13 @@ def test_window_bound_holds_for_every_neighbour_pair(K, delta):
                 n = int(pair.sum())
                 checked += n
                 # the bound from r's side and from p's side
+                q = (di / fx) ** 2 + (dj / fy) ** 2
                 for f_u, f_v, s in ((fu, fv, sr), (fu, fv, sp)):
                     assert np.all(abs(di) <= f_u[s][pair]), f"column offset {di} beyond the bound"
                     assert np.all(abs(dj) <= f_v[s][pair]), f"row offset {dj} beyond the bound"
+                    assert np.all(q <= r2[s][pair]), f"offset ({di}, {dj}) beyond the joint bound"
                 edge += int((pair & ((abs(di) == fu[sr]) | (abs(dj) == fv[sr]))).sum())
+                ell_edge += int((pair & (q > 0.8 * r2[sr])).sum())
     assert checked > 10**6
     assert edge > 100                       # the bound is met with equality: no slack to spare
+    assert ell_edge > 100                   # and pairs come near the joint bound
