@@ -1,6 +1,8 @@
 """The served form on the device: requests prepared while others score,
 launched in shared batches, must each get exactly the answer of scoring
-their scene alone."""
+their scene alone -- and that answer is the oracle's minimum (Sec. IV-A,
+"Parallel Search"; with the colour term, a choice that costs no more than
+the oracle's optimum within the binary32 colour tolerance)."""
 import dataclasses
 import sys
 import threading
@@ -13,9 +15,11 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402
 import paper_2008_00326_amd as pk  # noqa: E402
 from paper_2008_00326_amd import serve  # noqa: E402
 from paper_2008_00326_amd.workloads import make_config  # noqa: E402
+from tiny_meshes import TMesh, TScene  # noqa: E402
 
 
 def say(msg):
@@ -48,10 +52,39 @@ def alone(ctx, w):
     return [(int(a), int(b)) for a, b in zip(bi, bc)]
 
 
+def oracle_best(w):
+    """Per object: the oracle's counts of every candidate (windowed exact
+    search, equal to brute force) and its minimum."""
+    f = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0)
+    f |= {"aabb": oracle.VOL_AABB, "cyl": oracle.VOL_CYL, "label": oracle.VOL_LABEL}[w.volume]
+    sc = TScene(w.scene.K, w.scene.depth, w.scene.rgb if w.use_rgb else None, w.scene.labels)
+    out = []
+    for o in w.objects:
+        mesh = w.meshes[o.mesh]
+        m = mesh if w.use_rgb else TMesh(mesh.xyz, mesh.tri, None)
+        jr, jo, L, Q = oracle.score(m, sc, o.poses, delta_mm=w.delta_mm, tau_c=w.tau_c, flags=f, stride=w.stride,
+                                    label=o.label, threads=0, search="window")
+        out.append((jr, jo, L, Q, oracle.best(jr, jo)[:2]))
+    return out
+
+
+def check_against_oracle(w, answer, exp, what):
+    for k, ((bi, bc), (jr, jo, L, Q, (ebi, ebc))) in enumerate(zip(answer, exp)):
+        if (bi, bc) == (ebi, ebc):
+            continue
+        assert w.use_rgb, f"{what} object {k}: ({bi}, {bc}) against the oracle's ({ebi}, {ebc})"
+        EJ = jr.astype(np.int64) + jo
+        tol = np.ceil(0.001 * L) + np.ceil(0.001 * Q)
+        assert abs(bc - EJ[bi]) <= tol[bi], f"{what} object {k}: cost {bc} of pose {bi}, oracle {EJ[bi]}"
+        assert EJ[bi] <= ebc + tol[bi] + tol[ebi], f"{what} object {k}: pose {bi} against the oracle's {ebi}"
+
+
 def test_served_results_equal_alone(ctx):
     pool = [small(make_config(3, 0), 160), small(make_config(2, 1), 300), small(make_config(3, 2), 200)]
     ref = [alone(ctx, w) for w in pool]
-    say("references done")
+    for k, w in enumerate(pool):
+        check_against_oracle(w, ref[k], oracle_best(w), f"scene {k}")
+    say("references done, equal to the oracle's minima")
     ex = serve.GpuExecutor(ctx, slots=2, max_items=64, max_poses=6000)
     srv = serve.Server(ex, budget_bytes=300 << 20, max_items=64, max_poses=6000)
     reqs = [serve.Request(k, pool[k % 3], pool[k % 3].n_poses) for k in range(9)]
