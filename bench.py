@@ -289,6 +289,20 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
     }
 
+    # the served leg first: run after the many-scene leg, its scene preparations took three times as long
+    # (12.5 against 3.9 ms at the median) and every launch then held a single request
+    if not args.no_served:
+        r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0,
+                            prep_workers=args.prep_workers)
+        top = r["rates"][str(args.served_rate)]
+        result["served"] = {"workload": r["workload"], "rate_scenes_per_s": args.served_rate,
+                            "seconds": args.served_seconds,
+                            "served_poses_per_s": top["served"]["poses_per_s"],
+                            "plain_poses_per_s": top["plain"]["poses_per_s"], "vs_plain": top["vs_plain"],
+                            "latency_ms": {"served": top["served"]["latency_ms"], "plain": top["plain"]["latency_ms"]},
+                            "offered_poses_per_s": top["offered_poses_per_s"],
+                            "kernel_bound_poses_per_s": r.get("kernel_bound_poses_per_s"),
+                            "detail": top}
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
     if args.knn_sample > 0:
@@ -305,18 +319,6 @@ def main():
         result["batched"] = batched_vs_plain(ctx, args.seed, args.batched_steps, 1, args.batched_scenes,
                                              args.tune_cache)
     ctx.close()
-    if not args.no_served:
-        r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0,
-                            prep_workers=args.prep_workers)
-        top = r["rates"][str(args.served_rate)]
-        result["served"] = {"workload": r["workload"], "rate_scenes_per_s": args.served_rate,
-                            "seconds": args.served_seconds,
-                            "served_poses_per_s": top["served"]["poses_per_s"],
-                            "plain_poses_per_s": top["plain"]["poses_per_s"], "vs_plain": top["vs_plain"],
-                            "latency_ms": {"served": top["served"]["latency_ms"], "plain": top["plain"]["latency_ms"]},
-                            "offered_poses_per_s": top["offered_poses_per_s"],
-                            "kernel_bound_poses_per_s": r.get("kernel_bound_poses_per_s"),
-                            "detail": top}
     # the CPU oracle last: its worker threads share the host with the server's threads
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
@@ -789,7 +791,12 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
                     return ({"p50": round(float(np.percentile(v, 50)), 3), "p99": round(float(np.percentile(v, 99)), 3)}
                             if v else None)
 
+                def p50(attr):
+                    v = [getattr(r, attr) * 1e3 for r in reqs if getattr(r, attr) is not None]
+                    return round(float(np.percentile(v, 50)), 3) if v else None
+
                 extra = {"prep_workers": prep_workers,
+                         "preparation_p50_ms": {"set_scene": p50("scene_s"), "pose_upload": p50("upload_s")},
                          "stage_ms": {"admission": stage("arrival", "admitted"), "preparation": stage("admitted", "ready"),
                                       "ready_to_launch": stage("ready", "launched"),
                                       "launch_to_answer": stage("launched", "done")},

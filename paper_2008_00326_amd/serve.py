@@ -57,6 +57,8 @@ class Request:
     result: list | None = None          # per object (best index, J)
     error: str | None = None
     batch: int | None = None            # sequence number of the launch that scored it
+    scene_s: float | None = None        # of the preparation: time in set_scene
+    upload_s: float | None = None       # and in the pose upload
 
     @property
     def latency(self) -> float | None:
@@ -413,7 +415,7 @@ class GpuExecutor:
         self.meshes = MeshCache(ctx, mesh_cache_bytes)
         self.batches = [ctx.batch(max_items, max_poses, max_image_pixels) for _ in range(slots)]
         self.stream = torch.cuda.Stream()
-        self.prep_stream = torch.cuda.Stream()
+        self._local = threading.local()          # a copy stream per preparation thread
         self.n_items = [0] * slots
         self.table_bytes_per_px = 400.0           # running estimate of the neighbour table size
 
@@ -425,6 +427,7 @@ class GpuExecutor:
         return int(px * (per_px + self.table_bytes_per_px) + req.n_poses * (48 + 8))
 
     def prepare(self, req: Request) -> Prepared:
+        import numpy as np
         import torch
         import paper_2008_00326_amd as pk
         w = req.payload
@@ -434,6 +437,7 @@ class GpuExecutor:
             keys.append(k)
             mids.append(mid)
         s = w.scene
+        t0 = time.perf_counter()
         try:
             sid = self.ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None,
                                      s.labels if w.volume == "label" else None, delta_mm=w.delta_mm,
@@ -445,15 +449,26 @@ class GpuExecutor:
             if e.status == -2:
                 raise OutOfMemory(str(e)) from e
             raise
-        items, tensors = [], []
-        with torch.cuda.stream(self.prep_stream):
-            for o, mid in zip(w.objects, mids):
-                p = torch.from_numpy(o.poses).pin_memory().to("cuda", non_blocking=True)
-                tensors.append(p)
-                items.append({"scene": sid, "mesh": mid, "label": o.label, "poses": p,
-                              "jr": torch.empty(p.shape[0], dtype=torch.int32, device="cuda"),
-                              "jo": torch.empty(p.shape[0], dtype=torch.int32, device="cuda")})
-        self.prep_stream.synchronize()
+        t1 = time.perf_counter()
+        # every object's poses in one copy (and one allocation for the costs);
+        # the items take row slices
+        st = getattr(self._local, "stream", None)
+        if st is None:
+            st = self._local.stream = torch.cuda.Stream()
+        counts = [o.poses.shape[0] for o in w.objects]
+        allp = np.ascontiguousarray(np.concatenate([o.poses for o in w.objects]), dtype=np.float32)
+        with torch.cuda.stream(st):
+            dev = torch.from_numpy(allp).to("cuda")
+            costs = torch.empty((2, allp.shape[0]), dtype=torch.int32, device="cuda")
+        items, tensors = [], [dev, costs]
+        k = 0
+        for o, mid, n in zip(w.objects, mids, counts):
+            items.append({"scene": sid, "mesh": mid, "label": o.label, "poses": dev[k:k + n],
+                          "jr": costs[0, k:k + n], "jo": costs[1, k:k + n]})
+            k += n
+        st.synchronize()
+        req.scene_s = t1 - t0
+        req.upload_s = time.perf_counter() - t1
         info = self.ctx.scene_info(sid)
         W, H = int(s.K[0]), int(s.K[1])
         self.table_bytes_per_px = max(self.table_bytes_per_px, info["table_entries"] * 4.0 / (W * H))
