@@ -112,9 +112,15 @@ def main():
                          "copy_FETCH_SIZE, copy_WRITE_SIZE) to the per-launch counter record of the last --steps "
                          "dispatches of each scoring kernel, written to --profile-out")
     ap.add_argument("--profile-out", default=os.path.join(ROOT, "profiles", "score_kernel_cfg2_counters.json"))
+    ap.add_argument("--trace-gaps", default=None, metavar="DIR",
+                    help="only read a rocprofv3 kernel + marker trace of a --config 4 run under DIR and print, per "
+                         "pass of the plain loop and per graph launch, the GPU's busy share and idle gaps")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.trace_gaps:
+        trace_gaps(args.trace_gaps)
         return
     if args.reduce_profile:
         reduce_profile(args.reduce_profile, args.steps, args.profile_out, args.config, args.seed,
@@ -942,6 +948,59 @@ def reduce_profile(root, steps, out_path, cfg, seed, variant=None):
                           "traffic_GB": round((v.get("fetch_size_bytes_per_launch", 0)
                                                + v.get("write_size_bytes_per_launch", 0)) / 1e9, 4)}
                       for k, v in kernels.items()}), flush=True)
+
+
+def trace_gaps(root):
+    """GPU idle time of the many-scene run from its rocprofv3 trace: the
+    roctx ranges of the library's entry points delimit each pass of the plain
+    loop (one perch_best_poses per scene) and each graph launch; within each,
+    the union of kernel intervals is the busy time and what lies between
+    kernels the idle gaps."""
+    marks = _csv_rows(root, "marker_api_trace.csv")
+    kern = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in _csv_rows(root, "kernel_trace.csv"))
+    best = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in marks
+                  if r["Function"] == "perch_best_poses")
+    graph = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in marks
+                   if r["Function"] == "perch_batch_launch")
+    n_scenes = sum(1 for r in marks if r["Function"] == "perch_set_scene")
+
+    def window(t0, t1):
+        busy, gaps, cur = 0, [], None
+        for a, b in kern:
+            if b <= t0 or a >= t1:
+                continue
+            a, b = max(a, t0), min(b, t1)
+            if cur is None:
+                cur = [a, b]
+            elif a > cur[1]:
+                busy += cur[1] - cur[0]
+                gaps.append(a - cur[1])
+                cur = [a, b]
+            else:
+                cur[1] = max(cur[1], b)
+        if cur is not None:
+            busy += cur[1] - cur[0]
+        return busy, gaps
+
+    out = {"scenes": n_scenes, "plain_passes": [], "graph_launches": []}
+    for k in range(len(best) // max(n_scenes, 1)):
+        seg = best[k * n_scenes:(k + 1) * n_scenes]
+        t0, t1 = seg[0][0], max(b for a, b in kern if a < seg[-1][1])
+        busy, gaps = window(t0, t1)
+        out["plain_passes"].append({"wall_ms": round((t1 - t0) / 1e6, 3), "busy_frac": round(busy / (t1 - t0), 5),
+                                    "gaps": len(gaps), "gaps_ms": round(sum(gaps) / 1e6, 3),
+                                    "largest_gap_ms": round(max(gaps, default=0) / 1e6, 4)})
+    for n, (a, _) in enumerate(graph):
+        # up to the next call into the library
+        nxt = min((int(r["Start_Timestamp"]) for r in marks if int(r["Start_Timestamp"]) > a), default=1 << 62)
+        ends = [e for s_, e in kern if a <= s_ < nxt]
+        if not ends:
+            continue
+        t1 = max(ends)
+        busy, gaps = window(a, t1)
+        out["graph_launches"].append({"wall_ms": round((t1 - a) / 1e6, 3), "busy_frac": round(busy / (t1 - a), 5),
+                                      "gaps": len(gaps), "gaps_ms": round(sum(gaps) / 1e6, 3)})
+    print(json.dumps(out), flush=True)
 
 
 def kernel_source_sha():

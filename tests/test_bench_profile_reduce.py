@@ -79,3 +79,31 @@ def test_counters_apply_only_to_their_workload():
     assert bench.measured_counters("score_lds_large", 3) is None
     assert bench.measured_traffic("score_lds_large", 2, bench.counter_variant("cyl", None, None)) is None
     assert bench.measured_traffic("score_lds_small", 2, bench.counter_variant(None, "nn", None)) is None
+
+
+def test_trace_gaps_from_marker_ranges(tmp_path, capsys):
+    """Plain passes and graph launches are delimited by the library's roctx
+    ranges; busy time is the union of kernel intervals, gaps what lies
+    between them."""
+    root = str(tmp_path)
+    ms = 1_000_000
+    marks = [["perch_set_scene", 0, ms], ["perch_set_scene", ms, 2 * ms]]
+    kern = []
+    # one plain pass over the two scenes (each call returns once its kernels are done): kernels 10-20,
+    # 21-30 (1 ms gap), 30-40 (touching), 41-50 (1 ms gap)
+    marks += [["perch_best_poses", 10 * ms, 20 * ms + ms // 2], ["perch_best_poses", 21 * ms, 50 * ms + ms // 2]]
+    kern += [[10 * ms, 20 * ms], [21 * ms, 30 * ms], [30 * ms, 40 * ms], [41 * ms, 50 * ms]]
+    # one graph launch: overlapping kernels 60-70 and 65-80, then a later call at 100
+    marks += [["perch_batch_launch", 60 * ms, 61 * ms], ["perch_score_batch", 100 * ms, 101 * ms]]
+    kern += [[60 * ms, 70 * ms], [65 * ms, 80 * ms], [100 * ms, 110 * ms]]
+    _write(os.path.join(root, "t", "x_marker_api_trace.csv"), ["Function", "Start_Timestamp", "End_Timestamp"],
+           [[f, a, b] for f, a, b in marks])
+    _write(os.path.join(root, "t", "x_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           [["k", a, b] for a, b in kern])
+    bench.trace_gaps(root)
+    out = json.loads(capsys.readouterr().out)
+    assert out["scenes"] == 2
+    (p,) = out["plain_passes"]
+    assert p["wall_ms"] == 40.0 and p["gaps"] == 2 and p["gaps_ms"] == 2.0 and abs(p["busy_frac"] - 38 / 40) < 1e-9
+    (g,) = out["graph_launches"]
+    assert g["wall_ms"] == 20.0 and g["gaps"] == 0 and g["busy_frac"] == 1.0
