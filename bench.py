@@ -410,7 +410,7 @@ def refine_leg(ctx, w, mids, steps, cpu_sample):
         import oracle
         rng = np.random.default_rng(7)
         per = max(1, cpu_sample // len(w.objects))
-        threads = min(os.cpu_count() or 1, 16)
+        threads = oracle.threads()           # every thread the oracle's OpenMP runtime uses
         flags = (oracle.MARK_OCCLUDERS if w.mark_occluders else 0) | oracle.VOL_LABEL
         k = 0
         t0 = time.perf_counter()
@@ -506,7 +506,7 @@ def msg_leg(ctx, w, mids, beam, cpu_sample):
                     "flat_sum_cost": int(sum(int(c) for c in flat_cost))})
     if cpu_sample:
         import oracle
-        threads = min(os.cpu_count() or 1, 16)
+        threads = oracle.threads()           # every thread the oracle's OpenMP runtime uses
         o = w.objects[-1]
         flags = (oracle.USE_RGB if w.use_rgb else 0) | (oracle.MARK_OCCLUDERS if w.mark_occluders else 0) | \
             oracle.VOL_LABEL
