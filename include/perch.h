@@ -140,7 +140,10 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id);
  * colours, and a nearest-neighbour table -- for every pixel and every depth
  * a rendered point there could have, the nearest observed point within
  * delta (Eq. 2), ties to the lower pixel index.  Returns when the scene is
- * ready; the preparation runs on the context's own stream. */
+ * ready; the preparation runs on the context's own stream.  The table is
+ * allocated at its exact size: counted by the device (one wait for the
+ * count), or, while a batch of this context is running, by the host (the
+ * device's count is then checked against it: PERCH_EDEVICE on a difference). */
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *desc, int32_t *scene_id);
 perch_status perch_drop_scene(perch_ctx *ctx, int32_t scene_id);
 
@@ -150,6 +153,8 @@ typedef struct {
     int32_t window_x, window_y;   /* pixel half-windows that contain every neighbour pair */
     int32_t tile_cap_small;       /* LDS words (raster tile + J_o keys) of the scoring classes */
     int32_t tile_cap_large;       /*   1 and 2; larger footprints use device memory */
+    int32_t table_counted_on_host; /* 1 when the table's size was counted on the host */
+    int32_t reserved;
 } perch_scene_info;
 
 /* Describe a resident scene (footprint, search windows, tile classes). */

@@ -48,7 +48,8 @@ class _Intrinsics(ctypes.Structure):
 class _SceneInfo(ctypes.Structure):
     _fields_ = [("device_bytes", ctypes.c_size_t), ("table_entries", ctypes.c_int64),
                 ("window_x", ctypes.c_int32), ("window_y", ctypes.c_int32),
-                ("tile_cap_small", ctypes.c_int32), ("tile_cap_large", ctypes.c_int32)]
+                ("tile_cap_small", ctypes.c_int32), ("tile_cap_large", ctypes.c_int32),
+                ("table_counted_on_host", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Work(ctypes.Structure):

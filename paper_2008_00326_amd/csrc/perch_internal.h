@@ -128,7 +128,9 @@ hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, lon
                                hipStream_t st);
 // Block sums the table scan needs (long long each).
 int table_scan_blocks(int n_pixels);
-hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st);
+// Fills the table; entries at or past `cap` are not written (a table sized
+// on the host holds exactly the count the ranges kernels reach).
+hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, long long cap, hipStream_t st);
 constexpr uint32_t kHashFlag = 1u << 9;   // PERCH_HASH
 // Uniform-grid voxel hash of the observed cloud: count points per bucket,
 // exclusive scan into s.hstart (2^hbits + 1 ints), scatter into s.hpts.

@@ -1228,7 +1228,7 @@ constexpr int kFillChunk = 256;
 // distance, pixel index) into that depth's entry in LDS.  The entries'
 // back-projected (X, Y) are computed once per pass.  Ranges longer than
 // kFillChunk are filled in several passes.
-__global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tnn)
+__global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tnn, long long cap)
 {
     __shared__ unsigned long long acc[4][kFillChunk];
     __shared__ int2 exy[4][kFillChunk];
@@ -1279,7 +1279,7 @@ __global__ __launch_bounds__(256) void table_fill_kernel(SceneDev s, int32_t *tn
         wave_lds_sync();
         for (int e = lane; e < cn; e += 64) {
             const unsigned long long best = acc[wv][e];
-            tnn[th.x + c0 + e] = best == ~0ULL ? -1 : (int32_t)(best & 0xFFFFFFFFu);
+            if ((long long)th.x + c0 + e < cap) tnn[th.x + c0 + e] = best == ~0ULL ? -1 : (int32_t)(best & 0xFFFFFFFFu);
         }
         wave_lds_sync();
     }
@@ -1300,10 +1300,10 @@ hipError_t launch_table_ranges(const SceneDev &s, uint32_t *tmp, int2 *thdr, lon
     return hipGetLastError();
 }
 
-hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, hipStream_t st)
+hipError_t launch_table_fill(const SceneDev &s, int32_t *tnn, long long cap, hipStream_t st)
 {
     const int N = s.W * s.H;
-    table_fill_kernel<<<(N + 3) / 4, 256, 0, st>>>(s, tnn);
+    table_fill_kernel<<<(N + 3) / 4, 256, 0, st>>>(s, tnn, cap);
     return hipGetLastError();
 }
 

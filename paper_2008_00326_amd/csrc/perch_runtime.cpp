@@ -113,6 +113,7 @@ struct SceneRec {
     DevBuf depth, rgb, labels, opt, olab, kx, ky, ax, ay, thdr, tnn, hstart, hpts;
     SceneDev dev{};
     long long table_entries = 0;        // entries of the nearest-neighbour table (0 with the voxel hash)
+    bool table_on_host = false;         // its size counted on the host (a batch was running)
     std::vector<int32_t> host_labels;
     std::vector<uint16_t> host_depth;   // kept with labels: per-label depth ranges (pose proposals)
     std::map<int32_t, std::vector<int>> label_boxes;
@@ -888,6 +889,67 @@ perch_status perch_unload_mesh(perch_ctx *ctx, int32_t mesh_id)
     return ok();
 }
 
+namespace {
+
+// Entries of a scene's neighbour table counted on the host: per pixel the
+// depths [min - dzmm, max + dzmm] (kept inside [1, 65534]) of the valid
+// observed depths in its (2 wtx + 1) x (2 wty + 1) window, the count the
+// ranges kernels reach (row pass, then column pass, over the same clipped
+// windows).  -1 when the windows are too wide for this pass to pay.
+long long table_entries_host(const uint16_t *depth, int W, int H, int wtx, int wty, int dzmm)
+{
+    if (wtx > 48 || wty > 48) return -1;
+    const size_t N = (size_t)W * H;
+    std::vector<uint16_t> mn(N), mx(N), smn(W), smx(W);
+    for (int j = 0; j < H; ++j) {
+        const uint16_t *row = depth + (size_t)j * W;
+        uint16_t *a = mn.data() + (size_t)j * W, *b = mx.data() + (size_t)j * W;
+        for (int i = 0; i < W; ++i) {
+            smn[i] = row[i] ? row[i] : (uint16_t)0xFFFF;     // an empty pixel takes part in neither extreme
+            smx[i] = row[i];
+            a[i] = smn[i];
+            b[i] = smx[i];
+        }
+        for (int o = 1; o <= wtx && o < W; ++o) {
+            for (int i = 0; i + o < W; ++i) {
+                a[i] = std::min(a[i], smn[i + o]);
+                b[i] = std::max(b[i], smx[i + o]);
+            }
+            for (int i = o; i < W; ++i) {
+                a[i] = std::min(a[i], smn[i - o]);
+                b[i] = std::max(b[i], smx[i - o]);
+            }
+        }
+    }
+    std::vector<uint16_t> cmn(W), cmx(W);
+    long long total = 0;
+    for (int j = 0; j < H; ++j) {
+        std::fill(cmn.begin(), cmn.end(), (uint16_t)0xFFFF);
+        std::fill(cmx.begin(), cmx.end(), (uint16_t)0);
+        for (int jj = std::max(j - wty, 0); jj <= std::min(j + wty, H - 1); ++jj) {
+            const uint16_t *a = mn.data() + (size_t)jj * W, *b = mx.data() + (size_t)jj * W;
+            for (int i = 0; i < W; ++i) {
+                cmn[i] = std::min(cmn[i], a[i]);
+                cmx[i] = std::max(cmx[i], b[i]);
+            }
+        }
+        for (int i = 0; i < W; ++i)
+            if (cmx[i] > 0)
+                total += std::min(65534, (int)cmx[i] + dzmm) - std::max(1, (int)cmn[i] - dzmm) + 1;
+    }
+    return total;
+}
+
+// True while a batch of this context is still running (caller holds the lock).
+bool batches_busy(perch_ctx *ctx)
+{
+    for (perch_batch *b : ctx->batches)
+        if (b->pending && hipEventQuery(b->done) == hipErrorNotReady) return true;
+    return false;
+}
+
+}  // namespace
+
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t *scene_id)
 {
     const Range range_("perch_set_scene");
@@ -955,6 +1017,39 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     const size_t o_depth = 0, o_rgb = up8(N * 2), o_lab = o_rgb + (use_rgb ? up8(N * 3) : 0);
     const size_t o_kx = o_lab + (d->labels ? up8(N * 4) : 0), o_ky = o_kx + (size_t)W * 8, o_ax = o_ky + (size_t)H * 8;
     const size_t o_ay = o_ax + up8((size_t)W * 4), o_total = o_ay + up8((size_t)H * 4), stage_bytes = o_total + 8;
+    // Window half-sizes that hold every neighbour pair of this scene: a
+    // rendered point with an observed neighbour has depth >= dmin - dzmm,
+    // and the pixel window shrinks with depth.
+    const int dq = (int)std::nearbyint(16.0 * (double)d->delta_mm), dzmm = dq / 16;
+    int wtx = W, wty = H;
+    {
+        int dmin = 65535;
+        for (size_t k = 0; k < N; ++k)
+            if (d->depth_mm[k] > 0 && d->depth_mm[k] < dmin) dmin = d->depth_mm[k];
+        const double dl = (double)d->delta_mm + 0.25;
+        const double z = (double)dmin - (double)dzmm;
+        const double rx = std::max(std::fabs(0.0 - K.cx), std::fabs((double)(W - 1) - K.cx)) / K.fx;
+        const double ry = std::max(std::fabs(0.0 - K.cy), std::fabs((double)(H - 1) - K.cy)) / K.fy;
+        if (dmin < 65535 && z - dl > 1.0) {
+            wtx = std::min(W, (int)(K.fx * dl * std::sqrt(1.0 + rx * rx) / (z - dl)) + 2);
+            wty = std::min(H, (int)(K.fy * dl * std::sqrt(1.0 + ry * ry) / (z - dl)) + 2);
+        }
+    }
+    // The table's size decides its allocation.  While this context's batches
+    // keep the device busy, waiting for the ranges kernels' count would wait
+    // behind them (a scoring launch holds every compute unit): the host
+    // counts it instead, the device's count is checked against it at the end.
+    long long host_total = -1;
+    if (!hashed) {
+        bool busy;
+        {
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            busy = batches_busy(ctx);
+        }
+        if (busy) host_total = table_entries_host(d->depth_mm, W, H, wtx, wty, dzmm);
+        if (host_total >= (1LL << 31) - 1)
+            return fail(PERCH_ENOMEM, "scene neighbour table too large (%lld entries)", host_total);
+    }
     Staging *stg = nullptr;
     // allocation and kernel launches under the context lock; the waits outside it, so scoring on other streams
     // is not held up
@@ -987,6 +1082,7 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             A(r.hpts, N * sizeof(int4));
         } else {
             A(r.thdr, N * sizeof(int2));
+            if (host_total >= 0) A(r.tnn, (size_t)std::max(host_total, 1LL) * 4);
         }
         A(tmp, tmp_main + 64 + (size_t)(scan_blocks + 1) * 8);
         if (st == PERCH_OK) {
@@ -1043,31 +1139,15 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
     s.fy = K.fy;
     s.cx = K.cx;
     s.cy = K.cy;
-    s.dq = (int)std::nearbyint(16.0 * (double)d->delta_mm);
+    s.dq = dq;
     s.dq2 = s.dq * s.dq;
-    s.dzmm = s.dq / 16;
+    s.dzmm = dzmm;
     s.delta = d->delta_mm;
     s.tau = d->tau_c;
     s.flags = d->flags;
     s.stride = d->stride;
-    // Window half-sizes that hold every neighbour pair of this scene: a
-    // rendered point with an observed neighbour has depth >= dmin - dzmm,
-    // and the pixel window shrinks with depth.
-    int dmin = 65535;
-    for (size_t k = 0; k < N; ++k)
-        if (d->depth_mm[k] > 0 && d->depth_mm[k] < dmin) dmin = d->depth_mm[k];
-    {
-        const double dl = (double)d->delta_mm + 0.25;
-        const double z = (double)dmin - (double)s.dzmm;
-        const double rx = std::max(std::fabs(0.0 - K.cx), std::fabs((double)(W - 1) - K.cx)) / K.fx;
-        const double ry = std::max(std::fabs(0.0 - K.cy), std::fabs((double)(H - 1) - K.cy)) / K.fy;
-        s.wtx = W;
-        s.wty = H;
-        if (dmin < 65535 && z - dl > 1.0) {
-            s.wtx = std::min(W, (int)(K.fx * dl * std::sqrt(1.0 + rx * rx) / (z - dl)) + 2);
-            s.wty = std::min(H, (int)(K.fy * dl * std::sqrt(1.0 + ry * ry) / (z - dl)) + 2);
-        }
-    }
+    s.wtx = wtx;
+    s.wty = wty;
     // uploads from the pinned area, then points, colours and the search structure, all on the context stream
     long long *total_dev = (long long *)((char *)tmp.ptr + tmp_main);
     long long *blk_dev = (long long *)((char *)tmp.ptr + tmp_main + 64);
@@ -1094,8 +1174,15 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
             });
         if (e == hipSuccess && !hashed)
             e = hipMemcpyAsync(hs + o_total, total_dev, 8, hipMemcpyDeviceToHost, cs);
+        if (e == hipSuccess && host_total >= 0) {
+            s.tnn = (const int32_t *)r.tnn.ptr;
+            r.table_entries = host_total;
+            r.table_on_host = true;
+            e = ctx->timed(kProfScenePrep, cs,
+                           [&] { return launch_table_fill(s, (int32_t *)r.tnn.ptr, host_total, cs); });
+        }
     }
-    if (!hashed) {
+    if (!hashed && host_total < 0) {
         // the table's size decides its allocation: one wait for it
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         long long total = 0;
@@ -1117,12 +1204,21 @@ perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t 
         }
         s.tnn = (const int32_t *)r.tnn.ptr;
         e = ctx->timed(kProfScenePrep, ctx->stream,
-                       [&] { return launch_table_fill(s, (int32_t *)r.tnn.ptr, ctx->stream); });
+                       [&] { return launch_table_fill(s, (int32_t *)r.tnn.ptr, total, ctx->stream); });
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         cleanup();
         return fail(PERCH_EDEVICE, "scene preparation: %s", hipGetErrorString(e));
+    }
+    if (host_total >= 0) {
+        long long dev_total = 0;
+        std::memcpy(&dev_total, hs + o_total, 8);
+        if (dev_total != host_total) {
+            cleanup();
+            return fail(PERCH_EDEVICE, "neighbour table counted %lld entries on the host, %lld on the device", host_total,
+                        dev_total);
+        }
     }
     if (d->labels) {
         r.host_labels.assign(d->labels, d->labels + N);
@@ -1856,6 +1952,8 @@ perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_
     out->window_y = r.dev.wty;
     out->tile_cap_small = c.cap_small;
     out->tile_cap_large = c.cap_large;
+    out->table_counted_on_host = r.table_on_host ? 1 : 0;
+    out->reserved = 0;
     return ok();
 }
 

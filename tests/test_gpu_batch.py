@@ -203,3 +203,41 @@ def test_scene_prepared_while_batch_runs_and_memory_reused(ctx):
         ctx.drop_scene(got["sid"])     # released without a wait; the next prep may reuse its memory
     b.close()
     ctx.drop_scene(sid2)
+
+
+def test_scene_prepared_while_a_batch_runs(ctx):
+    """A scene set while one of the context's batches runs has its neighbour
+    table counted on the host (set_scene refuses it if the device's own count
+    differs): the same table size, and the same scores, as the same scene set
+    while the device is idle."""
+    say("scene prepared while a batch runs")
+    w = make_config(2, 0)
+    sid, mids = pk.load_workload(ctx, w)
+    items = [{"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": torch.from_numpy(o.poses).cuda()}
+             for o in w.objects]
+    b = ctx.batch(64, 65536, 640 * 480)
+    b.set(items + items)                                   # 64,000 poses: tens of milliseconds of work
+    w2 = make_config(2, 1)
+    s2 = w2.scene
+    torch.cuda.synchronize()
+    b.launch()
+    busy = ctx.set_scene(s2.K, s2.depth, s2.rgb, delta_mm=w2.delta_mm, tau_c=w2.tau_c)
+    b.wait()
+    idle = ctx.set_scene(s2.K, s2.depth, s2.rgb, delta_mm=w2.delta_mm, tau_c=w2.tau_c)
+    ib, ii = ctx.scene_info(busy), ctx.scene_info(idle)
+    say(f"table entries {ib['table_entries']} (host count: {ib['table_counted_on_host']}) / {ii['table_entries']}")
+    assert ib["table_counted_on_host"] == 1 and ii["table_counted_on_host"] == 0
+    assert ib["table_entries"] == ii["table_entries"] > 0
+    mids2 = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in w2.meshes]
+    for o in w2.objects:
+        p = torch.from_numpy(o.poses[:2000]).cuda()
+        a = ctx.score_poses(busy, mids2[o.mesh], p, label=o.label)
+        c = ctx.score_poses(idle, mids2[o.mesh], p, label=o.label)
+        torch.cuda.synchronize()
+        for x, y in zip(a, c):
+            assert torch.equal(x, y)
+    b.close()
+    for s_ in (sid, busy, idle):
+        ctx.drop_scene(s_)
+    for m in mids + mids2:
+        ctx.unload_mesh(m)
