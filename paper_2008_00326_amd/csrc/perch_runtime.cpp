@@ -9,6 +9,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -361,7 +362,10 @@ struct perch_batch {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
-    bool pending = false, valid = false, any_pv = false;
+    // launched and not yet waited for: written by the launching and waiting
+    // threads, read under the context lock by scene preparation and release
+    std::atomic<bool> pending{false};
+    bool valid = false, any_pv = false;
     int n_req = 0;
     std::vector<int32_t> scene_ids, mesh_ids;
     std::vector<int> item_of_req;
