@@ -160,6 +160,17 @@ typedef struct {
 /* Describe a resident scene (footprint, search windows, tile classes). */
 perch_status perch_scene_info_get(perch_ctx *ctx, int32_t scene_id, perch_scene_info *out);
 
+/* Entries of a neighbour table as set_scene counts them on the host (host
+ * code only; no device is used): for every pixel of the w x h depth image
+ * (uint16 mm, 0 = no reading; host memory, read only) the depths
+ * [min - dzmm, max + dzmm], kept inside [1, 65534], of the valid readings in
+ * its window of (2 wx + 1) x (2 wy + 1) pixels clipped to the image, and
+ * none where the window holds no reading.  *entries receives the sum, or -1
+ * when wx or wy exceeds 48 (set_scene then lets the device count).
+ * PERCH_EINVAL on null pointers, w or h < 1, or wx, wy, dzmm < 0. */
+perch_status perch_table_entries(const uint16_t *depth_mm, int32_t w, int32_t h, int32_t wx, int32_t wy,
+                                 int32_t dzmm, int64_t *entries);
+
 /* Score n poses of one mesh in one scene (Eq. 3 / Eq. 4).  Asynchronous on
  * hip_stream.
  *   label:      the object's label; used by PERCH_VOL_LABEL and, in that

@@ -122,6 +122,7 @@ def load_library():
         "perch_msg_expand": ([P, I32, P, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP, VP], ctypes.c_int),
         "perch_msg_search": ([P, I32, P, I32, I32, P, P, P, P, VP], ctypes.c_int),
         "perch_scene_info_get": ([P, I32, P], ctypes.c_int),
+        "perch_table_entries": ([P, I32, I32, I32, I32, I32, P], ctypes.c_int),
         "perch_profile_enable": ([P, I32], ctypes.c_int),
         "perch_profile_read": ([P, I32, P, P], ctypes.c_int),
         "perch_last_classes": ([P, VP, I32, P], ctypes.c_int),
@@ -162,6 +163,18 @@ def _stream_ptr(stream):
     if stream is None:
         return None
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def table_entries(depth, wx: int, wy: int, dzmm: int) -> int:
+    """Entries of the neighbour table of a uint16 mm depth image with pixel
+    half-windows (wx, wy) and depth reach dzmm, counted on the host as
+    set_scene counts them while the device is busy (-1: windows too wide)."""
+    lib = load_library()
+    d = np.ascontiguousarray(depth, np.uint16)
+    out = ctypes.c_int64()
+    _check(lib.perch_table_entries(_np_ptr(d), d.shape[1], d.shape[0], int(wx), int(wy), int(dzmm),
+                                   ctypes.byref(out)))
+    return int(out.value)
 
 
 class Context:

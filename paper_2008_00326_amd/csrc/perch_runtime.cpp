@@ -954,6 +954,15 @@ bool batches_busy(perch_ctx *ctx)
 
 }  // namespace
 
+perch_status perch_table_entries(const uint16_t *depth_mm, int32_t w, int32_t h, int32_t wx, int32_t wy,
+                                 int32_t dzmm, int64_t *entries)
+{
+    if (!depth_mm || !entries) return fail(PERCH_EINVAL, "null depth or output");
+    if (w < 1 || h < 1 || wx < 0 || wy < 0 || dzmm < 0) return fail(PERCH_EINVAL, "bad image size or window");
+    *entries = table_entries_host(depth_mm, w, h, wx, wy, dzmm);
+    return ok();
+}
+
 perch_status perch_set_scene(perch_ctx *ctx, const perch_scene_desc *d, int32_t *scene_id)
 {
     const Range range_("perch_set_scene");
