@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=8.0, help="arrival window of the served leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg of a plain run")
     ap.add_argument("--prep-workers", type=int, default=2, help="preparation threads of the server")
+    ap.add_argument("--hold-ms", type=float, default=8.0,
+                    help="while a batch runs, how long a lone ready request waits for another to join it")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--volume", choices=["aabb", "cyl", "label"], default=None,
                     help="V(O) of the plain run (default: the workload's)")
@@ -143,7 +145,8 @@ def main():
 
     if args.config == 5:
         rates = [float(x) for x in args.rates.split(",")]
-        r = served_vs_plain(rates, args.serve_seconds, args.seed, prep_workers=args.prep_workers)
+        r = served_vs_plain(rates, args.serve_seconds, args.seed, prep_workers=args.prep_workers,
+                            hold_s=args.hold_ms / 1e3)
         top = r["rates"][str(rates[0])]
         line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
                 "value": top["served"]["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": len(rates),
@@ -299,7 +302,7 @@ def main():
     # (12.5 against 3.9 ms at the median) and every launch then held a single request
     if not args.no_served:
         r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0,
-                            prep_workers=args.prep_workers)
+                            prep_workers=args.prep_workers, hold_s=args.hold_ms / 1e3)
         top = r["rates"][str(args.served_rate)]
         result["served"] = {"workload": r["workload"], "rate_scenes_per_s": args.served_rate,
                             "seconds": args.served_seconds,
@@ -719,7 +722,7 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
             "direct_launch_kernels_ms": {k: round(v[0], 4) for k, v in direct.items() if v[1]}}
 
 
-def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0, prep_workers=2):
+def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0, prep_workers=2, hold_s=0.0):
     """Poisson arrivals of 6-DoF scenes (8 objects of ~20k triangles, 8,192
     candidates, 640x480 RGB-D; a seeded pool of generated scenes, each arrival
     a new upload of one of them) served two ways on identical schedules: the
@@ -773,7 +776,7 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
             if mode == "served":
                 ex = serve.GpuExecutor(ctx, slots=2, max_items=256, max_poses=65536)
                 srv = serve.Server(ex, budget_bytes=int(budget_gb * 2**30), max_items=256, max_poses=65536,
-                                   prep_workers=prep_workers)
+                                   prep_workers=prep_workers, hold_s=hold_s)
 
                 def producer():
                     for r in reqs:

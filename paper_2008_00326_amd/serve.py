@@ -82,14 +82,17 @@ class Server:
     max_items, max_poses: capacity of one launch.
     prep_workers:   threads preparing admitted requests (admission stays in
                     arrival order; prepared requests are launched oldest first).
+    hold_s:         while a batch runs, a lone ready request waits up to this
+                    long for another to join its launch (0: launched at once).
     """
 
     def __init__(self, executor, *, budget_bytes: int, max_items: int, max_poses: int, clock=time.perf_counter,
-                 prep_workers: int = 1):
+                 prep_workers: int = 1, hold_s: float = 0.0):
         if prep_workers < 1:
             raise ValueError("prep_workers must be >= 1")
         self.ex = executor
         self.budget = int(budget_bytes)
+        self.hold_s = float(hold_s)
         self.max_items = int(max_items)
         self.max_poses = int(max_poses)
         self.clock = clock
@@ -231,7 +234,11 @@ class Server:
             with self.cv:
                 if self._prep_error is not None:
                     raise self._prep_error
-                take = self._take_batch() if (self.ready and free) else []
+                # a lone ready request waits while a batch runs and more requests may still come
+                more = not self.closed or bool(self.queue) or self.preparing > 0
+                hold = (self.hold_s > 0 and len(self.ready) == 1 and len(free) < self.ex.slots and more
+                        and self.clock() - self.ready[0].req.ready < self.hold_s)
+                take = self._take_batch() if (self.ready and free and not hold) else []
                 self.n_inflight += len(take)
                 finished = (self.closed and not take and not self.queue and not self.ready and not self.preparing
                             and not self._inflight)
@@ -267,7 +274,7 @@ class Server:
                     free.append(slot)
                     continue
                 with self.cv:
-                    if not self.ready:
+                    if not self.ready or (self.hold_s > 0 and len(self.ready) == 1):
                         self.cv.wait(timeout=poll_s)
                 continue
             with self.cv:

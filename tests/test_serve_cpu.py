@@ -75,8 +75,9 @@ def make_req(rid, poses=1000, nbytes=100, n_obj=3, **extra):
     return Request(rid, payload, poses)
 
 
-def serve(ex, reqs, *, budget=10_000, max_items=64, max_poses=100_000, spacing=0.0, prep_workers=1):
-    srv = Server(ex, budget_bytes=budget, max_items=max_items, max_poses=max_poses, prep_workers=prep_workers)
+def serve(ex, reqs, *, budget=10_000, max_items=64, max_poses=100_000, spacing=0.0, prep_workers=1, hold_s=0.0):
+    srv = Server(ex, budget_bytes=budget, max_items=max_items, max_poses=max_poses, prep_workers=prep_workers,
+                 hold_s=hold_s)
 
     def producer():
         for r in reqs:
@@ -148,6 +149,32 @@ def test_two_preparation_workers():
     assert spans[2] < 0.8 * spans[1]
     with pytest.raises(ValueError):
         Server(FakeExecutor(), budget_bytes=1, max_items=1, max_poses=1, prep_workers=0)
+
+
+def test_a_lone_ready_request_waits_to_be_joined():
+    """While a batch runs, one ready request is held (up to hold_s) for a
+    second to share its launch.  A long request runs; B arrives, then C: B
+    goes alone at once without holding, and with C when held."""
+    for hold, launches in ((0.0, 3), (0.03, 2)):
+        ex = FakeExecutor(per_pose_s=5e-6, prep_s=0.001)
+        reqs = [make_req(0, poses=10_000), make_req(1, poses=100), make_req(2, poses=100)]
+        srv = Server(ex, budget_bytes=10_000, max_items=64, max_poses=100_000, hold_s=hold)
+
+        def producer():
+            srv.submit(reqs[0])
+            time.sleep(0.01)                      # A is on the (serial, 50 ms) device
+            srv.submit(reqs[1])
+            time.sleep(0.005)
+            srv.submit(reqs[2])
+            srv.close()
+
+        t = threading.Thread(target=producer)
+        t.start()
+        done = srv.run()
+        t.join()
+        assert sorted(r.rid for r in done) == [0, 1, 2]
+        assert all(r.result == r.payload["answer"] for r in done)
+        assert len(ex.launches) == launches, (hold, ex.launches)
 
 
 def test_failures_stay_with_their_request():
