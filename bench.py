@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--served-rate", type=float, default=150.0,
                     help="arrival rate (scenes/s) of the served leg of a plain run, above the plain path's capacity")
     ap.add_argument("--served-seconds", type=float, default=8.0, help="arrival window of the served leg")
+    ap.add_argument("--served-capacity-rate", type=float, default=200.0,
+                    help="a second arrival rate of the served leg that saturates both forms (0: none), so that "
+                         "their poses/s are capacities")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg of a plain run")
     ap.add_argument("--prep-workers", type=int, default=2, help="preparation threads of the server")
     ap.add_argument("--hold-ms", type=float, default=8.0,
@@ -301,7 +304,8 @@ def main():
     # the served leg first: run after the many-scene leg, its scene preparations took three times as long
     # (12.5 against 3.9 ms at the median) and every launch then held a single request
     if not args.no_served:
-        r = served_vs_plain([args.served_rate], args.served_seconds, args.seed, drain_s=4.0,
+        rates = [args.served_rate] + ([args.served_capacity_rate] if args.served_capacity_rate > 0 else [])
+        r = served_vs_plain(rates, args.served_seconds, args.seed, drain_s=4.0,
                             prep_workers=args.prep_workers, hold_s=args.hold_ms / 1e3)
         top = r["rates"][str(args.served_rate)]
         result["served"] = {"workload": r["workload"], "rate_scenes_per_s": args.served_rate,
@@ -312,6 +316,13 @@ def main():
                             "offered_poses_per_s": top["offered_poses_per_s"],
                             "kernel_bound_poses_per_s": r.get("kernel_bound_poses_per_s"),
                             "detail": top}
+        if args.served_capacity_rate > 0:
+            cap = r["rates"][str(args.served_capacity_rate)]
+            result["served"]["capacity"] = {
+                "rate_scenes_per_s": args.served_capacity_rate, "offered_poses_per_s": cap["offered_poses_per_s"],
+                "served_poses_per_s": cap["served"]["poses_per_s"], "plain_poses_per_s": cap["plain"]["poses_per_s"],
+                "vs_plain": cap["vs_plain"], "mean_scenes_per_launch": cap["served"].get("mean_scenes_per_launch"),
+                "mismatches_vs_alone": cap["served"]["mismatches_vs_alone"] + cap["plain"]["mismatches_vs_alone"]}
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
     if args.knn_sample > 0:
