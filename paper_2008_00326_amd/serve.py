@@ -10,14 +10,15 @@ Search").  The server
 * prepares admitted requests on worker threads (one by default) -- meshes
   come from a resident cache keyed by content hash, the scene is uploaded
   and prepared on the library's own stream -- while the device scores
-  earlier requests; a preparation waits for the device twice (the table
-  size, the finished scene), and each wait can last as long as a scoring
-  launch that holds every compute unit, so two workers keep the ready
-  queue filled where one cannot;
+  earlier requests; a preparation waits for the device (for the finished
+  scene), and the wait can last as long as a scoring launch that holds
+  every compute unit, so two workers keep the ready queue filled where one
+  cannot;
 * launches prepared requests in batches on a small set of launch slots (two
   by default): a request that becomes ready while a batch runs joins the
   next launch, which is queued behind the running one, so the device never
-  waits for the host between batches;
+  waits for the host between batches (optionally a lone ready request is
+  held briefly for a second to share that launch);
 * returns each request's answer as soon as its batch completes and releases
   its memory.
 
