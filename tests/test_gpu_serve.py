@@ -79,14 +79,21 @@ def check_against_oracle(w, answer, exp, what):
         assert EJ[bi] <= ebc + tol[bi] + tol[ebi], f"{what} object {k}: pose {bi} against the oracle's {ebi}"
 
 
-def test_served_results_equal_alone(ctx):
+@pytest.fixture(scope="module")
+def pool_and_ref(ctx):
     pool = [small(make_config(3, 0), 160), small(make_config(2, 1), 300), small(make_config(3, 2), 200)]
     ref = [alone(ctx, w) for w in pool]
     for k, w in enumerate(pool):
         check_against_oracle(w, ref[k], oracle_best(w), f"scene {k}")
     say("references done, equal to the oracle's minima")
+    return pool, ref
+
+
+@pytest.mark.parametrize("hold_s", [0.0, 0.004])
+def test_served_results_equal_alone(ctx, pool_and_ref, hold_s):
+    pool, ref = pool_and_ref
     ex = serve.GpuExecutor(ctx, slots=2, max_items=64, max_poses=6000)
-    srv = serve.Server(ex, budget_bytes=300 << 20, max_items=64, max_poses=6000)
+    srv = serve.Server(ex, budget_bytes=300 << 20, max_items=64, max_poses=6000, prep_workers=2, hold_s=hold_s)
     reqs = [serve.Request(k, pool[k % 3], pool[k % 3].n_poses) for k in range(9)]
 
     def producer():
