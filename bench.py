@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--batched-scenes", type=int, default=64, help="scenes of the batched workload")
     ap.add_argument("--batched-steps", type=int, default=3, help="timed passes of the batched leg of a plain run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg of a plain run")
+    ap.add_argument("--batched-small", type=int, default=32,
+                    help="the batched leg also scores the first N candidates of each object (0: not)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default ~/.cache/perch)")
     ap.add_argument("--tuning", default=None,
                     help="launch tuning of the plain path as JSON, e.g. '{\"key_bands\": 1}' (results never change)")
@@ -163,7 +165,8 @@ def main():
 
     if args.config == 4:
         ctx = pk.Context(0)
-        r = batched_vs_plain(ctx, args.seed, args.steps, args.warmup, args.batched_scenes, args.tune_cache)
+        r = batched_vs_plain(ctx, args.seed, args.steps, args.warmup, args.batched_scenes, args.tune_cache,
+                             args.batched_small)
         ctx.close()
         line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
                 "value": r["batched_poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
@@ -337,7 +340,7 @@ def main():
         ctx.drop_scene(sid)
         ctx.set_tuning(None)
         result["batched"] = batched_vs_plain(ctx, args.seed, args.batched_steps, 1, args.batched_scenes,
-                                             args.tune_cache)
+                                             args.tune_cache, args.batched_small)
     ctx.close()
     # the CPU oracle last: its worker threads share the host with the server's threads
     if not args.no_cpu_baseline:
@@ -630,35 +633,66 @@ def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depth
     return out
 
 
-def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
+def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None, small=0):
     """The uneven many-scene workload (640x480 RGB-D scenes with 1-10 objects,
     200-8000 candidates per object, meshes of 500-50k triangles, 3-DoF and
     6-DoF mixed) scored two ways on identical inputs: the plain path, one
     best_poses launch sequence per scene, and the batched path, every scene
     in one graph-captured persistent launch with autotuned work spreading.
     Returns poses/s of both, their ratio, the per-object agreement and the
-    tuning used."""
+    tuning used.  With small > 0 the same resident scenes are scored again
+    with only the first `small` candidates of each object (a small search
+    per scene, as when refining around a few proposals), returned under
+    "small": there one scene's launch leaves most compute units idle."""
     import torch
-    import paper_2008_00326_amd as pk
-    from paper_2008_00326_amd import autotune
     from paper_2008_00326_amd.workloads import scenes
 
     _log(f"[bench] batched: generating {n_scenes} scenes")
     lib = scenes.mesh_library(seed)
     ws = scenes.config4(seed, n_scenes=n_scenes, library=lib)
     mids = [ctx.load_mesh(m.xyz, m.tri, m.rgb) for m in lib]
-    per_scene, items = [], []
+    scene_ids, polys = [], []
     for w in ws:
-        sid = ctx.set_scene(w.scene.K, w.scene.depth, w.scene.rgb, delta_mm=w.delta_mm, tau_c=w.tau_c)
-        polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
-        per_scene.append((sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects], polys))
-        items += [{"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": p} for o, p in zip(w.objects, polys)]
+        scene_ids.append(ctx.set_scene(w.scene.K, w.scene.depth, w.scene.rgb, delta_mm=w.delta_mm, tau_c=w.tau_c))
+        polys.append([torch.from_numpy(o.poses).cuda() for o in w.objects])
+    tris = np.mean([lib[o.mesh].n_tris for w in ws for o in w.objects])
+
+    def workload(cut):
+        per_scene, items = [], []
+        for w, sid, ps in zip(ws, scene_ids, polys):
+            ps = [p[:cut] if cut else p for p in ps]
+            per_scene.append((sid, [mids[o.mesh] for o in w.objects], [o.label for o in w.objects], ps))
+            items += [{"scene": sid, "mesh": mids[o.mesh], "label": o.label, "poses": p}
+                      for o, p in zip(w.objects, ps)]
+        return per_scene, items
+
+    per_scene, items = workload(0)
+    r = _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache)
+    r = dict({"workload": f"cfg4-batched-uneven ({n_scenes} scenes, {len(items)} objects, seed {seed})"}, **r)
+    if small > 0:
+        per_scene, items = workload(small)
+        _log(f"[bench] batched: the same scenes, first {small} candidates of each object")
+        r["small"] = dict({"workload": f"cfg4-batched-uneven, first {small} candidates of each object "
+                                       f"({n_scenes} scenes, {len(items)} objects, seed {seed})"},
+                          **_plain_and_batched(ctx, per_scene, items, tris, max(steps, 10), warmup, tune_cache))
+    for sid in scene_ids:
+        ctx.drop_scene(sid)
+    for m in mids:
+        ctx.unload_mesh(m)
+    return r
+
+
+def _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache):
+    """Time resident scenes' items the plain way (one blocking best_poses per
+    scene) and as one graph-captured batch, after autotuning the batch on
+    every fourth scene's items; the plain loop's GPU busy fraction bounds
+    what removing host gaps could gain."""
+    import torch
+    from paper_2008_00326_amd import autotune
+
     n_poses = sum(it["poses"].shape[0] for it in items)
     stream = torch.cuda.current_stream()
-
-    # the tuner times a sample: every fourth scene's items
     sample = [it for it in items if any(it["scene"] == per_scene[k][0] for k in range(0, len(per_scene), 4))]
-    tris = np.mean([lib[o.mesh].n_tris for w in ws for o in w.objects])
     bucket = autotune.shape_bucket(640 * 480, tris, n_poses / len(items), True)
     _log(f"[bench] batched: autotuning on {sum(i['poses'].shape[0] for i in sample)} poses ({bucket})")
     tuned = autotune.autotune(ctx, sample, bucket, cache_path=tune_cache or autotune.DEFAULT_CACHE, stream=stream)
@@ -715,12 +749,7 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None):
     direct = ctx.profile_read()
     ctx.profile(False)
     b.close()
-    for sid, *_ in per_scene:
-        ctx.drop_scene(sid)
-    for m in mids:
-        ctx.unload_mesh(m)
-    return {"workload": f"cfg4-batched-uneven ({n_scenes} scenes, {len(items)} objects, seed {seed})",
-            "poses_per_step": n_poses, "scenes": n_scenes, "objects": len(items),
+    return {"poses_per_step": n_poses, "scenes": len(per_scene), "objects": len(items),
             "plain_poses_per_s": round(n_poses / plain_s, 1), "plain_ms_per_step": round(plain_s * 1e3, 3),
             "batched_poses_per_s": round(n_poses / batched_s, 1), "batched_ms_per_step": round(batched_s * 1e3, 3),
             "vs_plain": round(plain_s / batched_s, 3), "identical_best_poses": got == ref,
