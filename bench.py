@@ -85,6 +85,10 @@ def main():
                     help="a second arrival rate of the served leg that saturates both forms (0: none), so that "
                          "their poses/s are capacities")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg of a plain run")
+    ap.add_argument("--served-small", type=int, default=64,
+                    help="the served leg also serves requests of the first N candidates of each object (0: not)")
+    ap.add_argument("--served-small-rate", type=float, default=800.0,
+                    help="arrival rate of the small requests, scenes/s (above both forms' capacity)")
     ap.add_argument("--prep-workers", type=int, default=2, help="preparation threads of the server")
     ap.add_argument("--hold-ms", type=float, default=8.0,
                     help="while a batch runs, how long a lone ready request waits for another to join it")
@@ -151,7 +155,7 @@ def main():
     if args.config == 5:
         rates = [float(x) for x in args.rates.split(",")]
         r = served_vs_plain(rates, args.serve_seconds, args.seed, prep_workers=args.prep_workers,
-                            hold_s=args.hold_ms / 1e3)
+                            hold_s=args.hold_ms / 1e3, poses_per_object=args.poses_per_object)
         top = r["rates"][str(rates[0])]
         line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
                 "value": top["served"]["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": len(rates),
@@ -326,6 +330,21 @@ def main():
                 "served_poses_per_s": cap["served"]["poses_per_s"], "plain_poses_per_s": cap["plain"]["poses_per_s"],
                 "vs_plain": cap["vs_plain"], "mean_scenes_per_launch": cap["served"].get("mean_scenes_per_launch"),
                 "mismatches_vs_alone": cap["served"]["mismatches_vs_alone"] + cap["plain"]["mismatches_vs_alone"]}
+        if args.served_small > 0 and args.served_small_rate > 0:
+            rs = served_vs_plain([args.served_small_rate], args.served_seconds, args.seed, drain_s=4.0,
+                                 prep_workers=args.prep_workers, hold_s=args.hold_ms / 1e3,
+                                 poses_per_object=args.served_small)
+            sm = rs["rates"][str(args.served_small_rate)]
+            result["served"]["small"] = {
+                "workload": rs["workload"], "rate_scenes_per_s": args.served_small_rate,
+                "offered_poses_per_s": sm["offered_poses_per_s"], "served_poses_per_s": sm["served"]["poses_per_s"],
+                "plain_poses_per_s": sm["plain"]["poses_per_s"], "vs_plain": sm["vs_plain"],
+                "served_scenes_per_s": round(sm["served"]["answered"] / max(sm["served"].get("span_s", 0), 1e-9), 1),
+                "plain_scenes_per_s": round(sm["plain"]["answered"] / max(sm["plain"].get("span_s", 0), 1e-9), 1),
+                "mean_scenes_per_launch": sm["served"].get("mean_scenes_per_launch"),
+                "preparation_p50_ms": sm["served"].get("preparation_p50_ms"),
+                "kernel_bound_poses_per_s": rs.get("kernel_bound_poses_per_s"),
+                "mismatches_vs_alone": sm["served"]["mismatches_vs_alone"] + sm["plain"]["mismatches_vs_alone"]}
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
     if args.knn_sample > 0:
@@ -762,22 +781,38 @@ def _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache):
             "direct_launch_kernels_ms": {k: round(v[0], 4) for k, v in direct.items() if v[1]}}
 
 
-def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0, prep_workers=2, hold_s=0.0):
+_POOLS = {}
+
+
+def _served_pool(seed, pool_size):
+    """The served workload's seeded scene pool, generated once per process."""
+    from paper_2008_00326_amd.workloads import make_config
+    if (seed, pool_size) not in _POOLS:
+        _log(f"[bench] served: generating a pool of {pool_size} scenes")
+        _POOLS[(seed, pool_size)] = [make_config(3, seed + k) for k in range(pool_size)]
+    return _POOLS[(seed, pool_size)]
+
+
+def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0, prep_workers=2, hold_s=0.0,
+                    poses_per_object=0):
     """Poisson arrivals of 6-DoF scenes (8 objects of ~20k triangles, 8,192
     candidates, 640x480 RGB-D; a seeded pool of generated scenes, each arrival
     a new upload of one of them) served two ways on identical schedules: the
     continuous-batching server and the plain loop (one scene at a time,
     prepared and scored alone).  Arrivals run for `seconds`; what is not
     answered `drain_s` later counts as unfinished, with its waiting time as a
-    lower bound of its latency."""
+    lower bound of its latency.  poses_per_object > 0 keeps only the first
+    candidates of each object (small searches)."""
+    import dataclasses
     import threading
     import torch
     import paper_2008_00326_amd as pk
     from paper_2008_00326_amd import serve
-    from paper_2008_00326_amd.workloads import make_config
 
-    _log(f"[bench] served: generating a pool of {pool_size} scenes")
-    pool = [make_config(3, seed + k) for k in range(pool_size)]
+    pool = _served_pool(seed, pool_size)
+    if poses_per_object > 0:
+        pool = [dataclasses.replace(w, objects=[dataclasses.replace(o, poses=np.ascontiguousarray(
+            o.poses[:poses_per_object])) for o in w.objects]) for w in pool]
     ctx = pk.Context(0)
     # reference answers, each scene scored alone; the GPU busy time of
     # preparing and scoring a scene (every kernel timed by HIP events) bounds
@@ -795,7 +830,9 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
         ctx.drop_scene(sid)
         for m in mids:
             ctx.unload_mesh(m)
-    out = {"workload": f"cfg5-served (Poisson arrivals of 6-DoF 640x480 scenes, pool of {pool_size}, seed {seed})",
+    cut = f", first {poses_per_object} candidates of each object" if poses_per_object > 0 else ""
+    out = {"workload": f"cfg5-served (Poisson arrivals of 6-DoF 640x480 scenes{cut}, pool of {pool_size}, "
+                       f"seed {seed})",
            "seconds": seconds, "drain_s": drain_s, "rates": {},
            "gpu_busy_ms_per_scene": round(busy_ms / pool_size, 3),
            "kernel_bound_poses_per_s": round(float(np.mean([w.n_poses for w in pool])) / (busy_ms / pool_size) * 1e3,
@@ -863,6 +900,7 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
             poses = sum(r.n_poses for r in ok)
             lat = serve.latency_stats(reqs, horizon=horizon)
             res[mode] = dict({"poses_per_s": round(poses / max(end - t0, 1e-9), 1), "answered": len(ok),
+                              "span_s": round(end - t0, 3),
                               "errors": sum(1 for r in done if r.error), "latency_ms": lat,
                               "mismatches_vs_alone": mismatch}, **extra)
         res["vs_plain"] = round(res["served"]["poses_per_s"] / max(res["plain"]["poses_per_s"], 1e-9), 3)

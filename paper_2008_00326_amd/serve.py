@@ -450,7 +450,8 @@ class GpuExecutor:
             sid = self.ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None,
                                      s.labels if w.volume == "label" else None, delta_mm=w.delta_mm,
                                      tau_c=w.tau_c, use_rgb=w.use_rgb, mark_occluders=w.mark_occluders,
-                                     volume=w.volume, stride=w.stride)
+                                     volume=w.volume, jo=getattr(w, "jo", "exact"),
+                                     search=getattr(w, "search", "table"), stride=w.stride)
         except pk.PerchError as e:
             for k in keys:
                 self.meshes.release(k)
@@ -532,7 +533,8 @@ def plain_loop(ctx, requests, *, clock=time.perf_counter, meshes: MeshCache | No
         s = w.scene
         sid = ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels if w.volume == "label" else None,
                             delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=w.use_rgb,
-                            mark_occluders=w.mark_occluders, volume=w.volume, stride=w.stride)
+                            mark_occluders=w.mark_occluders, volume=w.volume, jo=getattr(w, "jo", "exact"),
+                            search=getattr(w, "search", "table"), stride=w.stride)
         polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
         bi, bc = ctx.best_poses(sid, [m for _, m in keys_mids], [o.label for o in w.objects], polys, stream=stream)
         r.result = [(int(a), int(b)) for a, b in zip(bi, bc)]

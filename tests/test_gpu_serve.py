@@ -124,3 +124,25 @@ def test_plain_loop_matches(ctx):
     reqs = [serve.Request(k, w, w.n_poses, arrival=now) for k in range(2)]
     done = serve.plain_loop(ctx, reqs)
     assert [r.result for r in done] == [ref, ref]
+
+
+@pytest.mark.parametrize("opts", [{"jo": "nn"}, {"search": "hash"}])
+def test_scene_options_follow_the_workload(ctx, opts):
+    """The served form and the plain loop prepare each scene with the
+    workload's own J_o rule and neighbour search, as scoring it alone does."""
+    w = dataclasses.replace(small(make_config(2, 1), 96), **opts)
+    ref = alone(ctx, w)
+    if "jo" in opts:
+        assert ref != alone(ctx, dataclasses.replace(w, jo="exact"))   # the rule changes the costs
+    ex = serve.GpuExecutor(ctx, slots=2, max_items=64, max_poses=6000)
+    srv = serve.Server(ex, budget_bytes=300 << 20, max_items=64, max_poses=6000)
+    for k in range(3):
+        srv.submit(serve.Request(k, w, w.n_poses))
+    srv.close()
+    done = srv.run()
+    ex.close()
+    assert all(r.error is None for r in done)
+    assert [r.result for r in sorted(done, key=lambda r: r.rid)] == [ref] * 3
+    now = time.perf_counter()
+    done = serve.plain_loop(ctx, [serve.Request(k, w, w.n_poses, arrival=now) for k in range(2)])
+    assert [r.result for r in done] == [ref, ref]
