@@ -772,7 +772,7 @@ def _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache):
             "plain_poses_per_s": round(n_poses / plain_s, 1), "plain_ms_per_step": round(plain_s * 1e3, 3),
             "batched_poses_per_s": round(n_poses / batched_s, 1), "batched_ms_per_step": round(batched_s * 1e3, 3),
             "vs_plain": round(plain_s / batched_s, 3), "identical_best_poses": got == ref,
-            "plain_gpu_busy_frac": round(busy_ms / 1e3 / traced_s, 4),
+            "plain_gpu_busy_frac": round(busy_ms / 1e3 / traced_s, 4), "plain_gpu_busy_ms": round(busy_ms, 3),
             "vs_plain_bound": round(traced_s / max(busy_ms / 1e3, 1e-9), 3),
             "tuning": tuned["tuning"], "tuning_key": tuned["key"], "tuning_cached": tuned["cached"],
             "tuning_default_ms": tuned.get("default_ms"), "tuning_best_ms": tuned.get("ms"),
