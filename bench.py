@@ -89,6 +89,8 @@ def main():
                     help="the served leg also serves requests of the first N candidates of each object (0: not)")
     ap.add_argument("--served-small-rate", type=float, default=800.0,
                     help="arrival rate of the small requests, scenes/s (above both forms' capacity)")
+    ap.add_argument("--served-small-cached-rate", type=float, default=3000.0,
+                    help="arrival rate of the small requests with resident (cached) scenes, scenes/s (0: not)")
     ap.add_argument("--prep-workers", type=int, default=2, help="preparation threads of the server")
     ap.add_argument("--hold-ms", type=float, default=8.0,
                     help="while a batch runs, how long a lone ready request waits for another to join it")
@@ -345,6 +347,20 @@ def main():
                 "preparation_p50_ms": sm["served"].get("preparation_p50_ms"),
                 "kernel_bound_poses_per_s": rs.get("kernel_bound_poses_per_s"),
                 "mismatches_vs_alone": sm["served"]["mismatches_vs_alone"] + sm["plain"]["mismatches_vs_alone"]}
+            if args.served_small_cached_rate > 0:
+                rc = served_vs_plain([args.served_small_cached_rate], args.served_seconds, args.seed, drain_s=4.0,
+                                     prep_workers=args.prep_workers, hold_s=args.hold_ms / 1e3,
+                                     poses_per_object=args.served_small, scene_cache_gb=4.0)
+                sc = rc["rates"][str(args.served_small_cached_rate)]
+                result["served"]["small"]["scene_cache"] = {
+                    "workload": rc["workload"], "rate_scenes_per_s": args.served_small_cached_rate,
+                    "served_poses_per_s": sc["served"]["poses_per_s"], "plain_poses_per_s": sc["plain"]["poses_per_s"],
+                    "vs_plain": sc["vs_plain"],
+                    "served_scenes_per_s": round(sc["served"]["answered"] / max(sc["served"]["span_s"], 1e-9), 1),
+                    "plain_scenes_per_s": round(sc["plain"]["answered"] / max(sc["plain"]["span_s"], 1e-9), 1),
+                    "mean_scenes_per_launch": sc["served"].get("mean_scenes_per_launch"),
+                    "scene_cache_misses": [sc["served"].get("scene_cache_misses"), sc["plain"].get("scene_cache_misses")],
+                    "mismatches_vs_alone": sc["served"]["mismatches_vs_alone"] + sc["plain"]["mismatches_vs_alone"]}
     if not args.no_refine:
         result["refine"] = refine_leg(ctx, w, mids, args.refine_steps, 0 if args.no_cpu_baseline else 16)
     if args.knn_sample > 0:
@@ -794,7 +810,7 @@ def _served_pool(seed, pool_size):
 
 
 def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=32.0, prep_workers=2, hold_s=0.0,
-                    poses_per_object=0):
+                    poses_per_object=0, scene_cache_gb=0.0):
     """Poisson arrivals of 6-DoF scenes (8 objects of ~20k triangles, 8,192
     candidates, 640x480 RGB-D; a seeded pool of generated scenes, each arrival
     a new upload of one of them) served two ways on identical schedules: the
@@ -802,7 +818,9 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
     prepared and scored alone).  Arrivals run for `seconds`; what is not
     answered `drain_s` later counts as unfinished, with its waiting time as a
     lower bound of its latency.  poses_per_object > 0 keeps only the first
-    candidates of each object (small searches)."""
+    candidates of each object (small searches).  scene_cache_gb > 0 gives
+    both forms a scene cache of that size, so a scene of the pool is prepared
+    once and later arrivals of it skip preparation."""
     import dataclasses
     import threading
     import torch
@@ -831,6 +849,7 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
         for m in mids:
             ctx.unload_mesh(m)
     cut = f", first {poses_per_object} candidates of each object" if poses_per_object > 0 else ""
+    cut += ", scenes cached" if scene_cache_gb > 0 else ""
     out = {"workload": f"cfg5-served (Poisson arrivals of 6-DoF 640x480 scenes{cut}, pool of {pool_size}, "
                        f"seed {seed})",
            "seconds": seconds, "drain_s": drain_s, "rates": {},
@@ -851,7 +870,8 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
                 r.arrival = t0 + float(off)
             horizon = t0 + seconds + drain_s
             if mode == "served":
-                ex = serve.GpuExecutor(ctx, slots=2, max_items=256, max_poses=65536)
+                ex = serve.GpuExecutor(ctx, slots=2, max_items=256, max_poses=65536,
+                                       scene_cache_bytes=int(scene_cache_gb * 2**30))
                 srv = serve.Server(ex, budget_bytes=int(budget_gb * 2**30), max_items=256, max_poses=65536,
                                    prep_workers=prep_workers, hold_s=hold_s)
 
@@ -890,10 +910,16 @@ def served_vs_plain(rates, seconds, seed, pool_size=8, drain_s=10.0, budget_gb=3
                          "mean_scenes_per_launch": round(float(np.mean([b[1] for b in srv.batches])), 2)
                          if srv.batches else 0.0, "peak_admitted_MB": round(srv.peak_bytes / 2**20, 1),
                          "mesh_cache_hits": ex.meshes.hits, "mesh_cache_misses": ex.meshes.misses}
+                if ex.scenes is not None:
+                    extra["scene_cache_hits"], extra["scene_cache_misses"] = ex.scenes.hits, ex.scenes.misses
                 ex.close()
             else:
-                done = serve.plain_loop(ctx, reqs, stop_at=horizon)
+                cache = serve.SceneCache(ctx, int(scene_cache_gb * 2**30)) if scene_cache_gb > 0 else None
+                done = serve.plain_loop(ctx, reqs, stop_at=horizon, scenes=cache)
                 extra = {}
+                if cache is not None:
+                    extra = {"scene_cache_hits": cache.hits, "scene_cache_misses": cache.misses}
+                    cache.clear()
             ok = [r for r in done if r.error is None and r.result is not None]
             mismatch = sum(1 for r in ok if r.result != ref[int(picks[r.rid])])
             end = max([r.done for r in ok], default=t0)

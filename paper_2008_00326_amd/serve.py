@@ -403,24 +403,133 @@ class MeshCache:
             self.ctx.unload_mesh(mid)
 
 
+class SceneCache:
+    """Resident scenes keyed by content hash (camera, images and the options
+    they are prepared with), reference-counted: a request whose scene is
+    already resident skips its preparation.  Scenes no request uses are
+    dropped oldest first once the cache holds more than `max_bytes`, and all
+    of them when a preparation runs out of device memory (then it is tried
+    once more)."""
+
+    def __init__(self, ctx, max_bytes: int = 4 << 30):
+        self.ctx = ctx
+        self.max_bytes = max_bytes
+        self.lock = threading.Lock()
+        self.entries = collections.OrderedDict()    # key -> [scene_id, refs, bytes]
+        self.bytes = 0
+        self.hits = 0
+        self.misses = 0
+        self._seen = {}                              # id(workload) -> (workload, key): hash each once
+
+    @staticmethod
+    def key(w) -> str:
+        import numpy as np
+        s = w.scene
+        h = hashlib.blake2b(digest_size=16)
+        h.update(np.asarray(s.K, np.float64).tobytes())
+        h.update(np.ascontiguousarray(s.depth).tobytes())
+        if w.use_rgb and s.rgb is not None:
+            h.update(np.ascontiguousarray(s.rgb).tobytes())
+        if w.volume == "label" and s.labels is not None:
+            h.update(np.ascontiguousarray(s.labels).tobytes())
+        h.update(repr((float(w.delta_mm), float(w.tau_c), bool(w.use_rgb), bool(w.mark_occluders), w.volume,
+                       getattr(w, "jo", "exact"), getattr(w, "search", "table"), int(w.stride))).encode())
+        return h.hexdigest()
+
+    def _key_of(self, w) -> str:
+        # workloads are treated as immutable once submitted (as meshes are)
+        m = self._seen.get(id(w))
+        if m is not None and m[0] is w:
+            return m[1]
+        k = self.key(w)
+        if len(self._seen) > 4096:
+            self._seen.clear()
+        self._seen[id(w)] = (w, k)
+        return k
+
+    def acquire(self, w, prepare) -> tuple:
+        """(key, scene_id, hit); `prepare()` makes the scene resident on a miss."""
+        import paper_2008_00326_amd as pk
+        with self.lock:
+            k = self._key_of(w)
+            e = self.entries.get(k)
+            if e is not None:
+                e[1] += 1
+                self.entries.move_to_end(k)
+                self.hits += 1
+                return k, e[0], True
+        try:
+            sid = prepare()
+        except pk.PerchError as err:
+            if err.status != -2:
+                raise
+            self._evict(0)
+            sid = prepare()
+        nbytes = int(self.ctx.scene_info(sid)["device_bytes"])
+        with self.lock:
+            e = self.entries.get(k)
+            if e is not None:                         # prepared meanwhile by another thread
+                e[1] += 1
+                self.hits += 1
+                dup, sid = sid, e[0]
+            else:
+                self.entries[k] = [sid, 1, nbytes]
+                self.bytes += nbytes
+                self.misses += 1
+                dup = None
+        if dup is not None:
+            self.ctx.drop_scene(dup)
+        self._evict(self.max_bytes)
+        return k, sid, dup is not None
+
+    def release(self, key: str) -> None:
+        with self.lock:
+            self.entries[key][1] -= 1
+        self._evict(self.max_bytes)
+
+    def _evict(self, limit: int):
+        drop = []
+        with self.lock:
+            for k in list(self.entries):
+                if self.bytes <= limit:
+                    break
+                sid, refs, nb = self.entries[k]
+                if refs == 0:
+                    del self.entries[k]
+                    self.bytes -= nb
+                    drop.append(sid)
+        for sid in drop:
+            self.ctx.drop_scene(sid)
+
+    def clear(self):
+        """Drop every scene no request uses."""
+        self._evict(0)
+
+
 @dataclass
 class _Handle:
     scene_id: int
     mesh_keys: list
     items: list                     # score_batch item dicts
     tensors: list = field(default_factory=list)
+    scene_key: str | None = None    # the scene cache's key, when the scene is shared through it
 
 
 class GpuExecutor:
     """Executor over a library context: ``slots`` graph-captured batches of
-    capacity (max_items, max_poses) used in turn on one scoring stream."""
+    capacity (max_items, max_poses) used in turn on one scoring stream.
+    scene_cache_bytes > 0 keeps prepared scenes resident (SceneCache), so a
+    request for a scene seen before skips its preparation; the cache's
+    unused scenes are memory beyond the server's admission budget, as the
+    mesh cache's are."""
 
     def __init__(self, ctx, *, slots: int = 2, max_items: int = 256, max_poses: int = 65536,
-                 max_image_pixels: int = 640 * 480, mesh_cache_bytes: int = 4 << 30):
+                 max_image_pixels: int = 640 * 480, mesh_cache_bytes: int = 4 << 30, scene_cache_bytes: int = 0):
         import torch
         self.ctx = ctx
         self.slots = slots
         self.meshes = MeshCache(ctx, mesh_cache_bytes)
+        self.scenes = SceneCache(ctx, scene_cache_bytes) if scene_cache_bytes > 0 else None
         self.batches = [ctx.batch(max_items, max_poses, max_image_pixels) for _ in range(slots)]
         self.stream = torch.cuda.Stream()
         self._local = threading.local()          # a copy stream per preparation thread
@@ -446,12 +555,12 @@ class GpuExecutor:
             mids.append(mid)
         s = w.scene
         t0 = time.perf_counter()
+        skey = None
         try:
-            sid = self.ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None,
-                                     s.labels if w.volume == "label" else None, delta_mm=w.delta_mm,
-                                     tau_c=w.tau_c, use_rgb=w.use_rgb, mark_occluders=w.mark_occluders,
-                                     volume=w.volume, jo=getattr(w, "jo", "exact"),
-                                     search=getattr(w, "search", "table"), stride=w.stride)
+            if self.scenes is not None:
+                skey, sid, _ = self.scenes.acquire(w, lambda: set_scene(self.ctx, w))
+            else:
+                sid = set_scene(self.ctx, w)
         except pk.PerchError as e:
             for k in keys:
                 self.meshes.release(k)
@@ -482,7 +591,7 @@ class GpuExecutor:
         W, H = int(s.K[0]), int(s.K[1])
         self.table_bytes_per_px = max(self.table_bytes_per_px, info["table_entries"] * 4.0 / (W * H))
         nbytes = int(info["device_bytes"] + req.n_poses * (48 + 8))
-        return Prepared(req, _Handle(sid, keys, items, tensors), len(items), req.n_poses, nbytes)
+        return Prepared(req, _Handle(sid, keys, items, tensors, skey), len(items), req.n_poses, nbytes)
 
     def launch(self, slot: int, handles: list) -> None:
         items = [it for h in handles for it in h.items]
@@ -503,7 +612,10 @@ class GpuExecutor:
         return out
 
     def release(self, h: _Handle) -> None:
-        self.ctx.drop_scene(h.scene_id)
+        if h.scene_key is not None:
+            self.scenes.release(h.scene_key)
+        else:
+            self.ctx.drop_scene(h.scene_id)
         for k in h.mesh_keys:
             self.meshes.release(k)
         h.items.clear()
@@ -513,12 +625,26 @@ class GpuExecutor:
         for b in self.batches:
             b.close()
         self.batches = []
+        if self.scenes is not None:
+            self.scenes.clear()
 
 
-def plain_loop(ctx, requests, *, clock=time.perf_counter, meshes: MeshCache | None = None, stop_at=None):
+def set_scene(ctx, w) -> int:
+    """Make a workload's scene resident with the workload's own options."""
+    s = w.scene
+    return ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels if w.volume == "label" else None,
+                         delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=w.use_rgb, mark_occluders=w.mark_occluders,
+                         volume=w.volume, jo=getattr(w, "jo", "exact"), search=getattr(w, "search", "table"),
+                         stride=w.stride)
+
+
+def plain_loop(ctx, requests, *, clock=time.perf_counter, meshes: MeshCache | None = None, stop_at=None,
+               scenes: SceneCache | None = None):
     """The one-scene-per-launch reference: each request in arrival order,
-    prepared and scored alone (best_poses), nothing overlapped.  Requests
-    must carry their arrival times; returns them completed."""
+    prepared and scored alone (best_poses), nothing overlapped.  With
+    `scenes`, a scene seen before is taken from that cache instead of being
+    prepared again.  Requests must carry their arrival times; returns them
+    completed."""
     import torch
     meshes = meshes or MeshCache(ctx)
     stream = torch.cuda.current_stream()
@@ -530,16 +656,19 @@ def plain_loop(ctx, requests, *, clock=time.perf_counter, meshes: MeshCache | No
             time.sleep(r.arrival - now)
         w = r.payload
         keys_mids = [meshes.acquire(w.meshes[o.mesh], w.use_rgb) for o in w.objects]
-        s = w.scene
-        sid = ctx.set_scene(s.K, s.depth, s.rgb if w.use_rgb else None, s.labels if w.volume == "label" else None,
-                            delta_mm=w.delta_mm, tau_c=w.tau_c, use_rgb=w.use_rgb,
-                            mark_occluders=w.mark_occluders, volume=w.volume, jo=getattr(w, "jo", "exact"),
-                            search=getattr(w, "search", "table"), stride=w.stride)
+        skey = None
+        if scenes is not None:
+            skey, sid, _ = scenes.acquire(w, lambda: set_scene(ctx, w))
+        else:
+            sid = set_scene(ctx, w)
         polys = [torch.from_numpy(o.poses).cuda() for o in w.objects]
         bi, bc = ctx.best_poses(sid, [m for _, m in keys_mids], [o.label for o in w.objects], polys, stream=stream)
         r.result = [(int(a), int(b)) for a, b in zip(bi, bc)]
         r.done = clock()
-        ctx.drop_scene(sid)
+        if skey is not None:
+            scenes.release(skey)
+        else:
+            ctx.drop_scene(sid)
         for k, _ in keys_mids:
             meshes.release(k)
     return [r for r in requests if r.done is not None]

@@ -146,3 +146,31 @@ def test_scene_options_follow_the_workload(ctx, opts):
     now = time.perf_counter()
     done = serve.plain_loop(ctx, [serve.Request(k, w, w.n_poses, arrival=now) for k in range(2)])
     assert [r.result for r in done] == [ref, ref]
+
+
+def test_scene_cache_serves_repeated_scenes(ctx, pool_and_ref):
+    """With the scene cache a repeated scene is prepared once; every answer
+    still equals scoring the scene alone, served and in the plain loop."""
+    pool, ref = pool_and_ref
+    ex = serve.GpuExecutor(ctx, slots=2, max_items=64, max_poses=6000, scene_cache_bytes=1 << 30)
+    srv = serve.Server(ex, budget_bytes=300 << 20, max_items=64, max_poses=6000, prep_workers=2)
+    for k in range(9):
+        srv.submit(serve.Request(k, pool[k % 3], pool[k % 3].n_poses))
+    srv.close()
+    done = srv.run()
+    say(f"served 9 in {len(srv.batches)} launches, scene cache {ex.scenes.misses} misses, {ex.scenes.hits} hits")
+    assert len(done) == 9
+    for r in done:
+        assert r.error is None, r.error
+        assert r.result == ref[r.rid % 3], r.rid
+    assert ex.scenes.misses == 3 and ex.scenes.hits == 6
+    ex.close()
+    assert not ex.scenes.entries                  # closing drops the cached scenes
+    cache = serve.SceneCache(ctx, 1 << 30)
+    now = time.perf_counter()
+    done = serve.plain_loop(ctx, [serve.Request(k, pool[k % 3], pool[k % 3].n_poses, arrival=now) for k in range(6)],
+                            scenes=cache)
+    assert [r.result for r in done] == [ref[k % 3] for k in range(6)]
+    assert cache.misses == 3 and cache.hits == 3
+    cache.clear()
+    assert not cache.entries

@@ -275,3 +275,70 @@ def test_mesh_cache_by_content_and_eviction():
     assert ma not in ctx.loaded and len(ctx.loaded) == 2
     assert cache.acquire(a, True)[1] not in (ma,)      # reloaded under a new id
     assert cache.key(a, True) != cache.key(a, False)   # colours are part of the key only when used
+
+
+class FakeSceneCtx:
+    """set_scene / drop_scene / scene_info of a device with `capacity` bytes."""
+
+    def __init__(self, capacity, nbytes=1000):
+        self.capacity, self.nbytes = capacity, nbytes
+        self.next = 1
+        self.resident = {}
+        self.prepared = 0
+
+    def set_scene(self):
+        import paper_2008_00326_amd as pk
+        if (len(self.resident) + 1) * self.nbytes > self.capacity:
+            raise pk.PerchError(-2, "out of device memory")
+        sid = self.next
+        self.next += 1
+        self.resident[sid] = self.nbytes
+        self.prepared += 1
+        return sid
+
+    def drop_scene(self, sid):
+        del self.resident[sid]
+
+    def scene_info(self, sid):
+        return {"device_bytes": self.resident[sid]}
+
+
+def test_scene_cache_by_content_options_and_eviction():
+    import numpy as np
+    from types import SimpleNamespace
+    from paper_2008_00326_amd.serve import SceneCache
+
+    def work(seed, **opts):
+        r = np.random.default_rng(seed)
+        sc = SimpleNamespace(K=(64, 48, 50.0, 50.0, 32.0, 24.0), depth=r.integers(0, 2000, (48, 64)).astype(np.uint16),
+                             rgb=r.integers(0, 256, (48, 64, 3)).astype(np.uint8), labels=None)
+        w = SimpleNamespace(scene=sc, delta_mm=10.0, tau_c=20.0, use_rgb=True, mark_occluders=True, volume="aabb",
+                            jo="exact", search="table", stride=1)
+        w.__dict__.update(opts)
+        return w
+
+    ctx = FakeSceneCtx(capacity=3000)
+    cache = SceneCache(ctx, max_bytes=2000)
+    a, a_copy, b = work(1), work(1), work(2)
+    ka, sa, hit = cache.acquire(a, ctx.set_scene)
+    assert not hit and ctx.prepared == 1
+    kb, sb, hit = cache.acquire(a_copy, ctx.set_scene)     # same content, another object: no preparation
+    assert hit and (ka, sa) == (kb, sb) and ctx.prepared == 1 and cache.hits == 1
+    assert cache.key(a) != cache.key(work(1, jo="nn"))     # options are part of the key
+    assert cache.key(a) != cache.key(work(1, delta_mm=12.0))
+    cache.release(ka)
+    cache.release(kb)
+    assert sa in ctx.resident                              # unreferenced but within max_bytes: kept
+    k2, s2, _ = cache.acquire(b, ctx.set_scene)
+    k3, s3, _ = cache.acquire(work(3), ctx.set_scene)      # over max_bytes: a, unreferenced, dropped
+    assert sa not in ctx.resident and len(ctx.resident) == 2
+    cache.release(k3)
+    # the device is full: the preparation runs out of memory, the cache drops
+    # its unused scenes and tries once more
+    ctx.capacity = 2000
+    k4, s4, _ = cache.acquire(work(4), ctx.set_scene)
+    assert s3 not in ctx.resident and s4 in ctx.resident and s2 in ctx.resident
+    cache.release(k2)
+    cache.release(k4)
+    cache.clear()
+    assert ctx.resident == {}
