@@ -9,7 +9,8 @@ Search").  The server
   when the next request does not fit it waits for results to free memory;
 * prepares admitted requests on worker threads (one by default) -- meshes
   come from a resident cache keyed by content hash, the scene is uploaded
-  and prepared on the library's own stream -- while the device scores
+  and prepared on the library's own stream (or, with the optional scene
+  cache, taken from the scenes already resident) -- while the device scores
   earlier requests; a preparation waits for the device (for the finished
   scene), and the wait can last as long as a scoring launch that holds
   every compute unit, so two workers keep the ready queue filled where one
