@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg of a plain run")
     ap.add_argument("--batched-small", type=int, default=32,
                     help="the batched leg also scores the first N candidates of each object (0: not)")
+    ap.add_argument("--batched-small-only", action="store_true",
+                    help="config 4: only the small searches (the first --batched-small candidates of each object)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default ~/.cache/perch)")
     ap.add_argument("--tuning", default=None,
                     help="launch tuning of the plain path as JSON, e.g. '{\"key_bands\": 1}' (results never change)")
@@ -172,7 +174,7 @@ def main():
     if args.config == 4:
         ctx = pk.Context(0)
         r = batched_vs_plain(ctx, args.seed, args.steps, args.warmup, args.batched_scenes, args.tune_cache,
-                             args.batched_small)
+                             args.batched_small, full=not args.batched_small_only or args.batched_small <= 0)
         ctx.close()
         line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
                 "value": r["batched_poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
@@ -668,7 +670,7 @@ def pipeline6d_leg(ctx, seed, viewpoints=256, inplane=12, z_step=10.0, max_depth
     return out
 
 
-def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None, small=0):
+def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None, small=0, full=True):
     """The uneven many-scene workload (640x480 RGB-D scenes with 1-10 objects,
     200-8000 candidates per object, meshes of 500-50k triangles, 3-DoF and
     6-DoF mixed) scored two ways on identical inputs: the plain path, one
@@ -678,7 +680,8 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None, sma
     tuning used.  With small > 0 the same resident scenes are scored again
     with only the first `small` candidates of each object (a small search
     per scene, as when refining around a few proposals), returned under
-    "small": there one scene's launch leaves most compute units idle."""
+    "small": there one scene's launch leaves most compute units idle.
+    full=False measures the small searches alone and returns their result."""
     import torch
     from paper_2008_00326_amd.workloads import scenes
 
@@ -701,9 +704,11 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None, sma
                       for o, p in zip(w.objects, ps)]
         return per_scene, items
 
-    per_scene, items = workload(0)
-    r = _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache)
-    r = dict({"workload": f"cfg4-batched-uneven ({n_scenes} scenes, {len(items)} objects, seed {seed})"}, **r)
+    r = {}
+    if full:
+        per_scene, items = workload(0)
+        r = _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache)
+        r = dict({"workload": f"cfg4-batched-uneven ({n_scenes} scenes, {len(items)} objects, seed {seed})"}, **r)
     if small > 0:
         per_scene, items = workload(small)
         _log(f"[bench] batched: the same scenes, first {small} candidates of each object")
@@ -714,7 +719,7 @@ def batched_vs_plain(ctx, seed, steps, warmup, n_scenes=64, tune_cache=None, sma
         ctx.drop_scene(sid)
     for m in mids:
         ctx.unload_mesh(m)
-    return r
+    return r if full else r["small"]
 
 
 def _plain_and_batched(ctx, per_scene, items, tris, steps, warmup, tune_cache):
