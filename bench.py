@@ -91,6 +91,8 @@ def main():
                     help="the served leg also serves requests of the first N candidates of each object (0: not)")
     ap.add_argument("--served-small-rate", type=float, default=800.0,
                     help="arrival rate of the small requests, scenes/s (above both forms' capacity)")
+    ap.add_argument("--scene-cache-gb", type=float, default=0.0,
+                    help="config 5: scene cache of both forms, GB (0: every arrival prepares its scene)")
     ap.add_argument("--served-small-cached-rate", type=float, default=3000.0,
                     help="arrival rate of the small requests with resident (cached) scenes, scenes/s (0: not)")
     ap.add_argument("--prep-workers", type=int, default=2, help="preparation threads of the server")
@@ -159,7 +161,8 @@ def main():
     if args.config == 5:
         rates = [float(x) for x in args.rates.split(",")]
         r = served_vs_plain(rates, args.serve_seconds, args.seed, prep_workers=args.prep_workers,
-                            hold_s=args.hold_ms / 1e3, poses_per_object=args.poses_per_object)
+                            hold_s=args.hold_ms / 1e3, poses_per_object=args.poses_per_object,
+                            scene_cache_gb=args.scene_cache_gb)
         top = r["rates"][str(rates[0])]
         line = {"metric": "candidate poses scored/sec (render+cost), p50/p99 scene latency, vs plain",
                 "value": top["served"]["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": len(rates),
